@@ -1,0 +1,169 @@
+"""FP64 brute-force CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+A plain, slow, independent implementation of the periodic-box power-spectrum
+and bispectrum estimators of arXiv:2005.01739, used to check the GPU library.
+Only the tests, the package smoke check and the benchmark's CPU-baseline leg
+may import this module; the library never does.  See oracle.c for the
+definitions and the readings of the paper they follow.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+_dp = ct.POINTER(ct.c_double)
+_u8p = ct.POINTER(ct.c_uint8)
+_u64p = ct.POINTER(ct.c_uint64)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        src = os.path.join(_HERE, "oracle.c")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build()
+        L = ct.CDLL(path)
+        for name in ("oracle_window", "oracle_si", "oracle_legendre"):
+            pass
+        L.oracle_window.restype = ct.c_double
+        L.oracle_window.argtypes = [ct.c_double]
+        L.oracle_si.restype = ct.c_double
+        L.oracle_si.argtypes = [ct.c_double]
+        L.oracle_legendre.restype = ct.c_double
+        L.oracle_legendre.argtypes = [ct.c_int, ct.c_double]
+        L.oracle_D.restype = ct.c_double
+        L.oracle_D.argtypes = [ct.c_int, ct.c_double]
+        L.oracle_D_at_zero.restype = ct.c_double
+        L.oracle_D_at_zero.argtypes = [ct.c_int]
+        L.oracle_jbar.restype = ct.c_double
+        L.oracle_jbar.argtypes = [ct.c_int, ct.c_double, ct.c_double, ct.c_double]
+        L.oracle_jbar_series.restype = ct.c_double
+        L.oracle_jbar_series.argtypes = [ct.c_int, ct.c_double, ct.c_double, ct.c_double]
+        L.oracle_wtilde.restype = ct.c_double
+        L.oracle_wtilde.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_double]
+        L.oracle_ylm.restype = None
+        L.oracle_ylm.argtypes = [ct.c_int, ct.c_double, ct.c_double, ct.c_double, _dp, _dp]
+        L.oracle_sph_bessel_up.restype = None
+        L.oracle_sph_bessel_up.argtypes = [ct.c_int, ct.c_double, _dp]
+        L.oracle_pk_ell.restype = ct.c_int
+        L.oracle_pk_ell.argtypes = [ct.c_int64, _dp, _dp, ct.c_double, ct.c_double, ct.c_int, _dp,
+                                    ct.c_int, ct.c_int, _u8p, _dp, _dp, _dp, _dp, _u64p, ct.c_int]
+        L.oracle_bk_ell.restype = ct.c_int
+        L.oracle_bk_ell.argtypes = [ct.c_int64, _dp, _dp, ct.c_int64, _dp, _dp, ct.c_double,
+                                    ct.c_double, ct.c_int, _dp, ct.c_int, _u8p, _u8p, _dp, _dp,
+                                    _dp, _dp, _dp, _dp, _dp, _u64p, _u64p, ct.c_int]
+        _lib = L
+    return _lib
+
+
+def _ptr(a, t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def window(x: float) -> float:
+    return lib().oracle_window(float(x))
+
+
+def si(u: float) -> float:
+    return lib().oracle_si(float(u))
+
+
+def legendre(ell: int, mu: float) -> float:
+    return lib().oracle_legendre(int(ell), float(mu))
+
+
+def D(ell: int, u: float) -> float:
+    return lib().oracle_D(int(ell), float(u))
+
+
+def D_at_zero(ell: int) -> float:
+    return lib().oracle_D_at_zero(int(ell))
+
+
+def jbar(ell: int, x: float, k1: float, k2: float) -> float:
+    return lib().oracle_jbar(int(ell), float(x), float(k1), float(k2))
+
+
+def jbar_series(ell: int, x: float, k1: float, k2: float) -> float:
+    return lib().oracle_jbar_series(int(ell), float(x), float(k1), float(k2))
+
+
+def wtilde(r0: float, k1: float, k2: float, resolution: float = 4.0) -> float:
+    return lib().oracle_wtilde(float(r0), float(k1), float(k2), float(resolution))
+
+
+def sph_bessel_up(nmax: int, u: float) -> np.ndarray:
+    out = np.zeros(nmax + 1)
+    lib().oracle_sph_bessel_up(int(nmax), float(u), _ptr(out))
+    return out
+
+
+def ylm(lmax: int, v) -> np.ndarray:
+    """Complex Y_lm(v/|v|) at index l*l + l + m."""
+    re = np.zeros((lmax + 1) ** 2)
+    im = np.zeros((lmax + 1) ** 2)
+    lib().oracle_ylm(int(lmax), float(v[0]), float(v[1]), float(v[2]), _ptr(re), _ptr(im))
+    return re + 1j * im
+
+
+def pk_ell(pos, w, box, r0, k_edges, ell_max=4, los_axis=2, primary_mask=None, nthreads=0):
+    """Brute-force P^a_ell (even ell <= ell_max).  Returns a dict with pk, raw,
+    l1 ([n_ell, n_k]), wtilde [n_k] and n_pairs (ordered pairs inside R0)."""
+    pos = _f64(pos).reshape(-1, 3)
+    w = _f64(w)
+    k = _f64(k_edges)
+    n_k = k.size - 1
+    n_ell = ell_max // 2 + 1
+    pk = np.zeros((n_ell, n_k))
+    raw = np.zeros_like(pk)
+    l1 = np.zeros_like(pk)
+    wt = np.zeros(n_k)
+    npairs = ct.c_uint64(0)
+    mask = None if primary_mask is None else np.ascontiguousarray(primary_mask, dtype=np.uint8)
+    rc = lib().oracle_pk_ell(pos.shape[0], _ptr(pos), _ptr(w), float(box), float(r0), n_k, _ptr(k),
+                             int(ell_max), int(los_axis), _ptr(mask, _u8p), _ptr(pk), _ptr(raw),
+                             _ptr(l1), _ptr(wt), ct.byref(npairs), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_pk_ell: argument outside the oracle's range")
+    return {"pk": pk, "raw": raw, "l1": l1, "wtilde": wt, "n_pairs": int(npairs.value)}
+
+
+def bk_ell(pos, w, rpos, rw, box, r0, k_edges, ell_max, mask_d=None, mask_r=None, nthreads=0):
+    """Brute-force B^ab_ell, ell = 0..ell_max.  Returns a dict with bk, gd, cd,
+    gr, cr ([ell_max+1, n_k, n_k]), s0, wtilde [n_k], n_pairs_dd, n_pairs_rd."""
+    pos = _f64(pos).reshape(-1, 3)
+    w = _f64(w)
+    rpos = np.zeros((0, 3)) if rpos is None else _f64(rpos).reshape(-1, 3)
+    rw = _f64(rw)
+    k = _f64(k_edges)
+    n_k = k.size - 1
+    shp = (ell_max + 1, n_k, n_k)
+    out = {name: np.zeros(shp) for name in ("bk", "gd", "cd", "gr", "cr")}
+    s0 = np.zeros(n_k)
+    wt = np.zeros(n_k)
+    ndd = ct.c_uint64(0)
+    nrd = ct.c_uint64(0)
+    md = None if mask_d is None else np.ascontiguousarray(mask_d, dtype=np.uint8)
+    mr = None if mask_r is None else np.ascontiguousarray(mask_r, dtype=np.uint8)
+    rc = lib().oracle_bk_ell(pos.shape[0], _ptr(pos), _ptr(w), rpos.shape[0],
+                             _ptr(rpos) if rpos.shape[0] else None, _ptr(rw), float(box),
+                             float(r0), n_k, _ptr(k), int(ell_max), _ptr(md, _u8p),
+                             _ptr(mr, _u8p), _ptr(out["bk"]), _ptr(out["gd"]), _ptr(out["cd"]),
+                             _ptr(out["gr"]), _ptr(out["cr"]), _ptr(s0), _ptr(wt),
+                             ct.byref(ndd), ct.byref(nrd), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_bk_ell: argument outside the oracle's range")
+    out.update(s0=s0, wtilde=wt, n_pairs_dd=int(ndd.value), n_pairs_rd=int(nrd.value))
+    return out

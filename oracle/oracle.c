@@ -1,0 +1,585 @@
+/*
+ * FP64 brute-force CPU oracle for the periodic-box O(N^2) power-spectrum and
+ * bispectrum estimators of Philcox (2020), arXiv:2005.01739.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow definition that the
+ * GPU library is checked against.  It shares no code, header, table or helper
+ * with the GPU library, and nothing in the product calls it; only the tests,
+ * the package smoke check and the benchmark's CPU-baseline leg load it.
+ *
+ * Everything is double precision, compiled without floating-point
+ * contraction (-ffp-contract=off), so each expression rounds exactly as
+ * written.
+ *
+ * Conventions (readings of the paper, each listed in the design notes):
+ *  - pairs are ordered pairs (i, j), i != j by index (Sec. 2, discrete pair
+ *    count; self-counts excluded), coincident distinct particles included;
+ *  - separation x_ij = x_i - x_j, per axis wrapped to the nearest periodic
+ *    image by one comparison each way (d > L/2 -> d - L, d < -L/2 -> d + L);
+ *    r^2 = (dx*dx + dy*dy) + dz*dz, and a pair counts iff r^2 < R0*R0.  This
+ *    FP64 predicate defines the integer pair count;
+ *  - weights w_i enter as w_i w_j (Sec. 2 footnote on weights); the mean
+ *    density is n_w = sum(w) / V;
+ *  - the line of sight is a fixed box axis (Sec. 2, fixed LoS for
+ *    simulations), default z.
+ *
+ * Parity status: every function below is pinned by tests against mpmath or
+ * scipy evaluations, closed forms, brute-force triple sums or exact
+ * expectations of random catalogues (see tests/test_oracle_*.py), except the
+ * clustered bispectrum, which is pinned only by the brute-force triple sum and
+ * invariances ("parity unpinned" for a clustered closed form).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_ELL_MAX 6
+#define ORACLE_NK_MAX 128
+/* Below this argument D_ell is taken from its Taylor series; at and above it
+ * from the Appendix C recursion.  Both are accurate to < 1e-15 relative at the
+ * switch for ell <= 6 (checked against mpmath in the tests). */
+#define U_SWITCH 5.0
+
+static const double PI = 3.14159265358979323846264338327950288;
+
+/* ---------------------------------------------------------------- window */
+/* Smooth truncation window W(x), x = r / R0 (Sec. 2, eq. window_defn). */
+double oracle_window(double x)
+{
+    if (x < 0.0) return 0.0;
+    if (x < 0.5) return 1.0;
+    if (x < 0.75) {
+        double t = 2.0 * x - 1.0;
+        return 1.0 - 8.0 * t * t * t + 8.0 * t * t * t * t;
+    }
+    if (x < 1.0) {
+        double t = x - 1.0;
+        return -64.0 * t * t * t - 128.0 * t * t * t * t;
+    }
+    return 0.0;
+}
+
+/* Legendre polynomial L_ell(mu) by Bonnet's recursion. */
+double oracle_legendre(int ell, double mu)
+{
+    double p0 = 1.0, p1 = mu;
+    if (ell == 0) return p0;
+    for (int n = 1; n < ell; ++n) {
+        double p2 = ((2.0 * n + 1.0) * mu * p1 - n * p0) / (n + 1.0);
+        p0 = p1;
+        p1 = p2;
+    }
+    return p1;
+}
+
+/* ------------------------------------------------------- sine integral */
+/* Si(u) = int_0^u sin(t)/t dt.  Power series for u <= 4; above, through the
+ * exponential integral, Si(u) = pi/2 + Im E1(iu), with E1 from its continued
+ * fraction E1(z) = e^{-z} / (z + 1 - 1/(z + 3 - 4/(z + 5 - ...))) evaluated
+ * by the modified Lentz method (Lentz 1976; Thompson & Barnett 1986). */
+double oracle_si(double u)
+{
+    if (u < 0.0) return -oracle_si(-u);
+    if (u == 0.0) return 0.0;
+    if (u <= 4.0) {
+        double sum = 0.0, p = u; /* p = (-1)^n u^(2n+1) / (2n+1)! */
+        for (int n = 0; n < 60; ++n) {
+            double term = p / (2.0 * n + 1.0);
+            sum += term;
+            if (fabs(term) < 1e-18 * fabs(sum)) break;
+            p = -p * u * u / ((2.0 * n + 2.0) * (2.0 * n + 3.0));
+        }
+        return sum;
+    }
+    const double tiny = 1e-300;
+    double complex z = I * u;
+    double complex b = z + 1.0;
+    double complex c = 1.0 / tiny;
+    double complex d = 1.0 / b;
+    double complex h = d;
+    for (int n = 1; n < 1000; ++n) {
+        double a = -(double)n * (double)n;
+        b += 2.0;
+        d = 1.0 / (a * d + b);
+        c = b + a / c;
+        double complex del = c * d;
+        h *= del;
+        if (cabs(del - 1.0) < 1e-17) break;
+    }
+    double complex e1 = h * cexp(-z);
+    return 0.5 * PI + cimag(e1);
+}
+
+/* Spherical Bessel j_0..j_nmax by upward recurrence
+ * j_{n+1} = (2n+1)/u j_n - j_{n-1}.  Used only for u >= U_SWITCH, where the
+ * recurrence is accurate for the orders needed here (n <= 7). */
+void oracle_sph_bessel_up(int nmax, double u, double *j)
+{
+    double s = sin(u), c = cos(u);
+    j[0] = s / u;
+    if (nmax >= 1) j[1] = s / (u * u) - c / u;
+    for (int n = 1; n < nmax; ++n) j[n + 1] = (2.0 * n + 1.0) / u * j[n] - j[n - 1];
+}
+
+/* (2n+1)!! */
+static double dfact_odd(int n)
+{
+    double f = 1.0;
+    for (int k = 3; k <= 2 * n + 1; k += 2) f *= k;
+    return f;
+}
+
+/* D_ell(0) of the Appendix C recursion: with j_0(0)=1, j_n(0)=0 (n>0),
+ * I_0(0) = Si(0) = 0, I_1(0) = -j_0(0) = -1 and ell I_ell = (ell-1) I_{ell-2}
+ * - (2 ell - 1) j_{ell-1}, D_ell(0) = ell (ell+1) I_ell(0). */
+double oracle_D_at_zero(int ell)
+{
+    double I0 = 0.0, I1 = -1.0;
+    double Il[ORACLE_ELL_MAX + 2];
+    Il[0] = I0;
+    Il[1] = I1;
+    for (int l = 2; l <= ell; ++l) {
+        double jlm1 = (l - 1 == 0) ? 1.0 : 0.0;
+        Il[l] = ((l - 1) * Il[l - 2] - (2.0 * l - 1.0) * jlm1) / l;
+    }
+    return ell * (ell + 1.0) * Il[ell];
+}
+
+/* D_ell(u), the antiderivative of u^2 j_ell(u) in the normalisation fixed by
+ * the Appendix C recursion:
+ *   D_ell = u^2 j_{ell+1} - ell u j_ell + ell (ell+1) I_ell,
+ *   ell I_ell = (ell-1) I_{ell-2} - (2 ell - 1) j_{ell-1},
+ *   I_0 = Si, I_1 = -j_0.
+ * For u < U_SWITCH the recursion cancels catastrophically, so there
+ * D_ell(u) = D_ell(0) + int_0^u t^2 j_ell(t) dt with the integral from the
+ * term-by-term integrated Taylor series of j_ell. */
+double oracle_D(int ell, double u)
+{
+    if (u < U_SWITCH) {
+        /* sum_s (-1)^s u^(ell+2s+3) / ((ell+2s+3) 2^s s! (2ell+2s+1)!!) */
+        double sum = 0.0;
+        double t = pow(u, ell + 3) / dfact_odd(ell); /* s = 0, without 1/(ell+3) */
+        for (int s = 0; s < 80; ++s) {
+            double term = t / (ell + 2.0 * s + 3.0);
+            sum += term;
+            if (fabs(term) <= 1e-18 * fabs(sum) && s > 2) break;
+            t = -t * u * u / (2.0 * (s + 1.0) * (2.0 * ell + 2.0 * s + 3.0));
+        }
+        return oracle_D_at_zero(ell) + sum;
+    }
+    double j[ORACLE_ELL_MAX + 3];
+    oracle_sph_bessel_up(ell + 1, u, j);
+    double Il[ORACLE_ELL_MAX + 2];
+    Il[0] = oracle_si(u);
+    Il[1] = -j[0];
+    for (int l = 2; l <= ell; ++l)
+        Il[l] = ((l - 1) * Il[l - 2] - (2.0 * l - 1.0) * j[l - 1]) / l;
+    return u * u * j[ell + 1] - ell * u * j[ell] + ell * (ell + 1.0) * Il[ell];
+}
+
+/* k-bin averaged spherical Bessel function (Sec. 3, eq. jla-def):
+ *   jbar^a_ell(x) = 3 [D_ell(x k2) - D_ell(x k1)] / (x^3 (k2^3 - k1^3)).
+ * For x k2 < U_SWITCH the bin average is taken from the integrated Taylor
+ * series instead,
+ *   3/(k2^3-k1^3) sum_s (-1)^s x^(ell+2s) (k2^n - k1^n) / (n 2^s s! (2ell+2s+1)!!),
+ * n = ell+2s+3, which is exact and free of the small-argument cancellation;
+ * jbar^a_ell(0) = delta_{ell 0}. */
+double oracle_jbar_series(int ell, double x, double k1, double k2)
+{
+    if (x == 0.0) return ell == 0 ? 1.0 : 0.0;
+    double dk3 = k2 * k2 * k2 - k1 * k1 * k1;
+    double sum = 0.0;
+    double t = pow(x, ell) / dfact_odd(ell); /* (-1)^s x^(ell+2s) / (2^s s! (2l+2s+1)!!) */
+    for (int s = 0; s < 80; ++s) {
+        int n = ell + 2 * s + 3;
+        double term = t * (pow(k2, n) - pow(k1, n)) / n;
+        sum += term;
+        if (fabs(term) <= 1e-18 * fabs(sum) && s > 2) break;
+        t = -t * x * x / (2.0 * (s + 1.0) * (2.0 * ell + 2.0 * s + 3.0));
+    }
+    return 3.0 * sum / dk3;
+}
+
+double oracle_jbar(int ell, double x, double k1, double k2)
+{
+    if (x * k2 < U_SWITCH) return oracle_jbar_series(ell, x, k1, k2);
+    double dk3 = k2 * k2 * k2 - k1 * k1 * k1;
+    return 3.0 * (oracle_D(ell, x * k2) - oracle_D(ell, x * k1)) / (x * x * x * dk3);
+}
+
+/* jbar for all bins of one pair at once, from one D evaluation per edge. */
+static void jbar_all_bins(int ell, double x, int n_k, const double *k, double *out)
+{
+    double Dedge[ORACLE_NK_MAX + 1];
+    int have = 0;
+    for (int a = 0; a < n_k; ++a) {
+        if (x * k[a + 1] < U_SWITCH) {
+            out[a] = oracle_jbar_series(ell, x, k[a], k[a + 1]);
+            continue;
+        }
+        if (!have) {
+            for (int e = a; e <= n_k; ++e) Dedge[e] = oracle_D(ell, x * k[e]);
+            have = 1;
+        }
+        double dk3 = k[a + 1] * k[a + 1] * k[a + 1] - k[a] * k[a] * k[a];
+        out[a] = 3.0 * (Dedge[a + 1] - Dedge[a]) / (x * x * x * dk3);
+    }
+}
+
+/* --------------------------------------------------- spherical harmonics */
+/* Complex orthonormal Y_lm(theta, phi) with the Condon-Shortley phase,
+ * for 0 <= l <= lmax, -l <= m <= l, stored at index l*l + l + m.
+ * (x, y, z) need not be normalised; the zero vector is treated as +z. */
+void oracle_ylm(int lmax, double x, double y, double z, double *re, double *im)
+{
+    double r = sqrt(x * x + y * y + z * z);
+    double ct = r > 0.0 ? z / r : 1.0;
+    double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    double phi = (x == 0.0 && y == 0.0) ? 0.0 : atan2(y, x);
+    for (int m = 0; m <= lmax; ++m) {
+        /* P_m^m = (-1)^m (2m-1)!! st^m */
+        double pmm = 1.0;
+        for (int k = 1; k <= m; ++k) pmm *= -(2.0 * k - 1.0) * st;
+        double plm2 = 0.0, plm1 = pmm;
+        for (int l = m; l <= lmax; ++l) {
+            double plm;
+            if (l == m) plm = pmm;
+            else if (l == m + 1) plm = ct * (2.0 * m + 1.0) * pmm;
+            else plm = ((2.0 * l - 1.0) * ct * plm1 - (l + m - 1.0) * plm2) / (l - m);
+            if (l > m) { plm2 = plm1; plm1 = plm; }
+            else { plm1 = plm; plm2 = 0.0; }
+            /* normalisation sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) */
+            double ratio = 1.0;
+            for (int k = l - m + 1; k <= l + m; ++k) ratio /= k;
+            double nrm = sqrt((2.0 * l + 1.0) / (4.0 * PI) * ratio);
+            double yr = nrm * plm * cos(m * phi), yi = nrm * plm * sin(m * phi);
+            re[l * l + l + m] = yr;
+            im[l * l + l + m] = yi;
+            if (m > 0) { /* Y_{l,-m} = (-1)^m conj(Y_lm) */
+                double sg = (m & 1) ? -1.0 : 1.0;
+                re[l * l + l - m] = sg * yr;
+                im[l * l + l - m] = -sg * yi;
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------ window integral W~^a */
+static void gauss_legendre(int n, double *x, double *w)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = cos(PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 1; k < n; ++k) {
+                double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = z;
+            for (int k = 1; k < n; ++k) {
+                double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* W~^a(R0) = 4 pi int_0^R0 r^2 jbar^a_0(r) W(r/R0) dr (Sec. 3, eq. wka-def),
+ * by composite 20-point Gauss-Legendre on the three smooth pieces of W,
+ * [0, R0/2], [R0/2, 3R0/4], [3R0/4, R0], each cut into panels no wider than
+ * (pi / 2) / (k2 * resolution). */
+double oracle_wtilde(double r0, double k1, double k2, double resolution)
+{
+    enum { NG = 20 };
+    double gx[NG], gw[NG];
+    gauss_legendre(NG, gx, gw);
+    double cuts[4] = {0.0, 0.5 * r0, 0.75 * r0, r0};
+    double total = 0.0;
+    for (int piece = 0; piece < 3; ++piece) {
+        double a = cuts[piece], b = cuts[piece + 1];
+        double hmax = 0.5 * PI / (k2 * resolution);
+        int np = (int)ceil((b - a) / hmax);
+        if (np < 1) np = 1;
+        double h = (b - a) / np;
+        for (int p = 0; p < np; ++p) {
+            double lo = a + p * h, hi = lo + h, mid = 0.5 * (lo + hi), half = 0.5 * h;
+            for (int q = 0; q < NG; ++q) {
+                double r = mid + half * gx[q];
+                double f = r * r * oracle_jbar(0, r, k1, k2) * oracle_window(r / r0);
+                total += half * gw[q] * f;
+            }
+        }
+    }
+    return 4.0 * PI * total;
+}
+
+/* -------------------------------------------------------- pair geometry */
+static inline double min_image(double d, double L)
+{
+    if (d > 0.5 * L) return d - L;
+    if (d < -0.5 * L) return d + L;
+    return d;
+}
+
+static int nthreads_or_default(int nthreads)
+{
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------ power spectrum */
+/* P^a_ell for even ell = 0, 2, ..., ell_max (Sec. 3, binned estimator):
+ *   S^a_ell = sum_{i != j} w_i w_j (2 ell + 1) (-i)^ell W(r/R0) jbar^a_ell(r) L_ell(mu),
+ *   P^a_ell = S^a_ell / (n_w^2 V) - delta_{ell 0} W~^a,
+ * mu = (x_ij . los) / r (taken as 0 at r = 0, where jbar_{ell>0} = 0).
+ * Ordered pairs run over primaries i with primary_mask[i] != 0 (all when the
+ * mask is NULL) and every secondary j != i.
+ * Outputs are [n_ell][n_k], n_ell = ell_max/2 + 1: pk, raw (= S), l1 (the sum
+ * of |term|), wtilde [n_k]; *n_pairs counts the ordered pairs inside R0.
+ * Returns 0, or -1 on an argument outside the oracle's range. */
+int oracle_pk_ell(int64_t n, const double *pos, const double *w, double box, double r0,
+                  int n_k, const double *k, int ell_max, int los_axis,
+                  const uint8_t *primary_mask, double *pk, double *raw, double *l1,
+                  double *wtilde, uint64_t *n_pairs, int nthreads)
+{
+    if (n < 1 || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 || ell_max > ORACLE_ELL_MAX ||
+        (ell_max & 1) || los_axis < 0 || los_axis > 2 || !(r0 > 0.0) || r0 > 0.5 * box)
+        return -1;
+    const int n_ell = ell_max / 2 + 1;
+    const int nt = nthreads_or_default(nthreads);
+    const size_t nacc = (size_t)n_ell * n_k;
+    double *acc = calloc((size_t)nt * nacc * 2, sizeof(double));
+    uint64_t *cnt = calloc((size_t)nt, sizeof(uint64_t));
+    const double r02 = r0 * r0;
+
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+        double *S = acc + (size_t)tid * nacc * 2, *A = S + nacc;
+        double jb[ORACLE_NK_MAX];
+        uint64_t c = 0;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            if (primary_mask && !primary_mask[i]) continue;
+            const double wi = w ? w[i] : 1.0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double d[3];
+                for (int ax = 0; ax < 3; ++ax) d[ax] = min_image(pos[3 * i + ax] - pos[3 * j + ax], box);
+                double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                if (!(r2 < r02)) continue;
+                ++c;
+                double r = sqrt(r2);
+                double wgt = wi * (w ? w[j] : 1.0) * oracle_window(r / r0);
+                double mu = r > 0.0 ? d[los_axis] / r : 0.0;
+                for (int li = 0; li < n_ell; ++li) {
+                    int ell = 2 * li;
+                    double phase = (li & 1) ? -1.0 : 1.0; /* (-i)^ell, ell even */
+                    double lw = (2.0 * ell + 1.0) * phase * wgt * oracle_legendre(ell, mu);
+                    jbar_all_bins(ell, r, n_k, k, jb);
+                    for (int a = 0; a < n_k; ++a) {
+                        double term = lw * jb[a];
+                        S[li * n_k + a] += term;
+                        A[li * n_k + a] += fabs(term);
+                    }
+                }
+            }
+        }
+        cnt[tid] = c;
+    }
+    double p1 = 0.0;
+    for (int64_t i = 0; i < n; ++i) p1 += w ? w[i] : 1.0;
+    const double V = box * box * box, nw = p1 / V;
+    uint64_t ctot = 0;
+    for (int t = 0; t < nt; ++t) ctot += cnt[t];
+    for (int a = 0; a < n_k; ++a) wtilde[a] = oracle_wtilde(r0, k[a], k[a + 1], 4.0);
+    for (size_t q = 0; q < nacc; ++q) {
+        double s = 0.0, m = 0.0;
+        for (int t = 0; t < nt; ++t) {
+            s += acc[(size_t)t * nacc * 2 + q];
+            m += acc[(size_t)t * nacc * 2 + nacc + q];
+        }
+        if (raw) raw[q] = s;
+        if (l1) l1[q] = m;
+        int li = (int)(q / n_k), a = (int)(q % n_k);
+        pk[q] = s / (nw * nw * V) - (li == 0 ? wtilde[a] : 0.0);
+    }
+    if (n_pairs) *n_pairs = ctot;
+    free(acc);
+    free(cnt);
+    return 0;
+}
+
+/* ------------------------------------------------------------ bispectrum */
+/* Accumulate, for each primary p in [0, np) (mask permitting) against every
+ * data secondary j (skipping j == p when `self_exclude`):
+ *   A^a_lm(p) = sum_j w_j jbar^a_l(r) W(r/R0) Y_lm(x_pj / r)      (eq. AC-def, binned)
+ *   C^ab_l(p) = sum_j w_j^2 jbar^a_l jbar^b_l W^2
+ *   G^ab_l   += w_p (4 pi / (2l+1)) sum_m Re(A^a_lm conj(A^b_lm))
+ *   Cs^ab_l  += w_p C^ab_l(p)
+ *   S0^b     += w_p sum_j w_j jbar^b_0 W              (data primaries only)
+ * with x_pj = x_p - x_j.  G, Cs: [lmax+1][n_k][n_k]. */
+static uint64_t bk_primary_sums(int64_t np, const double *ppos, const double *pw,
+                                const uint8_t *mask, int self_exclude, int64_t n,
+                                const double *pos, const double *w, double box, double r0,
+                                int n_k, const double *k, int lmax, double *G, double *Cs,
+                                double *S0, int nt)
+{
+    const int nlm = (lmax + 1) * (lmax + 1);
+    const size_t ng = (size_t)(lmax + 1) * n_k * n_k;
+    double *acc = calloc((size_t)nt * (2 * ng + n_k), sizeof(double));
+    uint64_t *cnt = calloc((size_t)nt, sizeof(uint64_t));
+    const double r02 = r0 * r0;
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+        double *tG = acc + (size_t)tid * (2 * ng + n_k), *tC = tG + ng, *tS = tC + ng;
+        double complex *Alm = malloc(sizeof(double complex) * (size_t)n_k * nlm);
+        double *Cp = malloc(sizeof(double) * ng);
+        double *g = malloc(sizeof(double) * (size_t)(lmax + 1) * n_k);
+        double yre[(ORACLE_ELL_MAX + 1) * (ORACLE_ELL_MAX + 1)], yim[(ORACLE_ELL_MAX + 1) * (ORACLE_ELL_MAX + 1)];
+        uint64_t c = 0;
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < np; ++p) {
+            if (mask && !mask[p]) continue;
+            const double wp = pw ? pw[p] : 1.0;
+            memset(Alm, 0, sizeof(double complex) * (size_t)n_k * nlm);
+            memset(Cp, 0, sizeof(double) * ng);
+            double s0loc[ORACLE_NK_MAX];
+            for (int a = 0; a < n_k; ++a) s0loc[a] = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (self_exclude && j == p) continue;
+                double d[3];
+                for (int ax = 0; ax < 3; ++ax) d[ax] = min_image(ppos[3 * p + ax] - pos[3 * j + ax], box);
+                double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                if (!(r2 < r02)) continue;
+                ++c;
+                double r = sqrt(r2);
+                double wj = w ? w[j] : 1.0;
+                double W = oracle_window(r / r0);
+                for (int l = 0; l <= lmax; ++l) {
+                    jbar_all_bins(l, r, n_k, k, g + (size_t)l * n_k);
+                    for (int a = 0; a < n_k; ++a) g[(size_t)l * n_k + a] *= W;
+                }
+                oracle_ylm(lmax, d[0], d[1], d[2], yre, yim);
+                for (int l = 0; l <= lmax; ++l)
+                    for (int m = -l; m <= l; ++m) {
+                        double complex y = yre[l * l + l + m] + I * yim[l * l + l + m];
+                        for (int a = 0; a < n_k; ++a) Alm[(size_t)a * nlm + l * l + l + m] += wj * g[(size_t)l * n_k + a] * y;
+                    }
+                for (int l = 0; l <= lmax; ++l)
+                    for (int a = 0; a < n_k; ++a)
+                        for (int b = 0; b < n_k; ++b)
+                            Cp[((size_t)l * n_k + a) * n_k + b] += wj * wj * g[(size_t)l * n_k + a] * g[(size_t)l * n_k + b];
+                for (int a = 0; a < n_k; ++a) s0loc[a] += wj * g[a];
+            }
+            for (int l = 0; l <= lmax; ++l)
+                for (int a = 0; a < n_k; ++a)
+                    for (int b = 0; b < n_k; ++b) {
+                        double s = 0.0;
+                        for (int m = -l; m <= l; ++m)
+                            s += creal(Alm[(size_t)a * nlm + l * l + l + m] * conj(Alm[(size_t)b * nlm + l * l + l + m]));
+                        size_t q = ((size_t)l * n_k + a) * n_k + b;
+                        tG[q] += wp * (4.0 * PI / (2.0 * l + 1.0)) * s;
+                        tC[q] += wp * Cp[q];
+                    }
+            for (int a = 0; a < n_k; ++a) tS[a] += wp * s0loc[a];
+        }
+        cnt[tid] = c;
+        free(Alm);
+        free(Cp);
+        free(g);
+    }
+    uint64_t ctot = 0;
+    for (size_t q = 0; q < ng; ++q) { G[q] = 0.0; Cs[q] = 0.0; }
+    for (int a = 0; a < n_k; ++a) if (S0) S0[a] = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        const double *b = acc + (size_t)t * (2 * ng + n_k);
+        for (size_t q = 0; q < ng; ++q) { G[q] += b[q]; Cs[q] += b[ng + q]; }
+        if (S0) for (int a = 0; a < n_k; ++a) S0[a] += b[2 * ng + a];
+        ctot += cnt[t];
+    }
+    free(acc);
+    free(cnt);
+    return ctot;
+}
+
+/* B^ab_ell for ell = 0..ell_max (Sec. 4, summary estimator), with the DDR^II
+ * term from random primaries and every other random term analytic:
+ *   B = (-1)^l (2l+1) / (V n_w^3) [(G_D - C_D) - s_R (G_R - C_R)]
+ *       - delta_l0 / (V n_w^2) [W~^a S0^b + W~^b S0^a] + 2 delta_l0 W~^a W~^b,
+ * n_w = sum(w)/V and s_R = sum(w)/sum(w_rand) (= 1/f_rand for unit weights).
+ * With n_r == 0 the random-primary term is left out.  All matrix outputs are
+ * [ell_max+1][n_k][n_k]; s0 and wtilde are [n_k]; any of gd..s0 may be NULL. */
+int oracle_bk_ell(int64_t n, const double *pos, const double *w, int64_t n_r,
+                  const double *rpos, const double *rw, double box, double r0, int n_k,
+                  const double *k, int ell_max, const uint8_t *mask_d, const uint8_t *mask_r,
+                  double *bk, double *gd, double *cd, double *gr, double *cr, double *s0,
+                  double *wtilde, uint64_t *n_pairs_dd, uint64_t *n_pairs_rd, int nthreads)
+{
+    if (n < 1 || n_r < 0 || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 ||
+        ell_max > ORACLE_ELL_MAX || !(r0 > 0.0) || r0 > 0.5 * box)
+        return -1;
+    const int nt = nthreads_or_default(nthreads);
+    const size_t ng = (size_t)(ell_max + 1) * n_k * n_k;
+    double *GD = calloc(ng, sizeof(double)), *CD = calloc(ng, sizeof(double));
+    double *GR = calloc(ng, sizeof(double)), *CR = calloc(ng, sizeof(double));
+    double *S0 = calloc((size_t)n_k, sizeof(double)), *Wt = calloc((size_t)n_k, sizeof(double));
+    uint64_t cdd = bk_primary_sums(n, pos, w, mask_d, 1, n, pos, w, box, r0, n_k, k, ell_max, GD, CD, S0, nt);
+    uint64_t crd = 0;
+    if (n_r > 0)
+        crd = bk_primary_sums(n_r, rpos, rw, mask_r, 0, n, pos, w, box, r0, n_k, k, ell_max, GR, CR, NULL, nt);
+    double p1 = 0.0, pr = 0.0;
+    for (int64_t i = 0; i < n; ++i) p1 += w ? w[i] : 1.0;
+    for (int64_t i = 0; i < n_r; ++i) pr += rw ? rw[i] : 1.0;
+    const double V = box * box * box, nw = p1 / V, sR = n_r > 0 ? p1 / pr : 0.0;
+    for (int a = 0; a < n_k; ++a) Wt[a] = oracle_wtilde(r0, k[a], k[a + 1], 4.0);
+    for (int l = 0; l <= ell_max; ++l)
+        for (int a = 0; a < n_k; ++a)
+            for (int b = 0; b < n_k; ++b) {
+                size_t q = ((size_t)l * n_k + a) * n_k + b;
+                double sgn = (l & 1) ? -1.0 : 1.0;
+                double v = sgn * (2.0 * l + 1.0) / (V * nw * nw * nw) * ((GD[q] - CD[q]) - sR * (GR[q] - CR[q]));
+                if (l == 0)
+                    v += -(Wt[a] * S0[b] + Wt[b] * S0[a]) / (V * nw * nw) + 2.0 * Wt[a] * Wt[b];
+                bk[q] = v;
+            }
+    if (gd) memcpy(gd, GD, ng * sizeof(double));
+    if (cd) memcpy(cd, CD, ng * sizeof(double));
+    if (gr) memcpy(gr, GR, ng * sizeof(double));
+    if (cr) memcpy(cr, CR, ng * sizeof(double));
+    if (s0) memcpy(s0, S0, (size_t)n_k * sizeof(double));
+    if (wtilde) memcpy(wtilde, Wt, (size_t)n_k * sizeof(double));
+    if (n_pairs_dd) *n_pairs_dd = cdd;
+    if (n_pairs_rd) *n_pairs_rd = crd;
+    free(GD); free(CD); free(GR); free(CR); free(S0); free(Wt);
+    return 0;
+}
