@@ -1,0 +1,174 @@
+/*
+ * hipster.h -- C ABI of the MI355X pair-sweep library for the periodic-box
+ * small-scale power-spectrum and bispectrum estimators of Philcox (2020),
+ * "A Faster Fourier Transform?", arXiv:2005.01739.
+ *
+ * The problem, as the paper states it: N tracer positions (optionally with
+ * weights w_i entering pair counts as w_i w_j, Sec. 2 footnote) in a periodic
+ * cube of side L (volume V = L^3), a truncation radius R0 with the smooth
+ * window W(r/R0) (Sec. 2, eq. window_defn), k-bins given by their edges
+ * (Sec. 3, eq. pk-binned) and Legendre multipoles ell about a fixed line of
+ * sight (Sec. 2; a box axis for a simulation).
+ *
+ *   hipster_pk_ell: P^a_ell = (-i)^ell (2 ell+1)/(n^2 V) sum_{i!=j} W jbar^a_ell L_ell
+ *                   - delta_{ell 0} W~^a          (Sec. 3, binned estimator)
+ *   hipster_bk_ell: B^ab_ell from per-primary A^a_lm and C^ab_ell (Sec. 4,
+ *                   eq. AC-def and the summary estimator), with the DDR^II term
+ *                   from caller-supplied random primaries and all other random
+ *                   terms analytic.
+ *
+ * Conventions.  Pairs (i, j), i != j by index, separated by the minimum
+ * periodic image; a pair counts iff r^2 < R0^2 in double precision.  With
+ * weights, the density n is read as n_w = sum(w)/V and the random-primary
+ * scale 1/f_rand as sum(w)/sum(w_rand).
+ *
+ * Errors.  Every call returns a hipster_status; HIPSTER_OK is 0.  All
+ * arguments are checked before any device work; outputs are written only on
+ * HIPSTER_OK.  hipster_last_error() gives a message for the last failure on a
+ * context.  No C++ exception crosses this interface.
+ *
+ * Ownership.  The caller owns every input and output buffer; the library
+ * never frees or modifies them.  A context owns its device scratch memory
+ * (grown on demand, released by hipster_destroy).  One context serves one
+ * host thread and one HIP stream at a time.
+ *
+ * Synchrony.  Calls return when the host outputs are valid.  Device work is
+ * ordered on the context's stream; device input pointers must be valid on
+ * that stream (pass torch.cuda.current_stream().cuda_stream to share torch's).
+ */
+#ifndef HIPSTER_H
+#define HIPSTER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HIPSTER_OK = 0,
+  HIPSTER_EINVAL = 1,       /* NULL pointer, bad enum, N < 2, bad sizes */
+  HIPSTER_EDOMAIN = 2,      /* R0 outside (0, L/2], edges not increasing, ell out of range */
+  HIPSTER_EOUTOFBOX = 3,    /* a coordinate is not finite or not in [0, L) */
+  HIPSTER_ENOMEM = 4,       /* device allocation failed or exceeds the context cap */
+  HIPSTER_EHIP = 5,         /* a HIP runtime call failed; see hipster_last_error */
+  HIPSTER_EUNSUPPORTED = 6  /* a size beyond the compiled limits */
+} hipster_status;
+
+typedef enum { HIPSTER_F32 = 0, HIPSTER_F64 = 1 } hipster_dtype;
+
+/* Arithmetic of the pair weights.  MIXED: geometry, phase reduction and all
+ * accumulation in double precision, special-function amplitudes in single
+ * precision.  FP64: every step in double precision. */
+typedef enum { HIPSTER_MIXED = 0, HIPSTER_FP64 = 1 } hipster_precision;
+
+/* A catalogue.  pos: n x 3 row-major coordinates of `dtype`, each in [0, L).
+ * w: n weights of `dtype`, or NULL for unit weights.  on_device: 1 if pos and
+ * w are device pointers (HIP, same device as the context), 0 if host. */
+typedef struct {
+  int64_t n;
+  int32_t dtype;
+  int32_t on_device;
+  const void *pos;
+  const void *w;
+} hipster_points;
+
+/* Estimator parameters.  k_edges: n_k + 1 strictly increasing host doubles,
+ * k_edges[0] >= 0.  ell_max: P uses even ell = 0, 2, .., ell_max (ell_max
+ * even, <= 6); B uses ell = 0 .. ell_max (<= 6).  los_axis: 0, 1 or 2 (P only).
+ * primary_mask: NULL, or n host bytes; only primaries i with mask[i] != 0
+ * contribute their ordered pairs (i, j) -- a hook for checking a subset of a
+ * large catalogue against a brute-force reference. */
+typedef struct {
+  double box;
+  double r0;
+  int32_t n_k;
+  int32_t ell_max;
+  const double *k_edges;
+  int32_t los_axis;
+  int32_t precision;
+  const uint8_t *primary_mask;
+  const uint8_t *random_mask; /* B only: same role for the random primaries */
+} hipster_params;
+
+/* Optional diagnostics (host memory, caller-allocated; any pointer may be
+ * NULL).  For P: raw [n_ell][n_k] = the pair sums S^a_ell before
+ * normalisation.  For B: gd, cd, gr, cr [ell_max+1][n_k][n_k] = the data and
+ * random primary sums of w_p (4 pi/(2l+1)) sum_m A^a_lm A^b_lm and of
+ * w_p C^ab_l; s0 [n_k] = sum_{i!=j} w_i w_j jbar^b_0 W.  wtilde [n_k] = W~^a.
+ * Timings are wall-clock milliseconds of the device work measured with HIP
+ * events on the context stream. */
+typedef struct {
+  uint64_t n_pairs;       /* ordered data-data pairs inside R0 */
+  uint64_t n_pairs_rand;  /* ordered random-data pairs inside R0 (B) */
+  double *raw;
+  double *gd, *cd, *gr, *cr, *s0;
+  double *wtilde;
+  double ms_build;   /* cell lists */
+  double ms_pairs;   /* pair enumeration */
+  double ms_sweep;   /* pair-weight kernels (the dominant cost) */
+  double ms_total;   /* whole call */
+  uint64_t sweep_launches; /* number of pair-weight kernel launches in ms_sweep */
+} hipster_diag;
+
+typedef struct hipster_ctx hipster_ctx;
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t or
+ * NULL for the default stream.  Returns HIPSTER_EHIP if the device is absent. */
+hipster_status hipster_create(hipster_ctx **out, int device, void *hip_stream);
+
+/* Release the context and its device memory.  NULL is ignored. */
+void hipster_destroy(hipster_ctx *ctx);
+
+/* Power-spectrum multipoles (Sec. 3, binned estimator).
+ * pk: host output, [ell_max/2 + 1][n_k] doubles, rows ell = 0, 2, .. */
+hipster_status hipster_pk_ell(hipster_ctx *ctx, const hipster_points *pts,
+                              const hipster_params *prm, double *pk, hipster_diag *diag);
+
+/* Bispectrum multipoles (Sec. 4, summary estimator).  randoms: the uniform
+ * random catalogue used as primaries for the DDR^II term (Sec. 4, f_rand
+ * times the data), or NULL / n = 0 to leave that term out.
+ * bk: host output, [ell_max + 1][n_k][n_k] doubles (symmetric in a, b). */
+hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data,
+                              const hipster_points *randoms, const hipster_params *prm,
+                              double *bk, hipster_diag *diag);
+
+/* One box of a batch: its catalogue(s), parameters and host outputs. */
+typedef struct {
+  hipster_points data;
+  hipster_points randoms;   /* n = 0: no random primaries */
+  hipster_params pk_params; /* n_k = 0: no power spectrum for this box */
+  hipster_params bk_params; /* n_k = 0: no bispectrum for this box */
+  double *pk;               /* [pk ell_max/2+1][pk n_k] */
+  double *bk;               /* [bk ell_max+1][bk n_k][bk n_k] */
+  uint64_t n_pairs;         /* out: ordered data-data pairs */
+} hipster_box_job;
+
+/* Many independent boxes in one pass: every box's pairs are enumerated into
+ * one shared work stream, so the pair-weight kernels run as single launches
+ * balanced across boxes of very different size.  Equivalent to calling
+ * hipster_pk_ell / hipster_bk_ell per box. */
+hipster_status hipster_batch(hipster_ctx *ctx, int n_boxes, hipster_box_job *jobs,
+                             hipster_diag *diag);
+
+/* The binned window transform W~^a(R0) = 4 pi int_0^R0 r^2 jbar^a_0(r) W(r/R0) dr
+ * (Sec. 3, eq. wka-def) for the n_k bins given by k_edges (host doubles, as
+ * in hipster_params); out: n_k host doubles.  Host-only, needs no device.
+ * Returns HIPSTER_EINVAL / HIPSTER_EDOMAIN on bad arguments. */
+hipster_status hipster_wtilde(double r0, int32_t n_k, const double *k_edges, double *out);
+
+/* Message for the last failing call on ctx (never NULL). */
+const char *hipster_last_error(const hipster_ctx *ctx);
+
+/* Name of a status code. */
+const char *hipster_status_string(hipster_status s);
+
+/* Cap on the device memory a context may hold (bytes; 0 = no cap beyond the
+ * device).  Requests past the cap fail with HIPSTER_ENOMEM. */
+hipster_status hipster_set_memory_cap(hipster_ctx *ctx, uint64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIPSTER_H */

@@ -1,0 +1,362 @@
+// C ABI entry points: argument checks, context and scratch memory, the
+// host-side orchestration of the device passes, and the final normalisation
+// (Sec. 3 binned power spectrum; Sec. 4 bispectrum summary estimator).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <vector>
+
+#include "common.h"
+
+struct hipster_ctx {
+  hipster::Ctx c;
+};
+
+namespace hipster {
+
+void *ensure(Ctx &c, DevBuf &b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return b.p;
+  if (b.p) {
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    HIPSTER_HIP(hipFree(b.p));
+    c.mem_used -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = bytes + bytes / 8;  // headroom for the next, slightly larger call
+  if (c.mem_cap && c.mem_used + want > c.mem_cap) {
+    want = bytes;
+    if (c.mem_used + want > c.mem_cap) throw Error{HIPSTER_ENOMEM, "device memory cap exceeded"};
+  }
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    throw Error{HIPSTER_ENOMEM, std::string("hipMalloc of ") + std::to_string(want) + " bytes failed"};
+  }
+  b.cap = want;
+  c.mem_used += want;
+  return b.p;
+}
+
+void wtilde_bins(Ctx &c, double r0, int n_k, const double *k_edges, double *out) {
+  for (int a = 0; a < n_k; ++a) {
+    const auto key = std::make_tuple(r0, k_edges[a], k_edges[a + 1]);
+    auto it = c.wtilde_cache.find(key);
+    if (it == c.wtilde_cache.end()) {
+      if (c.wtilde_cache.size() > 100000) c.wtilde_cache.clear();
+      it = c.wtilde_cache.emplace(key, wtilde_bin(r0, k_edges[a], k_edges[a + 1])).first;
+    }
+    out[a] = it->second;
+  }
+}
+
+static void free_buf(DevBuf &b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+static void free_cells(CellScratch &s) {
+  DevBuf *all[] = {&s.cell, &s.count, &s.start, &s.cursor, &s.idx, &s.x, &s.y, &s.z, &s.w, &s.m, &s.bad, &s.scan_tmp};
+  for (DevBuf *b : all) free_buf(*b);
+}
+
+// ------------------------------------------------------------ validation
+static void check_points(const hipster_points *p, const char *what, double box) {
+  if (!p || !p->pos) throw Error{HIPSTER_EINVAL, std::string(what) + ": NULL catalogue or positions"};
+  if (p->dtype != HIPSTER_F32 && p->dtype != HIPSTER_F64) throw Error{HIPSTER_EINVAL, std::string(what) + ": bad dtype"};
+  if (p->n < 0 || p->n > int64_t(0x7fffffff)) throw Error{HIPSTER_EUNSUPPORTED, std::string(what) + ": n outside [0, 2^31)"};
+  if (p->on_device != 0 && p->on_device != 1) throw Error{HIPSTER_EINVAL, std::string(what) + ": on_device must be 0 or 1"};
+  (void)box;
+}
+
+static void check_params(const hipster_params *q, bool bispectrum) {
+  if (!q) throw Error{HIPSTER_EINVAL, "NULL parameters"};
+  if (!(q->box > 0.0) || !isfinite(q->box)) throw Error{HIPSTER_EDOMAIN, "box size must be finite and positive"};
+  if (!(q->r0 > 0.0) || !(q->r0 <= 0.5 * q->box)) throw Error{HIPSTER_EDOMAIN, "R0 must lie in (0, L/2]"};
+  const int maxk = bispectrum ? kMaxNkB : kMaxNk;
+  if (q->n_k < 1 || q->n_k > maxk)
+    throw Error{HIPSTER_EUNSUPPORTED, "n_k must lie in [1, " + std::to_string(maxk) + "]"};
+  if (!q->k_edges) throw Error{HIPSTER_EINVAL, "NULL k_edges"};
+  for (int a = 0; a <= q->n_k; ++a) {
+    if (!isfinite(q->k_edges[a]) || q->k_edges[a] < 0.0) throw Error{HIPSTER_EDOMAIN, "k edges must be finite and >= 0"};
+    if (a > 0 && !(q->k_edges[a] > q->k_edges[a - 1])) throw Error{HIPSTER_EDOMAIN, "k edges must increase strictly"};
+  }
+  if (q->ell_max < 0 || q->ell_max > kLMaxApi) throw Error{HIPSTER_EDOMAIN, "ell_max must lie in [0, 6]"};
+  if (!bispectrum && (q->ell_max & 1)) throw Error{HIPSTER_EDOMAIN, "power spectrum: ell_max must be even"};
+  if (!bispectrum && (q->los_axis < 0 || q->los_axis > 2)) throw Error{HIPSTER_EINVAL, "los_axis must be 0, 1 or 2"};
+  if (q->precision != HIPSTER_MIXED && q->precision != HIPSTER_FP64) throw Error{HIPSTER_EINVAL, "bad precision"};
+}
+
+// Device copy of a catalogue when it lives on the host.
+static const void *device_view(Ctx &c, DevBuf &b, const void *p, int64_t bytes, int on_device) {
+  if (!p) return nullptr;
+  if (on_device) return p;
+  void *d = ensure(c, b, size_t(bytes));
+  HIPSTER_HIP(hipMemcpyAsync(d, p, size_t(bytes), hipMemcpyHostToDevice, c.stream));
+  return d;
+}
+
+static const uint8_t *device_mask(Ctx &c, DevBuf &b, const uint8_t *mask, int64_t n) {
+  if (!mask) return nullptr;
+  void *d = ensure(c, b, size_t(n));
+  HIPSTER_HIP(hipMemcpyAsync(d, mask, size_t(n), hipMemcpyHostToDevice, c.stream));
+  return static_cast<const uint8_t *>(d);
+}
+
+static int64_t pair_chunk_capacity() {
+  const char *e = getenv("HIPSTER_PAIR_CHUNK");
+  int64_t cap = int64_t(1) << 28;
+  if (e) {
+    long long v = atoll(e);
+    if (v >= 1024) cap = v;
+  }
+  return cap;
+}
+
+struct Timer {
+  Ctx &c;
+  std::vector<hipEvent_t> evs;
+  explicit Timer(Ctx &cc) : c(cc) {}
+  hipEvent_t mark() {
+    hipEvent_t e;
+    HIPSTER_HIP(hipEventCreate(&e));
+    HIPSTER_HIP(hipEventRecord(e, c.stream));
+    evs.push_back(e);
+    return e;
+  }
+  static double ms(hipEvent_t a, hipEvent_t b) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, a, b) != hipSuccess) return 0.0;
+    return double(t);
+  }
+  ~Timer() {
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  }
+};
+
+// ---------------------------------------------------------- power spectrum
+static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, double *pk, hipster_diag *diag) {
+  check_points(pts, "data", q ? q->box : 0.0);
+  check_params(q, false);
+  if (!pk) throw Error{HIPSTER_EINVAL, "NULL output"};
+  if (pts->n < 2) throw Error{HIPSTER_EINVAL, "need at least two points"};
+  HIPSTER_HIP(hipSetDevice(c.device));
+  Timer tm(c);
+  hipEvent_t t0 = tm.mark();
+
+  const int64_t n = pts->n;
+  const size_t esz = pts->dtype == HIPSTER_F32 ? 4 : 8;
+  const void *pos = device_view(c, c.pos_in, pts->pos, n * 3 * int64_t(esz), pts->on_device);
+  const void *w = device_view(c, c.w_in, pts->w, n * int64_t(esz), pts->on_device);
+  const uint8_t *mask = device_mask(c, c.mask_in, q->primary_mask, n);
+  const Grid g = make_grid(q->box, q->r0);
+  const Sorted s = build_cells(c, c.cells_d, g, pos, w, mask, n, pts->dtype);
+  hipEvent_t t1 = tm.mark();
+
+  // count pass, offsets
+  const int64_t ncells = g.ncells();
+  int64_t *cnt = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
+  int64_t *off = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));
+  unsigned long long *ord = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 16));
+  HIPSTER_HIP(hipMemsetAsync(ord, 0, 8, c.stream));
+  pk_pairs_count(c, s, g, q->r0, cnt, ord);
+  scan_i64(c, cnt, off, ncells, c.pair_total);
+  std::vector<int64_t> hoff(size_t(ncells) + 1);
+  unsigned long long hord = 0;
+  HIPSTER_HIP(hipMemcpyAsync(hoff.data(), off, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(&hord, ord, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  const int64_t total = hoff[size_t(ncells)];
+
+  const int n_ell = q->ell_max / 2 + 1, n_edges = q->n_k + 1;
+  const bool fp64 = q->precision == HIPSTER_FP64;
+  double *edges = static_cast<double *>(ensure(c, c.edges, size_t(n_edges) * 8));
+  HIPSTER_HIP(hipMemcpyAsync(edges, q->k_edges, size_t(n_edges) * 8, hipMemcpyHostToDevice, c.stream));
+  const int nwaves = pk_sweep_waves(c);
+  const int cols = n_ell * n_edges;
+  double *partial = static_cast<double *>(ensure(c, c.partial, size_t(nwaves) * cols * 8));
+  HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwaves) * cols * 8, c.stream));
+
+  // chunks of home cells whose pairs fit the pair buffer
+  int64_t cap = std::min<int64_t>(pair_chunk_capacity(), std::max<int64_t>(total, 1));
+  for (int64_t a = 0; a < ncells; ++a) cap = std::max(cap, hoff[size_t(a + 1)] - hoff[size_t(a)]);
+  const size_t tsz = 8;
+  PkPairs pp;
+  pp.r = static_cast<double *>(ensure(c, c.pr, size_t(cap) * 8));
+  pp.mu = ensure(c, c.pmu, size_t(cap) * tsz);
+  pp.ww = ensure(c, c.pww, size_t(cap) * tsz);
+  double ms_pairs = 0.0, ms_sweep = 0.0;
+  uint64_t launches = 0;
+  hipEvent_t t2 = tm.mark();
+  ms_pairs += 0.0;
+  int64_t c0 = 0;
+  while (c0 < ncells) {
+    int64_t c1 = c0 + 1;
+    while (c1 < ncells && hoff[size_t(c1 + 1)] - hoff[size_t(c0)] <= cap) ++c1;
+    const int64_t base = hoff[size_t(c0)], np = hoff[size_t(c1)] - base;
+    if (np > 0) {
+      hipEvent_t a = tm.mark();
+      pk_pairs_write(c, s, g, q->r0, q->los_axis, fp64, off, base, c0, c1, pp);
+      hipEvent_t b = tm.mark();
+      pk_sweep(c, pp, np, n_ell, fp64, q->r0, edges, n_edges, partial, nwaves);
+      hipEvent_t d = tm.mark();
+      HIPSTER_HIP(hipEventSynchronize(d));
+      ms_pairs += Timer::ms(a, b);
+      ms_sweep += Timer::ms(b, d);
+      ++launches;
+    }
+    c0 = c1;
+  }
+  double *merged = static_cast<double *>(ensure(c, c.merged, size_t(cols) * 8));
+  merge_partials(c, partial, nwaves, cols, merged);
+  std::vector<double> E(static_cast<size_t>(cols));
+  HIPSTER_HIP(hipMemcpyAsync(E.data(), merged, size_t(cols) * 8, hipMemcpyDeviceToHost, c.stream));
+  hipEvent_t t3 = tm.mark();
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+
+  // finalize (host, FP64): S^a_l, W~^a, P^a_l
+  double p1 = 0.0;
+  if (pts->w) {
+    // sum of weights in input order (FP64)
+    std::vector<double> hw(static_cast<size_t>(n));
+    if (pts->on_device) {
+      std::vector<unsigned char> raw(size_t(n) * esz);
+      HIPSTER_HIP(hipMemcpy(raw.data(), pts->w, size_t(n) * esz, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < n; ++i)
+        hw[size_t(i)] = esz == 4 ? double(reinterpret_cast<float *>(raw.data())[i]) : reinterpret_cast<double *>(raw.data())[i];
+    } else {
+      for (int64_t i = 0; i < n; ++i)
+        hw[size_t(i)] = esz == 4 ? double(static_cast<const float *>(pts->w)[i]) : static_cast<const double *>(pts->w)[i];
+    }
+    for (double v : hw) p1 += v;
+  } else {
+    p1 = double(n);
+  }
+  const double V = q->box * q->box * q->box, nw = p1 / V, norm = 1.0 / (nw * nw * V);
+  std::vector<double> wt(static_cast<size_t>(q->n_k));
+  wtilde_bins(c, q->r0, q->n_k, q->k_edges, wt.data());
+  for (int li = 0; li < n_ell; ++li) {
+    const int ell = 2 * li;
+    const double phase = (li & 1) ? -1.0 : 1.0;  // (-i)^ell for even ell
+    for (int a = 0; a < q->n_k; ++a) {
+      const double ka = q->k_edges[a], kb = q->k_edges[a + 1];
+      const double a3 = ka * ka * ka, b3 = kb * kb * kb;
+      const double Ea = E[size_t(li * n_edges + a)], Eb = E[size_t(li * n_edges + a + 1)];
+      const double S = 3.0 * (2.0 * ell + 1.0) * phase * (b3 * Eb - a3 * Ea) / (b3 - a3);
+      if (diag && diag->raw) diag->raw[li * q->n_k + a] = S;
+      pk[li * q->n_k + a] = S * norm - (ell == 0 ? wt[size_t(a)] : 0.0);
+    }
+  }
+  if (diag) {
+    diag->n_pairs = hord;
+    diag->n_pairs_rand = 0;
+    if (diag->wtilde) memcpy(diag->wtilde, wt.data(), size_t(q->n_k) * 8);
+    diag->ms_build = Timer::ms(t0, t1);
+    diag->ms_pairs = Timer::ms(t1, t2) + ms_pairs;
+    diag->ms_sweep = ms_sweep;
+    diag->ms_total = Timer::ms(t0, t3);
+    diag->sweep_launches = launches;
+  }
+  (void)total;
+}
+
+template <class F>
+static hipster_status guarded(hipster_ctx *ctx, F &&f) {
+  if (!ctx) return HIPSTER_EINVAL;
+  try {
+    f();
+    ctx->c.last_error.clear();
+    return HIPSTER_OK;
+  } catch (const Error &e) {
+    ctx->c.last_error = e.msg;
+    if (e.status == HIPSTER_EHIP) (void)hipGetLastError();
+    return e.status;
+  } catch (const std::exception &e) {
+    ctx->c.last_error = e.what();
+    return HIPSTER_ENOMEM;
+  }
+}
+
+}  // namespace hipster
+
+using namespace hipster;
+
+extern "C" {
+
+hipster_status hipster_create(hipster_ctx **out, int device, void *hip_stream) {
+  if (!out) return HIPSTER_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    (void)hipGetLastError();
+    return HIPSTER_EHIP;
+  }
+  if (hipSetDevice(device) != hipSuccess) return HIPSTER_EHIP;
+  hipster_ctx *h = new (std::nothrow) hipster_ctx();
+  if (!h) return HIPSTER_ENOMEM;
+  h->c.device = device;
+  h->c.stream = static_cast<hipStream_t>(hip_stream);
+  *out = h;
+  return HIPSTER_OK;
+}
+
+void hipster_destroy(hipster_ctx *ctx) {
+  if (!ctx) return;
+  Ctx &c = ctx->c;
+  (void)hipSetDevice(c.device);
+  (void)hipStreamSynchronize(c.stream);
+  free_cells(c.cells_d);
+  free_cells(c.cells_r);
+  DevBuf *all[] = {&c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in, &c.rmask_in, &c.pair_cnt, &c.pair_ord,
+                   &c.pair_off, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
+                   &c.partial, &c.merged, &c.ordered_count, &c.bk_prim_off, &c.bk_partial};
+  for (DevBuf *b : all) free_buf(*b);
+  delete ctx;
+}
+
+hipster_status hipster_pk_ell(hipster_ctx *ctx, const hipster_points *pts, const hipster_params *prm, double *pk,
+                              hipster_diag *diag) {
+  return guarded(ctx, [&] { run_pk(ctx->c, pts, prm, pk, diag); });
+}
+
+hipster_status hipster_wtilde(double r0, int32_t n_k, const double *k_edges, double *out) {
+  if (!k_edges || !out || n_k < 1) return HIPSTER_EINVAL;
+  if (!(r0 > 0.0) || !isfinite(r0)) return HIPSTER_EDOMAIN;
+  for (int a = 0; a <= n_k; ++a) {
+    if (!isfinite(k_edges[a]) || k_edges[a] < 0.0) return HIPSTER_EDOMAIN;
+    if (a > 0 && !(k_edges[a] > k_edges[a - 1])) return HIPSTER_EDOMAIN;
+  }
+  for (int a = 0; a < n_k; ++a) out[a] = wtilde_bin(r0, k_edges[a], k_edges[a + 1]);
+  return HIPSTER_OK;
+}
+
+hipster_status hipster_set_memory_cap(hipster_ctx *ctx, uint64_t bytes) {
+  if (!ctx) return HIPSTER_EINVAL;
+  ctx->c.mem_cap = bytes;
+  return HIPSTER_OK;
+}
+
+const char *hipster_last_error(const hipster_ctx *ctx) {
+  if (!ctx) return "NULL context";
+  return ctx->c.last_error.c_str();
+}
+
+const char *hipster_status_string(hipster_status s) {
+  switch (s) {
+    case HIPSTER_OK: return "HIPSTER_OK";
+    case HIPSTER_EINVAL: return "HIPSTER_EINVAL";
+    case HIPSTER_EDOMAIN: return "HIPSTER_EDOMAIN";
+    case HIPSTER_EOUTOFBOX: return "HIPSTER_EOUTOFBOX";
+    case HIPSTER_ENOMEM: return "HIPSTER_ENOMEM";
+    case HIPSTER_EHIP: return "HIPSTER_EHIP";
+    case HIPSTER_EUNSUPPORTED: return "HIPSTER_EUNSUPPORTED";
+  }
+  return "HIPSTER_UNKNOWN";
+}
+
+}  // extern "C"

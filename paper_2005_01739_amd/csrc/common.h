@@ -1,0 +1,120 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/hipster.h"
+
+namespace hipster {
+
+// Largest sizes the kernels are compiled for.
+constexpr int kMaxNk = 128;        // power-spectrum bins
+constexpr int kMaxNkB = 16;        // bispectrum bins
+constexpr int kMaxCellsPerAxis = 160;
+constexpr int kLMaxApi = 6;          // largest multipole
+
+struct Error {
+  hipster_status status;
+  std::string msg;
+};
+
+#define HIPSTER_HIP(expr)                                                         \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw ::hipster::Error{HIPSTER_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// A grow-only device buffer owned by a context.
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+struct Ctx;
+void *ensure(Ctx &c, DevBuf &b, size_t bytes);
+
+// Periodic cell grid: n_c cells per axis of side L / n_c > R0.
+struct Grid {
+  int nc;
+  double L;
+  double scale;  // n_c / L
+  int64_t ncells() const { return int64_t(nc) * nc * nc; }
+};
+
+Grid make_grid(double L, double r0);
+
+// A catalogue sorted by cell, structure-of-arrays, coordinates in double
+// (exact for single-precision inputs).
+struct Sorted {
+  int64_t n = 0;
+  const double *x = nullptr, *y = nullptr, *z = nullptr, *w = nullptr;
+  const uint8_t *m = nullptr;      // primary mask per sorted particle (may be null)
+  const int64_t *cell_start = nullptr; // [ncells + 1]
+};
+
+// Pair stream for the power spectrum: one entry per unordered pair inside R0.
+// mu and ww are kept in double in both forms: L_l(mu) has slopes up to
+// l(l+1)/2, so a single-precision mu would cost ~1e-6 at l = 6.
+struct PkPairs {
+  double *r = nullptr;
+  void *mu = nullptr;
+  void *ww = nullptr;
+};
+
+// Scratch of one catalogue's cell list.
+struct CellScratch {
+  DevBuf cell, count, start, cursor, idx, x, y, z, w, m, bad, scan_tmp;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint64_t mem_cap = 0;
+  uint64_t mem_used = 0;
+  std::string last_error;
+  CellScratch cells_d, cells_r;
+  DevBuf pos_in, w_in, mask_in, rpos_in, rw_in, rmask_in;
+  DevBuf pair_cnt, pair_ord, pair_off, pair_total;
+  DevBuf pr, pmu, pww, pux, puy, puz;
+  DevBuf edges, partial, merged, ordered_count;
+  DevBuf bk_prim_off, bk_partial;
+  // W~^a depends only on (R0, k_a, k_{a+1}); repeated calls reuse it.
+  std::map<std::tuple<double, double, double>, double> wtilde_cache;
+};
+
+// W~^a for each bin, through the context's cache.
+void wtilde_bins(Ctx &c, double r0, int n_k, const double *k_edges, double *out);
+
+// ---------------------------------------------------------------- kernels
+// Cell list: sorts `n` points into the grid and fills `out` (device).
+Sorted build_cells(Ctx &c, CellScratch &s, const Grid &g, const void *pos, const void *w,
+                   const uint8_t *mask_dev, int64_t n, int dtype);
+
+// Exclusive scan of n int64 values (in-place allowed); out has n + 1 entries.
+void scan_i64(Ctx &c, const int64_t *in, int64_t *out, int64_t n, DevBuf &tmp);
+
+// Power-spectrum pair enumeration over home cells [c0, c1): count pass fills
+// cnt[cell] (entries to write) and adds the ordered-pair multiplicity to
+// *ordered; write pass stores entries at off[cell] - base.
+void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, double r0, int64_t *cnt,
+                    unsigned long long *ordered);
+void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, int los, bool fp64,
+                    const int64_t *off, int64_t base, int64_t c0, int64_t c1, PkPairs out);
+
+// Pair-weight sweep: adds into partial[nwaves][n_ell][n_edges] (zeroed by the
+// caller before the first chunk).  Returns the number of waves (partial rows).
+int pk_sweep(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0,
+             const double *edges_dev, int n_edges, double *partial, int nwaves_fixed);
+int pk_sweep_waves(Ctx &c);
+void merge_partials(Ctx &c, const double *partial, int rows, int cols, double *out);
+
+// Host analytic terms.
+double wtilde_bin(double r0, double k1, double k2);
+
+}  // namespace hipster

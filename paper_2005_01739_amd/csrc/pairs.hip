@@ -1,0 +1,148 @@
+// Pair enumeration for the power spectrum: every unordered pair {i, j} inside
+// R0 of a periodic box is found once by a half stencil of 14 cells (the home
+// cell with i < j, and 13 forward neighbours with all i, j), each neighbour
+// carrying its periodic image shift.  Pairs are compacted wave-by-wave
+// (ballot + popcount) into a coalesced stream (r, mu, w_i w_j m_ij) in double precision, written
+// in a deterministic order: a count pass sizes each home cell's output, an
+// exclusive scan gives offsets, and a write pass repeats the same tests.
+//
+// The separation is the paper's pair vector x_i - x_j at the periodic image
+// inside R0 (Sec. 2 pair counts; Sec. 3 periodic box); its squared length is
+// (dx^2 + dy^2) + dz^2 in double precision without contraction, the predicate
+// that defines the integer pair count.
+#include "common.h"
+#include "specfun.h"
+
+namespace hipster {
+
+// Half stencil: (0,0,0) first, then the 13 offsets lexicographically after it.
+__device__ inline void half_stencil(int s, int &ox, int &oy, int &oz) {
+  if (s == 0) {
+    ox = oy = oz = 0;
+    return;
+  }
+  int t = s + 13;  // index in the 27-cell cube ordered (ox, oy, oz) in -1..1
+  ox = t / 9 - 1;
+  oy = (t / 3) % 3 - 1;
+  oz = t % 3 - 1;
+}
+
+__device__ inline int wrap_axis(int v, int nc, int &shift) {
+  shift = 0;
+  if (v >= nc) {
+    shift = 1;
+    return v - nc;
+  }
+  if (v < 0) {
+    shift = -1;
+    return v + nc;
+  }
+  return v;
+}
+
+__device__ inline double image(double d, int shift, double L) {
+  // x_i - (x_j + shift * L), the neighbour image's offset; exact whenever the
+  // result is inside R0 <= L/2 (Sterbenz).
+  return shift > 0 ? d - L : (shift < 0 ? d + L : d);
+}
+
+__device__ inline double sq_norm_exact(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  double a = dx * dx;
+  double b = dy * dy;
+  double c = dz * dz;
+  return (a + b) + c;
+}
+
+template <bool WRITE, typename T>
+__global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, double r02, int los,
+                                                 int64_t *__restrict__ cnt,
+                                                 unsigned long long *__restrict__ ordered,
+                                                 const int64_t *__restrict__ off, int64_t base,
+                                                 int64_t c0, double *__restrict__ out_r,
+                                                 T *__restrict__ out_mu, T *__restrict__ out_ww) {
+  const int64_t cell = c0 + blockIdx.x;
+  const int lane = threadIdx.x;
+  const int cz = int(cell % nc), cy = int((cell / nc) % nc), cx = int(cell / (int64_t(nc) * nc));
+  const int64_t hs = s.cell_start[cell];
+  const int ni = int(s.cell_start[cell + 1] - hs);
+  int64_t written = 0;
+  unsigned long long ord = 0;
+  const int64_t wbase = WRITE ? off[cell] - base : 0;
+  for (int st = 0; st < 14 && ni > 0; ++st) {
+    int ox, oy, oz, sx, sy, sz;
+    half_stencil(st, ox, oy, oz);
+    const int nx = wrap_axis(cx + ox, nc, sx), ny = wrap_axis(cy + oy, nc, sy), nz = wrap_axis(cz + oz, nc, sz);
+    const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
+    const int64_t js = s.cell_start[nb];
+    const int nj = int(s.cell_start[nb + 1] - js);
+    if (nj == 0) continue;
+    const bool self = (st == 0);
+    const uint32_t total = uint32_t(ni) * uint32_t(nj);
+    for (uint32_t q0 = 0; q0 < total; q0 += 64) {
+      const uint32_t q = q0 + lane;
+      bool hit = false;
+      double r = 0.0, mu = 0.0, ww = 0.0;
+      if (q < total) {
+        const uint32_t ii = q / uint32_t(nj), jj = q - ii * uint32_t(nj);
+        if (!self || jj > ii) {
+          const int64_t i = hs + ii, j = js + jj;
+          const double dx = image(s.x[i] - s.x[j], sx, L);
+          const double dy = image(s.y[i] - s.y[j], sy, L);
+          const double dz = image(s.z[i] - s.z[j], sz, L);
+          const double r2 = sq_norm_exact(dx, dy, dz);
+          if (r2 < r02) {
+            const int mult = s.m ? int(s.m[i]) + int(s.m[j]) : 2;
+            ord += unsigned(mult);
+            if (mult > 0) {
+              hit = true;
+              if (WRITE) {
+                r = sqrt(r2);
+                const double dl = los == 0 ? dx : (los == 1 ? dy : dz);
+                mu = r > 0.0 ? dl / r : 0.0;
+                ww = s.w[i] * s.w[j] * double(mult);
+              }
+            }
+          }
+        }
+      }
+      const unsigned long long bal = __ballot(hit);
+      if (WRITE && hit) {
+        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        const int64_t k = wbase + written + pre;
+        out_r[k] = r;
+        out_mu[k] = T(mu);
+        out_ww[k] = T(ww);
+      }
+      written += __popcll(bal);
+    }
+  }
+  if (!WRITE) {
+    for (int o = 32; o > 0; o >>= 1) ord += __shfl_xor(ord, o);
+    if (lane == 0) {
+      cnt[cell] = written;
+      if (ord) atomicAdd(ordered, ord);
+    }
+  }
+}
+
+void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, double r0, int64_t *cnt,
+                    unsigned long long *ordered) {
+  const int64_t ncells = g.ncells();
+  k_pk_pairs<false, double><<<dim3(unsigned(ncells)), dim3(64), 0, c.stream>>>(
+      s, g.nc, g.L, r0 * r0, 2, cnt, ordered, nullptr, 0, 0, nullptr, nullptr, nullptr);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, int los, bool fp64,
+                    const int64_t *off, int64_t base, int64_t c0, int64_t c1, PkPairs out) {
+  if (c1 <= c0) return;
+  const dim3 grid(unsigned(c1 - c0));
+  (void)fp64;
+  k_pk_pairs<true, double><<<grid, dim3(64), 0, c.stream>>>(
+      s, g.nc, g.L, r0 * r0, los, nullptr, nullptr, off, base, c0, out.r,
+      static_cast<double *>(out.mu), static_cast<double *>(out.ww));
+  HIPSTER_HIP(hipGetLastError());
+}
+
+}  // namespace hipster

@@ -1,0 +1,137 @@
+// Power-spectrum pair-weight sweep (the dominant cost; Sec. 9 of the paper
+// names the Bessel weights the limiting step).
+//
+// For each unordered pair (r, mu, w_i w_j m_ij) and each bin edge k_e the
+// kernel adds c_l G_l(k_e r) to a per-lane double accumulator, with
+// c_l = w_i w_j m_ij W(r/R0) L_l(mu).  The bin values follow on the host as
+// S^a_l = 3 (2l+1) (-i)^l [k_{a+1}^3 E_l(a+1) - k_a^3 E_l(a)] / (k_{a+1}^3 - k_a^3)
+// (Sec. 3, binned estimator with eq. jla-def).  Edges are processed in chunks
+// of kChunk so the accumulators stay in registers; the pair stream is re-read
+// once per chunk.  Each wave reduces its lanes with cross-lane shuffles and
+// adds its sums to its own row of `partial`; rows are merged in a fixed order,
+// so results are bitwise reproducible.
+#include <type_traits>
+
+#include "common.h"
+#include "specfun.h"
+
+namespace hipster {
+
+constexpr int kSweepBlock = 256;
+constexpr int kChunk = 12;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int NE, bool FP64>
+__global__ __launch_bounds__(kSweepBlock) void k_pk_sweep(const double *__restrict__ pr,
+                                                          const void *__restrict__ pmu_,
+                                                          const void *__restrict__ pww_,
+                                                          int64_t npairs, double inv_r0,
+                                                          const double *__restrict__ edges,
+                                                          int n_edges, double *__restrict__ partial) {
+  using T = double;  // per-pair weights and mu are evaluated in double in both forms
+  const T *pmu = static_cast<const T *>(pmu_);
+  const T *pww = static_cast<const T *>(pww_);
+  const int64_t gtid = int64_t(blockIdx.x) * kSweepBlock + threadIdx.x;
+  const int64_t stride = int64_t(gridDim.x) * kSweepBlock;
+  const int wave = int(gtid >> 6), lane = threadIdx.x & 63;
+  for (int e0 = 0; e0 < n_edges; e0 += kChunk) {
+    double acc[NE][kChunk];
+#pragma unroll
+    for (int i = 0; i < NE; ++i)
+#pragma unroll
+      for (int cc = 0; cc < kChunk; ++cc) acc[i][cc] = 0.0;
+    for (int64_t p = gtid; p < npairs; p += stride) {
+      const double r = pr[p];
+      const T mu = pmu[p], ww = pww[p];
+      const T wt = ww * window<T>(T(r * inv_r0));
+      T L[NE];
+      legendre_even<T, NE>(mu, L);
+      double cf[NE];
+#pragma unroll
+      for (int i = 0; i < NE; ++i) cf[i] = double(wt * L[i]);
+#pragma unroll
+      for (int cc = 0; cc < kChunk; ++cc) {
+        const int e = e0 + cc;
+        if (e < n_edges) {
+          const double u = edges[e] * r;
+          if constexpr (FP64) {
+            const Gv<double, NE> G = G_fp64<NE, 2>(u);
+#pragma unroll
+            for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i], acc[i][cc]);
+          } else {
+            const Gv<double, NE> G = G_mixed<NE, 2>(u);
+#pragma unroll
+            for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i], acc[i][cc]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i)
+#pragma unroll
+      for (int cc = 0; cc < kChunk; ++cc) {
+        const double v = wave_sum(acc[i][cc]);
+        const int e = e0 + cc;
+        if (lane == 0 && e < n_edges) partial[(int64_t(wave) * NE + i) * n_edges + e] += v;
+      }
+  }
+}
+
+int pk_sweep_waves(Ctx &c) {
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c.device) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  return cus * 16;  // 4 blocks of 4 waves per CU
+}
+
+template <int NE>
+static void launch_sweep(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, double inv_r0,
+                         const double *edges, int n_edges, double *partial, int nwaves) {
+  const dim3 grid(unsigned(nwaves / 4)), block(kSweepBlock);
+  if (fp64)
+    k_pk_sweep<NE, true><<<grid, block, 0, c.stream>>>(p.r, p.mu, p.ww, npairs, inv_r0, edges, n_edges, partial);
+  else
+    k_pk_sweep<NE, false><<<grid, block, 0, c.stream>>>(p.r, p.mu, p.ww, npairs, inv_r0, edges, n_edges, partial);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+int pk_sweep(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0,
+             const double *edges_dev, int n_edges, double *partial, int nwaves) {
+  const double inv = 1.0 / r0;
+  switch (n_ell) {
+    case 1: launch_sweep<1>(c, p, npairs, fp64, inv, edges_dev, n_edges, partial, nwaves); break;
+    case 2: launch_sweep<2>(c, p, npairs, fp64, inv, edges_dev, n_edges, partial, nwaves); break;
+    case 3: launch_sweep<3>(c, p, npairs, fp64, inv, edges_dev, n_edges, partial, nwaves); break;
+    default: launch_sweep<4>(c, p, npairs, fp64, inv, edges_dev, n_edges, partial, nwaves); break;
+  }
+  return nwaves;
+}
+
+// out[col] = sum over rows of partial[row][col], summed in a fixed order.
+__global__ __launch_bounds__(256) void k_merge(const double *__restrict__ partial, int rows, int cols,
+                                               double *__restrict__ out) {
+  __shared__ double sh[256];
+  const int col = blockIdx.x, t = threadIdx.x;
+  double s = 0.0;
+  for (int r = t; r < rows; r += 256) s += partial[int64_t(r) * cols + col];
+  sh[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[col] = sh[0];
+}
+
+void merge_partials(Ctx &c, const double *partial, int rows, int cols, double *out) {
+  k_merge<<<dim3(unsigned(cols)), dim3(256), 0, c.stream>>>(partial, rows, cols, out);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+}  // namespace hipster

@@ -1,0 +1,260 @@
+// Device special functions for the pair weights of the periodic-box
+// power-spectrum and bispectrum estimators (Philcox 2020, arXiv:2005.01739).
+//
+// The bin-averaged spherical Bessel function (Sec. 3, eq. jla-def) is
+//   jbar^a_l(r) = 3 [D_l(k_{a+1} r) - D_l(k_a r)] / (r^3 (k_{a+1}^3 - k_a^3)),
+// with D_l(u) = int u^2 j_l(u) du (Appendix C).  The kernels accumulate, per
+// bin edge e, G_l(k_e r) = Dt_l(k_e r) / (k_e r)^3 where Dt_l(u) = D_l(u) -
+// D_l(0) = int_0^u t^2 j_l(t) dt, so that
+//   jbar^a_l(r) = 3 [k_{a+1}^3 G_l(k_{a+1} r) - k_a^3 G_l(k_a r)] / (k_{a+1}^3 - k_a^3).
+// G_l is bounded (G_0(0) = 1/3, G_{l>0}(0) = 0) and smooth, so pairs at r -> 0
+// need no special case.
+//
+// Running the Appendix C recursion (I_0 = Si, I_1 = -j_0) symbolically gives
+// D_l(u) = c_l Si(u) + a_l(u) sin u + b_l(u) cos u with Laurent polynomials
+// a_l, b_l and c_l = 0, 3, 15/2, 105/8 for even l = 0, 2, 4, 6 (c_l = 0 for
+// odd l); D_l(0) = 0, -2, 0, -8, 0, -16, 0 for l = 0..6.  For large u the sine
+// integral is written through its auxiliary functions,
+//   Si(u) = pi/2 - f(u) cos u - g(u) sin u,
+// so every term is a smooth amplitude times sin u or cos u.  Below U_BIG the
+// closed form cancels badly (the Laurent terms grow like u^-l), and G_l is
+// summed from its Taylor series instead.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "coeffs.h"
+
+namespace hipster {
+
+constexpr int kLMax = 6;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kHalfPi = 1.57079632679489661923;
+constexpr double kTwoOverPi = 0.63661977236758134308;
+// pi/2 split for Cody-Waite reduction: the high part has 33 significant bits,
+// so n * kPio2Hi is exact for |n| < 2^20.
+constexpr double kPio2Hi = 1.5707963267341256141662597656e+00;
+constexpr double kPio2Lo = 6.0771005065061922518e-11;
+// Below this argument the Taylor series needs only 14 terms.
+constexpr double kUSmall = 2.0;
+
+// Smooth truncation window W(x), x = r / R0 (Sec. 2, eq. window_defn).
+template <typename T>
+__host__ __device__ inline T window(T x) {
+  if (x < T(0.5)) return T(1);
+  if (x < T(0.75)) {
+    T t = T(2) * x - T(1);
+    T t3 = t * t * t;
+    return T(1) - T(8) * t3 + T(8) * t3 * t;
+  }
+  if (x < T(1)) {
+    T t = x - T(1);
+    T t3 = t * t * t;
+    return T(-64) * t3 - T(128) * t3 * t;
+  }
+  return T(0);
+}
+
+// Legendre polynomials of even order, L_0 .. L_{2(NE-1)}.
+template <typename T, int NE>
+__host__ __device__ inline void legendre_even(T mu, T (&L)[NE]) {
+  T m2 = mu * mu;
+  L[0] = T(1);
+  if (NE > 1) L[1] = T(1.5) * m2 - T(0.5);
+  if (NE > 2) L[2] = (T(35) * m2 * m2 - T(30) * m2 + T(3)) * T(0.125);
+  if (NE > 3) L[3] = ((T(231) * m2 - T(315)) * m2 * m2 + T(105) * m2 - T(5)) * T(0.0625);
+}
+
+// --------------------------------------------------------------- Taylor form
+// G_l(u) = u^l sum_s TAYLOR_G[l][s] (u^2)^s, double precision, NT terms.
+template <int NT>
+__device__ inline double taylor_G64(int l, double v, double ul) {
+  double p = TAYLOR_G[l][NT - 1];
+#pragma unroll
+  for (int s = NT - 2; s >= 0; --s) p = fma(p, v, TAYLOR_G[l][s]);
+  return p * ul;
+}
+
+// ------------------------------------------------------ closed-form pieces
+// Dt_l(u) from sin u, cos u, Si(u) and w = 1/u (closed forms of the Appendix C
+// recursion, minus D_l(0)).
+template <typename T>
+__device__ inline T Dt_closed(int l, T u, T w, T s, T c, T si) {
+  switch (l) {
+    case 0: return s - u * c;
+    case 1: return T(2) - u * s - T(2) * c;
+    case 2: return T(3) * si - T(4) * s + u * c;
+    case 3: return T(8) + (u - T(15) * w) * s + T(7) * c;
+    case 4: {
+      T w2 = w * w;
+      return T(7.5) * si + (T(11) - T(52.5) * w2) * s + (T(52.5) * w - u) * c;
+    }
+    case 5: {
+      T w2 = w * w;
+      return T(16) + ((T(105) - T(315) * w2) * w - u) * s + (T(315) * w2 - T(16)) * c;
+    }
+    default: {
+      T w2 = w * w;
+      return T(13.125) * si + ((T(-2598.75) * w2 + T(1063.125)) * w2 - T(22)) * s +
+             (u + (T(2598.75) * w2 - T(196.875)) * w) * c;
+    }
+  }
+}
+
+// Clenshaw sum of a Chebyshev series at x in [-1, 1].
+template <int N>
+__device__ inline double clenshaw(const double (&c)[N], double x) {
+  double b1 = 0.0, b2 = 0.0, x2 = 2.0 * x;
+#pragma unroll
+  for (int k = N - 1; k >= 1; --k) {
+    double b0 = fma(x2, b1, c[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return fma(x, b1, c[0] - b2);
+}
+
+// Values G_l(u) for l = 0, LSTEP, 2 LSTEP, ... (NL of them), returned in
+// registers.
+template <typename T, int NL>
+struct Gv {
+  T v[NL];
+};
+
+// Taylor branch in double precision (u < U_BIG); kept out of line so that
+// the kernels' edge loops stay compact.
+template <int NL, int LSTEP>
+__device__ __noinline__ Gv<double, NL> G_taylor64(double u) {
+  Gv<double, NL> G;
+  double v = u * u, ul = 1.0;
+  // 14 terms reach 1e-17 relative for u < 2; 32 terms for u < U_BIG.
+  const bool few = u < kUSmall;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    if (i > 0) {
+#pragma unroll
+      for (int q = 0; q < LSTEP; ++q) ul *= u;
+    }
+    G.v[i] = few ? taylor_G64<14>(i * LSTEP, v, ul) : taylor_G64<HIPSTER_N_TAYLOR>(i * LSTEP, v, ul);
+  }
+  return G;
+}
+
+// ----------------------------------------------------------- FP64 form
+template <int NL, int LSTEP>
+__device__ __noinline__ Gv<double, NL> G_fp64(double u) {
+  if (u < HIPSTER_U_BIG) return G_taylor64<NL, LSTEP>(u);
+  Gv<double, NL> G;
+  double s, c;
+  sincos(u, &s, &c);
+  double w = 1.0 / u;
+  double x = 2.0 * HIPSTER_U_BIG * w - 1.0;
+  double f = clenshaw(CHEB_F64, x) * w;
+  double g = clenshaw(CHEB_G64, x) * w * w;
+  double si = kHalfPi - f * c - g * s;
+  double w3 = w * w * w;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) G.v[i] = Dt_closed<double>(i * LSTEP, u, w, s, c, si) * w3;
+  return G;
+}
+
+// ---------------------------------------------------------- mixed form
+// G_l(u) with the phase u (double) reduced modulo pi/2 in double precision and
+// the smooth amplitudes in single precision.  Below U_BIG the Taylor series is
+// summed in double (kUSmall <= u) or single (u < kUSmall) precision.
+__device__ inline void sincos_reduced(double u, float &s, float &c) {
+  double n = rint(u * kTwoOverPi);
+  double t = fma(-n, kPio2Hi, u);
+  t = fma(-n, kPio2Lo, t);
+  float x = float(t), x2 = x * x;
+  // Taylor polynomials of sin and cos on |x| <= pi/4 (truncation < 3e-9).
+  float sp = fmaf(fmaf(fmaf(fmaf(2.7557319e-6f, x2, -1.9841270e-4f), x2, 8.3333333e-3f), x2,
+                       -1.6666667e-1f), x2, 1.0f) * x;
+  float cp = fmaf(fmaf(fmaf(fmaf(fmaf(-2.7557319e-7f, x2, 2.4801587e-5f), x2, -1.3888889e-3f), x2,
+                            4.1666667e-2f), x2, -0.5f), x2, 1.0f);
+  int q = int(int64_t(n) & 3);
+  float ss = (q & 1) ? cp : sp;
+  float cc = (q & 1) ? sp : cp;
+  s = (q & 2) ? -ss : ss;
+  c = ((q + 1) & 2) ? -cc : cc;
+}
+
+// sin and cos of u in double precision from the same reduction: Taylor
+// polynomials through x^17 / x^18 on |x| <= pi/4 (truncation < 2e-17).
+__device__ inline void sincos_reduced64(double u, double &s, double &c) {
+  double n = rint(u * kTwoOverPi);
+  double x = fma(-n, kPio2Hi, u);
+  x = fma(-n, kPio2Lo, x);
+  double x2 = x * x;
+  double sp = 2.8114572543455206e-15;  // 1/17!
+  sp = fma(sp, x2, -7.6471637318198165e-13);
+  sp = fma(sp, x2, 1.6059043836821613e-10);
+  sp = fma(sp, x2, -2.5052108385441720e-08);
+  sp = fma(sp, x2, 2.7557319223985893e-06);
+  sp = fma(sp, x2, -1.9841269841269841e-04);
+  sp = fma(sp, x2, 8.3333333333333333e-03);
+  sp = fma(sp, x2, -1.6666666666666667e-01);
+  sp = fma(sp * x2, x, x);
+  double cp = -1.5619206968586225e-16;  // -1/18!
+  cp = fma(cp, x2, 4.7794773323873853e-14);
+  cp = fma(cp, x2, -1.1470745597729725e-11);
+  cp = fma(cp, x2, 2.0876756987868099e-09);
+  cp = fma(cp, x2, -2.7557319223985891e-07);
+  cp = fma(cp, x2, 2.4801587301587302e-05);
+  cp = fma(cp, x2, -1.3888888888888889e-03);
+  cp = fma(cp, x2, 4.1666666666666667e-02);
+  cp = fma(cp, x2, -0.5);
+  cp = fma(cp, x2, 1.0);
+  int q = int(int64_t(n) & 3);
+  double ss = (q & 1) ? cp : sp;
+  double cc = (q & 1) ? sp : cp;
+  s = (q & 2) ? -ss : ss;
+  c = ((q + 1) & 2) ? -cc : cc;
+}
+
+template <int N>
+__device__ inline float horner32(const float (&p)[N], float t) {
+  float r = p[N - 1];
+#pragma unroll
+  for (int k = N - 2; k >= 0; --k) r = fmaf(r, t, p[k]);
+  return r;
+}
+
+// For l >= 5 the Laurent amplitudes of the closed form grow like 10^3 / u^4
+// near U_BIG and cancel against the Si term; single-precision amplitudes lose
+// too much there, so when such an l is requested the closed form keeps sin,
+// cos and the amplitudes in double precision (f and g stay single: they enter
+// multiplied by c_l / u and only need ~1e-8 relative accuracy).  Below U_BIG
+// the Taylor series is summed in double precision and kept in double: bin
+// averages difference neighbouring edges, which amplifies any rounding of
+// these slowly varying values by up to k / (3 dk).
+template <int NL, int LSTEP>
+__device__ inline Gv<double, NL> G_mixed(double u) {
+  constexpr bool kHighL = (NL - 1) * LSTEP >= 5;
+  if (u < HIPSTER_U_BIG) return G_taylor64<NL, LSTEP>(u);
+  Gv<double, NL> G;
+  float uf = float(u);
+  float w = __builtin_amdgcn_rcpf(uf);
+  float t = float(HIPSTER_U_BIG) * w;
+  float f = horner32(POLY_F32, t) * w;
+  float g = horner32(POLY_G32, t) * w * w;
+  if constexpr (kHighL) {
+    double s, c;
+    sincos_reduced64(u, s, c);
+    double wd = 1.0 / u;
+    double si = kHalfPi - double(f) * c - double(g) * s;
+    double w3 = wd * wd * wd;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) G.v[i] = Dt_closed<double>(i * LSTEP, u, wd, s, c, si) * w3;
+  } else {
+    float s, c;
+    sincos_reduced(u, s, c);
+    float si = float(kHalfPi) - f * c - g * s;
+    float w3 = w * w * w;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) G.v[i] = double(Dt_closed<float>(i * LSTEP, uf, w, s, c, si) * w3);
+  }
+  return G;
+}
+
+}  // namespace hipster
