@@ -139,6 +139,27 @@ struct Timer {
   }
 };
 
+// Sum of a catalogue's weights in input order (FP64; n for unit weights).
+static double weight_sum(const hipster_points *pts) {
+  const int64_t n = pts->n;
+  if (!pts->w) return double(n);
+  const size_t esz = pts->dtype == HIPSTER_F32 ? 4 : 8;
+  std::vector<unsigned char> raw(size_t(n) * esz);
+  if (pts->on_device) HIPSTER_HIP(hipMemcpy(raw.data(), pts->w, size_t(n) * esz, hipMemcpyDeviceToHost));
+  else memcpy(raw.data(), pts->w, size_t(n) * esz);
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    s += esz == 4 ? double(reinterpret_cast<const float *>(raw.data())[i]) : reinterpret_cast<const double *>(raw.data())[i];
+  return s;
+}
+
+static int device_cus(Ctx &c) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c.device) == hipSuccess && prop.multiProcessorCount > 0)
+    return prop.multiProcessorCount;
+  return 256;
+}
+
 // ---------------------------------------------------------- power spectrum
 static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, double *pk, hipster_diag *diag) {
   check_points(pts, "data", q ? q->box : 0.0);
@@ -220,23 +241,7 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
 
   // finalize (host, FP64): S^a_l, W~^a, P^a_l
-  double p1 = 0.0;
-  if (pts->w) {
-    // sum of weights in input order (FP64)
-    std::vector<double> hw(static_cast<size_t>(n));
-    if (pts->on_device) {
-      std::vector<unsigned char> raw(size_t(n) * esz);
-      HIPSTER_HIP(hipMemcpy(raw.data(), pts->w, size_t(n) * esz, hipMemcpyDeviceToHost));
-      for (int64_t i = 0; i < n; ++i)
-        hw[size_t(i)] = esz == 4 ? double(reinterpret_cast<float *>(raw.data())[i]) : reinterpret_cast<double *>(raw.data())[i];
-    } else {
-      for (int64_t i = 0; i < n; ++i)
-        hw[size_t(i)] = esz == 4 ? double(static_cast<const float *>(pts->w)[i]) : static_cast<const double *>(pts->w)[i];
-    }
-    for (double v : hw) p1 += v;
-  } else {
-    p1 = double(n);
-  }
+  const double p1 = weight_sum(pts);
   const double V = q->box * q->box * q->box, nw = p1 / V, norm = 1.0 / (nw * nw * V);
   std::vector<double> wt(static_cast<size_t>(q->n_k));
   wtilde_bins(c, q->r0, q->n_k, q->k_edges, wt.data());
@@ -263,6 +268,162 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
     diag->sweep_launches = launches;
   }
   (void)total;
+}
+
+// -------------------------------------------------------------- bispectrum
+static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, const hipster_params *q, double *bk,
+                   hipster_diag *diag) {
+  check_points(dp, "data", q ? q->box : 0.0);
+  check_params(q, true);
+  if (!bk) throw Error{HIPSTER_EINVAL, "NULL output"};
+  if (dp->n < 2) throw Error{HIPSTER_EINVAL, "need at least two points"};
+  const bool have_r = rp && rp->n > 0;
+  if (have_r) check_points(rp, "randoms", q->box);
+  HIPSTER_HIP(hipSetDevice(c.device));
+  Timer tm(c);
+  hipEvent_t t0 = tm.mark();
+
+  const int64_t n = dp->n, nr = have_r ? rp->n : 0;
+  const size_t esz = dp->dtype == HIPSTER_F32 ? 4 : 8;
+  const void *pos = device_view(c, c.pos_in, dp->pos, n * 3 * int64_t(esz), dp->on_device);
+  const void *w = device_view(c, c.w_in, dp->w, n * int64_t(esz), dp->on_device);
+  const uint8_t *mask = device_mask(c, c.mask_in, q->primary_mask, n);
+  const Grid g = make_grid(q->box, q->r0);
+  const Sorted sd = build_cells(c, c.cells_d, g, pos, w, mask, n, dp->dtype);
+  Sorted sr;
+  if (have_r) {
+    const size_t rsz = rp->dtype == HIPSTER_F32 ? 4 : 8;
+    const void *rpos = device_view(c, c.rpos_in, rp->pos, nr * 3 * int64_t(rsz), rp->on_device);
+    const void *rw = device_view(c, c.rw_in, rp->w, nr * int64_t(rsz), rp->on_device);
+    const uint8_t *rmask = device_mask(c, c.rmask_in, q->random_mask, nr);
+    sr = build_cells(c, c.cells_r, g, rpos, rw, rmask, nr, rp->dtype);
+  }
+  hipEvent_t t1 = tm.mark();
+
+  const int NK = q->n_k, NL = q->ell_max + 1, NT = NK * (NK + 1) / 2, nC = NL * NT, rowlen = 2 * nC + NK;
+  const bool fp64 = q->precision == HIPSTER_FP64;
+  std::vector<double> coef(static_cast<size_t>(NK));
+  for (int a = 0; a < NK; ++a) {
+    const double ka = q->k_edges[a], kb = q->k_edges[a + 1];
+    coef[size_t(a)] = 3.0 / (kb * kb * kb - ka * ka * ka);
+  }
+  double *edges = static_cast<double *>(ensure(c, c.edges, size_t(NK + 1) * 8));
+  double *coef_d = static_cast<double *>(ensure(c, c.bk_coef, size_t(NK) * 8));
+  HIPSTER_HIP(hipMemcpyAsync(edges, q->k_edges, size_t(NK + 1) * 8, hipMemcpyHostToDevice, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(coef_d, coef.data(), size_t(NK) * 8, hipMemcpyHostToDevice, c.stream));
+  const int nwaves = device_cus(c) * 8;
+  double *part[2];
+  part[0] = static_cast<double *>(ensure(c, c.bk_partial, size_t(nwaves) * rowlen * 8));
+  part[1] = static_cast<double *>(ensure(c, c.bk_partial_r, size_t(nwaves) * rowlen * 8));
+  HIPSTER_HIP(hipMemsetAsync(part[0], 0, size_t(nwaves) * rowlen * 8, c.stream));
+  HIPSTER_HIP(hipMemsetAsync(part[1], 0, size_t(nwaves) * rowlen * 8, c.stream));
+
+  uint64_t npairs[2] = {0, 0};
+  double ms_pairs = 0.0, ms_sweep = 0.0;
+  uint64_t launches = 0;
+  for (int set = 0; set < (have_r ? 2 : 1); ++set) {
+    const Sorted &prim = set == 0 ? sd : sr;
+    const int64_t np = prim.n;
+    int *pcnt = static_cast<int *>(ensure(c, c.bk_prim_cnt, size_t(np) * 4));
+    int64_t *pcnt64 = static_cast<int64_t *>(ensure(c, c.bk_prim_cnt64, size_t(np) * 8));
+    int64_t *poff = static_cast<int64_t *>(ensure(c, c.bk_prim_off, size_t(np + 1) * 8));
+    int *maxcnt = static_cast<int *>(ensure(c, c.bk_max, 16));
+    HIPSTER_HIP(hipMemsetAsync(maxcnt, 0, 4, c.stream));
+    HIPSTER_HIP(hipMemsetAsync(pcnt, 0, size_t(np) * 4, c.stream));
+    hipEvent_t a0 = tm.mark();
+    bk_pairs_count(c, prim, sd, g, q->r0, set == 0, pcnt, maxcnt);
+    widen_i32(c, pcnt, pcnt64, np);
+    scan_i64(c, pcnt64, poff, np, c.pair_total);
+    int64_t total = 0;
+    int hmax = 0;
+    HIPSTER_HIP(hipMemcpyAsync(&total, poff + np, 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipMemcpyAsync(&hmax, maxcnt, 4, hipMemcpyDeviceToHost, c.stream));
+    hipEvent_t a1 = tm.mark();
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    ms_pairs += Timer::ms(a0, a1);
+    npairs[set] = uint64_t(total);
+    if (total == 0) continue;
+    const int64_t cap = std::min<int64_t>(pair_chunk_capacity() / 2, total);
+    const int nchunks = int((total + cap - 1) / cap);
+    const int64_t bufn = cap + hmax;
+    BkPairs bp;
+    bp.r = static_cast<double *>(ensure(c, c.bpr, size_t(bufn) * 8));
+    bp.ux = static_cast<double *>(ensure(c, c.bux, size_t(bufn) * 8));
+    bp.uy = static_cast<double *>(ensure(c, c.buy, size_t(bufn) * 8));
+    bp.uz = static_cast<double *>(ensure(c, c.buz, size_t(bufn) * 8));
+    bp.wj = static_cast<double *>(ensure(c, c.bwj, size_t(bufn) * 8));
+    int64_t *bounds_d = static_cast<int64_t *>(ensure(c, c.bk_bounds, size_t(nchunks + 1) * 3 * 8));
+    chunk_bounds(c, poff, np, cap, nchunks, prim.scell, bounds_d);
+    std::vector<int64_t> bounds(size_t(nchunks + 1) * 3);
+    HIPSTER_HIP(hipMemcpyAsync(bounds.data(), bounds_d, bounds.size() * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    const int64_t ncells = g.ncells();
+    for (int k = 0; k < nchunks; ++k) {
+      const int64_t p_lo = bounds[size_t(3 * k)], p_hi = bounds[size_t(3 * k + 3)];
+      if (p_hi <= p_lo) continue;
+      const int64_t c_lo = bounds[size_t(3 * k + 1)];
+      const int64_t c_hi = (k + 1 < nchunks && p_hi < np) ? bounds[size_t(3 * k + 4)] + 1 : ncells;
+      const int64_t base = bounds[size_t(3 * k + 2)];
+      hipEvent_t b0 = tm.mark();
+      bk_pairs_write(c, prim, sd, g, q->r0, set == 0, p_lo, p_hi, c_lo, c_hi, poff, base, bp);
+      hipEvent_t b1 = tm.mark();
+      bk_sweep(c, bp, poff, base, p_lo, p_hi, prim.w, q->r0, edges, coef_d, NK, q->ell_max, set == 0, fp64, part[set],
+               rowlen, nwaves);
+      hipEvent_t b2 = tm.mark();
+      HIPSTER_HIP(hipEventSynchronize(b2));
+      ms_pairs += Timer::ms(b0, b1);
+      ms_sweep += Timer::ms(b1, b2);
+      ++launches;
+    }
+  }
+  double *merged = static_cast<double *>(ensure(c, c.merged, size_t(2 * rowlen) * 8));
+  merge_partials(c, part[0], nwaves, rowlen, merged);
+  merge_partials(c, part[1], nwaves, rowlen, merged + rowlen);
+  std::vector<double> M(static_cast<size_t>(2 * rowlen));
+  HIPSTER_HIP(hipMemcpyAsync(M.data(), merged, size_t(2 * rowlen) * 8, hipMemcpyDeviceToHost, c.stream));
+  hipEvent_t t3 = tm.mark();
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+
+  // assembly (Sec. 4 summary estimator), host FP64
+  const double p1 = weight_sum(dp), pr = have_r ? weight_sum(rp) : 0.0;
+  const double V = q->box * q->box * q->box, nw = p1 / V, sR = have_r ? p1 / pr : 0.0;
+  std::vector<double> wt(static_cast<size_t>(NK));
+  wtilde_bins(c, q->r0, NK, q->k_edges, wt.data());
+  const double *Md = M.data(), *Mr = M.data() + rowlen;
+  auto tri = [NK](int a, int b) {
+    if (a > b) std::swap(a, b);
+    return a * NK - a * (a - 1) / 2 + (b - a);
+  };
+  for (int l = 0; l < NL; ++l)
+    for (int a = 0; a < NK; ++a)
+      for (int b = 0; b < NK; ++b) {
+        const int t = l * NT + tri(a, b);
+        const size_t o = (size_t(l) * NK + a) * NK + b;
+        const double GD = Md[t], CD = Md[nC + t], GR = Mr[t], CR = Mr[nC + t];
+        const double sgn = (l & 1) ? -1.0 : 1.0;
+        double v = sgn * (2.0 * l + 1.0) / (V * nw * nw * nw) * ((GD - CD) - sR * (GR - CR));
+        if (l == 0) v += -(wt[size_t(a)] * Md[2 * nC + b] + wt[size_t(b)] * Md[2 * nC + a]) / (V * nw * nw) +
+                         2.0 * wt[size_t(a)] * wt[size_t(b)];
+        bk[o] = v;
+        if (diag) {
+          if (diag->gd) diag->gd[o] = GD;
+          if (diag->cd) diag->cd[o] = CD;
+          if (diag->gr) diag->gr[o] = GR;
+          if (diag->cr) diag->cr[o] = CR;
+        }
+      }
+  if (diag) {
+    if (diag->s0)
+      for (int b = 0; b < NK; ++b) diag->s0[b] = Md[2 * nC + b];
+    if (diag->wtilde) memcpy(diag->wtilde, wt.data(), size_t(NK) * 8);
+    diag->n_pairs = npairs[0];
+    diag->n_pairs_rand = npairs[1];
+    diag->ms_build = Timer::ms(t0, t1);
+    diag->ms_pairs = ms_pairs;
+    diag->ms_sweep = ms_sweep;
+    diag->ms_total = Timer::ms(t0, t3);
+    diag->sweep_launches = launches;
+  }
 }
 
 template <class F>
@@ -314,7 +475,9 @@ void hipster_destroy(hipster_ctx *ctx) {
   free_cells(c.cells_r);
   DevBuf *all[] = {&c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in, &c.rmask_in, &c.pair_cnt, &c.pair_ord,
                    &c.pair_off, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
-                   &c.partial, &c.merged, &c.ordered_count, &c.bk_prim_off, &c.bk_partial};
+                   &c.partial, &c.merged, &c.ordered_count, &c.bk_prim_cnt, &c.bk_prim_cnt64, &c.bk_prim_off,
+                   &c.bk_partial, &c.bk_partial_r, &c.bk_max, &c.bk_bounds, &c.bk_coef, &c.bpr, &c.bux, &c.buy,
+                   &c.buz, &c.bwj};
   for (DevBuf *b : all) free_buf(*b);
   delete ctx;
 }
@@ -322,6 +485,11 @@ void hipster_destroy(hipster_ctx *ctx) {
 hipster_status hipster_pk_ell(hipster_ctx *ctx, const hipster_points *pts, const hipster_params *prm, double *pk,
                               hipster_diag *diag) {
   return guarded(ctx, [&] { run_pk(ctx->c, pts, prm, pk, diag); });
+}
+
+hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data, const hipster_points *randoms,
+                              const hipster_params *prm, double *bk, hipster_diag *diag) {
+  return guarded(ctx, [&] { run_bk(ctx->c, data, randoms, prm, bk, diag); });
 }
 
 hipster_status hipster_wtilde(double r0, int32_t n_k, const double *k_edges, double *out) {

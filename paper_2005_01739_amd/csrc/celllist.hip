@@ -70,16 +70,24 @@ __global__ void k_sort_cells(const int64_t *__restrict__ start, int64_t ncells, 
 
 template <typename T>
 __global__ void k_gather(const T *__restrict__ pos, const T *__restrict__ w, const uint8_t *__restrict__ mask,
-                         const int *__restrict__ idx, int64_t n, double *__restrict__ x, double *__restrict__ y,
-                         double *__restrict__ z, double *__restrict__ ws, uint8_t *__restrict__ ms) {
+                         const int *__restrict__ idx, const int *__restrict__ cell, int64_t n,
+                         double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
+                         double *__restrict__ ws, uint8_t *__restrict__ ms, int *__restrict__ scell) {
   int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int i = idx[k];
+  scell[k] = cell[i];
   x[k] = double(pos[3 * int64_t(i)]);
   y[k] = double(pos[3 * int64_t(i) + 1]);
   z[k] = double(pos[3 * int64_t(i) + 2]);
   ws[k] = w ? double(w[i]) : 1.0;
   if (ms) ms[k] = mask[i] ? 1 : 0;
+}
+
+void widen_i32(Ctx &c, const int *in, int64_t *out, int64_t n) {
+  if (n <= 0) return;
+  k_widen<<<dim3(unsigned((n + 255) / 256)), 256, 0, c.stream>>>(in, out, n);
+  HIPSTER_HIP(hipGetLastError());
 }
 
 // ----------------------------------------------------------------- scan
@@ -161,9 +169,23 @@ static Sorted build_cells_t(Ctx &c, CellScratch &s, const Grid &g, const T *pos,
   double *z = static_cast<double *>(ensure(c, s.z, size_t(n) * sizeof(double)));
   double *ws = static_cast<double *>(ensure(c, s.w, size_t(n) * sizeof(double)));
   uint8_t *ms = mask_dev ? static_cast<uint8_t *>(ensure(c, s.m, size_t(n))) : nullptr;
+  int *scell = static_cast<int *>(ensure(c, s.scell, size_t(n) * sizeof(int)));
   int *bad = static_cast<int *>(ensure(c, s.bad, sizeof(int) * 4));
 
   HIPSTER_HIP(hipMemsetAsync(count, 0, size_t(ncells) * sizeof(int), c.stream));
+  if (n == 0) {
+    HIPSTER_HIP(hipMemsetAsync(start, 0, size_t(ncells + 1) * sizeof(int64_t), c.stream));
+    Sorted out;
+    out.n = 0;
+    out.x = x;
+    out.y = y;
+    out.z = z;
+    out.w = ws;
+    out.m = ms;
+    out.cell_start = start;
+    out.scell = scell;
+    return out;
+  }
   HIPSTER_HIP(hipMemsetAsync(cursor, 0, size_t(ncells) * sizeof(int), c.stream));
   HIPSTER_HIP(hipMemsetAsync(bad, 0, sizeof(int), c.stream));
   const unsigned nbp = unsigned((n + 255) / 256), nbc = unsigned((ncells + 255) / 256);
@@ -176,7 +198,7 @@ static Sorted build_cells_t(Ctx &c, CellScratch &s, const Grid &g, const T *pos,
   scan_i64(c, wide, start, ncells, s.scan_tmp);
   k_scatter<<<nbp, 256, 0, c.stream>>>(cell, n, start, cursor, idx);
   k_sort_cells<<<nbc, 256, 0, c.stream>>>(start, ncells, idx);
-  k_gather<T><<<nbp, 256, 0, c.stream>>>(pos, w, mask_dev, idx, n, x, y, z, ws, ms);
+  k_gather<T><<<nbp, 256, 0, c.stream>>>(pos, w, mask_dev, idx, cell, n, x, y, z, ws, ms, scell);
   HIPSTER_HIP(hipGetLastError());
   Sorted out;
   out.n = n;
@@ -186,6 +208,7 @@ static Sorted build_cells_t(Ctx &c, CellScratch &s, const Grid &g, const T *pos,
   out.w = ws;
   out.m = ms;
   out.cell_start = start;
+  out.scell = scell;
   return out;
 }
 

@@ -56,6 +56,13 @@ struct Sorted {
   const double *x = nullptr, *y = nullptr, *z = nullptr, *w = nullptr;
   const uint8_t *m = nullptr;      // primary mask per sorted particle (may be null)
   const int64_t *cell_start = nullptr; // [ncells + 1]
+  const int *scell = nullptr;          // cell of each sorted point
+};
+
+// Pair stream for the bispectrum: per primary, its neighbours inside R0 as
+// (r, unit vector x_pj / r, w_j), all double.
+struct BkPairs {
+  double *r = nullptr, *ux = nullptr, *uy = nullptr, *uz = nullptr, *wj = nullptr;
 };
 
 // Pair stream for the power spectrum: one entry per unordered pair inside R0.
@@ -69,7 +76,7 @@ struct PkPairs {
 
 // Scratch of one catalogue's cell list.
 struct CellScratch {
-  DevBuf cell, count, start, cursor, idx, x, y, z, w, m, bad, scan_tmp;
+  DevBuf cell, count, start, cursor, idx, x, y, z, w, m, bad, scan_tmp, scell;
 };
 
 struct Ctx {
@@ -83,7 +90,8 @@ struct Ctx {
   DevBuf pair_cnt, pair_ord, pair_off, pair_total;
   DevBuf pr, pmu, pww, pux, puy, puz;
   DevBuf edges, partial, merged, ordered_count;
-  DevBuf bk_prim_off, bk_partial;
+  DevBuf bk_prim_cnt, bk_prim_cnt64, bk_prim_off, bk_partial, bk_partial_r, bk_max, bk_bounds, bk_coef;
+  DevBuf bpr, bux, buy, buz, bwj;
   // W~^a depends only on (R0, k_a, k_{a+1}); repeated calls reuse it.
   std::map<std::tuple<double, double, double>, double> wtilde_cache;
 };
@@ -113,6 +121,19 @@ int pk_sweep(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, dou
              const double *edges_dev, int n_edges, double *partial, int nwaves_fixed);
 int pk_sweep_waves(Ctx &c);
 void merge_partials(Ctx &c, const double *partial, int rows, int cols, double *out);
+
+// Bispectrum pair enumeration (ordered, grouped by primary) and sweep.
+void bk_pairs_count(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
+                    int *pcnt, int *maxcnt);
+void bk_pairs_write(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
+                    int64_t p_lo, int64_t p_hi, int64_t c_lo, int64_t c_hi, const int64_t *poff, int64_t base,
+                    BkPairs out);
+void bk_sweep(Ctx &c, const BkPairs &p, const int64_t *poff, int64_t base, int64_t p_lo, int64_t p_hi,
+              const double *pw, double r0, const double *edges, const double *coef, int NK, int ell_max, bool s0,
+              bool fp64, double *partial, int rowlen, int nwaves);
+void chunk_bounds(Ctx &c, const int64_t *poff, int64_t np, int64_t cap, int nchunks, const int *scell,
+                  int64_t *out_dev);
+void widen_i32(Ctx &c, const int *in, int64_t *out, int64_t n);
 
 // Host analytic terms.
 double wtilde_bin(double r0, double k1, double k2);

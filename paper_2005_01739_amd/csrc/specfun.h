@@ -220,40 +220,30 @@ __device__ inline float horner32(const float (&p)[N], float t) {
   return r;
 }
 
-// For l >= 5 the Laurent amplitudes of the closed form grow like 10^3 / u^4
-// near U_BIG and cancel against the Si term; single-precision amplitudes lose
-// too much there, so when such an l is requested the closed form keeps sin,
-// cos and the amplitudes in double precision (f and g stay single: they enter
-// multiplied by c_l / u and only need ~1e-8 relative accuracy).  Below U_BIG
-// the Taylor series is summed in double precision and kept in double: bin
-// averages difference neighbouring edges, which amplifies any rounding of
-// these slowly varying values by up to k / (3 dk).
+// Closed form in the mixed form: the phase is reduced in double precision and
+// sin, cos and the Laurent amplitudes a_l, b_l are kept in double -- bin
+// averages difference neighbouring edges, and single-precision amplitudes
+// (whose terms cancel to ~10^-1 of their size near U_BIG, and by more for
+// l >= 4) leave per-pair errors of ~5e-7 after that differencing.  The sine
+// integral's auxiliary functions f and g are evaluated in single precision:
+// they enter multiplied by c_l / u and need only ~1e-8 relative accuracy.
+// Below U_BIG the Taylor series is summed in double precision.
 template <int NL, int LSTEP>
 __device__ inline Gv<double, NL> G_mixed(double u) {
-  constexpr bool kHighL = (NL - 1) * LSTEP >= 5;
   if (u < HIPSTER_U_BIG) return G_taylor64<NL, LSTEP>(u);
   Gv<double, NL> G;
-  float uf = float(u);
-  float w = __builtin_amdgcn_rcpf(uf);
-  float t = float(HIPSTER_U_BIG) * w;
-  float f = horner32(POLY_F32, t) * w;
-  float g = horner32(POLY_G32, t) * w * w;
-  if constexpr (kHighL) {
-    double s, c;
-    sincos_reduced64(u, s, c);
-    double wd = 1.0 / u;
-    double si = kHalfPi - double(f) * c - double(g) * s;
-    double w3 = wd * wd * wd;
+  const float uf = float(u);
+  const float w = __builtin_amdgcn_rcpf(uf);
+  const float t = float(HIPSTER_U_BIG) * w;
+  const float f = horner32(POLY_F32, t) * w;
+  const float g = horner32(POLY_G32, t) * w * w;
+  double s, c;
+  sincos_reduced64(u, s, c);
+  const double wd = 1.0 / u;
+  const double si = kHalfPi - double(f) * c - double(g) * s;
+  const double w3 = wd * wd * wd;
 #pragma unroll
-    for (int i = 0; i < NL; ++i) G.v[i] = Dt_closed<double>(i * LSTEP, u, wd, s, c, si) * w3;
-  } else {
-    float s, c;
-    sincos_reduced(u, s, c);
-    float si = float(kHalfPi) - f * c - g * s;
-    float w3 = w * w * w;
-#pragma unroll
-    for (int i = 0; i < NL; ++i) G.v[i] = double(Dt_closed<float>(i * LSTEP, uf, w, s, c, si) * w3);
-  }
+  for (int i = 0; i < NL; ++i) G.v[i] = Dt_closed<double>(i * LSTEP, u, wd, s, c, si) * w3;
   return G;
 }
 
