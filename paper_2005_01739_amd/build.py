@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhipster.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["celllist.hip", "pairs.hip", "pk.hip", "bk.hip", "api.hip", "batch.hip", "analytic.cpp"]
+SOURCES = ["celllist.hip", "pairs.hip", "pk.hip", "bk.hip", "api.hip", "analytic.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
          "-I" + CSRC, "-I" + os.path.join(os.path.dirname(HERE), "include")]

@@ -426,6 +426,229 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   }
 }
 
+// ------------------------------------------------------------------ batch
+// Power spectra of many boxes through one work-queue sweep per filled pair
+// stream; bispectra box by box on the same stream.
+static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag) {
+  if (nb < 1 || !jobs) throw Error{HIPSTER_EINVAL, "batch: need n_boxes >= 1 and a job array"};
+  int pk_prec = -1, ne_max = 1, cols_edges = 0;
+  for (int b = 0; b < nb; ++b) {
+    const hipster_box_job &j = jobs[b];
+    check_points(&j.data, "batch data", j.pk_params.box);
+    if (j.data.n < 2) throw Error{HIPSTER_EINVAL, "batch: every box needs at least two points"};
+    if (j.pk_params.n_k > 0) {
+      check_params(&j.pk_params, false);
+      if (!j.pk) throw Error{HIPSTER_EINVAL, "batch: NULL pk output"};
+      if (pk_prec >= 0 && j.pk_params.precision != pk_prec)
+        throw Error{HIPSTER_EINVAL, "batch: all power spectra must share one precision"};
+      pk_prec = j.pk_params.precision;
+      ne_max = std::max(ne_max, j.pk_params.ell_max / 2 + 1);
+      cols_edges = std::max(cols_edges, j.pk_params.n_k + 1);
+    }
+    if (j.bk_params.n_k > 0) {
+      check_params(&j.bk_params, true);
+      if (!j.bk) throw Error{HIPSTER_EINVAL, "batch: NULL bk output"};
+      if (j.randoms.n > 0) check_points(&j.randoms, "batch randoms", j.bk_params.box);
+    }
+  }
+  HIPSTER_HIP(hipSetDevice(c.device));
+  Timer tm(c);
+  hipEvent_t t0 = tm.mark();
+  double ms_pairs = 0.0, ms_sweep = 0.0, ms_build = 0.0;
+  uint64_t launches = 0;
+
+  // boxes with a power spectrum, largest expected pair count first
+  std::vector<int> order;
+  for (int b = 0; b < nb; ++b)
+    if (jobs[b].pk_params.n_k > 0) order.push_back(b);
+  auto cost = [&](int b) {
+    const hipster_params &q = jobs[b].pk_params;
+    const double n = double(jobs[b].data.n), V = q.box * q.box * q.box;
+    return n * n / V * q.r0 * q.r0 * q.r0 * double(q.n_k + 1);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+
+  const int cols = ne_max * std::max(cols_edges, 1);
+  const bool fp64 = pk_prec == HIPSTER_FP64;
+  const int64_t cap = pair_chunk_capacity();
+  const int64_t task_pairs = int64_t(1) << 16;
+  const int nwaves = pk_sweep_waves(c);
+  // per-box constants and packed edges
+  std::vector<BoxSweep> hbox(static_cast<size_t>(nb));
+  std::vector<double> hedges;
+  for (int b = 0; b < nb; ++b) {
+    const hipster_params &q = jobs[b].pk_params;
+    hbox[size_t(b)] = BoxSweep{q.n_k > 0 ? 1.0 / q.r0 : 0.0, int(hedges.size()), q.n_k > 0 ? q.n_k + 1 : 0};
+    for (int e = 0; q.n_k > 0 && e <= q.n_k; ++e) hedges.push_back(q.k_edges[e]);
+  }
+  BoxSweep *dbox = static_cast<BoxSweep *>(ensure(c, c.bt_boxes, hbox.size() * sizeof(BoxSweep)));
+  double *dedges = static_cast<double *>(ensure(c, c.edges, std::max<size_t>(hedges.size(), 1) * 8));
+  double *dout = static_cast<double *>(ensure(c, c.bt_out, size_t(nb) * cols * 8));
+  int *counter = static_cast<int *>(ensure(c, c.bt_counter, 16));
+  HIPSTER_HIP(hipMemcpyAsync(dbox, hbox.data(), hbox.size() * sizeof(BoxSweep), hipMemcpyHostToDevice, c.stream));
+  if (!hedges.empty())
+    HIPSTER_HIP(hipMemcpyAsync(dedges, hedges.data(), hedges.size() * 8, hipMemcpyHostToDevice, c.stream));
+  HIPSTER_HIP(hipMemsetAsync(dout, 0, size_t(nb) * cols * 8, c.stream));
+
+  PkPairs pp;
+  pp.r = static_cast<double *>(ensure(c, c.pr, size_t(cap) * 8));
+  pp.mu = ensure(c, c.pmu, size_t(cap) * 8);
+  pp.ww = ensure(c, c.pww, size_t(cap) * 8);
+  std::vector<PkTask> tasks;
+  std::vector<int> task_box_first;
+  int64_t fill = 0;
+  std::vector<uint64_t> ordered(static_cast<size_t>(nb), 0);
+
+  auto flush = [&]() {
+    if (tasks.empty()) return;
+    // tasks are grouped by box in the order the boxes were written
+    std::vector<int> first(static_cast<size_t>(nb) + 1, 0);
+    std::vector<PkTask> sorted;
+    sorted.reserve(tasks.size());
+    for (int b = 0; b < nb; ++b) {
+      first[size_t(b)] = int(sorted.size());
+      for (const PkTask &t : tasks)
+        if (t.box == b) sorted.push_back(t);
+    }
+    first[size_t(nb)] = int(sorted.size());
+    // queue order: largest boxes' tasks first (LPT), rows indexed by queue slot
+    std::vector<PkTask> queue;
+    std::vector<int> qfirst(static_cast<size_t>(nb) + 1, 0);
+    std::vector<int> box_pos(static_cast<size_t>(nb), 0);
+    int pos = 0;
+    for (int b : order) {
+      box_pos[size_t(b)] = pos;
+      pos += first[size_t(b) + 1] - first[size_t(b)];
+    }
+    queue.resize(sorted.size());
+    for (int b = 0; b < nb; ++b)
+      for (int t = first[size_t(b)]; t < first[size_t(b) + 1]; ++t) queue[size_t(box_pos[size_t(b)] + t - first[size_t(b)])] = sorted[size_t(t)];
+    PkTask *dtasks = static_cast<PkTask *>(ensure(c, c.bt_tasks, queue.size() * sizeof(PkTask)));
+    double *rows = static_cast<double *>(ensure(c, c.bt_rows, queue.size() * size_t(cols) * 8));
+    HIPSTER_HIP(hipMemcpyAsync(dtasks, queue.data(), queue.size() * sizeof(PkTask), hipMemcpyHostToDevice, c.stream));
+    HIPSTER_HIP(hipMemsetAsync(counter, 0, 4, c.stream));
+    hipEvent_t a = tm.mark();
+    pk_sweep_tasks(c, pp, dtasks, int(queue.size()), counter, dedges, dbox, cols, rows, ne_max, fp64, nwaves);
+    hipEvent_t d = tm.mark();
+    // rows of box b are queue slots [box_pos[b], box_pos[b] + n_b): merge each box's range
+    std::vector<int> mfirst(static_cast<size_t>(nb) * 2);
+    for (int b = 0; b < nb; ++b) {
+      mfirst[size_t(2 * b)] = box_pos[size_t(b)];
+      mfirst[size_t(2 * b + 1)] = box_pos[size_t(b)] + first[size_t(b) + 1] - first[size_t(b)];
+    }
+    int *dfirst = static_cast<int *>(ensure(c, c.bt_first, mfirst.size() * 4));
+    HIPSTER_HIP(hipMemcpyAsync(dfirst, mfirst.data(), mfirst.size() * 4, hipMemcpyHostToDevice, c.stream));
+    merge_boxes(c, rows, cols, dfirst, nb, dout);
+    HIPSTER_HIP(hipEventSynchronize(d));
+    ms_sweep += Timer::ms(a, d);
+    ++launches;
+    tasks.clear();
+    fill = 0;
+  };
+
+  for (int b : order) {
+    const hipster_box_job &j = jobs[b];
+    const hipster_params &q = j.pk_params;
+    const int64_t n = j.data.n;
+    const size_t esz = j.data.dtype == HIPSTER_F32 ? 4 : 8;
+    hipEvent_t a0 = tm.mark();
+    const void *pos = device_view(c, c.pos_in, j.data.pos, n * 3 * int64_t(esz), j.data.on_device);
+    const void *w = device_view(c, c.w_in, j.data.w, n * int64_t(esz), j.data.on_device);
+    const uint8_t *mask = device_mask(c, c.mask_in, q.primary_mask, n);
+    const Grid g = make_grid(q.box, q.r0);
+    const Sorted s = build_cells(c, c.cells_d, g, pos, w, mask, n, j.data.dtype);
+    hipEvent_t a1 = tm.mark();
+    const int64_t ncells = g.ncells();
+    int64_t *cnt = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
+    int64_t *off = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));
+    unsigned long long *ord = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 16));
+    HIPSTER_HIP(hipMemsetAsync(ord, 0, 8, c.stream));
+    pk_pairs_count(c, s, g, q.r0, cnt, ord);
+    scan_i64(c, cnt, off, ncells, c.pair_total);
+    std::vector<int64_t> hoff(static_cast<size_t>(ncells) + 1);
+    unsigned long long hord = 0;
+    HIPSTER_HIP(hipMemcpyAsync(hoff.data(), off, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipMemcpyAsync(&hord, ord, 8, hipMemcpyDeviceToHost, c.stream));
+    hipEvent_t a2 = tm.mark();
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    ms_build += Timer::ms(a0, a1);
+    ms_pairs += Timer::ms(a1, a2);
+    ordered[size_t(b)] = hord;
+    int64_t c0 = 0;
+    while (c0 < ncells) {
+      // largest cell range that fits the remaining stream
+      int64_t c1 = c0;
+      while (c1 < ncells && hoff[size_t(c1 + 1)] - hoff[size_t(c0)] <= cap - fill) ++c1;
+      if (c1 == c0) {
+        if (fill > 0) {
+          flush();
+          continue;
+        }
+        throw Error{HIPSTER_EUNSUPPORTED, "batch: one cell holds more pairs than the pair stream"};
+      }
+      const int64_t np = hoff[size_t(c1)] - hoff[size_t(c0)];
+      if (np > 0) {
+        hipEvent_t w0 = tm.mark();
+        // the write pass stores cell c's pairs at off[c] - base; shift base so they land at `fill`
+        pk_pairs_write(c, s, g, q.r0, q.los_axis, fp64, off, hoff[size_t(c0)] - fill, c0, c1, pp);
+        hipEvent_t w1 = tm.mark();
+        HIPSTER_HIP(hipEventSynchronize(w1));
+        ms_pairs += Timer::ms(w0, w1);
+        for (int64_t t0p = fill; t0p < fill + np; t0p += task_pairs)
+          tasks.push_back(PkTask{t0p, std::min(fill + np, t0p + task_pairs), b, 0});
+        fill += np;
+      }
+      c0 = c1;
+    }
+  }
+  flush();
+  std::vector<double> E(static_cast<size_t>(nb) * cols);
+  HIPSTER_HIP(hipMemcpyAsync(E.data(), dout, E.size() * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  for (int b : order) {
+    hipster_box_job &j = jobs[b];
+    const hipster_params &q = j.pk_params;
+    const int n_ell = q.ell_max / 2 + 1, n_edges = q.n_k + 1;
+    const double p1 = weight_sum(&j.data);
+    const double V = q.box * q.box * q.box, nw = p1 / V, norm = 1.0 / (nw * nw * V);
+    std::vector<double> wt(static_cast<size_t>(q.n_k));
+    wtilde_bins(c, q.r0, q.n_k, q.k_edges, wt.data());
+    const double *Eb = E.data() + size_t(b) * cols;
+    for (int li = 0; li < n_ell; ++li) {
+      const int ell = 2 * li;
+      const double phase = (li & 1) ? -1.0 : 1.0;
+      for (int a = 0; a < q.n_k; ++a) {
+        const double ka = q.k_edges[a], kb = q.k_edges[a + 1];
+        const double a3 = ka * ka * ka, b3 = kb * kb * kb;
+        const double S = 3.0 * (2.0 * ell + 1.0) * phase * (b3 * Eb[li * n_edges + a + 1] - a3 * Eb[li * n_edges + a]) / (b3 - a3);
+        j.pk[li * q.n_k + a] = S * norm - (ell == 0 ? wt[size_t(a)] : 0.0);
+      }
+    }
+    j.n_pairs = ordered[size_t(b)];
+  }
+  // bispectra, box by box
+  for (int b = 0; b < nb; ++b) {
+    hipster_box_job &j = jobs[b];
+    if (j.bk_params.n_k <= 0) continue;
+    hipster_diag d{};
+    run_bk(c, &j.data, j.randoms.n > 0 ? &j.randoms : nullptr, &j.bk_params, j.bk, &d);
+    ms_build += d.ms_build;
+    ms_pairs += d.ms_pairs;
+    ms_sweep += d.ms_sweep;
+    launches += d.sweep_launches;
+    if (j.pk_params.n_k <= 0) j.n_pairs = d.n_pairs;
+  }
+  hipEvent_t t9 = tm.mark();
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  if (diag) {
+    diag->ms_build = ms_build;
+    diag->ms_pairs = ms_pairs;
+    diag->ms_sweep = ms_sweep;
+    diag->ms_total = Timer::ms(t0, t9);
+    diag->sweep_launches = launches;
+  }
+}
+
 template <class F>
 static hipster_status guarded(hipster_ctx *ctx, F &&f) {
   if (!ctx) return HIPSTER_EINVAL;
@@ -477,7 +700,7 @@ void hipster_destroy(hipster_ctx *ctx) {
                    &c.pair_off, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
                    &c.partial, &c.merged, &c.ordered_count, &c.bk_prim_cnt, &c.bk_prim_cnt64, &c.bk_prim_off,
                    &c.bk_partial, &c.bk_partial_r, &c.bk_max, &c.bk_bounds, &c.bk_coef, &c.bpr, &c.bux, &c.buy,
-                   &c.buz, &c.bwj};
+                   &c.buz, &c.bwj, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out};
   for (DevBuf *b : all) free_buf(*b);
   delete ctx;
 }
@@ -490,6 +713,10 @@ hipster_status hipster_pk_ell(hipster_ctx *ctx, const hipster_points *pts, const
 hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data, const hipster_points *randoms,
                               const hipster_params *prm, double *bk, hipster_diag *diag) {
   return guarded(ctx, [&] { run_bk(ctx->c, data, randoms, prm, bk, diag); });
+}
+
+hipster_status hipster_batch(hipster_ctx *ctx, int n_boxes, hipster_box_job *jobs, hipster_diag *diag) {
+  return guarded(ctx, [&] { run_batch(ctx->c, n_boxes, jobs, diag); });
 }
 
 hipster_status hipster_wtilde(double r0, int32_t n_k, const double *k_edges, double *out) {

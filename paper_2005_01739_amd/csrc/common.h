@@ -74,6 +74,20 @@ struct PkPairs {
   void *ww = nullptr;
 };
 
+// A batched sweep task: a contiguous range of one box's pairs.
+struct PkTask {
+  int64_t begin, end;
+  int box;
+  int pad;
+};
+
+// Per-box constants of the batched sweep.
+struct BoxSweep {
+  double inv_r0;
+  int edge_off;
+  int n_edges;
+};
+
 // Scratch of one catalogue's cell list.
 struct CellScratch {
   DevBuf cell, count, start, cursor, idx, x, y, z, w, m, bad, scan_tmp, scell;
@@ -92,6 +106,7 @@ struct Ctx {
   DevBuf edges, partial, merged, ordered_count;
   DevBuf bk_prim_cnt, bk_prim_cnt64, bk_prim_off, bk_partial, bk_partial_r, bk_max, bk_bounds, bk_coef;
   DevBuf bpr, bux, buy, buz, bwj;
+  DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
   // W~^a depends only on (R0, k_a, k_{a+1}); repeated calls reuse it.
   std::map<std::tuple<double, double, double>, double> wtilde_cache;
 };
@@ -120,6 +135,9 @@ void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, int los, 
 int pk_sweep(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0,
              const double *edges_dev, int n_edges, double *partial, int nwaves_fixed);
 int pk_sweep_waves(Ctx &c);
+void pk_sweep_tasks(Ctx &c, const PkPairs &p, const PkTask *tasks, int ntasks, int *counter, const double *edges,
+                    const BoxSweep *boxes, int cols, double *rows, int n_ell, bool fp64, int nwaves);
+void merge_boxes(Ctx &c, const double *rows, int cols, const int *first, int nboxes, double *out);
 void merge_partials(Ctx &c, const double *partial, int rows, int cols, double *out);
 
 // Bispectrum pair enumeration (ordered, grouped by primary) and sweep.

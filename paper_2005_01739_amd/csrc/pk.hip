@@ -135,3 +135,110 @@ void merge_partials(Ctx &c, const double *partial, int rows, int cols, double *o
 }
 
 }  // namespace hipster
+
+namespace hipster {
+
+// ------------------------------------------------- batched work-queue sweep
+// Many boxes' pair streams concatenated into one; the stream is cut into
+// tasks (box, [begin, end)) of at most kTaskPairs pairs, ordered largest box
+// first.  A persistent grid of waves pulls tasks from an atomic counter until
+// the queue is empty (every wave reaches that exit), and each task writes its
+// own row of edge sums, so the merge per box is in task order and the result
+// does not depend on which wave took which task.
+template <int NE, bool FP64>
+__global__ __launch_bounds__(kSweepBlock) void k_pk_tasks(const double *__restrict__ pr, const double *__restrict__ pmu,
+                                                          const double *__restrict__ pww,
+                                                          const PkTask *__restrict__ tasks, int ntasks,
+                                                          int *__restrict__ counter, const double *__restrict__ edges_all,
+                                                          const BoxSweep *__restrict__ boxes, int cols,
+                                                          double *__restrict__ rows) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1);
+    t = __shfl(t, 0);
+    if (t >= ntasks) break;
+    const PkTask task = tasks[t];
+    const BoxSweep bx = boxes[task.box];
+    const double *edges = edges_all + bx.edge_off;
+    const int n_edges = bx.n_edges;
+    double *row = rows + int64_t(t) * cols;
+    for (int e0 = 0; e0 < n_edges; e0 += kChunk) {
+      double acc[NE][kChunk];
+#pragma unroll
+      for (int i = 0; i < NE; ++i)
+#pragma unroll
+        for (int cc = 0; cc < kChunk; ++cc) acc[i][cc] = 0.0;
+      for (int64_t p = task.begin + lane; p < task.end; p += 64) {
+        const double r = pr[p];
+        const double wt = pww[p] * window<double>(r * bx.inv_r0);
+        double L[NE];
+        legendre_even<double, NE>(pmu[p], L);
+        double cf[NE];
+#pragma unroll
+        for (int i = 0; i < NE; ++i) cf[i] = wt * L[i];
+#pragma unroll
+        for (int cc = 0; cc < kChunk; ++cc) {
+          const int e = e0 + cc;
+          if (e < n_edges) {
+            const double u = edges[e] * r;
+            Gv<double, NE> G;
+            if constexpr (FP64) G = G_fp64<NE, 2>(u);
+            else G = G_mixed<NE, 2>(u);
+#pragma unroll
+            for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i], acc[i][cc]);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NE; ++i)
+#pragma unroll
+        for (int cc = 0; cc < kChunk; ++cc) {
+          const double v = wave_sum(acc[i][cc]);
+          const int e = e0 + cc;
+          if (lane == 0 && e < n_edges) row[i * n_edges + e] = v;
+        }
+    }
+  }
+}
+
+template <int NE>
+static void launch_tasks(Ctx &c, const PkPairs &p, const PkTask *tasks, int ntasks, int *counter, const double *edges,
+                         const BoxSweep *boxes, int cols, double *rows, bool fp64, int nwaves) {
+  const dim3 grid(unsigned(nwaves / 4)), block(kSweepBlock);
+  const double *mu = static_cast<const double *>(p.mu), *ww = static_cast<const double *>(p.ww);
+  if (fp64)
+    k_pk_tasks<NE, true><<<grid, block, 0, c.stream>>>(p.r, mu, ww, tasks, ntasks, counter, edges, boxes, cols, rows);
+  else
+    k_pk_tasks<NE, false><<<grid, block, 0, c.stream>>>(p.r, mu, ww, tasks, ntasks, counter, edges, boxes, cols, rows);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+void pk_sweep_tasks(Ctx &c, const PkPairs &p, const PkTask *tasks, int ntasks, int *counter, const double *edges,
+                    const BoxSweep *boxes, int cols, double *rows, int n_ell, bool fp64, int nwaves) {
+  switch (n_ell) {
+    case 1: launch_tasks<1>(c, p, tasks, ntasks, counter, edges, boxes, cols, rows, fp64, nwaves); break;
+    case 2: launch_tasks<2>(c, p, tasks, ntasks, counter, edges, boxes, cols, rows, fp64, nwaves); break;
+    case 3: launch_tasks<3>(c, p, tasks, ntasks, counter, edges, boxes, cols, rows, fp64, nwaves); break;
+    default: launch_tasks<4>(c, p, tasks, ntasks, counter, edges, boxes, cols, rows, fp64, nwaves); break;
+  }
+}
+
+// out[b][col] += sum of rows[t][col] over the tasks t of box b, in task order;
+// box b's rows are the consecutive range [range[2b], range[2b+1]).
+__global__ __launch_bounds__(256) void k_merge_boxes(const double *__restrict__ rows, int cols,
+                                                     const int *__restrict__ range, double *__restrict__ out) {
+  const int b = blockIdx.y;
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= cols) return;
+  double s = 0.0;
+  for (int t = range[2 * b]; t < range[2 * b + 1]; ++t) s += rows[int64_t(t) * cols + col];
+  out[int64_t(b) * cols + col] += s;
+}
+
+void merge_boxes(Ctx &c, const double *rows, int cols, const int *first, int nboxes, double *out) {
+  k_merge_boxes<<<dim3(unsigned((cols + 255) / 256), unsigned(nboxes)), dim3(256), 0, c.stream>>>(rows, cols, first, out);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+}  // namespace hipster
