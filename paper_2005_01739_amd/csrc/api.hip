@@ -300,7 +300,7 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   }
   hipEvent_t t1 = tm.mark();
 
-  const int NK = q->n_k, NL = q->ell_max + 1, NT = NK * (NK + 1) / 2, nC = NL * NT, rowlen = 2 * nC + NK;
+  const int NK = q->n_k, NL = q->ell_max + 1, nT = NL * 256, rowlen = 2 * nT + 16;
   const bool fp64 = q->precision == HIPSTER_FP64;
   std::vector<double> coef(static_cast<size_t>(NK));
   for (int a = 0; a < NK; ++a) {
@@ -317,65 +317,24 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   part[1] = static_cast<double *>(ensure(c, c.bk_partial_r, size_t(nwaves) * rowlen * 8));
   HIPSTER_HIP(hipMemsetAsync(part[0], 0, size_t(nwaves) * rowlen * 8, c.stream));
   HIPSTER_HIP(hipMemsetAsync(part[1], 0, size_t(nwaves) * rowlen * 8, c.stream));
+  unsigned long long *cnt = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 16));
+  HIPSTER_HIP(hipMemsetAsync(cnt, 0, 16, c.stream));
 
-  uint64_t npairs[2] = {0, 0};
-  double ms_pairs = 0.0, ms_sweep = 0.0;
+  double ms_sweep = 0.0;
+  const double ms_pairs = 0.0;  // enumeration is fused into the sweep
   uint64_t launches = 0;
   for (int set = 0; set < (have_r ? 2 : 1); ++set) {
     const Sorted &prim = set == 0 ? sd : sr;
-    const int64_t np = prim.n;
-    int *pcnt = static_cast<int *>(ensure(c, c.bk_prim_cnt, size_t(np) * 4));
-    int64_t *pcnt64 = static_cast<int64_t *>(ensure(c, c.bk_prim_cnt64, size_t(np) * 8));
-    int64_t *poff = static_cast<int64_t *>(ensure(c, c.bk_prim_off, size_t(np + 1) * 8));
-    int *maxcnt = static_cast<int *>(ensure(c, c.bk_max, 16));
-    HIPSTER_HIP(hipMemsetAsync(maxcnt, 0, 4, c.stream));
-    HIPSTER_HIP(hipMemsetAsync(pcnt, 0, size_t(np) * 4, c.stream));
-    hipEvent_t a0 = tm.mark();
-    bk_pairs_count(c, prim, sd, g, q->r0, set == 0, pcnt, maxcnt);
-    widen_i32(c, pcnt, pcnt64, np);
-    scan_i64(c, pcnt64, poff, np, c.pair_total);
-    int64_t total = 0;
-    int hmax = 0;
-    HIPSTER_HIP(hipMemcpyAsync(&total, poff + np, 8, hipMemcpyDeviceToHost, c.stream));
-    HIPSTER_HIP(hipMemcpyAsync(&hmax, maxcnt, 4, hipMemcpyDeviceToHost, c.stream));
-    hipEvent_t a1 = tm.mark();
-    HIPSTER_HIP(hipStreamSynchronize(c.stream));
-    ms_pairs += Timer::ms(a0, a1);
-    npairs[set] = uint64_t(total);
-    if (total == 0) continue;
-    const int64_t cap = std::min<int64_t>(pair_chunk_capacity() / 2, total);
-    const int nchunks = int((total + cap - 1) / cap);
-    const int64_t bufn = cap + hmax;
-    BkPairs bp;
-    bp.r = static_cast<double *>(ensure(c, c.bpr, size_t(bufn) * 8));
-    bp.ux = static_cast<double *>(ensure(c, c.bux, size_t(bufn) * 8));
-    bp.uy = static_cast<double *>(ensure(c, c.buy, size_t(bufn) * 8));
-    bp.uz = static_cast<double *>(ensure(c, c.buz, size_t(bufn) * 8));
-    bp.wj = static_cast<double *>(ensure(c, c.bwj, size_t(bufn) * 8));
-    int64_t *bounds_d = static_cast<int64_t *>(ensure(c, c.bk_bounds, size_t(nchunks + 1) * 3 * 8));
-    chunk_bounds(c, poff, np, cap, nchunks, prim.scell, bounds_d);
-    std::vector<int64_t> bounds(size_t(nchunks + 1) * 3);
-    HIPSTER_HIP(hipMemcpyAsync(bounds.data(), bounds_d, bounds.size() * 8, hipMemcpyDeviceToHost, c.stream));
-    HIPSTER_HIP(hipStreamSynchronize(c.stream));
-    const int64_t ncells = g.ncells();
-    for (int k = 0; k < nchunks; ++k) {
-      const int64_t p_lo = bounds[size_t(3 * k)], p_hi = bounds[size_t(3 * k + 3)];
-      if (p_hi <= p_lo) continue;
-      const int64_t c_lo = bounds[size_t(3 * k + 1)];
-      const int64_t c_hi = (k + 1 < nchunks && p_hi < np) ? bounds[size_t(3 * k + 4)] + 1 : ncells;
-      const int64_t base = bounds[size_t(3 * k + 2)];
-      hipEvent_t b0 = tm.mark();
-      bk_pairs_write(c, prim, sd, g, q->r0, set == 0, p_lo, p_hi, c_lo, c_hi, poff, base, bp);
-      hipEvent_t b1 = tm.mark();
-      bk_sweep(c, bp, poff, base, p_lo, p_hi, prim.w, q->r0, edges, coef_d, NK, q->ell_max, set == 0, fp64, part[set],
-               rowlen, nwaves);
-      hipEvent_t b2 = tm.mark();
-      HIPSTER_HIP(hipEventSynchronize(b2));
-      ms_pairs += Timer::ms(b0, b1);
-      ms_sweep += Timer::ms(b1, b2);
-      ++launches;
-    }
+    hipEvent_t b1 = tm.mark();
+    bk_fused(c, prim, sd, g, q->r0, set == 0, edges, coef_d, NK, q->ell_max, fp64, part[set], rowlen, nwaves,
+             cnt + set);
+    hipEvent_t b2 = tm.mark();
+    HIPSTER_HIP(hipEventSynchronize(b2));
+    ms_sweep += Timer::ms(b1, b2);
+    ++launches;
   }
+  unsigned long long hcnt[2] = {0, 0};
+  HIPSTER_HIP(hipMemcpyAsync(hcnt, cnt, 16, hipMemcpyDeviceToHost, c.stream));
   double *merged = static_cast<double *>(ensure(c, c.merged, size_t(2 * rowlen) * 8));
   merge_partials(c, part[0], nwaves, rowlen, merged);
   merge_partials(c, part[1], nwaves, rowlen, merged + rowlen);
@@ -390,19 +349,17 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   std::vector<double> wt(static_cast<size_t>(NK));
   wtilde_bins(c, q->r0, NK, q->k_edges, wt.data());
   const double *Md = M.data(), *Mr = M.data() + rowlen;
-  auto tri = [NK](int a, int b) {
-    if (a > b) std::swap(a, b);
-    return a * NK - a * (a - 1) / 2 + (b - a);
-  };
+  // tiles are 16 x 16 per l; the Gram sums are symmetric up to rounding, so
+  // the upper triangle is mirrored to make the output exactly symmetric
   for (int l = 0; l < NL; ++l)
     for (int a = 0; a < NK; ++a)
       for (int b = 0; b < NK; ++b) {
-        const int t = l * NT + tri(a, b);
+        const int t = l * 256 + std::min(a, b) * 16 + std::max(a, b);
         const size_t o = (size_t(l) * NK + a) * NK + b;
-        const double GD = Md[t], CD = Md[nC + t], GR = Mr[t], CR = Mr[nC + t];
+        const double GD = Md[t], CD = Md[nT + t], GR = Mr[t], CR = Mr[nT + t];
         const double sgn = (l & 1) ? -1.0 : 1.0;
         double v = sgn * (2.0 * l + 1.0) / (V * nw * nw * nw) * ((GD - CD) - sR * (GR - CR));
-        if (l == 0) v += -(wt[size_t(a)] * Md[2 * nC + b] + wt[size_t(b)] * Md[2 * nC + a]) / (V * nw * nw) +
+        if (l == 0) v += -(wt[size_t(a)] * Md[2 * nT + b] + wt[size_t(b)] * Md[2 * nT + a]) / (V * nw * nw) +
                          2.0 * wt[size_t(a)] * wt[size_t(b)];
         bk[o] = v;
         if (diag) {
@@ -414,10 +371,10 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
       }
   if (diag) {
     if (diag->s0)
-      for (int b = 0; b < NK; ++b) diag->s0[b] = Md[2 * nC + b];
+      for (int b = 0; b < NK; ++b) diag->s0[b] = Md[2 * nT + b];
     if (diag->wtilde) memcpy(diag->wtilde, wt.data(), size_t(NK) * 8);
-    diag->n_pairs = npairs[0];
-    diag->n_pairs_rand = npairs[1];
+    diag->n_pairs = hcnt[0];
+    diag->n_pairs_rand = hcnt[1];
     diag->ms_build = Timer::ms(t0, t1);
     diag->ms_pairs = ms_pairs;
     diag->ms_sweep = ms_sweep;
@@ -698,9 +655,7 @@ void hipster_destroy(hipster_ctx *ctx) {
   free_cells(c.cells_r);
   DevBuf *all[] = {&c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in, &c.rmask_in, &c.pair_cnt, &c.pair_ord,
                    &c.pair_off, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
-                   &c.partial, &c.merged, &c.ordered_count, &c.bk_prim_cnt, &c.bk_prim_cnt64, &c.bk_prim_off,
-                   &c.bk_partial, &c.bk_partial_r, &c.bk_max, &c.bk_bounds, &c.bk_coef, &c.bpr, &c.bux, &c.buy,
-                   &c.buz, &c.bwj, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out};
+                   &c.partial, &c.merged, &c.ordered_count, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out};
   for (DevBuf *b : all) free_buf(*b);
   delete ctx;
 }

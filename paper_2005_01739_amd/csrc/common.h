@@ -59,11 +59,6 @@ struct Sorted {
   const int *scell = nullptr;          // cell of each sorted point
 };
 
-// Pair stream for the bispectrum: per primary, its neighbours inside R0 as
-// (r, unit vector x_pj / r, w_j), all double.
-struct BkPairs {
-  double *r = nullptr, *ux = nullptr, *uy = nullptr, *uz = nullptr, *wj = nullptr;
-};
 
 // Pair stream for the power spectrum: one entry per unordered pair inside R0.
 // mu and ww are kept in double in both forms: L_l(mu) has slopes up to
@@ -104,8 +99,7 @@ struct Ctx {
   DevBuf pair_cnt, pair_ord, pair_off, pair_total;
   DevBuf pr, pmu, pww, pux, puy, puz;
   DevBuf edges, partial, merged, ordered_count;
-  DevBuf bk_prim_cnt, bk_prim_cnt64, bk_prim_off, bk_partial, bk_partial_r, bk_max, bk_bounds, bk_coef;
-  DevBuf bpr, bux, buy, buz, bwj;
+  DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
   // W~^a depends only on (R0, k_a, k_{a+1}); repeated calls reuse it.
   std::map<std::tuple<double, double, double>, double> wtilde_cache;
@@ -140,17 +134,11 @@ void pk_sweep_tasks(Ctx &c, const PkPairs &p, const PkTask *tasks, int ntasks, i
 void merge_boxes(Ctx &c, const double *rows, int cols, const int *first, int nboxes, double *out);
 void merge_partials(Ctx &c, const double *partial, int rows, int cols, double *out);
 
-// Bispectrum pair enumeration (ordered, grouped by primary) and sweep.
-void bk_pairs_count(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
-                    int *pcnt, int *maxcnt);
-void bk_pairs_write(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
-                    int64_t p_lo, int64_t p_hi, int64_t c_lo, int64_t c_hi, const int64_t *poff, int64_t base,
-                    BkPairs out);
-void bk_sweep(Ctx &c, const BkPairs &p, const int64_t *poff, int64_t base, int64_t p_lo, int64_t p_hi,
-              const double *pw, double r0, const double *edges, const double *coef, int NK, int ell_max, bool s0,
-              bool fp64, double *partial, int rowlen, int nwaves);
-void chunk_bounds(Ctx &c, const int64_t *poff, int64_t np, int64_t cap, int nchunks, const int *scell,
-                  int64_t *out_dev);
+// Bispectrum: fused enumeration and MFMA contraction over one primary catalogue.
+void bk_fused(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
+              const double *edges, const double *coef, int NK, int ell_max, bool fp64, double *partial, int rowlen,
+              int nwaves, unsigned long long *npairs);
+size_t bk_fused_lds(int NL);
 void widen_i32(Ctx &c, const int *in, int64_t *out, int64_t n);
 
 // Host analytic terms.

@@ -35,7 +35,8 @@ constexpr double kTwoOverPi = 0.63661977236758134308;
 // so n * kPio2Hi is exact for |n| < 2^20.
 constexpr double kPio2Hi = 1.5707963267341256141662597656e+00;
 constexpr double kPio2Lo = 6.0771005065061922518e-11;
-// Below this argument the Taylor series needs only 14 terms.
+// Below this argument the Taylor series needs only 14 terms, and the mixed
+// form switches from the Taylor series to the closed form.
 constexpr double kUSmall = 2.0;
 
 // Smooth truncation window W(x), x = r / R0 (Sec. 2, eq. window_defn).
@@ -223,24 +224,38 @@ __device__ inline float horner32(const float (&p)[N], float t) {
 // Closed form in the mixed form: the phase is reduced in double precision and
 // sin, cos and the Laurent amplitudes a_l, b_l are kept in double -- bin
 // averages difference neighbouring edges, and single-precision amplitudes
-// (whose terms cancel to ~10^-1 of their size near U_BIG, and by more for
-// l >= 4) leave per-pair errors of ~5e-7 after that differencing.  The sine
-// integral's auxiliary functions f and g are evaluated in single precision:
-// they enter multiplied by c_l / u and need only ~1e-8 relative accuracy.
-// Below U_BIG the Taylor series is summed in double precision.
+// leave per-pair errors of ~5e-7 after that differencing.  The form is used
+// from u = kUSmall = 2 up: there its worst cancellation (l = 6 at u = 2, a
+// factor ~4e5) still leaves ~4e-11 relative error.  Si comes from its power
+// series below U_BIG (at most a factor ~40 of cancellation at u = 8) and
+// through its auxiliary functions f and g above; f and g are evaluated in
+// single precision, since they enter multiplied by c_l / u and need only
+// ~1e-8 relative accuracy.  Below u = 2 G_l is summed from its Taylor series.
 template <int NL, int LSTEP>
 __device__ inline Gv<double, NL> G_mixed(double u) {
-  if (u < HIPSTER_U_BIG) return G_taylor64<NL, LSTEP>(u);
+  constexpr bool kNeedSi = (NL - 1) * LSTEP >= 2;  // some even l >= 2 is requested
+  if (u < kUSmall) return G_taylor64<NL, LSTEP>(u);
   Gv<double, NL> G;
-  const float uf = float(u);
-  const float w = __builtin_amdgcn_rcpf(uf);
-  const float t = float(HIPSTER_U_BIG) * w;
-  const float f = horner32(POLY_F32, t) * w;
-  const float g = horner32(POLY_G32, t) * w * w;
   double s, c;
   sincos_reduced64(u, s, c);
   const double wd = 1.0 / u;
-  const double si = kHalfPi - double(f) * c - double(g) * s;
+  double si = 0.0;
+  if constexpr (kNeedSi) {
+    if (u < HIPSTER_U_BIG) {
+      const double v = u * u;
+      double p = SI_TAYLOR[HIPSTER_N_SI_TAYLOR - 1];
+#pragma unroll
+      for (int n = HIPSTER_N_SI_TAYLOR - 2; n >= 0; --n) p = fma(p, v, SI_TAYLOR[n]);
+      si = p * u;
+    } else {
+      const float uf = float(u);
+      const float w = __builtin_amdgcn_rcpf(uf);
+      const float t = float(HIPSTER_U_BIG) * w;
+      const float f = horner32(POLY_F32, t) * w;
+      const float g = horner32(POLY_G32, t) * w * w;
+      si = kHalfPi - double(f) * c - double(g) * s;
+    }
+  }
   const double w3 = wd * wd * wd;
 #pragma unroll
   for (int i = 0; i < NL; ++i) G.v[i] = Dt_closed<double>(i * LSTEP, u, wd, s, c, si) * w3;
