@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-primaries", type=int, default=16384)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--scale", type=float, default=0.1,
+                    help="batch workload: fraction of each box's N (pairs scale as its square)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -161,7 +163,24 @@ def main():
         cfg = {"workload": wl.name, "n_points": wl.n, "n_randoms": int(rnd.shape[0]), "box": wl.box, "r0": wl.r0,
                "n_k": n_k, "ell_max": wl.ell_max_b, "precision": prec}
     else:
-        raise SystemExit("batch workload: see hipster_batch")
+        boxes = synthetic.batch_boxes(64, args.scale)
+        specs = []
+        for b in boxes:
+            pos = torch.from_numpy(b.pos).cuda()
+            rnd = torch.from_numpy(b.randoms()).cuda()
+            specs.append(dict(pos=pos, randoms=rnd, box=b.box, r0=b.r0, pk_edges=b.k_edges_p, pk_ell_max=b.ell_max_p,
+                              bk_edges=b.k_edges_b, bk_ell_max=b.ell_max_b))
+        prec = "mixed"
+        nkp, nkb = len(boxes[0].k_edges_p) - 1, len(boxes[0].k_edges_b) - 1
+
+        def step():
+            outs, info = hp.batch(specs, precision=prec, return_diag=True)
+            info["n_pairs"] = sum(o["n_pairs"] for o in outs)
+            return outs, info
+        units_per_pair = None
+        cfg = {"workload": "batch_64_boxes", "n_boxes": 64, "scale": args.scale,
+               "n_points_total": int(sum(b.n for b in boxes)), "pk": {"n_k": nkp, "ells": [0, 2, 4]},
+               "bk": {"n_k": nkb, "ell_max": boxes[0].ell_max_b}, "randoms_per_point": 3, "precision": prec}
 
     for _ in range(args.warmup):
         step()
@@ -177,6 +196,14 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
+    if args.workload == "batch":
+        value = 64 / (dt / args.steps)
+        out = {"metric": METRIC, "value": value, "unit": "boxes/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic", "config": cfg,
+               "pk_pairs_per_step": pairs, "avg_sweep_ms": sweep_ms / args.steps}
+        print(json.dumps(out), flush=True)
+        return
     value = (pairs + pairs_r) * units_per_pair / (dt / args.steps)
 
     out = {"metric": METRIC, "value": value, "unit": "pair-weights/s", "n_gpus": 1, "steps": args.steps,

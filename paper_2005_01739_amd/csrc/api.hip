@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.h"
+#include "specfun.h"
 
 struct hipster_ctx {
   hipster::Ctx c;
@@ -179,25 +180,38 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
   const Sorted s = build_cells(c, c.cells_d, g, pos, w, mask, n, pts->dtype);
   hipEvent_t t1 = tm.mark();
 
-  // count pass, offsets
+  // count pass (two r-buckets), offsets
   const int64_t ncells = g.ncells();
-  int64_t *cnt = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
-  int64_t *off = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));
+  const bool fp64 = q->precision == HIPSTER_FP64;
+  const double r_split = q->k_edges[0] > 0.0 ? (fp64 ? HIPSTER_U_BIG : kUSmall) / q->k_edges[0] : 0.0;
+  int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
+  int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(ncells) * 8));
+  int64_t *off_a = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));
+  int64_t *off_b = static_cast<int64_t *>(ensure(c, c.pair_off_b, size_t(ncells + 1) * 8));
   unsigned long long *ord = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 16));
   HIPSTER_HIP(hipMemsetAsync(ord, 0, 8, c.stream));
-  pk_pairs_count(c, s, g, q->r0, cnt, ord);
-  scan_i64(c, cnt, off, ncells, c.pair_total);
-  std::vector<int64_t> hoff(size_t(ncells) + 1);
+  pk_pairs_count(c, s, g, q->r0, r_split, cnt_a, cnt_b, ord);
+  scan_i64(c, cnt_a, off_a, ncells, c.pair_total);
+  scan_i64(c, cnt_b, off_b, ncells, c.pair_total);
+  std::vector<int64_t> ha(size_t(ncells) + 1), hb(size_t(ncells) + 1);
   unsigned long long hord = 0;
-  HIPSTER_HIP(hipMemcpyAsync(hoff.data(), off, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(ha.data(), off_a, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(hb.data(), off_b, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
   HIPSTER_HIP(hipMemcpyAsync(&hord, ord, 8, hipMemcpyDeviceToHost, c.stream));
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
-  const int64_t total = hoff[size_t(ncells)];
+  auto pairs_in = [&](int64_t a, int64_t b) { return (ha[size_t(b)] - ha[size_t(a)]) + (hb[size_t(b)] - hb[size_t(a)]); };
+  const int64_t total = pairs_in(0, ncells);
 
   const int n_ell = q->ell_max / 2 + 1, n_edges = q->n_k + 1;
-  const bool fp64 = q->precision == HIPSTER_FP64;
-  double *edges = static_cast<double *>(ensure(c, c.edges, size_t(n_edges) * 8));
-  HIPSTER_HIP(hipMemcpyAsync(edges, q->k_edges, size_t(n_edges) * 8, hipMemcpyHostToDevice, c.stream));
+  // edges followed by their reciprocals (0 for a zero edge, whose u = 0
+  // always takes the Taylor branch)
+  std::vector<double> he(static_cast<size_t>(2 * n_edges));
+  for (int e = 0; e < n_edges; ++e) {
+    he[size_t(e)] = q->k_edges[e];
+    he[size_t(n_edges + e)] = q->k_edges[e] > 0.0 ? 1.0 / q->k_edges[e] : 0.0;
+  }
+  double *edges = static_cast<double *>(ensure(c, c.edges, size_t(2 * n_edges) * 8));
+  HIPSTER_HIP(hipMemcpyAsync(edges, he.data(), size_t(2 * n_edges) * 8, hipMemcpyHostToDevice, c.stream));
   const int nwaves = pk_sweep_waves(c);
   const int cols = n_ell * n_edges;
   double *partial = static_cast<double *>(ensure(c, c.partial, size_t(nwaves) * cols * 8));
@@ -205,24 +219,23 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
 
   // chunks of home cells whose pairs fit the pair buffer
   int64_t cap = std::min<int64_t>(pair_chunk_capacity(), std::max<int64_t>(total, 1));
-  for (int64_t a = 0; a < ncells; ++a) cap = std::max(cap, hoff[size_t(a + 1)] - hoff[size_t(a)]);
-  const size_t tsz = 8;
+  for (int64_t a = 0; a < ncells; ++a) cap = std::max(cap, pairs_in(a, a + 1));
   PkPairs pp;
   pp.r = static_cast<double *>(ensure(c, c.pr, size_t(cap) * 8));
-  pp.mu = ensure(c, c.pmu, size_t(cap) * tsz);
-  pp.ww = ensure(c, c.pww, size_t(cap) * tsz);
+  pp.mu = ensure(c, c.pmu, size_t(cap) * 8);
+  pp.ww = ensure(c, c.pww, size_t(cap) * 8);
   double ms_pairs = 0.0, ms_sweep = 0.0;
   uint64_t launches = 0;
   hipEvent_t t2 = tm.mark();
-  ms_pairs += 0.0;
   int64_t c0 = 0;
   while (c0 < ncells) {
     int64_t c1 = c0 + 1;
-    while (c1 < ncells && hoff[size_t(c1 + 1)] - hoff[size_t(c0)] <= cap) ++c1;
-    const int64_t base = hoff[size_t(c0)], np = hoff[size_t(c1)] - base;
+    while (c1 < ncells && pairs_in(c0, c1 + 1) <= cap) ++c1;
+    const int64_t np = pairs_in(c0, c1), n_a = ha[size_t(c1)] - ha[size_t(c0)];
     if (np > 0) {
       hipEvent_t a = tm.mark();
-      pk_pairs_write(c, s, g, q->r0, q->los_axis, fp64, off, base, c0, c1, pp);
+      pk_pairs_write(c, s, g, q->r0, r_split, q->los_axis, off_a, off_b, ha[size_t(c0)], hb[size_t(c0)], n_a, c0, c1,
+                     pp);
       hipEvent_t b = tm.mark();
       pk_sweep(c, pp, np, n_ell, fp64, q->r0, edges, n_edges, partial, nwaves);
       hipEvent_t d = tm.mark();
@@ -267,7 +280,6 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
     diag->ms_total = Timer::ms(t0, t3);
     diag->sweep_launches = launches;
   }
-  (void)total;
 }
 
 // -------------------------------------------------------------- bispectrum
@@ -516,15 +528,20 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
     const Sorted s = build_cells(c, c.cells_d, g, pos, w, mask, n, j.data.dtype);
     hipEvent_t a1 = tm.mark();
     const int64_t ncells = g.ncells();
-    int64_t *cnt = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
-    int64_t *off = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));
+    const double r_split = q.k_edges[0] > 0.0 ? (fp64 ? HIPSTER_U_BIG : kUSmall) / q.k_edges[0] : 0.0;
+    int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
+    int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(ncells) * 8));
+    int64_t *off_a = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));
+    int64_t *off_b = static_cast<int64_t *>(ensure(c, c.pair_off_b, size_t(ncells + 1) * 8));
     unsigned long long *ord = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 16));
     HIPSTER_HIP(hipMemsetAsync(ord, 0, 8, c.stream));
-    pk_pairs_count(c, s, g, q.r0, cnt, ord);
-    scan_i64(c, cnt, off, ncells, c.pair_total);
-    std::vector<int64_t> hoff(static_cast<size_t>(ncells) + 1);
+    pk_pairs_count(c, s, g, q.r0, r_split, cnt_a, cnt_b, ord);
+    scan_i64(c, cnt_a, off_a, ncells, c.pair_total);
+    scan_i64(c, cnt_b, off_b, ncells, c.pair_total);
+    std::vector<int64_t> ha(static_cast<size_t>(ncells) + 1), hb(static_cast<size_t>(ncells) + 1);
     unsigned long long hord = 0;
-    HIPSTER_HIP(hipMemcpyAsync(hoff.data(), off, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipMemcpyAsync(ha.data(), off_a, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipMemcpyAsync(hb.data(), off_b, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
     HIPSTER_HIP(hipMemcpyAsync(&hord, ord, 8, hipMemcpyDeviceToHost, c.stream));
     hipEvent_t a2 = tm.mark();
     HIPSTER_HIP(hipStreamSynchronize(c.stream));
@@ -535,7 +552,8 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
     while (c0 < ncells) {
       // largest cell range that fits the remaining stream
       int64_t c1 = c0;
-      while (c1 < ncells && hoff[size_t(c1 + 1)] - hoff[size_t(c0)] <= cap - fill) ++c1;
+      auto in = [&](int64_t x, int64_t y) { return (ha[size_t(y)] - ha[size_t(x)]) + (hb[size_t(y)] - hb[size_t(x)]); };
+      while (c1 < ncells && in(c0, c1 + 1) <= cap - fill) ++c1;
       if (c1 == c0) {
         if (fill > 0) {
           flush();
@@ -543,11 +561,12 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
         }
         throw Error{HIPSTER_EUNSUPPORTED, "batch: one cell holds more pairs than the pair stream"};
       }
-      const int64_t np = hoff[size_t(c1)] - hoff[size_t(c0)];
+      const int64_t np = in(c0, c1), n_a = ha[size_t(c1)] - ha[size_t(c0)];
       if (np > 0) {
         hipEvent_t w0 = tm.mark();
-        // the write pass stores cell c's pairs at off[c] - base; shift base so they land at `fill`
-        pk_pairs_write(c, s, g, q.r0, q.los_axis, fp64, off, hoff[size_t(c0)] - fill, c0, c1, pp);
+        // shift the bases so the cells' pairs land at [fill, fill + np)
+        pk_pairs_write(c, s, g, q.r0, r_split, q.los_axis, off_a, off_b, ha[size_t(c0)] - fill, hb[size_t(c0)] - fill,
+                       n_a, c0, c1, pp);
         hipEvent_t w1 = tm.mark();
         HIPSTER_HIP(hipEventSynchronize(w1));
         ms_pairs += Timer::ms(w0, w1);
@@ -653,8 +672,8 @@ void hipster_destroy(hipster_ctx *ctx) {
   (void)hipStreamSynchronize(c.stream);
   free_cells(c.cells_d);
   free_cells(c.cells_r);
-  DevBuf *all[] = {&c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in, &c.rmask_in, &c.pair_cnt, &c.pair_ord,
-                   &c.pair_off, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
+  DevBuf *all[] = {&c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in, &c.rmask_in, &c.pair_cnt, &c.pair_cnt_b,
+                   &c.pair_ord, &c.pair_off, &c.pair_off_b, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
                    &c.partial, &c.merged, &c.ordered_count, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out};
   for (DevBuf *b : all) free_buf(*b);
   delete ctx;

@@ -96,7 +96,7 @@ struct Ctx {
   std::string last_error;
   CellScratch cells_d, cells_r;
   DevBuf pos_in, w_in, mask_in, rpos_in, rw_in, rmask_in;
-  DevBuf pair_cnt, pair_ord, pair_off, pair_total;
+  DevBuf pair_cnt, pair_cnt_b, pair_ord, pair_off, pair_off_b, pair_total;
   DevBuf pr, pmu, pww, pux, puy, puz;
   DevBuf edges, partial, merged, ordered_count;
   DevBuf bk_partial, bk_partial_r, bk_coef;
@@ -116,13 +116,16 @@ Sorted build_cells(Ctx &c, CellScratch &s, const Grid &g, const void *pos, const
 // Exclusive scan of n int64 values (in-place allowed); out has n + 1 entries.
 void scan_i64(Ctx &c, const int64_t *in, int64_t *out, int64_t n, DevBuf &tmp);
 
-// Power-spectrum pair enumeration over home cells [c0, c1): count pass fills
-// cnt[cell] (entries to write) and adds the ordered-pair multiplicity to
-// *ordered; write pass stores entries at off[cell] - base.
-void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, double r0, int64_t *cnt,
-                    unsigned long long *ordered);
-void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, int los, bool fp64,
-                    const int64_t *off, int64_t base, int64_t c0, int64_t c1, PkPairs out);
+// Power-spectrum pair enumeration.  The count pass fills cnt_a[cell] /
+// cnt_b[cell] (pairs with r < r_split / the rest) and adds the ordered-pair
+// multiplicity to *ordered.  The write pass over home cells [c0, c1) stores a
+// cell's near pairs at off_a[cell] - base_a and its far pairs at
+// n_a + off_b[cell] - base_b.
+void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_split, int64_t *cnt_a,
+                    int64_t *cnt_b, unsigned long long *ordered);
+void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_split, int los,
+                    const int64_t *off_a, const int64_t *off_b, int64_t base_a, int64_t base_b, int64_t n_a,
+                    int64_t c0, int64_t c1, PkPairs out);
 
 // Pair-weight sweep: adds into partial[nwaves][n_ell][n_edges] (zeroed by the
 // caller before the first chunk).  Returns the number of waves (partial rows).

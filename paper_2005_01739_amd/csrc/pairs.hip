@@ -6,6 +6,11 @@
 // in a deterministic order: a count pass sizes each home cell's output, an
 // exclusive scan gives offsets, and a write pass repeats the same tests.
 //
+// Pairs are written in two buckets: r < r_split first, then the rest.  With
+// r_split = u_switch / k_min no pair of the second bucket ever takes the
+// small-argument (Taylor) branch of the pair weight, so the sweep's waves over
+// that bucket -- most of the pairs -- never diverge into it.
+//
 // The separation is the paper's pair vector x_i - x_j at the periodic image
 // inside R0 (Sec. 2 pair counts; Sec. 3 periodic box); its squared length is
 // (dx^2 + dy^2) + dz^2 in double precision without contraction, the predicate
@@ -55,10 +60,11 @@ __device__ inline double sq_norm_exact(double dx, double dy, double dz) {
 }
 
 template <bool WRITE, typename T>
-__global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, double r02, int los,
-                                                 int64_t *__restrict__ cnt,
+__global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, double r02, double rs2, int los,
+                                                 int64_t *__restrict__ cnt_a, int64_t *__restrict__ cnt_b,
                                                  unsigned long long *__restrict__ ordered,
-                                                 const int64_t *__restrict__ off, int64_t base,
+                                                 const int64_t *__restrict__ off_a, const int64_t *__restrict__ off_b,
+                                                 int64_t base_a, int64_t base_b, int64_t n_a,
                                                  int64_t c0, double *__restrict__ out_r,
                                                  T *__restrict__ out_mu, T *__restrict__ out_ww) {
   const int64_t cell = c0 + blockIdx.x;
@@ -66,9 +72,10 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
   const int cz = int(cell % nc), cy = int((cell / nc) % nc), cx = int(cell / (int64_t(nc) * nc));
   const int64_t hs = s.cell_start[cell];
   const int ni = int(s.cell_start[cell + 1] - hs);
-  int64_t written = 0;
+  int64_t written_a = 0, written_b = 0;
   unsigned long long ord = 0;
-  const int64_t wbase = WRITE ? off[cell] - base : 0;
+  const int64_t wbase_a = WRITE ? off_a[cell] - base_a : 0;
+  const int64_t wbase_b = WRITE ? n_a + off_b[cell] - base_b : 0;
   for (int st = 0; st < 14 && ni > 0; ++st) {
     int ox, oy, oz, sx, sy, sz;
     half_stencil(st, ox, oy, oz);
@@ -81,7 +88,7 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
     const uint32_t total = uint32_t(ni) * uint32_t(nj);
     for (uint32_t q0 = 0; q0 < total; q0 += 64) {
       const uint32_t q = q0 + lane;
-      bool hit = false;
+      bool hit = false, near = false;
       double r = 0.0, mu = 0.0, ww = 0.0;
       if (q < total) {
         const uint32_t ii = q / uint32_t(nj), jj = q - ii * uint32_t(nj);
@@ -96,6 +103,7 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
             ord += unsigned(mult);
             if (mult > 0) {
               hit = true;
+              near = r2 < rs2;
               if (WRITE) {
                 r = sqrt(r2);
                 const double dl = los == 0 ? dx : (los == 1 ? dy : dz);
@@ -106,42 +114,46 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
           }
         }
       }
-      const unsigned long long bal = __ballot(hit);
+      const unsigned long long bal_a = __ballot(hit && near), bal_b = __ballot(hit && !near);
       if (WRITE && hit) {
-        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-        const int64_t k = wbase + written + pre;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        const int64_t k = near ? wbase_a + written_a + __popcll(bal_a & below)
+                               : wbase_b + written_b + __popcll(bal_b & below);
         out_r[k] = r;
         out_mu[k] = T(mu);
         out_ww[k] = T(ww);
       }
-      written += __popcll(bal);
+      written_a += __popcll(bal_a);
+      written_b += __popcll(bal_b);
     }
   }
   if (!WRITE) {
     for (int o = 32; o > 0; o >>= 1) ord += __shfl_xor(ord, o);
     if (lane == 0) {
-      cnt[cell] = written;
+      cnt_a[cell] = written_a;
+      cnt_b[cell] = written_b;
       if (ord) atomicAdd(ordered, ord);
     }
   }
 }
 
-void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, double r0, int64_t *cnt,
-                    unsigned long long *ordered) {
+void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_split, int64_t *cnt_a,
+                    int64_t *cnt_b, unsigned long long *ordered) {
   const int64_t ncells = g.ncells();
   k_pk_pairs<false, double><<<dim3(unsigned(ncells)), dim3(64), 0, c.stream>>>(
-      s, g.nc, g.L, r0 * r0, 2, cnt, ordered, nullptr, 0, 0, nullptr, nullptr, nullptr);
+      s, g.nc, g.L, r0 * r0, r_split * r_split, 2, cnt_a, cnt_b, ordered, nullptr, nullptr, 0, 0, 0, 0, nullptr,
+      nullptr, nullptr);
   HIPSTER_HIP(hipGetLastError());
 }
 
-void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, int los, bool fp64,
-                    const int64_t *off, int64_t base, int64_t c0, int64_t c1, PkPairs out) {
+void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_split, int los,
+                    const int64_t *off_a, const int64_t *off_b, int64_t base_a, int64_t base_b, int64_t n_a,
+                    int64_t c0, int64_t c1, PkPairs out) {
   if (c1 <= c0) return;
   const dim3 grid(unsigned(c1 - c0));
-  (void)fp64;
   k_pk_pairs<true, double><<<grid, dim3(64), 0, c.stream>>>(
-      s, g.nc, g.L, r0 * r0, los, nullptr, nullptr, off, base, c0, out.r,
-      static_cast<double *>(out.mu), static_cast<double *>(out.ww));
+      s, g.nc, g.L, r0 * r0, r_split * r_split, los, nullptr, nullptr, nullptr, off_a, off_b, base_a, base_b, n_a,
+      c0, out.r, static_cast<double *>(out.mu), static_cast<double *>(out.ww));
   HIPSTER_HIP(hipGetLastError());
 }
 

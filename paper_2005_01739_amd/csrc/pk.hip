@@ -5,9 +5,9 @@
 // kernel adds c_l G_l(k_e r) to a per-lane double accumulator, with
 // c_l = w_i w_j m_ij W(r/R0) L_l(mu).  The bin values follow on the host as
 // S^a_l = 3 (2l+1) (-i)^l [k_{a+1}^3 E_l(a+1) - k_a^3 E_l(a)] / (k_{a+1}^3 - k_a^3)
-// (Sec. 3, binned estimator with eq. jla-def).  Edges are processed in chunks
-// of kChunk so the accumulators stay in registers; the pair stream is re-read
-// once per chunk.  Each wave reduces its lanes with cross-lane shuffles and
+// (Sec. 3, binned estimator with eq. jla-def).  Edges are processed in
+// balanced chunks of at most kChunk so the accumulators stay in registers and
+// occupancy stays high; the pair stream is re-read once per chunk.  Each wave reduces its lanes with cross-lane shuffles and
 // adds its sums to its own row of `partial`; rows are merged in a fixed order,
 // so results are bitwise reproducible.
 #include <type_traits>
@@ -18,7 +18,7 @@
 namespace hipster {
 
 constexpr int kSweepBlock = 256;
-constexpr int kChunk = 12;
+constexpr int kChunk = 8;
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -32,6 +32,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_pk_sweep(const double *__restri
                                                           const void *__restrict__ pww_,
                                                           int64_t npairs, double inv_r0,
                                                           const double *__restrict__ edges,
+                                                          const double *__restrict__ inv_edges,
                                                           int n_edges, double *__restrict__ partial) {
   using T = double;  // per-pair weights and mu are evaluated in double in both forms
   const T *pmu = static_cast<const T *>(pmu_);
@@ -39,7 +40,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_pk_sweep(const double *__restri
   const int64_t gtid = int64_t(blockIdx.x) * kSweepBlock + threadIdx.x;
   const int64_t stride = int64_t(gridDim.x) * kSweepBlock;
   const int wave = int(gtid >> 6), lane = threadIdx.x & 63;
-  for (int e0 = 0; e0 < n_edges; e0 += kChunk) {
+  // balanced chunks of at most kChunk edges
+  const int nchunk = (n_edges + kChunk - 1) / kChunk, per = (n_edges + nchunk - 1) / nchunk;
+  for (int e0 = 0; e0 < n_edges; e0 += per) {
+    const int e_end = e0 + per < n_edges ? e0 + per : n_edges;
     double acc[NE][kChunk];
 #pragma unroll
     for (int i = 0; i < NE; ++i)
@@ -54,17 +58,18 @@ __global__ __launch_bounds__(kSweepBlock) void k_pk_sweep(const double *__restri
       double cf[NE];
 #pragma unroll
       for (int i = 0; i < NE; ++i) cf[i] = double(wt * L[i]);
+      const double inv_r = r > 0.0 ? 1.0 / r : 0.0;
 #pragma unroll
       for (int cc = 0; cc < kChunk; ++cc) {
         const int e = e0 + cc;
-        if (e < n_edges) {
+        if (e < e_end) {
           const double u = edges[e] * r;
           if constexpr (FP64) {
             const Gv<double, NE> G = G_fp64<NE, 2>(u);
 #pragma unroll
             for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i], acc[i][cc]);
           } else {
-            const Gv<double, NE> G = G_mixed<NE, 2>(u);
+            const Gv<double, NE> G = G_mixed_w<NE, 2>(u, inv_edges[e] * inv_r);
 #pragma unroll
             for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i], acc[i][cc]);
           }
@@ -77,7 +82,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_pk_sweep(const double *__restri
       for (int cc = 0; cc < kChunk; ++cc) {
         const double v = wave_sum(acc[i][cc]);
         const int e = e0 + cc;
-        if (lane == 0 && e < n_edges) partial[(int64_t(wave) * NE + i) * n_edges + e] += v;
+        if (lane == 0 && e < e_end) partial[(int64_t(wave) * NE + i) * n_edges + e] += v;
       }
   }
 }
@@ -94,10 +99,13 @@ template <int NE>
 static void launch_sweep(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, double inv_r0,
                          const double *edges, int n_edges, double *partial, int nwaves) {
   const dim3 grid(unsigned(nwaves / 4)), block(kSweepBlock);
+  const double *inv_edges = edges + n_edges;  // the caller stores 1/k_e after the edges
   if (fp64)
-    k_pk_sweep<NE, true><<<grid, block, 0, c.stream>>>(p.r, p.mu, p.ww, npairs, inv_r0, edges, n_edges, partial);
+    k_pk_sweep<NE, true><<<grid, block, 0, c.stream>>>(p.r, p.mu, p.ww, npairs, inv_r0, edges, inv_edges, n_edges,
+                                                       partial);
   else
-    k_pk_sweep<NE, false><<<grid, block, 0, c.stream>>>(p.r, p.mu, p.ww, npairs, inv_r0, edges, n_edges, partial);
+    k_pk_sweep<NE, false><<<grid, block, 0, c.stream>>>(p.r, p.mu, p.ww, npairs, inv_r0, edges, inv_edges, n_edges,
+                                                        partial);
   HIPSTER_HIP(hipGetLastError());
 }
 
@@ -163,7 +171,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_pk_tasks(const double *__restri
     const double *edges = edges_all + bx.edge_off;
     const int n_edges = bx.n_edges;
     double *row = rows + int64_t(t) * cols;
-    for (int e0 = 0; e0 < n_edges; e0 += kChunk) {
+    const int nchunk = (n_edges + kChunk - 1) / kChunk, per = (n_edges + nchunk - 1) / nchunk;
+    for (int e0 = 0; e0 < n_edges; e0 += per) {
+      const int e_end = e0 + per < n_edges ? e0 + per : n_edges;
       double acc[NE][kChunk];
 #pragma unroll
       for (int i = 0; i < NE; ++i)
@@ -180,7 +190,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_pk_tasks(const double *__restri
 #pragma unroll
         for (int cc = 0; cc < kChunk; ++cc) {
           const int e = e0 + cc;
-          if (e < n_edges) {
+          if (e < e_end) {
             const double u = edges[e] * r;
             Gv<double, NE> G;
             if constexpr (FP64) G = G_fp64<NE, 2>(u);
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_pk_tasks(const double *__restri
         for (int cc = 0; cc < kChunk; ++cc) {
           const double v = wave_sum(acc[i][cc]);
           const int e = e0 + cc;
-          if (lane == 0 && e < n_edges) row[i * n_edges + e] = v;
+          if (lane == 0 && e < e_end) row[i * n_edges + e] = v;
         }
     }
   }

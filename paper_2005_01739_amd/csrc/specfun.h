@@ -213,6 +213,37 @@ __device__ inline void sincos_reduced64(double u, double &s, double &c) {
   c = ((q + 1) & 2) ? -cc : cc;
 }
 
+// The same for the mixed form, through x^15 / x^16 (truncation < 2e-14,
+// far below the single-precision parts of that form).
+__device__ inline void sincos_reduced64_short(double u, double &s, double &c) {
+  double n = rint(u * kTwoOverPi);
+  double x = fma(-n, kPio2Hi, u);
+  x = fma(-n, kPio2Lo, x);
+  double x2 = x * x;
+  double sp = -7.6471637318198165e-13;  // -1/15!
+  sp = fma(sp, x2, 1.6059043836821613e-10);
+  sp = fma(sp, x2, -2.5052108385441720e-08);
+  sp = fma(sp, x2, 2.7557319223985893e-06);
+  sp = fma(sp, x2, -1.9841269841269841e-04);
+  sp = fma(sp, x2, 8.3333333333333333e-03);
+  sp = fma(sp, x2, -1.6666666666666667e-01);
+  sp = fma(sp * x2, x, x);
+  double cp = 4.7794773323873853e-14;  // 1/16!
+  cp = fma(cp, x2, -1.1470745597729725e-11);
+  cp = fma(cp, x2, 2.0876756987868099e-09);
+  cp = fma(cp, x2, -2.7557319223985891e-07);
+  cp = fma(cp, x2, 2.4801587301587302e-05);
+  cp = fma(cp, x2, -1.3888888888888889e-03);
+  cp = fma(cp, x2, 4.1666666666666667e-02);
+  cp = fma(cp, x2, -0.5);
+  cp = fma(cp, x2, 1.0);
+  int q = int(int64_t(n) & 3);
+  double ss = (q & 1) ? cp : sp;
+  double cc = (q & 1) ? sp : cp;
+  s = (q & 2) ? -ss : ss;
+  c = ((q + 1) & 2) ? -cc : cc;
+}
+
 template <int N>
 __device__ inline float horner32(const float (&p)[N], float t) {
   float r = p[N - 1];
@@ -222,7 +253,7 @@ __device__ inline float horner32(const float (&p)[N], float t) {
 }
 
 // Closed form in the mixed form: the phase is reduced in double precision and
-// sin, cos and the Laurent amplitudes a_l, b_l are kept in double -- bin
+// sin, cos (polynomials through x^15 / x^16) and the Laurent amplitudes a_l, b_l are kept in double -- bin
 // averages difference neighbouring edges, and single-precision amplitudes
 // leave per-pair errors of ~5e-7 after that differencing.  The form is used
 // from u = kUSmall = 2 up: there its worst cancellation (l = 6 at u = 2, a
@@ -231,14 +262,14 @@ __device__ inline float horner32(const float (&p)[N], float t) {
 // through its auxiliary functions f and g above; f and g are evaluated in
 // single precision, since they enter multiplied by c_l / u and need only
 // ~1e-8 relative accuracy.  Below u = 2 G_l is summed from its Taylor series.
+// wd = 1/u, supplied by the caller (from per-pair 1/r and per-edge 1/k).
 template <int NL, int LSTEP>
-__device__ inline Gv<double, NL> G_mixed(double u) {
+__device__ inline Gv<double, NL> G_mixed_w(double u, double wd) {
   constexpr bool kNeedSi = (NL - 1) * LSTEP >= 2;  // some even l >= 2 is requested
   if (u < kUSmall) return G_taylor64<NL, LSTEP>(u);
   Gv<double, NL> G;
   double s, c;
-  sincos_reduced64(u, s, c);
-  const double wd = 1.0 / u;
+  sincos_reduced64_short(u, s, c);
   double si = 0.0;
   if constexpr (kNeedSi) {
     if (u < HIPSTER_U_BIG) {
@@ -248,8 +279,7 @@ __device__ inline Gv<double, NL> G_mixed(double u) {
       for (int n = HIPSTER_N_SI_TAYLOR - 2; n >= 0; --n) p = fma(p, v, SI_TAYLOR[n]);
       si = p * u;
     } else {
-      const float uf = float(u);
-      const float w = __builtin_amdgcn_rcpf(uf);
+      const float w = float(wd);
       const float t = float(HIPSTER_U_BIG) * w;
       const float f = horner32(POLY_F32, t) * w;
       const float g = horner32(POLY_G32, t) * w * w;
@@ -260,6 +290,15 @@ __device__ inline Gv<double, NL> G_mixed(double u) {
 #pragma unroll
   for (int i = 0; i < NL; ++i) G.v[i] = Dt_closed<double>(i * LSTEP, u, wd, s, c, si) * w3;
   return G;
+}
+
+template <int NL, int LSTEP>
+__device__ inline Gv<double, NL> G_mixed(double u) {
+  // 1/u from the single-precision reciprocal and two Newton steps (~1e-16)
+  double wd = double(__builtin_amdgcn_rcpf(float(u)));
+  wd = wd * fma(-u, wd, 2.0);
+  wd = wd * fma(-u, wd, 2.0);
+  return G_mixed_w<NL, LSTEP>(u, wd);
 }
 
 }  // namespace hipster
