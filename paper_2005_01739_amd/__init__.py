@@ -66,7 +66,9 @@ _lib = None
 
 
 def library_path() -> str:
-    return os.path.join(_HERE, "libhipster.so")
+    """The in-tree build, or the file named by HIPSTER_LIBRARY (an alternative
+    build of the same sources, e.g. with different compile-time tuning)."""
+    return os.environ.get("HIPSTER_LIBRARY") or os.path.join(_HERE, "libhipster.so")
 
 
 def load_library():

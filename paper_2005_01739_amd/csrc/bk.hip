@@ -46,8 +46,8 @@ __device__ inline double bk_sq_norm(double dx, double dy, double dz) {
 // Real orthonormal spherical harmonics y_lm of a unit vector, index l*l+l+m:
 // y_l0 = N_l0 Q_l^0(z), y_lm = N_lm Q_l^m(z) Re (x+iy)^m, y_l-m = N_lm Q_l^m(z) Im (x+iy)^m,
 // with Q_l^m = d^m P_l / dz^m by its three-term recurrence.
-template <int LM>
-__device__ inline void real_ylm(double x, double y, double z, double (&Y)[(LM + 1) * (LM + 1)]) {
+template <int LM, typename Out>
+__device__ inline void real_ylm(double x, double y, double z, Out Y) {
   double C[LM + 1], S[LM + 1];
   C[0] = 1.0;
   S[0] = 0.0;
@@ -103,6 +103,12 @@ __device__ inline d4_t mfma_f64(double a, double b, d4_t c) {
 
 constexpr int kHitCap = 128;
 
+// Minimum waves per SIMD the compiler must fit the fused kernel into (1 lets
+// it use all 512 registers; 2 trades a few spills for twice the occupancy).
+#ifndef HIPSTER_BK_WAVES_PER_EU
+#define HIPSTER_BK_WAVES_PER_EU 1
+#endif
+
 size_t bk_fused_lds(int NL) {
   // y_lm staging [64][NL^2] and the A tile [NL][16][16] share the allocation
   const size_t a = size_t(64) * NL * NL, b = size_t(256) * NL;
@@ -110,7 +116,7 @@ size_t bk_fused_lds(int NL) {
 }
 
 template <int NL, bool FP64>
-__global__ __launch_bounds__(64) void k_bk_fused(Sorted prim, Sorted sec, int nc, double L, double r02, int self_set,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_WAVES_PER_EU))) void k_bk_fused(Sorted prim, Sorted sec, int nc, double L, double r02, int self_set,
                                                  int64_t p_lo, int64_t p_hi, double inv_r0,
                                                  const double *__restrict__ edges, const double *__restrict__ coef,
                                                  int NK, double *__restrict__ partial, int rowlen,
@@ -131,12 +137,12 @@ __global__ __launch_bounds__(64) void k_bk_fused(Sorted prim, Sorted sec, int nc
   const double kn3 = kn * kn * kn;
   const double cfb = has_bin ? coef[col] : 0.0;
   const bool extra_edge = (col == 15) && (NK == 16);  // the 17th edge
-  d4_t accC[NL], accG[NL];
+  d4_t accC[NL];
 #pragma unroll
-  for (int l = 0; l < NL; ++l) {
-    accC[l] = d4_t{0.0, 0.0, 0.0, 0.0};
-    accG[l] = d4_t{0.0, 0.0, 0.0, 0.0};
-  }
+  for (int l = 0; l < NL; ++l) accC[l] = d4_t{0.0, 0.0, 0.0, 0.0};
+  // the Gram sums live in this wave's own row of `partial` (zeroed by the
+  // host), updated once per primary, to keep registers for the batch work
+  double *row = partial + int64_t(blockIdx.x) * rowlen;
   double accS0 = 0.0;
   unsigned long long pcount = 0;
   int64_t cur_cell = -1;
@@ -173,16 +179,11 @@ __global__ __launch_bounds__(64) void k_bk_fused(Sorted prim, Sorted sec, int nc
 
     auto batch = [&](int nv) {
       // y_lm of the lane's own pair into LDS (zeros past the batch)
-      {
-        double Y[NLM];
-        if (lane < nv) {
-          real_ylm<NL - 1>(hb_x[lane], hb_y[lane], hb_z[lane], Y);
-        } else {
+      if (lane < nv) {
+        real_ylm<NL - 1>(hb_x[lane], hb_y[lane], hb_z[lane], ylds + lane * NLM);
+      } else {
 #pragma unroll
-          for (int q = 0; q < NLM; ++q) Y[q] = 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < NLM; ++q) ylds[lane * NLM + q] = Y[q];
+        for (int q = 0; q < NLM; ++q) ylds[lane * NLM + q] = 0.0;
       }
       __syncthreads();
       for (int s = 0; s < 16 && 4 * s < nv; ++s) {
@@ -291,22 +292,25 @@ __global__ __launch_bounds__(64) void k_bk_fused(Sorted prim, Sorted sec, int nc
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       const double sc = wp * (4.0 * kPi / double(2 * l + 1));
+      d4_t g4;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) g4[v] = row[l * 256 + (t4 + 4 * v) * 16 + col];
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
         const double x = ylds[l * 256 + col * 16 + 4 * s2 + t4];
-        accG[l] = mfma_f64(x * sc, x, accG[l]);
+        g4 = mfma_f64(x * sc, x, g4);
       }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) row[l * 256 + (t4 + 4 * v) * 16 + col] = g4[v];
     }
     __syncthreads();
   }
-  // per-wave partial row: [G tiles NL*256 | C tiles NL*256 | S0 16]
-  double *row = partial + int64_t(blockIdx.x) * rowlen;
+  // per-wave partial row: [G tiles NL*256 (already there) | C tiles NL*256 | S0 16]
 #pragma unroll
   for (int l = 0; l < NL; ++l)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int e = (t4 + 4 * v) * 16 + col;
-      row[l * 256 + e] += accG[l][v];
       row[NL * 256 + l * 256 + e] += accC[l][v];
     }
   double s0 = accS0;
