@@ -55,6 +55,15 @@ def pk_flops_per_pair(n_k: int, n_ell: int) -> float:
     return 40.0 + 80.0 * (n_k + 1) + 5.0 * n_k * n_ell
 
 
+def bk_flops_per_pair(n_k: int, ell_max: int) -> float:
+    """Algorithmic FLOPs per ordered pair for the bispectrum weights: the special
+    functions at n_k+1 edges (60 shared + 10 per multipole per edge), the real
+    harmonics (6 per y_lm), the A_lm sums (2 n_k (l_max+1)^2) and the C^ab_l sums
+    over a <= b (2 (l_max+1) n_k (n_k+1)/2)."""
+    n_l = ell_max + 1
+    return 40.0 + (60.0 + 10.0 * n_l) * (n_k + 1) + 6.0 * n_l * n_l + 2.0 * n_k * n_l * n_l + n_l * n_k * (n_k + 1)
+
+
 def traffic_from_profile():
     """HBM bytes per sweep launch from the committed counter summary, or None."""
     if not os.path.exists(PROFILE):
@@ -220,8 +229,12 @@ def main():
                            "traffic": traffic_from_profile() if args.workload == "pk" else None,
                            "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
     else:
-        out["roofline"] = {"bound": "alu", "kernel": "k_bk_sweep", "achieved": None, "peak": PEAK_VALU_TFLOPS,
-                           "unit": "TFLOP/s", "frac": None, "traffic": None, "avg_launch_ms": avg_launch_ms}
+        # both primary catalogues, per launch (data primaries, then random primaries)
+        flops = (pairs + pairs_r) * bk_flops_per_pair(n_k, wl.ell_max_b) / (launches / args.steps)
+        achieved = flops / (avg_launch_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": "k_bk_fused", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+                           "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                           "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
     out["pairs_per_step"] = pairs + pairs_r
     if not args.no_cpu_baseline and args.workload == "pk":
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_primaries)
