@@ -141,7 +141,7 @@ void merge_partials(Ctx &c, const double *partial, int rows, int cols, double *o
 void bk_fused(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
               const double *edges, const double *coef, int NK, int ell_max, bool fp64, double *partial, int rowlen,
               int nwaves, unsigned long long *npairs);
-size_t bk_fused_lds(int NL);
+size_t bk_fused_lds(int NL, int NK);
 void widen_i32(Ctx &c, const int *in, int64_t *out, int64_t n);
 
 // Host analytic terms.
