@@ -183,7 +183,9 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
   // count pass (two r-buckets), offsets
   const int64_t ncells = g.ncells();
   const bool fp64 = q->precision == HIPSTER_FP64;
-  const double r_split = q->k_edges[0] > 0.0 ? (fp64 ? HIPSTER_U_BIG : kUSmall) / q->k_edges[0] : 0.0;
+  // pairs with r >= U_BIG / k_0 evaluate every edge on the large-argument
+  // path (closed form with the Si auxiliaries); the near bucket holds the rest
+  const double r_split = q->k_edges[0] > 0.0 ? HIPSTER_U_BIG / q->k_edges[0] : 0.0;
   int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
   int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(ncells) * 8));
   int64_t *off_a = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));
@@ -528,7 +530,7 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
     const Sorted s = build_cells(c, c.cells_d, g, pos, w, mask, n, j.data.dtype);
     hipEvent_t a1 = tm.mark();
     const int64_t ncells = g.ncells();
-    const double r_split = q.k_edges[0] > 0.0 ? (fp64 ? HIPSTER_U_BIG : kUSmall) / q.k_edges[0] : 0.0;
+    const double r_split = q.k_edges[0] > 0.0 ? HIPSTER_U_BIG / q.k_edges[0] : 0.0;
     int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
     int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(ncells) * 8));
     int64_t *off_a = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));

@@ -133,10 +133,6 @@ __device__ inline double from_next_lane_in_row(double v) {
   return __hiloint2double(nhi, nlo);
 }
 
-// An empty asm that takes v in a register, so the load that produced v is
-// not turned into an exec-masked load by a later select.
-__device__ inline void pin(double &v) { asm volatile("" : "+v"(v)); }
-
 // y_lm staging of one lane's pair: element idx of pair q at ylds[idx][q],
 // rows padded to kBatch + 1 doubles so that lanes write distinct banks.
 struct YRow {
@@ -154,12 +150,11 @@ constexpr int kYStride = kBatch + 1;  // row stride of the y_lm staging
 static_assert(kYStride == 64 + 1, "YRow assumes kBatch = 64");
 
 size_t bk_fused_lds(int NL, int NK) {
-  // y_lm [NL^2][kYStride] and the top-edge values [NL][kBatch] (written for
-  // 16 bins only); after the batches the same memory holds the A tile
-  // [NL][16][16]
+  // y_lm [NL^2][kYStride], one row of zeros, then a region that holds the
+  // top-edge values [NL][kBatch] (16 bins) during batches and the A tile
+  // [NL][16][16] after them
   (void)NK;
-  const size_t a = size_t(kYStride) * NL * NL + size_t(NL) * kBatch, b = size_t(256) * NL;
-  return (a > b ? a : b) * 8;
+  return (size_t(kYStride) * (NL * NL + 1) + size_t(256) * NL) * 8;
 }
 
 // G_l(u) of the mixed form for the closed-form lanes, with lanes below
@@ -172,9 +167,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_W
     double *__restrict__ partial, int rowlen, unsigned long long *__restrict__ npairs) {
   constexpr int NLM = NL * NL;
   extern __shared__ __align__(16) double lds[];
-  double *ylds = lds;                    // [NLM][kYStride]
-  double *gtop = lds + kYStride * NLM;   // [NL][kBatch]: k_NK^3 G_l(k_NK r_q), written for 16 bins
-  __shared__ double hb_r[kHitCap], hb_ir[kHitCap], hb_f[kHitCap], hb_x[kHitCap], hb_y[kHitCap], hb_z[kHitCap];
+  double *ylds = lds;                          // [NLM + 1][kYStride], row NLM all zeros
+  double *gtop = lds + kYStride * (NLM + 1);   // [NL][kBatch]: k_NK^3 G_l(k_NK r_q), 16 bins
+  double *atile = gtop;                        // [NL][16][16] between primaries
+  // hit buffer; slot kHitCap is a neutral pair (weight 0) read by lanes
+  // past the end of a batch, so that no operand load needs a condition
+  __shared__ double hb_r[kHitCap + 1], hb_ir[kHitCap + 1], hb_f[kHitCap + 1], hb_x[kHitCap], hb_y[kHitCap],
+      hb_z[kHitCap];
   __shared__ int64_t nb_beg[27], nb_end[27], run_beg[27], run_end[27];
   __shared__ int nb_sh[27], run_sh[27], n_runs_s;
   const int lane = threadIdx.x, t4 = lane >> 4, col = lane & 15;
@@ -201,6 +200,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_W
   double accS0 = 0.0;
   unsigned long long pcount = 0;
   int64_t cur_cell = -1;
+  if (lane == 0) {
+    hb_r[kHitCap] = 0.5 / inv_r0;
+    hb_ir[kHitCap] = 2.0 * inv_r0;
+    hb_f[kHitCap] = 0.0;
+  }
+  ylds[NLM * kYStride + lane] = 0.0;
 
   // XCD-aware assignment: workgroups are dealt to the 8 XCDs round-robin, so
   // the waves of XCD x (blockIdx % 8 == x) share one contiguous eighth of the
@@ -274,43 +279,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_W
         __syncthreads();
         // 4 pairs per step: lane (col, t4) evaluates G_l at edge col for pair
         // q = 4s + t4, takes edge col+1 from the next lane, and feeds bin col
-        // of pair q to the matrix instructions.  The pair data of the next
-        // step is loaded one step ahead; every LDS read is unconditional and
-        // in bounds (q + 4 < kHitCap; y rows clamped to the l block), with
-        // entries past the batch masked by selects.
+        // of pair q to the matrix instructions.  Lanes past the batch read the
+        // neutral slot, and columns outside an l block read the zero row, so
+        // every load is unconditional.
         const int nsteps = (nv + 3) >> 2;
-        double pr = hb_r[t4], pir = hb_ir[t4], pf = hb_f[t4];
-        pin(pr);
-        pin(pir);
-        pin(pf);
         for (int s = 0; s < nsteps; ++s) {
           const int q = 4 * s + t4;
-          const bool valid = q < nv;
-          const double rq = valid ? pr : 0.0;
-          const double irq = valid ? pir : 0.0;
-          const double fb = valid ? pf * cfb : 0.0;
-          pr = hb_r[q + 4];
-          pir = hb_ir[q + 4];
-          pf = hb_f[q + 4];
-          pin(pr);
-          pin(pir);
-          pin(pf);
+          const int qe = q < nv ? q : kHitCap;
+          const double rq = hb_r[qe], irq = hb_ir[qe];
+          const double fb = hb_f[qe] * cfb;
           Gv<double, NL> Ge;
           if constexpr (FP64) Ge = G_fp64<NL, 1>(ke * rq);
           else Ge = G_mixed_w<NL, 1>(ke * rq, ike * irq);
 #pragma unroll
           for (int l = 0; l < NL; ++l) {
             const double gn = from_next_lane_in_row(Ge.v[l]);
-            double gt = gtop[l * kBatch + q];
-            pin(gt);
-            const double hi = top_lane ? gt : kn3 * gn;
+            const double hi = top_lane ? gtop[l * kBatch + q] : kn3 * gn;
             const double g = fb * (hi - ke3 * Ge.v[l]);
             if (l == 0) {
               a0 += g;
             } else {
-              double yv = ylds[(l * l + (col < 2 * l ? col : 2 * l)) * kYStride + q];
-              pin(yv);
-              const double y = col < 2 * l + 1 ? yv : 0.0;
+              const int row = col < 2 * l + 1 ? l * l + col : NLM;
+              const double y = ylds[row * kYStride + q];
               accA[l] = mfma_f64(g, y, accA[l]);
             }
             accC[l] = mfma_f64(g * wp, g, accC[l]);
@@ -430,14 +420,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_W
 #pragma unroll
         for (int l = 1; l < NL; ++l)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) lds[l * 256 + (t4 + 4 * v) * 16 + col] = accA[l][v];
+          for (int v = 0; v < 4; ++v) atile[l * 256 + (t4 + 4 * v) * 16 + col] = accA[l][v];
         __syncthreads();
 #pragma unroll
         for (int l = 1; l < NL; ++l) {
           const double sc = wp * (4.0 * kPi / double(2 * l + 1));
 #pragma unroll
           for (int s2 = 0; s2 < 4; ++s2) {
-            const double x = lds[l * 256 + col * 16 + 4 * s2 + t4];
+            const double x = atile[l * 256 + col * 16 + 4 * s2 + t4];
             accG[l] = mfma_f64(x * sc, x, accG[l]);
           }
         }

@@ -26,8 +26,13 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Minimum waves per SIMD for the sweep (a build-time tuning knob).
+#ifndef HIPSTER_PK_WAVES_PER_EU
+#define HIPSTER_PK_WAVES_PER_EU 1
+#endif
+
 template <int NE, bool FP64>
-__global__ __launch_bounds__(kSweepBlock) void k_pk_sweep(const double *__restrict__ pr,
+__global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIPSTER_PK_WAVES_PER_EU))) void k_pk_sweep(const double *__restrict__ pr,
                                                           const void *__restrict__ pmu_,
                                                           const void *__restrict__ pww_,
                                                           int64_t npairs, double inv_r0,

@@ -28,6 +28,17 @@
 namespace hipster {
 
 constexpr int kLMax = 6;
+
+// a * b + c rounded once, written as the three-operand v_fma_f64.  For a
+// Horner step whose addend is a constant held in a register, the compiler
+// otherwise emits the two-operand v_fmac_f64 (which overwrites its addend)
+// plus a copy of the constant, two instructions per step.  The result is the
+// same correctly rounded fused multiply-add either way.
+__device__ inline double fma3(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kHalfPi = 1.57079632679489661923;
 constexpr double kTwoOverPi = 0.63661977236758134308;
@@ -72,7 +83,7 @@ template <int NT>
 __device__ inline double taylor_G64(int l, double v, double ul) {
   double p = TAYLOR_G[l][NT - 1];
 #pragma unroll
-  for (int s = NT - 2; s >= 0; --s) p = fma(p, v, TAYLOR_G[l][s]);
+  for (int s = NT - 2; s >= 0; --s) p = fma3(p, v, TAYLOR_G[l][s]);
   return p * ul;
 }
 
@@ -188,24 +199,24 @@ __device__ inline void sincos_reduced64(double u, double &s, double &c) {
   x = fma(-n, kPio2Lo, x);
   double x2 = x * x;
   double sp = 2.8114572543455206e-15;  // 1/17!
-  sp = fma(sp, x2, -7.6471637318198165e-13);
-  sp = fma(sp, x2, 1.6059043836821613e-10);
-  sp = fma(sp, x2, -2.5052108385441720e-08);
-  sp = fma(sp, x2, 2.7557319223985893e-06);
-  sp = fma(sp, x2, -1.9841269841269841e-04);
-  sp = fma(sp, x2, 8.3333333333333333e-03);
-  sp = fma(sp, x2, -1.6666666666666667e-01);
+  sp = fma3(sp, x2, -7.6471637318198165e-13);
+  sp = fma3(sp, x2, 1.6059043836821613e-10);
+  sp = fma3(sp, x2, -2.5052108385441720e-08);
+  sp = fma3(sp, x2, 2.7557319223985893e-06);
+  sp = fma3(sp, x2, -1.9841269841269841e-04);
+  sp = fma3(sp, x2, 8.3333333333333333e-03);
+  sp = fma3(sp, x2, -1.6666666666666667e-01);
   sp = fma(sp * x2, x, x);
   double cp = -1.5619206968586225e-16;  // -1/18!
-  cp = fma(cp, x2, 4.7794773323873853e-14);
-  cp = fma(cp, x2, -1.1470745597729725e-11);
-  cp = fma(cp, x2, 2.0876756987868099e-09);
-  cp = fma(cp, x2, -2.7557319223985891e-07);
-  cp = fma(cp, x2, 2.4801587301587302e-05);
-  cp = fma(cp, x2, -1.3888888888888889e-03);
-  cp = fma(cp, x2, 4.1666666666666667e-02);
-  cp = fma(cp, x2, -0.5);
-  cp = fma(cp, x2, 1.0);
+  cp = fma3(cp, x2, 4.7794773323873853e-14);
+  cp = fma3(cp, x2, -1.1470745597729725e-11);
+  cp = fma3(cp, x2, 2.0876756987868099e-09);
+  cp = fma3(cp, x2, -2.7557319223985891e-07);
+  cp = fma3(cp, x2, 2.4801587301587302e-05);
+  cp = fma3(cp, x2, -1.3888888888888889e-03);
+  cp = fma3(cp, x2, 4.1666666666666667e-02);
+  cp = fma3(cp, x2, -0.5);
+  cp = fma3(cp, x2, 1.0);
   int q = int(int64_t(n) & 3);
   double ss = (q & 1) ? cp : sp;
   double cc = (q & 1) ? sp : cp;
@@ -221,22 +232,22 @@ __device__ inline void sincos_reduced64_short(double u, double &s, double &c) {
   x = fma(-n, kPio2Lo, x);
   double x2 = x * x;
   double sp = -7.6471637318198165e-13;  // -1/15!
-  sp = fma(sp, x2, 1.6059043836821613e-10);
-  sp = fma(sp, x2, -2.5052108385441720e-08);
-  sp = fma(sp, x2, 2.7557319223985893e-06);
-  sp = fma(sp, x2, -1.9841269841269841e-04);
-  sp = fma(sp, x2, 8.3333333333333333e-03);
-  sp = fma(sp, x2, -1.6666666666666667e-01);
+  sp = fma3(sp, x2, 1.6059043836821613e-10);
+  sp = fma3(sp, x2, -2.5052108385441720e-08);
+  sp = fma3(sp, x2, 2.7557319223985893e-06);
+  sp = fma3(sp, x2, -1.9841269841269841e-04);
+  sp = fma3(sp, x2, 8.3333333333333333e-03);
+  sp = fma3(sp, x2, -1.6666666666666667e-01);
   sp = fma(sp * x2, x, x);
   double cp = 4.7794773323873853e-14;  // 1/16!
-  cp = fma(cp, x2, -1.1470745597729725e-11);
-  cp = fma(cp, x2, 2.0876756987868099e-09);
-  cp = fma(cp, x2, -2.7557319223985891e-07);
-  cp = fma(cp, x2, 2.4801587301587302e-05);
-  cp = fma(cp, x2, -1.3888888888888889e-03);
-  cp = fma(cp, x2, 4.1666666666666667e-02);
-  cp = fma(cp, x2, -0.5);
-  cp = fma(cp, x2, 1.0);
+  cp = fma3(cp, x2, -1.1470745597729725e-11);
+  cp = fma3(cp, x2, 2.0876756987868099e-09);
+  cp = fma3(cp, x2, -2.7557319223985891e-07);
+  cp = fma3(cp, x2, 2.4801587301587302e-05);
+  cp = fma3(cp, x2, -1.3888888888888889e-03);
+  cp = fma3(cp, x2, 4.1666666666666667e-02);
+  cp = fma3(cp, x2, -0.5);
+  cp = fma3(cp, x2, 1.0);
   int q = int(int64_t(n) & 3);
   double ss = (q & 1) ? cp : sp;
   double cc = (q & 1) ? sp : cp;
@@ -276,7 +287,7 @@ __device__ inline Gv<double, NL> G_mixed_w(double u, double wd) {
       const double v = u * u;
       double p = SI_TAYLOR[HIPSTER_N_SI_TAYLOR - 1];
 #pragma unroll
-      for (int n = HIPSTER_N_SI_TAYLOR - 2; n >= 0; --n) p = fma(p, v, SI_TAYLOR[n]);
+      for (int n = HIPSTER_N_SI_TAYLOR - 2; n >= 0; --n) p = fma3(p, v, SI_TAYLOR[n]);
       si = p * u;
     } else {
       const float w = float(wd);
