@@ -2,9 +2,11 @@
 // R0 of a periodic box is found once by a half stencil of 14 cells (the home
 // cell with i < j, and 13 forward neighbours with all i, j), each neighbour
 // carrying its periodic image shift.  Pairs are compacted wave-by-wave
-// (ballot + popcount) into a coalesced stream (r, mu, w_i w_j m_ij) in double precision, written
-// in a deterministic order: a count pass sizes each home cell's output, an
-// exclusive scan gives offsets, and a write pass repeats the same tests.
+// (ballot + popcount) into a coalesced stream (r, mu, w_i w_j m_ij) in double
+// precision, written in a deterministic order: a count pass sizes each home
+// cell's output, an exclusive scan gives offsets, and a write pass repeats the
+// same tests.  The home cell and each neighbour are staged through LDS in
+// tiles of 64 points, and a tile pair's candidates are packed 64 per step.
 //
 // Pairs are written in two buckets: r < r_split first, then the rest.  With
 // r_split = u_switch / k_min no pair of the second bucket ever takes the
@@ -59,6 +61,17 @@ __device__ inline double sq_norm_exact(double dx, double dy, double dz) {
   return (a + b) + c;
 }
 
+constexpr int kPairTile = 64;  // points of a cell staged in LDS at a time
+
+// q / d for 0 <= q < 2^16 and 1 <= d <= kPairTile, from a single-precision
+// reciprocal and an exact correction.
+__device__ inline uint32_t small_div(uint32_t q, uint32_t d, float inv_d) {
+  uint32_t t = uint32_t(float(q) * inv_d);
+  if (t * d > q) --t;
+  else if ((t + 1) * d <= q) ++t;
+  return t;
+}
+
 template <bool WRITE, typename T>
 __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, double r02, double rs2, int los,
                                                  int64_t *__restrict__ cnt_a, int64_t *__restrict__ cnt_b,
@@ -67,6 +80,11 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
                                                  int64_t base_a, int64_t base_b, int64_t n_a,
                                                  int64_t c0, double *__restrict__ out_r,
                                                  T *__restrict__ out_mu, T *__restrict__ out_ww) {
+  // home-cell and neighbour-cell tiles of kPairTile points in LDS; the
+  // candidates of a tile pair are packed 64 to a step
+  __shared__ double hx[kPairTile], hy[kPairTile], hz[kPairTile], hw[kPairTile];
+  __shared__ double jx[kPairTile], jy[kPairTile], jz[kPairTile], jw[kPairTile];
+  __shared__ int hm[kPairTile], jm[kPairTile];
   const int64_t cell = c0 + blockIdx.x;
   const int lane = threadIdx.x;
   const int cz = int(cell % nc), cy = int((cell / nc) % nc), cx = int(cell / (int64_t(nc) * nc));
@@ -76,55 +94,81 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
   unsigned long long ord = 0;
   const int64_t wbase_a = WRITE ? off_a[cell] - base_a : 0;
   const int64_t wbase_b = WRITE ? n_a + off_b[cell] - base_b : 0;
-  for (int st = 0; st < 14 && ni > 0; ++st) {
-    int ox, oy, oz, sx, sy, sz;
-    half_stencil(st, ox, oy, oz);
-    const int nx = wrap_axis(cx + ox, nc, sx), ny = wrap_axis(cy + oy, nc, sy), nz = wrap_axis(cz + oz, nc, sz);
-    const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
-    const int64_t js = s.cell_start[nb];
-    const int nj = int(s.cell_start[nb + 1] - js);
-    if (nj == 0) continue;
-    const bool self = (st == 0);
-    const uint32_t total = uint32_t(ni) * uint32_t(nj);
-    for (uint32_t q0 = 0; q0 < total; q0 += 64) {
-      const uint32_t q = q0 + lane;
-      bool hit = false, near = false;
-      double r = 0.0, mu = 0.0, ww = 0.0;
-      if (q < total) {
-        const uint32_t ii = q / uint32_t(nj), jj = q - ii * uint32_t(nj);
-        if (!self || jj > ii) {
-          const int64_t i = hs + ii, j = js + jj;
-          const double dx = image(s.x[i] - s.x[j], sx, L);
-          const double dy = image(s.y[i] - s.y[j], sy, L);
-          const double dz = image(s.z[i] - s.z[j], sz, L);
-          const double r2 = sq_norm_exact(dx, dy, dz);
-          if (r2 < r02) {
-            const int mult = s.m ? int(s.m[i]) + int(s.m[j]) : 2;
-            ord += unsigned(mult);
-            if (mult > 0) {
-              hit = true;
-              near = r2 < rs2;
-              if (WRITE) {
-                r = sqrt(r2);
-                const double dl = los == 0 ? dx : (los == 1 ? dy : dz);
-                mu = r > 0.0 ? dl / r : 0.0;
-                ww = s.w[i] * s.w[j] * double(mult);
+  for (int i0 = 0; i0 < ni; i0 += kPairTile) {
+    const int ti = ni - i0 < kPairTile ? ni - i0 : kPairTile;
+    __syncthreads();
+    if (lane < ti) {
+      const int64_t i = hs + i0 + lane;
+      hx[lane] = s.x[i];
+      hy[lane] = s.y[i];
+      hz[lane] = s.z[i];
+      hw[lane] = s.w[i];
+      hm[lane] = s.m ? int(s.m[i]) : 1;
+    }
+    for (int st = 0; st < 14; ++st) {
+      int ox, oy, oz, sx, sy, sz;
+      half_stencil(st, ox, oy, oz);
+      const int nx = wrap_axis(cx + ox, nc, sx), ny = wrap_axis(cy + oy, nc, sy), nz = wrap_axis(cz + oz, nc, sz);
+      const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
+      const int64_t js = s.cell_start[nb];
+      const int nj = int(s.cell_start[nb + 1] - js);
+      const bool self = (st == 0);
+      // in the home cell only pairs j > i: tiles wholly below the home tile
+      // hold none
+      for (int j0 = self ? i0 : 0; j0 < nj; j0 += kPairTile) {
+        const int tj = nj - j0 < kPairTile ? nj - j0 : kPairTile;
+        __syncthreads();
+        if (lane < tj) {
+          const int64_t j = js + j0 + lane;
+          jx[lane] = s.x[j];
+          jy[lane] = s.y[j];
+          jz[lane] = s.z[j];
+          jw[lane] = s.w[j];
+          jm[lane] = s.m ? int(s.m[j]) : 1;
+        }
+        __syncthreads();
+        const uint32_t total = uint32_t(ti) * uint32_t(tj);
+        const float inv_tj = 1.0f / float(tj);
+        for (uint32_t q0 = 0; q0 < total; q0 += 64) {
+          const uint32_t q = q0 + lane;
+          bool hit = false, near = false;
+          double r = 0.0, mu = 0.0, ww = 0.0;
+          if (q < total) {
+            const uint32_t ii = small_div(q, uint32_t(tj), inv_tj), jj = q - ii * uint32_t(tj);
+            if (!self || j0 + int(jj) > i0 + int(ii)) {
+              const double dx = image(hx[ii] - jx[jj], sx, L);
+              const double dy = image(hy[ii] - jy[jj], sy, L);
+              const double dz = image(hz[ii] - jz[jj], sz, L);
+              const double r2 = sq_norm_exact(dx, dy, dz);
+              if (r2 < r02) {
+                const int mult = hm[ii] + jm[jj];
+                ord += unsigned(mult);
+                if (mult > 0) {
+                  hit = true;
+                  near = r2 < rs2;
+                  if (WRITE) {
+                    r = sqrt(r2);
+                    const double dl = los == 0 ? dx : (los == 1 ? dy : dz);
+                    mu = r > 0.0 ? dl / r : 0.0;
+                    ww = hw[ii] * jw[jj] * double(mult);
+                  }
+                }
               }
             }
           }
+          const unsigned long long bal_a = __ballot(hit && near), bal_b = __ballot(hit && !near);
+          if (WRITE && hit) {
+            const unsigned long long below = (1ull << lane) - 1ull;
+            const int64_t k = near ? wbase_a + written_a + __popcll(bal_a & below)
+                                   : wbase_b + written_b + __popcll(bal_b & below);
+            out_r[k] = r;
+            out_mu[k] = T(mu);
+            out_ww[k] = T(ww);
+          }
+          written_a += __popcll(bal_a);
+          written_b += __popcll(bal_b);
         }
       }
-      const unsigned long long bal_a = __ballot(hit && near), bal_b = __ballot(hit && !near);
-      if (WRITE && hit) {
-        const unsigned long long below = (1ull << lane) - 1ull;
-        const int64_t k = near ? wbase_a + written_a + __popcll(bal_a & below)
-                               : wbase_b + written_b + __popcll(bal_b & below);
-        out_r[k] = r;
-        out_mu[k] = T(mu);
-        out_ww[k] = T(ww);
-      }
-      written_a += __popcll(bal_a);
-      written_b += __popcll(bal_b);
     }
   }
   if (!WRITE) {
