@@ -56,6 +56,10 @@ def lib():
         L.oracle_pk_ell.restype = ct.c_int
         L.oracle_pk_ell.argtypes = [ct.c_int64, _dp, _dp, ct.c_double, ct.c_double, ct.c_int, _dp,
                                     ct.c_int, ct.c_int, _u8p, _dp, _dp, _dp, _dp, _u64p, ct.c_int]
+        L.oracle_pk_survey.restype = ct.c_int
+        L.oracle_pk_survey.argtypes = [ct.c_int64, _dp, _dp, _u8p, ct.c_int64, _dp, _dp, _u8p,
+                                       ct.c_double, ct.c_double, ct.c_int, _dp, ct.c_int,
+                                       _dp, _dp, _dp, _dp, _dp, _u64p, ct.c_int]
         L.oracle_bk_ell.restype = ct.c_int
         L.oracle_bk_ell.argtypes = [ct.c_int64, _dp, _dp, ct.c_int64, _dp, _dp, ct.c_double,
                                     ct.c_double, ct.c_int, _dp, ct.c_int, _u8p, _u8p, _dp, _dp,
@@ -138,6 +142,32 @@ def pk_ell(pos, w, box, r0, k_edges, ell_max=4, los_axis=2, primary_mask=None, n
     if rc != 0:
         raise ValueError("oracle_pk_ell: argument outside the oracle's range")
     return {"pk": pk, "raw": raw, "l1": l1, "wtilde": wt, "n_pairs": int(npairs.value)}
+
+
+def pk_survey(pos, w, rpos, rw, volume, r0, k_edges, ell_max=4, mask_d=None, mask_r=None, nthreads=0):
+    """Brute-force survey-geometry P^a_ell (no periodicity, observer at the
+    origin, pair-midpoint line of sight; even ell <= ell_max).  Returns a dict
+    with pk, raw_dd, raw_dr (DR + RD), raw_rr, l1 ([n_ell, n_k]) and the
+    contributing ordered pair counts n_dd, n_dr, n_rr."""
+    pos = _f64(pos).reshape(-1, 3)
+    w = _f64(w)
+    rpos = _f64(rpos).reshape(-1, 3)
+    rw = _f64(rw)
+    k = _f64(k_edges)
+    n_k = k.size - 1
+    shp = (ell_max // 2 + 1, n_k)
+    out = {name: np.zeros(shp) for name in ("pk", "raw_dd", "raw_dr", "raw_rr", "l1")}
+    counts = (ct.c_uint64 * 3)()
+    md = None if mask_d is None else np.ascontiguousarray(mask_d, dtype=np.uint8)
+    mr = None if mask_r is None else np.ascontiguousarray(mask_r, dtype=np.uint8)
+    rc = lib().oracle_pk_survey(pos.shape[0], _ptr(pos), _ptr(w), _ptr(md, _u8p), rpos.shape[0], _ptr(rpos),
+                                _ptr(rw), _ptr(mr, _u8p), float(volume), float(r0), n_k, _ptr(k), int(ell_max),
+                                _ptr(out["pk"]), _ptr(out["raw_dd"]), _ptr(out["raw_dr"]), _ptr(out["raw_rr"]),
+                                _ptr(out["l1"]), ct.cast(counts, _u64p), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_pk_survey: argument outside the oracle's range")
+    out["n_dd"], out["n_dr"], out["n_rr"] = int(counts[0]), int(counts[1]), int(counts[2])
+    return out
 
 
 def bk_ell(pos, w, rpos, rw, box, r0, k_edges, ell_max, mask_d=None, mask_r=None, nthreads=0):

@@ -21,7 +21,8 @@
  *  - weights w_i enter as w_i w_j (Sec. 2 footnote on weights); the mean
  *    density is n_w = sum(w) / V;
  *  - the line of sight is a fixed box axis (Sec. 2, fixed LoS for
- *    simulations), default z.
+ *    simulations), default z; the survey-geometry estimator (no periodicity)
+ *    takes it along each pair's midpoint, the observer at the origin.
  *
  * Parity status: every function below is pinned by tests against mpmath or
  * scipy evaluations, closed forms, brute-force triple sums or exact
@@ -431,6 +432,129 @@ int oracle_pk_ell(int64_t n, const double *pos, const double *w, double box, dou
     if (n_pairs) *n_pairs = ctot;
     free(acc);
     free(cnt);
+    return 0;
+}
+
+/* ----------------------------------------------- survey-geometry power spectrum */
+/* The general estimator of Sec. 2 (eq. general-Pk-ell with the pair counts of
+ * eq. general-XY-counts), binned in k as in Sec. 3 (eq. jla-def): data D and
+ * randoms R at arbitrary positions, no periodicity, observer at the origin,
+ * and the line of sight of pair (i, j) along its midpoint (x_i + x_j) / 2.
+ *
+ *   XY^a_l = (-i)^l (2l+1) sum_{i in X} sum_{j in Y, j != i if X = Y}
+ *            v_i v_j jbar^a_l(r_ij) L_l(xhat_ij . nhat_ij) W(r_ij / R0)
+ *   P^a_l  = [DD - (DR + RD) + RR]^a_l / (n_w^2 V),   n_w = sum(w_D) / V
+ *
+ * with v = w for data and v = s_R w for randoms, s_R = sum(w_D) / sum(w_R)
+ * (random catalogues normalised to the data, the reading also used for the
+ * bispectrum), and DR + RD = 2 DR for even l.  V is the caller's survey
+ * volume.  A pair counts iff r^2 < R0^2 with r^2 = (dx^2 + dy^2) + dz^2 in
+ * FP64; mu = 0 when r = 0 or the midpoint is the observer.  Masks: only
+ * ordered pairs (i, j) whose first point has mask != 0 contribute.
+ * Accumulates the ordered pairs (i in X, j in Y) of one kind into S, |S| into
+ * A, with the factor f = v-scale of the pair kind. */
+static uint64_t survey_pair_sums(int64_t nx, const double *px, const double *wx, const uint8_t *mx,
+                                 int64_t ny, const double *py, const double *wy, int same, double f,
+                                 double r0, int n_k, const double *k, int n_ell, double *S, double *A,
+                                 int nthreads)
+{
+    const size_t nacc = (size_t)n_ell * n_k;
+    const int nt = nthreads_or_default(nthreads);
+    double *acc = calloc((size_t)nt * nacc * 2, sizeof(double));
+    uint64_t *cnt = calloc((size_t)nt, sizeof(uint64_t));
+    const double r02 = r0 * r0;
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+        double *Sl = acc + (size_t)tid * nacc * 2, *Al = Sl + nacc;
+        double jb[ORACLE_NK_MAX];
+        uint64_t c = 0;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nx; ++i) {
+            if (mx && !mx[i]) continue;
+            const double wi = wx ? wx[i] : 1.0;
+            for (int64_t j = 0; j < ny; ++j) {
+                if (same && j == i) continue;
+                double d[3], m[3];
+                for (int ax = 0; ax < 3; ++ax) {
+                    d[ax] = px[3 * i + ax] - py[3 * j + ax];
+                    m[ax] = px[3 * i + ax] + py[3 * j + ax];
+                }
+                double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                if (!(r2 < r02)) continue;
+                ++c;
+                double r = sqrt(r2);
+                double mn = sqrt((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2]);
+                double mu = (r > 0.0 && mn > 0.0) ? ((d[0] * m[0] + d[1] * m[1]) + d[2] * m[2]) / (r * mn) : 0.0;
+                double wgt = f * wi * (wy ? wy[j] : 1.0) * oracle_window(r / r0);
+                for (int li = 0; li < n_ell; ++li) {
+                    int ell = 2 * li;
+                    double phase = (li & 1) ? -1.0 : 1.0; /* (-i)^ell, ell even */
+                    double lw = (2.0 * ell + 1.0) * phase * wgt * oracle_legendre(ell, mu);
+                    jbar_all_bins(ell, r, n_k, k, jb);
+                    for (int a = 0; a < n_k; ++a) {
+                        double term = lw * jb[a];
+                        Sl[li * n_k + a] += term;
+                        Al[li * n_k + a] += fabs(term);
+                    }
+                }
+            }
+        }
+        cnt[tid] = c;
+    }
+    uint64_t ctot = 0;
+    for (int t = 0; t < nt; ++t) {
+        ctot += cnt[t];
+        for (size_t q = 0; q < nacc; ++q) {
+            S[q] += acc[(size_t)t * nacc * 2 + q];
+            A[q] += acc[(size_t)t * nacc * 2 + nacc + q];
+        }
+    }
+    free(acc);
+    free(cnt);
+    return ctot;
+}
+
+int oracle_pk_survey(int64_t nd, const double *pd, const double *wd, const uint8_t *md,
+                     int64_t nr, const double *pr, const double *wr, const uint8_t *mr,
+                     double volume, double r0, int n_k, const double *k, int ell_max,
+                     double *pk, double *raw_dd, double *raw_dr, double *raw_rr, double *l1,
+                     uint64_t *counts, int nthreads)
+{
+    if (nd < 1 || nr < 1 || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 || ell_max > ORACLE_ELL_MAX ||
+        (ell_max & 1) || !(r0 > 0.0) || !(volume > 0.0))
+        return -1;
+    const int n_ell = ell_max / 2 + 1;
+    const size_t nacc = (size_t)n_ell * n_k;
+    double p1 = 0.0, pr1 = 0.0;
+    for (int64_t i = 0; i < nd; ++i) p1 += wd ? wd[i] : 1.0;
+    for (int64_t i = 0; i < nr; ++i) pr1 += wr ? wr[i] : 1.0;
+    const double sR = p1 / pr1;
+    memset(raw_dd, 0, nacc * sizeof(double));
+    memset(raw_dr, 0, nacc * sizeof(double));
+    memset(raw_rr, 0, nacc * sizeof(double));
+    double *Add = calloc(nacc, sizeof(double)), *Adr = calloc(nacc, sizeof(double)), *Arr = calloc(nacc, sizeof(double));
+    uint64_t c_dd = survey_pair_sums(nd, pd, wd, md, nd, pd, wd, 1, 1.0, r0, n_k, k, n_ell, raw_dd, Add, nthreads);
+    uint64_t c_dr = survey_pair_sums(nd, pd, wd, md, nr, pr, wr, 0, sR, r0, n_k, k, n_ell, raw_dr, Adr, nthreads);
+    c_dr += survey_pair_sums(nr, pr, wr, mr, nd, pd, wd, 0, sR, r0, n_k, k, n_ell, raw_dr, Adr, nthreads);
+    uint64_t c_rr = survey_pair_sums(nr, pr, wr, mr, nr, pr, wr, 1, sR * sR, r0, n_k, k, n_ell, raw_rr, Arr, nthreads);
+    const double nw = p1 / volume;
+    for (size_t q = 0; q < nacc; ++q) {
+        pk[q] = (raw_dd[q] - raw_dr[q] + raw_rr[q]) / (nw * nw * volume);
+        if (l1) l1[q] = Add[q] + Adr[q] + Arr[q];
+    }
+    if (counts) {
+        counts[0] = c_dd;
+        counts[1] = c_dr;
+        counts[2] = c_rr;
+    }
+    free(Add);
+    free(Adr);
+    free(Arr);
     return 0;
 }
 
