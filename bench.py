@@ -1,6 +1,6 @@
 """Benchmark of the periodic-box pair sweep on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pk|bk|pk5|bk5|batch]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pk|bk|pk5|bk5|batch|survey]
 
 Default workload: the mixed-precision power spectrum of a 2,000,000-point
 Thomas cluster catalogue (10 children per parent, sigma = 2 Mpc/h, extra
@@ -8,6 +8,12 @@ N(0, 4 Mpc/h) line-of-sight displacement) in a 1000 Mpc/h periodic box,
 R0 = 25 Mpc/h, ell = 0, 2, 4, 40 log-spaced k-bins over 1-10 h/Mpc.  One step
 is one full hipster_pk_ell call on device-resident positions: cell list,
 pair enumeration, pair-weight sweep, merge and normalisation.
+
+Other workloads: the bispectrum (bk, bk5), the 2^24-point box (pk5), the
+64-box batch (batch) and the survey-geometry power spectrum (survey: 1e6 Thomas
+points and 3e6 randoms in a 1000 Mpc/h cube 1000-2000 Mpc/h from the observer,
+DD - 2DR + RR with the pair-midpoint line of sight; pairs are the ordered DD,
+DR + RD and RR pairs).
 
 Prints one JSON line.  `value` is pair-weights per second (ordered pairs
 inside R0 x n_k x n_ell, per second of the whole step).  `roofline` refers to
@@ -118,7 +124,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pk", choices=["pk", "pk-fp64", "bk", "bk-fp64", "pk5", "bk5", "batch"])
+    ap.add_argument("--workload", default="pk",
+                    choices=["pk", "pk-fp64", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-primaries", type=int, default=16384)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -157,6 +164,24 @@ def main():
         cfg = {"workload": wl.name, "n_points": wl.n, "box": wl.box, "r0": wl.r0, "n_k": n_k,
                "ells": list(range(0, wl.ell_max_p + 1, 2)), "k_range": [float(wl.k_edges_p[0]), float(wl.k_edges_p[-1])],
                "precision": prec, "weights": wl.weights is not None}
+    elif args.workload in ("survey", "survey-fp64"):
+        sv = synthetic.survey()
+        prec = "fp64" if args.workload == "survey-fp64" else "mixed"
+        pos = torch.from_numpy(sv.pos).cuda()
+        rnd = torch.from_numpy(sv.randoms).cuda()
+        n_k, n_ell = len(sv.k_edges) - 1, sv.ell_max // 2 + 1
+
+        def step():
+            out, info = hp.pk_survey(pos, None, rnd, volume=sv.volume, r0=sv.r0, k_edges=sv.k_edges,
+                                     ell_max=sv.ell_max, precision=prec, return_diag=True)
+            info = dict(info)
+            info["n_pairs_rand"] = info["n_pairs_rand"] + info["n_pairs_rr"]
+            return out, info
+        units_per_pair = n_k * n_ell
+        cfg = {"workload": sv.name, "n_points": sv.n, "n_randoms": int(sv.randoms.shape[0]), "volume": sv.volume,
+               "r0": sv.r0, "n_k": n_k, "ells": list(range(0, sv.ell_max + 1, 2)),
+               "k_range": [float(sv.k_edges[0]), float(sv.k_edges[-1])], "precision": prec,
+               "estimator": "DD - 2DR + RR, pair-midpoint line of sight"}
     elif args.workload in ("bk", "bk-fp64", "bk5"):
         wl = synthetic.workload(5 if args.workload == "bk5" else 3)
         prec = "fp64" if args.workload == "bk-fp64" else "mixed"
@@ -220,8 +245,8 @@ def main():
            "vs_baseline": None, "dtype": "f64+f32" if prec == "mixed" else "f64", "data": "synthetic",
            "config": cfg}
     avg_launch_ms = sweep_ms / max(launches, 1)
-    if args.workload in ("pk", "pk-fp64", "pk5"):
-        unordered = pairs / 2.0
+    if args.workload in ("pk", "pk-fp64", "pk5", "survey", "survey-fp64"):
+        unordered = (pairs + pairs_r) / 2.0
         flops = unordered * pk_flops_per_pair(n_k, n_ell) / (launches / args.steps)
         achieved = flops / (avg_launch_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "kernel": "k_pk_sweep", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,

@@ -109,6 +109,7 @@ typedef struct {
   double ms_sweep;   /* pair-weight kernels (the dominant cost) */
   double ms_total;   /* whole call */
   uint64_t sweep_launches; /* number of pair-weight kernel launches in ms_sweep */
+  uint64_t n_pairs_rr;    /* survey power spectrum: ordered random-random pairs inside R0 */
 } hipster_diag;
 
 typedef struct hipster_ctx hipster_ctx;
@@ -132,6 +133,42 @@ hipster_status hipster_pk_ell(hipster_ctx *ctx, const hipster_points *pts,
 hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data,
                               const hipster_points *randoms, const hipster_params *prm,
                               double *bk, hipster_diag *diag);
+
+/* Parameters of the survey-geometry power spectrum (hipster_pk_survey).
+ * volume: V of the normalisation 1/(n_w^2 V), n_w = sum(w_data) / V (the
+ * paper normalises by the ideal n^2 V, Sec. 2).  r0, n_k, ell_max, k_edges,
+ * precision: as in hipster_params (ell_max even, <= 6; n_k <= 128).
+ * primary_mask / random_mask: NULL, or one byte per data / random point; only
+ * ordered pairs (i, j) whose first point has a non-zero byte contribute (a
+ * hook for checking a subset of a large catalogue).  reserved: set to 0. */
+typedef struct {
+  double volume;
+  double r0;
+  int32_t n_k;
+  int32_t ell_max;
+  const double *k_edges;
+  int32_t precision;
+  int32_t reserved;
+  const uint8_t *primary_mask;
+  const uint8_t *random_mask;
+} hipster_survey_params;
+
+/* Power-spectrum multipoles of a survey (Sec. 2, the general estimator
+ * DD - 2DR + RR of eq. general-Pk-ell with the pair counts of eq.
+ * general-XY-counts, binned in k as in Sec. 3):
+ *   P^a_l = [DD - 2 DR + RR]^a_l / (n_w^2 V),
+ *   XY^a_l = (-i)^l (2l+1) sum_{i in X} sum_{j in Y, j != i if X = Y}
+ *            v_i v_j jbar^a_l(r_ij) L_l(xhat_ij . nhat_ij) W(r_ij / R0),
+ * the line of sight nhat_ij along the pair midpoint (x_i + x_j) / 2 with the
+ * observer at the origin, and no periodicity.  v = w for data and
+ * v = s_R w for randoms, s_R = sum(w_data) / sum(w_rand), so that the random
+ * catalogue stands for the data's mean density.  data, randoms: catalogues at
+ * any finite positions; randoms must be non-empty.  pk: host output,
+ * [ell_max/2 + 1][n_k].  diag: raw = [DD - 2DR + RR]^a_l before the
+ * normalisation; n_pairs / n_pairs_rand / n_pairs_rr = ordered DD, DR + RD and
+ * RR pairs inside R0 (mask-weighted when masks are given); wtilde unused. */
+hipster_status hipster_pk_survey(hipster_ctx *ctx, const hipster_points *data, const hipster_points *randoms,
+                                 const hipster_survey_params *prm, double *pk, hipster_diag *diag);
 
 /* One box of a batch: its catalogue(s), parameters and host outputs. */
 typedef struct {

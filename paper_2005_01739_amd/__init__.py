@@ -18,7 +18,7 @@ from typing import Any
 import numpy as np
 
 __all__ = ["Context", "wtilde", "pk_ell", "bk_ell", "batch", "HipsterError", "library_path", "load_library",
-           "EXPORTED_SYMBOLS", "MIXED", "FP64"]
+           "EXPORTED_SYMBOLS", "MIXED", "FP64", "pk_survey"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 MIXED, FP64 = 0, 1
@@ -26,7 +26,7 @@ _F32, _F64 = 0, 1
 
 EXPORTED_SYMBOLS = ("hipster_create", "hipster_destroy", "hipster_pk_ell", "hipster_bk_ell",
                     "hipster_batch", "hipster_last_error", "hipster_status_string",
-                    "hipster_set_memory_cap", "hipster_wtilde")
+                    "hipster_set_memory_cap", "hipster_wtilde", "hipster_pk_survey")
 
 
 class HipsterError(RuntimeError):
@@ -54,7 +54,13 @@ class _Diag(ct.Structure):
     _fields_ = [("n_pairs", ct.c_uint64), ("n_pairs_rand", ct.c_uint64), ("raw", _dp), ("gd", _dp),
                 ("cd", _dp), ("gr", _dp), ("cr", _dp), ("s0", _dp), ("wtilde", _dp),
                 ("ms_build", ct.c_double), ("ms_pairs", ct.c_double), ("ms_sweep", ct.c_double),
-                ("ms_total", ct.c_double), ("sweep_launches", ct.c_uint64)]
+                ("ms_total", ct.c_double), ("sweep_launches", ct.c_uint64), ("n_pairs_rr", ct.c_uint64)]
+
+
+class _SurveyParams(ct.Structure):
+    _fields_ = [("volume", ct.c_double), ("r0", ct.c_double), ("n_k", ct.c_int32), ("ell_max", ct.c_int32),
+                ("k_edges", _dp), ("precision", ct.c_int32), ("reserved", ct.c_int32),
+                ("primary_mask", ct.POINTER(ct.c_uint8)), ("random_mask", ct.POINTER(ct.c_uint8))]
 
 
 class _BoxJob(ct.Structure):
@@ -86,6 +92,9 @@ def load_library():
     L.hipster_destroy.argtypes = [ct.c_void_p]
     L.hipster_pk_ell.restype = ct.c_int
     L.hipster_pk_ell.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Params), _dp, ct.POINTER(_Diag)]
+    L.hipster_pk_survey.restype = ct.c_int
+    L.hipster_pk_survey.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Points), ct.POINTER(_SurveyParams),
+                                    _dp, ct.POINTER(_Diag)]
     L.hipster_bk_ell.restype = ct.c_int
     L.hipster_bk_ell.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Points), ct.POINTER(_Params),
                                  _dp, ct.POINTER(_Diag)]
@@ -252,6 +261,43 @@ def pk_ell(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, los
     return out, {"raw": raw, "wtilde": wt, "n_pairs": int(d.n_pairs), "ms_build": d.ms_build,
                  "ms_pairs": d.ms_pairs, "ms_sweep": d.ms_sweep, "ms_total": d.ms_total,
                  "sweep_launches": int(d.sweep_launches)}
+
+
+def pk_survey(pos, w=None, randoms=None, rw=None, *, volume: float, r0: float, k_edges, ell_max: int = 4,
+              precision: str = "mixed", primary_mask=None, random_mask=None, ctx: Context | None = None,
+              return_diag: bool = False) -> Any:
+    """Survey-geometry power-spectrum multipoles (DD - 2DR + RR, pair-midpoint
+    line of sight, observer at the origin, no periodicity): float64 array of
+    shape (ell_max/2 + 1, n_k).  `randoms` is required.  With return_diag, also
+    the raw pair sums, the DD, DR + RD and RR pair counts and timings."""
+    L = load_library()
+    if randoms is None:
+        raise ValueError("pk_survey needs a random catalogue")
+    keep: list = []
+    pts = _points(pos, w, keep)
+    rpts = _points(randoms, rw, keep)
+    k = np.ascontiguousarray(k_edges, dtype=np.float64)
+    if k.ndim != 1 or k.size < 2:
+        raise ValueError("k_edges must be 1-D with at least two entries")
+    prec = {"mixed": MIXED, "fp64": FP64, MIXED: MIXED, FP64: FP64}[precision]
+    m = None if primary_mask is None else np.ascontiguousarray(primary_mask, dtype=np.uint8)
+    rm = None if random_mask is None else np.ascontiguousarray(random_mask, dtype=np.uint8)
+    keep += [k, m, rm]
+    u8 = ct.POINTER(ct.c_uint8)
+    prm = _SurveyParams(float(volume), float(r0), int(k.size - 1), int(ell_max), k.ctypes.data_as(_dp), prec, 0,
+                        None if m is None else m.ctypes.data_as(u8), None if rm is None else rm.ctypes.data_as(u8))
+    n_ell, n_k = ell_max // 2 + 1, prm.n_k
+    out = np.zeros((n_ell, n_k))
+    raw = np.zeros((n_ell, n_k))
+    d = _Diag()
+    d.raw = _ptr(raw)
+    c = ctx or _context_for(pos)
+    c.check(L.hipster_pk_survey(c.handle, ct.byref(pts), ct.byref(rpts), ct.byref(prm), _ptr(out), ct.byref(d)))
+    if not return_diag:
+        return out
+    return out, {"raw": raw, "n_pairs": int(d.n_pairs), "n_pairs_rand": int(d.n_pairs_rand),
+                 "n_pairs_rr": int(d.n_pairs_rr), "ms_build": d.ms_build, "ms_pairs": d.ms_pairs,
+                 "ms_sweep": d.ms_sweep, "ms_total": d.ms_total, "sweep_launches": int(d.sweep_launches)}
 
 
 def bk_ell(pos, w=None, randoms=None, rw=None, *, box: float, r0: float, k_edges, ell_max: int = 4,

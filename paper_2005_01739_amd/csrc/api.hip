@@ -162,6 +162,107 @@ static int device_cus(Ctx &c) {
 }
 
 // ---------------------------------------------------------- power spectrum
+// One set of pairs through the power-spectrum sweep: the count pass (two
+// r-buckets per home cell), offsets, then chunks of home cells whose pairs fit
+// the pair buffer, each written and swept into `partial`.  count(cnt_a,
+// cnt_b, ord) and write(off_a, off_b, base_a, base_b, n_a, c0, c1, pairs) run
+// the set's enumeration kernels.
+struct SweepStats {
+  uint64_t ordered = 0;
+  double ms_pairs = 0.0, ms_sweep = 0.0;
+  uint64_t launches = 0;
+};
+
+template <typename CountF, typename WriteF>
+static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t ncells, CountF &&count, WriteF &&write, int n_ell,
+                                 bool fp64, double r0, const double *edges, int n_edges, double *partial,
+                                 int nwaves) {
+  SweepStats st;
+  int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
+  int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(ncells) * 8));
+  int64_t *off_a = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));
+  int64_t *off_b = static_cast<int64_t *>(ensure(c, c.pair_off_b, size_t(ncells + 1) * 8));
+  unsigned long long *ord = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 16));
+  hipEvent_t e0 = tm.mark();
+  HIPSTER_HIP(hipMemsetAsync(ord, 0, 8, c.stream));
+  count(cnt_a, cnt_b, ord);
+  scan_i64(c, cnt_a, off_a, ncells, c.pair_total);
+  scan_i64(c, cnt_b, off_b, ncells, c.pair_total);
+  std::vector<int64_t> ha(size_t(ncells) + 1), hb(size_t(ncells) + 1);
+  unsigned long long hord = 0;
+  HIPSTER_HIP(hipMemcpyAsync(ha.data(), off_a, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(hb.data(), off_b, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(&hord, ord, 8, hipMemcpyDeviceToHost, c.stream));
+  hipEvent_t e1 = tm.mark();
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  st.ordered = hord;
+  st.ms_pairs += Timer::ms(e0, e1);
+  auto pairs_in = [&](int64_t a, int64_t b) { return (ha[size_t(b)] - ha[size_t(a)]) + (hb[size_t(b)] - hb[size_t(a)]); };
+  const int64_t total = pairs_in(0, ncells);
+  if (total == 0) return st;
+  int64_t cap = std::min<int64_t>(pair_chunk_capacity(), total);
+  for (int64_t a = 0; a < ncells; ++a) cap = std::max(cap, pairs_in(a, a + 1));
+  PkPairs pp;
+  pp.r = static_cast<double *>(ensure(c, c.pr, size_t(cap) * 8));
+  pp.mu = ensure(c, c.pmu, size_t(cap) * 8);
+  pp.ww = ensure(c, c.pww, size_t(cap) * 8);
+  int64_t c0 = 0;
+  while (c0 < ncells) {
+    int64_t c1 = c0 + 1;
+    while (c1 < ncells && pairs_in(c0, c1 + 1) <= cap) ++c1;
+    const int64_t np = pairs_in(c0, c1), n_a = ha[size_t(c1)] - ha[size_t(c0)];
+    if (np > 0) {
+      hipEvent_t a = tm.mark();
+      write(off_a, off_b, ha[size_t(c0)], hb[size_t(c0)], n_a, c0, c1, pp);
+      hipEvent_t b = tm.mark();
+      pk_sweep(c, pp, np, n_ell, fp64, r0, edges, n_edges, partial, nwaves);
+      hipEvent_t d = tm.mark();
+      HIPSTER_HIP(hipEventSynchronize(d));
+      st.ms_pairs += Timer::ms(a, b);
+      st.ms_sweep += Timer::ms(b, d);
+      ++st.launches;
+    }
+    c0 = c1;
+  }
+  return st;
+}
+
+// Bin edges and their reciprocals on the device (0 for a zero edge, whose
+// u = 0 always takes the Taylor branch).
+static double *upload_edges(Ctx &c, int n_k, const double *k_edges) {
+  const int n_edges = n_k + 1;
+  std::vector<double> he(static_cast<size_t>(2 * n_edges));
+  for (int e = 0; e < n_edges; ++e) {
+    he[size_t(e)] = k_edges[e];
+    he[size_t(n_edges + e)] = k_edges[e] > 0.0 ? 1.0 / k_edges[e] : 0.0;
+  }
+  double *edges = static_cast<double *>(ensure(c, c.edges, size_t(2 * n_edges) * 8));
+  HIPSTER_HIP(hipMemcpyAsync(edges, he.data(), size_t(2 * n_edges) * 8, hipMemcpyHostToDevice, c.stream));
+  return edges;
+}
+
+// Merged edge sums -> S^a_l = 3 (2l+1)(-i)^l [k_{a+1}^3 E_{a+1} - k_a^3 E_a] / (k_{a+1}^3 - k_a^3).
+static std::vector<double> bin_sums(Ctx &c, double *partial, int nwaves, int n_ell, int n_k, const double *k_edges) {
+  const int n_edges = n_k + 1, cols = n_ell * n_edges;
+  double *merged = static_cast<double *>(ensure(c, c.merged, size_t(cols) * 8));
+  merge_partials(c, partial, nwaves, cols, merged);
+  std::vector<double> E(static_cast<size_t>(cols));
+  HIPSTER_HIP(hipMemcpyAsync(E.data(), merged, size_t(cols) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  std::vector<double> S(static_cast<size_t>(n_ell * n_k));
+  for (int li = 0; li < n_ell; ++li) {
+    const int ell = 2 * li;
+    const double phase = (li & 1) ? -1.0 : 1.0;  // (-i)^ell for even ell
+    for (int a = 0; a < n_k; ++a) {
+      const double ka = k_edges[a], kb = k_edges[a + 1];
+      const double a3 = ka * ka * ka, b3 = kb * kb * kb;
+      const double Ea = E[size_t(li * n_edges + a)], Eb = E[size_t(li * n_edges + a + 1)];
+      S[size_t(li * n_k + a)] = 3.0 * (2.0 * ell + 1.0) * phase * (b3 * Eb - a3 * Ea) / (b3 - a3);
+    }
+  }
+  return S;
+}
+
 static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, double *pk, hipster_diag *diag) {
   check_points(pts, "data", q ? q->box : 0.0);
   check_params(q, false);
@@ -180,107 +281,144 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
   const Sorted s = build_cells(c, c.cells_d, g, pos, w, mask, n, pts->dtype);
   hipEvent_t t1 = tm.mark();
 
-  // count pass (two r-buckets), offsets
-  const int64_t ncells = g.ncells();
   const bool fp64 = q->precision == HIPSTER_FP64;
   // pairs with r >= U_BIG / k_0 evaluate every edge on the large-argument
   // path (closed form with the Si auxiliaries); the near bucket holds the rest
   const double r_split = q->k_edges[0] > 0.0 ? HIPSTER_U_BIG / q->k_edges[0] : 0.0;
-  int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
-  int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(ncells) * 8));
-  int64_t *off_a = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));
-  int64_t *off_b = static_cast<int64_t *>(ensure(c, c.pair_off_b, size_t(ncells + 1) * 8));
-  unsigned long long *ord = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 16));
-  HIPSTER_HIP(hipMemsetAsync(ord, 0, 8, c.stream));
-  pk_pairs_count(c, s, g, q->r0, r_split, cnt_a, cnt_b, ord);
-  scan_i64(c, cnt_a, off_a, ncells, c.pair_total);
-  scan_i64(c, cnt_b, off_b, ncells, c.pair_total);
-  std::vector<int64_t> ha(size_t(ncells) + 1), hb(size_t(ncells) + 1);
-  unsigned long long hord = 0;
-  HIPSTER_HIP(hipMemcpyAsync(ha.data(), off_a, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
-  HIPSTER_HIP(hipMemcpyAsync(hb.data(), off_b, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
-  HIPSTER_HIP(hipMemcpyAsync(&hord, ord, 8, hipMemcpyDeviceToHost, c.stream));
-  HIPSTER_HIP(hipStreamSynchronize(c.stream));
-  auto pairs_in = [&](int64_t a, int64_t b) { return (ha[size_t(b)] - ha[size_t(a)]) + (hb[size_t(b)] - hb[size_t(a)]); };
-  const int64_t total = pairs_in(0, ncells);
-
   const int n_ell = q->ell_max / 2 + 1, n_edges = q->n_k + 1;
-  // edges followed by their reciprocals (0 for a zero edge, whose u = 0
-  // always takes the Taylor branch)
-  std::vector<double> he(static_cast<size_t>(2 * n_edges));
-  for (int e = 0; e < n_edges; ++e) {
-    he[size_t(e)] = q->k_edges[e];
-    he[size_t(n_edges + e)] = q->k_edges[e] > 0.0 ? 1.0 / q->k_edges[e] : 0.0;
-  }
-  double *edges = static_cast<double *>(ensure(c, c.edges, size_t(2 * n_edges) * 8));
-  HIPSTER_HIP(hipMemcpyAsync(edges, he.data(), size_t(2 * n_edges) * 8, hipMemcpyHostToDevice, c.stream));
+  double *edges = upload_edges(c, q->n_k, q->k_edges);
   const int nwaves = pk_sweep_waves(c);
   const int cols = n_ell * n_edges;
   double *partial = static_cast<double *>(ensure(c, c.partial, size_t(nwaves) * cols * 8));
   HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwaves) * cols * 8, c.stream));
-
-  // chunks of home cells whose pairs fit the pair buffer
-  int64_t cap = std::min<int64_t>(pair_chunk_capacity(), std::max<int64_t>(total, 1));
-  for (int64_t a = 0; a < ncells; ++a) cap = std::max(cap, pairs_in(a, a + 1));
-  PkPairs pp;
-  pp.r = static_cast<double *>(ensure(c, c.pr, size_t(cap) * 8));
-  pp.mu = ensure(c, c.pmu, size_t(cap) * 8);
-  pp.ww = ensure(c, c.pww, size_t(cap) * 8);
-  double ms_pairs = 0.0, ms_sweep = 0.0;
-  uint64_t launches = 0;
-  hipEvent_t t2 = tm.mark();
-  int64_t c0 = 0;
-  while (c0 < ncells) {
-    int64_t c1 = c0 + 1;
-    while (c1 < ncells && pairs_in(c0, c1 + 1) <= cap) ++c1;
-    const int64_t np = pairs_in(c0, c1), n_a = ha[size_t(c1)] - ha[size_t(c0)];
-    if (np > 0) {
-      hipEvent_t a = tm.mark();
-      pk_pairs_write(c, s, g, q->r0, r_split, q->los_axis, off_a, off_b, ha[size_t(c0)], hb[size_t(c0)], n_a, c0, c1,
-                     pp);
-      hipEvent_t b = tm.mark();
-      pk_sweep(c, pp, np, n_ell, fp64, q->r0, edges, n_edges, partial, nwaves);
-      hipEvent_t d = tm.mark();
-      HIPSTER_HIP(hipEventSynchronize(d));
-      ms_pairs += Timer::ms(a, b);
-      ms_sweep += Timer::ms(b, d);
-      ++launches;
-    }
-    c0 = c1;
-  }
-  double *merged = static_cast<double *>(ensure(c, c.merged, size_t(cols) * 8));
-  merge_partials(c, partial, nwaves, cols, merged);
-  std::vector<double> E(static_cast<size_t>(cols));
-  HIPSTER_HIP(hipMemcpyAsync(E.data(), merged, size_t(cols) * 8, hipMemcpyDeviceToHost, c.stream));
+  const SweepStats st = sweep_pair_set(
+      c, tm, g.ncells(),
+      [&](int64_t *ca, int64_t *cb, unsigned long long *ord) { pk_pairs_count(c, s, g, q->r0, r_split, ca, cb, ord); },
+      [&](const int64_t *oa, const int64_t *ob, int64_t ba, int64_t bb, int64_t na, int64_t c0, int64_t c1,
+          PkPairs pp) { pk_pairs_write(c, s, g, q->r0, r_split, q->los_axis, oa, ob, ba, bb, na, c0, c1, pp); },
+      n_ell, fp64, q->r0, edges, n_edges, partial, nwaves);
+  const std::vector<double> S = bin_sums(c, partial, nwaves, n_ell, q->n_k, q->k_edges);
   hipEvent_t t3 = tm.mark();
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
 
-  // finalize (host, FP64): S^a_l, W~^a, P^a_l
+  // finalize (host, FP64): P^a_l = S^a_l / (n_w^2 V) - delta_l0 W~^a
   const double p1 = weight_sum(pts);
   const double V = q->box * q->box * q->box, nw = p1 / V, norm = 1.0 / (nw * nw * V);
   std::vector<double> wt(static_cast<size_t>(q->n_k));
   wtilde_bins(c, q->r0, q->n_k, q->k_edges, wt.data());
-  for (int li = 0; li < n_ell; ++li) {
-    const int ell = 2 * li;
-    const double phase = (li & 1) ? -1.0 : 1.0;  // (-i)^ell for even ell
+  for (int li = 0; li < n_ell; ++li)
     for (int a = 0; a < q->n_k; ++a) {
-      const double ka = q->k_edges[a], kb = q->k_edges[a + 1];
-      const double a3 = ka * ka * ka, b3 = kb * kb * kb;
-      const double Ea = E[size_t(li * n_edges + a)], Eb = E[size_t(li * n_edges + a + 1)];
-      const double S = 3.0 * (2.0 * ell + 1.0) * phase * (b3 * Eb - a3 * Ea) / (b3 - a3);
-      if (diag && diag->raw) diag->raw[li * q->n_k + a] = S;
-      pk[li * q->n_k + a] = S * norm - (ell == 0 ? wt[size_t(a)] : 0.0);
+      const double Sa = S[size_t(li * q->n_k + a)];
+      if (diag && diag->raw) diag->raw[li * q->n_k + a] = Sa;
+      pk[li * q->n_k + a] = Sa * norm - (li == 0 ? wt[size_t(a)] : 0.0);
     }
-  }
   if (diag) {
-    diag->n_pairs = hord;
+    diag->n_pairs = st.ordered;
     diag->n_pairs_rand = 0;
+    diag->n_pairs_rr = 0;
     if (diag->wtilde) memcpy(diag->wtilde, wt.data(), size_t(q->n_k) * 8);
     diag->ms_build = Timer::ms(t0, t1);
-    diag->ms_pairs = Timer::ms(t1, t2) + ms_pairs;
-    diag->ms_sweep = ms_sweep;
+    diag->ms_pairs = st.ms_pairs;
+    diag->ms_sweep = st.ms_sweep;
     diag->ms_total = Timer::ms(t0, t3);
-    diag->sweep_launches = launches;
+    diag->sweep_launches = st.launches;
+  }
+}
+
+// ------------------------------------------------- survey power spectrum
+// Sec. 2 general estimator with the binned kernels of Sec. 3: the DD, DR
+// and RR pair sets, each with its signed weight scale, go through the same
+// sweep into one set of edge sums, so the result is DD - 2DR + RR.
+static void run_pk_survey(Ctx &c, const hipster_points *dp, const hipster_points *rp,
+                          const hipster_survey_params *q, double *pk, hipster_diag *diag) {
+  check_points(dp, "data", 0.0);
+  check_points(rp, "randoms", 0.0);
+  if (!q) throw Error{HIPSTER_EINVAL, "NULL parameters"};
+  if (!pk) throw Error{HIPSTER_EINVAL, "NULL output"};
+  if (dp->n < 1 || rp->n < 1) throw Error{HIPSTER_EINVAL, "survey: need at least one data and one random point"};
+  if (!(q->volume > 0.0) || !isfinite(q->volume)) throw Error{HIPSTER_EDOMAIN, "survey: volume must be finite and positive"};
+  if (!(q->r0 > 0.0) || !isfinite(q->r0)) throw Error{HIPSTER_EDOMAIN, "R0 must be finite and positive"};
+  {
+    // the binning and precision checks of the periodic estimator
+    hipster_params pp{};
+    pp.box = 2.0 * q->r0;
+    pp.r0 = q->r0;
+    pp.n_k = q->n_k;
+    pp.ell_max = q->ell_max;
+    pp.k_edges = q->k_edges;
+    pp.los_axis = 2;
+    pp.precision = q->precision;
+    check_params(&pp, false);
+  }
+  HIPSTER_HIP(hipSetDevice(c.device));
+  Timer tm(c);
+  hipEvent_t t0 = tm.mark();
+
+  const int64_t nd = dp->n, nr = rp->n;
+  const size_t ed = dp->dtype == HIPSTER_F32 ? 4 : 8, er = rp->dtype == HIPSTER_F32 ? 4 : 8;
+  const void *dpos = device_view(c, c.pos_in, dp->pos, nd * 3 * int64_t(ed), dp->on_device);
+  const void *dw = device_view(c, c.w_in, dp->w, nd * int64_t(ed), dp->on_device);
+  const void *rpos = device_view(c, c.rpos_in, rp->pos, nr * 3 * int64_t(er), rp->on_device);
+  const void *rw = device_view(c, c.rw_in, rp->w, nr * int64_t(er), rp->on_device);
+  const uint8_t *dmask = device_mask(c, c.mask_in, q->primary_mask, nd);
+  const uint8_t *rmask = device_mask(c, c.rmask_in, q->random_mask, nr);
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bounding_box(c, dpos, nd, dp->dtype, lo, hi);
+  bounding_box(c, rpos, nr, rp->dtype, lo, hi);
+  const Grid g = make_survey_grid(lo, hi, q->r0);
+  const Sorted sd = build_cells(c, c.cells_d, g, dpos, dw, dmask, nd, dp->dtype);
+  const Sorted sr = build_cells(c, c.cells_r, g, rpos, rw, rmask, nr, rp->dtype);
+  hipEvent_t t1 = tm.mark();
+
+  const double p1 = weight_sum(dp), pr1 = weight_sum(rp), sR = p1 / pr1;
+  const bool fp64 = q->precision == HIPSTER_FP64;
+  const double r_split = q->k_edges[0] > 0.0 ? HIPSTER_U_BIG / q->k_edges[0] : 0.0;
+  const int n_ell = q->ell_max / 2 + 1, n_edges = q->n_k + 1;
+  double *edges = upload_edges(c, q->n_k, q->k_edges);
+  const int nwaves = pk_sweep_waves(c);
+  const int cols = n_ell * n_edges;
+  double *partial = static_cast<double *>(ensure(c, c.partial, size_t(nwaves) * cols * 8));
+  HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwaves) * cols * 8, c.stream));
+  // DD (+1), DR + RD (-s_R: each (d, r) pair once, weighted by m_d + m_r),
+  // RR (+s_R^2)
+  struct Set {
+    const Sorted *a, *b;
+    bool cross;
+    double scale;
+  } sets[3] = {{&sd, &sd, false, 1.0}, {&sd, &sr, true, -sR}, {&sr, &sr, false, sR * sR}};
+  SweepStats st[3];
+  for (int k = 0; k < 3; ++k) {
+    const Set &z = sets[k];
+    st[k] = sweep_pair_set(
+        c, tm, g.ncells(),
+        [&](int64_t *ca, int64_t *cb, unsigned long long *ord) {
+          survey_pairs_count(c, *z.a, *z.b, z.cross, g, q->r0, r_split, ca, cb, ord);
+        },
+        [&](const int64_t *oa, const int64_t *ob, int64_t ba, int64_t bb, int64_t na, int64_t c0, int64_t c1,
+            PkPairs pp) {
+          survey_pairs_write(c, *z.a, *z.b, z.cross, g, q->r0, r_split, z.scale, oa, ob, ba, bb, na, c0, c1, pp);
+        },
+        n_ell, fp64, q->r0, edges, n_edges, partial, nwaves);
+  }
+  const std::vector<double> S = bin_sums(c, partial, nwaves, n_ell, q->n_k, q->k_edges);
+  hipEvent_t t3 = tm.mark();
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+
+  // P^a_l = S^a_l / (n_w^2 V), n_w = sum(w_data) / V
+  const double nw = p1 / q->volume, norm = 1.0 / (nw * nw * q->volume);
+  for (int i = 0; i < n_ell * q->n_k; ++i) {
+    if (diag && diag->raw) diag->raw[i] = S[size_t(i)];
+    pk[i] = S[size_t(i)] * norm;
+  }
+  if (diag) {
+    diag->n_pairs = st[0].ordered;
+    diag->n_pairs_rand = st[1].ordered;
+    diag->n_pairs_rr = st[2].ordered;
+    diag->ms_build = Timer::ms(t0, t1);
+    diag->ms_pairs = st[0].ms_pairs + st[1].ms_pairs + st[2].ms_pairs;
+    diag->ms_sweep = st[0].ms_sweep + st[1].ms_sweep + st[2].ms_sweep;
+    diag->ms_total = Timer::ms(t0, t3);
+    diag->sweep_launches = st[0].launches + st[1].launches + st[2].launches;
   }
 }
 
@@ -388,6 +526,7 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
       for (int b = 0; b < NK; ++b) diag->s0[b] = Md[2 * nT + b];
     if (diag->wtilde) memcpy(diag->wtilde, wt.data(), size_t(NK) * 8);
     diag->n_pairs = hcnt[0];
+    diag->n_pairs_rr = 0;
     diag->n_pairs_rand = hcnt[1];
     diag->ms_build = Timer::ms(t0, t1);
     diag->ms_pairs = ms_pairs;
@@ -619,6 +758,7 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
   hipEvent_t t9 = tm.mark();
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
   if (diag) {
+    diag->n_pairs_rr = 0;
     diag->ms_build = ms_build;
     diag->ms_pairs = ms_pairs;
     diag->ms_sweep = ms_sweep;
@@ -676,7 +816,7 @@ void hipster_destroy(hipster_ctx *ctx) {
   free_cells(c.cells_r);
   DevBuf *all[] = {&c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in, &c.rmask_in, &c.pair_cnt, &c.pair_cnt_b,
                    &c.pair_ord, &c.pair_off, &c.pair_off_b, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
-                   &c.partial, &c.merged, &c.ordered_count, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out};
+                   &c.partial, &c.merged, &c.ordered_count, &c.bbox, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out};
   for (DevBuf *b : all) free_buf(*b);
   delete ctx;
 }
@@ -684,6 +824,11 @@ void hipster_destroy(hipster_ctx *ctx) {
 hipster_status hipster_pk_ell(hipster_ctx *ctx, const hipster_points *pts, const hipster_params *prm, double *pk,
                               hipster_diag *diag) {
   return guarded(ctx, [&] { run_pk(ctx->c, pts, prm, pk, diag); });
+}
+
+hipster_status hipster_pk_survey(hipster_ctx *ctx, const hipster_points *data, const hipster_points *randoms,
+                                 const hipster_survey_params *prm, double *pk, hipster_diag *diag) {
+  return guarded(ctx, [&] { run_pk_survey(ctx->c, data, randoms, prm, pk, diag); });
 }
 
 hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data, const hipster_points *randoms,

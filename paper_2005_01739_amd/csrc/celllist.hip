@@ -1,30 +1,107 @@
-// Device-built periodic cell list: every point is assigned to a cubic cell of
-// side L / n_c > R0, points are counting-sorted by cell (ties in original index
+// Device-built cell list: every point is assigned to a cubic cell of side
+// L / n_c > R0 (of the periodic box, or of a survey's bounding cube), points are counting-sorted by cell (ties in original index
 // order, so the layout -- and every sum over it -- is deterministic), and the
 // coordinates are gathered into coalesced structure-of-arrays in double
 // precision.  Memory-bound; a few passes over ~40 bytes per point.
 #include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "common.h"
 
 namespace hipster {
 
-Grid make_grid(double L, double r0) {
+static int cells_per_axis(double L, double r0) {
   int nc = int(floor(L / r0));
   // Keep the cell side clear of R0 by a margin far above the rounding of the
   // cell assignment, so a pair inside R0 always lies in neighbouring cells.
   while (nc > 1 && L / nc < r0 * (1.0 + 1e-6)) --nc;
   if (nc < 1) nc = 1;
   if (nc > kMaxCellsPerAxis) nc = kMaxCellsPerAxis;
+  return nc;
+}
+
+Grid make_grid(double L, double r0) {
+  const int nc = cells_per_axis(L, r0);
   return Grid{nc, L, double(nc) / L};
 }
 
+Grid make_survey_grid(const double lo[3], const double hi[3], double r0) {
+  double ext = 0.0;
+  for (int d = 0; d < 3; ++d) ext = fmax(ext, hi[d] - lo[d]);
+  // the cube [lo, lo + L) must hold the largest coordinate strictly inside
+  const double L = ext * (1.0 + 1e-9) + 1e-9 * fmax(1.0, r0);
+  const int nc = cells_per_axis(L, r0);
+  Grid g{nc, L, double(nc) / L};
+  g.ox = lo[0];
+  g.oy = lo[1];
+  g.oz = lo[2];
+  g.periodic = false;
+  return g;
+}
+
 template <typename T>
-__global__ void k_assign(const T *__restrict__ pos, int64_t n, double L, int nc, double scale,
-                         int *__restrict__ cell, int *__restrict__ count, int *__restrict__ bad) {
+__global__ __launch_bounds__(256) void k_bbox(const T *__restrict__ pos, int64_t n, double *__restrict__ out,
+                                              int *__restrict__ bad) {
+  __shared__ double sh[6][256];
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  bool finite = true;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    for (int d = 0; d < 3; ++d) {
+      const double x = double(pos[3 * i + d]);
+      finite = finite && isfinite(x);
+      v[d] = fmin(v[d], x);
+      v[3 + d] = fmax(v[3 + d], x);
+    }
+  if (!finite) atomicOr(bad, 1);
+  for (int d = 0; d < 6; ++d) sh[d][threadIdx.x] = v[d];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o)
+      for (int d = 0; d < 6; ++d)
+        sh[d][threadIdx.x] = d < 3 ? fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + o])
+                                   : fmax(sh[d][threadIdx.x], sh[d][threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int d = 0; d < 6; ++d) out[blockIdx.x * 6 + d] = sh[d][0];
+}
+
+void bounding_box(Ctx &c, const void *pos, int64_t n, int dtype, double lo[3], double hi[3]) {
+  if (n <= 0) return;
+  const int nb = int(std::min<int64_t>(1024, (n + 255) / 256));
+  double *out = static_cast<double *>(ensure(c, c.bbox, size_t(nb) * 6 * 8 + 64));
+  int *bad = reinterpret_cast<int *>(out + size_t(nb) * 6);
+  HIPSTER_HIP(hipMemsetAsync(bad, 0, sizeof(int), c.stream));
+  if (dtype == HIPSTER_F32)
+    k_bbox<float><<<dim3(unsigned(nb)), 256, 0, c.stream>>>(static_cast<const float *>(pos), n, out, bad);
+  else
+    k_bbox<double><<<dim3(unsigned(nb)), 256, 0, c.stream>>>(static_cast<const double *>(pos), n, out, bad);
+  HIPSTER_HIP(hipGetLastError());
+  std::vector<double> h(size_t(nb) * 6 + 8);
+  HIPSTER_HIP(hipMemcpyAsync(h.data(), out, (size_t(nb) * 6 + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  int hbad = 0;
+  memcpy(&hbad, h.data() + size_t(nb) * 6, sizeof(int));
+  if (hbad) throw Error{HIPSTER_EOUTOFBOX, "a coordinate is not finite"};
+  for (int b = 0; b < nb; ++b)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], h[size_t(b) * 6 + d]);
+      hi[d] = fmax(hi[d], h[size_t(b) * 6 + 3 + d]);
+    }
+}
+
+// Cell of each point of [o, o + L)^3; a point outside (or not finite) sets
+// *bad.  The sorted coordinates keep the input values, so pair separations
+// are differences of the inputs, as in the definition.
+template <typename T>
+__global__ void k_assign(const T *__restrict__ pos, int64_t n, double L, int nc, double scale, double ox, double oy,
+                         double oz, int *__restrict__ cell, int *__restrict__ count, int *__restrict__ bad) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double x = double(pos[3 * i]), y = double(pos[3 * i + 1]), z = double(pos[3 * i + 2]);
+  double x = double(pos[3 * i]) - ox, y = double(pos[3 * i + 1]) - oy, z = double(pos[3 * i + 2]) - oz;
   bool ok = (x >= 0.0) && (x < L) && (y >= 0.0) && (y < L) && (z >= 0.0) && (z < L);
   if (!ok) {
     atomicOr(bad, 1);
@@ -189,11 +266,12 @@ static Sorted build_cells_t(Ctx &c, CellScratch &s, const Grid &g, const T *pos,
   HIPSTER_HIP(hipMemsetAsync(cursor, 0, size_t(ncells) * sizeof(int), c.stream));
   HIPSTER_HIP(hipMemsetAsync(bad, 0, sizeof(int), c.stream));
   const unsigned nbp = unsigned((n + 255) / 256), nbc = unsigned((ncells + 255) / 256);
-  k_assign<T><<<nbp, 256, 0, c.stream>>>(pos, n, g.L, g.nc, g.scale, cell, count, bad);
+  k_assign<T><<<nbp, 256, 0, c.stream>>>(pos, n, g.L, g.nc, g.scale, g.ox, g.oy, g.oz, cell, count, bad);
   int hbad = 0;
   HIPSTER_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c.stream));
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
-  if (hbad) throw Error{HIPSTER_EOUTOFBOX, "a coordinate is not finite or outside [0, L)"};
+  if (hbad) throw Error{HIPSTER_EOUTOFBOX, g.periodic ? "a coordinate is not finite or outside [0, L)"
+                                                     : "a coordinate is not finite or outside the survey grid"};
   k_widen<<<nbc, 256, 0, c.stream>>>(count, wide, ncells);
   scan_i64(c, wide, start, ncells, s.scan_tmp);
   k_scatter<<<nbp, 256, 0, c.stream>>>(cell, n, start, cursor, idx);

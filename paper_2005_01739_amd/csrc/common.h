@@ -39,15 +39,24 @@ struct DevBuf {
 struct Ctx;
 void *ensure(Ctx &c, DevBuf &b, size_t bytes);
 
-// Periodic cell grid: n_c cells per axis of side L / n_c > R0.
+// Cell grid: n_c cells per axis of side L / n_c > R0 covering the cube
+// [o, o + L)^3.  A periodic box has o = 0; a survey grid is the bounding cube
+// of its catalogues, with no periodicity.
 struct Grid {
   int nc;
   double L;
   double scale;  // n_c / L
+  double ox = 0.0, oy = 0.0, oz = 0.0;
+  bool periodic = true;
   int64_t ncells() const { return int64_t(nc) * nc * nc; }
 };
 
 Grid make_grid(double L, double r0);
+Grid make_survey_grid(const double lo[3], const double hi[3], double r0);
+
+// Bounding box of a catalogue (device or host-copied positions), merged into
+// lo/hi (host); throws HIPSTER_EOUTOFBOX on a non-finite coordinate.
+void bounding_box(Ctx &c, const void *pos, int64_t n, int dtype, double lo[3], double hi[3]);
 
 // A catalogue sorted by cell, structure-of-arrays, coordinates in double
 // (exact for single-precision inputs).
@@ -98,7 +107,7 @@ struct Ctx {
   DevBuf pos_in, w_in, mask_in, rpos_in, rw_in, rmask_in;
   DevBuf pair_cnt, pair_cnt_b, pair_ord, pair_off, pair_off_b, pair_total;
   DevBuf pr, pmu, pww, pux, puy, puz;
-  DevBuf edges, partial, merged, ordered_count;
+  DevBuf edges, partial, merged, ordered_count, bbox;
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
   // W~^a depends only on (R0, k_a, k_{a+1}); repeated calls reuse it.
@@ -126,6 +135,18 @@ void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_
 void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_split, int los,
                     const int64_t *off_a, const int64_t *off_b, int64_t base_a, int64_t base_b, int64_t n_a,
                     int64_t c0, int64_t c1, PkPairs out);
+
+// Survey-geometry enumeration (no periodicity, line of sight along each
+// pair's midpoint).  Home cells come from catalogue `a`.  cross = false: `b`
+// is `a` and every unordered pair is found once (half stencil); cross = true:
+// every pair (i in a, j in b) is found once (27 cells).  A pair's weight is
+// scale * w_i w_j (m_i + m_j), m the mask bits (1 without a mask); the count
+// pass adds sum (m_i + m_j) to *ordered.
+void survey_pairs_count(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, double r0,
+                        double r_split, int64_t *cnt_a, int64_t *cnt_b, unsigned long long *ordered);
+void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, double r0,
+                        double r_split, double scale, const int64_t *off_a, const int64_t *off_b, int64_t base_a,
+                        int64_t base_b, int64_t n_a, int64_t c0, int64_t c1, PkPairs out);
 
 // Pair-weight sweep: adds into partial[nwaves][n_ell][n_edges] (zeroed by the
 // caller before the first chunk).  Returns the number of waves (partial rows).

@@ -1,5 +1,6 @@
 // Pair enumeration for the power spectrum: every unordered pair {i, j} inside
-// R0 of a periodic box is found once by a half stencil of 14 cells (the home
+// R0 of a periodic box (or of a survey catalogue, or every pair between a
+// survey's data and randoms, without periodicity) is found once by a half stencil of 14 cells (the home
 // cell with i < j, and 13 forward neighbours with all i, j), each neighbour
 // carrying its periodic image shift.  Pairs are compacted wave-by-wave
 // (ballot + popcount) into a coalesced stream (r, mu, w_i w_j m_ij) in double
@@ -72,24 +73,32 @@ __device__ inline uint32_t small_div(uint32_t q, uint32_t d, float inv_d) {
   return t;
 }
 
-template <bool WRITE, typename T>
-__global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, double r02, double rs2, int los,
-                                                 int64_t *__restrict__ cnt_a, int64_t *__restrict__ cnt_b,
+// Enumeration modes: the periodic box (half stencil, image shifts, a fixed
+// line-of-sight axis); a survey catalogue with itself (half stencil, no
+// periodicity, midpoint line of sight); a survey catalogue against another
+// (all 27 neighbours, every pair once).
+enum PairMode { kPeriodic = 0, kSurveySelf = 1, kSurveyCross = 2 };
+
+template <bool WRITE, int MODE>
+__global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, double L, double r02, double rs2,
+                                                 int los, double scale, int64_t *__restrict__ cnt_a,
+                                                 int64_t *__restrict__ cnt_b,
                                                  unsigned long long *__restrict__ ordered,
                                                  const int64_t *__restrict__ off_a, const int64_t *__restrict__ off_b,
-                                                 int64_t base_a, int64_t base_b, int64_t n_a,
-                                                 int64_t c0, double *__restrict__ out_r,
-                                                 T *__restrict__ out_mu, T *__restrict__ out_ww) {
+                                                 int64_t base_a, int64_t base_b, int64_t n_a, int64_t c0,
+                                                 double *__restrict__ out_r, double *__restrict__ out_mu,
+                                                 double *__restrict__ out_ww) {
   // home-cell and neighbour-cell tiles of kPairTile points in LDS; the
   // candidates of a tile pair are packed 64 to a step
   __shared__ double hx[kPairTile], hy[kPairTile], hz[kPairTile], hw[kPairTile];
   __shared__ double jx[kPairTile], jy[kPairTile], jz[kPairTile], jw[kPairTile];
   __shared__ int hm[kPairTile], jm[kPairTile];
+  constexpr int kStencil = MODE == kSurveyCross ? 27 : 14;
   const int64_t cell = c0 + blockIdx.x;
   const int lane = threadIdx.x;
   const int cz = int(cell % nc), cy = int((cell / nc) % nc), cx = int(cell / (int64_t(nc) * nc));
-  const int64_t hs = s.cell_start[cell];
-  const int ni = int(s.cell_start[cell + 1] - hs);
+  const int64_t hs = a.cell_start[cell];
+  const int ni = int(a.cell_start[cell + 1] - hs);
   int64_t written_a = 0, written_b = 0;
   unsigned long long ord = 0;
   const int64_t wbase_a = WRITE ? off_a[cell] - base_a : 0;
@@ -99,20 +108,35 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
     __syncthreads();
     if (lane < ti) {
       const int64_t i = hs + i0 + lane;
-      hx[lane] = s.x[i];
-      hy[lane] = s.y[i];
-      hz[lane] = s.z[i];
-      hw[lane] = s.w[i];
-      hm[lane] = s.m ? int(s.m[i]) : 1;
+      hx[lane] = a.x[i];
+      hy[lane] = a.y[i];
+      hz[lane] = a.z[i];
+      hw[lane] = a.w[i];
+      hm[lane] = a.m ? int(a.m[i]) : 1;
     }
-    for (int st = 0; st < 14; ++st) {
-      int ox, oy, oz, sx, sy, sz;
-      half_stencil(st, ox, oy, oz);
-      const int nx = wrap_axis(cx + ox, nc, sx), ny = wrap_axis(cy + oy, nc, sy), nz = wrap_axis(cz + oz, nc, sz);
+    for (int st = 0; st < kStencil; ++st) {
+      int ox, oy, oz, sx = 0, sy = 0, sz = 0, nx, ny, nz;
+      if (MODE == kSurveyCross) {
+        ox = st / 9 - 1;
+        oy = (st / 3) % 3 - 1;
+        oz = st % 3 - 1;
+      } else {
+        half_stencil(st, ox, oy, oz);
+      }
+      if (MODE == kPeriodic) {
+        nx = wrap_axis(cx + ox, nc, sx);
+        ny = wrap_axis(cy + oy, nc, sy);
+        nz = wrap_axis(cz + oz, nc, sz);
+      } else {
+        nx = cx + ox;
+        ny = cy + oy;
+        nz = cz + oz;
+        if (nx < 0 || nx >= nc || ny < 0 || ny >= nc || nz < 0 || nz >= nc) continue;
+      }
       const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
-      const int64_t js = s.cell_start[nb];
-      const int nj = int(s.cell_start[nb + 1] - js);
-      const bool self = (st == 0);
+      const int64_t js = b.cell_start[nb];
+      const int nj = int(b.cell_start[nb + 1] - js);
+      const bool self = MODE != kSurveyCross && st == 0;
       // in the home cell only pairs j > i: tiles wholly below the home tile
       // hold none
       for (int j0 = self ? i0 : 0; j0 < nj; j0 += kPairTile) {
@@ -120,11 +144,11 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
         __syncthreads();
         if (lane < tj) {
           const int64_t j = js + j0 + lane;
-          jx[lane] = s.x[j];
-          jy[lane] = s.y[j];
-          jz[lane] = s.z[j];
-          jw[lane] = s.w[j];
-          jm[lane] = s.m ? int(s.m[j]) : 1;
+          jx[lane] = b.x[j];
+          jy[lane] = b.y[j];
+          jz[lane] = b.z[j];
+          jw[lane] = b.w[j];
+          jm[lane] = b.m ? int(b.m[j]) : 1;
         }
         __syncthreads();
         const uint32_t total = uint32_t(ti) * uint32_t(tj);
@@ -148,9 +172,16 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
                   near = r2 < rs2;
                   if (WRITE) {
                     r = sqrt(r2);
-                    const double dl = los == 0 ? dx : (los == 1 ? dy : dz);
-                    mu = r > 0.0 ? dl / r : 0.0;
-                    ww = hw[ii] * jw[jj] * double(mult);
+                    if (MODE == kPeriodic) {
+                      const double dl = los == 0 ? dx : (los == 1 ? dy : dz);
+                      mu = r > 0.0 ? dl / r : 0.0;
+                    } else {
+                      // line of sight along the pair midpoint (x_i + x_j) / 2
+                      const double mx = hx[ii] + jx[jj], my = hy[ii] + jy[jj], mz = hz[ii] + jz[jj];
+                      const double mn = sqrt((mx * mx + my * my) + mz * mz);
+                      mu = (r > 0.0 && mn > 0.0) ? ((dx * mx + dy * my) + dz * mz) / (r * mn) : 0.0;
+                    }
+                    ww = scale * (hw[ii] * jw[jj]) * double(mult);
                   }
                 }
               }
@@ -162,8 +193,8 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
             const int64_t k = near ? wbase_a + written_a + __popcll(bal_a & below)
                                    : wbase_b + written_b + __popcll(bal_b & below);
             out_r[k] = r;
-            out_mu[k] = T(mu);
-            out_ww[k] = T(ww);
+            out_mu[k] = mu;
+            out_ww[k] = ww;
           }
           written_a += __popcll(bal_a);
           written_b += __popcll(bal_b);
@@ -184,9 +215,9 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted s, int nc, double L, dou
 void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_split, int64_t *cnt_a,
                     int64_t *cnt_b, unsigned long long *ordered) {
   const int64_t ncells = g.ncells();
-  k_pk_pairs<false, double><<<dim3(unsigned(ncells)), dim3(64), 0, c.stream>>>(
-      s, g.nc, g.L, r0 * r0, r_split * r_split, 2, cnt_a, cnt_b, ordered, nullptr, nullptr, 0, 0, 0, 0, nullptr,
-      nullptr, nullptr);
+  k_pk_pairs<false, kPeriodic><<<dim3(unsigned(ncells)), dim3(64), 0, c.stream>>>(
+      s, s, g.nc, g.L, r0 * r0, r_split * r_split, 2, 1.0, cnt_a, cnt_b, ordered, nullptr, nullptr, 0, 0, 0, 0,
+      nullptr, nullptr, nullptr);
   HIPSTER_HIP(hipGetLastError());
 }
 
@@ -195,9 +226,40 @@ void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_
                     int64_t c0, int64_t c1, PkPairs out) {
   if (c1 <= c0) return;
   const dim3 grid(unsigned(c1 - c0));
-  k_pk_pairs<true, double><<<grid, dim3(64), 0, c.stream>>>(
-      s, g.nc, g.L, r0 * r0, r_split * r_split, los, nullptr, nullptr, nullptr, off_a, off_b, base_a, base_b, n_a,
-      c0, out.r, static_cast<double *>(out.mu), static_cast<double *>(out.ww));
+  k_pk_pairs<true, kPeriodic><<<grid, dim3(64), 0, c.stream>>>(
+      s, s, g.nc, g.L, r0 * r0, r_split * r_split, los, 1.0, nullptr, nullptr, nullptr, off_a, off_b, base_a, base_b,
+      n_a, c0, out.r, static_cast<double *>(out.mu), static_cast<double *>(out.ww));
+  HIPSTER_HIP(hipGetLastError());
+}
+
+void survey_pairs_count(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, double r0,
+                        double r_split, int64_t *cnt_a, int64_t *cnt_b, unsigned long long *ordered) {
+  const dim3 grid(unsigned(g.ncells()));
+  if (cross)
+    k_pk_pairs<false, kSurveyCross><<<grid, dim3(64), 0, c.stream>>>(
+        a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, cnt_a, cnt_b, ordered, nullptr, nullptr, 0, 0, 0, 0,
+        nullptr, nullptr, nullptr);
+  else
+    k_pk_pairs<false, kSurveySelf><<<grid, dim3(64), 0, c.stream>>>(
+        a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, cnt_a, cnt_b, ordered, nullptr, nullptr, 0, 0, 0, 0,
+        nullptr, nullptr, nullptr);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, double r0,
+                        double r_split, double scale, const int64_t *off_a, const int64_t *off_b, int64_t base_a,
+                        int64_t base_b, int64_t n_a, int64_t c0, int64_t c1, PkPairs out) {
+  if (c1 <= c0) return;
+  const dim3 grid(unsigned(c1 - c0));
+  double *mu = static_cast<double *>(out.mu), *ww = static_cast<double *>(out.ww);
+  if (cross)
+    k_pk_pairs<true, kSurveyCross><<<grid, dim3(64), 0, c.stream>>>(
+        a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, nullptr, nullptr, nullptr, off_a, off_b, base_a,
+        base_b, n_a, c0, out.r, mu, ww);
+  else
+    k_pk_pairs<true, kSurveySelf><<<grid, dim3(64), 0, c.stream>>>(
+        a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, nullptr, nullptr, nullptr, off_a, off_b, base_a,
+        base_b, n_a, c0, out.r, mu, ww);
   HIPSTER_HIP(hipGetLastError());
 }
 

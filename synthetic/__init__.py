@@ -17,6 +17,10 @@ to the stated dtype; a coordinate that rounds up to L after the cast is set to
 * ``randoms(N_R, L)``: uniform random catalogue for the bispectrum's
   random-primary term, drawn from ``default_rng(seed + 1)``.
 * weights, when asked for, are U[0.5, 1.5] drawn after the positions.
+* ``survey(N, ...)``: a survey-like region seen by an observer at the origin:
+  the cube [-h, h]^2 x [d, d + 2h] (default h = 500, d = 1000 Mpc/h), a Thomas
+  catalogue wrapped into it and 3N uniform randoms over it (no periodicity is
+  implied: the wrap only keeps every point inside the region).
 """
 from __future__ import annotations
 
@@ -25,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "poisson", "thomas", "uniform_weights", "randoms", "Workload", "workload",
-    "batch_boxes", "WORKLOADS",
+    "batch_boxes", "WORKLOADS", "survey", "Survey",
 ]
 
 
@@ -148,3 +152,36 @@ def batch_boxes(n_boxes: int = 64, scale: float = 1.0):
                             np.geomspace(1.0, 10.0, 31), 4,
                             np.linspace(0.5, 3.0, 11), 4, seed=4000 + b))
     return out
+
+
+@dataclasses.dataclass
+class Survey:
+    """A survey-geometry workload: data and randoms in a region seen from the
+    origin, with the power-spectrum parameters."""
+    name: str
+    pos: np.ndarray
+    randoms: np.ndarray
+    volume: float
+    r0: float
+    k_edges: np.ndarray
+    ell_max: int
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+
+def survey(n: int = 1_000_000, f_rand: float = 3.0, half: float = 500.0, dist: float = 1000.0,
+           c: int = 10, sigma: float = 2.0, seed: int = 6, dtype=np.float32, r0: float = 25.0,
+           k_edges=None, ell_max: int = 4) -> Survey:
+    """Thomas catalogue (n/c parents, c children, N(0, sigma^2) offsets) and
+    f_rand * n uniform randoms in [-half, half]^2 x [dist, dist + 2 half];
+    default bins geomspace(1, 10, 41), ell = 0, 2, 4, R0 = 25."""
+    side = 2.0 * half
+    lo = np.array([-half, -half, dist])
+    pos = thomas(n // c * c, side, c, sigma, 0.0, seed, np.float64)
+    pos = np.ascontiguousarray((pos + lo).astype(dtype))
+    rnd = poisson(int(round(f_rand * (n // c * c))), side, seed + 1, np.float64)
+    rnd = np.ascontiguousarray((rnd + lo).astype(dtype))
+    k = np.geomspace(1.0, 10.0, 41) if k_edges is None else np.asarray(k_edges, dtype=np.float64)
+    return Survey(f"survey_thomas_{n}", pos, rnd, side ** 3, r0, k, ell_max)
