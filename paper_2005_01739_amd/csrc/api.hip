@@ -166,7 +166,8 @@ static int device_cus(Ctx &c) {
 // r-buckets per home cell), offsets, then chunks of home cells whose pairs fit
 // the pair buffer, each written and swept into `partial`.  count(cnt_a,
 // cnt_b, ord) and write(off_a, off_b, base_a, base_b, n_a, c0, c1, pairs) run
-// the set's enumeration kernels.
+// the set's enumeration kernels.  far_ok (k_0 > 0) says the second bucket,
+// r >= U_BIG / k_0, may take the sweep's far path.
 struct SweepStats {
   uint64_t ordered = 0;
   double ms_pairs = 0.0, ms_sweep = 0.0;
@@ -175,8 +176,8 @@ struct SweepStats {
 
 template <typename CountF, typename WriteF>
 static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t ncells, CountF &&count, WriteF &&write, int n_ell,
-                                 bool fp64, double r0, const double *edges, int n_edges, double *partial,
-                                 int nwaves) {
+                                 bool fp64, double r0, const double *edges, int n_edges, bool far_ok,
+                                 double *partial, int nwaves) {
   SweepStats st;
   int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
   int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(ncells) * 8));
@@ -215,7 +216,7 @@ static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t ncells, CountF &&cou
       hipEvent_t a = tm.mark();
       write(off_a, off_b, ha[size_t(c0)], hb[size_t(c0)], n_a, c0, c1, pp);
       hipEvent_t b = tm.mark();
-      pk_sweep(c, pp, np, n_ell, fp64, r0, edges, n_edges, partial, nwaves);
+      pk_sweep(c, pp, far_ok ? n_a : np, np, n_ell, fp64, r0, edges, n_edges, partial, nwaves);
       hipEvent_t d = tm.mark();
       HIPSTER_HIP(hipEventSynchronize(d));
       st.ms_pairs += Timer::ms(a, b);
@@ -227,21 +228,28 @@ static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t ncells, CountF &&cou
   return st;
 }
 
-// Bin edges and their reciprocals on the device (0 for a zero edge, whose
-// u = 0 always takes the Taylor branch).
+// The sweep's edge table on the device: k_e, 1/k_e, k_e^3 (doubles), then
+// U_BIG / k_e (floats).  A zero edge stores 0 for its reciprocals; its u = 0
+// always takes the general (Taylor) path.
 static double *upload_edges(Ctx &c, int n_k, const double *k_edges) {
   const int n_edges = n_k + 1;
-  std::vector<double> he(static_cast<size_t>(2 * n_edges));
+  const size_t bytes = size_t(n_edges) * (3 * 8 + 4);
+  std::vector<double> he((bytes + 7) / 8, 0.0);
+  float *tf = reinterpret_cast<float *>(he.data() + 3 * n_edges);
   for (int e = 0; e < n_edges; ++e) {
-    he[size_t(e)] = k_edges[e];
-    he[size_t(n_edges + e)] = k_edges[e] > 0.0 ? 1.0 / k_edges[e] : 0.0;
+    const double k = k_edges[e];
+    he[size_t(e)] = k;
+    he[size_t(n_edges + e)] = k > 0.0 ? 1.0 / k : 0.0;
+    he[size_t(2 * n_edges + e)] = k * k * k;
+    tf[e] = k > 0.0 ? float(HIPSTER_U_BIG / k) : 0.0f;
   }
-  double *edges = static_cast<double *>(ensure(c, c.edges, size_t(2 * n_edges) * 8));
-  HIPSTER_HIP(hipMemcpyAsync(edges, he.data(), size_t(2 * n_edges) * 8, hipMemcpyHostToDevice, c.stream));
+  double *edges = static_cast<double *>(ensure(c, c.edges, he.size() * 8));
+  HIPSTER_HIP(hipMemcpyAsync(edges, he.data(), he.size() * 8, hipMemcpyHostToDevice, c.stream));
   return edges;
 }
 
-// Merged edge sums -> S^a_l = 3 (2l+1)(-i)^l [k_{a+1}^3 E_{a+1} - k_a^3 E_a] / (k_{a+1}^3 - k_a^3).
+// Merged edge sums -> S^a_l = 3 (2l+1)(-i)^l [E'_{a+1} - E'_a] / (k_{a+1}^3 - k_a^3),
+// E'_e = k_e^3 E_e as accumulated by the sweep.
 static std::vector<double> bin_sums(Ctx &c, double *partial, int nwaves, int n_ell, int n_k, const double *k_edges) {
   const int n_edges = n_k + 1, cols = n_ell * n_edges;
   double *merged = static_cast<double *>(ensure(c, c.merged, size_t(cols) * 8));
@@ -257,7 +265,7 @@ static std::vector<double> bin_sums(Ctx &c, double *partial, int nwaves, int n_e
       const double ka = k_edges[a], kb = k_edges[a + 1];
       const double a3 = ka * ka * ka, b3 = kb * kb * kb;
       const double Ea = E[size_t(li * n_edges + a)], Eb = E[size_t(li * n_edges + a + 1)];
-      S[size_t(li * n_k + a)] = 3.0 * (2.0 * ell + 1.0) * phase * (b3 * Eb - a3 * Ea) / (b3 - a3);
+      S[size_t(li * n_k + a)] = 3.0 * (2.0 * ell + 1.0) * phase * (Eb - Ea) / (b3 - a3);
     }
   }
   return S;
@@ -296,7 +304,7 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
       [&](int64_t *ca, int64_t *cb, unsigned long long *ord) { pk_pairs_count(c, s, g, q->r0, r_split, ca, cb, ord); },
       [&](const int64_t *oa, const int64_t *ob, int64_t ba, int64_t bb, int64_t na, int64_t c0, int64_t c1,
           PkPairs pp) { pk_pairs_write(c, s, g, q->r0, r_split, q->los_axis, oa, ob, ba, bb, na, c0, c1, pp); },
-      n_ell, fp64, q->r0, edges, n_edges, partial, nwaves);
+      n_ell, fp64, q->r0, edges, n_edges, q->k_edges[0] > 0.0, partial, nwaves);
   const std::vector<double> S = bin_sums(c, partial, nwaves, n_ell, q->n_k, q->k_edges);
   hipEvent_t t3 = tm.mark();
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
@@ -398,7 +406,7 @@ static void run_pk_survey(Ctx &c, const hipster_points *dp, const hipster_points
             PkPairs pp) {
           survey_pairs_write(c, *z.a, *z.b, z.cross, g, q->r0, r_split, z.scale, oa, ob, ba, bb, na, c0, c1, pp);
         },
-        n_ell, fp64, q->r0, edges, n_edges, partial, nwaves);
+        n_ell, fp64, q->r0, edges, n_edges, q->k_edges[0] > 0.0, partial, nwaves);
   }
   const std::vector<double> S = bin_sums(c, partial, nwaves, n_ell, q->n_k, q->k_edges);
   hipEvent_t t3 = tm.mark();

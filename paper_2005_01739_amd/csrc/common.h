@@ -148,10 +148,14 @@ void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, co
                         double r_split, double scale, const int64_t *off_a, const int64_t *off_b, int64_t base_a,
                         int64_t base_b, int64_t n_a, int64_t c0, int64_t c1, PkPairs out);
 
-// Pair-weight sweep: adds into partial[nwaves][n_ell][n_edges] (zeroed by the
-// caller before the first chunk).  Returns the number of waves (partial rows).
-int pk_sweep(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0,
-             const double *edges_dev, int n_edges, double *partial, int nwaves_fixed);
+// Pair-weight sweep: adds E'_l(e) = sum c_l k_e^3 G_l(k_e r) into
+// partial[nwaves][n_ell][n_edges] (zeroed by the caller before the first
+// chunk).  Pairs [n_near, npairs) must have r >= U_BIG / k_0 with k_0 > 0 (the
+// far bucket); pass n_near = npairs when there is no such bucket.  `ek` is the
+// device edge table (k_e, 1/k_e, k_e^3 as doubles, then U_BIG / k_e as
+// floats).  Returns the number of waves (partial rows).
+int pk_sweep(Ctx &c, const PkPairs &p, int64_t n_near, int64_t npairs, int n_ell, bool fp64, double r0,
+             const double *ek, int n_edges, double *partial, int nwaves_fixed);
 int pk_sweep_waves(Ctx &c);
 void pk_sweep_tasks(Ctx &c, const PkPairs &p, const PkTask *tasks, int ntasks, int *counter, const double *edges,
                     const BoxSweep *boxes, int cols, double *rows, int n_ell, bool fp64, int nwaves);

@@ -2,13 +2,16 @@
 // names the Bessel weights the limiting step).
 //
 // For each unordered pair (r, mu, w_i w_j m_ij) and each bin edge k_e the
-// kernel adds c_l G_l(k_e r) to a per-lane double accumulator, with
-// c_l = w_i w_j m_ij W(r/R0) L_l(mu).  The bin values follow on the host as
-// S^a_l = 3 (2l+1) (-i)^l [k_{a+1}^3 E_l(a+1) - k_a^3 E_l(a)] / (k_{a+1}^3 - k_a^3)
-// (Sec. 3, binned estimator with eq. jla-def).  Edges are processed in
-// balanced chunks (at most 21 edges in the mixed single-box sweep, 8 otherwise)
-// so the accumulators stay in registers; the pair stream is re-read once per
-// chunk.  Each wave reduces its lanes with cross-lane shuffles and
+// single-box sweep adds c_l k_e^3 G_l(k_e r) to a per-lane double accumulator,
+// with c_l = w_i w_j m_ij W(r/R0) L_l(mu).  The bin values follow on the host as
+// S^a_l = 3 (2l+1) (-i)^l [E'_l(a+1) - E'_l(a)] / (k_{a+1}^3 - k_a^3),
+// E'_l(e) = sum over pairs of c_l k_e^3 G_l(k_e r) (Sec. 3, binned estimator
+// with eq. jla-def).  Since k^3 G_l(k r) = Dt_l(k r) / r^3, pairs of the far
+// bucket (r >= U_BIG / k_0, so every edge is on the large-argument side)
+// accumulate (c_l / r^3) Dt_l(k_e r) with no per-edge rescaling; pairs of the
+// near bucket evaluate G_l and scale it by k_e^3.  Edges are processed in
+// balanced chunks (SweepChunk edges at most) so the accumulators stay in
+// registers; the pair stream is re-read once per chunk.  Each wave reduces its lanes with cross-lane shuffles and
 // adds its sums to its own row of `partial`; rows are merged in a fixed order,
 // so results are bitwise reproducible.
 #include <type_traits>
@@ -24,10 +27,11 @@ constexpr int kChunk = 8;  // batched sweep; single-box sweep: SweepChunk below
 // Edges per chunk of the single-box sweep.  A larger chunk reads the pair
 // stream fewer times and spreads each pair's set-up (window, Legendre, 1/r)
 // over more edges, at the cost of registers: the mixed form has room for 21
-// (two chunks for 41 edges, measured 12% faster than 8); the FP64 form's
-// longer special functions keep it at 8 (larger chunks measured slower).
-template <bool FP64>
-constexpr int SweepChunk = FP64 ? 8 : 21;
+// edges of up to three multipoles (two chunks for 41 edges, measured 12%
+// faster than 8) and 14 of four; the FP64 form's longer special functions keep
+// it at 8 (larger chunks measured slower).
+template <bool FP64, int NE>
+constexpr int SweepChunk = FP64 ? 8 : (NE <= 3 ? 21 : 14);
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -37,25 +41,39 @@ __device__ inline double wave_sum(double v) {
 
 // Minimum waves per SIMD for the sweep (a build-time tuning knob).
 #ifndef HIPSTER_PK_WAVES_PER_EU
-#define HIPSTER_PK_WAVES_PER_EU 1
+#define HIPSTER_PK_WAVES_PER_EU 2
 #endif
 
+// Per-pair set-up shared by both buckets: c_l = w W(r/R0) L_l(mu).
+template <int NE>
+__device__ inline void pair_coeffs(double r, double mu, double ww, double inv_r0, double (&cf)[NE]) {
+  const double wt = ww * window<double>(r * inv_r0);
+  double L[NE];
+  legendre_even<double, NE>(mu, L);
+#pragma unroll
+  for (int i = 0; i < NE; ++i) cf[i] = wt * L[i];
+}
+
+// ek holds the edge table written by the host: k_e, 1/k_e, k_e^3 (doubles,
+// n_edges each) followed by U_BIG / k_e as floats.  Pairs [0, n_near) take the
+// general path; pairs [n_near, npairs) take the far path (the mixed form only;
+// the host passes n_near = npairs otherwise).
 template <int NE, bool FP64>
-__global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIPSTER_PK_WAVES_PER_EU))) void k_pk_sweep(const double *__restrict__ pr,
-                                                          const void *__restrict__ pmu_,
-                                                          const void *__restrict__ pww_,
-                                                          int64_t npairs, double inv_r0,
-                                                          const double *__restrict__ edges,
-                                                          const double *__restrict__ inv_edges,
-                                                          int n_edges, double *__restrict__ partial) {
-  using T = double;  // per-pair weights and mu are evaluated in double in both forms
-  const T *pmu = static_cast<const T *>(pmu_);
-  const T *pww = static_cast<const T *>(pww_);
+__global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIPSTER_PK_WAVES_PER_EU))) void k_pk_sweep(
+    const double *__restrict__ pr, const double *__restrict__ pmu, const double *__restrict__ pww, int64_t n_near,
+    int64_t npairs, double inv_r0, const double *__restrict__ ek, int n_edges, double *__restrict__ partial) {
+  __shared__ double2 tab[256];
+  if (!FP64) {
+    for (int i = threadIdx.x; i < 256; i += kSweepBlock) tab[i] = make_double2(SINCOS_TAB[i][0], SINCOS_TAB[i][1]);
+    __syncthreads();
+  }
+  const double *k_e = ek, *inv_k = ek + n_edges, *k3 = ek + 2 * n_edges;
+  const float *t_e = reinterpret_cast<const float *>(ek + 3 * n_edges);
   const int64_t gtid = int64_t(blockIdx.x) * kSweepBlock + threadIdx.x;
   const int64_t stride = int64_t(gridDim.x) * kSweepBlock;
   const int wave = int(gtid >> 6), lane = threadIdx.x & 63;
   // balanced chunks of at most CH edges
-  constexpr int CH = SweepChunk<FP64>;
+  constexpr int CH = SweepChunk<FP64, NE>;
   const int nchunk = (n_edges + CH - 1) / CH, per = (n_edges + nchunk - 1) / nchunk;
   for (int e0 = 0; e0 < n_edges; e0 += per) {
     const int e_end = e0 + per < n_edges ? e0 + per : n_edges;
@@ -64,29 +82,44 @@ __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIP
     for (int i = 0; i < NE; ++i)
 #pragma unroll
       for (int cc = 0; cc < CH; ++cc) acc[i][cc] = 0.0;
-    for (int64_t p = gtid; p < npairs; p += stride) {
+    // near bucket (and every pair in the FP64 form): G_l(k_e r) k_e^3
+    for (int64_t p = gtid; p < n_near; p += stride) {
       const double r = pr[p];
-      const T mu = pmu[p], ww = pww[p];
-      const T wt = ww * window<T>(T(r * inv_r0));
-      T L[NE];
-      legendre_even<T, NE>(mu, L);
       double cf[NE];
-#pragma unroll
-      for (int i = 0; i < NE; ++i) cf[i] = double(wt * L[i]);
+      pair_coeffs<NE>(r, pmu[p], pww[p], inv_r0, cf);
       const double inv_r = r > 0.0 ? 1.0 / r : 0.0;
 #pragma unroll
       for (int cc = 0; cc < CH; ++cc) {
         const int e = e0 + cc;
         if (e < e_end) {
-          const double u = edges[e] * r;
-          if constexpr (FP64) {
-            const Gv<double, NE> G = G_fp64<NE, 2>(u);
+          const double u = k_e[e] * r;
+          Gv<double, NE> G;
+          if constexpr (FP64) G = G_fp64<NE, 2>(u);
+          else G = G_mixed_w<NE, 2>(u, inv_k[e] * inv_r);
+          const double s3 = k3[e];
 #pragma unroll
-            for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i], acc[i][cc]);
-          } else {
-            const Gv<double, NE> G = G_mixed_w<NE, 2>(u, inv_edges[e] * inv_r);
+          for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i] * s3, acc[i][cc]);
+        }
+      }
+    }
+    if constexpr (!FP64) {
+      // far bucket: (c_l / r^3) Dt_l(k_e r), every edge on the large-argument side
+      for (int64_t p = n_near + gtid; p < npairs; p += stride) {
+        const double r = pr[p];
+        double cf[NE];
+        pair_coeffs<NE>(r, pmu[p], pww[p], inv_r0, cf);
+        const double inv_r = 1.0 / r;
+        const double ir3 = inv_r * inv_r * inv_r;
 #pragma unroll
-            for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i], acc[i][cc]);
+        for (int i = 0; i < NE; ++i) cf[i] *= ir3;
+        const float inv_rf = float(inv_r);
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) {
+          const int e = e0 + cc;
+          if (e < e_end) {
+            const Gv<double, NE> D = Dt_far_mixed<NE, 2>(k_e[e] * r, inv_k[e] * inv_r, t_e[e] * inv_rf, tab);
+#pragma unroll
+            for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], D.v[i], acc[i][cc]);
           }
         }
       }
@@ -111,27 +144,26 @@ int pk_sweep_waves(Ctx &c) {
 }
 
 template <int NE>
-static void launch_sweep(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, double inv_r0,
-                         const double *edges, int n_edges, double *partial, int nwaves) {
+static void launch_sweep(Ctx &c, const PkPairs &p, int64_t n_near, int64_t npairs, bool fp64, double inv_r0,
+                         const double *ek, int n_edges, double *partial, int nwaves) {
   const dim3 grid(unsigned(nwaves / 4)), block(kSweepBlock);
-  const double *inv_edges = edges + n_edges;  // the caller stores 1/k_e after the edges
+  const double *mu = static_cast<const double *>(p.mu), *ww = static_cast<const double *>(p.ww);
   if (fp64)
-    k_pk_sweep<NE, true><<<grid, block, 0, c.stream>>>(p.r, p.mu, p.ww, npairs, inv_r0, edges, inv_edges, n_edges,
-                                                       partial);
+    k_pk_sweep<NE, true><<<grid, block, 0, c.stream>>>(p.r, mu, ww, npairs, npairs, inv_r0, ek, n_edges, partial);
   else
-    k_pk_sweep<NE, false><<<grid, block, 0, c.stream>>>(p.r, p.mu, p.ww, npairs, inv_r0, edges, inv_edges, n_edges,
-                                                        partial);
+    k_pk_sweep<NE, false><<<grid, block, 0, c.stream>>>(p.r, mu, ww, n_near, npairs, inv_r0, ek, n_edges, partial);
   HIPSTER_HIP(hipGetLastError());
 }
 
-int pk_sweep(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0,
-             const double *edges_dev, int n_edges, double *partial, int nwaves) {
+int pk_sweep(Ctx &c, const PkPairs &p, int64_t n_near, int64_t npairs, int n_ell, bool fp64, double r0,
+             const double *ek, int n_edges, double *partial, int nwaves) {
+  if (n_near < 0 || n_near > npairs) throw Error{HIPSTER_EINVAL, "sweep: near-bucket size out of range"};
   const double inv = 1.0 / r0;
   switch (n_ell) {
-    case 1: launch_sweep<1>(c, p, npairs, fp64, inv, edges_dev, n_edges, partial, nwaves); break;
-    case 2: launch_sweep<2>(c, p, npairs, fp64, inv, edges_dev, n_edges, partial, nwaves); break;
-    case 3: launch_sweep<3>(c, p, npairs, fp64, inv, edges_dev, n_edges, partial, nwaves); break;
-    default: launch_sweep<4>(c, p, npairs, fp64, inv, edges_dev, n_edges, partial, nwaves); break;
+    case 1: launch_sweep<1>(c, p, n_near, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
+    case 2: launch_sweep<2>(c, p, n_near, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
+    case 3: launch_sweep<3>(c, p, n_near, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
+    default: launch_sweep<4>(c, p, n_near, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
   }
   return nwaves;
 }

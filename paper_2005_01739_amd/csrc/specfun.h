@@ -255,6 +255,24 @@ __device__ inline void sincos_reduced64_short(double u, double &s, double &c) {
   c = ((q + 1) & 2) ? -cc : cc;
 }
 
+// sin and cos of u >= 0 from the table SINCOS_TAB (sin, cos at n pi/128,
+// staged in LDS by the caller as tab[n] = {sin, cos}) and short polynomials in
+// the remainder x = u - n pi/128, |x| <= pi/256:
+//   sin u = S_n cos x + C_n sin x,  cos u = C_n cos x - S_n sin x,
+// with sin x through x^5 (truncation < 1e-17) and cos x through x^4
+// (truncation < 5e-15).  The reduction is exact for u < 2^26 pi/128 ~ 1.6e6.
+__device__ inline void sincos_tab(double u, const double2 *__restrict__ tab, double &s, double &c) {
+  const double n = rint(u * INV_PIO128);
+  double x = fma(-n, PIO128_HI, u);
+  x = fma(-n, PIO128_LO, x);
+  const double2 sc = tab[int(n) & 255];
+  const double x2 = x * x;
+  const double sx = fma(x * x2, fma3(x2, 1.0 / 120.0, -1.0 / 6.0), x);
+  const double cx = fma3(x2, fma3(x2, 1.0 / 24.0, -0.5), 1.0);
+  s = fma(sc.x, cx, sc.y * sx);
+  c = fma(sc.y, cx, -(sc.x * sx));
+}
+
 template <int N>
 __device__ inline float horner32(const float (&p)[N], float t) {
   float r = p[N - 1];
@@ -301,6 +319,34 @@ __device__ inline Gv<double, NL> G_mixed_w(double u, double wd) {
 #pragma unroll
   for (int i = 0; i < NL; ++i) G.v[i] = Dt_closed<double>(i * LSTEP, u, wd, s, c, si) * w3;
   return G;
+}
+
+// Dt_l(u) = u^3 G_l(u) on the large-argument side (u >= U_BIG) in the mixed
+// form: sin and cos from the table, f and g in single precision as in
+// G_mixed_w but written in t = U_BIG / u (supplied as tf = U_BIG / u in
+// float), f = t P(t) / U_BIG and g = t^2 Q(t) / U_BIG^2 (the scalings by
+// powers of two are exact).  wd = 1/u in double for the Laurent terms.
+template <int NL, int LSTEP>
+__device__ inline Gv<double, NL> Dt_far_mixed(double u, double wd, float tf, const double2 *__restrict__ tab) {
+  constexpr bool kNeedSi = (NL - 1) * LSTEP >= 2;
+  static_assert(HIPSTER_U_BIG == 8.0, "the f, g scalings below assume U_BIG = 8");
+  Gv<double, NL> D;
+  double s, c;
+  sincos_tab(u, tab, s, c);
+  double si = 0.0;
+  if constexpr (kNeedSi) {
+    float pf = POLY_F32[HIPSTER_N_POLY32 - 1] * 0.125f, pg = POLY_G32[HIPSTER_N_POLY32 - 1] * 0.015625f;
+#pragma unroll
+    for (int k = HIPSTER_N_POLY32 - 2; k >= 0; --k) {
+      pf = fmaf(pf, tf, POLY_F32[k] * 0.125f);
+      pg = fmaf(pg, tf, POLY_G32[k] * 0.015625f);
+    }
+    const float f = pf * tf, g = pg * tf * tf;
+    si = fma(-double(g), s, fma(-double(f), c, kHalfPi));
+  }
+#pragma unroll
+  for (int i = 0; i < NL; ++i) D.v[i] = Dt_closed<double>(i * LSTEP, u, wd, s, c, si);
+  return D;
 }
 
 template <int NL, int LSTEP>
