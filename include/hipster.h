@@ -110,6 +110,8 @@ typedef struct {
   double ms_total;   /* whole call */
   uint64_t sweep_launches; /* number of pair-weight kernel launches in ms_sweep */
   uint64_t n_pairs_rr;    /* survey power spectrum: ordered random-random pairs inside R0 */
+  double ms_sweep_far;    /* P, mixed form: the far-pair kernel's part of ms_sweep */
+  uint64_t n_pairs_far;   /* P, mixed form: unordered pairs swept by the far-pair kernel */
 } hipster_diag;
 
 typedef struct hipster_ctx hipster_ctx;

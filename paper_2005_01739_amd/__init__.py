@@ -54,7 +54,8 @@ class _Diag(ct.Structure):
     _fields_ = [("n_pairs", ct.c_uint64), ("n_pairs_rand", ct.c_uint64), ("raw", _dp), ("gd", _dp),
                 ("cd", _dp), ("gr", _dp), ("cr", _dp), ("s0", _dp), ("wtilde", _dp),
                 ("ms_build", ct.c_double), ("ms_pairs", ct.c_double), ("ms_sweep", ct.c_double),
-                ("ms_total", ct.c_double), ("sweep_launches", ct.c_uint64), ("n_pairs_rr", ct.c_uint64)]
+                ("ms_total", ct.c_double), ("sweep_launches", ct.c_uint64), ("n_pairs_rr", ct.c_uint64),
+                ("ms_sweep_far", ct.c_double), ("n_pairs_far", ct.c_uint64)]
 
 
 class _SurveyParams(ct.Structure):
@@ -260,7 +261,8 @@ def pk_ell(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, los
         return out
     return out, {"raw": raw, "wtilde": wt, "n_pairs": int(d.n_pairs), "ms_build": d.ms_build,
                  "ms_pairs": d.ms_pairs, "ms_sweep": d.ms_sweep, "ms_total": d.ms_total,
-                 "sweep_launches": int(d.sweep_launches)}
+                 "sweep_launches": int(d.sweep_launches), "ms_sweep_far": d.ms_sweep_far,
+                 "n_pairs_far": int(d.n_pairs_far)}
 
 
 def pk_survey(pos, w=None, randoms=None, rw=None, *, volume: float, r0: float, k_edges, ell_max: int = 4,
@@ -297,7 +299,8 @@ def pk_survey(pos, w=None, randoms=None, rw=None, *, volume: float, r0: float, k
         return out
     return out, {"raw": raw, "n_pairs": int(d.n_pairs), "n_pairs_rand": int(d.n_pairs_rand),
                  "n_pairs_rr": int(d.n_pairs_rr), "ms_build": d.ms_build, "ms_pairs": d.ms_pairs,
-                 "ms_sweep": d.ms_sweep, "ms_total": d.ms_total, "sweep_launches": int(d.sweep_launches)}
+                 "ms_sweep": d.ms_sweep, "ms_total": d.ms_total, "sweep_launches": int(d.sweep_launches),
+                 "ms_sweep_far": d.ms_sweep_far, "n_pairs_far": int(d.n_pairs_far)}
 
 
 def bk_ell(pos, w=None, randoms=None, rw=None, *, box: float, r0: float, k_edges, ell_max: int = 4,

@@ -170,8 +170,8 @@ static int device_cus(Ctx &c) {
 // r >= U_BIG / k_0, may take the sweep's far path.
 struct SweepStats {
   uint64_t ordered = 0;
-  double ms_pairs = 0.0, ms_sweep = 0.0;
-  uint64_t launches = 0;
+  double ms_pairs = 0.0, ms_sweep = 0.0, ms_far = 0.0;
+  uint64_t launches = 0, far_pairs = 0;
 };
 
 template <typename CountF, typename WriteF>
@@ -216,11 +216,24 @@ static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t ncells, CountF &&cou
       hipEvent_t a = tm.mark();
       write(off_a, off_b, ha[size_t(c0)], hb[size_t(c0)], n_a, c0, c1, pp);
       hipEvent_t b = tm.mark();
-      pk_sweep(c, pp, far_ok ? n_a : np, np, n_ell, fp64, r0, edges, n_edges, partial, nwaves);
+      // near bucket (or every pair) through the general kernel, the far
+      // bucket through the far kernel
+      const int64_t n_gen = far_ok && !fp64 ? n_a : np;
+      pk_sweep_general(c, pp, n_gen, n_ell, fp64, r0, edges, n_edges, partial, nwaves);
+      hipEvent_t m = tm.mark();
+      if (n_gen < np) {
+        PkPairs far;
+        far.r = pp.r + n_gen;
+        far.mu = static_cast<double *>(pp.mu) + n_gen;
+        far.ww = static_cast<double *>(pp.ww) + n_gen;
+        pk_sweep_far(c, far, np - n_gen, n_ell, r0, edges, n_edges, partial, nwaves);
+      }
       hipEvent_t d = tm.mark();
       HIPSTER_HIP(hipEventSynchronize(d));
       st.ms_pairs += Timer::ms(a, b);
       st.ms_sweep += Timer::ms(b, d);
+      st.ms_far += Timer::ms(m, d);
+      st.far_pairs += uint64_t(np - n_gen);
       ++st.launches;
     }
     c0 = c1;
@@ -228,20 +241,17 @@ static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t ncells, CountF &&cou
   return st;
 }
 
-// The sweep's edge table on the device: k_e, 1/k_e, k_e^3 (doubles), then
-// U_BIG / k_e (floats).  A zero edge stores 0 for its reciprocals; its u = 0
-// always takes the general (Taylor) path.
+// The sweep's edge table on the device: k_e, 1/k_e, k_e^3 (doubles).  A zero
+// edge stores 0 for its reciprocal; its u = 0 always takes the general
+// (Taylor) path.
 static double *upload_edges(Ctx &c, int n_k, const double *k_edges) {
   const int n_edges = n_k + 1;
-  const size_t bytes = size_t(n_edges) * (3 * 8 + 4);
-  std::vector<double> he((bytes + 7) / 8, 0.0);
-  float *tf = reinterpret_cast<float *>(he.data() + 3 * n_edges);
+  std::vector<double> he(size_t(3 * n_edges));
   for (int e = 0; e < n_edges; ++e) {
     const double k = k_edges[e];
     he[size_t(e)] = k;
     he[size_t(n_edges + e)] = k > 0.0 ? 1.0 / k : 0.0;
     he[size_t(2 * n_edges + e)] = k * k * k;
-    tf[e] = k > 0.0 ? float(HIPSTER_U_BIG / k) : 0.0f;
   }
   double *edges = static_cast<double *>(ensure(c, c.edges, he.size() * 8));
   HIPSTER_HIP(hipMemcpyAsync(edges, he.data(), he.size() * 8, hipMemcpyHostToDevice, c.stream));
@@ -330,6 +340,8 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
     diag->ms_sweep = st.ms_sweep;
     diag->ms_total = Timer::ms(t0, t3);
     diag->sweep_launches = st.launches;
+    diag->ms_sweep_far = st.ms_far;
+    diag->n_pairs_far = st.far_pairs;
   }
 }
 
@@ -427,6 +439,8 @@ static void run_pk_survey(Ctx &c, const hipster_points *dp, const hipster_points
     diag->ms_sweep = st[0].ms_sweep + st[1].ms_sweep + st[2].ms_sweep;
     diag->ms_total = Timer::ms(t0, t3);
     diag->sweep_launches = st[0].launches + st[1].launches + st[2].launches;
+    diag->ms_sweep_far = st[0].ms_far + st[1].ms_far + st[2].ms_far;
+    diag->n_pairs_far = st[0].far_pairs + st[1].far_pairs + st[2].far_pairs;
   }
 }
 
@@ -541,6 +555,8 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
     diag->ms_sweep = ms_sweep;
     diag->ms_total = Timer::ms(t0, t3);
     diag->sweep_launches = launches;
+    diag->ms_sweep_far = 0.0;
+    diag->n_pairs_far = 0;
   }
 }
 
@@ -772,6 +788,8 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
     diag->ms_sweep = ms_sweep;
     diag->ms_total = Timer::ms(t0, t9);
     diag->sweep_launches = launches;
+    diag->ms_sweep_far = 0.0;
+    diag->n_pairs_far = 0;
   }
 }
 

@@ -7,13 +7,15 @@
 // S^a_l = 3 (2l+1) (-i)^l [E'_l(a+1) - E'_l(a)] / (k_{a+1}^3 - k_a^3),
 // E'_l(e) = sum over pairs of c_l k_e^3 G_l(k_e r) (Sec. 3, binned estimator
 // with eq. jla-def).  Since k^3 G_l(k r) = Dt_l(k r) / r^3, pairs of the far
-// bucket (r >= U_BIG / k_0, so every edge is on the large-argument side)
-// accumulate (c_l / r^3) Dt_l(k_e r) with no per-edge rescaling; pairs of the
-// near bucket evaluate G_l and scale it by k_e^3.  Edges are processed in
-// balanced chunks (SweepChunk edges at most) so the accumulators stay in
-// registers; the pair stream is re-read once per chunk.  Each wave reduces its lanes with cross-lane shuffles and
-// adds its sums to its own row of `partial`; rows are merged in a fixed order,
-// so results are bitwise reproducible.
+// bucket (r >= U_BIG / k_0, so every edge is on the large-argument side) go
+// through a kernel of their own that accumulates (c_l / r^3) Dt_l(k_e r) with
+// no per-edge rescaling; pairs of the near bucket (and every pair in the FP64
+// form) take the general kernel, which evaluates G_l and scales it by k_e^3.
+// Edges are processed in chunks so the accumulators stay in registers; the
+// pair stream is re-read once per chunk.  Each wave reduces its lanes with
+// cross-lane shuffles and adds its sums to its own row of `partial` (the far
+// kernel runs after the general one on the same stream, with the same rows);
+// rows are merged in a fixed order, so results are bitwise reproducible.
 #include <type_traits>
 
 #include "common.h"
@@ -22,16 +24,18 @@
 namespace hipster {
 
 constexpr int kSweepBlock = 256;
-constexpr int kChunk = 8;  // batched sweep; single-box sweep: SweepChunk below
+constexpr int kChunk = 8;  // batched sweep
 
 // Edges per chunk of the single-box sweep.  A larger chunk reads the pair
 // stream fewer times and spreads each pair's set-up (window, Legendre, 1/r)
-// over more edges, at the cost of registers: the mixed form has room for 21
-// edges of up to three multipoles (two chunks for 41 edges, measured 12%
-// faster than 8) and 14 of four; the FP64 form's longer special functions keep
-// it at 8 (larger chunks measured slower).
-template <bool FP64, int NE>
-constexpr int SweepChunk = FP64 ? 8 : (NE <= 3 ? 21 : 14);
+// over more edges, at the cost of registers.  The far kernel evaluates all CH
+// edges of a chunk without branches (past the last edge it repeats the last
+// edge and discards the result), so the host picks its CH per edge count from
+// the compiled sizes below to keep that padding small.
+constexpr int kChunksMixed3[3] = {21, 16, 11};  // far path, up to three multipoles
+constexpr int kChunksMixed4[3] = {14, 11, 8};   // far path, four multipoles
+constexpr int kChunkNear = 11;                  // general path, mixed form (near bucket)
+constexpr int kChunkFp64 = 8;                   // general path, FP64 form
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -55,25 +59,19 @@ __device__ inline void pair_coeffs(double r, double mu, double ww, double inv_r0
 }
 
 // ek holds the edge table written by the host: k_e, 1/k_e, k_e^3 (doubles,
-// n_edges each) followed by U_BIG / k_e as floats.  Pairs [0, n_near) take the
-// general path; pairs [n_near, npairs) take the far path (the mixed form only;
-// the host passes n_near = npairs otherwise).
-template <int NE, bool FP64>
+// n_edges each).
+//
+// General path: pairs [0, npairs) of its stream, any r, G_l(k_e r) k_e^3 from
+// the full special functions (the FP64 form, and the near bucket of the mixed
+// form).  Balanced chunks of at most CH edges.
+template <int NE, bool FP64, int CH>
 __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIPSTER_PK_WAVES_PER_EU))) void k_pk_sweep(
-    const double *__restrict__ pr, const double *__restrict__ pmu, const double *__restrict__ pww, int64_t n_near,
-    int64_t npairs, double inv_r0, const double *__restrict__ ek, int n_edges, double *__restrict__ partial) {
-  __shared__ double2 tab[256];
-  if (!FP64) {
-    for (int i = threadIdx.x; i < 256; i += kSweepBlock) tab[i] = make_double2(SINCOS_TAB[i][0], SINCOS_TAB[i][1]);
-    __syncthreads();
-  }
+    const double *__restrict__ pr, const double *__restrict__ pmu, const double *__restrict__ pww, int64_t npairs,
+    double inv_r0, const double *__restrict__ ek, int n_edges, double *__restrict__ partial) {
   const double *k_e = ek, *inv_k = ek + n_edges, *k3 = ek + 2 * n_edges;
-  const float *t_e = reinterpret_cast<const float *>(ek + 3 * n_edges);
   const int64_t gtid = int64_t(blockIdx.x) * kSweepBlock + threadIdx.x;
   const int64_t stride = int64_t(gridDim.x) * kSweepBlock;
   const int wave = int(gtid >> 6), lane = threadIdx.x & 63;
-  // balanced chunks of at most CH edges
-  constexpr int CH = SweepChunk<FP64, NE>;
   const int nchunk = (n_edges + CH - 1) / CH, per = (n_edges + nchunk - 1) / nchunk;
   for (int e0 = 0; e0 < n_edges; e0 += per) {
     const int e_end = e0 + per < n_edges ? e0 + per : n_edges;
@@ -82,8 +80,7 @@ __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIP
     for (int i = 0; i < NE; ++i)
 #pragma unroll
       for (int cc = 0; cc < CH; ++cc) acc[i][cc] = 0.0;
-    // near bucket (and every pair in the FP64 form): G_l(k_e r) k_e^3
-    for (int64_t p = gtid; p < n_near; p += stride) {
+    for (int64_t p = gtid; p < npairs; p += stride) {
       const double r = pr[p];
       double cf[NE];
       pair_coeffs<NE>(r, pmu[p], pww[p], inv_r0, cf);
@@ -102,26 +99,65 @@ __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIP
         }
       }
     }
-    if constexpr (!FP64) {
-      // far bucket: (c_l / r^3) Dt_l(k_e r), every edge on the large-argument side
-      for (int64_t p = n_near + gtid; p < npairs; p += stride) {
-        const double r = pr[p];
-        double cf[NE];
-        pair_coeffs<NE>(r, pmu[p], pww[p], inv_r0, cf);
-        const double inv_r = 1.0 / r;
-        const double ir3 = inv_r * inv_r * inv_r;
 #pragma unroll
-        for (int i = 0; i < NE; ++i) cf[i] *= ir3;
-        const float inv_rf = float(inv_r);
+    for (int i = 0; i < NE; ++i)
 #pragma unroll
-        for (int cc = 0; cc < CH; ++cc) {
-          const int e = e0 + cc;
-          if (e < e_end) {
-            const Gv<double, NE> D = Dt_far_mixed<NE, 2>(k_e[e] * r, inv_k[e] * inv_r, t_e[e] * inv_rf, tab);
+      for (int cc = 0; cc < CH; ++cc) {
+        const double v = wave_sum(acc[i][cc]);
+        const int e = e0 + cc;
+        if (lane == 0 && e < e_end) partial[(int64_t(wave) * NE + i) * n_edges + e] += v;
+      }
+  }
+}
+
+// Far path (mixed form): pairs with r >= U_BIG / k_0, k_0 > 0, so every edge
+// is on the large-argument side; accumulates (c_l / r^3) Dt_l(k_e r).  Chunk j
+// covers edges [j CH, (j+1) CH) and evaluates all CH of them without branches
+// (past the last edge it repeats the last edge and discards the result).  The
+// sine/cosine table and the edges' (k, 1/k) are staged in LDS; the next pair's
+// values are loaded one iteration ahead (the last iteration reloads its own
+// pair) and each edge's (k, 1/k) one edge ahead.
+template <int NE, int CH>
+__global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIPSTER_PK_WAVES_PER_EU))) void k_pk_far(
+    const double *__restrict__ pr, const double *__restrict__ pmu, const double *__restrict__ pww, int64_t npairs,
+    double inv_r0, const double *__restrict__ ek, int n_edges, double *__restrict__ partial) {
+  __shared__ double2 tab[kSinCosTab];
+  __shared__ double2 ekk[kMaxNk + 1];
+  for (int i = threadIdx.x; i < kSinCosTab; i += kSweepBlock) tab[i] = make_double2(SINCOS_TAB[i][0], SINCOS_TAB[i][1]);
+  for (int i = threadIdx.x; i < n_edges; i += kSweepBlock) ekk[i] = make_double2(ek[i], ek[n_edges + i]);
+  __syncthreads();
+  const int64_t gtid = int64_t(blockIdx.x) * kSweepBlock + threadIdx.x;
+  const int64_t stride = int64_t(gridDim.x) * kSweepBlock;
+  const int wave = int(gtid >> 6), lane = threadIdx.x & 63;
+  for (int e0 = 0; e0 < n_edges; e0 += CH) {
+    const int e_end = e0 + CH < n_edges ? e0 + CH : n_edges;
+    double acc[NE][CH];
 #pragma unroll
-            for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], D.v[i], acc[i][cc]);
-          }
-        }
+    for (int i = 0; i < NE; ++i)
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) acc[i][cc] = 0.0;
+    int64_t p = gtid;
+    double r_n = 0.0, mu_n = 0.0, ww_n = 0.0;
+    if (p < npairs) r_n = pr[p], mu_n = pmu[p], ww_n = pww[p];
+    for (; p < npairs; p += stride) {
+      const double r = r_n, mu = mu_n, ww = ww_n;
+      const int64_t q = p + stride < npairs ? p + stride : p;
+      r_n = pr[q], mu_n = pmu[q], ww_n = pww[q];
+      double cf[NE];
+      pair_coeffs<NE>(r, mu, ww, inv_r0, cf);
+      const double inv_r = 1.0 / r;
+      const double ir3 = inv_r * inv_r * inv_r;
+#pragma unroll
+      for (int i = 0; i < NE; ++i) cf[i] *= ir3;
+      double2 kk = ekk[e0];
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) {
+        const double2 kc = kk;
+        const int en = e0 + cc + 1 < e_end ? e0 + cc + 1 : e_end - 1;
+        kk = ekk[en];
+        const Gv<double, NE> D = Dt_far_mixed<NE, 2>(kc.x * r, kc.y * inv_r, tab);
+#pragma unroll
+        for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], D.v[i], acc[i][cc]);
       }
     }
 #pragma unroll
@@ -143,29 +179,77 @@ int pk_sweep_waves(Ctx &c) {
   return cus * 16;  // 4 blocks of 4 waves per CU
 }
 
+// Chunk size of the far path for n_edges edges from the compiled sizes: the
+// fewest padded edge evaluations plus about three edges' worth of set-up per
+// pair and chunk.
+static int pick_chunk(const int (&sizes)[3], int n_edges) {
+  int best = sizes[0];
+  long best_cost = -1;
+  for (int ch : sizes) {
+    const long nchunk = (n_edges + ch - 1) / ch, cost = nchunk * (ch + 3);
+    if (best_cost < 0 || cost < best_cost) best = ch, best_cost = cost;
+  }
+  return best;
+}
+
 template <int NE>
-static void launch_sweep(Ctx &c, const PkPairs &p, int64_t n_near, int64_t npairs, bool fp64, double inv_r0,
-                         const double *ek, int n_edges, double *partial, int nwaves) {
+static void launch_general(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, double inv_r0, const double *ek,
+                           int n_edges, double *partial, int nwaves) {
   const dim3 grid(unsigned(nwaves / 4)), block(kSweepBlock);
   const double *mu = static_cast<const double *>(p.mu), *ww = static_cast<const double *>(p.ww);
   if (fp64)
-    k_pk_sweep<NE, true><<<grid, block, 0, c.stream>>>(p.r, mu, ww, npairs, npairs, inv_r0, ek, n_edges, partial);
+    k_pk_sweep<NE, true, kChunkFp64><<<grid, block, 0, c.stream>>>(p.r, mu, ww, npairs, inv_r0, ek, n_edges, partial);
   else
-    k_pk_sweep<NE, false><<<grid, block, 0, c.stream>>>(p.r, mu, ww, n_near, npairs, inv_r0, ek, n_edges, partial);
+    k_pk_sweep<NE, false, kChunkNear><<<grid, block, 0, c.stream>>>(p.r, mu, ww, npairs, inv_r0, ek, n_edges, partial);
   HIPSTER_HIP(hipGetLastError());
 }
 
-int pk_sweep(Ctx &c, const PkPairs &p, int64_t n_near, int64_t npairs, int n_ell, bool fp64, double r0,
-             const double *ek, int n_edges, double *partial, int nwaves) {
-  if (n_near < 0 || n_near > npairs) throw Error{HIPSTER_EINVAL, "sweep: near-bucket size out of range"};
+template <int NE, int CH>
+static void launch_far_ch(Ctx &c, const PkPairs &p, int64_t npairs, double inv_r0, const double *ek, int n_edges,
+                          double *partial, int nwaves) {
+  const double *mu = static_cast<const double *>(p.mu), *ww = static_cast<const double *>(p.ww);
+  k_pk_far<NE, CH><<<dim3(unsigned(nwaves / 4)), dim3(kSweepBlock), 0, c.stream>>>(p.r, mu, ww, npairs, inv_r0, ek,
+                                                                                     n_edges, partial);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+template <int NE>
+static void launch_far(Ctx &c, const PkPairs &p, int64_t npairs, double inv_r0, const double *ek, int n_edges,
+                       double *partial, int nwaves) {
+  constexpr bool four = NE >= 4;
+  constexpr int c0 = four ? kChunksMixed4[0] : kChunksMixed3[0];
+  constexpr int c1 = four ? kChunksMixed4[1] : kChunksMixed3[1];
+  constexpr int c2 = four ? kChunksMixed4[2] : kChunksMixed3[2];
+  const int ch = pick_chunk(four ? kChunksMixed4 : kChunksMixed3, n_edges);
+  if (ch == c0) launch_far_ch<NE, c0>(c, p, npairs, inv_r0, ek, n_edges, partial, nwaves);
+  else if (ch == c1) launch_far_ch<NE, c1>(c, p, npairs, inv_r0, ek, n_edges, partial, nwaves);
+  else launch_far_ch<NE, c2>(c, p, npairs, inv_r0, ek, n_edges, partial, nwaves);
+}
+
+void pk_sweep_general(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0, const double *ek,
+                      int n_edges, double *partial, int nwaves) {
+  if (npairs <= 0) return;
+  if (n_edges < 1 || n_edges > kMaxNk + 1) throw Error{HIPSTER_EINVAL, "sweep: edge count out of range"};
   const double inv = 1.0 / r0;
   switch (n_ell) {
-    case 1: launch_sweep<1>(c, p, n_near, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
-    case 2: launch_sweep<2>(c, p, n_near, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
-    case 3: launch_sweep<3>(c, p, n_near, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
-    default: launch_sweep<4>(c, p, n_near, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
+    case 1: launch_general<1>(c, p, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
+    case 2: launch_general<2>(c, p, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
+    case 3: launch_general<3>(c, p, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
+    default: launch_general<4>(c, p, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
   }
-  return nwaves;
+}
+
+void pk_sweep_far(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, double r0, const double *ek, int n_edges,
+                  double *partial, int nwaves) {
+  if (npairs <= 0) return;
+  if (n_edges < 1 || n_edges > kMaxNk + 1) throw Error{HIPSTER_EINVAL, "sweep: edge count out of range"};
+  const double inv = 1.0 / r0;
+  switch (n_ell) {
+    case 1: launch_far<1>(c, p, npairs, inv, ek, n_edges, partial, nwaves); break;
+    case 2: launch_far<2>(c, p, npairs, inv, ek, n_edges, partial, nwaves); break;
+    case 3: launch_far<3>(c, p, npairs, inv, ek, n_edges, partial, nwaves); break;
+    default: launch_far<4>(c, p, npairs, inv, ek, n_edges, partial, nwaves); break;
+  }
 }
 
 // out[col] = sum over rows of partial[row][col], summed in a fixed order.

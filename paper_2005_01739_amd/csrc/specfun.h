@@ -261,11 +261,17 @@ __device__ inline void sincos_reduced64_short(double u, double &s, double &c) {
 //   sin u = S_n cos x + C_n sin x,  cos u = C_n cos x - S_n sin x,
 // with sin x through x^5 (truncation < 1e-17) and cos x through x^4
 // (truncation < 5e-15).  The reduction is exact for u < 2^26 pi/128 ~ 1.6e6.
+// n = round(u / (pi/128)) comes from adding 1.5 * 2^52: the fused sum rounds
+// to an integer whose low mantissa bits are n, so the table index is the low
+// byte of the sum, with no conversion.
+constexpr int kSinCosTab = 256;
 __device__ inline void sincos_tab(double u, const double2 *__restrict__ tab, double &s, double &c) {
-  const double n = rint(u * INV_PIO128);
+  constexpr double kRound = 6755399441055744.0;  // 1.5 * 2^52
+  const double big = fma(u, INV_PIO128, kRound);
+  const double n = big - kRound;
   double x = fma(-n, PIO128_HI, u);
   x = fma(-n, PIO128_LO, x);
-  const double2 sc = tab[int(n) & 255];
+  const double2 sc = tab[__double2loint(big) & (kSinCosTab - 1)];
   const double x2 = x * x;
   const double sx = fma(x * x2, fma3(x2, 1.0 / 120.0, -1.0 / 6.0), x);
   const double cx = fma3(x2, fma3(x2, 1.0 / 24.0, -0.5), 1.0);
@@ -322,30 +328,43 @@ __device__ inline Gv<double, NL> G_mixed_w(double u, double wd) {
 }
 
 // Dt_l(u) = u^3 G_l(u) on the large-argument side (u >= U_BIG) in the mixed
-// form: sin and cos from the table, f and g in single precision as in
-// G_mixed_w but written in t = U_BIG / u (supplied as tf = U_BIG / u in
-// float), f = t P(t) / U_BIG and g = t^2 Q(t) / U_BIG^2 (the scalings by
-// powers of two are exact).  wd = 1/u in double for the Laurent terms.
+// form: sin and cos from the table, the sine-integral auxiliaries f and g in
+// single precision as in G_mixed_w (single-precision FMAs issue at twice the
+// double rate on this hardware), written in w = 1/u (wd; wf its
+// single-precision rounding) rather than t = U_BIG w: f = w P(t) = w P''(w),
+// g = w^2 Q(t) = w^2 Q''(w) with P''_k = P_k U_BIG^k, Q''_k = Q_k U_BIG^k
+// (exact scalings by powers of two for U_BIG = 8).
 template <int NL, int LSTEP>
-__device__ inline Gv<double, NL> Dt_far_mixed(double u, double wd, float tf, const double2 *__restrict__ tab) {
+__device__ inline Gv<double, NL> Dt_far_mixed(double u, double wd, const double2 *__restrict__ tab) {
   constexpr bool kNeedSi = (NL - 1) * LSTEP >= 2;
-  static_assert(HIPSTER_U_BIG == 8.0, "the f, g scalings below assume U_BIG = 8");
+  static_assert(HIPSTER_U_BIG == 8.0, "the coefficient scalings assume U_BIG = 8");
   Gv<double, NL> D;
   double s, c;
   sincos_tab(u, tab, s, c);
   double si = 0.0;
   if constexpr (kNeedSi) {
-    float pf = POLY_F32[HIPSTER_N_POLY32 - 1] * 0.125f, pg = POLY_G32[HIPSTER_N_POLY32 - 1] * 0.015625f;
+    const float wf = float(wd);
+    float pf = POLY_F32[HIPSTER_N_POLY32 - 1] * float(1 << (3 * (HIPSTER_N_POLY32 - 1)));
+    float pg = POLY_G32[HIPSTER_N_POLY32 - 1] * float(1 << (3 * (HIPSTER_N_POLY32 - 1)));
 #pragma unroll
     for (int k = HIPSTER_N_POLY32 - 2; k >= 0; --k) {
-      pf = fmaf(pf, tf, POLY_F32[k] * 0.125f);
-      pg = fmaf(pg, tf, POLY_G32[k] * 0.015625f);
+      pf = fmaf(pf, wf, POLY_F32[k] * float(1 << (3 * k)));
+      pg = fmaf(pg, wf, POLY_G32[k] * float(1 << (3 * k)));
     }
-    const float f = pf * tf, g = pg * tf * tf;
+    const float f = pf * wf, g = pg * wf * wf;
     si = fma(-double(g), s, fma(-double(f), c, kHalfPi));
   }
+  // l = 0, 2, 4 rewritten through Dt_0 = s - u c (the same closed forms):
+  //   Dt_2 = 3 (Si - s) - Dt_0,  Dt_4 = 7.5 Si + 10 s + Dt_0 - 52.5 w (w s - c)
+  const double d0 = fma(-u, c, s);
 #pragma unroll
-  for (int i = 0; i < NL; ++i) D.v[i] = Dt_closed<double>(i * LSTEP, u, wd, s, c, si);
+  for (int i = 0; i < NL; ++i) {
+    const int l = i * LSTEP;
+    if (l == 0) D.v[i] = d0;
+    else if (l == 2) D.v[i] = fma(3.0, si - s, -d0);
+    else if (l == 4) D.v[i] = fma(-52.5, wd * fma(wd, s, -c), fma(7.5, si, fma(10.0, s, d0)));
+    else D.v[i] = Dt_closed<double>(l, u, wd, s, c, si);
+  }
   return D;
 }
 
