@@ -22,11 +22,13 @@ k_pk_far (pairs with every edge on the large-argument side, about 90% of the
 pairs), otherwise the whole pair-weight sweep; algorithmic FLOPs per launch
 (the per-pair model 40 + 80 (n_k+1) + 5 n_k n_ell per unordered pair, times
 the pairs that launch sweeps) over its average duration measured with HIP
-events on the library's stream, against the 78.6 TFLOP/s non-packed vector
-peak of the chip.  `roofline.whole_sweep` gives the same figure for both
-sweep kernels together.  `traffic` is read from the committed rocprofv3
-counter summary of that kernel when the kernel's sources are unchanged since
-the counters were taken, else null.
+events on the library's stream, against the chip's 157.3 TFLOP/s FP32 vector
+peak (the kernels compute mostly in FP64, which issues at half that rate;
+`frac_fp64` gives the fraction of the 78.6 TFLOP/s FP64 vector peak).
+`roofline.whole_sweep` gives the same figures for both sweep kernels
+together.  `traffic` is read from the committed rocprofv3 counter summary of
+that kernel when the kernel's sources are unchanged since the counters were
+taken, else null.
 `cpu_baseline` times the FP64 brute-force oracle on the host cores over a
 fixed subset of primaries of the same catalogue.
 """
@@ -46,7 +48,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair-weights/s (P_ℓ & B_ℓ) + boxes/s, mixed vs FP64 GPU at ≤1e-6 rel err"
-PEAK_VALU_TFLOPS = 78.6  # 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-packed FP32 = FP64 rate
+# FP32 vector peak: 256 CUs x 128 FP32 FMA per clock x 2 flop x 2.4 GHz.  Non-packed
+# FP32 FMAs issue at this rate on gfx950 (twice the FP64 rate, 78.6 TFLOP/s).
+PEAK_VALU_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 SWEEP_SOURCES = ["paper_2005_01739_amd/csrc/pk.hip", "paper_2005_01739_amd/csrc/specfun.h",
                  "paper_2005_01739_amd/csrc/coeffs.h"]
 PROFILE = os.path.join(ROOT, "profiles", "k_pk_far_mixed_thomas_2e6.md")
@@ -257,6 +262,7 @@ def main():
         flops = unordered * per_pair / (launches / args.steps)
         achieved = flops / (avg_launch_ms * 1e-3) / 1e12
         sweep = {"kernels": "k_pk_sweep + k_pk_far", "achieved": achieved, "frac": achieved / PEAK_VALU_TFLOPS,
+                 "frac_fp64": achieved / PEAK_FP64_TFLOPS,
                  "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
         if far_pairs > 0 and far_ms > 0.0:
             # the dominant kernel: the far-pair kernel, timed on its own
@@ -265,19 +271,22 @@ def main():
             far_ach = far_flops / (far_avg * 1e-3) / 1e12
             out["roofline"] = {"bound": "alu", "kernel": "k_pk_far", "achieved": far_ach, "peak": PEAK_VALU_TFLOPS,
                                "unit": "TFLOP/s", "frac": far_ach / PEAK_VALU_TFLOPS,
+                               "frac_fp64": far_ach / PEAK_FP64_TFLOPS,
                                "traffic": traffic_from_profile() if args.workload == "pk" else None,
                                "flops_per_launch": far_flops, "avg_launch_ms": far_avg,
                                "pairs_per_launch": far_pairs / (launches / args.steps), "whole_sweep": sweep}
         else:
             out["roofline"] = {"bound": "alu", "kernel": "k_pk_sweep", "achieved": achieved,
                                "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                               "frac_fp64": achieved / PEAK_FP64_TFLOPS,
                                "traffic": None, "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
     else:
         # both primary catalogues, per launch (data primaries, then random primaries)
         flops = (pairs + pairs_r) * bk_flops_per_pair(n_k, wl.ell_max_b) / (launches / args.steps)
         achieved = flops / (avg_launch_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "kernel": "k_bk_fused", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
-                           "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                           "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                           "frac_fp64": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                            "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
     out["pairs_per_step"] = pairs + pairs_r
     if not args.no_cpu_baseline and args.workload == "pk":

@@ -146,6 +146,7 @@ __device__ inline int64_t uniform_i64(int64_t v) {
   return int64_t((uint64_t(uint32_t(hi)) << 32) | uint64_t(uint32_t(lo)));
 }
 
+constexpr int kSinCosTabBk = 64;      // sine/cosine table entries (LDS)
 constexpr int kYStride = kBatch + 1;  // row stride of the y_lm staging
 static_assert(kYStride == 64 + 1, "YRow assumes kBatch = 64");
 
@@ -175,6 +176,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_W
   __shared__ double hb_r[kHitCap + 1], hb_ir[kHitCap + 1], hb_f[kHitCap + 1], hb_x[kHitCap], hb_y[kHitCap],
       hb_z[kHitCap];
   __shared__ int64_t nb_beg[27], nb_end[27], run_beg[27], run_end[27];
+  // sine/cosine table for the mixed form's closed branch (64 entries: the
+  // LDS of four one-wave workgroups per CU has room for 1 KB more)
+  __shared__ double2 sc_tab[FP64 ? 1 : kSinCosTabBk];
+  if constexpr (!FP64) {
+    stage_sincos_tab<kSinCosTabBk>(sc_tab);
+    __syncthreads();
+  }
   __shared__ int nb_sh[27], run_sh[27], n_runs_s;
   const int lane = threadIdx.x, t4 = lane >> 4, col = lane & 15;
   // per-lane edge constants: this lane evaluates edge `col`, bin `col`
@@ -272,7 +280,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_W
           const double rq = v ? hb_r[lane] : 0.0, irq = v ? hb_ir[lane] : 0.0;
           Gv<double, NL> T;
           if constexpr (FP64) T = G_fp64<NL, 1>(ktop * rq);
-          else T = G_mixed_w<NL, 1>(ktop * rq, iktop * irq);
+          else T = G_mixed_w<NL, 1, kSinCosTabBk>(ktop * rq, iktop * irq, sc_tab);
 #pragma unroll
           for (int l = 0; l < NL; ++l) gtop[l * kBatch + lane] = ktop3 * T.v[l];
         }
@@ -290,7 +298,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_W
           const double fb = hb_f[qe] * cfb;
           Gv<double, NL> Ge;
           if constexpr (FP64) Ge = G_fp64<NL, 1>(ke * rq);
-          else Ge = G_mixed_w<NL, 1>(ke * rq, ike * irq);
+          else Ge = G_mixed_w<NL, 1, kSinCosTabBk>(ke * rq, ike * irq, sc_tab);
 #pragma unroll
           for (int l = 0; l < NL; ++l) {
             const double gn = from_next_lane_in_row(Ge.v[l]);

@@ -69,6 +69,11 @@ __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIP
     const double *__restrict__ pr, const double *__restrict__ pmu, const double *__restrict__ pww, int64_t npairs,
     double inv_r0, const double *__restrict__ ek, int n_edges, double *__restrict__ partial) {
   const double *k_e = ek, *inv_k = ek + n_edges, *k3 = ek + 2 * n_edges;
+  __shared__ double2 tab[FP64 ? 1 : kSinCosTab];
+  if constexpr (!FP64) {
+    stage_sincos_tab<kSinCosTab>(tab);
+    __syncthreads();
+  }
   const int64_t gtid = int64_t(blockIdx.x) * kSweepBlock + threadIdx.x;
   const int64_t stride = int64_t(gridDim.x) * kSweepBlock;
   const int wave = int(gtid >> 6), lane = threadIdx.x & 63;
@@ -92,7 +97,7 @@ __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIP
           const double u = k_e[e] * r;
           Gv<double, NE> G;
           if constexpr (FP64) G = G_fp64<NE, 2>(u);
-          else G = G_mixed_w<NE, 2>(u, inv_k[e] * inv_r);
+          else G = G_mixed_w<NE, 2>(u, inv_k[e] * inv_r, tab);
           const double s3 = k3[e];
 #pragma unroll
           for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i] * s3, acc[i][cc]);
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIP
     double inv_r0, const double *__restrict__ ek, int n_edges, double *__restrict__ partial) {
   __shared__ double2 tab[kSinCosTab];
   __shared__ double2 ekk[kMaxNk + 1];
-  for (int i = threadIdx.x; i < kSinCosTab; i += kSweepBlock) tab[i] = make_double2(SINCOS_TAB[i][0], SINCOS_TAB[i][1]);
+  stage_sincos_tab<kSinCosTab>(tab);
   for (int i = threadIdx.x; i < n_edges; i += kSweepBlock) ekk[i] = make_double2(ek[i], ek[n_edges + i]);
   __syncthreads();
   const int64_t gtid = int64_t(blockIdx.x) * kSweepBlock + threadIdx.x;
@@ -292,6 +297,11 @@ __global__ __launch_bounds__(kSweepBlock) void k_pk_tasks(const double *__restri
                                                           const BoxSweep *__restrict__ boxes, int cols,
                                                           double *__restrict__ rows) {
   const int lane = threadIdx.x & 63;
+  __shared__ double2 tab[FP64 ? 1 : kSinCosTab];
+  if constexpr (!FP64) {
+    stage_sincos_tab<kSinCosTab>(tab);
+    __syncthreads();
+  }
   for (;;) {
     int t = 0;
     if (lane == 0) t = atomicAdd(counter, 1);
@@ -325,7 +335,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_pk_tasks(const double *__restri
             const double u = edges[e] * r;
             Gv<double, NE> G;
             if constexpr (FP64) G = G_fp64<NE, 2>(u);
-            else G = G_mixed<NE, 2>(u);
+            else G = G_mixed<NE, 2>(u, tab);
 #pragma unroll
             for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i], acc[i][cc]);
           }

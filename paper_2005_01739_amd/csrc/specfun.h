@@ -41,11 +41,6 @@ __device__ inline double fma3(double a, double b, double c) {
 }
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kHalfPi = 1.57079632679489661923;
-constexpr double kTwoOverPi = 0.63661977236758134308;
-// pi/2 split for Cody-Waite reduction: the high part has 33 significant bits,
-// so n * kPio2Hi is exact for |n| < 2^20.
-constexpr double kPio2Hi = 1.5707963267341256141662597656e+00;
-constexpr double kPio2Lo = 6.0771005065061922518e-11;
 // Below this argument the Taylor series needs only 14 terms, and the mixed
 // form switches from the Taylor series to the closed form.
 constexpr double kUSmall = 2.0;
@@ -171,110 +166,45 @@ __device__ __noinline__ Gv<double, NL> G_fp64(double u) {
 }
 
 // ---------------------------------------------------------- mixed form
-// G_l(u) with the phase u (double) reduced modulo pi/2 in double precision and
-// the smooth amplitudes in single precision.  Below U_BIG the Taylor series is
-// summed in double (kUSmall <= u) or single (u < kUSmall) precision.
-__device__ inline void sincos_reduced(double u, float &s, float &c) {
-  double n = rint(u * kTwoOverPi);
-  double t = fma(-n, kPio2Hi, u);
-  t = fma(-n, kPio2Lo, t);
-  float x = float(t), x2 = x * x;
-  // Taylor polynomials of sin and cos on |x| <= pi/4 (truncation < 3e-9).
-  float sp = fmaf(fmaf(fmaf(fmaf(2.7557319e-6f, x2, -1.9841270e-4f), x2, 8.3333333e-3f), x2,
-                       -1.6666667e-1f), x2, 1.0f) * x;
-  float cp = fmaf(fmaf(fmaf(fmaf(fmaf(-2.7557319e-7f, x2, 2.4801587e-5f), x2, -1.3888889e-3f), x2,
-                            4.1666667e-2f), x2, -0.5f), x2, 1.0f);
-  int q = int(int64_t(n) & 3);
-  float ss = (q & 1) ? cp : sp;
-  float cc = (q & 1) ? sp : cp;
-  s = (q & 2) ? -ss : ss;
-  c = ((q + 1) & 2) ? -cc : cc;
-}
-
-// sin and cos of u in double precision from the same reduction: Taylor
-// polynomials through x^17 / x^18 on |x| <= pi/4 (truncation < 2e-17).
-__device__ inline void sincos_reduced64(double u, double &s, double &c) {
-  double n = rint(u * kTwoOverPi);
-  double x = fma(-n, kPio2Hi, u);
-  x = fma(-n, kPio2Lo, x);
-  double x2 = x * x;
-  double sp = 2.8114572543455206e-15;  // 1/17!
-  sp = fma3(sp, x2, -7.6471637318198165e-13);
-  sp = fma3(sp, x2, 1.6059043836821613e-10);
-  sp = fma3(sp, x2, -2.5052108385441720e-08);
-  sp = fma3(sp, x2, 2.7557319223985893e-06);
-  sp = fma3(sp, x2, -1.9841269841269841e-04);
-  sp = fma3(sp, x2, 8.3333333333333333e-03);
-  sp = fma3(sp, x2, -1.6666666666666667e-01);
-  sp = fma(sp * x2, x, x);
-  double cp = -1.5619206968586225e-16;  // -1/18!
-  cp = fma3(cp, x2, 4.7794773323873853e-14);
-  cp = fma3(cp, x2, -1.1470745597729725e-11);
-  cp = fma3(cp, x2, 2.0876756987868099e-09);
-  cp = fma3(cp, x2, -2.7557319223985891e-07);
-  cp = fma3(cp, x2, 2.4801587301587302e-05);
-  cp = fma3(cp, x2, -1.3888888888888889e-03);
-  cp = fma3(cp, x2, 4.1666666666666667e-02);
-  cp = fma3(cp, x2, -0.5);
-  cp = fma3(cp, x2, 1.0);
-  int q = int(int64_t(n) & 3);
-  double ss = (q & 1) ? cp : sp;
-  double cc = (q & 1) ? sp : cp;
-  s = (q & 2) ? -ss : ss;
-  c = ((q + 1) & 2) ? -cc : cc;
-}
-
-// The same for the mixed form, through x^15 / x^16 (truncation < 2e-14,
-// far below the single-precision parts of that form).
-__device__ inline void sincos_reduced64_short(double u, double &s, double &c) {
-  double n = rint(u * kTwoOverPi);
-  double x = fma(-n, kPio2Hi, u);
-  x = fma(-n, kPio2Lo, x);
-  double x2 = x * x;
-  double sp = -7.6471637318198165e-13;  // -1/15!
-  sp = fma3(sp, x2, 1.6059043836821613e-10);
-  sp = fma3(sp, x2, -2.5052108385441720e-08);
-  sp = fma3(sp, x2, 2.7557319223985893e-06);
-  sp = fma3(sp, x2, -1.9841269841269841e-04);
-  sp = fma3(sp, x2, 8.3333333333333333e-03);
-  sp = fma3(sp, x2, -1.6666666666666667e-01);
-  sp = fma(sp * x2, x, x);
-  double cp = 4.7794773323873853e-14;  // 1/16!
-  cp = fma3(cp, x2, -1.1470745597729725e-11);
-  cp = fma3(cp, x2, 2.0876756987868099e-09);
-  cp = fma3(cp, x2, -2.7557319223985891e-07);
-  cp = fma3(cp, x2, 2.4801587301587302e-05);
-  cp = fma3(cp, x2, -1.3888888888888889e-03);
-  cp = fma3(cp, x2, 4.1666666666666667e-02);
-  cp = fma3(cp, x2, -0.5);
-  cp = fma3(cp, x2, 1.0);
-  int q = int(int64_t(n) & 3);
-  double ss = (q & 1) ? cp : sp;
-  double cc = (q & 1) ? sp : cp;
-  s = (q & 2) ? -ss : ss;
-  c = ((q + 1) & 2) ? -cc : cc;
-}
-
-// sin and cos of u >= 0 from the table SINCOS_TAB (sin, cos at n pi/128,
-// staged in LDS by the caller as tab[n] = {sin, cos}) and short polynomials in
-// the remainder x = u - n pi/128, |x| <= pi/256:
-//   sin u = S_n cos x + C_n sin x,  cos u = C_n cos x - S_n sin x,
-// with sin x through x^5 (truncation < 1e-17) and cos x through x^4
-// (truncation < 5e-15).  The reduction is exact for u < 2^26 pi/128 ~ 1.6e6.
-// n = round(u / (pi/128)) comes from adding 1.5 * 2^52: the fused sum rounds
-// to an integer whose low mantissa bits are n, so the table index is the low
-// byte of the sum, with no conversion.
+// G_l(u) with the phase reduced in double precision, sin and cos from a
+// table in double, and the sine integral's auxiliaries in single precision.
+// Below kUSmall the Taylor series is summed in double precision.
+// sin and cos of u >= 0 from a table of sin, cos at n 2 pi / N (N = 256: the
+// generated SINCOS_TAB; N = 64: its every fourth entry), staged in LDS by the
+// caller as tab[n] = {sin, cos} (stage_sincos_tab), and short polynomials in
+// the remainder x = u - n 2 pi / N, |x| <= pi / N:
+//   sin u = S_n cos x + C_n sin x,  cos u = C_n cos x - S_n sin x.
+// N = 256: sin x through x^5 (truncation < 1e-17), cos x through x^4 (< 5e-15);
+// N = 64: sin x through x^7 (< 5e-18), cos x through x^6 (< 1e-15).  The
+// reduction (pi/128 split in 27 + 53 bits, scaled by 256/N) is exact for
+// u < 2^26 pi/128 ~ 1.6e6.  n = round(u N / (2 pi)) comes from adding
+// 1.5 * 2^52: the fused sum rounds to an integer whose low mantissa bits are
+// n, so the table index is read from the low word of the sum.
 constexpr int kSinCosTab = 256;
+template <int N>
+__device__ inline void stage_sincos_tab(double2 *tab) {
+  static_assert(N == 256 || N == 64, "table sizes 256 and 64");
+  for (int i = threadIdx.x; i < N; i += blockDim.x)
+    tab[i] = make_double2(SINCOS_TAB[i * (256 / N)][0], SINCOS_TAB[i * (256 / N)][1]);
+}
+template <int N = kSinCosTab>
 __device__ inline void sincos_tab(double u, const double2 *__restrict__ tab, double &s, double &c) {
+  constexpr double kScale = 256.0 / N;  // a power of two: the scalings are exact
   constexpr double kRound = 6755399441055744.0;  // 1.5 * 2^52
-  const double big = fma(u, INV_PIO128, kRound);
+  const double big = fma(u, INV_PIO128 / kScale, kRound);
   const double n = big - kRound;
-  double x = fma(-n, PIO128_HI, u);
-  x = fma(-n, PIO128_LO, x);
-  const double2 sc = tab[__double2loint(big) & (kSinCosTab - 1)];
+  double x = fma(-n, PIO128_HI * kScale, u);
+  x = fma(-n, PIO128_LO * kScale, x);
+  const double2 sc = tab[__double2loint(big) & (N - 1)];
   const double x2 = x * x;
-  const double sx = fma(x * x2, fma3(x2, 1.0 / 120.0, -1.0 / 6.0), x);
-  const double cx = fma3(x2, fma3(x2, 1.0 / 24.0, -0.5), 1.0);
+  double sx, cx;
+  if constexpr (N == 256) {
+    sx = fma(x * x2, fma3(x2, 1.0 / 120.0, -1.0 / 6.0), x);
+    cx = fma3(x2, fma3(x2, 1.0 / 24.0, -0.5), 1.0);
+  } else {
+    sx = fma(x * x2, fma3(x2, fma3(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), x);
+    cx = fma3(x2, fma3(x2, fma3(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+  }
   s = fma(sc.x, cx, sc.y * sx);
   c = fma(sc.y, cx, -(sc.x * sx));
 }
@@ -287,10 +217,11 @@ __device__ inline float horner32(const float (&p)[N], float t) {
   return r;
 }
 
-// Closed form in the mixed form: the phase is reduced in double precision and
-// sin, cos (polynomials through x^15 / x^16) and the Laurent amplitudes a_l, b_l are kept in double -- bin
-// averages difference neighbouring edges, and single-precision amplitudes
-// leave per-pair errors of ~5e-7 after that differencing.  The form is used
+// Closed form in the mixed form: sin and cos in double precision from the
+// table (sincos_tab; NTAB entries staged in LDS by the caller) and the Laurent
+// amplitudes a_l, b_l in double -- bin averages difference neighbouring edges,
+// and single-precision amplitudes leave per-pair errors of ~5e-7 after that
+// differencing.  The form is used
 // from u = kUSmall = 2 up: there its worst cancellation (l = 6 at u = 2, a
 // factor ~4e5) still leaves ~4e-11 relative error.  Si comes from its power
 // series below U_BIG (at most a factor ~40 of cancellation at u = 8) and
@@ -298,13 +229,13 @@ __device__ inline float horner32(const float (&p)[N], float t) {
 // single precision, since they enter multiplied by c_l / u and need only
 // ~1e-8 relative accuracy.  Below u = 2 G_l is summed from its Taylor series.
 // wd = 1/u, supplied by the caller (from per-pair 1/r and per-edge 1/k).
-template <int NL, int LSTEP>
-__device__ inline Gv<double, NL> G_mixed_w(double u, double wd) {
+template <int NL, int LSTEP, int NTAB = kSinCosTab>
+__device__ inline Gv<double, NL> G_mixed_w(double u, double wd, const double2 *__restrict__ tab) {
   constexpr bool kNeedSi = (NL - 1) * LSTEP >= 2;  // some even l >= 2 is requested
   if (u < kUSmall) return G_taylor64<NL, LSTEP>(u);
   Gv<double, NL> G;
   double s, c;
-  sincos_reduced64_short(u, s, c);
+  sincos_tab<NTAB>(u, tab, s, c);
   double si = 0.0;
   if constexpr (kNeedSi) {
     if (u < HIPSTER_U_BIG) {
@@ -369,12 +300,12 @@ __device__ inline Gv<double, NL> Dt_far_mixed(double u, double wd, const double2
 }
 
 template <int NL, int LSTEP>
-__device__ inline Gv<double, NL> G_mixed(double u) {
+__device__ inline Gv<double, NL> G_mixed(double u, const double2 *__restrict__ tab) {
   // 1/u from the single-precision reciprocal and two Newton steps (~1e-16)
   double wd = double(__builtin_amdgcn_rcpf(float(u)));
   wd = wd * fma(-u, wd, 2.0);
   wd = wd * fma(-u, wd, 2.0);
-  return G_mixed_w<NL, LSTEP>(u, wd);
+  return G_mixed_w<NL, LSTEP>(u, wd, tab);
 }
 
 }  // namespace hipster
