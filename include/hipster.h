@@ -57,9 +57,11 @@ typedef enum {
 
 typedef enum { HIPSTER_F32 = 0, HIPSTER_F64 = 1 } hipster_dtype;
 
-/* Arithmetic of the pair weights.  MIXED: geometry, phase reduction and all
- * accumulation in double precision, special-function amplitudes in single
- * precision.  FP64: every step in double precision. */
+/* Arithmetic of the pair weights.  MIXED: geometry, phase reduction, sine
+ * and cosine (table-driven) and all accumulation in double precision, the
+ * sine integral's auxiliary functions in single precision; it requires
+ * k_edges[n_k] * R0 <= 1e6 (the table reduction's exact range), else
+ * HIPSTER_EUNSUPPORTED.  FP64: every step in double precision, no limit. */
 typedef enum { HIPSTER_MIXED = 0, HIPSTER_FP64 = 1 } hipster_precision;
 
 /* A catalogue.  pos: n x 3 row-major coordinates of `dtype`, each in [0, L).

@@ -91,6 +91,10 @@ static void check_params(const hipster_params *q, bool bispectrum) {
   if (!bispectrum && (q->ell_max & 1)) throw Error{HIPSTER_EDOMAIN, "power spectrum: ell_max must be even"};
   if (!bispectrum && (q->los_axis < 0 || q->los_axis > 2)) throw Error{HIPSTER_EINVAL, "los_axis must be 0, 1 or 2"};
   if (q->precision != HIPSTER_MIXED && q->precision != HIPSTER_FP64) throw Error{HIPSTER_EINVAL, "bad precision"};
+  // the mixed form's table-driven sine and cosine reduce u = k r exactly only
+  // below ~1.6e6 (a 27-bit pi/128 times the table index)
+  if (q->precision == HIPSTER_MIXED && q->k_edges[q->n_k] * q->r0 > kMaxPhaseMixed)
+    throw Error{HIPSTER_EUNSUPPORTED, "mixed precision needs k_max * R0 <= 1e6; use HIPSTER_FP64"};
 }
 
 // Device copy of a catalogue when it lives on the host.

@@ -17,6 +17,7 @@ constexpr int kMaxNk = 128;        // power-spectrum bins
 constexpr int kMaxNkB = 16;        // bispectrum bins
 constexpr int kMaxCellsPerAxis = 160;
 constexpr int kLMaxApi = 6;          // largest multipole
+constexpr double kMaxPhaseMixed = 1e6;  // largest k * R0 of the mixed form
 
 struct Error {
   hipster_status status;
