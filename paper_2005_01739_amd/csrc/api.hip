@@ -62,7 +62,8 @@ static void free_buf(DevBuf &b) {
 }
 
 static void free_cells(CellScratch &s) {
-  DevBuf *all[] = {&s.cell, &s.count, &s.start, &s.cursor, &s.idx, &s.x, &s.y, &s.z, &s.w, &s.m, &s.bad, &s.scan_tmp};
+  DevBuf *all[] = {&s.cell,  &s.count, &s.start, &s.cursor,   &s.idx,   &s.x,       &s.y,
+                   &s.z,     &s.w,     &s.m,     &s.bad,      &s.scan_tmp, &s.scell, &s.sort_tmp};
   for (DevBuf *b : all) free_buf(*b);
 }
 
@@ -167,10 +168,10 @@ static int device_cus(Ctx &c) {
 
 // ---------------------------------------------------------- power spectrum
 // One set of pairs through the power-spectrum sweep: the count pass (two
-// r-buckets per home cell), offsets, then chunks of home cells whose pairs fit
-// the pair buffer, each written and swept into `partial`.  count(cnt_a,
-// cnt_b, ord) and write(off_a, off_b, base_a, base_b, n_a, c0, c1, pairs) run
-// the set's enumeration kernels.  far_ok (k_0 > 0) says the second bucket,
+// r-buckets per work unit, a home cell's tile), offsets, then chunks of units
+// whose pairs fit the pair buffer, each written and swept into `partial`.
+// count(cnt_a, cnt_b, ord) and write(off_a, off_b, base_a, base_b, n_a, u0,
+// u1, pairs) run the set's enumeration kernels.  far_ok (k_0 > 0) says the second bucket,
 // r >= U_BIG / k_0, may take the sweep's far path.
 struct SweepStats {
   uint64_t ordered = 0;
@@ -179,42 +180,42 @@ struct SweepStats {
 };
 
 template <typename CountF, typename WriteF>
-static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t ncells, CountF &&count, WriteF &&write, int n_ell,
+static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t nunits, CountF &&count, WriteF &&write, int n_ell,
                                  bool fp64, double r0, const double *edges, int n_edges, bool far_ok,
                                  double *partial, int nwaves) {
   SweepStats st;
-  int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
-  int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(ncells) * 8));
-  int64_t *off_a = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(ncells + 1) * 8));
-  int64_t *off_b = static_cast<int64_t *>(ensure(c, c.pair_off_b, size_t(ncells + 1) * 8));
+  int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(nunits) * 8));
+  int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(nunits) * 8));
+  int64_t *off_a = static_cast<int64_t *>(ensure(c, c.pair_off, size_t(nunits + 1) * 8));
+  int64_t *off_b = static_cast<int64_t *>(ensure(c, c.pair_off_b, size_t(nunits + 1) * 8));
   unsigned long long *ord = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 16));
   hipEvent_t e0 = tm.mark();
   HIPSTER_HIP(hipMemsetAsync(ord, 0, 8, c.stream));
   count(cnt_a, cnt_b, ord);
-  scan_i64(c, cnt_a, off_a, ncells, c.pair_total);
-  scan_i64(c, cnt_b, off_b, ncells, c.pair_total);
-  std::vector<int64_t> ha(size_t(ncells) + 1), hb(size_t(ncells) + 1);
+  scan_i64(c, cnt_a, off_a, nunits, c.pair_total);
+  scan_i64(c, cnt_b, off_b, nunits, c.pair_total);
+  std::vector<int64_t> ha(size_t(nunits) + 1), hb(size_t(nunits) + 1);
   unsigned long long hord = 0;
-  HIPSTER_HIP(hipMemcpyAsync(ha.data(), off_a, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
-  HIPSTER_HIP(hipMemcpyAsync(hb.data(), off_b, size_t(ncells + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(ha.data(), off_a, size_t(nunits + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(hb.data(), off_b, size_t(nunits + 1) * 8, hipMemcpyDeviceToHost, c.stream));
   HIPSTER_HIP(hipMemcpyAsync(&hord, ord, 8, hipMemcpyDeviceToHost, c.stream));
   hipEvent_t e1 = tm.mark();
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
   st.ordered = hord;
   st.ms_pairs += Timer::ms(e0, e1);
   auto pairs_in = [&](int64_t a, int64_t b) { return (ha[size_t(b)] - ha[size_t(a)]) + (hb[size_t(b)] - hb[size_t(a)]); };
-  const int64_t total = pairs_in(0, ncells);
+  const int64_t total = pairs_in(0, nunits);
   if (total == 0) return st;
   int64_t cap = std::min<int64_t>(pair_chunk_capacity(), total);
-  for (int64_t a = 0; a < ncells; ++a) cap = std::max(cap, pairs_in(a, a + 1));
+  for (int64_t a = 0; a < nunits; ++a) cap = std::max(cap, pairs_in(a, a + 1));
   PkPairs pp;
   pp.r = static_cast<double *>(ensure(c, c.pr, size_t(cap) * 8));
   pp.mu = ensure(c, c.pmu, size_t(cap) * 8);
   pp.ww = ensure(c, c.pww, size_t(cap) * 8);
   int64_t c0 = 0;
-  while (c0 < ncells) {
+  while (c0 < nunits) {
     int64_t c1 = c0 + 1;
-    while (c1 < ncells && pairs_in(c0, c1 + 1) <= cap) ++c1;
+    while (c1 < nunits && pairs_in(c0, c1 + 1) <= cap) ++c1;
     const int64_t np = pairs_in(c0, c1), n_a = ha[size_t(c1)] - ha[size_t(c0)];
     if (np > 0) {
       hipEvent_t a = tm.mark();
@@ -313,11 +314,14 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
   const int cols = n_ell * n_edges;
   double *partial = static_cast<double *>(ensure(c, c.partial, size_t(nwaves) * cols * 8));
   HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwaves) * cols * 8, c.stream));
+  const PairUnits units = make_pair_units(c, s, g);
   const SweepStats st = sweep_pair_set(
-      c, tm, g.ncells(),
-      [&](int64_t *ca, int64_t *cb, unsigned long long *ord) { pk_pairs_count(c, s, g, q->r0, r_split, ca, cb, ord); },
-      [&](const int64_t *oa, const int64_t *ob, int64_t ba, int64_t bb, int64_t na, int64_t c0, int64_t c1,
-          PkPairs pp) { pk_pairs_write(c, s, g, q->r0, r_split, q->los_axis, oa, ob, ba, bb, na, c0, c1, pp); },
+      c, tm, units.n,
+      [&](int64_t *ca, int64_t *cb, unsigned long long *ord) {
+        pk_pairs_count(c, s, g, units, q->r0, r_split, ca, cb, ord);
+      },
+      [&](const int64_t *oa, const int64_t *ob, int64_t ba, int64_t bb, int64_t na, int64_t u0, int64_t u1,
+          PkPairs pp) { pk_pairs_write(c, s, g, units, q->r0, r_split, q->los_axis, oa, ob, ba, bb, na, u0, u1, pp); },
       n_ell, fp64, q->r0, edges, n_edges, q->k_edges[0] > 0.0, partial, nwaves);
   const std::vector<double> S = bin_sums(c, partial, nwaves, n_ell, q->n_k, q->k_edges);
   hipEvent_t t3 = tm.mark();
@@ -413,14 +417,16 @@ static void run_pk_survey(Ctx &c, const hipster_points *dp, const hipster_points
   SweepStats st[3];
   for (int k = 0; k < 3; ++k) {
     const Set &z = sets[k];
+    const PairUnits units = make_pair_units(c, *z.a, g);
     st[k] = sweep_pair_set(
-        c, tm, g.ncells(),
+        c, tm, units.n,
         [&](int64_t *ca, int64_t *cb, unsigned long long *ord) {
-          survey_pairs_count(c, *z.a, *z.b, z.cross, g, q->r0, r_split, ca, cb, ord);
+          survey_pairs_count(c, *z.a, *z.b, z.cross, g, units, q->r0, r_split, ca, cb, ord);
         },
-        [&](const int64_t *oa, const int64_t *ob, int64_t ba, int64_t bb, int64_t na, int64_t c0, int64_t c1,
+        [&](const int64_t *oa, const int64_t *ob, int64_t ba, int64_t bb, int64_t na, int64_t u0, int64_t u1,
             PkPairs pp) {
-          survey_pairs_write(c, *z.a, *z.b, z.cross, g, q->r0, r_split, z.scale, oa, ob, ba, bb, na, c0, c1, pp);
+          survey_pairs_write(c, *z.a, *z.b, z.cross, g, units, q->r0, r_split, z.scale, oa, ob, ba, bb, na, u0, u1,
+                             pp);
         },
         n_ell, fp64, q->r0, edges, n_edges, q->k_edges[0] > 0.0, partial, nwaves);
   }
@@ -695,8 +701,9 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
     const uint8_t *mask = device_mask(c, c.mask_in, q.primary_mask, n);
     const Grid g = make_grid(q.box, q.r0);
     const Sorted s = build_cells(c, c.cells_d, g, pos, w, mask, n, j.data.dtype);
+    const PairUnits units = make_pair_units(c, s, g);
     hipEvent_t a1 = tm.mark();
-    const int64_t ncells = g.ncells();
+    const int64_t ncells = units.n;  // work units (home-cell tiles) of this box
     const double r_split = q.k_edges[0] > 0.0 ? HIPSTER_U_BIG / q.k_edges[0] : 0.0;
     int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(ncells) * 8));
     int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(ncells) * 8));
@@ -704,7 +711,7 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
     int64_t *off_b = static_cast<int64_t *>(ensure(c, c.pair_off_b, size_t(ncells + 1) * 8));
     unsigned long long *ord = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 16));
     HIPSTER_HIP(hipMemsetAsync(ord, 0, 8, c.stream));
-    pk_pairs_count(c, s, g, q.r0, r_split, cnt_a, cnt_b, ord);
+    pk_pairs_count(c, s, g, units, q.r0, r_split, cnt_a, cnt_b, ord);
     scan_i64(c, cnt_a, off_a, ncells, c.pair_total);
     scan_i64(c, cnt_b, off_b, ncells, c.pair_total);
     std::vector<int64_t> ha(static_cast<size_t>(ncells) + 1), hb(static_cast<size_t>(ncells) + 1);
@@ -728,13 +735,14 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
           flush();
           continue;
         }
-        throw Error{HIPSTER_EUNSUPPORTED, "batch: one cell holds more pairs than the pair stream"};
+        throw Error{HIPSTER_EUNSUPPORTED, "batch: one cell tile holds more pairs than the pair stream"};
       }
       const int64_t np = in(c0, c1), n_a = ha[size_t(c1)] - ha[size_t(c0)];
       if (np > 0) {
         hipEvent_t w0 = tm.mark();
         // shift the bases so the cells' pairs land at [fill, fill + np)
-        pk_pairs_write(c, s, g, q.r0, r_split, q.los_axis, off_a, off_b, ha[size_t(c0)] - fill, hb[size_t(c0)] - fill,
+        pk_pairs_write(c, s, g, units, q.r0, r_split, q.los_axis, off_a, off_b, ha[size_t(c0)] - fill,
+                       hb[size_t(c0)] - fill,
                        n_a, c0, c1, pp);
         hipEvent_t w1 = tm.mark();
         HIPSTER_HIP(hipEventSynchronize(w1));
@@ -846,7 +854,8 @@ void hipster_destroy(hipster_ctx *ctx) {
   free_cells(c.cells_r);
   DevBuf *all[] = {&c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in, &c.rmask_in, &c.pair_cnt, &c.pair_cnt_b,
                    &c.pair_ord, &c.pair_off, &c.pair_off_b, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
-                   &c.partial, &c.merged, &c.ordered_count, &c.bbox, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out};
+                   &c.partial, &c.merged, &c.ordered_count, &c.bbox, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out,
+                   &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile};
   for (DevBuf *b : all) free_buf(*b);
   delete ctx;
 }

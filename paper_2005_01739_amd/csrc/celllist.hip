@@ -1,6 +1,7 @@
 // Device-built cell list: every point is assigned to a cubic cell of side
-// L / n_c > R0 (of the periodic box, or of a survey's bounding cube), points are counting-sorted by cell (ties in original index
-// order, so the layout -- and every sum over it -- is deterministic), and the
+// L / n_c > R0 (of the periodic box, or of a survey's bounding cube), points
+// are sorted by cell with a stable radix sort (ties in original index order,
+// so the layout -- and every sum over it -- is deterministic), and the
 // coordinates are gathered into coalesced structure-of-arrays in double
 // precision.  Memory-bound; a few passes over ~40 bytes per point.
 #include <math.h>
@@ -8,6 +9,8 @@
 
 #include <algorithm>
 #include <vector>
+
+#include <hipcub/hipcub.hpp>
 
 #include "common.h"
 
@@ -119,41 +122,18 @@ __global__ void k_widen(const int *__restrict__ in, int64_t *__restrict__ out, i
   if (i < n) out[i] = in[i];
 }
 
-__global__ void k_scatter(const int *__restrict__ cell, int64_t n, const int64_t *__restrict__ start,
-                          int *__restrict__ cursor, int *__restrict__ idx) {
+__global__ void k_iota(int *__restrict__ v, int64_t n) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int c = cell[i];
-  int slot = atomicAdd(&cursor[c], 1);
-  idx[start[c] + slot] = int(i);
-}
-
-// Order each cell's entries by original index (insertion sort; cells hold
-// tens to hundreds of points).
-__global__ void k_sort_cells(const int64_t *__restrict__ start, int64_t ncells, int *__restrict__ idx) {
-  int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= ncells) return;
-  int64_t s = start[c], e = start[c + 1];
-  for (int64_t a = s + 1; a < e; ++a) {
-    int v = idx[a];
-    int64_t b = a - 1;
-    while (b >= s && idx[b] > v) {
-      idx[b + 1] = idx[b];
-      --b;
-    }
-    idx[b + 1] = v;
-  }
+  if (i < n) v[i] = int(i);
 }
 
 template <typename T>
 __global__ void k_gather(const T *__restrict__ pos, const T *__restrict__ w, const uint8_t *__restrict__ mask,
-                         const int *__restrict__ idx, const int *__restrict__ cell, int64_t n,
-                         double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
-                         double *__restrict__ ws, uint8_t *__restrict__ ms, int *__restrict__ scell) {
+                         const int *__restrict__ idx, int64_t n, double *__restrict__ x, double *__restrict__ y,
+                         double *__restrict__ z, double *__restrict__ ws, uint8_t *__restrict__ ms) {
   int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int i = idx[k];
-  scell[k] = cell[i];
   x[k] = double(pos[3 * int64_t(i)]);
   y[k] = double(pos[3 * int64_t(i) + 1]);
   z[k] = double(pos[3 * int64_t(i) + 2]);
@@ -239,7 +219,7 @@ static Sorted build_cells_t(Ctx &c, CellScratch &s, const Grid &g, const T *pos,
   int *count = static_cast<int *>(ensure(c, s.count, size_t(ncells) * sizeof(int)));
   int64_t *start = static_cast<int64_t *>(ensure(c, s.start, size_t(2 * ncells + 2) * sizeof(int64_t)));
   int64_t *wide = start + ncells + 1;
-  int *cursor = static_cast<int *>(ensure(c, s.cursor, size_t(ncells) * sizeof(int)));
+  int *iota = static_cast<int *>(ensure(c, s.cursor, size_t(n) * sizeof(int)));
   int *idx = static_cast<int *>(ensure(c, s.idx, size_t(n) * sizeof(int)));
   double *x = static_cast<double *>(ensure(c, s.x, size_t(n) * sizeof(double)));
   double *y = static_cast<double *>(ensure(c, s.y, size_t(n) * sizeof(double)));
@@ -263,7 +243,6 @@ static Sorted build_cells_t(Ctx &c, CellScratch &s, const Grid &g, const T *pos,
     out.scell = scell;
     return out;
   }
-  HIPSTER_HIP(hipMemsetAsync(cursor, 0, size_t(ncells) * sizeof(int), c.stream));
   HIPSTER_HIP(hipMemsetAsync(bad, 0, sizeof(int), c.stream));
   const unsigned nbp = unsigned((n + 255) / 256), nbc = unsigned((ncells + 255) / 256);
   k_assign<T><<<nbp, 256, 0, c.stream>>>(pos, n, g.L, g.nc, g.scale, g.ox, g.oy, g.oz, cell, count, bad);
@@ -274,9 +253,20 @@ static Sorted build_cells_t(Ctx &c, CellScratch &s, const Grid &g, const T *pos,
                                                      : "a coordinate is not finite or outside the survey grid"};
   k_widen<<<nbc, 256, 0, c.stream>>>(count, wide, ncells);
   scan_i64(c, wide, start, ncells, s.scan_tmp);
-  k_scatter<<<nbp, 256, 0, c.stream>>>(cell, n, start, cursor, idx);
-  k_sort_cells<<<nbc, 256, 0, c.stream>>>(start, ncells, idx);
-  k_gather<T><<<nbp, 256, 0, c.stream>>>(pos, w, mask_dev, idx, cell, n, x, y, z, ws, ms, scell);
+  // (cell, index) pairs in cell order, each cell's points in input order: a
+  // stable LSD radix sort of the cell ids with the point indices as values
+  // (deterministic, O(n) whatever the points per cell); the sorted keys are
+  // the per-point cell ids of the sorted arrays
+  k_iota<<<nbp, 256, 0, c.stream>>>(iota, n);
+  int bits = 1;
+  while (bits < 31 && (int64_t(1) << bits) < ncells) ++bits;
+  size_t tmp_bytes = 0;
+  HIPSTER_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, cell, scell, iota, idx, int(n), 0, bits,
+                                                 c.stream));
+  void *tmp = ensure(c, s.sort_tmp, std::max<size_t>(tmp_bytes, 16));
+  HIPSTER_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, cell, scell, iota, idx, int(n), 0, bits,
+                                                 c.stream));
+  k_gather<T><<<nbp, 256, 0, c.stream>>>(pos, w, mask_dev, idx, n, x, y, z, ws, ms);
   HIPSTER_HIP(hipGetLastError());
   Sorted out;
   out.n = n;

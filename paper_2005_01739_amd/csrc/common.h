@@ -95,7 +95,7 @@ struct BoxSweep {
 
 // Scratch of one catalogue's cell list.
 struct CellScratch {
-  DevBuf cell, count, start, cursor, idx, x, y, z, w, m, bad, scan_tmp, scell;
+  DevBuf cell, count, start, cursor, idx, x, y, z, w, m, bad, scan_tmp, scell, sort_tmp;
 };
 
 struct Ctx {
@@ -109,6 +109,7 @@ struct Ctx {
   DevBuf pair_cnt, pair_cnt_b, pair_ord, pair_off, pair_off_b, pair_total;
   DevBuf pr, pmu, pww, pux, puy, puz;
   DevBuf edges, partial, merged, ordered_count, bbox;
+  DevBuf unit_tiles, unit_base, unit_cell, unit_tile;
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
   // W~^a depends only on (R0, k_a, k_{a+1}); repeated calls reuse it.
@@ -126,28 +127,39 @@ Sorted build_cells(Ctx &c, CellScratch &s, const Grid &g, const void *pos, const
 // Exclusive scan of n int64 values (in-place allowed); out has n + 1 entries.
 void scan_i64(Ctx &c, const int64_t *in, int64_t *out, int64_t n, DevBuf &tmp);
 
-// Power-spectrum pair enumeration.  The count pass fills cnt_a[cell] /
-// cnt_b[cell] (pairs with r < r_split / the rest) and adds the ordered-pair
-// multiplicity to *ordered.  The write pass over home cells [c0, c1) stores a
-// cell's near pairs at off_a[cell] - base_a and its far pairs at
-// n_a + off_b[cell] - base_b.
-void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_split, int64_t *cnt_a,
-                    int64_t *cnt_b, unsigned long long *ordered);
-void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_split, int los,
+// Work units of the pair enumeration: unit u is home cell unit_cell[u]'s
+// tile unit_tile[u] of up to 64 points (one workgroup each); units are ordered
+// by cell, then tile.  Built from the home catalogue's cell list (device
+// arrays; n is read back to the host).
+struct PairUnits {
+  int64_t n = 0;
+  int *cell = nullptr;
+  int *tile = nullptr;
+};
+PairUnits make_pair_units(Ctx &c, const Sorted &a, const Grid &g);
+
+// Power-spectrum pair enumeration.  The count pass fills cnt_a[u] / cnt_b[u]
+// (pairs with r < r_split / the rest) for every unit and adds the
+// ordered-pair multiplicity to *ordered.  The write pass over units [u0, u1)
+// stores a unit's near pairs at off_a[u] - base_a and its far pairs at
+// n_a + off_b[u] - base_b.
+void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, const PairUnits &u, double r0, double r_split,
+                    int64_t *cnt_a, int64_t *cnt_b, unsigned long long *ordered);
+void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, const PairUnits &u, double r0, double r_split, int los,
                     const int64_t *off_a, const int64_t *off_b, int64_t base_a, int64_t base_b, int64_t n_a,
-                    int64_t c0, int64_t c1, PkPairs out);
+                    int64_t u0, int64_t u1, PkPairs out);
 
 // Survey-geometry enumeration (no periodicity, line of sight along each
-// pair's midpoint).  Home cells come from catalogue `a`.  cross = false: `b`
-// is `a` and every unordered pair is found once (half stencil); cross = true:
-// every pair (i in a, j in b) is found once (27 cells).  A pair's weight is
-// scale * w_i w_j (m_i + m_j), m the mask bits (1 without a mask); the count
-// pass adds sum (m_i + m_j) to *ordered.
-void survey_pairs_count(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, double r0,
-                        double r_split, int64_t *cnt_a, int64_t *cnt_b, unsigned long long *ordered);
-void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, double r0,
-                        double r_split, double scale, const int64_t *off_a, const int64_t *off_b, int64_t base_a,
-                        int64_t base_b, int64_t n_a, int64_t c0, int64_t c1, PkPairs out);
+// pair's midpoint).  Home cells (and units) come from catalogue `a`.
+// cross = false: `b` is `a` and every unordered pair is found once (half
+// stencil); cross = true: every pair (i in a, j in b) is found once (27
+// cells).  A pair's weight is scale * w_i w_j (m_i + m_j), m the mask bits (1
+// without a mask); the count pass adds sum (m_i + m_j) to *ordered.
+void survey_pairs_count(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, const PairUnits &u,
+                        double r0, double r_split, int64_t *cnt_a, int64_t *cnt_b, unsigned long long *ordered);
+void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, const PairUnits &u,
+                        double r0, double r_split, double scale, const int64_t *off_a, const int64_t *off_b,
+                        int64_t base_a, int64_t base_b, int64_t n_a, int64_t u0, int64_t u1, PkPairs out);
 
 // Pair-weight sweep: adds E'_l(e) = sum c_l k_e^3 G_l(k_e r) into
 // partial[nwaves][n_ell][n_edges] (zeroed by the caller before the first

@@ -4,10 +4,12 @@
 // cell with i < j, and 13 forward neighbours with all i, j), each neighbour
 // carrying its periodic image shift.  Pairs are compacted wave-by-wave
 // (ballot + popcount) into a coalesced stream (r, mu, w_i w_j m_ij) in double
-// precision, written in a deterministic order: a count pass sizes each home
-// cell's output, an exclusive scan gives offsets, and a write pass repeats the
-// same tests.  The home cell and each neighbour are staged through LDS in
-// tiles of 64 points, and a tile pair's candidates are packed 64 per step.
+// precision, written in a deterministic order: a count pass sizes the output
+// of each work unit (a home cell's tile of up to 64 points, one workgroup
+// each, so a dense cell spreads over many workgroups), an exclusive scan gives
+// offsets, and a write pass repeats the same tests.  The home tile and each
+// neighbour are staged through LDS in tiles of 64 points, and a tile pair's
+// candidates are packed 64 per step.
 //
 // Pairs are written in two buckets: r < r_split first, then the rest.  With
 // r_split = u_switch / k_min no pair of the second bucket ever takes the
@@ -79,13 +81,19 @@ __device__ inline uint32_t small_div(uint32_t q, uint32_t d, float inv_d) {
 // (all 27 neighbours, every pair once).
 enum PairMode { kPeriodic = 0, kSurveySelf = 1, kSurveyCross = 2 };
 
+// One workgroup (one wave) per work unit: a home cell's tile of up to
+// kPairTile points against the home cell and its stencil neighbours.  Units
+// are ordered by home cell, then tile, so the stream order is the same for
+// any number of units per launch, and a dense cell is spread over as many
+// workgroups as it has tiles.
 template <bool WRITE, int MODE>
 __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, double L, double r02, double rs2,
-                                                 int los, double scale, int64_t *__restrict__ cnt_a,
-                                                 int64_t *__restrict__ cnt_b,
+                                                 int los, double scale, const int *__restrict__ unit_cell,
+                                                 const int *__restrict__ unit_tile, int64_t u0,
+                                                 int64_t *__restrict__ cnt_a, int64_t *__restrict__ cnt_b,
                                                  unsigned long long *__restrict__ ordered,
                                                  const int64_t *__restrict__ off_a, const int64_t *__restrict__ off_b,
-                                                 int64_t base_a, int64_t base_b, int64_t n_a, int64_t c0,
+                                                 int64_t base_a, int64_t base_b, int64_t n_a,
                                                  double *__restrict__ out_r, double *__restrict__ out_mu,
                                                  double *__restrict__ out_ww) {
   // home-cell and neighbour-cell tiles of kPairTile points in LDS; the
@@ -94,18 +102,19 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
   __shared__ double jx[kPairTile], jy[kPairTile], jz[kPairTile], jw[kPairTile];
   __shared__ int hm[kPairTile], jm[kPairTile];
   constexpr int kStencil = MODE == kSurveyCross ? 27 : 14;
-  const int64_t cell = c0 + blockIdx.x;
+  const int64_t unit = u0 + blockIdx.x;
+  const int64_t cell = unit_cell[unit];
   const int lane = threadIdx.x;
   const int cz = int(cell % nc), cy = int((cell / nc) % nc), cx = int(cell / (int64_t(nc) * nc));
   const int64_t hs = a.cell_start[cell];
   const int ni = int(a.cell_start[cell + 1] - hs);
   int64_t written_a = 0, written_b = 0;
   unsigned long long ord = 0;
-  const int64_t wbase_a = WRITE ? off_a[cell] - base_a : 0;
-  const int64_t wbase_b = WRITE ? n_a + off_b[cell] - base_b : 0;
-  for (int i0 = 0; i0 < ni; i0 += kPairTile) {
+  const int64_t wbase_a = WRITE ? off_a[unit] - base_a : 0;
+  const int64_t wbase_b = WRITE ? n_a + off_b[unit] - base_b : 0;
+  {
+    const int i0 = unit_tile[unit] * kPairTile;
     const int ti = ni - i0 < kPairTile ? ni - i0 : kPairTile;
-    __syncthreads();
     if (lane < ti) {
       const int64_t i = hs + i0 + lane;
       hx[lane] = a.x[i];
@@ -205,61 +214,98 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
   if (!WRITE) {
     for (int o = 32; o > 0; o >>= 1) ord += __shfl_xor(ord, o);
     if (lane == 0) {
-      cnt_a[cell] = written_a;
-      cnt_b[cell] = written_b;
+      cnt_a[unit] = written_a;
+      cnt_b[unit] = written_b;
       if (ord) atomicAdd(ordered, ord);
     }
   }
 }
 
-void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_split, int64_t *cnt_a,
-                    int64_t *cnt_b, unsigned long long *ordered) {
+// Tiles per cell of catalogue `a` (at least one for a non-empty cell).
+__global__ void k_unit_tiles(const int64_t *__restrict__ cell_start, int64_t ncells, int64_t *__restrict__ tiles) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  tiles[c] = (cell_start[c + 1] - cell_start[c] + kPairTile - 1) / kPairTile;
+}
+
+// unit_cell[u], unit_tile[u] for the units [base[c], base[c + 1]) of cell c.
+__global__ void k_unit_fill(const int64_t *__restrict__ base, int64_t ncells, int *__restrict__ unit_cell,
+                            int *__restrict__ unit_tile) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  for (int64_t u = base[c], t = 0; u < base[c + 1]; ++u, ++t) {
+    unit_cell[u] = int(c);
+    unit_tile[u] = int(t);
+  }
+}
+
+PairUnits make_pair_units(Ctx &c, const Sorted &a, const Grid &g) {
   const int64_t ncells = g.ncells();
-  k_pk_pairs<false, kPeriodic><<<dim3(unsigned(ncells)), dim3(64), 0, c.stream>>>(
-      s, s, g.nc, g.L, r0 * r0, r_split * r_split, 2, 1.0, cnt_a, cnt_b, ordered, nullptr, nullptr, 0, 0, 0, 0,
-      nullptr, nullptr, nullptr);
+  int64_t *tiles = static_cast<int64_t *>(ensure(c, c.unit_tiles, size_t(ncells) * 8));
+  int64_t *base = static_cast<int64_t *>(ensure(c, c.unit_base, size_t(ncells + 1) * 8));
+  const unsigned nb = unsigned((ncells + 255) / 256);
+  k_unit_tiles<<<nb, 256, 0, c.stream>>>(a.cell_start, ncells, tiles);
+  scan_i64(c, tiles, base, ncells, c.pair_total);
+  int64_t total = 0;
+  HIPSTER_HIP(hipMemcpyAsync(&total, base + ncells, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  PairUnits u;
+  u.n = total;
+  u.cell = static_cast<int *>(ensure(c, c.unit_cell, size_t(std::max<int64_t>(total, 1)) * 4));
+  u.tile = static_cast<int *>(ensure(c, c.unit_tile, size_t(std::max<int64_t>(total, 1)) * 4));
+  if (total > 0) k_unit_fill<<<nb, 256, 0, c.stream>>>(base, ncells, u.cell, u.tile);
+  HIPSTER_HIP(hipGetLastError());
+  return u;
+}
+
+void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, const PairUnits &u, double r0, double r_split,
+                    int64_t *cnt_a, int64_t *cnt_b, unsigned long long *ordered) {
+  if (u.n <= 0) return;
+  k_pk_pairs<false, kPeriodic><<<dim3(unsigned(u.n)), dim3(64), 0, c.stream>>>(
+      s, s, g.nc, g.L, r0 * r0, r_split * r_split, 2, 1.0, u.cell, u.tile, 0, cnt_a, cnt_b, ordered, nullptr,
+      nullptr, 0, 0, 0, nullptr, nullptr, nullptr);
   HIPSTER_HIP(hipGetLastError());
 }
 
-void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, double r0, double r_split, int los,
+void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, const PairUnits &u, double r0, double r_split, int los,
                     const int64_t *off_a, const int64_t *off_b, int64_t base_a, int64_t base_b, int64_t n_a,
-                    int64_t c0, int64_t c1, PkPairs out) {
-  if (c1 <= c0) return;
-  const dim3 grid(unsigned(c1 - c0));
-  k_pk_pairs<true, kPeriodic><<<grid, dim3(64), 0, c.stream>>>(
-      s, s, g.nc, g.L, r0 * r0, r_split * r_split, los, 1.0, nullptr, nullptr, nullptr, off_a, off_b, base_a, base_b,
-      n_a, c0, out.r, static_cast<double *>(out.mu), static_cast<double *>(out.ww));
+                    int64_t u0, int64_t u1, PkPairs out) {
+  if (u1 <= u0) return;
+  k_pk_pairs<true, kPeriodic><<<dim3(unsigned(u1 - u0)), dim3(64), 0, c.stream>>>(
+      s, s, g.nc, g.L, r0 * r0, r_split * r_split, los, 1.0, u.cell, u.tile, u0, nullptr, nullptr, nullptr, off_a,
+      off_b, base_a, base_b, n_a, out.r, static_cast<double *>(out.mu), static_cast<double *>(out.ww));
   HIPSTER_HIP(hipGetLastError());
 }
 
-void survey_pairs_count(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, double r0,
-                        double r_split, int64_t *cnt_a, int64_t *cnt_b, unsigned long long *ordered) {
-  const dim3 grid(unsigned(g.ncells()));
+void survey_pairs_count(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, const PairUnits &u,
+                        double r0, double r_split, int64_t *cnt_a, int64_t *cnt_b, unsigned long long *ordered) {
+  if (u.n <= 0) return;
+  const dim3 grid(unsigned(u.n));
   if (cross)
     k_pk_pairs<false, kSurveyCross><<<grid, dim3(64), 0, c.stream>>>(
-        a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, cnt_a, cnt_b, ordered, nullptr, nullptr, 0, 0, 0, 0,
-        nullptr, nullptr, nullptr);
+        a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, u.cell, u.tile, 0, cnt_a, cnt_b, ordered, nullptr,
+        nullptr, 0, 0, 0, nullptr, nullptr, nullptr);
   else
     k_pk_pairs<false, kSurveySelf><<<grid, dim3(64), 0, c.stream>>>(
-        a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, cnt_a, cnt_b, ordered, nullptr, nullptr, 0, 0, 0, 0,
-        nullptr, nullptr, nullptr);
+        a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, u.cell, u.tile, 0, cnt_a, cnt_b, ordered, nullptr,
+        nullptr, 0, 0, 0, nullptr, nullptr, nullptr);
   HIPSTER_HIP(hipGetLastError());
 }
 
-void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, double r0,
-                        double r_split, double scale, const int64_t *off_a, const int64_t *off_b, int64_t base_a,
-                        int64_t base_b, int64_t n_a, int64_t c0, int64_t c1, PkPairs out) {
-  if (c1 <= c0) return;
-  const dim3 grid(unsigned(c1 - c0));
+void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, const PairUnits &u,
+                        double r0, double r_split, double scale, const int64_t *off_a, const int64_t *off_b,
+                        int64_t base_a, int64_t base_b, int64_t n_a, int64_t u0, int64_t u1, PkPairs out) {
+  if (u1 <= u0) return;
+  const dim3 grid(unsigned(u1 - u0));
   double *mu = static_cast<double *>(out.mu), *ww = static_cast<double *>(out.ww);
   if (cross)
     k_pk_pairs<true, kSurveyCross><<<grid, dim3(64), 0, c.stream>>>(
-        a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, nullptr, nullptr, nullptr, off_a, off_b, base_a,
-        base_b, n_a, c0, out.r, mu, ww);
+        a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, u.cell, u.tile, u0, nullptr, nullptr, nullptr, off_a,
+        off_b, base_a, base_b, n_a, out.r, mu, ww);
   else
     k_pk_pairs<true, kSurveySelf><<<grid, dim3(64), 0, c.stream>>>(
-        a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, nullptr, nullptr, nullptr, off_a, off_b, base_a,
-        base_b, n_a, c0, out.r, mu, ww);
+        a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, u.cell, u.tile, u0, nullptr, nullptr, nullptr, off_a,
+        off_b, base_a, base_b, n_a, out.r, mu, ww);
   HIPSTER_HIP(hipGetLastError());
 }
 
