@@ -139,3 +139,18 @@ def test_full_size_large_weighted_box_subset():
     mask = np.zeros(wl.n, np.uint8)
     mask[np.random.default_rng(2).choice(wl.n, 64, replace=False)] = 1
     run_case(wl.pos, wl.weights, wl.box, wl.r0, wl.k_edges_p, wl.ell_max_p, "mixed", mask=mask)
+
+
+# (ell_max, number of edges) pairs that make the host pick each compiled
+# chunk size of the far-pair kernel: 11, 16, 21 edges for up to three
+# multipoles, 8, 11, 14 for four; the edge counts leave ragged last chunks
+# (padding), and 129 edges is the largest binning (128 bins).
+CHUNK_CASES = [(0, 7), (2, 13), (4, 19), (4, 11), (2, 34), (0, 16), (6, 5), (6, 10), (6, 13), (6, 27), (4, 129)]
+
+
+@pytest.mark.parametrize("ell_max,n_edges", CHUNK_CASES)
+def test_far_kernel_chunk_sizes(ell_max, n_edges):
+    # k_0 = 1 puts the far bucket at r >= 8 inside R0 = 20, so both sweep
+    # kernels run; mixed form against the FP64 oracle
+    pos = synthetic.thomas(3000, 200.0, 10, 2.0, 3.0, 21, np.float32)
+    run_case(pos, None, 200.0, 20.0, np.geomspace(1.0, 6.0, n_edges), ell_max, "mixed")
