@@ -26,9 +26,10 @@
  *
  * Parity status: every function below is pinned by tests against mpmath or
  * scipy evaluations, closed forms, brute-force triple sums or exact
- * expectations of random catalogues (see tests/test_oracle_*.py), except the
- * clustered bispectrum, which is pinned only by the brute-force triple sum and
- * invariances ("parity unpinned" for a clustered closed form).
+ * expectations of random catalogues (see tests/test_oracle_*.py).  For
+ * clustered catalogues the bispectrum's pin is the brute-force sum over
+ * distinct triples (run on a clustered catalogue) and the invariances; no
+ * closed-form expectation is derived for them.
  */
 #include <complex.h>
 #include <math.h>
