@@ -96,8 +96,10 @@ __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIP
         if (e < e_end) {
           const double u = k_e[e] * r;
           Gv<double, NE> G;
-          if constexpr (FP64) G = G_fp64<NE, 2>(u);
-          else G = G_mixed_w<NE, 2>(u, inv_k[e] * inv_r, tab);
+          // the Taylor branch inline (measured faster), except with four
+          // multipoles, where it would spill
+          if constexpr (FP64) G = G_fp64<NE, 2, true>(u);
+          else G = G_mixed_w<NE, 2, kSinCosTab, (NE <= 3)>(u, inv_k[e] * inv_r, tab);
           const double s3 = k3[e];
 #pragma unroll
           for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i] * s3, acc[i][cc]);
@@ -334,8 +336,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_pk_tasks(const double *__restri
           if (e < e_end) {
             const double u = edges[e] * r;
             Gv<double, NE> G;
-            if constexpr (FP64) G = G_fp64<NE, 2>(u);
-            else G = G_mixed<NE, 2>(u, tab);
+            if constexpr (FP64) G = G_fp64<NE, 2, true>(u);
+            else G = G_mixed<NE, 2, false>(u, tab);  // inline Taylor would cost this kernel an occupancy level
 #pragma unroll
             for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], G.v[i], acc[i][cc]);
           }

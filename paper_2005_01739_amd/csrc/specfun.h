@@ -128,10 +128,12 @@ struct Gv {
   T v[NL];
 };
 
-// Taylor branch in double precision (u < U_BIG); kept out of line so that
-// the kernels' edge loops stay compact.
+// Taylor branch in double precision (u < U_BIG).  INL selects where it is
+// compiled: inline in the caller (the power-spectrum kernels, measured
+// faster), or out of line (the bispectrum kernel, whose registers the inline
+// form would overflow into the accumulation registers).
 template <int NL, int LSTEP>
-__device__ __noinline__ Gv<double, NL> G_taylor64(double u) {
+__device__ __forceinline__ Gv<double, NL> G_taylor64_inl(double u) {
   Gv<double, NL> G;
   double v = u * u, ul = 1.0;
   // 14 terms reach 1e-17 relative for u < 2; 32 terms for u < U_BIG.
@@ -147,10 +149,21 @@ __device__ __noinline__ Gv<double, NL> G_taylor64(double u) {
   return G;
 }
 
-// ----------------------------------------------------------- FP64 form
 template <int NL, int LSTEP>
+__device__ __noinline__ Gv<double, NL> G_taylor64_call(double u) {
+  return G_taylor64_inl<NL, LSTEP>(u);
+}
+
+template <int NL, int LSTEP, bool INL>
+__device__ inline Gv<double, NL> G_taylor64(double u) {
+  if constexpr (INL) return G_taylor64_inl<NL, LSTEP>(u);
+  else return G_taylor64_call<NL, LSTEP>(u);
+}
+
+// ----------------------------------------------------------- FP64 form
+template <int NL, int LSTEP, bool INL = false>
 __device__ __noinline__ Gv<double, NL> G_fp64(double u) {
-  if (u < HIPSTER_U_BIG) return G_taylor64<NL, LSTEP>(u);
+  if (u < HIPSTER_U_BIG) return G_taylor64<NL, LSTEP, INL>(u);
   Gv<double, NL> G;
   double s, c;
   sincos(u, &s, &c);
@@ -229,10 +242,10 @@ __device__ inline float horner32(const float (&p)[N], float t) {
 // single precision, since they enter multiplied by c_l / u and need only
 // ~1e-8 relative accuracy.  Below u = 2 G_l is summed from its Taylor series.
 // wd = 1/u, supplied by the caller (from per-pair 1/r and per-edge 1/k).
-template <int NL, int LSTEP, int NTAB = kSinCosTab>
+template <int NL, int LSTEP, int NTAB = kSinCosTab, bool INL = false>
 __device__ inline Gv<double, NL> G_mixed_w(double u, double wd, const double2 *__restrict__ tab) {
   constexpr bool kNeedSi = (NL - 1) * LSTEP >= 2;  // some even l >= 2 is requested
-  if (u < kUSmall) return G_taylor64<NL, LSTEP>(u);
+  if (u < kUSmall) return G_taylor64<NL, LSTEP, INL>(u);
   Gv<double, NL> G;
   double s, c;
   sincos_tab<NTAB>(u, tab, s, c);
@@ -299,13 +312,13 @@ __device__ inline Gv<double, NL> Dt_far_mixed(double u, double wd, const double2
   return D;
 }
 
-template <int NL, int LSTEP>
+template <int NL, int LSTEP, bool INL = false>
 __device__ inline Gv<double, NL> G_mixed(double u, const double2 *__restrict__ tab) {
   // 1/u from the single-precision reciprocal and two Newton steps (~1e-16)
   double wd = double(__builtin_amdgcn_rcpf(float(u)));
   wd = wd * fma(-u, wd, 2.0);
   wd = wd * fma(-u, wd, 2.0);
-  return G_mixed_w<NL, LSTEP>(u, wd, tab);
+  return G_mixed_w<NL, LSTEP, kSinCosTab, INL>(u, wd, tab);
 }
 
 }  // namespace hipster
