@@ -223,7 +223,7 @@ static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t nunits, CountF &&cou
       hipEvent_t b = tm.mark();
       // near bucket (or every pair) through the general kernel, the far
       // bucket through the far kernel
-      const int64_t n_gen = far_ok && !fp64 ? n_a : np;
+      const int64_t n_gen = far_ok ? n_a : np;
       pk_sweep_general(c, pp, n_gen, n_ell, fp64, r0, edges, n_edges, partial, nwaves);
       hipEvent_t m = tm.mark();
       if (n_gen < np) {
@@ -231,7 +231,7 @@ static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t nunits, CountF &&cou
         far.r = pp.r + n_gen;
         far.mu = static_cast<double *>(pp.mu) + n_gen;
         far.ww = static_cast<double *>(pp.ww) + n_gen;
-        pk_sweep_far(c, far, np - n_gen, n_ell, r0, edges, n_edges, partial, nwaves);
+        pk_sweep_far(c, far, np - n_gen, n_ell, fp64, r0, edges, n_edges, partial, nwaves);
       }
       hipEvent_t d = tm.mark();
       HIPSTER_HIP(hipEventSynchronize(d));

@@ -164,12 +164,12 @@ void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, co
 // Pair-weight sweep: adds E'_l(e) = sum c_l k_e^3 G_l(k_e r) into
 // partial[nwaves][n_ell][n_edges] (zeroed by the caller before the first
 // chunk).  `ek` is the device edge table (k_e, 1/k_e, k_e^3, doubles).  The
-// general kernel takes any pairs; the far kernel (mixed form) only pairs with
-// r >= U_BIG / k_0 and k_0 > 0.
+// general kernel takes any pairs; the far kernel (either form) only pairs
+// with r >= U_BIG / k_0 and k_0 > 0.
 void pk_sweep_general(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0, const double *ek,
                       int n_edges, double *partial, int nwaves);
-void pk_sweep_far(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, double r0, const double *ek, int n_edges,
-                  double *partial, int nwaves);
+void pk_sweep_far(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0, const double *ek,
+                  int n_edges, double *partial, int nwaves);
 int pk_sweep_waves(Ctx &c);
 void pk_sweep_tasks(Ctx &c, const PkPairs &p, const PkTask *tasks, int ntasks, int *counter, const double *edges,
                     const BoxSweep *boxes, int cols, double *rows, int n_ell, bool fp64, int nwaves);

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIP
 // sine/cosine table and the edges' (k, 1/k) are staged in LDS; the next pair's
 // values are loaded one iteration ahead (the last iteration reloads its own
 // pair) and each edge's (k, 1/k) one edge ahead.
-template <int NE, int CH>
+template <int NE, int CH, bool FP64>
 __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIPSTER_PK_WAVES_PER_EU))) void k_pk_far(
     const double *__restrict__ pr, const double *__restrict__ pmu, const double *__restrict__ pww, int64_t npairs,
     double inv_r0, const double *__restrict__ ek, int n_edges, double *__restrict__ partial) {
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(HIP
         const double2 kc = kk;
         const int en = e0 + cc + 1 < e_end ? e0 + cc + 1 : e_end - 1;
         kk = ekk[en];
-        const Gv<double, NE> D = Dt_far_mixed<NE, 2>(kc.x * r, kc.y * inv_r, tab);
+        const Gv<double, NE> D = Dt_far<NE, 2, FP64>(kc.x * r, kc.y * inv_r, tab);
 #pragma unroll
         for (int i = 0; i < NE; ++i) acc[i][cc] = fma(cf[i], D.v[i], acc[i][cc]);
       }
@@ -212,25 +212,28 @@ static void launch_general(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, 
 }
 
 template <int NE, int CH>
-static void launch_far_ch(Ctx &c, const PkPairs &p, int64_t npairs, double inv_r0, const double *ek, int n_edges,
-                          double *partial, int nwaves) {
+static void launch_far_ch(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, double inv_r0, const double *ek,
+                          int n_edges, double *partial, int nwaves) {
   const double *mu = static_cast<const double *>(p.mu), *ww = static_cast<const double *>(p.ww);
-  k_pk_far<NE, CH><<<dim3(unsigned(nwaves / 4)), dim3(kSweepBlock), 0, c.stream>>>(p.r, mu, ww, npairs, inv_r0, ek,
-                                                                                     n_edges, partial);
+  const dim3 grid(unsigned(nwaves / 4)), block(kSweepBlock);
+  if (fp64)
+    k_pk_far<NE, CH, true><<<grid, block, 0, c.stream>>>(p.r, mu, ww, npairs, inv_r0, ek, n_edges, partial);
+  else
+    k_pk_far<NE, CH, false><<<grid, block, 0, c.stream>>>(p.r, mu, ww, npairs, inv_r0, ek, n_edges, partial);
   HIPSTER_HIP(hipGetLastError());
 }
 
 template <int NE>
-static void launch_far(Ctx &c, const PkPairs &p, int64_t npairs, double inv_r0, const double *ek, int n_edges,
-                       double *partial, int nwaves) {
+static void launch_far(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, double inv_r0, const double *ek,
+                       int n_edges, double *partial, int nwaves) {
   constexpr bool four = NE >= 4;
   constexpr int c0 = four ? kChunksMixed4[0] : kChunksMixed3[0];
   constexpr int c1 = four ? kChunksMixed4[1] : kChunksMixed3[1];
   constexpr int c2 = four ? kChunksMixed4[2] : kChunksMixed3[2];
   const int ch = pick_chunk(four ? kChunksMixed4 : kChunksMixed3, n_edges);
-  if (ch == c0) launch_far_ch<NE, c0>(c, p, npairs, inv_r0, ek, n_edges, partial, nwaves);
-  else if (ch == c1) launch_far_ch<NE, c1>(c, p, npairs, inv_r0, ek, n_edges, partial, nwaves);
-  else launch_far_ch<NE, c2>(c, p, npairs, inv_r0, ek, n_edges, partial, nwaves);
+  if (ch == c0) launch_far_ch<NE, c0>(c, p, npairs, fp64, inv_r0, ek, n_edges, partial, nwaves);
+  else if (ch == c1) launch_far_ch<NE, c1>(c, p, npairs, fp64, inv_r0, ek, n_edges, partial, nwaves);
+  else launch_far_ch<NE, c2>(c, p, npairs, fp64, inv_r0, ek, n_edges, partial, nwaves);
 }
 
 void pk_sweep_general(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0, const double *ek,
@@ -246,16 +249,16 @@ void pk_sweep_general(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool 
   }
 }
 
-void pk_sweep_far(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, double r0, const double *ek, int n_edges,
-                  double *partial, int nwaves) {
+void pk_sweep_far(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0, const double *ek,
+                  int n_edges, double *partial, int nwaves) {
   if (npairs <= 0) return;
   if (n_edges < 1 || n_edges > kMaxNk + 1) throw Error{HIPSTER_EINVAL, "sweep: edge count out of range"};
   const double inv = 1.0 / r0;
   switch (n_ell) {
-    case 1: launch_far<1>(c, p, npairs, inv, ek, n_edges, partial, nwaves); break;
-    case 2: launch_far<2>(c, p, npairs, inv, ek, n_edges, partial, nwaves); break;
-    case 3: launch_far<3>(c, p, npairs, inv, ek, n_edges, partial, nwaves); break;
-    default: launch_far<4>(c, p, npairs, inv, ek, n_edges, partial, nwaves); break;
+    case 1: launch_far<1>(c, p, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
+    case 2: launch_far<2>(c, p, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
+    case 3: launch_far<3>(c, p, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
+    default: launch_far<4>(c, p, npairs, fp64, inv, ek, n_edges, partial, nwaves); break;
   }
 }
 

@@ -108,17 +108,13 @@ __device__ inline T Dt_closed(int l, T u, T w, T s, T c, T si) {
   }
 }
 
-// Clenshaw sum of a Chebyshev series at x in [-1, 1].
+// Horner sum of a polynomial with double coefficients.
 template <int N>
-__device__ inline double clenshaw(const double (&c)[N], double x) {
-  double b1 = 0.0, b2 = 0.0, x2 = 2.0 * x;
+__device__ inline double horner64(const double (&p)[N], double t) {
+  double r = p[N - 1];
 #pragma unroll
-  for (int k = N - 1; k >= 1; --k) {
-    double b0 = fma(x2, b1, c[k] - b2);
-    b2 = b1;
-    b1 = b0;
-  }
-  return fma(x, b1, c[0] - b2);
+  for (int k = N - 2; k >= 0; --k) r = fma3(r, t, p[k]);
+  return r;
 }
 
 // Values G_l(u) for l = 0, LSTEP, 2 LSTEP, ... (NL of them), returned in
@@ -168,9 +164,9 @@ __device__ __noinline__ Gv<double, NL> G_fp64(double u) {
   double s, c;
   sincos(u, &s, &c);
   double w = 1.0 / u;
-  double x = 2.0 * HIPSTER_U_BIG * w - 1.0;
-  double f = clenshaw(CHEB_F64, x) * w;
-  double g = clenshaw(CHEB_G64, x) * w * w;
+  double t = HIPSTER_U_BIG * w;
+  double f = horner64(POLY_F64, t) * w;
+  double g = horner64(POLY_G64, t) * w * w;
   double si = kHalfPi - f * c - g * s;
   double w3 = w * w * w;
 #pragma unroll
@@ -200,7 +196,7 @@ __device__ inline void stage_sincos_tab(double2 *tab) {
   for (int i = threadIdx.x; i < N; i += blockDim.x)
     tab[i] = make_double2(SINCOS_TAB[i * (256 / N)][0], SINCOS_TAB[i * (256 / N)][1]);
 }
-template <int N = kSinCosTab>
+template <int N = kSinCosTab, bool FULL = false>
 __device__ inline void sincos_tab(double u, const double2 *__restrict__ tab, double &s, double &c) {
   constexpr double kScale = 256.0 / N;  // a power of two: the scalings are exact
   constexpr double kRound = 6755399441055744.0;  // 1.5 * 2^52
@@ -211,7 +207,11 @@ __device__ inline void sincos_tab(double u, const double2 *__restrict__ tab, dou
   const double2 sc = tab[__double2loint(big) & (N - 1)];
   const double x2 = x * x;
   double sx, cx;
-  if constexpr (N == 256) {
+  if constexpr (N == 256 && FULL) {
+    // the FP64 form: sin x through x^7, cos x through x^6 (truncation < 1e-20)
+    sx = fma(x * x2, fma3(x2, fma3(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), x);
+    cx = fma3(x2, fma3(x2, fma3(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+  } else if constexpr (N == 256) {
     sx = fma(x * x2, fma3(x2, 1.0 / 120.0, -1.0 / 6.0), x);
     cx = fma3(x2, fma3(x2, 1.0 / 24.0, -0.5), 1.0);
   } else {
@@ -278,15 +278,23 @@ __device__ inline Gv<double, NL> G_mixed_w(double u, double wd, const double2 *_
 // single-precision rounding) rather than t = U_BIG w: f = w P(t) = w P''(w),
 // g = w^2 Q(t) = w^2 Q''(w) with P''_k = P_k U_BIG^k, Q''_k = Q_k U_BIG^k
 // (exact scalings by powers of two for U_BIG = 8).
-template <int NL, int LSTEP>
-__device__ inline Gv<double, NL> Dt_far_mixed(double u, double wd, const double2 *__restrict__ tab) {
+// FP64 = true gives the FP64 form of the same path: sin and cos from the table
+// with longer remainder polynomials, f and g from their 22-term double
+// fits (as G_fp64).
+template <int NL, int LSTEP, bool FP64 = false>
+__device__ inline Gv<double, NL> Dt_far(double u, double wd, const double2 *__restrict__ tab) {
   constexpr bool kNeedSi = (NL - 1) * LSTEP >= 2;
   static_assert(HIPSTER_U_BIG == 8.0, "the coefficient scalings assume U_BIG = 8");
   Gv<double, NL> D;
   double s, c;
-  sincos_tab(u, tab, s, c);
+  sincos_tab<kSinCosTab, FP64>(u, tab, s, c);
   double si = 0.0;
-  if constexpr (kNeedSi) {
+  if constexpr (kNeedSi && FP64) {
+    const double t = HIPSTER_U_BIG * wd;
+    const double f = horner64(POLY_F64, t) * wd;
+    const double g = horner64(POLY_G64, t) * wd * wd;
+    si = kHalfPi - f * c - g * s;
+  } else if constexpr (kNeedSi) {
     const float wf = float(wd);
     float pf = POLY_F32[HIPSTER_N_POLY32 - 1] * float(1 << (3 * (HIPSTER_N_POLY32 - 1)));
     float pg = POLY_G32[HIPSTER_N_POLY32 - 1] * float(1 << (3 * (HIPSTER_N_POLY32 - 1)));
