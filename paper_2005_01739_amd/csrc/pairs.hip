@@ -50,12 +50,6 @@ __device__ inline int wrap_axis(int v, int nc, int &shift) {
   return v;
 }
 
-__device__ inline double image(double d, int shift, double L) {
-  // x_i - (x_j + shift * L), the neighbour image's offset; exact whenever the
-  // result is inside R0 <= L/2 (Sterbenz).
-  return shift > 0 ? d - L : (shift < 0 ? d + L : d);
-}
-
 __device__ inline double sq_norm_exact(double dx, double dy, double dz) {
 #pragma clang fp contract(off)
   double a = dx * dx;
@@ -86,7 +80,7 @@ enum PairMode { kPeriodic = 0, kSurveySelf = 1, kSurveyCross = 2 };
 // are ordered by home cell, then tile, so the stream order is the same for
 // any number of units per launch, and a dense cell is spread over as many
 // workgroups as it has tiles.
-template <bool WRITE, int MODE>
+template <bool WRITE, int MODE, bool MASKED>
 __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, double L, double r02, double rs2,
                                                  int los, double scale, const int *__restrict__ unit_cell,
                                                  const int *__restrict__ unit_tile, int64_t u0,
@@ -109,7 +103,8 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
   const int64_t hs = a.cell_start[cell];
   const int ni = int(a.cell_start[cell + 1] - hs);
   int64_t written_a = 0, written_b = 0;
-  unsigned long long ord = 0;
+  unsigned long long ord = 0;       // per lane, with masks
+  unsigned long long ord_w = 0;     // per wave, without masks
   const int64_t wbase_a = WRITE ? off_a[unit] - base_a : 0;
   const int64_t wbase_b = WRITE ? n_a + off_b[unit] - base_b : 0;
   {
@@ -121,7 +116,7 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
       hy[lane] = a.y[i];
       hz[lane] = a.z[i];
       hw[lane] = a.w[i];
-      hm[lane] = a.m ? int(a.m[i]) : 1;
+      if (MASKED) hm[lane] = a.m ? int(a.m[i]) : 1;
     }
     for (int st = 0; st < kStencil; ++st) {
       int ox, oy, oz, sx = 0, sy = 0, sz = 0, nx, ny, nz;
@@ -142,6 +137,10 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
         nz = cz + oz;
         if (nx < 0 || nx >= nc || ny < 0 || ny >= nc || nz < 0 || nz >= nc) continue;
       }
+      // the neighbour image's offset s L (s = -1, 0, 1), uniform over the
+      // stencil cell; (x_i - x_j) - s L is exact whenever the result lies
+      // inside R0 <= L/2 (Sterbenz)
+      const double offx = double(sx) * L, offy = double(sy) * L, offz = double(sz) * L;
       const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
       const int64_t js = b.cell_start[nb];
       const int nj = int(b.cell_start[nb + 1] - js);
@@ -157,7 +156,7 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
           jy[lane] = b.y[j];
           jz[lane] = b.z[j];
           jw[lane] = b.w[j];
-          jm[lane] = b.m ? int(b.m[j]) : 1;
+          if (MASKED) jm[lane] = b.m ? int(b.m[j]) : 1;
         }
         __syncthreads();
         const uint32_t total = uint32_t(ti) * uint32_t(tj);
@@ -169,13 +168,17 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
           if (q < total) {
             const uint32_t ii = small_div(q, uint32_t(tj), inv_tj), jj = q - ii * uint32_t(tj);
             if (!self || j0 + int(jj) > i0 + int(ii)) {
-              const double dx = image(hx[ii] - jx[jj], sx, L);
-              const double dy = image(hy[ii] - jy[jj], sy, L);
-              const double dz = image(hz[ii] - jz[jj], sz, L);
+              double dx = hx[ii] - jx[jj], dy = hy[ii] - jy[jj], dz = hz[ii] - jz[jj];
+              if constexpr (MODE == kPeriodic) {
+                dx -= offx;
+                dy -= offy;
+                dz -= offz;
+              }
               const double r2 = sq_norm_exact(dx, dy, dz);
               if (r2 < r02) {
-                const int mult = hm[ii] + jm[jj];
-                ord += unsigned(mult);
+                // without masks every pair counts twice (i, j) and (j, i)
+                const int mult = MASKED ? hm[ii] + jm[jj] : 2;
+                if (MASKED) ord += unsigned(mult);
                 if (mult > 0) {
                   hit = true;
                   near = r2 < rs2;
@@ -197,6 +200,7 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
             }
           }
           const unsigned long long bal_a = __ballot(hit && near), bal_b = __ballot(hit && !near);
+          if (!MASKED) ord_w += 2u * unsigned(__popcll(bal_a | bal_b));
           if (WRITE && hit) {
             const unsigned long long below = (1ull << lane) - 1ull;
             const int64_t k = near ? wbase_a + written_a + __popcll(bal_a & below)
@@ -212,7 +216,10 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
     }
   }
   if (!WRITE) {
-    for (int o = 32; o > 0; o >>= 1) ord += __shfl_xor(ord, o);
+    if (MASKED)
+      for (int o = 32; o > 0; o >>= 1) ord += __shfl_xor(ord, o);
+    else
+      ord = ord_w;
     if (lane == 0) {
       cnt_a[unit] = written_a;
       cnt_b[unit] = written_b;
@@ -258,23 +265,34 @@ PairUnits make_pair_units(Ctx &c, const Sorted &a, const Grid &g) {
   return u;
 }
 
+// One launch of the enumeration kernel, with the mask handling compiled in
+// only when a catalogue carries a mask.
+template <bool WRITE, int MODE, typename... Args>
+static void launch_pairs(Ctx &c, dim3 grid, const Sorted &a, const Sorted &b, Args... args) {
+  if (a.m || b.m)
+    k_pk_pairs<WRITE, MODE, true><<<grid, dim3(64), 0, c.stream>>>(a, b, args...);
+  else
+    k_pk_pairs<WRITE, MODE, false><<<grid, dim3(64), 0, c.stream>>>(a, b, args...);
+  HIPSTER_HIP(hipGetLastError());
+}
+
 void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, const PairUnits &u, double r0, double r_split,
                     int64_t *cnt_a, int64_t *cnt_b, unsigned long long *ordered) {
   if (u.n <= 0) return;
-  k_pk_pairs<false, kPeriodic><<<dim3(unsigned(u.n)), dim3(64), 0, c.stream>>>(
-      s, s, g.nc, g.L, r0 * r0, r_split * r_split, 2, 1.0, u.cell, u.tile, 0, cnt_a, cnt_b, ordered, nullptr,
-      nullptr, 0, 0, 0, nullptr, nullptr, nullptr);
-  HIPSTER_HIP(hipGetLastError());
+  launch_pairs<false, kPeriodic>(c, dim3(unsigned(u.n)), s, s, g.nc, g.L, r0 * r0, r_split * r_split, 2, 1.0,
+                                 u.cell, u.tile, int64_t(0), cnt_a, cnt_b, ordered, (const int64_t *)nullptr,
+                                 (const int64_t *)nullptr, int64_t(0), int64_t(0), int64_t(0), (double *)nullptr,
+                                 (double *)nullptr, (double *)nullptr);
 }
 
 void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, const PairUnits &u, double r0, double r_split, int los,
                     const int64_t *off_a, const int64_t *off_b, int64_t base_a, int64_t base_b, int64_t n_a,
                     int64_t u0, int64_t u1, PkPairs out) {
   if (u1 <= u0) return;
-  k_pk_pairs<true, kPeriodic><<<dim3(unsigned(u1 - u0)), dim3(64), 0, c.stream>>>(
-      s, s, g.nc, g.L, r0 * r0, r_split * r_split, los, 1.0, u.cell, u.tile, u0, nullptr, nullptr, nullptr, off_a,
-      off_b, base_a, base_b, n_a, out.r, static_cast<double *>(out.mu), static_cast<double *>(out.ww));
-  HIPSTER_HIP(hipGetLastError());
+  launch_pairs<true, kPeriodic>(c, dim3(unsigned(u1 - u0)), s, s, g.nc, g.L, r0 * r0, r_split * r_split, los, 1.0,
+                                u.cell, u.tile, u0, (int64_t *)nullptr, (int64_t *)nullptr,
+                                (unsigned long long *)nullptr, off_a, off_b, base_a, base_b, n_a, out.r,
+                                static_cast<double *>(out.mu), static_cast<double *>(out.ww));
 }
 
 void survey_pairs_count(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, const PairUnits &u,
@@ -282,14 +300,15 @@ void survey_pairs_count(Ctx &c, const Sorted &a, const Sorted &b, bool cross, co
   if (u.n <= 0) return;
   const dim3 grid(unsigned(u.n));
   if (cross)
-    k_pk_pairs<false, kSurveyCross><<<grid, dim3(64), 0, c.stream>>>(
-        a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, u.cell, u.tile, 0, cnt_a, cnt_b, ordered, nullptr,
-        nullptr, 0, 0, 0, nullptr, nullptr, nullptr);
+    launch_pairs<false, kSurveyCross>(c, grid, a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, u.cell, u.tile,
+                                      int64_t(0), cnt_a, cnt_b, ordered, (const int64_t *)nullptr,
+                                      (const int64_t *)nullptr, int64_t(0), int64_t(0), int64_t(0),
+                                      (double *)nullptr, (double *)nullptr, (double *)nullptr);
   else
-    k_pk_pairs<false, kSurveySelf><<<grid, dim3(64), 0, c.stream>>>(
-        a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, u.cell, u.tile, 0, cnt_a, cnt_b, ordered, nullptr,
-        nullptr, 0, 0, 0, nullptr, nullptr, nullptr);
-  HIPSTER_HIP(hipGetLastError());
+    launch_pairs<false, kSurveySelf>(c, grid, a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, u.cell, u.tile,
+                                     int64_t(0), cnt_a, cnt_b, ordered, (const int64_t *)nullptr,
+                                     (const int64_t *)nullptr, int64_t(0), int64_t(0), int64_t(0),
+                                     (double *)nullptr, (double *)nullptr, (double *)nullptr);
 }
 
 void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, const PairUnits &u,
@@ -299,14 +318,13 @@ void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, co
   const dim3 grid(unsigned(u1 - u0));
   double *mu = static_cast<double *>(out.mu), *ww = static_cast<double *>(out.ww);
   if (cross)
-    k_pk_pairs<true, kSurveyCross><<<grid, dim3(64), 0, c.stream>>>(
-        a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, u.cell, u.tile, u0, nullptr, nullptr, nullptr, off_a,
-        off_b, base_a, base_b, n_a, out.r, mu, ww);
+    launch_pairs<true, kSurveyCross>(c, grid, a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, u.cell, u.tile,
+                                     u0, (int64_t *)nullptr, (int64_t *)nullptr, (unsigned long long *)nullptr,
+                                     off_a, off_b, base_a, base_b, n_a, out.r, mu, ww);
   else
-    k_pk_pairs<true, kSurveySelf><<<grid, dim3(64), 0, c.stream>>>(
-        a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, u.cell, u.tile, u0, nullptr, nullptr, nullptr, off_a,
-        off_b, base_a, base_b, n_a, out.r, mu, ww);
-  HIPSTER_HIP(hipGetLastError());
+    launch_pairs<true, kSurveySelf>(c, grid, a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, u.cell, u.tile,
+                                    u0, (int64_t *)nullptr, (int64_t *)nullptr, (unsigned long long *)nullptr, off_a,
+                                    off_b, base_a, base_b, n_a, out.r, mu, ww);
 }
 
 }  // namespace hipster
