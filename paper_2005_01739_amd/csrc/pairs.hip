@@ -60,15 +60,6 @@ __device__ inline double sq_norm_exact(double dx, double dy, double dz) {
 
 constexpr int kPairTile = 64;  // points of a cell staged in LDS at a time
 
-// q / d for 0 <= q < 2^16 and 1 <= d <= kPairTile, from a single-precision
-// reciprocal and an exact correction.
-__device__ inline uint32_t small_div(uint32_t q, uint32_t d, float inv_d) {
-  uint32_t t = uint32_t(float(q) * inv_d);
-  if (t * d > q) --t;
-  else if ((t + 1) * d <= q) ++t;
-  return t;
-}
-
 // Enumeration modes: the periodic box (half stencil, image shifts, a fixed
 // line-of-sight axis); a survey catalogue with itself (half stencil, no
 // periodicity, midpoint line of sight); a survey catalogue against another
@@ -160,13 +151,19 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
         }
         __syncthreads();
         const uint32_t total = uint32_t(ti) * uint32_t(tj);
-        const float inv_tj = 1.0f / float(tj);
-        for (uint32_t q0 = 0; q0 < total; q0 += 64) {
+        // candidate q = ii * tj + jj of the tile pair; lanes advance by 64
+        // candidates per step, i.e. by (64 / tj, 64 % tj) with a carry
+        const uint32_t utj = uint32_t(tj), d64 = 64u / utj, r64 = 64u - d64 * utj;
+        uint32_t ii = uint32_t(lane) / utj, jj = uint32_t(lane) - ii * utj;
+        for (uint32_t q0 = 0; q0 < total; q0 += 64, ii += d64, jj += r64) {
+          if (jj >= utj) {
+            jj -= utj;
+            ++ii;
+          }
           const uint32_t q = q0 + lane;
           bool hit = false, near = false;
           double r = 0.0, mu = 0.0, ww = 0.0;
           if (q < total) {
-            const uint32_t ii = small_div(q, uint32_t(tj), inv_tj), jj = q - ii * uint32_t(tj);
             if (!self || j0 + int(jj) > i0 + int(ii)) {
               double dx = hx[ii] - jx[jj], dy = hy[ii] - jy[jj], dz = hz[ii] - jz[jj];
               if constexpr (MODE == kPeriodic) {
