@@ -64,6 +64,17 @@ def lib():
         L.oracle_bk_ell.argtypes = [ct.c_int64, _dp, _dp, ct.c_int64, _dp, _dp, ct.c_double,
                                     ct.c_double, ct.c_int, _dp, ct.c_int, _u8p, _u8p, _dp, _dp,
                                     _dp, _dp, _dp, _dp, _dp, _u64p, _u64p, ct.c_int]
+        L.oracle_eii.restype = ct.c_int
+        L.oracle_eii.argtypes = [ct.c_double, ct.c_double, ct.c_int, ct.c_int, _dp, _dp]
+        L.oracle_eii_table.restype = ct.c_int
+        L.oracle_eii_table.argtypes = [ct.c_double, ct.c_int, _dp, ct.c_int, ct.c_int, _dp, ct.c_int]
+        L.oracle_ddr2.restype = ct.c_int
+        L.oracle_ddr2.argtypes = [ct.c_int64, _dp, _dp, ct.c_double, ct.c_double, ct.c_int, _dp, ct.c_int,
+                                  ct.c_int, _dp, _u8p, _dp, _dp, _u64p, ct.c_int]
+        L.oracle_bk_ell_analytic.restype = ct.c_int
+        L.oracle_bk_ell_analytic.argtypes = [ct.c_int64, _dp, _dp, ct.c_double, ct.c_double, ct.c_int, _dp,
+                                             ct.c_int, ct.c_int, _dp, _u8p, _dp, _dp, _dp, _dp, _dp, _dp,
+                                             _dp, _u64p, _u64p, ct.c_int]
         _lib = L
     return _lib
 
@@ -196,4 +207,73 @@ def bk_ell(pos, w, rpos, rw, box, r0, k_edges, ell_max, mask_d=None, mask_r=None
     if rc != 0:
         raise ValueError("oracle_bk_ell: argument outside the oracle's range")
     out.update(s0=s0, wtilde=wt, n_pairs_dd=int(ndd.value), n_pairs_rd=int(nrd.value))
+    return out
+
+
+def eii(x, r0, ell, k_edges):
+    """E^{II,ab}_ell(x) of the analytic DDR^II term, [n_k, n_k]."""
+    k = _f64(k_edges)
+    n_k = k.size - 1
+    out = np.zeros((n_k, n_k))
+    if lib().oracle_eii(float(x), float(r0), int(ell), n_k, _ptr(k), _ptr(out)) != 0:
+        raise ValueError("oracle_eii: argument outside the oracle's range")
+    return out
+
+
+def eii_table(r0, k_edges, ell_max, n_x, nthreads=0):
+    """E^{II,ab}_ell on the nodes m 2 R0 / n_x, m = 0..n_x:
+    [ell_max+1, n_k, n_k, n_x+1]."""
+    k = _f64(k_edges)
+    n_k = k.size - 1
+    out = np.zeros((ell_max + 1, n_k, n_k, n_x + 1))
+    if lib().oracle_eii_table(float(r0), n_k, _ptr(k), int(ell_max), int(n_x), _ptr(out), int(nthreads)) != 0:
+        raise ValueError("oracle_eii_table: argument outside the oracle's range")
+    return out
+
+
+def ddr2(pos, w, box, r0, k_edges, ell_max, n_x, table=None, mask=None, nthreads=0):
+    """T^ab_ell = sum over ordered pairs i != j and periodic images inside 2 R0
+    of w_i w_j E^{II,ab}_ell (interpolated table).  Returns a dict with t2,
+    l1 ([ell_max+1, n_k, n_k]), n_pairs and the table used."""
+    pos = _f64(pos).reshape(-1, 3)
+    w = _f64(w)
+    k = _f64(k_edges)
+    n_k = k.size - 1
+    tab = eii_table(r0, k, ell_max, n_x, nthreads) if table is None else _f64(table)
+    shp = (ell_max + 1, n_k, n_k)
+    T = np.zeros(shp)
+    l1 = np.zeros(shp)
+    npairs = ct.c_uint64(0)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    rc = lib().oracle_ddr2(pos.shape[0], _ptr(pos), _ptr(w), float(box), float(r0), n_k, _ptr(k),
+                           int(ell_max), int(n_x), _ptr(tab), _ptr(m, _u8p), _ptr(T), _ptr(l1),
+                           ct.byref(npairs), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_ddr2: argument outside the oracle's range")
+    return {"t2": T, "l1": l1, "n_pairs": int(npairs.value), "table": tab}
+
+
+def bk_ell_analytic(pos, w, box, r0, k_edges, ell_max, n_x, table=None, mask_d=None, nthreads=0):
+    """B^ab_ell with the DDR^II term from the E^II kernel (no randoms).
+    Returns a dict with bk, gd, cd, t2, t2_l1 ([ell_max+1, n_k, n_k]), s0,
+    wtilde [n_k], n_pairs_dd (inside R0), n_pairs_2r0 and the table."""
+    pos = _f64(pos).reshape(-1, 3)
+    w = _f64(w)
+    k = _f64(k_edges)
+    n_k = k.size - 1
+    tab = eii_table(r0, k, ell_max, n_x, nthreads) if table is None else _f64(table)
+    shp = (ell_max + 1, n_k, n_k)
+    out = {name: np.zeros(shp) for name in ("bk", "gd", "cd", "t2", "t2_l1")}
+    s0 = np.zeros(n_k)
+    wt = np.zeros(n_k)
+    ndd = ct.c_uint64(0)
+    n2 = ct.c_uint64(0)
+    md = None if mask_d is None else np.ascontiguousarray(mask_d, dtype=np.uint8)
+    rc = lib().oracle_bk_ell_analytic(pos.shape[0], _ptr(pos), _ptr(w), float(box), float(r0), n_k, _ptr(k),
+                                      int(ell_max), int(n_x), _ptr(tab), _ptr(md, _u8p), _ptr(out["bk"]),
+                                      _ptr(out["gd"]), _ptr(out["cd"]), _ptr(out["t2"]), _ptr(out["t2_l1"]),
+                                      _ptr(s0), _ptr(wt), ct.byref(ndd), ct.byref(n2), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_bk_ell_analytic: argument outside the oracle's range")
+    out.update(s0=s0, wtilde=wt, n_pairs_dd=int(ndd.value), n_pairs_2r0=int(n2.value), table=tab)
     return out

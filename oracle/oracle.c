@@ -29,7 +29,11 @@
  * expectations of random catalogues (see tests/test_oracle_*.py).  For
  * clustered catalogues the bispectrum's pin is the brute-force sum over
  * distinct triples (run on a clustered catalogue) and the invariances; no
- * closed-form expectation is derived for them.
+ * closed-form expectation is derived for them.  The analytic DDR^II kernel
+ * (oracle_eii) is pinned against the 3-D definition integrated by scipy in
+ * other coordinates, its exact volume integral and its x -> 0 limit; the pair
+ * sum over its interpolated table (oracle_ddr2) against random primaries on a
+ * fine lattice and against per-pair kernel values.
  */
 #include <complex.h>
 #include <math.h>
@@ -707,4 +711,292 @@ int oracle_bk_ell(int64_t n, const double *pos, const double *w, int64_t n_r,
     if (n_pairs_rd) *n_pairs_rd = crd;
     free(GD); free(CD); free(GR); free(CR); free(S0); free(Wt);
     return 0;
+}
+
+/* ------------------------------------------ analytic DDR^II (Apps. A, B) */
+/* The second data-data-random term of the bispectrum without randoms
+ * (Sec. 4, eq. EII-intro; Appendix A, eq. DDRII-kernel; Appendix B): it is a
+ * sum over data pairs out to 2 R0 of a kernel of the pair separation,
+ *   E^{II,ab}_l(x) = (2 pi / x) int_0^R0 int_0^R0 dr1 dr2 r1 r2 beta(Delta)
+ *                    g^a_l(r1) g^b_l(r2) L_l(Delta),
+ *   Delta = (r1^2 + r2^2 - x^2) / (2 r1 r2),  g^a_l(r) = jbar^a_l(r) W(r/R0),
+ * where beta(Delta) restricts the square to the band |r1 - r2| <= x <= r1 + r2
+ * (Appendix B, last form).  Readings: E at x = 0 is its limit
+ * 4 pi int_0^R0 r^2 g^a_l g^b_l dr (the band shrinks to r2 = r1, where
+ * Delta = 1); E = 0 for x >= 2 R0.
+ *
+ * Quadrature: composite 16-point Gauss-Legendre.  Both integration ranges
+ * are cut where the integrand or a limit of the inner range is not smooth --
+ * the joins of W at R0/2 and 3R0/4, r1 = x (the inner range starts at
+ * r2 = 0), and the values of r1 at which an inner limit |x - r1| or r1 + x
+ * crosses a join of W or reaches R0 -- and every piece is split into panels
+ * no wider than min(R0/8, (pi/2)/k_max). */
+#define EII_NG 16
+
+/* g^b_l(r) for all bins. */
+static void eii_g(int ell, double r, double r0, int n_k, const double *k, double *g)
+{
+    const double W = oracle_window(r / r0);
+    jbar_all_bins(ell, r, n_k, k, g);
+    for (int b = 0; b < n_k; ++b) g[b] *= W;
+}
+
+/* Gauss-Legendre nodes and weights of [lo, hi] cut at cuts[] and into panels
+ * no wider than hmax.  Returns the node count; xs, ws hold at least
+ * EII_NG * (ceil((hi - lo) / hmax) + ncut + 1) entries. */
+static int eii_nodes(double lo, double hi, const double *cuts, int ncut, double hmax,
+                     const double *gx, const double *gw, double *xs, double *ws)
+{
+    double pts[16];
+    int np = 0;
+    pts[np++] = lo;
+    for (int c = 0; c < ncut; ++c)
+        if (cuts[c] > lo && cuts[c] < hi) pts[np++] = cuts[c];
+    pts[np++] = hi;
+    for (int i = 1; i < np; ++i) /* insertion sort */
+        for (int j = i; j > 0 && pts[j] < pts[j - 1]; --j) {
+            double t = pts[j]; pts[j] = pts[j - 1]; pts[j - 1] = t;
+        }
+    int n = 0;
+    for (int s = 0; s + 1 < np; ++s) {
+        double a = pts[s], b = pts[s + 1];
+        if (!(b > a)) continue;
+        int npan = (int)ceil((b - a) / hmax);
+        if (npan < 1) npan = 1;
+        double h = (b - a) / npan;
+        for (int p = 0; p < npan; ++p) {
+            double mid = a + (p + 0.5) * h, half = 0.5 * h;
+            for (int q = 0; q < EII_NG; ++q) {
+                xs[n] = mid + half * gx[q];
+                ws[n] = half * gw[q];
+                ++n;
+            }
+        }
+    }
+    return n;
+}
+
+/* E^{II,ab}_l(x) for all bins a, b: out [n_k][n_k]. */
+int oracle_eii(double x, double r0, int ell, int n_k, const double *k, double *out)
+{
+    if (!(r0 > 0.0) || !(x >= 0.0) || ell < 0 || ell > ORACLE_ELL_MAX || n_k < 1 || n_k > ORACLE_NK_MAX)
+        return -1;
+    for (int q = 0; q < n_k * n_k; ++q) out[q] = 0.0;
+    if (x >= 2.0 * r0) return 0;
+    double gx[EII_NG], gw[EII_NG];
+    gauss_legendre(EII_NG, gx, gw);
+    double hmax = 0.125 * r0;
+    if (0.5 * PI / k[n_k] < hmax) hmax = 0.5 * PI / k[n_k];
+    const int cap = EII_NG * ((int)ceil(r0 / hmax) + 12);
+    double *x1 = malloc(sizeof(double) * cap), *w1 = malloc(sizeof(double) * cap);
+    double *x2 = malloc(sizeof(double) * cap), *w2 = malloc(sizeof(double) * cap);
+    double *ga = malloc(sizeof(double) * n_k), *gb = malloc(sizeof(double) * n_k);
+    double *H = malloc(sizeof(double) * n_k);
+    const double joins[2] = {0.5 * r0, 0.75 * r0};
+    if (x == 0.0) {
+        int n = eii_nodes(0.0, r0, joins, 2, hmax, gx, gw, x1, w1);
+        for (int i = 0; i < n; ++i) {
+            double r = x1[i];
+            eii_g(ell, r, r0, n_k, k, ga);
+            for (int a = 0; a < n_k; ++a)
+                for (int b = 0; b < n_k; ++b) out[a * n_k + b] += w1[i] * r * r * ga[a] * ga[b];
+        }
+        for (int q = 0; q < n_k * n_k; ++q) out[q] *= 4.0 * PI;
+    } else {
+        const double cuts1[10] = {0.5 * r0, 0.75 * r0, x, x - 0.5 * r0, x + 0.5 * r0,
+                                  x - 0.75 * r0, x + 0.75 * r0, 0.5 * r0 - x, 0.75 * r0 - x, r0 - x};
+        const double lo1 = x > r0 ? x - r0 : 0.0;
+        int n1 = eii_nodes(lo1, r0, cuts1, 10, hmax, gx, gw, x1, w1);
+        for (int i = 0; i < n1; ++i) {
+            double r1 = x1[i];
+            double lo2 = fabs(x - r1), hi2 = r1 + x < r0 ? r1 + x : r0;
+            if (!(hi2 > lo2)) continue;
+            int n2 = eii_nodes(lo2, hi2, joins, 2, hmax, gx, gw, x2, w2);
+            for (int b = 0; b < n_k; ++b) H[b] = 0.0;
+            for (int j = 0; j < n2; ++j) {
+                double r2 = x2[j];
+                /* Delta, with r1^2 - x^2 formed as (r1 - x)(r1 + x) */
+                double D = ((r1 - x) * (r1 + x) + r2 * r2) / (2.0 * r1 * r2);
+                if (D > 1.0) D = 1.0;
+                if (D < -1.0) D = -1.0;
+                double Lw = w2[j] * r2 * oracle_legendre(ell, D);
+                eii_g(ell, r2, r0, n_k, k, gb);
+                for (int b = 0; b < n_k; ++b) H[b] += Lw * gb[b];
+            }
+            eii_g(ell, r1, r0, n_k, k, ga);
+            for (int a = 0; a < n_k; ++a)
+                for (int b = 0; b < n_k; ++b) out[a * n_k + b] += w1[i] * r1 * ga[a] * H[b];
+        }
+        for (int q = 0; q < n_k * n_k; ++q) out[q] *= 2.0 * PI / x;
+    }
+    free(x1); free(w1); free(x2); free(w2); free(ga); free(gb); free(H);
+    return 0;
+}
+
+/* E^{II,ab}_l on the n_x + 1 nodes x_m = m h, h = 2 R0 / n_x, l = 0..ell_max:
+ * out [ell_max+1][n_k][n_k][n_x+1]. */
+int oracle_eii_table(double r0, int n_k, const double *k, int ell_max, int n_x, double *out, int nthreads)
+{
+    if (!(r0 > 0.0) || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 || ell_max > ORACLE_ELL_MAX || n_x < 1)
+        return -1;
+    const int nt = nthreads_or_default(nthreads);
+    const double h = 2.0 * r0 / n_x;
+    const int njob = (ell_max + 1) * (n_x + 1);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(| : bad)
+    for (int job = 0; job < njob; ++job) {
+        int l = job / (n_x + 1), m = job % (n_x + 1);
+        double *e = malloc(sizeof(double) * n_k * n_k);
+        bad |= oracle_eii(m * h, r0, l, n_k, k, e) != 0;
+        for (int a = 0; a < n_k; ++a)
+            for (int b = 0; b < n_k; ++b)
+                out[(((size_t)l * n_k + a) * n_k + b) * (n_x + 1) + m] = e[a * n_k + b];
+        free(e);
+    }
+    return bad ? -1 : 0;
+}
+
+/* The tabulated kernel at separation r (0 <= r < 2 R0): the cubic through the
+ * four nodes m-1 .. m+2 around r, m = floor(r / h), t = r / h - m (four-point
+ * Lagrange interpolation), with the nodes outside the table taken from the
+ * symmetry of E as a function of the pair vector (E(-h) = E(h)) and from its
+ * support (E(2 R0 + h) = 0).  tab: one (a, b, l) row of n_x + 1 nodes. */
+static double eii_interp(const double *tab, int n_x, double r, double h)
+{
+    double s = r / h;
+    int m = (int)floor(s);
+    if (m > n_x - 1) m = n_x - 1;
+    double t = s - m;
+    double e[4];
+    for (int q = -1; q <= 2; ++q) {
+        int node = m + q;
+        double v;
+        if (node < 0) v = tab[-node];
+        else if (node > n_x) v = 0.0;
+        else v = tab[node];
+        e[q + 1] = v;
+    }
+    double lm1 = -t * (t - 1.0) * (t - 2.0) / 6.0;
+    double l0 = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
+    double l1 = -(t + 1.0) * t * (t - 2.0) / 2.0;
+    double l2 = (t + 1.0) * t * (t - 1.0) / 6.0;
+    return lm1 * e[0] + l0 * e[1] + l1 * e[2] + l2 * e[3];
+}
+
+/* T^{ab}_l = sum_{i != j} w_i w_j E^{II,ab}_l(|x_i - x_j + n L|) over ordered
+ * pairs of distinct points and every periodic image n with separation
+ * < 2 R0 (squared, in double precision, as for the pair count inside R0).
+ * With R0 <= L/2 every such image has n in {-1, 0, 1}^3, and the torus
+ * integral over x3 of the two windows is exactly this sum over images.
+ * E is the interpolated table (eii_interp).  Primaries i with mask[i] == 0 are
+ * skipped.  T, l1 (sum of |term|): [ell_max+1][n_k][n_k].  *n_pairs counts
+ * the ordered (pair, image) terms. */
+int oracle_ddr2(int64_t n, const double *pos, const double *w, double box, double r0, int n_k,
+                const double *k, int ell_max, int n_x, const double *table, const uint8_t *mask,
+                double *T, double *l1, uint64_t *n_pairs, int nthreads)
+{
+    if (n < 1 || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 || ell_max > ORACLE_ELL_MAX ||
+        !(r0 > 0.0) || r0 > 0.5 * box || n_x < 1)
+        return -1;
+    const int nt = nthreads_or_default(nthreads);
+    const size_t ng = (size_t)(ell_max + 1) * n_k * n_k;
+    const double h = 2.0 * r0 / n_x, lim2 = 4.0 * r0 * r0;
+    double *acc = calloc((size_t)nt * 2 * ng, sizeof(double));
+    uint64_t *cnt = calloc((size_t)nt, sizeof(uint64_t));
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+        double *tT = acc + (size_t)tid * 2 * ng, *tL = tT + ng;
+        uint64_t c = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            if (mask && !mask[i]) continue;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double wij = (w ? w[i] : 1.0) * (w ? w[j] : 1.0);
+                for (int img = 0; img < 27; ++img) {
+                    double d[3];
+                    d[0] = pos[3 * i] - pos[3 * j] + (img / 9 - 1) * box;
+                    d[1] = pos[3 * i + 1] - pos[3 * j + 1] + ((img / 3) % 3 - 1) * box;
+                    d[2] = pos[3 * i + 2] - pos[3 * j + 2] + (img % 3 - 1) * box;
+                    double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                    if (!(r2 < lim2)) continue;
+                    ++c;
+                    double r = sqrt(r2);
+                    for (size_t q = 0; q < ng; ++q) {
+                        double v = wij * eii_interp(table + q * (n_x + 1), n_x, r, h);
+                        tT[q] += v;
+                        tL[q] += fabs(v);
+                    }
+                }
+            }
+        }
+        cnt[tid] = c;
+    }
+    uint64_t ctot = 0;
+    for (size_t q = 0; q < ng; ++q) { T[q] = 0.0; if (l1) l1[q] = 0.0; }
+    for (int t = 0; t < nt; ++t) {
+        for (size_t q = 0; q < ng; ++q) {
+            T[q] += acc[(size_t)t * 2 * ng + q];
+            if (l1) l1[q] += acc[(size_t)t * 2 * ng + ng + q];
+        }
+        ctot += cnt[t];
+    }
+    if (n_pairs) *n_pairs = ctot;
+    free(acc);
+    free(cnt);
+    return 0;
+}
+
+/* B^ab_ell with the DDR^II term from the kernel E^II instead of random
+ * primaries (Sec. 4 summary estimator; Appendix A, binned DDR^II):
+ *   B = (-1)^l (2l+1) / (V n_w^3) [(G_D - C_D) - n_w T]
+ *       - delta_l0 / (V n_w^2) [W~^a S0^b + W~^b S0^a] + 2 delta_l0 W~^a W~^b,
+ * with T from oracle_ddr2 on the table `table` (n_x intervals).  The random
+ * term of oracle_bk_ell, s_R (G_R - C_R), estimates n_w T by sampling the x3
+ * integral at the randoms.  Outputs as oracle_bk_ell; t2 = T. */
+int oracle_bk_ell_analytic(int64_t n, const double *pos, const double *w, double box, double r0, int n_k,
+                           const double *k, int ell_max, int n_x, const double *table, const uint8_t *mask_d,
+                           double *bk, double *gd, double *cd, double *t2, double *t2_l1, double *s0,
+                           double *wtilde, uint64_t *n_pairs_dd, uint64_t *n_pairs_2r0, int nthreads)
+{
+    if (n < 1 || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 || ell_max > ORACLE_ELL_MAX ||
+        !(r0 > 0.0) || r0 > 0.5 * box || n_x < 1)
+        return -1;
+    const int nt = nthreads_or_default(nthreads);
+    const size_t ng = (size_t)(ell_max + 1) * n_k * n_k;
+    double *GD = calloc(ng, sizeof(double)), *CD = calloc(ng, sizeof(double));
+    double *T = calloc(ng, sizeof(double)), *TL = calloc(ng, sizeof(double));
+    double *S0 = calloc((size_t)n_k, sizeof(double)), *Wt = calloc((size_t)n_k, sizeof(double));
+    uint64_t cdd = bk_primary_sums(n, pos, w, mask_d, 1, n, pos, w, box, r0, n_k, k, ell_max, GD, CD, S0, nt);
+    uint64_t c2 = 0;
+    int rc = oracle_ddr2(n, pos, w, box, r0, n_k, k, ell_max, n_x, table, mask_d, T, TL, &c2, nt);
+    double p1 = 0.0;
+    for (int64_t i = 0; i < n; ++i) p1 += w ? w[i] : 1.0;
+    const double V = box * box * box, nw = p1 / V;
+    for (int a = 0; a < n_k; ++a) Wt[a] = oracle_wtilde(r0, k[a], k[a + 1], 4.0);
+    for (int l = 0; l <= ell_max; ++l)
+        for (int a = 0; a < n_k; ++a)
+            for (int b = 0; b < n_k; ++b) {
+                size_t q = ((size_t)l * n_k + a) * n_k + b;
+                double sgn = (l & 1) ? -1.0 : 1.0;
+                double v = sgn * (2.0 * l + 1.0) / (V * nw * nw * nw) * ((GD[q] - CD[q]) - nw * T[q]);
+                if (l == 0)
+                    v += -(Wt[a] * S0[b] + Wt[b] * S0[a]) / (V * nw * nw) + 2.0 * Wt[a] * Wt[b];
+                bk[q] = v;
+            }
+    if (gd) memcpy(gd, GD, ng * sizeof(double));
+    if (cd) memcpy(cd, CD, ng * sizeof(double));
+    if (t2) memcpy(t2, T, ng * sizeof(double));
+    if (t2_l1) memcpy(t2_l1, TL, ng * sizeof(double));
+    if (s0) memcpy(s0, S0, (size_t)n_k * sizeof(double));
+    if (wtilde) memcpy(wtilde, Wt, (size_t)n_k * sizeof(double));
+    if (n_pairs_dd) *n_pairs_dd = cdd;
+    if (n_pairs_2r0) *n_pairs_2r0 = c2;
+    free(GD); free(CD); free(T); free(TL); free(S0); free(Wt);
+    return rc;
 }
