@@ -16,6 +16,8 @@
  *                   eq. AC-def and the summary estimator), with the DDR^II term
  *                   from caller-supplied random primaries and all other random
  *                   terms analytic.
+ *   hipster_bk_ell_analytic: the same with the DDR^II term from the kernel
+ *                   E^II (Appendices A, B): no randoms at all.
  *
  * Conventions.  Pairs (i, j), i != j by index, separated by the minimum
  * periodic image; a pair counts iff r^2 < R0^2 in double precision.  With
@@ -114,6 +116,10 @@ typedef struct {
   uint64_t n_pairs_rr;    /* survey power spectrum: ordered random-random pairs inside R0 */
   double ms_sweep_far;    /* P, mixed form: the far-pair kernel's part of ms_sweep */
   uint64_t n_pairs_far;   /* P, mixed form: unordered pairs swept by the far-pair kernel */
+  double ms_eii_table;    /* B analytic: building the E^II table (0 when the context reused it) */
+  double ms_ddr2;         /* B analytic: the 2 R0 pair sweep and its contraction with the table */
+  uint64_t n_pairs_2r0;   /* B analytic: ordered (pair, periodic image) terms inside 2 R0 */
+  int64_t eii_nodes;      /* B analytic: the table's n_x (intervals over [0, 2 R0]) */
 } hipster_diag;
 
 typedef struct hipster_ctx hipster_ctx;
@@ -137,6 +143,45 @@ hipster_status hipster_pk_ell(hipster_ctx *ctx, const hipster_points *pts,
 hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data,
                               const hipster_points *randoms, const hipster_params *prm,
                               double *bk, hipster_diag *diag);
+
+/* Bispectrum multipoles with the DDR^II term computed without randoms
+ * (Sec. 4, eq. EII-intro; Appendix A, eq. DDRII-kernel and its binned form;
+ * Appendix B): the random-primary sum of hipster_bk_ell,
+ * s_R sum_r [(4 pi/(2l+1)) sum_m A A* - C], is replaced by the x3 integral it
+ * samples, n_w T^ab_l with
+ *   T^ab_l = sum_{i != j} w_i w_j E^{II,ab}_l(|x_i - x_j + n L|)
+ * over ordered pairs of distinct data points and every periodic image with
+ * separation < 2 R0 (double-precision r^2 predicate, as for R0), and
+ *   E^{II,ab}_l(x) = (2 pi / x) int int dr1 dr2 r1 r2 g^a_l(r1) g^b_l(r2) L_l(Delta)
+ * over the band |r1 - r2| <= x <= r1 + r2 of [0, R0]^2, g^a_l = jbar^a_l W,
+ * Delta = (r1^2 + r2^2 - x^2)/(2 r1 r2).  As the paper suggests, E is
+ * tabulated (double precision, composite Gauss-Legendre) on the nodes
+ * x_m = m h, h = 2 R0 / n_x, m = 0..n_x, and interpolated per pair by the cubic
+ * through the nodes m-1..m+2 around x (m = floor(x/h); E(-h) = E(h), nodes at
+ * and beyond 2 R0 hold 0).  The interpolation error is about 0.02 (k_max h)^4
+ * of the kernel.
+ * n_x: table intervals, 0 for the default (the smallest multiple of 64 with
+ * k_max h <= 0.05, at least 64, at most 8192); 2 <= n_x <= 8192 and the device
+ * must hold an (n_x + 1)-entry double histogram in one workgroup's LDS, else
+ * HIPSTER_EUNSUPPORTED.  k_edges[n_k] * R0 <= 1e6 (HIPSTER_EUNSUPPORTED).
+ * The table is cached in the context and reused while (R0, n_x, ell_max,
+ * k_edges) stay the same.  Other arguments, output and errors as
+ * hipster_bk_ell; prm->random_mask is ignored.  In diag: gr = T, cr = 0,
+ * n_pairs_rand = 0, n_pairs_2r0, ms_eii_table, ms_ddr2, eii_nodes.  Pair sums
+ * within a workgroup use floating-point atomics, so repeated calls agree to
+ * rounding (about 1e-16 relative), not bit for bit. */
+hipster_status hipster_bk_ell_analytic(hipster_ctx *ctx, const hipster_points *data, const hipster_params *prm,
+                                       int32_t n_x, double *bk, hipster_diag *diag);
+
+/* The E^{II,ab}_l table of hipster_bk_ell_analytic: table (host,
+ * caller-allocated) [ell_max+1][n_k][n_k][n_x+1] doubles, entry
+ * ((l n_k + a) n_k + b)(n_x + 1) + m = E^{II,ab}_l(m 2 R0 / n_x), l = 0..ell_max.
+ * r0, n_k, k_edges, ell_max as in hipster_params (n_k <= 16, ell_max <= 6);
+ * n_x >= 2 as in hipster_bk_ell_analytic (0 is not accepted here).  Errors:
+ * HIPSTER_EINVAL (NULL pointers), HIPSTER_EDOMAIN (R0 <= 0, bad edges or
+ * ell_max), HIPSTER_EUNSUPPORTED (sizes). */
+hipster_status hipster_eii_table(hipster_ctx *ctx, double r0, int32_t n_k, const double *k_edges, int32_t ell_max,
+                                 int32_t n_x, double *table);
 
 /* Parameters of the survey-geometry power spectrum (hipster_pk_survey).
  * volume: V of the normalisation 1/(n_w^2 V), n_w = sum(w_data) / V (the

@@ -18,7 +18,7 @@ from typing import Any
 import numpy as np
 
 __all__ = ["Context", "wtilde", "pk_ell", "bk_ell", "batch", "HipsterError", "library_path", "load_library",
-           "EXPORTED_SYMBOLS", "MIXED", "FP64", "pk_survey"]
+           "EXPORTED_SYMBOLS", "MIXED", "FP64", "pk_survey", "bk_ell_analytic", "eii_table"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 MIXED, FP64 = 0, 1
@@ -26,7 +26,8 @@ _F32, _F64 = 0, 1
 
 EXPORTED_SYMBOLS = ("hipster_create", "hipster_destroy", "hipster_pk_ell", "hipster_bk_ell",
                     "hipster_batch", "hipster_last_error", "hipster_status_string",
-                    "hipster_set_memory_cap", "hipster_wtilde", "hipster_pk_survey")
+                    "hipster_set_memory_cap", "hipster_wtilde", "hipster_pk_survey",
+                    "hipster_bk_ell_analytic", "hipster_eii_table")
 
 
 class HipsterError(RuntimeError):
@@ -55,7 +56,8 @@ class _Diag(ct.Structure):
                 ("cd", _dp), ("gr", _dp), ("cr", _dp), ("s0", _dp), ("wtilde", _dp),
                 ("ms_build", ct.c_double), ("ms_pairs", ct.c_double), ("ms_sweep", ct.c_double),
                 ("ms_total", ct.c_double), ("sweep_launches", ct.c_uint64), ("n_pairs_rr", ct.c_uint64),
-                ("ms_sweep_far", ct.c_double), ("n_pairs_far", ct.c_uint64)]
+                ("ms_sweep_far", ct.c_double), ("n_pairs_far", ct.c_uint64), ("ms_eii_table", ct.c_double),
+                ("ms_ddr2", ct.c_double), ("n_pairs_2r0", ct.c_uint64), ("eii_nodes", ct.c_int64)]
 
 
 class _SurveyParams(ct.Structure):
@@ -99,6 +101,11 @@ def load_library():
     L.hipster_bk_ell.restype = ct.c_int
     L.hipster_bk_ell.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Points), ct.POINTER(_Params),
                                  _dp, ct.POINTER(_Diag)]
+    L.hipster_bk_ell_analytic.restype = ct.c_int
+    L.hipster_bk_ell_analytic.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Params), ct.c_int32, _dp,
+                                          ct.POINTER(_Diag)]
+    L.hipster_eii_table.restype = ct.c_int
+    L.hipster_eii_table.argtypes = [ct.c_void_p, ct.c_double, ct.c_int32, _dp, ct.c_int32, ct.c_int32, _dp]
     L.hipster_batch.restype = ct.c_int
     L.hipster_batch.argtypes = [ct.c_void_p, ct.c_int, ct.POINTER(_BoxJob), ct.POINTER(_Diag)]
     L.hipster_last_error.restype = ct.c_char_p
@@ -332,6 +339,50 @@ def bk_ell(pos, w=None, randoms=None, rw=None, *, box: float, r0: float, k_edges
     info.update(s0=s0, wtilde=wt, n_pairs=int(d.n_pairs), n_pairs_rand=int(d.n_pairs_rand), ms_build=d.ms_build,
                 ms_pairs=d.ms_pairs, ms_sweep=d.ms_sweep, ms_total=d.ms_total, sweep_launches=int(d.sweep_launches))
     return out, info
+
+
+def bk_ell_analytic(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, n_x: int = 0,
+                    precision: str = "mixed", primary_mask=None, ctx: Context | None = None,
+                    return_diag: bool = False) -> Any:
+    """Bispectrum multipoles B^ab_ell with the DDR^II term from the E^II kernel
+    (no randoms): float64 array of shape (ell_max + 1, n_k, n_k).  n_x: E^II
+    table intervals over [0, 2 R0] (0: the library's default).  With
+    return_diag, also gd, cd, t2 (= sum_{i!=j} w_i w_j E^II), s0, W~^a, pair
+    counts and timings."""
+    L = load_library()
+    keep: list = []
+    pts = _points(pos, w, keep)
+    prm = _params(box, r0, k_edges, ell_max, 2, precision, primary_mask, None, keep)
+    n_k = prm.n_k
+    shp = (ell_max + 1, n_k, n_k)
+    out = np.zeros(shp)
+    parts = {k: np.zeros(shp) for k in ("gd", "cd", "gr", "cr")}
+    s0 = np.zeros(n_k)
+    wt = np.zeros(n_k)
+    d = _Diag()
+    d.gd, d.cd, d.gr, d.cr = (_ptr(parts[k]) for k in ("gd", "cd", "gr", "cr"))
+    d.s0, d.wtilde = _ptr(s0), _ptr(wt)
+    c = ctx or _context_for(pos)
+    c.check(L.hipster_bk_ell_analytic(c.handle, ct.byref(pts), ct.byref(prm), int(n_x), _ptr(out), ct.byref(d)))
+    if not return_diag:
+        return out
+    info = {"gd": parts["gd"], "cd": parts["cd"], "t2": parts["gr"]}
+    info.update(s0=s0, wtilde=wt, n_pairs=int(d.n_pairs), n_pairs_2r0=int(d.n_pairs_2r0), ms_build=d.ms_build,
+                ms_sweep=d.ms_sweep, ms_eii_table=d.ms_eii_table, ms_ddr2=d.ms_ddr2, ms_total=d.ms_total,
+                eii_nodes=int(d.eii_nodes))
+    return out, info
+
+
+def eii_table(r0: float, k_edges, ell_max: int, n_x: int, *, ctx: Context | None = None):
+    """The E^{II,ab}_ell table on the nodes m 2 R0 / n_x, m = 0..n_x, computed
+    on the GPU: float64 array of shape (ell_max + 1, n_k, n_k, n_x + 1)."""
+    L = load_library()
+    k = np.ascontiguousarray(k_edges, dtype=np.float64)
+    n_k = k.size - 1
+    out = np.zeros((ell_max + 1, n_k, n_k, n_x + 1))
+    c = ctx or _context_for(None)
+    c.check(L.hipster_eii_table(c.handle, float(r0), n_k, _ptr(k), int(ell_max), int(n_x), _ptr(out)))
+    return out
 
 
 def batch(boxes, *, precision: str = "mixed", ctx: Context | None = None, return_diag: bool = False):

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.environ.get("HIPSTER_BUILD_OUT") or os.path.join(HERE, "libhipster.so")
 BUILD = os.environ.get("HIPSTER_BUILD_DIR") or os.path.join(HERE, "_build")
 EXTRA = os.environ.get("HIPSTER_BUILD_DEFINES", "").split()  # e.g. -DHIPSTER_BK_WAVES_PER_EU=2
-SOURCES = ["celllist.hip", "pairs.hip", "pk.hip", "bk.hip", "api.hip", "analytic.cpp"]
+SOURCES = ["celllist.hip", "pairs.hip", "pk.hip", "bk.hip", "eii.hip", "api.hip", "analytic.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
          "-I" + CSRC, "-I" + os.path.join(os.path.dirname(HERE), "include"), *EXTRA]

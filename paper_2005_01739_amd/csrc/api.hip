@@ -455,13 +455,50 @@ static void run_pk_survey(Ctx &c, const hipster_points *dp, const hipster_points
 }
 
 // -------------------------------------------------------------- bispectrum
+// E^{II,ab}_l table of the analytic DDR^II term on the device, rebuilt only
+// when (R0, n_x, ell_max, edges) change; *ms is its build time (0 if reused).
+static const double *eii_device_table(Ctx &c, Timer &tm, double r0, int n_k, const double *k, int ell_max, int n_x,
+                                      double *ms) {
+  std::vector<double> key = {r0, double(n_k), double(ell_max), double(n_x)};
+  key.insert(key.end(), k, k + n_k + 1);
+  const size_t bytes = size_t(ell_max + 1) * n_k * n_k * (size_t(n_x) + 1) * 8;
+  *ms = 0.0;
+  if (c.eii_key == key && c.eii_tab.p && c.eii_tab.cap >= bytes) return static_cast<const double *>(c.eii_tab.p);
+  c.eii_key.clear();
+  double *tab = static_cast<double *>(ensure(c, c.eii_tab, bytes));
+  hipEvent_t e0 = tm.mark();
+  eii_table(c, r0, n_k, k, ell_max, n_x, tab);
+  hipEvent_t e1 = tm.mark();
+  HIPSTER_HIP(hipEventSynchronize(e1));
+  *ms = Timer::ms(e0, e1);
+  c.eii_key = key;
+  return tab;
+}
+
+// Table size of the analytic DDR^II term: n_x = 0 picks the default.
+static int check_eii_nodes(Ctx &c, const hipster_params *q, int n_x) {
+  if (q->k_edges[q->n_k] * q->r0 > kMaxPhaseMixed)
+    throw Error{HIPSTER_EUNSUPPORTED, "analytic DDR^II: the kernel table needs k_max * R0 <= 1e6"};
+  if (n_x == 0) n_x = eii_default_nodes(q->r0, q->k_edges[q->n_k]);
+  if (n_x < 2 || n_x > kEiiMaxNodes)
+    throw Error{HIPSTER_EUNSUPPORTED, "analytic DDR^II: n_x must lie in [2, " + std::to_string(kEiiMaxNodes) + "]"};
+  if (size_t(n_x) + 1 > ddr2_max_nodes(c))
+    throw Error{HIPSTER_EUNSUPPORTED, "analytic DDR^II: the pair histogram exceeds the device's LDS"};
+  return n_x;
+}
+
+// analytic_nx < 0: the DDR^II term from the random primaries `rp`;
+// otherwise from the E^II kernel with that many table intervals (0: default)
+// and no randoms.
 static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, const hipster_params *q, double *bk,
-                   hipster_diag *diag) {
+                   hipster_diag *diag, int analytic_nx = -1) {
   check_points(dp, "data", q ? q->box : 0.0);
   check_params(q, true);
   if (!bk) throw Error{HIPSTER_EINVAL, "NULL output"};
   if (dp->n < 2) throw Error{HIPSTER_EINVAL, "need at least two points"};
-  const bool have_r = rp && rp->n > 0;
+  const bool analytic = analytic_nx >= 0;
+  if (analytic) analytic_nx = check_eii_nodes(c, q, analytic_nx);
+  const bool have_r = !analytic && rp && rp->n > 0;
   if (have_r) check_points(rp, "randoms", q->box);
   HIPSTER_HIP(hipSetDevice(c.device));
   Timer tm(c);
@@ -517,6 +554,24 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
     ms_sweep += Timer::ms(b1, b2);
     ++launches;
   }
+  // analytic DDR^II: the kernel table, then every data pair inside 2 R0 on
+  // a grid of cells >= 2 R0 (the data re-sorted into the randoms' scratch)
+  std::vector<double> T;
+  double ms_table = 0.0, ms_ddr2 = 0.0;
+  if (analytic) {
+    const double *tab = eii_device_table(c, tm, q->r0, NK, q->k_edges, q->ell_max, analytic_nx, &ms_table);
+    hipEvent_t d0 = tm.mark();
+    const Grid g2 = make_grid(q->box, 2.0 * q->r0);
+    const Sorted s2 = build_cells(c, c.cells_r, g2, pos, w, mask, n, dp->dtype);
+    const int rows = NL * NK * NK;
+    double *Td = static_cast<double *>(ensure(c, c.ddr2_T, size_t(rows) * 8));
+    ddr2_sweep(c, s2, g2, q->r0, analytic_nx, tab, rows, Td, cnt + 1);
+    T.resize(size_t(rows));
+    HIPSTER_HIP(hipMemcpyAsync(T.data(), Td, size_t(rows) * 8, hipMemcpyDeviceToHost, c.stream));
+    hipEvent_t d1 = tm.mark();
+    HIPSTER_HIP(hipEventSynchronize(d1));
+    ms_ddr2 = Timer::ms(d0, d1);
+  }
   unsigned long long hcnt[2] = {0, 0};
   HIPSTER_HIP(hipMemcpyAsync(hcnt, cnt, 16, hipMemcpyDeviceToHost, c.stream));
   double *merged = static_cast<double *>(ensure(c, c.merged, size_t(2 * rowlen) * 8));
@@ -540,9 +595,13 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
       for (int b = 0; b < NK; ++b) {
         const int t = l * 256 + std::min(a, b) * 16 + std::max(a, b);
         const size_t o = (size_t(l) * NK + a) * NK + b;
-        const double GD = Md[t], CD = Md[nT + t], GR = Mr[t], CR = Mr[nT + t];
+        const double GD = Md[t], CD = Md[nT + t];
+        // the random-primary term s_R (G_R - C_R) estimates n_w T, T = sum_{i!=j} w_i w_j E^II
+        const double GR = analytic ? T[(size_t(l) * NK + std::min(a, b)) * NK + std::max(a, b)] : Mr[t];
+        const double CR = analytic ? 0.0 : Mr[nT + t];
         const double sgn = (l & 1) ? -1.0 : 1.0;
-        double v = sgn * (2.0 * l + 1.0) / (V * nw * nw * nw) * ((GD - CD) - sR * (GR - CR));
+        const double ddr2 = analytic ? nw * GR : sR * (GR - CR);
+        double v = sgn * (2.0 * l + 1.0) / (V * nw * nw * nw) * ((GD - CD) - ddr2);
         if (l == 0) v += -(wt[size_t(a)] * Md[2 * nT + b] + wt[size_t(b)] * Md[2 * nT + a]) / (V * nw * nw) +
                          2.0 * wt[size_t(a)] * wt[size_t(b)];
         bk[o] = v;
@@ -559,7 +618,7 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
     if (diag->wtilde) memcpy(diag->wtilde, wt.data(), size_t(NK) * 8);
     diag->n_pairs = hcnt[0];
     diag->n_pairs_rr = 0;
-    diag->n_pairs_rand = hcnt[1];
+    diag->n_pairs_rand = analytic ? 0 : hcnt[1];
     diag->ms_build = Timer::ms(t0, t1);
     diag->ms_pairs = ms_pairs;
     diag->ms_sweep = ms_sweep;
@@ -567,7 +626,34 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
     diag->sweep_launches = launches;
     diag->ms_sweep_far = 0.0;
     diag->n_pairs_far = 0;
+    diag->ms_eii_table = ms_table;
+    diag->ms_ddr2 = ms_ddr2;
+    diag->n_pairs_2r0 = analytic ? hcnt[1] : 0;
+    diag->eii_nodes = analytic ? analytic_nx : 0;
   }
+}
+
+// E^{II,ab}_l on the nodes m 2 R0 / n_x, copied to the host.
+static void run_eii_table(Ctx &c, double r0, int32_t n_k, const double *k_edges, int32_t ell_max, int32_t n_x,
+                          double *out) {
+  if (!out || !k_edges) throw Error{HIPSTER_EINVAL, "NULL argument"};
+  hipster_params q{};
+  q.box = 2.0 * r0;
+  q.r0 = r0;
+  q.n_k = n_k;
+  q.ell_max = ell_max;
+  q.k_edges = k_edges;
+  q.precision = HIPSTER_FP64;
+  check_params(&q, true);
+  if (n_x < 2) throw Error{HIPSTER_EUNSUPPORTED, "E^II table: n_x must be >= 2"};
+  HIPSTER_HIP(hipSetDevice(c.device));
+  n_x = check_eii_nodes(c, &q, n_x);
+  Timer tm(c);
+  double ms = 0.0;
+  const double *tab = eii_device_table(c, tm, r0, n_k, k_edges, ell_max, n_x, &ms);
+  const size_t bytes = size_t(ell_max + 1) * n_k * n_k * (size_t(n_x) + 1) * 8;
+  HIPSTER_HIP(hipMemcpyAsync(out, tab, bytes, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
 }
 
 // ------------------------------------------------------------------ batch
@@ -855,7 +941,8 @@ void hipster_destroy(hipster_ctx *ctx) {
   DevBuf *all[] = {&c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in, &c.rmask_in, &c.pair_cnt, &c.pair_cnt_b,
                    &c.pair_ord, &c.pair_off, &c.pair_off_b, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
                    &c.partial, &c.merged, &c.ordered_count, &c.bbox, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out,
-                   &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile};
+                   &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile, &c.eii_consts, &c.eii_tab,
+                   &c.ddr2_partial, &c.ddr2_hist, &c.ddr2_counter, &c.ddr2_T};
   for (DevBuf *b : all) free_buf(*b);
   delete ctx;
 }
@@ -873,6 +960,17 @@ hipster_status hipster_pk_survey(hipster_ctx *ctx, const hipster_points *data, c
 hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data, const hipster_points *randoms,
                               const hipster_params *prm, double *bk, hipster_diag *diag) {
   return guarded(ctx, [&] { run_bk(ctx->c, data, randoms, prm, bk, diag); });
+}
+
+hipster_status hipster_bk_ell_analytic(hipster_ctx *ctx, const hipster_points *data, const hipster_params *prm,
+                                       int32_t n_x, double *bk, hipster_diag *diag) {
+  if (n_x < 0) return HIPSTER_EINVAL;
+  return guarded(ctx, [&] { run_bk(ctx->c, data, nullptr, prm, bk, diag, n_x); });
+}
+
+hipster_status hipster_eii_table(hipster_ctx *ctx, double r0, int32_t n_k, const double *k_edges, int32_t ell_max,
+                                 int32_t n_x, double *table) {
+  return guarded(ctx, [&] { run_eii_table(ctx->c, r0, n_k, k_edges, ell_max, n_x, table); });
 }
 
 hipster_status hipster_batch(hipster_ctx *ctx, int n_boxes, hipster_box_job *jobs, hipster_diag *diag) {

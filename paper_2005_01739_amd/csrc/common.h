@@ -18,6 +18,7 @@ constexpr int kMaxNkB = 16;        // bispectrum bins
 constexpr int kMaxCellsPerAxis = 160;
 constexpr int kLMaxApi = 6;          // largest multipole
 constexpr double kMaxPhaseMixed = 1e6;  // largest k * R0 of the mixed form
+constexpr int kEiiMaxNodes = 8192;      // largest E^II table (intervals over [0, 2 R0])
 
 struct Error {
   hipster_status status;
@@ -112,6 +113,9 @@ struct Ctx {
   DevBuf unit_tiles, unit_base, unit_cell, unit_tile;
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
+  DevBuf eii_consts, eii_tab, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T;
+  // The E^II table on the device and the (R0, n_x, ell_max, edges) it holds.
+  std::vector<double> eii_key;
   // W~^a depends only on (R0, k_a, k_{a+1}); repeated calls reuse it.
   std::map<std::tuple<double, double, double>, double> wtilde_cache;
 };
@@ -182,6 +186,17 @@ void bk_fused(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, doub
               int nwaves, unsigned long long *npairs);
 size_t bk_fused_lds(int NL, int NK);
 void widen_i32(Ctx &c, const int *in, int64_t *out, int64_t n);
+
+// Analytic DDR^II term: the E^{II,ab}_l table on the nodes m 2 R0 / n_x
+// (device, [ell_max+1][n_k][n_k][n_x+1]); the 2 R0 pair sweep of the
+// cubic-interpolation weights and its contraction with the table into
+// T[rows] (rows = (ell_max+1) n_k^2), adding the ordered (pair, image) count
+// to *ordered.  `s` is the data sorted on a grid of cells >= 2 R0.
+int eii_default_nodes(double r0, double k_max);
+void eii_table(Ctx &c, double r0, int n_k, const double *k_edges, int ell_max, int n_x, double *table);
+void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, const double *table, int rows,
+                double *T, unsigned long long *ordered);
+size_t ddr2_max_nodes(Ctx &c);
 
 // Host analytic terms.
 double wtilde_bin(double r0, double k1, double k2);

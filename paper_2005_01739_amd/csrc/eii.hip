@@ -1,0 +1,516 @@
+// The bispectrum's second data-data-random term without randoms (Sec. 4,
+// eq. EII-intro; Appendix A, eq. DDRII-kernel; Appendix B).  It is a sum over
+// data pairs out to 2 R0 of a kernel of the pair separation,
+//   DDR^II,ab_l = n (-1)^l (2l+1) sum_{i!=j} w_i w_j E^{II,ab}_l(|x_ij|),
+//   E^{II,ab}_l(x) = (2 pi / x) int int dr1 dr2 r1 r2 g^a_l(r1) g^b_l(r2) L_l(Delta)
+// over the band |r1 - r2| <= x <= r1 + r2 of [0, R0]^2 (the beta(Delta) of the
+// triple-Bessel identity), Delta = (r1^2 + r2^2 - x^2) / (2 r1 r2),
+// g^a_l = jbar^a_l W.  As the paper suggests, E is tabulated once per (R0,
+// bins) and interpolated per pair:
+//
+//   k_eii_table   E on the nodes x_m = m h, h = 2 R0 / n_x, by composite
+//                 8-point Gauss-Legendre in double precision (one workgroup
+//                 per (l, m); the outer r1 nodes are spread over the threads,
+//                 each thread sums its inner r2 integral for every bin);
+//   k_ddr2_hist   every (pair, periodic image) inside 2 R0 adds its four
+//                 cubic-interpolation weights l_q(t), times w_i w_j, to the
+//                 nodes m-1 .. m+2 of an LDS histogram: the pair sum of the
+//                 interpolated kernel is then sum_m E_m H_m exactly, so the
+//                 sweep does the same small work for any number of bins and
+//                 multipoles;
+//   k_ddr2_reduce, k_ddr2_contract
+//                 fixed-order sums of the per-workgroup histograms and the
+//                 contraction T^ab_l = sum_m E^ab_l(x_m) H_m.
+//
+// Interpolation (a reading: the paper leaves the scheme open): on
+// [x_m, x_{m+1}) the cubic through the nodes m-1 .. m+2, t = x/h - m; the
+// node below 0 takes E(-h) = E(h) (E is a smooth function of the pair vector,
+// even in x) and the nodes at and beyond 2 R0 hold E = 0 (its support).
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "specfun.h"
+
+namespace hipster {
+
+constexpr int kEiiThreads = 256;
+constexpr int kEiiMaxNk = 16;
+
+// Gauss-Legendre nodes and weights on [-1, 1] (8 points), computed on the
+// host by Newton's method on the Legendre polynomial.
+struct GL8 {
+  double x[8], w[8];
+};
+
+static GL8 gauss_legendre8() {
+  GL8 g{};
+  const int n = 8;
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5)), d = 0.0;
+    for (int it = 0; it < 50; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 1; k < n; ++k) {
+        const double p2 = ((2 * k + 1) * z * p1 - k * p0) / (k + 1);
+        p0 = p1;
+        p1 = p2;
+      }
+      d = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / d;
+      z -= dz;
+      if (fabs(dz) < 1e-17) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 1; k < n; ++k) {
+      const double p2 = ((2 * k + 1) * z * p1 - k * p0) / (k + 1);
+      p0 = p1;
+      p1 = p2;
+    }
+    d = n * (z * p1 - p0) / (z * z - 1.0);
+    g.x[i] = z;
+    g.w[i] = 2.0 / ((1.0 - z * z) * d * d);
+  }
+  return g;
+}
+
+// G_l(u) = Dt_l(u) / u^3 for one multipole l (uniform over the workgroup),
+// double precision throughout: the Taylor series below U_BIG, above it the
+// closed form with table-driven sine and cosine (exact reduction for
+// u < ~1.6e6) and the 22-term fits of the sine integral's auxiliaries.
+__device__ inline double G_one(int l, double u, const double2 *__restrict__ tab) {
+  if (u < HIPSTER_U_BIG) {
+    const double v = u * u;
+    double ul = 1.0;
+    for (int q = 0; q < l; ++q) ul *= u;
+    return u < kUSmall ? taylor_G64<14>(l, v, ul) : taylor_G64<HIPSTER_N_TAYLOR>(l, v, ul);
+  }
+  double s, c;
+  sincos_tab<kSinCosTab, true>(u, tab, s, c);
+  const double w = 1.0 / u;
+  double si = 0.0;
+  if (l >= 2 && (l & 1) == 0) {
+    const double t = HIPSTER_U_BIG * w;
+    const double f = horner64(POLY_F64, t) * w;
+    const double g = horner64(POLY_G64, t) * w * w;
+    si = kHalfPi - f * c - g * s;
+  }
+  return Dt_closed<double>(l, u, w, s, c, si) * (w * w * w);
+}
+
+// g^b_l(r) = jbar^b_l(r) W(r/R0) for the n_k bins, from one G per edge:
+//   jbar^b = 3 (k_{b+1}^3 G(k_{b+1} r) - k_b^3 G(k_b r)) / (k_{b+1}^3 - k_b^3).
+__device__ inline void g_bins(int l, double r, double inv_r0, int n_k, const double *__restrict__ ek,
+                              const double *__restrict__ coef, const double2 *__restrict__ tab,
+                              double (&g)[kEiiMaxNk]) {
+  const double W = window(r * inv_r0);
+  double prev = ek[1] * G_one(l, ek[0] * r, tab);  // k_0^3 G(k_0 r)
+#pragma unroll
+  for (int b = 0; b < kEiiMaxNk; ++b) {
+    if (b < n_k) {
+      const double cur = ek[2 * (b + 1) + 1] * G_one(l, ek[2 * (b + 1)] * r, tab);
+      g[b] = coef[b] * (cur - prev) * W;
+      prev = cur;
+    } else {
+      g[b] = 0.0;
+    }
+  }
+}
+
+// Legendre polynomial L_l(mu) by the three-term recurrence.
+__device__ inline double legendre_l(int l, double mu) {
+  double p0 = 1.0, p1 = mu;
+  if (l == 0) return 1.0;
+  for (int n = 1; n < l; ++n) {
+    const double p2 = ((2 * n + 1) * mu * p1 - n * p0) / double(n + 1);
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+// Pieces of [lo, hi] between sorted cut points, each split into panels no
+// wider than hmax.
+struct Pieces {
+  double p[13];
+  int npan[12];
+  int start[13];  // first panel of each piece; start[n] = total panels
+  int n;
+};
+
+__device__ inline void make_pieces(double lo, double hi, const double *cuts, int ncut, double hmax, Pieces &P) {
+  int np = 0;
+  P.p[np++] = lo;
+  for (int c = 0; c < ncut; ++c)
+    if (cuts[c] > lo && cuts[c] < hi) P.p[np++] = cuts[c];
+  P.p[np++] = hi;
+  for (int i = 1; i < np; ++i)
+    for (int j = i; j > 0 && P.p[j] < P.p[j - 1]; --j) {
+      const double t = P.p[j];
+      P.p[j] = P.p[j - 1];
+      P.p[j - 1] = t;
+    }
+  P.n = np - 1;
+  int tot = 0;
+  for (int s = 0; s < P.n; ++s) {
+    const double len = P.p[s + 1] - P.p[s];
+    int k = len > 0.0 ? int(ceil(len / hmax)) : 0;
+    P.npan[s] = k;
+    P.start[s] = tot;
+    tot += k;
+  }
+  P.start[P.n] = tot;
+}
+
+// One workgroup per (l, m): E^{II,ab}_l(m h) for all a, b, written to
+// table[((l n_k + a) n_k + b) (n_x + 1) + m].
+__global__ __launch_bounds__(kEiiThreads) void k_eii_table(double r0, double h, int n_x, int n_k,
+                                                           const double *__restrict__ ek_g,
+                                                           const double *__restrict__ coef_g, GL8 gl, double hmax,
+                                                           double *__restrict__ table) {
+  __shared__ double2 tab[kSinCosTab];
+  __shared__ double ek[2 * (kEiiMaxNk + 1)], coef[kEiiMaxNk];
+  // the outer nodes' rows w1 r1 g^a(r1) and H^b(r1), staged half a
+  // workgroup at a time
+  __shared__ double A[kEiiThreads / 2][kEiiMaxNk + 1], Hs[kEiiThreads / 2][kEiiMaxNk + 1];
+  __shared__ Pieces outer;
+  const int m = blockIdx.x, l = blockIdx.y, tid = threadIdx.x;
+  const int nab = n_k * n_k;
+  const size_t stride = size_t(n_x) + 1;
+  if (m == n_x) {  // x = 2 R0: outside the support
+    for (int q = tid; q < nab; q += kEiiThreads) table[(size_t(l) * nab + q) * stride + m] = 0.0;
+    return;
+  }
+  const double x = m * h, inv_r0 = 1.0 / r0;
+  stage_sincos_tab<kSinCosTab>(tab);
+  for (int i = tid; i < 2 * (n_k + 1); i += kEiiThreads) ek[i] = ek_g[i];
+  for (int i = tid; i < n_k; i += kEiiThreads) coef[i] = coef_g[i];
+  if (tid == 0) {
+    // cuts of r1: the joins of W, r1 = x, and where |x - r1| or r1 + x meets a
+    // join of W or R0
+    const double cuts[10] = {0.5 * r0, 0.75 * r0, x, x - 0.5 * r0, x + 0.5 * r0,
+                             x - 0.75 * r0, x + 0.75 * r0, 0.5 * r0 - x, 0.75 * r0 - x, r0 - x};
+    make_pieces(x > r0 ? x - r0 : 0.0, r0, cuts, x > 0.0 ? 10 : 2, hmax, outer);
+  }
+  __syncthreads();
+  const int n1 = 8 * outer.start[outer.n];
+  const double joins[2] = {0.5 * r0, 0.75 * r0};
+  double acc = 0.0;
+  const int my_a = tid / n_k, my_b = tid - my_a * n_k;
+  for (int q0 = 0; q0 < n1; q0 += kEiiThreads) {
+    const int q = q0 + tid;
+    double ga[kEiiMaxNk], H[kEiiMaxNk];
+#pragma unroll
+    for (int b = 0; b < kEiiMaxNk; ++b) {
+      ga[b] = 0.0;
+      H[b] = 0.0;
+    }
+    if (q < n1) {
+      const int pan = q >> 3, node = q & 7;
+      int s = 0;
+      while (pan >= outer.start[s + 1]) ++s;
+      const double ph = (outer.p[s + 1] - outer.p[s]) / outer.npan[s];
+      const double mid = outer.p[s] + (pan - outer.start[s] + 0.5) * ph;
+      const double r1 = mid + 0.5 * ph * gl.x[node], w1 = 0.5 * ph * gl.w[node];
+      g_bins(l, r1, inv_r0, n_k, ek, coef, tab, ga);
+      if (x == 0.0) {
+        // limit x -> 0: 4 pi int r^2 g^a g^b dr
+#pragma unroll
+        for (int b = 0; b < kEiiMaxNk; ++b) {
+          H[b] = ga[b];
+          ga[b] *= w1 * r1 * r1;
+        }
+      } else {
+        const double lo2 = fabs(x - r1), hi2 = fmin(r0, r1 + x);
+        const double c1 = (r1 - x) * (r1 + x), inv2r1 = 0.5 / r1;
+        if (hi2 > lo2) {
+          Pieces inner;
+          make_pieces(lo2, hi2, joins, 2, hmax, inner);
+          for (int s2 = 0; s2 < inner.n; ++s2) {
+            const double a2 = inner.p[s2];
+            const int np2 = inner.npan[s2];
+            if (np2 == 0) continue;
+            const double ph2 = (inner.p[s2 + 1] - a2) / np2;
+            for (int p2 = 0; p2 < np2; ++p2) {
+              const double mid2 = a2 + (p2 + 0.5) * ph2;
+              for (int j = 0; j < 8; ++j) {
+                const double r2 = mid2 + 0.5 * ph2 * gl.x[j];
+                double D = (c1 + r2 * r2) * inv2r1 / r2;
+                D = fmin(1.0, fmax(-1.0, D));
+                const double wl = 0.5 * ph2 * gl.w[j] * r2 * legendre_l(l, D);
+                double gb[kEiiMaxNk];
+                g_bins(l, r2, inv_r0, n_k, ek, coef, tab, gb);
+#pragma unroll
+                for (int b = 0; b < kEiiMaxNk; ++b) H[b] = fma(wl, gb[b], H[b]);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < kEiiMaxNk; ++b) ga[b] *= w1 * r1;
+      }
+    }
+    for (int half = 0; half < 2; ++half) {
+      constexpr int kHalf = kEiiThreads / 2;
+      if ((tid >= kHalf) == (half == 1)) {
+#pragma unroll
+        for (int b = 0; b < kEiiMaxNk; ++b) {
+          A[tid - half * kHalf][b] = ga[b];
+          Hs[tid - half * kHalf][b] = H[b];
+        }
+      }
+      __syncthreads();
+      if (tid < nab) {
+        const int cnt = min(kHalf, n1 - q0 - half * kHalf);
+        for (int j = 0; j < cnt; ++j) acc = fma(A[j][my_a], Hs[j][my_b], acc);
+      }
+      __syncthreads();
+    }
+  }
+  if (tid < nab) {
+    const double pref = x == 0.0 ? 4.0 * kPi : 2.0 * kPi / x;
+    table[(size_t(l) * nab + tid) * stride + m] = pref * acc;
+  }
+}
+
+// ------------------------------------------------------------ pair sweep
+constexpr int kHistThreads = 512;  // 8 waves; one home tile shared by all
+constexpr int kHistTile = 64;
+
+// Persistent workgroups take home tiles (unit = a home cell's tile of up to
+// 64 points) from a counter; the waves of a workgroup split the unit's
+// neighbour tiles (14 half-stencil cells, each in tiles of 64 points): each
+// lane holds one neighbour point and runs over the home tile, read from LDS
+// by broadcast.  A (pair, image) with r^2 < (2 R0)^2 (the exact double
+// predicate of the pair counts) adds w_i w_j l_q(t) to the four nodes around
+// x = r; without masks every unordered pair counts both ways (factor 2).
+template <bool MASKED>
+__global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, double L, double lim2, double inv_h,
+                                                            int n_x, const int *__restrict__ unit_cell,
+                                                            const int *__restrict__ unit_tile, int64_t n_units,
+                                                            unsigned long long *__restrict__ counter,
+                                                            unsigned long long *__restrict__ ordered,
+                                                            double *__restrict__ partial) {
+  extern __shared__ double hist[];  // n_x + 1 nodes
+  __shared__ double4 home[kHistTile];
+  __shared__ int hm[kHistTile];
+  __shared__ int64_t nb_start[14];
+  __shared__ int nb_count[14], nb_first[15];
+  __shared__ double nb_off[14][3];
+  __shared__ int64_t cur_unit;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int kWaves = kHistThreads / 64;
+  for (int i = tid; i <= n_x; i += kHistThreads) hist[i] = 0.0;
+  unsigned long long ord = 0;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) cur_unit = int64_t(atomicAdd(counter, 1ull));
+    __syncthreads();
+    const int64_t unit = cur_unit;
+    if (unit >= n_units) break;
+    const int cell = unit_cell[unit];
+    const int i0 = unit_tile[unit] * kHistTile;
+    const int cz = cell % nc, cy = (cell / nc) % nc, cx = cell / (nc * nc);
+    const int64_t hs = s.cell_start[cell];
+    const int ni = int(s.cell_start[cell + 1] - hs);
+    const int ti = min(kHistTile, ni - i0);
+    if (tid < ti) {
+      const int64_t i = hs + i0 + tid;
+      home[tid] = make_double4(s.x[i], s.y[i], s.z[i], s.w[i]);
+      if (MASKED) hm[tid] = s.m ? int(s.m[i]) : 1;
+    }
+    if (tid < 14) {
+      int ox, oy, oz;
+      if (tid == 0) {
+        ox = oy = oz = 0;
+      } else {
+        const int t = tid + 13;
+        ox = t / 9 - 1;
+        oy = (t / 3) % 3 - 1;
+        oz = t % 3 - 1;
+      }
+      int sx = 0, sy = 0, sz = 0;
+      int nx = cx + ox, ny = cy + oy, nz = cz + oz;
+      if (nx >= nc) { nx -= nc; sx = 1; } else if (nx < 0) { nx += nc; sx = -1; }
+      if (ny >= nc) { ny -= nc; sy = 1; } else if (ny < 0) { ny += nc; sy = -1; }
+      if (nz >= nc) { nz -= nc; sz = 1; } else if (nz < 0) { nz += nc; sz = -1; }
+      const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
+      nb_start[tid] = s.cell_start[nb];
+      nb_count[tid] = int(s.cell_start[nb + 1] - s.cell_start[nb]);
+      nb_off[tid][0] = double(sx) * L;
+      nb_off[tid][1] = double(sy) * L;
+      nb_off[tid][2] = double(sz) * L;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // neighbour tiles; in the home cell only tiles from the home tile on
+      // hold pairs j > i
+      int tot = 0;
+      for (int st = 0; st < 14; ++st) {
+        nb_first[st] = tot;
+        const int t0 = st == 0 ? i0 / kHistTile : 0;
+        tot += max(0, (nb_count[st] + kHistTile - 1) / kHistTile - t0);
+      }
+      nb_first[14] = tot;
+    }
+    __syncthreads();
+    const int items = nb_first[14];
+    for (int it = wave; it < items; it += kWaves) {
+      int st = 0;
+      while (it >= nb_first[st + 1]) ++st;
+      const int j0 = ((st == 0 ? i0 / kHistTile : 0) + it - nb_first[st]) * kHistTile;
+      const int tj = min(kHistTile, nb_count[st] - j0);
+      const bool self = st == 0;
+      const double offx = nb_off[st][0], offy = nb_off[st][1], offz = nb_off[st][2];
+      double jx = 0.0, jy = 0.0, jz = 0.0, jw = 0.0;
+      int jm = 0;
+      if (lane < tj) {
+        const int64_t j = nb_start[st] + j0 + lane;
+        jx = s.x[j];
+        jy = s.y[j];
+        jz = s.z[j];
+        jw = s.w[j];
+        if (MASKED) jm = s.m ? int(s.m[j]) : 1;
+      }
+      const int jg = j0 + lane;  // index of this lane's point within its cell
+      if (lane < tj) {
+        for (int ii = 0; ii < ti; ++ii) {
+          if (self && jg <= i0 + ii) continue;
+          const double4 p = home[ii];
+          double dx = p.x - jx, dy = p.y - jy, dz = p.z - jz;
+          dx -= offx;
+          dy -= offy;
+          dz -= offz;
+          double r2;
+          {
+#pragma clang fp contract(off)
+            const double a = dx * dx, b = dy * dy, c = dz * dz;
+            r2 = (a + b) + c;
+          }
+          if (r2 < lim2) {
+            const int mult = MASKED ? hm[ii] + jm : 2;
+            if (mult == 0) continue;
+            ord += unsigned(mult);
+            const double ww = p.w * jw * double(mult);
+            const double sx = sqrt(r2) * inv_h;
+            int mi = int(sx);
+            if (mi > n_x - 1) mi = n_x - 1;
+            const double t = sx - double(mi);
+            const double tm1 = t - 1.0, tm2 = t - 2.0, tp1 = t + 1.0;
+            const double lm1 = -t * tm1 * tm2 * (1.0 / 6.0);
+            const double l0 = tp1 * tm1 * tm2 * 0.5;
+            const double l1 = -tp1 * t * tm2 * 0.5;
+            const double l2 = tp1 * t * tm1 * (1.0 / 6.0);
+            // node m-1 < 0 folds onto node 1 (E even); nodes >= n_x hold E = 0
+            atomicAdd(&hist[mi == 0 ? 1 : mi - 1], ww * lm1);
+            atomicAdd(&hist[mi], ww * l0);
+            if (mi + 1 < n_x) atomicAdd(&hist[mi + 1], ww * l1);
+            if (mi + 2 < n_x) atomicAdd(&hist[mi + 2], ww * l2);
+          }
+        }
+      }
+    }
+  }
+  // ordered (pair, image) terms of the workgroup, and its histogram
+  for (int o = 32; o > 0; o >>= 1) ord += __shfl_xor(ord, o);
+  if (lane == 0 && ord) atomicAdd(ordered, ord);
+  __syncthreads();
+  double *out = partial + size_t(blockIdx.x) * (size_t(n_x) + 1);
+  for (int i = tid; i <= n_x; i += kHistThreads) out[i] = hist[i];
+}
+
+// H[m] = sum over workgroups of partial[wg][m], in workgroup order.
+__global__ void k_ddr2_reduce(const double *__restrict__ partial, int nwg, int n_nodes, double *__restrict__ H) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_nodes) return;
+  double s = 0.0;
+  for (int g = 0; g < nwg; ++g) s += partial[size_t(g) * n_nodes + m];
+  H[m] = s;
+}
+
+// T[row] = sum_m table[row][m] H[m]; one workgroup per (l, a, b) row, a
+// fixed-order tree reduction.
+__global__ __launch_bounds__(256) void k_ddr2_contract(const double *__restrict__ table, const double *__restrict__ H,
+                                                       int n_nodes, double *__restrict__ T) {
+  __shared__ double red[256];
+  const double *row = table + size_t(blockIdx.x) * n_nodes;
+  double s = 0.0;
+  for (int m = threadIdx.x; m < n_nodes; m += 256) s = fma(row[m], H[m], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) T[blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------------------------ host
+int eii_default_nodes(double r0, double k_max) {
+  // k_max h <= 0.05: the cubic's error is ~0.02 (k h)^4 ~ 1e-7 of the kernel
+  const double want = 40.0 * k_max * r0;
+  int n = int(std::min(double(kEiiMaxNodes), ceil(want / 64.0) * 64.0));
+  return std::max(64, n);
+}
+
+void eii_table(Ctx &c, double r0, int n_k, const double *k_edges, int ell_max, int n_x, double *table) {
+  std::vector<double> ek(static_cast<size_t>(2 * (n_k + 1))), coef(static_cast<size_t>(n_k));
+  for (int e = 0; e <= n_k; ++e) {
+    ek[size_t(2 * e)] = k_edges[e];
+    ek[size_t(2 * e + 1)] = k_edges[e] * k_edges[e] * k_edges[e];
+  }
+  for (int b = 0; b < n_k; ++b) coef[size_t(b)] = 3.0 / (ek[size_t(2 * b + 3)] - ek[size_t(2 * b + 1)]);
+  double *dk = static_cast<double *>(ensure(c, c.eii_consts, size_t(3 * n_k + 2) * 8));
+  HIPSTER_HIP(hipMemcpyAsync(dk, ek.data(), ek.size() * 8, hipMemcpyHostToDevice, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(dk + ek.size(), coef.data(), coef.size() * 8, hipMemcpyHostToDevice, c.stream));
+  const double k_max = k_edges[n_k];
+  const double hmax = std::min(0.125 * r0, 1.5 / k_max);
+  k_eii_table<<<dim3(unsigned(n_x + 1), unsigned(ell_max + 1)), dim3(kEiiThreads), 0, c.stream>>>(
+      r0, 2.0 * r0 / n_x, n_x, n_k, dk, dk + ek.size(), gauss_legendre8(), hmax, table);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+size_t ddr2_max_nodes(Ctx &c) {
+  int lds = 0;
+  HIPSTER_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device));
+  hipFuncAttributes fa{};
+  HIPSTER_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_ddr2_hist<true>)));
+  const long avail = long(lds) - long(fa.sharedSizeBytes);
+  return avail > 8 ? size_t(avail / 8) : 0;
+}
+
+void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, const double *table, int rows,
+                double *T, unsigned long long *ordered) {
+  const PairUnits u = make_pair_units(c, s, g);
+  const int n_nodes = n_x + 1;
+  int nwg = 0;
+  {
+    int dev = c.device, cus = 0;
+    HIPSTER_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    nwg = std::max(1, cus) * 2;
+  }
+  double *partial = static_cast<double *>(ensure(c, c.ddr2_partial, size_t(nwg) * n_nodes * 8));
+  double *H = static_cast<double *>(ensure(c, c.ddr2_hist, size_t(n_nodes) * 8));
+  unsigned long long *counter = static_cast<unsigned long long *>(ensure(c, c.ddr2_counter, 8));
+  HIPSTER_HIP(hipMemsetAsync(counter, 0, 8, c.stream));
+  const size_t lds = size_t(n_nodes) * 8;
+  const double lim2 = (2.0 * r0) * (2.0 * r0), inv_h = n_x / (2.0 * r0);
+  if (u.n > 0) {
+    if (s.m)
+      k_ddr2_hist<true><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
+          s, g.nc, g.L, lim2, inv_h, n_x, u.cell, u.tile, u.n, counter, ordered, partial);
+    else
+      k_ddr2_hist<false><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
+          s, g.nc, g.L, lim2, inv_h, n_x, u.cell, u.tile, u.n, counter, ordered, partial);
+    HIPSTER_HIP(hipGetLastError());
+  } else {
+    HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_nodes * 8, c.stream));
+  }
+  k_ddr2_reduce<<<dim3(unsigned((n_nodes + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_nodes, H);
+  HIPSTER_HIP(hipGetLastError());
+  k_ddr2_contract<<<dim3(unsigned(rows)), dim3(256), 0, c.stream>>>(table, H, n_nodes, T);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+}  // namespace hipster

@@ -1,0 +1,189 @@
+"""GPU parity of the analytic DDR^II path (hipster_eii_table,
+hipster_bk_ell_analytic) against the FP64 oracle.
+
+* The E^II table: both sides integrate the same band integral in double
+  precision with different Gauss-Legendre rules, so they agree to quadrature
+  accuracy: |dE| <= 1e-10 of the largest |E| of that (l, a, b) row plus
+  1e-13 of the largest of that l.
+* T^ab_l = sum_{i!=j} w_i w_j E^II(r_ij): the interpolation is the same
+  definition on both sides; the tables differ as above and the GPU sums in a
+  different order, so |dT| <= 1e-9 of the sum of |terms| (the oracle's L1).
+* The (pair, image) count inside 2 R0 and the data-data count inside R0 are
+  bit-exact; the data-primary sums G_D, C_D, S0 and B follow the bispectrum
+  tolerances (FP64 1e-12, mixed 1e-6 relative, or a scaled bound).
+At the full 5e5-point size the pair sums are checked on a subset of primaries
+and the table through its exact volume integral."""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-12, 1e-14), "mixed": (1e-6, 2.0 ** -24)}
+
+
+def _scale(X):
+    d = np.sqrt(np.abs(np.einsum("lii->li", X)))
+    return d[:, :, None] * d[:, None, :]
+
+
+def check(got, ref, scale, rel_tol, sc_tol, what):
+    err = np.abs(got - ref)
+    rel = err / np.maximum(np.abs(ref), 1e-300)
+    scn = err / np.maximum(scale, 1e-300)
+    ok = (rel <= rel_tol) | (scn <= sc_tol)
+    assert ok.all(), f"{what}: worst rel {rel.max():.3e}, worst scaled {scn.max():.3e}, failing {np.argwhere(~ok)[:6].tolist()}"
+
+
+def check_table(got, ref):
+    row = np.abs(ref).max(axis=-1, keepdims=True)
+    per_l = np.abs(ref).reshape(ref.shape[0], -1).max(axis=1)[:, None, None, None]
+    err = np.abs(got - ref)
+    bound = 1e-10 * row + 1e-13 * per_l
+    assert np.all(err <= bound), f"table: worst {(err / np.maximum(row, 1e-300)).max():.3e} of the row maximum"
+
+
+def test_table_small():
+    import paper_2005_01739_amd as hp
+    r0, k, lmax, n_x = 20.0, np.linspace(0.1, 0.5, 4), 3, 32
+    got = hp.eii_table(r0, k, lmax, n_x)
+    ref = oracle.eii_table(r0, k, lmax, n_x)
+    assert got.shape == ref.shape
+    assert np.all(got[..., n_x] == 0.0)
+    check_table(got, ref)
+
+
+def test_table_nodes_at_large_k_r0():
+    # 12 bins over [0.5, 3] with R0 = 30 (k_max R0 = 90): spot nodes against
+    # per-node oracle integrals, run in parallel threads
+    import paper_2005_01739_amd as hp
+    r0, k, lmax, n_x = 30.0, np.linspace(0.5, 3.0, 13), 5, 64
+    got = hp.eii_table(r0, k, lmax, n_x)
+    picks = [(0, 0), (5, 1), (2, 17), (3, 40), (1, 63)]
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        refs = list(ex.map(lambda p: oracle.eii(p[1] * 2 * r0 / n_x, r0, p[0], k), picks))
+    for (l, m), ref in zip(picks, refs):
+        scale = np.abs(got[l]).max()
+        assert np.abs(got[l, :, :, m] - ref).max() <= 1e-10 * scale, (l, m)
+
+
+def run_case(pos, w, L, r0, k, lmax, n_x, precision, mask=None):
+    import torch
+    import paper_2005_01739_amd as hp
+    ref = oracle.bk_ell_analytic(pos, w, L, r0, k, lmax, n_x, mask_d=mask)
+    t = lambda a: None if a is None else torch.from_numpy(a).cuda()
+    got, info = hp.bk_ell_analytic(t(pos), t(w), box=L, r0=r0, k_edges=k, ell_max=lmax, n_x=n_x,
+                                   precision=precision, primary_mask=mask, return_diag=True)
+    assert info["eii_nodes"] == n_x
+    assert info["n_pairs"] == ref["n_pairs_dd"]
+    assert info["n_pairs_2r0"] == ref["n_pairs_2r0"]
+    rel_tol, sc_tol = TOL[precision]
+    scales = {name: _scale(ref[name]) for name in ("gd", "cd")}
+    for name in ("gd", "cd"):
+        check(info[name], ref[name], scales[name], rel_tol, sc_tol, name)
+    check(info["t2"], ref["t2"], ref["t2_l1"], 0.0, 1e-9, "t2")
+    V = L ** 3
+    p1 = len(pos) if w is None else float(np.sum(np.asarray(w, np.float64)))
+    nw = p1 / V
+    fac = np.array([(2 * l + 1) for l in range(lmax + 1)])[:, None, None] / (V * nw ** 3)
+    sc = fac * (scales["gd"] + scales["cd"] + nw * ref["t2_l1"] * max(1e-9 / sc_tol, 1.0))
+    wt = np.abs(ref["wtilde"])
+    sc[0] += (np.outer(wt, np.abs(ref["s0"])) + np.outer(np.abs(ref["s0"]), wt)) / (V * nw ** 2) + 2 * np.outer(wt, wt)
+    check(got, ref["bk"], sc, rel_tol, sc_tol, "bk")
+    return got, info, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_thomas_weighted_several_images(precision):
+    # 2 R0 = 40 > L/2: pairs have up to several images inside 2 R0 (2 cells per axis)
+    L = 100.0
+    pos = synthetic.thomas(1500, L, 10, 2.0, 0.0, 31, np.float32)
+    w = synthetic.uniform_weights(1500, 32, np.float32)
+    run_case(pos, w, L, 20.0, np.linspace(0.05, 0.4, 5), 4, 64, precision)
+
+
+def test_many_cells_masked():
+    # 2 R0 = 24 in L = 150: 6 cells per axis; half the primaries masked out
+    L = 150.0
+    pos = synthetic.thomas(2500, L, 10, 1.5, 2.0, 41, np.float64)
+    mask = (np.arange(2500) % 2 == 1).astype(np.uint8)
+    run_case(pos, None, L, 12.0, np.linspace(0.2, 1.2, 6), 3, 96, "fp64", mask=mask)
+
+
+def test_edge_cases():
+    import paper_2005_01739_amd as hp
+    # two points; R0 = L/2 (2 R0 = L: one cell, every image in play); a pair
+    # at a node separation and coincident points
+    for pos, L, r0 in ((np.array([[1.0, 2.0, 3.0], [4.0, 2.5, 3.5]]), 20.0, 10.0),
+                       (np.array([[5.0, 5.0, 5.0], [5.0, 5.0, 5.0], [15.0, 5.0, 5.0]]), 20.0, 6.0),
+                       (synthetic.poisson(40, 30.0, 51), 30.0, 15.0)):
+        run_case(pos, None, L, r0, np.array([0.1, 0.3, 0.6]), 2, 16, "fp64")
+    # errors: n_x outside [2, 8192], k_max R0 beyond the table's range
+    pos = synthetic.poisson(100, 50.0, 52)
+    for n_x in (1, 8193):
+        with pytest.raises(hp.HipsterError) as e:
+            hp.bk_ell_analytic(pos, box=50.0, r0=10.0, k_edges=[0.1, 0.2], ell_max=2, n_x=n_x)
+        assert e.value.name == "HIPSTER_EUNSUPPORTED"
+    with pytest.raises(hp.HipsterError) as e:
+        hp.bk_ell_analytic(pos, box=50.0, r0=10.0, k_edges=[0.1, 2e5], ell_max=2, precision="fp64")
+    assert e.value.name == "HIPSTER_EUNSUPPORTED"
+
+
+def test_default_nodes_and_table_reuse():
+    import paper_2005_01739_amd as hp
+    L = 100.0
+    pos = synthetic.thomas(800, L, 8, 2.0, 0.0, 61, np.float32)
+    k = np.linspace(0.2, 1.0, 5)
+    ctx = hp.Context(0)
+    a, ia = hp.bk_ell_analytic(pos, box=L, r0=15.0, k_edges=k, ell_max=2, ctx=ctx, return_diag=True)
+    b, ib = hp.bk_ell_analytic(pos, box=L, r0=15.0, k_edges=k, ell_max=2, ctx=ctx, return_diag=True)
+    # default: smallest multiple of 64 with k_max h <= 0.05, at least 64
+    assert ia["eii_nodes"] == max(64, int(np.ceil(40 * 1.0 * 15.0 / 64)) * 64)
+    assert ia["ms_eii_table"] > 0.0 and ib["ms_eii_table"] == 0.0
+    assert np.allclose(a, b, rtol=1e-13, atol=1e-13 * np.abs(a).max())
+
+
+def test_full_size_bispectrum_workload_subset():
+    # the 5e5-point Thomas box (L = 500, R0 = 30) with a subset of primaries;
+    # 3 bins over the workload's k range keep the oracle's table quick
+    import torch
+    import paper_2005_01739_amd as hp
+    L, r0 = 500.0, 30.0
+    pos = synthetic.thomas(500_000, L, 10, 3.0, 0.0, 3, np.float32)
+    mask = np.zeros(len(pos), np.uint8)
+    mask[np.random.default_rng(7).choice(len(pos), 48, replace=False)] = 1
+    k = np.linspace(0.5, 3.0, 4)
+    ref = oracle.ddr2(pos, None, L, r0, k, 1, 64, mask=mask)
+    got, info = hp.bk_ell_analytic(torch.from_numpy(pos).cuda(), box=L, r0=r0, k_edges=k, ell_max=1, n_x=64,
+                                   precision="mixed", primary_mask=mask, return_diag=True)
+    assert info["n_pairs_2r0"] == ref["n_pairs"]
+    check(info["t2"], ref["t2"], ref["l1"], 0.0, 1e-9, "t2")
+
+
+def test_full_size_table_volume_integral():
+    # 4 pi int_0^{2 R0} x^2 E^{II,ab}_l dx = delta_l0 W~^a W~^b at the
+    # bispectrum workload's bins and default table size, integrating the
+    # interpolating cubics of the table exactly
+    import paper_2005_01739_amd as hp
+    r0, k, lmax = 30.0, np.linspace(0.5, 3.0, 13), 5
+    n_x = max(64, int(np.ceil(40 * 3.0 * r0 / 64)) * 64)
+    E = hp.eii_table(r0, k, lmax, n_x)
+    h = 2 * r0 / n_x
+    gx, gw = np.polynomial.legendre.leggauss(4)
+    t = 0.5 * (gx + 1.0)
+    basis = np.stack([-t * (t - 1) * (t - 2) / 6, (t + 1) * (t - 1) * (t - 2) / 2,
+                      -(t + 1) * t * (t - 2) / 2, (t + 1) * t * (t - 1) / 6])  # [4 nodes, 4 points]
+    ext = np.concatenate([E[..., 1:2], E, np.zeros(E.shape[:-1] + (1,))], axis=-1)  # nodes -1 .. n_x + 1
+    tot = np.zeros(E.shape[:-1])
+    for m in range(n_x):
+        vals = np.einsum("...q,qp->...p", ext[..., m:m + 4], basis)
+        x = (m + t) * h
+        tot += np.einsum("...p,p->...", vals, 0.5 * gw * h * 4 * np.pi * x * x)
+    wt = hp.wtilde(r0, k)
+    WW = np.outer(wt, wt)
+    assert np.abs(tot[0] - WW).max() <= 1e-6 * np.abs(WW).max()
+    assert np.abs(tot[1:]).max() <= 1e-6 * np.abs(WW).max()
