@@ -134,7 +134,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pk",
-                    choices=["pk", "pk-fp64", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64"])
+                    choices=["pk", "pk-fp64", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64",
+                             "bk-analytic", "bk-analytic-fp64", "bk5-analytic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-primaries", type=int, default=16384)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -205,6 +206,23 @@ def main():
         units_per_pair = n_k * (wl.ell_max_b + 1) ** 2
         cfg = {"workload": wl.name, "n_points": wl.n, "n_randoms": int(rnd.shape[0]), "box": wl.box, "r0": wl.r0,
                "n_k": n_k, "ell_max": wl.ell_max_b, "precision": prec}
+    elif args.workload in ("bk-analytic", "bk-analytic-fp64", "bk5-analytic"):
+        wl = synthetic.workload(5 if args.workload == "bk5-analytic" else 3)
+        prec = "fp64" if args.workload == "bk-analytic-fp64" else "mixed"
+        pos = torch.from_numpy(wl.pos).cuda()
+        w = None if wl.weights is None else torch.from_numpy(wl.weights).cuda()
+        n_k = len(wl.k_edges_b) - 1
+        n_tables = (wl.ell_max_b + 1) * n_k * (n_k + 1) // 2
+
+        def step():
+            out, info = hp.bk_ell_analytic(pos, w, box=wl.box, r0=wl.r0, k_edges=wl.k_edges_b,
+                                           ell_max=wl.ell_max_b, precision=prec, return_diag=True)
+            info = dict(info, sweep_launches=1, n_pairs_rand=0)
+            return out, info
+        units_per_pair = n_k * (wl.ell_max_b + 1) ** 2
+        cfg = {"workload": wl.name + "_analytic_ddr2", "n_points": wl.n, "n_randoms": 0, "box": wl.box,
+               "r0": wl.r0, "n_k": n_k, "ell_max": wl.ell_max_b, "precision": prec,
+               "ddr2": "E^II kernel table + pair sweep to 2 R0 (no randoms)"}
     else:
         boxes = synthetic.batch_boxes(64, args.scale)
         specs = []
@@ -229,6 +247,7 @@ def main():
         step()
     torch.cuda.synchronize()
     sweep_ms, far_ms, launches, pairs, pairs_r, far_pairs = 0.0, 0.0, 0, 0, 0, 0
+    ddr2_ms, table_ms, pairs_2r0 = 0.0, 0.0, 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         _, info = step()
@@ -238,9 +257,38 @@ def main():
         pairs = info["n_pairs"]
         pairs_r = info.get("n_pairs_rand", 0)
         far_pairs = info.get("n_pairs_far", 0)
+        ddr2_ms += info.get("ms_ddr2", 0.0)
+        table_ms += info.get("ms_eii_table", 0.0)
+        pairs_2r0 = info.get("n_pairs_2r0", 0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
+    if args.workload in ("bk-analytic", "bk-analytic-fp64", "bk5-analytic"):
+        # DD pairs inside R0 carry n_k (l_max+1)^2 weights (the a_lm sums); each
+        # (pair, image) inside 2 R0 carries one interpolated kernel value per
+        # (l, a <= b) table
+        value = (pairs * units_per_pair + pairs_2r0 * n_tables) / (dt / args.steps)
+        avg_launch_ms = sweep_ms / max(launches, 1)
+        flops = pairs * bk_flops_per_pair(n_k, wl.ell_max_b) / (launches / args.steps)
+        achieved = flops / (avg_launch_ms * 1e-3) / 1e12
+        # the table depends on (R0, bins) only: built in the warm-up, reused by the
+        # context in the timed steps; its cold build time is reported beside
+        _, cold = hp.bk_ell_analytic(pos, w, box=wl.box, r0=wl.r0, k_edges=wl.k_edges_b, ell_max=wl.ell_max_b,
+                                     precision=prec, ctx=hp.Context(0), return_diag=True)
+        out = {"metric": METRIC, "value": value, "unit": "pair-weights/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f64+f32" if prec == "mixed" else "f64", "data": "synthetic",
+               "config": cfg,
+               "roofline": {"bound": "alu", "kernel": "k_bk_fused", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+                            "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                            "frac_fp64": achieved / PEAK_FP64_TFLOPS, "traffic": None, "flops_per_launch": flops,
+                            "avg_launch_ms": avg_launch_ms},
+               "pairs_per_step": pairs, "pairs_2r0_per_step": pairs_2r0, "n_tables": n_tables,
+               "avg_ddr2_ms": ddr2_ms / args.steps, "table_ms_in_steps": table_ms / args.steps,
+               "table_ms_cold": cold["ms_eii_table"], "eii_nodes": cold["eii_nodes"],
+               "ms_per_step_with_cold_table": ms_step + cold["ms_eii_table"]}
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "batch":
         value = 64 / (dt / args.steps)
         out = {"metric": METRIC, "value": value, "unit": "boxes/s", "n_gpus": 1, "steps": args.steps,

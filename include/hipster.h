@@ -156,12 +156,12 @@ hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data,
  * over the band |r1 - r2| <= x <= r1 + r2 of [0, R0]^2, g^a_l = jbar^a_l W,
  * Delta = (r1^2 + r2^2 - x^2)/(2 r1 r2).  As the paper suggests, E is
  * tabulated (double precision, composite Gauss-Legendre) on the nodes
- * x_m = m h, h = 2 R0 / n_x, m = 0..n_x, and interpolated per pair by the cubic
- * through the nodes m-1..m+2 around x (m = floor(x/h); E(-h) = E(h), nodes at
- * and beyond 2 R0 hold 0).  The interpolation error is about 0.02 (k_max h)^4
- * of the kernel.
+ * x_m = m h, h = 2 R0 / n_x, m = 0..n_x, and interpolated per pair by the
+ * quintic through the nodes m-2..m+3 around x (m = floor(x/h); E(-x) = E(x),
+ * nodes at and beyond 2 R0 hold 0).  The interpolation error is about
+ * 5e-3 (k_max h)^6 of the kernel.
  * n_x: table intervals, 0 for the default (the smallest multiple of 64 with
- * k_max h <= 0.05, at least 64, at most 8192); 2 <= n_x <= 8192 and the device
+ * k_max h <= 0.15, at least 64, at most 8192); 2 <= n_x <= 8192 and the device
  * must hold an (n_x + 1)-entry double histogram in one workgroup's LDS, else
  * HIPSTER_EUNSUPPORTED.  k_edges[n_k] * R0 <= 1e6 (HIPSTER_EUNSUPPORTED).
  * The table is cached in the context and reused while (R0, n_x, ell_max,

@@ -856,31 +856,34 @@ int oracle_eii_table(double r0, int n_k, const double *k, int ell_max, int n_x, 
     return bad ? -1 : 0;
 }
 
-/* The tabulated kernel at separation r (0 <= r < 2 R0): the cubic through the
- * four nodes m-1 .. m+2 around r, m = floor(r / h), t = r / h - m (four-point
- * Lagrange interpolation), with the nodes outside the table taken from the
- * symmetry of E as a function of the pair vector (E(-h) = E(h)) and from its
- * support (E(2 R0 + h) = 0).  tab: one (a, b, l) row of n_x + 1 nodes. */
+/* The tabulated kernel at separation r (0 <= r < 2 R0): the quintic through
+ * the six nodes m-2 .. m+3 around r, m = floor(r / h), t = r / h - m
+ * (six-point Lagrange interpolation), with the nodes outside the table taken
+ * from the symmetry of E as a function of the pair vector (E(-x) = E(x)) and
+ * from its support (E = 0 from 2 R0 on).  tab: one (a, b, l) row of n_x + 1
+ * nodes. */
 static double eii_interp(const double *tab, int n_x, double r, double h)
 {
     double s = r / h;
     int m = (int)floor(s);
     if (m > n_x - 1) m = n_x - 1;
     double t = s - m;
-    double e[4];
-    for (int q = -1; q <= 2; ++q) {
+    double sum = 0.0;
+    for (int q = -2; q <= 3; ++q) {
         int node = m + q;
         double v;
-        if (node < 0) v = tab[-node];
-        else if (node > n_x) v = 0.0;
-        else v = tab[node];
-        e[q + 1] = v;
+        if (node < 0) node = -node;
+        v = node > n_x ? 0.0 : tab[node];
+        /* Lagrange basis of node q over the nodes -2 .. 3 */
+        double num = 1.0, den = 1.0;
+        for (int i = -2; i <= 3; ++i) {
+            if (i == q) continue;
+            num *= t - i;
+            den *= q - i;
+        }
+        sum += v * (num / den);
     }
-    double lm1 = -t * (t - 1.0) * (t - 2.0) / 6.0;
-    double l0 = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
-    double l1 = -(t + 1.0) * t * (t - 2.0) / 2.0;
-    double l2 = (t + 1.0) * t * (t - 1.0) / 6.0;
-    return lm1 * e[0] + l0 * e[1] + l1 * e[2] + l2 * e[3];
+    return sum;
 }
 
 /* T^{ab}_l = sum_{i != j} w_i w_j E^{II,ab}_l(|x_i - x_j + n L|) over ordered

@@ -9,12 +9,12 @@
 // bins) and interpolated per pair:
 //
 //   k_eii_table   E on the nodes x_m = m h, h = 2 R0 / n_x, by composite
-//                 8-point Gauss-Legendre in double precision (one workgroup
+//                 16-point Gauss-Legendre in double precision (one workgroup
 //                 per (l, m); the outer r1 nodes are spread over the threads,
 //                 each thread sums its inner r2 integral for every bin);
-//   k_ddr2_hist   every (pair, periodic image) inside 2 R0 adds its four
-//                 cubic-interpolation weights l_q(t), times w_i w_j, to the
-//                 nodes m-1 .. m+2 of an LDS histogram: the pair sum of the
+//   k_ddr2_hist   every (pair, periodic image) inside 2 R0 adds its six
+//                 interpolation weights l_q(t), times w_i w_j, to the nodes
+//                 m-2 .. m+3 of an LDS histogram: the pair sum of the
 //                 interpolated kernel is then sum_m E_m H_m exactly, so the
 //                 sweep does the same small work for any number of bins and
 //                 multipoles;
@@ -23,9 +23,9 @@
 //                 contraction T^ab_l = sum_m E^ab_l(x_m) H_m.
 //
 // Interpolation (a reading: the paper leaves the scheme open): on
-// [x_m, x_{m+1}) the cubic through the nodes m-1 .. m+2, t = x/h - m; the
-// node below 0 takes E(-h) = E(h) (E is a smooth function of the pair vector,
-// even in x) and the nodes at and beyond 2 R0 hold E = 0 (its support).
+// [x_m, x_{m+1}) the quintic through the nodes m-2 .. m+3, t = x/h - m; nodes
+// below 0 take E(-x) = E(x) (E is a smooth function of the pair vector, even
+// in x) and the nodes at and beyond 2 R0 hold E = 0 (its support).
 #include <math.h>
 
 #include <algorithm>
@@ -39,15 +39,19 @@ namespace hipster {
 constexpr int kEiiThreads = 256;
 constexpr int kEiiMaxNk = 16;
 
-// Gauss-Legendre nodes and weights on [-1, 1] (8 points), computed on the
-// host by Newton's method on the Legendre polynomial.
-struct GL8 {
-  double x[8], w[8];
+// Gauss-Legendre nodes and weights on [-1, 1] (16 points), computed on the
+// host by Newton's method on the Legendre polynomial.  Panels are at most
+// 8 / k_max wide: the integrands oscillate at up to 2 k_max (a product of two
+// bin averages), so a panel spans at most ~16 radians of phase, where the
+// 16-point rule's error is ~1e-16 relative.
+constexpr int kGL = 16;
+struct GLRule {
+  double x[kGL], w[kGL];
 };
 
-static GL8 gauss_legendre8() {
-  GL8 g{};
-  const int n = 8;
+static GLRule gauss_legendre16() {
+  GLRule g{};
+  const int n = kGL;
   for (int i = 0; i < n; ++i) {
     double z = cos(M_PI * (i + 0.75) / (n + 0.5)), d = 0.0;
     for (int it = 0; it < 50; ++it) {
@@ -167,7 +171,7 @@ __device__ inline void make_pieces(double lo, double hi, const double *cuts, int
 // table[((l n_k + a) n_k + b) (n_x + 1) + m].
 __global__ __launch_bounds__(kEiiThreads) void k_eii_table(double r0, double h, int n_x, int n_k,
                                                            const double *__restrict__ ek_g,
-                                                           const double *__restrict__ coef_g, GL8 gl, double hmax,
+                                                           const double *__restrict__ coef_g, GLRule gl, double hmax,
                                                            double *__restrict__ table) {
   __shared__ double2 tab[kSinCosTab];
   __shared__ double ek[2 * (kEiiMaxNk + 1)], coef[kEiiMaxNk];
@@ -194,7 +198,7 @@ __global__ __launch_bounds__(kEiiThreads) void k_eii_table(double r0, double h, 
     make_pieces(x > r0 ? x - r0 : 0.0, r0, cuts, x > 0.0 ? 10 : 2, hmax, outer);
   }
   __syncthreads();
-  const int n1 = 8 * outer.start[outer.n];
+  const int n1 = kGL * outer.start[outer.n];
   const double joins[2] = {0.5 * r0, 0.75 * r0};
   double acc = 0.0;
   const int my_a = tid / n_k, my_b = tid - my_a * n_k;
@@ -207,7 +211,7 @@ __global__ __launch_bounds__(kEiiThreads) void k_eii_table(double r0, double h, 
       H[b] = 0.0;
     }
     if (q < n1) {
-      const int pan = q >> 3, node = q & 7;
+      const int pan = q / kGL, node = q % kGL;
       int s = 0;
       while (pan >= outer.start[s + 1]) ++s;
       const double ph = (outer.p[s + 1] - outer.p[s]) / outer.npan[s];
@@ -234,7 +238,7 @@ __global__ __launch_bounds__(kEiiThreads) void k_eii_table(double r0, double h, 
             const double ph2 = (inner.p[s2 + 1] - a2) / np2;
             for (int p2 = 0; p2 < np2; ++p2) {
               const double mid2 = a2 + (p2 + 0.5) * ph2;
-              for (int j = 0; j < 8; ++j) {
+              for (int j = 0; j < kGL; ++j) {
                 const double r2 = mid2 + 0.5 * ph2 * gl.x[j];
                 double D = (c1 + r2 * r2) * inv2r1 / r2;
                 D = fmin(1.0, fmax(-1.0, D));
@@ -284,7 +288,8 @@ constexpr int kHistTile = 64;
 // lane holds one neighbour point and runs over the home tile, read from LDS
 // by broadcast.  A (pair, image) with r^2 < (2 R0)^2 (the exact double
 // predicate of the pair counts) adds w_i w_j l_q(t) to the four nodes around
-// x = r; without masks every unordered pair counts both ways (factor 2).
+// x = r (six nodes m-2 .. m+3); without masks every unordered pair counts
+// both ways (factor 2).
 template <bool MASKED>
 __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, double L, double lim2, double inv_h,
                                                             int n_x, const int *__restrict__ unit_cell,
@@ -397,16 +402,19 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
             int mi = int(sx);
             if (mi > n_x - 1) mi = n_x - 1;
             const double t = sx - double(mi);
-            const double tm1 = t - 1.0, tm2 = t - 2.0, tp1 = t + 1.0;
-            const double lm1 = -t * tm1 * tm2 * (1.0 / 6.0);
-            const double l0 = tp1 * tm1 * tm2 * 0.5;
-            const double l1 = -tp1 * t * tm2 * 0.5;
-            const double l2 = tp1 * t * tm1 * (1.0 / 6.0);
-            // node m-1 < 0 folds onto node 1 (E even); nodes >= n_x hold E = 0
-            atomicAdd(&hist[mi == 0 ? 1 : mi - 1], ww * lm1);
-            atomicAdd(&hist[mi], ww * l0);
-            if (mi + 1 < n_x) atomicAdd(&hist[mi + 1], ww * l1);
-            if (mi + 2 < n_x) atomicAdd(&hist[mi + 2], ww * l2);
+            const double tp2 = t + 2.0, tp1 = t + 1.0, tm1 = t - 1.0, tm2 = t - 2.0, tm3 = t - 3.0;
+            // six-point Lagrange weights of the nodes m-2 .. m+3
+            const double a01 = tp2 * tp1, a34 = tm2 * tm3, b = t * tm1;
+            const double lw[6] = {-tp1 * b * a34 * (1.0 / 120.0), tp2 * b * a34 * (1.0 / 24.0),
+                                  -a01 * tm1 * a34 * (1.0 / 12.0), a01 * t * a34 * (1.0 / 12.0),
+                                  -a01 * b * tm3 * (1.0 / 24.0), a01 * b * tm2 * (1.0 / 120.0)};
+            // nodes below 0 fold onto their mirror (E even); nodes >= n_x hold E = 0
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+              int node = mi + q - 2;
+              node = node < 0 ? -node : node;
+              if (node < n_x) atomicAdd(&hist[node], ww * lw[q]);
+            }
           }
         }
       }
@@ -448,8 +456,8 @@ __global__ __launch_bounds__(256) void k_ddr2_contract(const double *__restrict_
 
 // ------------------------------------------------------------------ host
 int eii_default_nodes(double r0, double k_max) {
-  // k_max h <= 0.05: the cubic's error is ~0.02 (k h)^4 ~ 1e-7 of the kernel
-  const double want = 40.0 * k_max * r0;
+  // k_max h <= 0.15: the quintic's error is ~5e-3 (k h)^6 ~ 6e-8 of the kernel
+  const double want = 2.0 * k_max * r0 / 0.15;
   int n = int(std::min(double(kEiiMaxNodes), ceil(want / 64.0) * 64.0));
   return std::max(64, n);
 }
@@ -465,9 +473,9 @@ void eii_table(Ctx &c, double r0, int n_k, const double *k_edges, int ell_max, i
   HIPSTER_HIP(hipMemcpyAsync(dk, ek.data(), ek.size() * 8, hipMemcpyHostToDevice, c.stream));
   HIPSTER_HIP(hipMemcpyAsync(dk + ek.size(), coef.data(), coef.size() * 8, hipMemcpyHostToDevice, c.stream));
   const double k_max = k_edges[n_k];
-  const double hmax = std::min(0.125 * r0, 1.5 / k_max);
+  const double hmax = std::min(0.25 * r0, 8.0 / k_max);
   k_eii_table<<<dim3(unsigned(n_x + 1), unsigned(ell_max + 1)), dim3(kEiiThreads), 0, c.stream>>>(
-      r0, 2.0 * r0 / n_x, n_x, n_k, dk, dk + ek.size(), gauss_legendre8(), hmax, table);
+      r0, 2.0 * r0 / n_x, n_x, n_k, dk, dk + ek.size(), gauss_legendre16(), hmax, table);
   HIPSTER_HIP(hipGetLastError());
 }
 

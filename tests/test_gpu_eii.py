@@ -141,8 +141,8 @@ def test_default_nodes_and_table_reuse():
     ctx = hp.Context(0)
     a, ia = hp.bk_ell_analytic(pos, box=L, r0=15.0, k_edges=k, ell_max=2, ctx=ctx, return_diag=True)
     b, ib = hp.bk_ell_analytic(pos, box=L, r0=15.0, k_edges=k, ell_max=2, ctx=ctx, return_diag=True)
-    # default: smallest multiple of 64 with k_max h <= 0.05, at least 64
-    assert ia["eii_nodes"] == max(64, int(np.ceil(40 * 1.0 * 15.0 / 64)) * 64)
+    # default: smallest multiple of 64 with k_max h <= 0.15, at least 64
+    assert ia["eii_nodes"] == max(64, int(np.ceil(2 * 1.0 * 15.0 / 0.15 / 64)) * 64)
     assert ia["ms_eii_table"] > 0.0 and ib["ms_eii_table"] == 0.0
     assert np.allclose(a, b, rtol=1e-13, atol=1e-13 * np.abs(a).max())
 
@@ -167,20 +167,20 @@ def test_full_size_bispectrum_workload_subset():
 def test_full_size_table_volume_integral():
     # 4 pi int_0^{2 R0} x^2 E^{II,ab}_l dx = delta_l0 W~^a W~^b at the
     # bispectrum workload's bins and default table size, integrating the
-    # interpolating cubics of the table exactly
+    # interpolating quintics of the table exactly
     import paper_2005_01739_amd as hp
     r0, k, lmax = 30.0, np.linspace(0.5, 3.0, 13), 5
-    n_x = max(64, int(np.ceil(40 * 3.0 * r0 / 64)) * 64)
+    n_x = max(64, int(np.ceil(2 * 3.0 * r0 / 0.15 / 64)) * 64)
     E = hp.eii_table(r0, k, lmax, n_x)
     h = 2 * r0 / n_x
-    gx, gw = np.polynomial.legendre.leggauss(4)
+    gx, gw = np.polynomial.legendre.leggauss(5)
     t = 0.5 * (gx + 1.0)
-    basis = np.stack([-t * (t - 1) * (t - 2) / 6, (t + 1) * (t - 1) * (t - 2) / 2,
-                      -(t + 1) * t * (t - 2) / 2, (t + 1) * t * (t - 1) / 6])  # [4 nodes, 4 points]
-    ext = np.concatenate([E[..., 1:2], E, np.zeros(E.shape[:-1] + (1,))], axis=-1)  # nodes -1 .. n_x + 1
+    nodes = np.arange(-2, 4)
+    basis = np.stack([np.prod([(t - i) / (q - i) for i in nodes if i != q], axis=0) for q in nodes])  # [6, 5]
+    ext = np.concatenate([E[..., 2:0:-1], E, np.zeros(E.shape[:-1] + (2,))], axis=-1)  # nodes -2 .. n_x + 2
     tot = np.zeros(E.shape[:-1])
     for m in range(n_x):
-        vals = np.einsum("...q,qp->...p", ext[..., m:m + 4], basis)
+        vals = np.einsum("...q,qp->...p", ext[..., m:m + 6], basis)
         x = (m + t) * h
         tot += np.einsum("...p,p->...", vals, 0.5 * gw * h * 4 * np.pi * x * x)
     wt = hp.wtilde(r0, k)

@@ -104,7 +104,7 @@ def test_pair_sum_matches_lattice_randoms():
 
 
 def test_pair_sum_interpolation_converges():
-    # T from the n_x-interval table against per-pair kernel values: fourth-order convergence
+    # T from the n_x-interval table against per-pair kernel values: sixth-order convergence
     L, r0, ell_max = 50.0, 12.0, 2
     k = np.array([0.2, 0.35, 0.5])
     pos = np.random.default_rng(9).uniform(0, L, (10, 3))
@@ -123,9 +123,9 @@ def test_pair_sum_interpolation_converges():
     for n_x in (16, 128):
         t = oracle.ddr2(pos, None, L, r0, k, ell_max, n_x)
         errs.append(np.abs(t["t2"] - exact).max() / np.abs(exact).max())
-    # an 8x finer table: 8^4 = 4096 for a fourth-order rule (a third-order one gives 512)
-    assert errs[1] < 1e-7
-    assert errs[0] / errs[1] > 1500
+    # an 8x finer table: 8^6 = 262144 for a sixth-order rule (a fifth-order one gives 32768)
+    assert errs[1] < 1e-9
+    assert errs[0] / errs[1] > 60000
 
 
 def test_interpolated_kernel_exact_at_nodes():
