@@ -282,14 +282,26 @@ __global__ __launch_bounds__(kEiiThreads) void k_eii_table(double r0, double h, 
 constexpr int kHistThreads = 512;  // 8 waves; one home tile shared by all
 constexpr int kHistTile = 64;
 
+// Orders one wave's LDS accesses: a value a lane stored is seen by the loads
+// of the wave's other lanes that follow (LDS serves a wave's accesses in
+// order; the fence keeps the compiler from moving them across).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Persistent workgroups take home tiles (unit = a home cell's tile of up to
 // 64 points) from a counter; the waves of a workgroup split the unit's
 // neighbour tiles (14 half-stencil cells, each in tiles of 64 points): each
 // lane holds one neighbour point and runs over the home tile, read from LDS
 // by broadcast.  A (pair, image) with r^2 < (2 R0)^2 (the exact double
-// predicate of the pair counts) adds w_i w_j l_q(t) to the four nodes around
-// x = r (six nodes m-2 .. m+3); without masks every unordered pair counts
-// both ways (factor 2).
+// predicate of the pair counts) adds w_i w_j l_q(t) to the six nodes m-2 ..
+// m+3 around x = r; without masks every unordered pair counts both ways
+// (factor 2).  Only ~15% of the candidates hit: a single-precision
+// prefilter with a safe margin passes the candidates that may lie inside
+// 2 R0 into a per-wave LDS queue (ballot + prefix count), and the exact
+// double-precision test and the weights run on 64 of them at a time with
+// every lane busy.
 template <bool MASKED>
 __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, double L, double lim2, double inv_h,
                                                             int n_x, const int *__restrict__ unit_cell,
@@ -304,10 +316,63 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
   __shared__ int nb_count[14], nb_first[15];
   __shared__ double nb_off[14][3];
   __shared__ int64_t cur_unit;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int kWaves = kHistThreads / 64;
+  // single-precision home coordinates for the prefilter
+  __shared__ float4 homef[kHistTile];
+  // per wave: candidates (home index, neighbour lane) that passed the
+  // prefilter, and the neighbour tile (coordinates, weight) they refer to
+  __shared__ int q_i[kWaves][128], q_j[kWaves][128];
+  __shared__ double4 jt[kWaves][kHistTile];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  // prefilter bound: (2 R0 + delta)^2 in single precision, delta = 2^-17 L
+  // covers the rounding of coordinates below 2 L to single precision (each
+  // within 2^-24 of its magnitude) and of the single-precision distance
+  const float lim2f = float((sqrt(lim2) + 0x1p-17 * L) * (sqrt(lim2) + 0x1p-17 * L));
   for (int i = tid; i <= n_x; i += kHistThreads) hist[i] = 0.0;
   unsigned long long ord = 0;
+  int qn = 0;  // queued candidates of this wave (uniform over the wave)
+  // one (pair, image) at x = sqrt(r2): six-point Lagrange weights of the
+  // nodes m-2 .. m+3 times ww; nodes below 0 fold onto their mirror (E is
+  // even), nodes >= n_x hold E = 0
+  auto spread = [&](double r2, double ww) {
+    const double sx = sqrt(r2) * inv_h;
+    int mi = int(sx);
+    if (mi > n_x - 1) mi = n_x - 1;
+    const double t = sx - double(mi);
+    const double tp2 = t + 2.0, tp1 = t + 1.0, tm1 = t - 1.0, tm2 = t - 2.0, tm3 = t - 3.0;
+    const double a01 = tp2 * tp1, a34 = tm2 * tm3, b = t * tm1;
+    const double lw[6] = {-tp1 * b * a34 * (1.0 / 120.0), tp2 * b * a34 * (1.0 / 24.0),
+                          -a01 * tm1 * a34 * (1.0 / 12.0), a01 * t * a34 * (1.0 / 12.0),
+                          -a01 * b * tm3 * (1.0 / 24.0), a01 * b * tm2 * (1.0 / 120.0)};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      int node = mi + q - 2;
+      node = node < 0 ? -node : node;
+      if (node < n_x) atomicAdd(&hist[node], ww * lw[q]);
+    }
+  };
+  // the exact double-precision test of candidate (home ii, neighbour
+  // jbase + jl) and, inside 2 R0, its ordered-pair multiplicity and weight
+  auto exact = [&](int ii, int jl, int64_t jbase, double offx, double offy, double offz) {
+    const double4 p = home[ii], q = jt[wave][jl];
+    const int64_t j = jbase + jl;
+    double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+    dx -= offx;
+    dy -= offy;
+    dz -= offz;
+    double r2;
+    {
+#pragma clang fp contract(off)
+      const double a = dx * dx, b = dy * dy, c = dz * dz;
+      r2 = (a + b) + c;
+    }
+    if (r2 < lim2) {
+      const int mult = MASKED ? hm[ii] + (s.m ? int(s.m[j]) : 1) : 2;
+      ord += unsigned(mult);
+      if (mult > 0) spread(r2, p.w * q.w * double(mult));
+    }
+  };
   for (;;) {
     __syncthreads();
     if (tid == 0) cur_unit = int64_t(atomicAdd(counter, 1ull));
@@ -323,6 +388,7 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
     if (tid < ti) {
       const int64_t i = hs + i0 + tid;
       home[tid] = make_double4(s.x[i], s.y[i], s.z[i], s.w[i]);
+      homef[tid] = make_float4(float(s.x[i]), float(s.y[i]), float(s.z[i]), 0.0f);
       if (MASKED) hm[tid] = s.m ? int(s.m[i]) : 1;
     }
     if (tid < 14) {
@@ -368,56 +434,59 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
       const int tj = min(kHistTile, nb_count[st] - j0);
       const bool self = st == 0;
       const double offx = nb_off[st][0], offy = nb_off[st][1], offz = nb_off[st][2];
-      double jx = 0.0, jy = 0.0, jz = 0.0, jw = 0.0;
-      int jm = 0;
+      const int64_t jbase = nb_start[st] + j0;
+      // single-precision copy of this lane's neighbour image for the prefilter
+      float fx = 0.0f, fy = 0.0f, fz = 0.0f;
       if (lane < tj) {
-        const int64_t j = nb_start[st] + j0 + lane;
-        jx = s.x[j];
-        jy = s.y[j];
-        jz = s.z[j];
-        jw = s.w[j];
-        if (MASKED) jm = s.m ? int(s.m[j]) : 1;
+        const int64_t j = jbase + lane;
+        const double4 q = make_double4(s.x[j], s.y[j], s.z[j], s.w[j]);
+        jt[wave][lane] = q;
+        fx = float(q.x + offx);
+        fy = float(q.y + offy);
+        fz = float(q.z + offz);
       }
+      wave_sync();
       const int jg = j0 + lane;  // index of this lane's point within its cell
-      if (lane < tj) {
-        for (int ii = 0; ii < ti; ++ii) {
-          if (self && jg <= i0 + ii) continue;
-          const double4 p = home[ii];
-          double dx = p.x - jx, dy = p.y - jy, dz = p.z - jz;
-          dx -= offx;
-          dy -= offy;
-          dz -= offz;
-          double r2;
-          {
-#pragma clang fp contract(off)
-            const double a = dx * dx, b = dy * dy, c = dz * dz;
-            r2 = (a + b) + c;
+      for (int ii = 0; ii < ti; ++ii) {
+        bool cand = false;
+        if (lane < tj && !(self && jg <= i0 + ii)) {
+          const float4 p = homef[ii];
+          const float dx = p.x - fx, dy = p.y - fy, dz = p.z - fz;
+          cand = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim2f;
+        }
+        // compact the candidates into the wave's queue; test and weigh 64 at a time
+        const unsigned long long bal = __ballot(cand);
+        if (bal) {
+          if (cand) {
+            const int at = qn + __popcll(bal & below);
+            q_i[wave][at] = ii;
+            q_j[wave][at] = lane;
           }
-          if (r2 < lim2) {
-            const int mult = MASKED ? hm[ii] + jm : 2;
-            if (mult == 0) continue;
-            ord += unsigned(mult);
-            const double ww = p.w * jw * double(mult);
-            const double sx = sqrt(r2) * inv_h;
-            int mi = int(sx);
-            if (mi > n_x - 1) mi = n_x - 1;
-            const double t = sx - double(mi);
-            const double tp2 = t + 2.0, tp1 = t + 1.0, tm1 = t - 1.0, tm2 = t - 2.0, tm3 = t - 3.0;
-            // six-point Lagrange weights of the nodes m-2 .. m+3
-            const double a01 = tp2 * tp1, a34 = tm2 * tm3, b = t * tm1;
-            const double lw[6] = {-tp1 * b * a34 * (1.0 / 120.0), tp2 * b * a34 * (1.0 / 24.0),
-                                  -a01 * tm1 * a34 * (1.0 / 12.0), a01 * t * a34 * (1.0 / 12.0),
-                                  -a01 * b * tm3 * (1.0 / 24.0), a01 * b * tm2 * (1.0 / 120.0)};
-            // nodes below 0 fold onto their mirror (E even); nodes >= n_x hold E = 0
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-              int node = mi + q - 2;
-              node = node < 0 ? -node : node;
-              if (node < n_x) atomicAdd(&hist[node], ww * lw[q]);
+          qn += __popcll(bal);
+          if (qn >= 64) {
+            wave_sync();
+            exact(q_i[wave][lane], q_j[wave][lane], jbase, offx, offy, offz);
+            const int rest = qn - 64;
+            int a = 0, b = 0;
+            if (lane < rest) {
+              a = q_i[wave][64 + lane];
+              b = q_j[wave][64 + lane];
             }
+            wave_sync();
+            if (lane < rest) {
+              q_i[wave][lane] = a;
+              q_j[wave][lane] = b;
+            }
+            qn = rest;
+            wave_sync();
           }
         }
       }
+      // the queue refers to this neighbour tile: drain it before the next
+      wave_sync();
+      if (lane < qn) exact(q_i[wave][lane], q_j[wave][lane], jbase, offx, offy, offz);
+      qn = 0;
+      wave_sync();
     }
   }
   // ordered (pair, image) terms of the workgroup, and its histogram
@@ -496,7 +565,7 @@ void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, cons
   {
     int dev = c.device, cus = 0;
     HIPSTER_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    nwg = std::max(1, cus) * 2;
+    nwg = std::max(1, cus) * 4;
   }
   double *partial = static_cast<double *>(ensure(c, c.ddr2_partial, size_t(nwg) * n_nodes * 8));
   double *H = static_cast<double *>(ensure(c, c.ddr2_hist, size_t(n_nodes) * 8));
