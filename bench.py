@@ -70,13 +70,16 @@ def pk_flops_per_pair(n_k: int, n_ell: int) -> float:
     return 40.0 + 80.0 * (n_k + 1) + 5.0 * n_k * n_ell
 
 
-def bk_flops_per_pair(n_k: int, ell_max: int) -> float:
+def bk_flops_per_pair(n_k: int, ell_max: int, with_c: bool = True) -> float:
     """Algorithmic FLOPs per ordered pair for the bispectrum weights: the special
     functions at n_k+1 edges (60 shared + 10 per multipole per edge), the real
-    harmonics (6 per y_lm), the A_lm sums (2 n_k (l_max+1)^2) and the C^ab_l sums
-    over a <= b (2 (l_max+1) n_k (n_k+1)/2)."""
+    harmonics (6 per y_lm), the A_lm sums (2 n_k (l_max+1)^2) and, when the fused
+    kernel sums them (FP64 form, random primaries), the C^ab_l sums over a <= b
+    (2 (l_max+1) n_k (n_k+1)/2).  The mixed form takes the data primaries' C from
+    the separate C-term pair histogram."""
     n_l = ell_max + 1
-    return 40.0 + (60.0 + 10.0 * n_l) * (n_k + 1) + 6.0 * n_l * n_l + 2.0 * n_k * n_l * n_l + n_l * n_k * (n_k + 1)
+    c_term = n_l * n_k * (n_k + 1) if with_c else 0.0
+    return 40.0 + (60.0 + 10.0 * n_l) * (n_k + 1) + 6.0 * n_l * n_l + 2.0 * n_k * n_l * n_l + c_term
 
 
 def traffic_from_profile():
@@ -269,7 +272,7 @@ def main():
         # (l, a <= b) table
         value = (pairs * units_per_pair + pairs_2r0 * n_tables) / (dt / args.steps)
         avg_launch_ms = sweep_ms / max(launches, 1)
-        flops = pairs * bk_flops_per_pair(n_k, wl.ell_max_b) / (launches / args.steps)
+        flops = pairs * bk_flops_per_pair(n_k, wl.ell_max_b, with_c=prec == "fp64") / (launches / args.steps)
         achieved = flops / (avg_launch_ms * 1e-3) / 1e12
         # the table depends on (R0, bins) only: built in the warm-up, reused by the
         # context in the timed steps; its cold build time is reported beside
@@ -330,7 +333,8 @@ def main():
                                "traffic": None, "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
     else:
         # both primary catalogues, per launch (data primaries, then random primaries)
-        flops = (pairs + pairs_r) * bk_flops_per_pair(n_k, wl.ell_max_b) / (launches / args.steps)
+        flops = (pairs * bk_flops_per_pair(n_k, wl.ell_max_b, with_c=prec == "fp64")
+                 + pairs_r * bk_flops_per_pair(n_k, wl.ell_max_b)) / (launches / args.steps)
         achieved = flops / (avg_launch_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "kernel": "k_bk_fused", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                            "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,

@@ -120,6 +120,7 @@ typedef struct {
   double ms_ddr2;         /* B analytic: the 2 R0 pair sweep and its contraction with the table */
   uint64_t n_pairs_2r0;   /* B analytic: ordered (pair, periodic image) terms inside 2 R0 */
   int64_t eii_nodes;      /* B analytic: the table's n_x (intervals over [0, 2 R0]) */
+  double ms_cterm;        /* B, mixed form: the C-term pair sweep of the data primaries */
 } hipster_diag;
 
 typedef struct hipster_ctx hipster_ctx;

@@ -57,7 +57,8 @@ class _Diag(ct.Structure):
                 ("ms_build", ct.c_double), ("ms_pairs", ct.c_double), ("ms_sweep", ct.c_double),
                 ("ms_total", ct.c_double), ("sweep_launches", ct.c_uint64), ("n_pairs_rr", ct.c_uint64),
                 ("ms_sweep_far", ct.c_double), ("n_pairs_far", ct.c_uint64), ("ms_eii_table", ct.c_double),
-                ("ms_ddr2", ct.c_double), ("n_pairs_2r0", ct.c_uint64), ("eii_nodes", ct.c_int64)]
+                ("ms_ddr2", ct.c_double), ("n_pairs_2r0", ct.c_uint64), ("eii_nodes", ct.c_int64),
+                ("ms_cterm", ct.c_double)]
 
 
 class _SurveyParams(ct.Structure):
@@ -337,7 +338,8 @@ def bk_ell(pos, w=None, randoms=None, rw=None, *, box: float, r0: float, k_edges
         return out
     info = dict(parts)
     info.update(s0=s0, wtilde=wt, n_pairs=int(d.n_pairs), n_pairs_rand=int(d.n_pairs_rand), ms_build=d.ms_build,
-                ms_pairs=d.ms_pairs, ms_sweep=d.ms_sweep, ms_total=d.ms_total, sweep_launches=int(d.sweep_launches))
+                ms_pairs=d.ms_pairs, ms_sweep=d.ms_sweep, ms_total=d.ms_total, sweep_launches=int(d.sweep_launches),
+                ms_cterm=d.ms_cterm)
     return out, info
 
 
@@ -369,7 +371,7 @@ def bk_ell_analytic(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int
     info = {"gd": parts["gd"], "cd": parts["cd"], "t2": parts["gr"]}
     info.update(s0=s0, wtilde=wt, n_pairs=int(d.n_pairs), n_pairs_2r0=int(d.n_pairs_2r0), ms_build=d.ms_build,
                 ms_sweep=d.ms_sweep, ms_eii_table=d.ms_eii_table, ms_ddr2=d.ms_ddr2, ms_total=d.ms_total,
-                eii_nodes=int(d.eii_nodes))
+                eii_nodes=int(d.eii_nodes), ms_cterm=d.ms_cterm)
     return out, info
 
 

@@ -538,8 +538,12 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   part[1] = static_cast<double *>(ensure(c, c.bk_partial_r, size_t(nwaves) * rowlen * 8));
   HIPSTER_HIP(hipMemsetAsync(part[0], 0, size_t(nwaves) * rowlen * 8, c.stream));
   HIPSTER_HIP(hipMemsetAsync(part[1], 0, size_t(nwaves) * rowlen * 8, c.stream));
-  unsigned long long *cnt = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 16));
-  HIPSTER_HIP(hipMemsetAsync(cnt, 0, 16, c.stream));
+  unsigned long long *cnt = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 24));
+  HIPSTER_HIP(hipMemsetAsync(cnt, 0, 24, c.stream));
+  // the mixed form takes C of the data primaries from the C-term pair
+  // histogram (exact window, tabulated jbar^a jbar^b) instead of the fused
+  // kernel's matrix instructions; the FP64 form keeps C in the fused kernel
+  const bool c_hist = !fp64;
 
   double ms_sweep = 0.0;
   const double ms_pairs = 0.0;  // enumeration is fused into the sweep
@@ -547,12 +551,30 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   for (int set = 0; set < (have_r ? 2 : 1); ++set) {
     const Sorted &prim = set == 0 ? sd : sr;
     hipEvent_t b1 = tm.mark();
-    bk_fused(c, prim, sd, g, q->r0, set == 0, edges, coef_d, NK, q->ell_max, fp64, part[set], rowlen, nwaves,
+    bk_fused(c, prim, sd, g, q->r0, set == 0, edges, coef_d, NK, q->ell_max, fp64, !(c_hist && set == 0), part[set],
+             rowlen, nwaves,
              cnt + set);
     hipEvent_t b2 = tm.mark();
     HIPSTER_HIP(hipEventSynchronize(b2));
     ms_sweep += Timer::ms(b1, b2);
     ++launches;
+  }
+  std::vector<double> Ch;
+  double ms_cterm = 0.0;
+  if (c_hist) {
+    hipEvent_t c0 = tm.mark();
+    const int rows = NL * NK * NK;
+    double *Cd = static_cast<double *>(ensure(c, c.ct_C, size_t(rows) * 8));
+    unsigned long long n_dd = 0;
+    HIPSTER_HIP(hipMemcpyAsync(&n_dd, cnt, 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    cterm_sweep(c, sd, g, q->r0, NK, q->k_edges, q->ell_max, cterm_default_nodes(q->r0, q->k_edges[NK]), n_dd, Cd,
+                cnt + 2);
+    Ch.resize(size_t(rows));
+    HIPSTER_HIP(hipMemcpyAsync(Ch.data(), Cd, size_t(rows) * 8, hipMemcpyDeviceToHost, c.stream));
+    hipEvent_t c1 = tm.mark();
+    HIPSTER_HIP(hipEventSynchronize(c1));
+    ms_cterm = Timer::ms(c0, c1);
   }
   // analytic DDR^II: the kernel table, then every data pair inside 2 R0 on
   // a grid of cells >= 2 R0 (the data re-sorted into the randoms' scratch)
@@ -595,7 +617,8 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
       for (int b = 0; b < NK; ++b) {
         const int t = l * 256 + std::min(a, b) * 16 + std::max(a, b);
         const size_t o = (size_t(l) * NK + a) * NK + b;
-        const double GD = Md[t], CD = Md[nT + t];
+        const double GD = Md[t];
+        const double CD = c_hist ? Ch[(size_t(l) * NK + std::min(a, b)) * NK + std::max(a, b)] : Md[nT + t];
         // the random-primary term s_R (G_R - C_R) estimates n_w T, T = sum_{i!=j} w_i w_j E^II
         const double GR = analytic ? T[(size_t(l) * NK + std::min(a, b)) * NK + std::max(a, b)] : Mr[t];
         const double CR = analytic ? 0.0 : Mr[nT + t];
@@ -630,6 +653,7 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
     diag->ms_ddr2 = ms_ddr2;
     diag->n_pairs_2r0 = analytic ? hcnt[1] : 0;
     diag->eii_nodes = analytic ? analytic_nx : 0;
+    diag->ms_cterm = ms_cterm;
   }
 }
 
@@ -942,7 +966,8 @@ void hipster_destroy(hipster_ctx *ctx) {
                    &c.pair_ord, &c.pair_off, &c.pair_off_b, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
                    &c.partial, &c.merged, &c.ordered_count, &c.bbox, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out,
                    &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile, &c.eii_consts, &c.eii_tab,
-                   &c.ddr2_partial, &c.ddr2_hist, &c.ddr2_counter, &c.ddr2_T};
+                   &c.ddr2_partial, &c.ddr2_hist, &c.ddr2_counter, &c.ddr2_T, &c.ct_tab, &c.ct_consts, &c.ct_C,
+                   &c.ct_wmax};
   for (DevBuf *b : all) free_buf(*b);
   delete ctx;
 }

@@ -123,6 +123,10 @@ constexpr int kXcds = 8;             // accelerator complex dies of the MI355X (
 #ifndef HIPSTER_BK_WAVES_PER_EU
 #define HIPSTER_BK_WAVES_PER_EU 1
 #endif
+// Occupancy hint of the variant without the C sums (fewer accumulators).
+#ifndef HIPSTER_BK_WAVES_PER_EU_NOC
+#define HIPSTER_BK_WAVES_PER_EU_NOC 1
+#endif
 
 // The value held by lane L+1 of the same 16-lane row (lane 15 of a row gets
 // 0): a DPP row shift, no LDS round trip.
@@ -161,8 +165,14 @@ size_t bk_fused_lds(int NL, int NK) {
 // G_l(u) of the mixed form for the closed-form lanes, with lanes below
 // kUSmall replaced by the Taylor branch (a uniform branch, taken only when
 // some lane needs it).
-template <int NL, bool FP64>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_WAVES_PER_EU))) void k_bk_fused(
+// WITH_C = false leaves the C sums out (their partial-row entries stay zero):
+// the mixed form takes C of the data primaries from the pair histogram of
+// the C-term sweep instead (k_ddr2_hist), which saves the NL matrix
+// instructions per step that C costs here.
+template <int NL, bool FP64, bool WITH_C>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WITH_C ? HIPSTER_BK_WAVES_PER_EU
+                                                                             : HIPSTER_BK_WAVES_PER_EU_NOC))) void
+k_bk_fused(
     Sorted prim, Sorted sec, int nc, double L, double r02, int self_set, int64_t p_lo, int64_t p_hi,
     double inv_r0, const double *__restrict__ edges, const double *__restrict__ coef, int NK,
     double *__restrict__ partial, int rowlen, unsigned long long *__restrict__ npairs) {
@@ -311,7 +321,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_W
               const double y = ylds[row * kYStride + q];
               accA[l] = mfma_f64(g, y, accA[l]);
             }
-            accC[l] = mfma_f64(g * wp, g, accC[l]);
+            if constexpr (WITH_C) accC[l] = mfma_f64(g * wp, g, accC[l]);
           }
         }
         __syncthreads();
@@ -452,7 +462,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_W
     for (int v = 0; v < 4; ++v) {
       const int e = (t4 + 4 * v) * 16 + col;
       row[l * 256 + e] += accG[l][v];
-      row[NL * 256 + l * 256 + e] += accC[l][v];
+      if constexpr (WITH_C) row[NL * 256 + l * 256 + e] += accC[l][v];
     }
   if (t4 == 0) row[2 * NL * 256 + col] += accS0;
   if (lane == 0 && pcount) atomicAdd(npairs, pcount);
@@ -460,32 +470,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HIPSTER_BK_W
 
 template <int NL>
 static void launch_fused(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
-                         const double *edges, const double *coef, int NK, bool fp64, double *partial, int rowlen,
-                         int nwaves, unsigned long long *npairs) {
+                         const double *edges, const double *coef, int NK, bool fp64, bool with_c, double *partial,
+                         int rowlen, int nwaves, unsigned long long *npairs) {
   const size_t lds = bk_fused_lds(NL, NK);
   if (prim.n == 0) return;
   if (NK < 1 || NK > kMaxNkB) throw Error{HIPSTER_EUNSUPPORTED, "bispectrum: n_k outside [1, 16]"};
   if (nwaves < kXcds || nwaves % kXcds) throw Error{HIPSTER_EINVAL, "bispectrum: wave count must be a multiple of 8"};
+  if (fp64 && !with_c) throw Error{HIPSTER_EINVAL, "bispectrum: the FP64 form sums C in the fused kernel"};
   if (fp64)
-    k_bk_fused<NL, true><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(
+    k_bk_fused<NL, true, true><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(
+        prim, sec, g.nc, g.L, r0 * r0, self_set ? 1 : 0, 0, prim.n, 1.0 / r0, edges, coef, NK, partial, rowlen, npairs);
+  else if (with_c)
+    k_bk_fused<NL, false, true><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(
         prim, sec, g.nc, g.L, r0 * r0, self_set ? 1 : 0, 0, prim.n, 1.0 / r0, edges, coef, NK, partial, rowlen, npairs);
   else
-    k_bk_fused<NL, false><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(
+    k_bk_fused<NL, false, false><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(
         prim, sec, g.nc, g.L, r0 * r0, self_set ? 1 : 0, 0, prim.n, 1.0 / r0, edges, coef, NK, partial, rowlen, npairs);
   HIPSTER_HIP(hipGetLastError());
 }
 
 void bk_fused(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
-              const double *edges, const double *coef, int NK, int ell_max, bool fp64, double *partial, int rowlen,
-              int nwaves, unsigned long long *npairs) {
+              const double *edges, const double *coef, int NK, int ell_max, bool fp64, bool with_c, double *partial,
+              int rowlen, int nwaves, unsigned long long *npairs) {
   switch (ell_max) {
-    case 0: launch_fused<1>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, partial, rowlen, nwaves, npairs); break;
-    case 1: launch_fused<2>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, partial, rowlen, nwaves, npairs); break;
-    case 2: launch_fused<3>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, partial, rowlen, nwaves, npairs); break;
-    case 3: launch_fused<4>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, partial, rowlen, nwaves, npairs); break;
-    case 4: launch_fused<5>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, partial, rowlen, nwaves, npairs); break;
-    case 5: launch_fused<6>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, partial, rowlen, nwaves, npairs); break;
-    default: launch_fused<7>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, partial, rowlen, nwaves, npairs); break;
+    case 0: launch_fused<1>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
+    case 1: launch_fused<2>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
+    case 2: launch_fused<3>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
+    case 3: launch_fused<4>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
+    case 4: launch_fused<5>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
+    case 5: launch_fused<6>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
+    default: launch_fused<7>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
   }
 }
 

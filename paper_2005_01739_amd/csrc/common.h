@@ -113,7 +113,7 @@ struct Ctx {
   DevBuf unit_tiles, unit_base, unit_cell, unit_tile;
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
-  DevBuf eii_consts, eii_tab, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T;
+  DevBuf eii_consts, eii_tab, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T, ct_tab, ct_consts, ct_C, ct_wmax;
   // The E^II table on the device and the (R0, n_x, ell_max, edges) it holds.
   std::vector<double> eii_key;
   // W~^a depends only on (R0, k_a, k_{a+1}); repeated calls reuse it.
@@ -181,9 +181,10 @@ void merge_boxes(Ctx &c, const double *rows, int cols, const int *first, int nbo
 void merge_partials(Ctx &c, const double *partial, int rows, int cols, double *out);
 
 // Bispectrum: fused enumeration and MFMA contraction over one primary catalogue.
+// with_c = false (mixed form only): the C sums are left out (zero rows).
 void bk_fused(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
-              const double *edges, const double *coef, int NK, int ell_max, bool fp64, double *partial, int rowlen,
-              int nwaves, unsigned long long *npairs);
+              const double *edges, const double *coef, int NK, int ell_max, bool fp64, bool with_c, double *partial,
+              int rowlen, int nwaves, unsigned long long *npairs);
 size_t bk_fused_lds(int NL, int NK);
 void widen_i32(Ctx &c, const int *in, int64_t *out, int64_t n);
 
@@ -197,6 +198,16 @@ void eii_table(Ctx &c, double r0, int n_k, const double *k_edges, int ell_max, i
 void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, const double *table, int rows,
                 double *T, unsigned long long *ordered);
 size_t ddr2_max_nodes(Ctx &c);
+// C term of the bispectrum's data primaries in the mixed form:
+// C^ab_l = sum over ordered pairs (p, q != p) inside R0, p selected by the
+// mask, of w_p w_q^2 W(r/R0)^2 jbar^a_l(r) jbar^b_l(r), from a pair histogram
+// of interpolation weights on the nodes m R0 / n_c and a table of
+// jbar^a jbar^b; C [ell_max+1][n_k][n_k] (device).  `s` is the data sorted on
+// the R0 grid `g`.
+int cterm_default_nodes(double r0, double k_max);
+// n_ordered: the ordered pairs inside R0 (bounds the fixed-point sums).
+void cterm_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, const double *k_edges, int ell_max,
+                 int n_c, uint64_t n_ordered, double *C, unsigned long long *ordered);
 
 // Host analytic terms.
 double wtilde_bin(double r0, double k1, double k2);

@@ -27,6 +27,7 @@
 // below 0 take E(-x) = E(x) (E is a smooth function of the pair vector, even
 // in x) and the nodes at and beyond 2 R0 hold E = 0 (its support).
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <vector>
@@ -302,14 +303,28 @@ __device__ inline void wave_sync() {
 // 2 R0 into a per-wave LDS queue (ballot + prefix count), and the exact
 // double-precision test and the weights run on 64 of them at a time with
 // every lane busy.
-template <bool MASKED>
+// What a pair adds to the histogram.
+enum HistKind {
+  kHistDdr2 = 0,   // pairs inside 2 R0, weight w_i w_j per orientation
+  kHistCterm = 1,  // pairs inside R0, weight w_p w_q^2 W(r/R0)^2 per orientation (p, q)
+};
+
+// n_x: table intervals (the interval index is clamped to n_x - 1); nodes
+// below n_keep receive weights, the others hold a zero kernel value;
+// n_hist: histogram entries.  kHistDdr2: n_keep = n_x, n_hist = n_x + 1,
+// double sums (FP64 LDS atomics: reproducible to rounding); kHistCterm:
+// n_keep = n_hist = n_x + 3 (the table runs past R0), 64-bit fixed-point
+// sums with scale fix_scale (bitwise reproducible).
+template <bool MASKED, int KIND>
 __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, double L, double lim2, double inv_h,
-                                                            int n_x, const int *__restrict__ unit_cell,
+                                                            int n_x, int n_keep, int n_hist, double inv_r0,
+                                                            double fix_scale,
+                                                            const int *__restrict__ unit_cell,
                                                             const int *__restrict__ unit_tile, int64_t n_units,
                                                             unsigned long long *__restrict__ counter,
                                                             unsigned long long *__restrict__ ordered,
                                                             double *__restrict__ partial) {
-  extern __shared__ double hist[];  // n_x + 1 nodes
+  extern __shared__ double hist[];  // n_hist nodes
   __shared__ double4 home[kHistTile];
   __shared__ int hm[kHistTile];
   __shared__ int64_t nb_start[14];
@@ -325,16 +340,16 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
   __shared__ double4 jt[kWaves][kHistTile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long below = (1ull << lane) - 1ull;
-  // prefilter bound: (2 R0 + delta)^2 in single precision, delta = 2^-17 L
+  // prefilter bound: (sqrt(lim2) + delta)^2 in single precision, delta = 2^-17 L
   // covers the rounding of coordinates below 2 L to single precision (each
   // within 2^-24 of its magnitude) and of the single-precision distance
   const float lim2f = float((sqrt(lim2) + 0x1p-17 * L) * (sqrt(lim2) + 0x1p-17 * L));
-  for (int i = tid; i <= n_x; i += kHistThreads) hist[i] = 0.0;
+  for (int i = tid; i < n_hist; i += kHistThreads) hist[i] = 0.0;
   unsigned long long ord = 0;
   int qn = 0;  // queued candidates of this wave (uniform over the wave)
   // one (pair, image) at x = sqrt(r2): six-point Lagrange weights of the
-  // nodes m-2 .. m+3 times ww; nodes below 0 fold onto their mirror (E is
-  // even), nodes >= n_x hold E = 0
+  // nodes m-2 .. m+3 times ww; nodes below 0 fold onto their mirror (both
+  // kernels are even in x), nodes >= n_keep hold a zero kernel
   auto spread = [&](double r2, double ww) {
     const double sx = sqrt(r2) * inv_h;
     int mi = int(sx);
@@ -349,7 +364,16 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
     for (int q = 0; q < 6; ++q) {
       int node = mi + q - 2;
       node = node < 0 ? -node : node;
-      if (node < n_x) atomicAdd(&hist[node], ww * lw[q]);
+      if (node < n_keep) {
+        if constexpr (KIND == kHistCterm) {
+          // fixed point (scale 2^e chosen on the host so no sum can
+          // overflow): integer sums do not depend on the order of the adds
+          const long long iv = llrint(ww * lw[q] * fix_scale);
+          atomicAdd(reinterpret_cast<unsigned long long *>(&hist[node]), static_cast<unsigned long long>(iv));
+        } else {
+          atomicAdd(&hist[node], ww * lw[q]);
+        }
+      }
     }
   };
   // the exact double-precision test of candidate (home ii, neighbour
@@ -368,9 +392,17 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
       r2 = (a + b) + c;
     }
     if (r2 < lim2) {
-      const int mult = MASKED ? hm[ii] + (s.m ? int(s.m[j]) : 1) : 2;
-      ord += unsigned(mult);
-      if (mult > 0) spread(r2, p.w * q.w * double(mult));
+      const int mi_ = MASKED ? hm[ii] : 1, mj_ = MASKED ? (s.m ? int(s.m[j]) : 1) : 1;
+      ord += unsigned(mi_ + mj_);
+      if (mi_ + mj_ > 0) {
+        if constexpr (KIND == kHistDdr2) {
+          spread(r2, p.w * q.w * double(mi_ + mj_));
+        } else {
+          // (i, j) as (p, q) if i is selected, and (j, i) if j is
+          const double W = window<double>(sqrt(r2) * inv_r0);
+          spread(r2, p.w * q.w * (double(mi_) * q.w + double(mj_) * p.w) * (W * W));
+        }
+      }
     }
   };
   for (;;) {
@@ -493,8 +525,8 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
   for (int o = 32; o > 0; o >>= 1) ord += __shfl_xor(ord, o);
   if (lane == 0 && ord) atomicAdd(ordered, ord);
   __syncthreads();
-  double *out = partial + size_t(blockIdx.x) * (size_t(n_x) + 1);
-  for (int i = tid; i <= n_x; i += kHistThreads) out[i] = hist[i];
+  double *out = partial + size_t(blockIdx.x) * size_t(n_hist);
+  for (int i = tid; i < n_hist; i += kHistThreads) out[i] = hist[i];
 }
 
 // H[m] = sum over workgroups of partial[wg][m], in workgroup order.
@@ -504,6 +536,28 @@ __global__ void k_ddr2_reduce(const double *__restrict__ partial, int nwg, int n
   double s = 0.0;
   for (int g = 0; g < nwg; ++g) s += partial[size_t(g) * n_nodes + m];
   H[m] = s;
+}
+
+// The same for fixed-point histograms (the partial rows hold int64 bit
+// patterns): an exact integer sum, then H[m] = sum / scale.
+__global__ void k_hist_reduce_fix(const double *__restrict__ partial, int nwg, int n_nodes, double inv_scale,
+                                  double *__restrict__ H) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_nodes) return;
+  const long long *p = reinterpret_cast<const long long *>(partial);
+  long long s = 0;
+  for (int g = 0; g < nwg; ++g) s += p[size_t(g) * n_nodes + m];
+  H[m] = double(s) * inv_scale;
+}
+
+// Largest |w| of n doubles, as the bit pattern of a non-negative double
+// (which orders like the integer).
+__global__ void k_absmax(const double *__restrict__ w, int64_t n, unsigned long long *__restrict__ out) {
+  unsigned long long best = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    best = max(best, static_cast<unsigned long long>(__double_as_longlong(fabs(w[i]))));
+  for (int o = 32; o > 0; o >>= 1) best = max(best, static_cast<unsigned long long>(__shfl_xor(best, o)));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, best);
 }
 
 // T[row] = sum_m table[row][m] H[m]; one workgroup per (l, a, b) row, a
@@ -552,42 +606,125 @@ size_t ddr2_max_nodes(Ctx &c) {
   int lds = 0;
   HIPSTER_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device));
   hipFuncAttributes fa{};
-  HIPSTER_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_ddr2_hist<true>)));
+  HIPSTER_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_ddr2_hist<true, kHistDdr2>)));
   const long avail = long(lds) - long(fa.sharedSizeBytes);
   return avail > 8 ? size_t(avail / 8) : 0;
 }
 
-void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, const double *table, int rows,
-                double *T, unsigned long long *ordered) {
+// One histogram sweep of `s` (sorted on grid `g`) and its contraction
+// out[row] = sum_m table[row][m] H[m] over n_hist nodes.
+template <int KIND>
+static void hist_sweep(Ctx &c, const Sorted &s, const Grid &g, double lim2, double inv_h, int n_x, int n_keep,
+                       int n_hist, double inv_r0, double fix_scale, const double *table, int rows, double *out,
+                       unsigned long long *ordered) {
+  if (size_t(n_hist) > ddr2_max_nodes(c)) throw Error{HIPSTER_EUNSUPPORTED, "pair histogram exceeds the device's LDS"};
   const PairUnits u = make_pair_units(c, s, g);
-  const int n_nodes = n_x + 1;
   int nwg = 0;
   {
-    int dev = c.device, cus = 0;
-    HIPSTER_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int cus = 0;
+    HIPSTER_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
     nwg = std::max(1, cus) * 4;
   }
-  double *partial = static_cast<double *>(ensure(c, c.ddr2_partial, size_t(nwg) * n_nodes * 8));
-  double *H = static_cast<double *>(ensure(c, c.ddr2_hist, size_t(n_nodes) * 8));
+  double *partial = static_cast<double *>(ensure(c, c.ddr2_partial, size_t(nwg) * n_hist * 8));
+  double *H = static_cast<double *>(ensure(c, c.ddr2_hist, size_t(n_hist) * 8));
   unsigned long long *counter = static_cast<unsigned long long *>(ensure(c, c.ddr2_counter, 8));
   HIPSTER_HIP(hipMemsetAsync(counter, 0, 8, c.stream));
-  const size_t lds = size_t(n_nodes) * 8;
-  const double lim2 = (2.0 * r0) * (2.0 * r0), inv_h = n_x / (2.0 * r0);
+  const size_t lds = size_t(n_hist) * 8;
   if (u.n > 0) {
     if (s.m)
-      k_ddr2_hist<true><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
-          s, g.nc, g.L, lim2, inv_h, n_x, u.cell, u.tile, u.n, counter, ordered, partial);
+      k_ddr2_hist<true, KIND><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
+          s, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, u.cell, u.tile, u.n, counter, ordered,
+          partial);
     else
-      k_ddr2_hist<false><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
-          s, g.nc, g.L, lim2, inv_h, n_x, u.cell, u.tile, u.n, counter, ordered, partial);
+      k_ddr2_hist<false, KIND><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
+          s, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, u.cell, u.tile, u.n, counter, ordered,
+          partial);
     HIPSTER_HIP(hipGetLastError());
   } else {
-    HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_nodes * 8, c.stream));
+    HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_hist * 8, c.stream));
   }
-  k_ddr2_reduce<<<dim3(unsigned((n_nodes + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_nodes, H);
+  if (KIND == kHistCterm)
+    k_hist_reduce_fix<<<dim3(unsigned((n_hist + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_hist,
+                                                                                          1.0 / fix_scale, H);
+  else
+    k_ddr2_reduce<<<dim3(unsigned((n_hist + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_hist, H);
   HIPSTER_HIP(hipGetLastError());
-  k_ddr2_contract<<<dim3(unsigned(rows)), dim3(256), 0, c.stream>>>(table, H, n_nodes, T);
+  k_ddr2_contract<<<dim3(unsigned(rows)), dim3(256), 0, c.stream>>>(table, H, n_hist, out);
   HIPSTER_HIP(hipGetLastError());
+}
+
+void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, const double *table, int rows,
+                double *T, unsigned long long *ordered) {
+  hist_sweep<kHistDdr2>(c, s, g, (2.0 * r0) * (2.0 * r0), n_x / (2.0 * r0), n_x, n_x, n_x + 1, 0.0, 1.0, table, rows,
+                        T, ordered);
+}
+
+// ------------------------------------------------------------------ C term
+// F^ab_l(x_m) = jbar^a_l(x_m) jbar^b_l(x_m) on the nodes x_m = m R0 / n_c,
+// m = 0 .. n_c + 2 (past R0: the quintic around r < R0 reaches node
+// n_c + 2); F is even in x (jbar_l ~ x^l times a series in x^2).  The window
+// is not in the table: the sweep applies W(r/R0)^2 to each pair exactly, so
+// the tabulated function is entire and the interpolation error stays at
+// ~5e-3 (2 k_max h)^6 of it.
+__global__ __launch_bounds__(256) void k_cterm_table(double h, int n_nodes, int n_k, int n_l,
+                                                     const double *__restrict__ ek_g,
+                                                     const double *__restrict__ coef_g, double *__restrict__ F) {
+  __shared__ double2 tab[kSinCosTab];
+  __shared__ double ek[2 * (kEiiMaxNk + 1)], coef[kEiiMaxNk];
+  stage_sincos_tab<kSinCosTab>(tab);
+  for (int i = threadIdx.x; i < 2 * (n_k + 1); i += 256) ek[i] = ek_g[i];
+  for (int i = threadIdx.x; i < n_k; i += 256) coef[i] = coef_g[i];
+  __syncthreads();
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n_nodes * n_l) return;
+  const int l = idx / n_nodes, m = idx - l * n_nodes;
+  double g[kEiiMaxNk];
+  g_bins(l, m * h, 0.0, n_k, ek, coef, tab, g);  // W(0) = 1: plain jbar
+  for (int a = 0; a < n_k; ++a)
+    for (int b = 0; b < n_k; ++b) F[((size_t(l) * n_k + a) * n_k + b) * n_nodes + m] = g[a] * g[b];
+}
+
+int cterm_default_nodes(double r0, double k_max) {
+  // 2 k_max h <= 0.1: the quintic's error is ~5e-3 (0.1)^6 = 5e-9 of F
+  const double want = 2.0 * k_max * r0 / 0.1;
+  int n = int(std::min(double(kEiiMaxNodes - 64), ceil(want / 64.0) * 64.0));
+  return std::max(64, n);
+}
+
+void cterm_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, const double *k_edges, int ell_max,
+                 int n_c, uint64_t n_ordered, double *C, unsigned long long *ordered) {
+  const int n_nodes = n_c + 3, n_l = ell_max + 1, rows = n_l * n_k * n_k;
+  std::vector<double> ek(static_cast<size_t>(2 * (n_k + 1))), coef(static_cast<size_t>(n_k));
+  for (int e = 0; e <= n_k; ++e) {
+    ek[size_t(2 * e)] = k_edges[e];
+    ek[size_t(2 * e + 1)] = k_edges[e] * k_edges[e] * k_edges[e];
+  }
+  for (int b = 0; b < n_k; ++b) coef[size_t(b)] = 3.0 / (ek[size_t(2 * b + 3)] - ek[size_t(2 * b + 1)]);
+  double *dk = static_cast<double *>(ensure(c, c.ct_consts, size_t(3 * n_k + 2) * 8));
+  HIPSTER_HIP(hipMemcpyAsync(dk, ek.data(), ek.size() * 8, hipMemcpyHostToDevice, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(dk + ek.size(), coef.data(), coef.size() * 8, hipMemcpyHostToDevice, c.stream));
+  double *F = static_cast<double *>(ensure(c, c.ct_tab, size_t(rows) * n_nodes * 8));
+  const double h = r0 / n_c;
+  k_cterm_table<<<dim3(unsigned((n_nodes * n_l + 255) / 256)), dim3(256), 0, c.stream>>>(h, n_nodes, n_k, n_l, dk,
+                                                                                         dk + ek.size(), F);
+  HIPSTER_HIP(hipGetLastError());
+  // fixed-point scale: every node's sum of |w_p w_q^2 W^2 l_q(t)| is at most
+  // n_ordered * w_max^3 * max|l_q| (|l_q| < 1.2 on [0, 1)), kept below 2^61
+  unsigned long long *wm = static_cast<unsigned long long *>(ensure(c, c.ct_wmax, 8));
+  HIPSTER_HIP(hipMemsetAsync(wm, 0, 8, c.stream));
+  if (s.n > 0) {
+    k_absmax<<<dim3(unsigned(std::min<int64_t>((s.n + 255) / 256, 1024))), dim3(256), 0, c.stream>>>(s.w, s.n, wm);
+    HIPSTER_HIP(hipGetLastError());
+  }
+  unsigned long long wbits = 0;
+  HIPSTER_HIP(hipMemcpyAsync(&wbits, wm, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  double w_max;
+  memcpy(&w_max, &wbits, 8);
+  const double bound = (double(n_ordered) + 1.0) * 1.2 * std::max(w_max * w_max * w_max, 1e-300);
+  const int e = std::min(52, 61 - int(ceil(log2(bound))));
+  const double fix_scale = ldexp(1.0, e);
+  hist_sweep<kHistCterm>(c, s, g, r0 * r0, 1.0 / h, n_c, n_nodes, n_nodes, 1.0 / r0, fix_scale, F, rows, C, ordered);
 }
 
 }  // namespace hipster
