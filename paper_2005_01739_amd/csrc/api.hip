@@ -551,27 +551,31 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   for (int set = 0; set < (have_r ? 2 : 1); ++set) {
     const Sorted &prim = set == 0 ? sd : sr;
     hipEvent_t b1 = tm.mark();
-    bk_fused(c, prim, sd, g, q->r0, set == 0, edges, coef_d, NK, q->ell_max, fp64, !(c_hist && set == 0), part[set],
-             rowlen, nwaves,
+    bk_fused(c, prim, sd, g, q->r0, set == 0, edges, coef_d, NK, q->ell_max, fp64, !c_hist, part[set], rowlen, nwaves,
              cnt + set);
     hipEvent_t b2 = tm.mark();
     HIPSTER_HIP(hipEventSynchronize(b2));
     ms_sweep += Timer::ms(b1, b2);
     ++launches;
   }
-  std::vector<double> Ch;
+  // C of the data primaries (Ch[0]) and of the random primaries (Ch[1])
+  std::vector<double> Ch[2];
   double ms_cterm = 0.0;
   if (c_hist) {
     hipEvent_t c0 = tm.mark();
     const int rows = NL * NK * NK;
-    double *Cd = static_cast<double *>(ensure(c, c.ct_C, size_t(rows) * 8));
-    unsigned long long n_dd = 0;
-    HIPSTER_HIP(hipMemcpyAsync(&n_dd, cnt, 8, hipMemcpyDeviceToHost, c.stream));
+    double *Cd = static_cast<double *>(ensure(c, c.ct_C, size_t(2 * rows) * 8));
+    unsigned long long n_ord[2] = {0, 0};
+    HIPSTER_HIP(hipMemcpyAsync(n_ord, cnt, 16, hipMemcpyDeviceToHost, c.stream));
     HIPSTER_HIP(hipStreamSynchronize(c.stream));
-    cterm_sweep(c, sd, g, q->r0, NK, q->k_edges, q->ell_max, cterm_default_nodes(q->r0, q->k_edges[NK]), n_dd, Cd,
-                cnt + 2);
-    Ch.resize(size_t(rows));
-    HIPSTER_HIP(hipMemcpyAsync(Ch.data(), Cd, size_t(rows) * 8, hipMemcpyDeviceToHost, c.stream));
+    const int n_c = cterm_default_nodes(q->r0, q->k_edges[NK]);
+    for (int set = 0; set < (have_r ? 2 : 1); ++set) {
+      cterm_sweep(c, set == 0 ? sd : sr, sd, set == 1, g, q->r0, NK, q->k_edges, q->ell_max, n_c, n_ord[set],
+                  Cd + size_t(set) * rows, cnt + 2);
+      Ch[set].resize(size_t(rows));
+      HIPSTER_HIP(hipMemcpyAsync(Ch[set].data(), Cd + size_t(set) * rows, size_t(rows) * 8, hipMemcpyDeviceToHost,
+                                 c.stream));
+    }
     hipEvent_t c1 = tm.mark();
     HIPSTER_HIP(hipEventSynchronize(c1));
     ms_cterm = Timer::ms(c0, c1);
@@ -618,10 +622,11 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
         const int t = l * 256 + std::min(a, b) * 16 + std::max(a, b);
         const size_t o = (size_t(l) * NK + a) * NK + b;
         const double GD = Md[t];
-        const double CD = c_hist ? Ch[(size_t(l) * NK + std::min(a, b)) * NK + std::max(a, b)] : Md[nT + t];
+        const size_t tc = (size_t(l) * NK + std::min(a, b)) * NK + std::max(a, b);
+        const double CD = c_hist ? Ch[0][tc] : Md[nT + t];
         // the random-primary term s_R (G_R - C_R) estimates n_w T, T = sum_{i!=j} w_i w_j E^II
         const double GR = analytic ? T[(size_t(l) * NK + std::min(a, b)) * NK + std::max(a, b)] : Mr[t];
-        const double CR = analytic ? 0.0 : Mr[nT + t];
+        const double CR = analytic ? 0.0 : (c_hist && have_r ? Ch[1][tc] : Mr[nT + t]);
         const double sgn = (l & 1) ? -1.0 : 1.0;
         const double ddr2 = analytic ? nw * GR : sR * (GR - CR);
         double v = sgn * (2.0 * l + 1.0) / (V * nw * nw * nw) * ((GD - CD) - ddr2);

@@ -166,9 +166,9 @@ size_t bk_fused_lds(int NL, int NK) {
 // kUSmall replaced by the Taylor branch (a uniform branch, taken only when
 // some lane needs it).
 // WITH_C = false leaves the C sums out (their partial-row entries stay zero):
-// the mixed form takes C of the data primaries from the pair histogram of
-// the C-term sweep instead (k_ddr2_hist), which saves the NL matrix
-// instructions per step that C costs here.
+// the mixed form takes C from the pair histogram of the C-term sweep instead
+// (k_ddr2_hist), which saves the NL matrix instructions per step that C costs
+// here.
 template <int NL, bool FP64, bool WITH_C>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WITH_C ? HIPSTER_BK_WAVES_PER_EU
                                                                              : HIPSTER_BK_WAVES_PER_EU_NOC))) void

@@ -198,16 +198,19 @@ void eii_table(Ctx &c, double r0, int n_k, const double *k_edges, int ell_max, i
 void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, const double *table, int rows,
                 double *T, unsigned long long *ordered);
 size_t ddr2_max_nodes(Ctx &c);
-// C term of the bispectrum's data primaries in the mixed form:
+// C term of the bispectrum in the mixed form:
 // C^ab_l = sum over ordered pairs (p, q != p) inside R0, p selected by the
 // mask, of w_p w_q^2 W(r/R0)^2 jbar^a_l(r) jbar^b_l(r), from a pair histogram
 // of interpolation weights on the nodes m R0 / n_c and a table of
 // jbar^a jbar^b; C [ell_max+1][n_k][n_k] (device).  `s` is the data sorted on
 // the R0 grid `g`.
 int cterm_default_nodes(double r0, double k_max);
+// cross = false: `s` with itself (b ignored); cross = true: primaries `s`
+// (random primaries) against secondaries `b` (the data), every pair once.
 // n_ordered: the ordered pairs inside R0 (bounds the fixed-point sums).
-void cterm_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, const double *k_edges, int ell_max,
-                 int n_c, uint64_t n_ordered, double *C, unsigned long long *ordered);
+void cterm_sweep(Ctx &c, const Sorted &s, const Sorted &b, bool cross, const Grid &g, double r0, int n_k,
+                 const double *k_edges, int ell_max, int n_c, uint64_t n_ordered, double *C,
+                 unsigned long long *ordered);
 
 // Host analytic terms.
 double wtilde_bin(double r0, double k1, double k2);

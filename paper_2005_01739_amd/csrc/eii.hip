@@ -309,14 +309,19 @@ enum HistKind {
   kHistCterm = 1,  // pairs inside R0, weight w_p w_q^2 W(r/R0)^2 per orientation (p, q)
 };
 
+// CROSS: the home points (primaries) come from `s` and the neighbours from
+// `b`, found once per (primary, neighbour) pair through all 27 cells (the C
+// term of random primaries against the data); otherwise `b` is `s` and each
+// unordered pair is found once through the half stencil.
 // n_x: table intervals (the interval index is clamped to n_x - 1); nodes
 // below n_keep receive weights, the others hold a zero kernel value;
 // n_hist: histogram entries.  kHistDdr2: n_keep = n_x, n_hist = n_x + 1,
 // double sums (FP64 LDS atomics: reproducible to rounding); kHistCterm:
 // n_keep = n_hist = n_x + 3 (the table runs past R0), 64-bit fixed-point
 // sums with scale fix_scale (bitwise reproducible).
-template <bool MASKED, int KIND>
-__global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, double L, double lim2, double inv_h,
+template <bool MASKED, int KIND, bool CROSS>
+__global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
+                                                            double inv_h,
                                                             int n_x, int n_keep, int n_hist, double inv_r0,
                                                             double fix_scale,
                                                             const int *__restrict__ unit_cell,
@@ -327,9 +332,10 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
   extern __shared__ double hist[];  // n_hist nodes
   __shared__ double4 home[kHistTile];
   __shared__ int hm[kHistTile];
-  __shared__ int64_t nb_start[14];
-  __shared__ int nb_count[14], nb_first[15];
-  __shared__ double nb_off[14][3];
+  constexpr int kStencil = CROSS ? 27 : 14;
+  __shared__ int64_t nb_start[kStencil];
+  __shared__ int nb_count[kStencil], nb_first[kStencil + 1];
+  __shared__ double nb_off[kStencil][3];
   __shared__ int64_t cur_unit;
   constexpr int kWaves = kHistThreads / 64;
   // single-precision home coordinates for the prefilter
@@ -392,10 +398,14 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
       r2 = (a + b) + c;
     }
     if (r2 < lim2) {
-      const int mi_ = MASKED ? hm[ii] : 1, mj_ = MASKED ? (s.m ? int(s.m[j]) : 1) : 1;
+      const int mi_ = MASKED ? hm[ii] : 1, mj_ = CROSS ? 0 : (MASKED ? (b.m ? int(b.m[j]) : 1) : 1);
       ord += unsigned(mi_ + mj_);
       if (mi_ + mj_ > 0) {
-        if constexpr (KIND == kHistDdr2) {
+        if constexpr (CROSS) {
+          // (primary i, neighbour j) only
+          const double W = window<double>(sqrt(r2) * inv_r0);
+          spread(r2, p.w * q.w * q.w * double(mi_) * (W * W));
+        } else if constexpr (KIND == kHistDdr2) {
           spread(r2, p.w * q.w * double(mi_ + mj_));
         } else {
           // (i, j) as (p, q) if i is selected, and (j, i) if j is
@@ -423,9 +433,13 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
       homef[tid] = make_float4(float(s.x[i]), float(s.y[i]), float(s.z[i]), 0.0f);
       if (MASKED) hm[tid] = s.m ? int(s.m[i]) : 1;
     }
-    if (tid < 14) {
+    if (tid < kStencil) {
       int ox, oy, oz;
-      if (tid == 0) {
+      if (CROSS) {
+        ox = tid / 9 - 1;
+        oy = (tid / 3) % 3 - 1;
+        oz = tid % 3 - 1;
+      } else if (tid == 0) {
         ox = oy = oz = 0;
       } else {
         const int t = tid + 13;
@@ -439,8 +453,8 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
       if (ny >= nc) { ny -= nc; sy = 1; } else if (ny < 0) { ny += nc; sy = -1; }
       if (nz >= nc) { nz -= nc; sz = 1; } else if (nz < 0) { nz += nc; sz = -1; }
       const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
-      nb_start[tid] = s.cell_start[nb];
-      nb_count[tid] = int(s.cell_start[nb + 1] - s.cell_start[nb]);
+      nb_start[tid] = b.cell_start[nb];
+      nb_count[tid] = int(b.cell_start[nb + 1] - b.cell_start[nb]);
       nb_off[tid][0] = double(sx) * L;
       nb_off[tid][1] = double(sy) * L;
       nb_off[tid][2] = double(sz) * L;
@@ -450,28 +464,28 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, int nc, do
       // neighbour tiles; in the home cell only tiles from the home tile on
       // hold pairs j > i
       int tot = 0;
-      for (int st = 0; st < 14; ++st) {
+      for (int st = 0; st < kStencil; ++st) {
         nb_first[st] = tot;
-        const int t0 = st == 0 ? i0 / kHistTile : 0;
+        const int t0 = !CROSS && st == 0 ? i0 / kHistTile : 0;
         tot += max(0, (nb_count[st] + kHistTile - 1) / kHistTile - t0);
       }
-      nb_first[14] = tot;
+      nb_first[kStencil] = tot;
     }
     __syncthreads();
-    const int items = nb_first[14];
+    const int items = nb_first[kStencil];
     for (int it = wave; it < items; it += kWaves) {
       int st = 0;
       while (it >= nb_first[st + 1]) ++st;
-      const int j0 = ((st == 0 ? i0 / kHistTile : 0) + it - nb_first[st]) * kHistTile;
+      const int j0 = ((!CROSS && st == 0 ? i0 / kHistTile : 0) + it - nb_first[st]) * kHistTile;
       const int tj = min(kHistTile, nb_count[st] - j0);
-      const bool self = st == 0;
+      const bool self = !CROSS && st == 0;
       const double offx = nb_off[st][0], offy = nb_off[st][1], offz = nb_off[st][2];
       const int64_t jbase = nb_start[st] + j0;
       // single-precision copy of this lane's neighbour image for the prefilter
       float fx = 0.0f, fy = 0.0f, fz = 0.0f;
       if (lane < tj) {
         const int64_t j = jbase + lane;
-        const double4 q = make_double4(s.x[j], s.y[j], s.z[j], s.w[j]);
+        const double4 q = make_double4(b.x[j], b.y[j], b.z[j], b.w[j]);
         jt[wave][lane] = q;
         fx = float(q.x + offx);
         fy = float(q.y + offy);
@@ -606,15 +620,16 @@ size_t ddr2_max_nodes(Ctx &c) {
   int lds = 0;
   HIPSTER_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device));
   hipFuncAttributes fa{};
-  HIPSTER_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_ddr2_hist<true, kHistDdr2>)));
+  HIPSTER_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_ddr2_hist<true, kHistCterm, true>)));
   const long avail = long(lds) - long(fa.sharedSizeBytes);
   return avail > 8 ? size_t(avail / 8) : 0;
 }
 
 // One histogram sweep of `s` (sorted on grid `g`) and its contraction
 // out[row] = sum_m table[row][m] H[m] over n_hist nodes.
-template <int KIND>
-static void hist_sweep(Ctx &c, const Sorted &s, const Grid &g, double lim2, double inv_h, int n_x, int n_keep,
+template <int KIND, bool CROSS>
+static void hist_sweep(Ctx &c, const Sorted &s, const Sorted &b, const Grid &g, double lim2, double inv_h, int n_x,
+                       int n_keep,
                        int n_hist, double inv_r0, double fix_scale, const double *table, int rows, double *out,
                        unsigned long long *ordered) {
   if (size_t(n_hist) > ddr2_max_nodes(c)) throw Error{HIPSTER_EUNSUPPORTED, "pair histogram exceeds the device's LDS"};
@@ -631,13 +646,13 @@ static void hist_sweep(Ctx &c, const Sorted &s, const Grid &g, double lim2, doub
   HIPSTER_HIP(hipMemsetAsync(counter, 0, 8, c.stream));
   const size_t lds = size_t(n_hist) * 8;
   if (u.n > 0) {
-    if (s.m)
-      k_ddr2_hist<true, KIND><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
-          s, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, u.cell, u.tile, u.n, counter, ordered,
+    if (s.m || (!CROSS && b.m))
+      k_ddr2_hist<true, KIND, CROSS><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
+          s, b, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, u.cell, u.tile, u.n, counter, ordered,
           partial);
     else
-      k_ddr2_hist<false, KIND><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
-          s, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, u.cell, u.tile, u.n, counter, ordered,
+      k_ddr2_hist<false, KIND, CROSS><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
+          s, b, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, u.cell, u.tile, u.n, counter, ordered,
           partial);
     HIPSTER_HIP(hipGetLastError());
   } else {
@@ -655,7 +670,7 @@ static void hist_sweep(Ctx &c, const Sorted &s, const Grid &g, double lim2, doub
 
 void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, const double *table, int rows,
                 double *T, unsigned long long *ordered) {
-  hist_sweep<kHistDdr2>(c, s, g, (2.0 * r0) * (2.0 * r0), n_x / (2.0 * r0), n_x, n_x, n_x + 1, 0.0, 1.0, table, rows,
+  hist_sweep<kHistDdr2, false>(c, s, s, g, (2.0 * r0) * (2.0 * r0), n_x / (2.0 * r0), n_x, n_x, n_x + 1, 0.0, 1.0, table, rows,
                         T, ordered);
 }
 
@@ -691,8 +706,25 @@ int cterm_default_nodes(double r0, double k_max) {
   return std::max(64, n);
 }
 
-void cterm_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, const double *k_edges, int ell_max,
-                 int n_c, uint64_t n_ordered, double *C, unsigned long long *ordered) {
+// Largest |w| of a sorted catalogue (host value).
+static double weight_max(Ctx &c, const Sorted &s) {
+  unsigned long long *wm = static_cast<unsigned long long *>(ensure(c, c.ct_wmax, 8));
+  HIPSTER_HIP(hipMemsetAsync(wm, 0, 8, c.stream));
+  if (s.n > 0) {
+    k_absmax<<<dim3(unsigned(std::min<int64_t>((s.n + 255) / 256, 1024))), dim3(256), 0, c.stream>>>(s.w, s.n, wm);
+    HIPSTER_HIP(hipGetLastError());
+  }
+  unsigned long long wbits = 0;
+  HIPSTER_HIP(hipMemcpyAsync(&wbits, wm, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  double w_max;
+  memcpy(&w_max, &wbits, 8);
+  return w_max;
+}
+
+void cterm_sweep(Ctx &c, const Sorted &s, const Sorted &b, bool cross, const Grid &g, double r0, int n_k,
+                 const double *k_edges, int ell_max, int n_c, uint64_t n_ordered, double *C,
+                 unsigned long long *ordered) {
   const int n_nodes = n_c + 3, n_l = ell_max + 1, rows = n_l * n_k * n_k;
   std::vector<double> ek(static_cast<size_t>(2 * (n_k + 1))), coef(static_cast<size_t>(n_k));
   for (int e = 0; e <= n_k; ++e) {
@@ -709,22 +741,18 @@ void cterm_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, con
                                                                                          dk + ek.size(), F);
   HIPSTER_HIP(hipGetLastError());
   // fixed-point scale: every node's sum of |w_p w_q^2 W^2 l_q(t)| is at most
-  // n_ordered * w_max^3 * max|l_q| (|l_q| < 1.2 on [0, 1)), kept below 2^61
-  unsigned long long *wm = static_cast<unsigned long long *>(ensure(c, c.ct_wmax, 8));
-  HIPSTER_HIP(hipMemsetAsync(wm, 0, 8, c.stream));
-  if (s.n > 0) {
-    k_absmax<<<dim3(unsigned(std::min<int64_t>((s.n + 255) / 256, 1024))), dim3(256), 0, c.stream>>>(s.w, s.n, wm);
-    HIPSTER_HIP(hipGetLastError());
-  }
-  unsigned long long wbits = 0;
-  HIPSTER_HIP(hipMemcpyAsync(&wbits, wm, 8, hipMemcpyDeviceToHost, c.stream));
-  HIPSTER_HIP(hipStreamSynchronize(c.stream));
-  double w_max;
-  memcpy(&w_max, &wbits, 8);
-  const double bound = (double(n_ordered) + 1.0) * 1.2 * std::max(w_max * w_max * w_max, 1e-300);
+  // n_ordered * max w_p * (max w_q)^2 * max|l_q| (|l_q| < 1.2 on [0, 1)),
+  // kept below 2^61
+  const double wa = weight_max(c, s), wb = cross ? weight_max(c, b) : wa;
+  const double bound = (double(n_ordered) + 1.0) * 1.2 * std::max(wa * wb * wb, 1e-300);
   const int e = std::min(52, 61 - int(ceil(log2(bound))));
   const double fix_scale = ldexp(1.0, e);
-  hist_sweep<kHistCterm>(c, s, g, r0 * r0, 1.0 / h, n_c, n_nodes, n_nodes, 1.0 / r0, fix_scale, F, rows, C, ordered);
+  if (cross)
+    hist_sweep<kHistCterm, true>(c, s, b, g, r0 * r0, 1.0 / h, n_c, n_nodes, n_nodes, 1.0 / r0, fix_scale, F, rows,
+                                 C, ordered);
+  else
+    hist_sweep<kHistCterm, false>(c, s, s, g, r0 * r0, 1.0 / h, n_c, n_nodes, n_nodes, 1.0 / r0, fix_scale, F, rows,
+                                  C, ordered);
 }
 
 }  // namespace hipster
