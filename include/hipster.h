@@ -168,9 +168,9 @@ hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data,
  * The table is cached in the context and reused while (R0, n_x, ell_max,
  * k_edges) stay the same.  Other arguments, output and errors as
  * hipster_bk_ell; prm->random_mask is ignored.  In diag: gr = T, cr = 0,
- * n_pairs_rand = 0, n_pairs_2r0, ms_eii_table, ms_ddr2, eii_nodes.  Pair sums
- * within a workgroup use floating-point atomics, so repeated calls agree to
- * rounding (about 1e-16 relative), not bit for bit. */
+ * n_pairs_rand = 0, n_pairs_2r0, ms_eii_table, ms_ddr2, eii_nodes.  The pair
+ * sums go through 64-bit fixed-point histograms, so repeated calls give the
+ * same bits. */
 hipster_status hipster_bk_ell_analytic(hipster_ctx *ctx, const hipster_points *data, const hipster_params *prm,
                                        int32_t n_x, double *bk, hipster_diag *diag);
 

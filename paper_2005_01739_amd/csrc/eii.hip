@@ -18,9 +18,10 @@
 //                 interpolated kernel is then sum_m E_m H_m exactly, so the
 //                 sweep does the same small work for any number of bins and
 //                 multipoles;
-//   k_ddr2_reduce, k_ddr2_contract
-//                 fixed-order sums of the per-workgroup histograms and the
-//                 contraction T^ab_l = sum_m E^ab_l(x_m) H_m.
+//   k_hist_reduce_fix, k_ddr2_contract
+//                 exact integer sums of the per-workgroup (64-bit fixed
+//                 point) histograms and the fixed-order contraction
+//                 T^ab_l = sum_m E^ab_l(x_m) H_m.
 //
 // Interpolation (a reading: the paper leaves the scheme open): on
 // [x_m, x_{m+1}) the quintic through the nodes m-2 .. m+3, t = x/h - m; nodes
@@ -315,10 +316,10 @@ enum HistKind {
 // unordered pair is found once through the half stencil.
 // n_x: table intervals (the interval index is clamped to n_x - 1); nodes
 // below n_keep receive weights, the others hold a zero kernel value;
-// n_hist: histogram entries.  kHistDdr2: n_keep = n_x, n_hist = n_x + 1,
-// double sums (FP64 LDS atomics: reproducible to rounding); kHistCterm:
-// n_keep = n_hist = n_x + 3 (the table runs past R0), 64-bit fixed-point
-// sums with scale fix_scale (bitwise reproducible).
+// n_hist: histogram entries.  kHistDdr2: n_keep = n_x, n_hist = n_x + 1;
+// kHistCterm: n_keep = n_hist = n_x + 3 (the table runs past R0).  Both sum
+// in 64-bit fixed point with scale fix_scale, so the histogram does not
+// depend on the order of the adds (bitwise reproducible).
 template <bool MASKED, int KIND, bool CROSS>
 __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
                                                             double inv_h,
@@ -371,13 +372,11 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
       int node = mi + q - 2;
       node = node < 0 ? -node : node;
       if (node < n_keep) {
-        if constexpr (KIND == kHistCterm) {
+        {
           // fixed point (scale 2^e chosen on the host so no sum can
           // overflow): integer sums do not depend on the order of the adds
           const long long iv = llrint(ww * lw[q] * fix_scale);
           atomicAdd(reinterpret_cast<unsigned long long *>(&hist[node]), static_cast<unsigned long long>(iv));
-        } else {
-          atomicAdd(&hist[node], ww * lw[q]);
         }
       }
     }
@@ -543,17 +542,8 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
   for (int i = tid; i < n_hist; i += kHistThreads) out[i] = hist[i];
 }
 
-// H[m] = sum over workgroups of partial[wg][m], in workgroup order.
-__global__ void k_ddr2_reduce(const double *__restrict__ partial, int nwg, int n_nodes, double *__restrict__ H) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n_nodes) return;
-  double s = 0.0;
-  for (int g = 0; g < nwg; ++g) s += partial[size_t(g) * n_nodes + m];
-  H[m] = s;
-}
-
-// The same for fixed-point histograms (the partial rows hold int64 bit
-// patterns): an exact integer sum, then H[m] = sum / scale.
+// H[m] = sum over workgroups of partial[wg][m] (the rows hold the int64 bit
+// patterns of fixed-point sums): an exact integer sum, then H[m] = sum / scale.
 __global__ void k_hist_reduce_fix(const double *__restrict__ partial, int nwg, int n_nodes, double inv_scale,
                                   double *__restrict__ H) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
@@ -658,20 +648,57 @@ static void hist_sweep(Ctx &c, const Sorted &s, const Sorted &b, const Grid &g, 
   } else {
     HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_hist * 8, c.stream));
   }
-  if (KIND == kHistCterm)
-    k_hist_reduce_fix<<<dim3(unsigned((n_hist + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_hist,
-                                                                                          1.0 / fix_scale, H);
-  else
-    k_ddr2_reduce<<<dim3(unsigned((n_hist + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_hist, H);
+  k_hist_reduce_fix<<<dim3(unsigned((n_hist + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_hist,
+                                                                                        1.0 / fix_scale, H);
   HIPSTER_HIP(hipGetLastError());
   k_ddr2_contract<<<dim3(unsigned(rows)), dim3(256), 0, c.stream>>>(table, H, n_hist, out);
   HIPSTER_HIP(hipGetLastError());
 }
 
+static double weight_max(Ctx &c, const Sorted &s);
+
+// Upper bound of the ordered (pair, image) terms of a half-stencil sweep:
+// twice the candidate pairs, sum over cells of n_cell times the points of
+// its 14 half-stencil cells.
+__global__ void k_candidate_bound(const int64_t *__restrict__ cell_start, int nc,
+                                  unsigned long long *__restrict__ out) {
+  const int64_t ncell = int64_t(nc) * nc * nc;
+  unsigned long long acc = 0;
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < ncell; c += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t n = cell_start[c + 1] - cell_start[c];
+    if (n == 0) continue;
+    const int cz = int(c % nc), cy = int((c / nc) % nc), cx = int(c / (int64_t(nc) * nc));
+    int64_t m = 0;
+    for (int t = 13; t < 27; ++t) {
+      const int nx = (cx + t / 9 - 1 + nc) % nc, ny = (cy + (t / 3) % 3 - 1 + nc) % nc, nz = (cz + t % 3 - 1 + nc) % nc;
+      const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
+      m += cell_start[nb + 1] - cell_start[nb];
+    }
+    acc += static_cast<unsigned long long>(2 * n * m);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+}
+
 void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, const double *table, int rows,
                 double *T, unsigned long long *ordered) {
-  hist_sweep<kHistDdr2, false>(c, s, s, g, (2.0 * r0) * (2.0 * r0), n_x / (2.0 * r0), n_x, n_x, n_x + 1, 0.0, 1.0, table, rows,
-                        T, ordered);
+  // fixed-point scale from the candidate bound: every node's sum of
+  // |w_i w_j l_q(t)| is at most (ordered candidates) * w_max^2 * 2.5 (a node
+  // takes at most two basis values of a pair, each below 1.25 in size)
+  unsigned long long *cb = static_cast<unsigned long long *>(ensure(c, c.ct_wmax, 8));
+  HIPSTER_HIP(hipMemsetAsync(cb, 0, 8, c.stream));
+  const int64_t ncell = g.ncells();
+  k_candidate_bound<<<dim3(unsigned(std::min<int64_t>((ncell + 255) / 256, 1024))), dim3(256), 0, c.stream>>>(
+      s.cell_start, g.nc, cb);
+  HIPSTER_HIP(hipGetLastError());
+  unsigned long long cand = 0;
+  HIPSTER_HIP(hipMemcpyAsync(&cand, cb, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  const double wm = weight_max(c, s);
+  const double bound = (double(cand) + 1.0) * 2.5 * std::max(wm * wm, 1e-300);
+  const int e = std::min(52, 61 - int(ceil(log2(bound))));
+  hist_sweep<kHistDdr2, false>(c, s, s, g, (2.0 * r0) * (2.0 * r0), n_x / (2.0 * r0), n_x, n_x, n_x + 1, 0.0,
+                               ldexp(1.0, e), table, rows, T, ordered);
 }
 
 // ------------------------------------------------------------------ C term
@@ -741,10 +768,10 @@ void cterm_sweep(Ctx &c, const Sorted &s, const Sorted &b, bool cross, const Gri
                                                                                          dk + ek.size(), F);
   HIPSTER_HIP(hipGetLastError());
   // fixed-point scale: every node's sum of |w_p w_q^2 W^2 l_q(t)| is at most
-  // n_ordered * max w_p * (max w_q)^2 * max|l_q| (|l_q| < 1.2 on [0, 1)),
-  // kept below 2^61
+  // n_ordered * max w_p * (max w_q)^2 * 2.5 (a node takes at most two basis
+  // values of a pair, each below 1.25 in size), kept below 2^61
   const double wa = weight_max(c, s), wb = cross ? weight_max(c, b) : wa;
-  const double bound = (double(n_ordered) + 1.0) * 1.2 * std::max(wa * wb * wb, 1e-300);
+  const double bound = (double(n_ordered) + 1.0) * 2.5 * std::max(wa * wb * wb, 1e-300);
   const int e = std::min(52, 61 - int(ceil(log2(bound))));
   const double fix_scale = ldexp(1.0, e);
   if (cross)
