@@ -20,6 +20,10 @@
 // inside R0 (Sec. 2 pair counts; Sec. 3 periodic box); its squared length is
 // (dx^2 + dy^2) + dz^2 in double precision without contraction, the predicate
 // that defines the integer pair count.
+#include <math.h>
+
+#include <algorithm>
+
 #include "common.h"
 #include "specfun.h"
 
@@ -71,9 +75,17 @@ enum PairMode { kPeriodic = 0, kSurveySelf = 1, kSurveyCross = 2 };
 // are ordered by home cell, then tile, so the stream order is the same for
 // any number of units per launch, and a dense cell is spread over as many
 // workgroups as it has tiles.
+//
+// Only ~1 candidate in 6 lies inside R0.  A single-precision prefilter, whose
+// bound lim2f covers the rounding of the coordinates to float with a wide
+// margin, passes candidates into a per-wave LDS queue (ballot + prefix
+// count); the exact double-precision predicate, the bucket and the stream
+// writes then run on 64 queued candidates at a time with every lane busy.
+// The queue keeps candidate order, so the count and write passes see the
+// same sequence.
 template <bool WRITE, int MODE, bool MASKED>
-__global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, double L, double r02, double rs2,
-                                                 int los, double scale, const int *__restrict__ unit_cell,
+__global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, double L, double r02, float lim2f,
+                                                 double rs2, int los, double scale, const int *__restrict__ unit_cell,
                                                  const int *__restrict__ unit_tile, int64_t u0,
                                                  int64_t *__restrict__ cnt_a, int64_t *__restrict__ cnt_b,
                                                  unsigned long long *__restrict__ ordered,
@@ -86,6 +98,8 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
   __shared__ double hx[kPairTile], hy[kPairTile], hz[kPairTile], hw[kPairTile];
   __shared__ double jx[kPairTile], jy[kPairTile], jz[kPairTile], jw[kPairTile];
   __shared__ int hm[kPairTile], jm[kPairTile];
+  __shared__ float hxf[kPairTile], hyf[kPairTile], hzf[kPairTile], jxf[kPairTile], jyf[kPairTile], jzf[kPairTile];
+  __shared__ int q_ii[128], q_jj[128];  // prefilter-passed candidates, in order
   constexpr int kStencil = MODE == kSurveyCross ? 27 : 14;
   const int64_t unit = u0 + blockIdx.x;
   const int64_t cell = unit_cell[unit];
@@ -107,6 +121,9 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
       hy[lane] = a.y[i];
       hz[lane] = a.z[i];
       hw[lane] = a.w[i];
+      hxf[lane] = float(a.x[i]);
+      hyf[lane] = float(a.y[i]);
+      hzf[lane] = float(a.z[i]);
       if (MASKED) hm[lane] = a.m ? int(a.m[i]) : 1;
     }
     for (int st = 0; st < kStencil; ++st) {
@@ -147,6 +164,10 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
           jy[lane] = b.y[j];
           jz[lane] = b.z[j];
           jw[lane] = b.w[j];
+          // the neighbour image, rounded to float for the prefilter
+          jxf[lane] = float(b.x[j] + offx);
+          jyf[lane] = float(b.y[j] + offy);
+          jzf[lane] = float(b.z[j] + offz);
           if (MASKED) jm[lane] = b.m ? int(b.m[j]) : 1;
         }
         __syncthreads();
@@ -155,43 +176,41 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
         // candidates per step, i.e. by (64 / tj, 64 % tj) with a carry
         const uint32_t utj = uint32_t(tj), d64 = 64u / utj, r64 = 64u - d64 * utj;
         uint32_t ii = uint32_t(lane) / utj, jj = uint32_t(lane) - ii * utj;
-        for (uint32_t q0 = 0; q0 < total; q0 += 64, ii += d64, jj += r64) {
-          if (jj >= utj) {
-            jj -= utj;
-            ++ii;
-          }
-          const uint32_t q = q0 + lane;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        int qn = 0;
+        // the exact test of queued candidates [0, cnt) (lane e takes entry e),
+        // then the buckets, the counts and (write pass) the stream
+        auto process = [&](int cnt) {
           bool hit = false, near = false;
           double r = 0.0, mu = 0.0, ww = 0.0;
-          if (q < total) {
-            if (!self || j0 + int(jj) > i0 + int(ii)) {
-              double dx = hx[ii] - jx[jj], dy = hy[ii] - jy[jj], dz = hz[ii] - jz[jj];
-              if constexpr (MODE == kPeriodic) {
-                dx -= offx;
-                dy -= offy;
-                dz -= offz;
-              }
-              const double r2 = sq_norm_exact(dx, dy, dz);
-              if (r2 < r02) {
-                // without masks every pair counts twice (i, j) and (j, i)
-                const int mult = MASKED ? hm[ii] + jm[jj] : 2;
-                if (MASKED) ord += unsigned(mult);
-                if (mult > 0) {
-                  hit = true;
-                  near = r2 < rs2;
-                  if (WRITE) {
-                    r = sqrt(r2);
-                    if (MODE == kPeriodic) {
-                      const double dl = los == 0 ? dx : (los == 1 ? dy : dz);
-                      mu = r > 0.0 ? dl / r : 0.0;
-                    } else {
-                      // line of sight along the pair midpoint (x_i + x_j) / 2
-                      const double mx = hx[ii] + jx[jj], my = hy[ii] + jy[jj], mz = hz[ii] + jz[jj];
-                      const double mn = sqrt((mx * mx + my * my) + mz * mz);
-                      mu = (r > 0.0 && mn > 0.0) ? ((dx * mx + dy * my) + dz * mz) / (r * mn) : 0.0;
-                    }
-                    ww = scale * (hw[ii] * jw[jj]) * double(mult);
+          if (lane < cnt) {
+            const int ci = q_ii[lane], cj = q_jj[lane];
+            double dx = hx[ci] - jx[cj], dy = hy[ci] - jy[cj], dz = hz[ci] - jz[cj];
+            if constexpr (MODE == kPeriodic) {
+              dx -= offx;
+              dy -= offy;
+              dz -= offz;
+            }
+            const double r2 = sq_norm_exact(dx, dy, dz);
+            if (r2 < r02) {
+              // without masks every pair counts twice (i, j) and (j, i)
+              const int mult = MASKED ? hm[ci] + jm[cj] : 2;
+              if (MASKED) ord += unsigned(mult);
+              if (mult > 0) {
+                hit = true;
+                near = r2 < rs2;
+                if (WRITE) {
+                  r = sqrt(r2);
+                  if (MODE == kPeriodic) {
+                    const double dl = los == 0 ? dx : (los == 1 ? dy : dz);
+                    mu = r > 0.0 ? dl / r : 0.0;
+                  } else {
+                    // line of sight along the pair midpoint (x_i + x_j) / 2
+                    const double mx = hx[ci] + jx[cj], my = hy[ci] + jy[cj], mz = hz[ci] + jz[cj];
+                    const double mn = sqrt((mx * mx + my * my) + mz * mz);
+                    mu = (r > 0.0 && mn > 0.0) ? ((dx * mx + dy * my) + dz * mz) / (r * mn) : 0.0;
                   }
+                  ww = scale * (hw[ci] * jw[cj]) * double(mult);
                 }
               }
             }
@@ -199,7 +218,6 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
           const unsigned long long bal_a = __ballot(hit && near), bal_b = __ballot(hit && !near);
           if (!MASKED) ord_w += 2u * unsigned(__popcll(bal_a | bal_b));
           if (WRITE && hit) {
-            const unsigned long long below = (1ull << lane) - 1ull;
             const int64_t k = near ? wbase_a + written_a + __popcll(bal_a & below)
                                    : wbase_b + written_b + __popcll(bal_b & below);
             out_r[k] = r;
@@ -208,7 +226,47 @@ __global__ __launch_bounds__(64) void k_pk_pairs(Sorted a, Sorted b, int nc, dou
           }
           written_a += __popcll(bal_a);
           written_b += __popcll(bal_b);
+        };
+        for (uint32_t q0 = 0; q0 < total; q0 += 64, ii += d64, jj += r64) {
+          if (jj >= utj) {
+            jj -= utj;
+            ++ii;
+          }
+          const uint32_t q = q0 + lane;
+          bool cand = false;
+          if (q < total && (!self || j0 + int(jj) > i0 + int(ii))) {
+            const float fx = hxf[ii] - jxf[jj], fy = hyf[ii] - jyf[jj], fz = hzf[ii] - jzf[jj];
+            cand = fmaf(fx, fx, fmaf(fy, fy, fz * fz)) < lim2f;
+          }
+          const unsigned long long bal = __ballot(cand);
+          if (bal) {
+            if (cand) {
+              const int at = qn + __popcll(bal & below);
+              q_ii[at] = int(ii);
+              q_jj[at] = int(jj);
+            }
+            qn += __popcll(bal);
+            if (qn >= 64) {
+              __syncthreads();
+              process(64);
+              const int rest = qn - 64;
+              int vi = 0, vj = 0;
+              if (lane < rest) {
+                vi = q_ii[64 + lane];
+                vj = q_jj[64 + lane];
+              }
+              __syncthreads();
+              if (lane < rest) {
+                q_ii[lane] = vi;
+                q_jj[lane] = vj;
+              }
+              qn = rest;
+              __syncthreads();
+            }
+          }
         }
+        __syncthreads();
+        if (qn > 0) process(qn);
       }
     }
   }
@@ -262,6 +320,22 @@ PairUnits make_pair_units(Ctx &c, const Sorted &a, const Grid &g) {
   return u;
 }
 
+// Bound of the single-precision prefilter: (R0 + delta)^2 with
+// delta = 2^-17 M, M the largest coordinate magnitude a test sees (2 L for a
+// periodic neighbour image, else the grid's extent from the origin).  A
+// coordinate rounds to float within 2^-24 M and the float distance errs by
+// less than 2^-20 M, so no pair inside R0 is rejected.
+static float prefilter_bound(const Grid &g, double r0) {
+  double m = 2.0 * g.L;
+  if (!g.periodic) {
+    const double o[3] = {g.ox, g.oy, g.oz};
+    m = 0.0;
+    for (int d = 0; d < 3; ++d) m = std::max(m, std::max(fabs(o[d]), fabs(o[d] + g.L)));
+  }
+  const double b = r0 + 0x1p-17 * m;
+  return float(b * b);
+}
+
 // One launch of the enumeration kernel, with the mask handling compiled in
 // only when a catalogue carries a mask.
 template <bool WRITE, int MODE, typename... Args>
@@ -276,7 +350,7 @@ static void launch_pairs(Ctx &c, dim3 grid, const Sorted &a, const Sorted &b, Ar
 void pk_pairs_count(Ctx &c, const Sorted &s, const Grid &g, const PairUnits &u, double r0, double r_split,
                     int64_t *cnt_a, int64_t *cnt_b, unsigned long long *ordered) {
   if (u.n <= 0) return;
-  launch_pairs<false, kPeriodic>(c, dim3(unsigned(u.n)), s, s, g.nc, g.L, r0 * r0, r_split * r_split, 2, 1.0,
+  launch_pairs<false, kPeriodic>(c, dim3(unsigned(u.n)), s, s, g.nc, g.L, r0 * r0, prefilter_bound(g, r0), r_split * r_split, 2, 1.0,
                                  u.cell, u.tile, int64_t(0), cnt_a, cnt_b, ordered, (const int64_t *)nullptr,
                                  (const int64_t *)nullptr, int64_t(0), int64_t(0), int64_t(0), (double *)nullptr,
                                  (double *)nullptr, (double *)nullptr);
@@ -286,7 +360,7 @@ void pk_pairs_write(Ctx &c, const Sorted &s, const Grid &g, const PairUnits &u, 
                     const int64_t *off_a, const int64_t *off_b, int64_t base_a, int64_t base_b, int64_t n_a,
                     int64_t u0, int64_t u1, PkPairs out) {
   if (u1 <= u0) return;
-  launch_pairs<true, kPeriodic>(c, dim3(unsigned(u1 - u0)), s, s, g.nc, g.L, r0 * r0, r_split * r_split, los, 1.0,
+  launch_pairs<true, kPeriodic>(c, dim3(unsigned(u1 - u0)), s, s, g.nc, g.L, r0 * r0, prefilter_bound(g, r0), r_split * r_split, los, 1.0,
                                 u.cell, u.tile, u0, (int64_t *)nullptr, (int64_t *)nullptr,
                                 (unsigned long long *)nullptr, off_a, off_b, base_a, base_b, n_a, out.r,
                                 static_cast<double *>(out.mu), static_cast<double *>(out.ww));
@@ -297,12 +371,12 @@ void survey_pairs_count(Ctx &c, const Sorted &a, const Sorted &b, bool cross, co
   if (u.n <= 0) return;
   const dim3 grid(unsigned(u.n));
   if (cross)
-    launch_pairs<false, kSurveyCross>(c, grid, a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, u.cell, u.tile,
+    launch_pairs<false, kSurveyCross>(c, grid, a, b, g.nc, g.L, r0 * r0, prefilter_bound(g, r0), r_split * r_split, 0, 1.0, u.cell, u.tile,
                                       int64_t(0), cnt_a, cnt_b, ordered, (const int64_t *)nullptr,
                                       (const int64_t *)nullptr, int64_t(0), int64_t(0), int64_t(0),
                                       (double *)nullptr, (double *)nullptr, (double *)nullptr);
   else
-    launch_pairs<false, kSurveySelf>(c, grid, a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, 1.0, u.cell, u.tile,
+    launch_pairs<false, kSurveySelf>(c, grid, a, a, g.nc, g.L, r0 * r0, prefilter_bound(g, r0), r_split * r_split, 0, 1.0, u.cell, u.tile,
                                      int64_t(0), cnt_a, cnt_b, ordered, (const int64_t *)nullptr,
                                      (const int64_t *)nullptr, int64_t(0), int64_t(0), int64_t(0),
                                      (double *)nullptr, (double *)nullptr, (double *)nullptr);
@@ -315,11 +389,11 @@ void survey_pairs_write(Ctx &c, const Sorted &a, const Sorted &b, bool cross, co
   const dim3 grid(unsigned(u1 - u0));
   double *mu = static_cast<double *>(out.mu), *ww = static_cast<double *>(out.ww);
   if (cross)
-    launch_pairs<true, kSurveyCross>(c, grid, a, b, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, u.cell, u.tile,
+    launch_pairs<true, kSurveyCross>(c, grid, a, b, g.nc, g.L, r0 * r0, prefilter_bound(g, r0), r_split * r_split, 0, scale, u.cell, u.tile,
                                      u0, (int64_t *)nullptr, (int64_t *)nullptr, (unsigned long long *)nullptr,
                                      off_a, off_b, base_a, base_b, n_a, out.r, mu, ww);
   else
-    launch_pairs<true, kSurveySelf>(c, grid, a, a, g.nc, g.L, r0 * r0, r_split * r_split, 0, scale, u.cell, u.tile,
+    launch_pairs<true, kSurveySelf>(c, grid, a, a, g.nc, g.L, r0 * r0, prefilter_bound(g, r0), r_split * r_split, 0, scale, u.cell, u.tile,
                                     u0, (int64_t *)nullptr, (int64_t *)nullptr, (unsigned long long *)nullptr, off_a,
                                     off_b, base_a, base_b, n_a, out.r, mu, ww);
 }
