@@ -75,6 +75,17 @@ def lib():
         L.oracle_bk_ell_analytic.argtypes = [ct.c_int64, _dp, _dp, ct.c_double, ct.c_double, ct.c_int, _dp,
                                              ct.c_int, ct.c_int, _dp, _u8p, _dp, _dp, _dp, _dp, _dp, _dp,
                                              _dp, _u64p, _u64p, ct.c_int]
+        L.oracle_sph_jl.restype = ct.c_double
+        L.oracle_sph_jl.argtypes = [ct.c_int, ct.c_double]
+        L.oracle_wigner3j_000.restype = ct.c_double
+        L.oracle_wigner3j_000.argtypes = [ct.c_int, ct.c_int, ct.c_int]
+        L.oracle_omega.restype = ct.c_int
+        L.oracle_omega.argtypes = [ct.c_double, ct.c_double, ct.c_int, ct.c_int, _dp, _dp]
+        L.oracle_pk_window_theory.restype = ct.c_int
+        L.oracle_pk_window_theory.argtypes = [ct.c_double, ct.c_int, _dp, ct.c_int, ct.c_int, _dp, _dp, _dp, _dp]
+        L.oracle_cov_gauss.restype = ct.c_int
+        L.oracle_cov_gauss.argtypes = [ct.c_double, ct.c_double, ct.c_int, _dp, ct.c_int, ct.c_int, _dp, _dp, _dp,
+                                       _dp, ct.c_int]
         _lib = L
     return _lib
 
@@ -276,4 +287,49 @@ def bk_ell_analytic(pos, w, box, r0, k_edges, ell_max, n_x, table=None, mask_d=N
     if rc != 0:
         raise ValueError("oracle_bk_ell_analytic: argument outside the oracle's range")
     out.update(s0=s0, wtilde=wt, n_pairs_dd=int(ndd.value), n_pairs_2r0=int(n2.value), table=tab)
+    return out
+
+
+def sph_jl(ell, x):
+    return lib().oracle_sph_jl(int(ell), float(x))
+
+
+def wigner3j_000(l1, l2, l3):
+    return lib().oracle_wigner3j_000(int(l1), int(l2), int(l3))
+
+
+def omega(p, r0, ell, k_edges):
+    """omega^a_ell(p; R0) for all bins, [n_k]."""
+    k = _f64(k_edges)
+    out = np.zeros(k.size - 1)
+    if lib().oracle_omega(float(p), float(r0), int(ell), k.size - 1, _ptr(k), _ptr(out)) != 0:
+        raise ValueError("oracle_omega: argument outside the oracle's range")
+    return out
+
+
+def pk_window_theory(r0, k_edges, ell_max, r, wr, xi):
+    """Windowed P^a_ell(R0) of model multipoles xi [ell_max/2+1, n_r] on the
+    quadrature (r, wr): [ell_max/2+1, n_k]."""
+    k = _f64(k_edges)
+    r, wr = _f64(r), _f64(wr)
+    xi = _f64(xi).reshape(ell_max // 2 + 1, r.size)
+    out = np.zeros((ell_max // 2 + 1, k.size - 1))
+    if lib().oracle_pk_window_theory(float(r0), k.size - 1, _ptr(k), int(ell_max), r.size, _ptr(r), _ptr(wr),
+                                     _ptr(xi), _ptr(out)) != 0:
+        raise ValueError("oracle_pk_window_theory: argument outside the oracle's range")
+    return out
+
+
+def cov_gauss(r0, volume, k_edges, ell_max, p, wp, pk, nthreads=0):
+    """Gaussian covariance of the binned windowed multipoles on the p
+    quadrature (p, wp) with model P_ell(p) [ell_max/2+1, n_p]:
+    [n_ell, n_k, n_ell, n_k]."""
+    k = _f64(k_edges)
+    p, wp = _f64(p), _f64(wp)
+    n_ell, n_k = ell_max // 2 + 1, k.size - 1
+    pk = _f64(pk).reshape(n_ell, p.size)
+    out = np.zeros((n_ell, n_k, n_ell, n_k))
+    if lib().oracle_cov_gauss(float(r0), float(volume), n_k, _ptr(k), int(ell_max), p.size, _ptr(p), _ptr(wp),
+                              _ptr(pk), _ptr(out), int(nthreads)) != 0:
+        raise ValueError("oracle_cov_gauss: argument outside the oracle's range")
     return out

@@ -33,7 +33,10 @@
  * (oracle_eii) is pinned against the 3-D definition integrated by scipy in
  * other coordinates, its exact volume integral and its x -> 0 limit; the pair
  * sum over its interpolated table (oracle_ddr2) against random primaries on a
- * fine lattice and against per-pair kernel values.
+ * fine lattice and against per-pair kernel values.  The theory side
+ * (oracle_omega, oracle_cov_gauss, oracle_pk_window_theory) is pinned against
+ * scipy quadrature, Parseval's relation with the E^II kernel at zero
+ * separation, and the Gaunt integral of Q by direct angular quadrature.
  */
 #include <complex.h>
 #include <math.h>
@@ -1002,4 +1005,145 @@ int oracle_bk_ell_analytic(int64_t n, const double *pos, const double *w, double
     if (n_pairs_2r0) *n_pairs_2r0 = c2;
     free(GD); free(CD); free(T); free(TL); free(S0); free(Wt);
     return rc;
+}
+
+/* ------------------------------------------------- theory side (Secs. 5, 6) */
+/* Spherical Bessel j_ell(x): the power series
+ *   j_l(x) = x^l / (2l+1)!! sum_s (-x^2/2)^s / (s! (2l+3)(2l+5)...(2l+2s+1))
+ * below x = 5, upward recurrence above (as oracle_sph_bessel_up). */
+double oracle_sph_jl(int ell, double x)
+{
+    if (x < U_SWITCH) {
+        double t = pow(x, ell) / dfact_odd(ell), sum = 0.0;
+        for (int s = 0; s < 60; ++s) {
+            sum += t;
+            if (fabs(t) <= 1e-18 * fabs(sum) && s > 1) break;
+            t *= -0.5 * x * x / ((s + 1.0) * (2.0 * ell + 2.0 * s + 3.0));
+        }
+        return sum;
+    }
+    double j[ORACLE_ELL_MAX + 2];
+    oracle_sph_bessel_up(ell, x, j);
+    return j[ell];
+}
+
+/* Wigner 3j symbol (l1 l2 l3; 0 0 0) from its closed form: zero unless
+ * J = l1 + l2 + l3 is even and the triangle holds; else
+ *   (-1)^(J/2) sqrt((J-2l1)! (J-2l2)! (J-2l3)! / (J+1)!) (J/2)! / ((J/2-l1)! (J/2-l2)! (J/2-l3)!). */
+double oracle_wigner3j_000(int l1, int l2, int l3)
+{
+    int J = l1 + l2 + l3;
+    if (J & 1) return 0.0;
+    if (l3 > l1 + l2 || l3 < abs(l1 - l2)) return 0.0;
+    int g = J / 2;
+    double lf = lgamma(J - 2.0 * l1 + 1) + lgamma(J - 2.0 * l2 + 1) + lgamma(J - 2.0 * l3 + 1) - lgamma(J + 2.0);
+    double v = exp(0.5 * lf + lgamma(g + 1.0) - lgamma(g - l1 + 1.0) - lgamma(g - l2 + 1.0) - lgamma(g - l3 + 1.0));
+    return (g & 1) ? -v : v;
+}
+
+/* omega^a_l(p; R0) = 4 pi int_0^R0 r^2 j_l(p r) jbar^a_l(r) W(r/R0) dr for all
+ * bins (Sec. 6, eq. omega-ell-a-def), by composite 16-point Gauss-Legendre on
+ * the three smooth pieces of W, each cut into panels no wider than
+ * min(R0/8, (pi/2)/max(p, k_max)).  out [n_k]. */
+int oracle_omega(double p, double r0, int ell, int n_k, const double *k, double *out)
+{
+    if (!(r0 > 0.0) || !(p >= 0.0) || ell < 0 || ell > ORACLE_ELL_MAX || n_k < 1 || n_k > ORACLE_NK_MAX)
+        return -1;
+    double gx[EII_NG], gw[EII_NG];
+    gauss_legendre(EII_NG, gx, gw);
+    double kmax = k[n_k] > p ? k[n_k] : p;
+    double hmax = 0.125 * r0;
+    if (0.5 * PI / kmax < hmax) hmax = 0.5 * PI / kmax;
+    const int cap = EII_NG * ((int)ceil(r0 / hmax) + 4);
+    double *xs = malloc(sizeof(double) * cap), *ws = malloc(sizeof(double) * cap), *g = malloc(sizeof(double) * n_k);
+    const double joins[2] = {0.5 * r0, 0.75 * r0};
+    int n = eii_nodes(0.0, r0, joins, 2, hmax, gx, gw, xs, ws);
+    for (int a = 0; a < n_k; ++a) out[a] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double r = xs[i];
+        eii_g(ell, r, r0, n_k, k, g);
+        double f = ws[i] * r * r * oracle_sph_jl(ell, p * r);
+        for (int a = 0; a < n_k; ++a) out[a] += f * g[a];
+    }
+    for (int a = 0; a < n_k; ++a) out[a] *= 4.0 * PI;
+    free(xs); free(ws); free(g);
+    return 0;
+}
+
+/* Windowed power-spectrum multipoles of a model 2PCF (Sec. 5):
+ *   P^a_l(R0) = 4 pi (-i)^l int r^2 xi_l(r) W(r/R0) jbar^a_l(r) dr,
+ * for even l = 0, 2, .., ell_max, with the integral taken as the caller's
+ * quadrature sum over nodes r[m] with weights wr[m] (m < n_r):
+ *   P^a_l = 4 pi (-i)^l sum_m wr[m] r[m]^2 xi[l/2][m] W(r[m]/R0) jbar^a_l(r[m]).
+ * xi [ell_max/2+1][n_r]; out [ell_max/2+1][n_k]. */
+int oracle_pk_window_theory(double r0, int n_k, const double *k, int ell_max, int n_r, const double *r,
+                            const double *wr, const double *xi, double *out)
+{
+    if (!(r0 > 0.0) || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 || ell_max > ORACLE_ELL_MAX || (ell_max & 1) ||
+        n_r < 1)
+        return -1;
+    const int n_ell = ell_max / 2 + 1;
+    double g[ORACLE_NK_MAX];
+    for (int li = 0; li < n_ell; ++li) {
+        const int ell = 2 * li;
+        const double phase = (li & 1) ? -1.0 : 1.0; /* (-i)^l for even l */
+        for (int a = 0; a < n_k; ++a) out[li * n_k + a] = 0.0;
+        for (int m = 0; m < n_r; ++m) {
+            eii_g(ell, r[m], r0, n_k, k, g);
+            const double f = wr[m] * r[m] * r[m] * xi[(size_t)li * n_r + m];
+            for (int a = 0; a < n_k; ++a) out[li * n_k + a] += f * g[a];
+        }
+        for (int a = 0; a < n_k; ++a) out[li * n_k + a] *= 4.0 * PI * phase;
+    }
+    return 0;
+}
+
+/* Gaussian intrinsic covariance of the binned multipoles (Sec. 6, eq.
+ * cov-int, for even l, l' <= ell_max):
+ *   C^ab_ll' = 2 (2l+1)(2l'+1)/V int p^2 dp/(2 pi^2) omega^a_l(p) omega^b_l'(p) Q_ll'(p),
+ *   Q_ll'(p) = sum_{L, l1, l2} (2L+1) (l l' L; 0 0 0)^2 (l1 l2 L; 0 0 0)^2 P_l1(p) P_l2(p),
+ * with the p integral the caller's quadrature sum over nodes p[i], weights
+ * wp[i] (i < n_p), and pk [n_ell][n_p] the model multipoles P_l1(p[i]) for
+ * even l1 = 0 .. ell_max (higher multipoles of P taken as zero).
+ * out [n_ell][n_k][n_ell][n_k]: entry ((l n_k + a) n_ell + l') n_k + b. */
+int oracle_cov_gauss(double r0, double volume, int n_k, const double *k, int ell_max, int n_p, const double *p,
+                     const double *wp, const double *pk, double *out, int nthreads)
+{
+    if (!(r0 > 0.0) || !(volume > 0.0) || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 ||
+        ell_max > ORACLE_ELL_MAX || (ell_max & 1) || n_p < 1)
+        return -1;
+    const int n_ell = ell_max / 2 + 1, nt = nthreads_or_default(nthreads);
+    const size_t nout = (size_t)n_ell * n_k * n_ell * n_k;
+    /* omega^a_l at every node */
+    double *om = malloc(sizeof(double) * (size_t)n_p * n_ell * n_k);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+    for (int i = 0; i < n_p; ++i)
+        for (int li = 0; li < n_ell; ++li) oracle_omega(p[i], r0, 2 * li, n_k, k, om + ((size_t)i * n_ell + li) * n_k);
+    for (size_t q = 0; q < nout; ++q) out[q] = 0.0;
+    for (int i = 0; i < n_p; ++i) {
+        for (int li = 0; li < n_ell; ++li)
+            for (int lj = 0; lj < n_ell; ++lj) {
+                const int l = 2 * li, lp = 2 * lj;
+                double Q = 0.0;
+                for (int L = 0; L <= 2 * ORACLE_ELL_MAX; L += 2) {
+                    double t1 = oracle_wigner3j_000(l, lp, L);
+                    if (t1 == 0.0) continue;
+                    double s = 0.0;
+                    for (int m1 = 0; m1 < n_ell; ++m1)
+                        for (int m2 = 0; m2 < n_ell; ++m2) {
+                            double t2 = oracle_wigner3j_000(2 * m1, 2 * m2, L);
+                            s += t2 * t2 * pk[(size_t)m1 * n_p + i] * pk[(size_t)m2 * n_p + i];
+                        }
+                    Q += (2.0 * L + 1.0) * t1 * t1 * s;
+                }
+                const double f = 2.0 * (2.0 * l + 1.0) * (2.0 * lp + 1.0) / volume * wp[i] * p[i] * p[i] /
+                                 (2.0 * PI * PI) * Q;
+                for (int a = 0; a < n_k; ++a)
+                    for (int b = 0; b < n_k; ++b)
+                        out[(((size_t)li * n_k + a) * n_ell + lj) * n_k + b] +=
+                            f * om[((size_t)i * n_ell + li) * n_k + a] * om[((size_t)i * n_ell + lj) * n_k + b];
+            }
+    }
+    free(om);
+    return 0;
 }

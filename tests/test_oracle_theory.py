@@ -1,0 +1,107 @@
+"""Pins for the oracle's theory side (Secs. 5 and 6): the spherical Bessel
+function and Wigner 3j symbols against scipy and sympy; omega^a_l(p; R0)
+against scipy's adaptive quadrature of its definition, its p -> 0 limit
+(W~^a for l = 0) and Parseval's relation with the analytic-DDR^II kernel at
+zero separation, int p^2 dp/(2 pi^2) omega^a omega^b = E^{II,ab}(0)
+(Appendix A); the Gaussian covariance through that relation for a constant
+power spectrum and through Q_ll' as a direct angular integral; the windowed
+theory power spectrum against an independent evaluation."""
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import eval_legendre, spherical_jn
+from sympy.physics.wigner import wigner_3j
+
+import oracle
+
+R0 = 20.0
+K = np.linspace(0.1, 0.5, 4)
+
+
+def test_spherical_bessel_and_wigner3j():
+    for ell in range(7):
+        for x in (1e-6, 0.1, 1.0, 3.0, 4.99, 5.0, 7.3, 20.0):
+            ref = spherical_jn(ell, x)
+            assert abs(oracle.sph_jl(ell, x) - ref) <= 1e-13 * max(abs(ref), 1e-300)
+    for a in range(0, 8):
+        for b in range(0, 8):
+            for c in range(0, 15):
+                assert abs(oracle.wigner3j_000(a, b, c) - float(wigner_3j(a, b, c, 0, 0, 0))) < 1e-14
+
+
+@pytest.mark.parametrize("p,ell", [(0.05, 0), (0.33, 2), (0.9, 4), (2.5, 2)])
+def test_omega_matches_adaptive_quadrature(p, ell):
+    got = oracle.omega(p, R0, ell, K)
+    for a in range(3):
+        f = lambda r: r * r * spherical_jn(ell, p * r) * oracle.jbar(ell, r, K[a], K[a + 1]) * oracle.window(r / R0)
+        ref = 4 * np.pi * integrate.quad(f, 0.0, R0, points=[0.5 * R0, 0.75 * R0], epsabs=0, epsrel=1e-12,
+                                         limit=400)[0]
+        assert abs(got[a] - ref) <= 1e-10 * np.abs(got).max()
+
+
+def test_omega_at_zero_momentum():
+    wt = np.array([oracle.wtilde(R0, K[a], K[a + 1]) for a in range(3)])
+    assert np.allclose(oracle.omega(0.0, R0, 0, K), wt, rtol=1e-11, atol=0)
+    for ell in (2, 4):
+        assert np.all(oracle.omega(0.0, R0, ell, K) == 0.0)
+
+
+def _p_quadrature(pmax, panels=150, n=16):
+    gx, gw = np.polynomial.legendre.leggauss(n)
+    e = np.linspace(0.0, pmax, panels + 1)
+    mid, half = 0.5 * (e[:-1] + e[1:]), 0.5 * (e[1:] - e[:-1])
+    return (mid[:, None] + half[:, None] * gx).ravel(), (half[:, None] * gw).ravel()
+
+
+@pytest.mark.parametrize("ell", [0, 2])
+def test_parseval_with_eii_at_zero(ell):
+    # int_0^inf p^2 dp/(2 pi^2) omega^a omega^b = 4 pi int r^2 g^a g^b dr = E^{II,ab}(0)
+    p, w = _p_quadrature(12.0)
+    om = np.array([oracle.omega(pi, R0, ell, K) for pi in p])
+    lhs = np.einsum("i,ia,ib->ab", w * p * p / (2 * np.pi ** 2), om, om)
+    ref = oracle.eii(0.0, R0, ell, K)
+    assert np.abs(lhs - ref).max() <= 1e-7 * np.abs(ref).max()
+
+
+def test_covariance_constant_power_and_Q():
+    V, ell_max = 1e6, 4
+    # constant monopole P0, no higher multipoles: C = 2 (2l+1) P0^2 / V delta_ll' E^{II,ab}_l(0)
+    p, w = _p_quadrature(12.0)
+    P0 = 250.0
+    pk = np.zeros((3, p.size))
+    pk[0] = P0
+    C = oracle.cov_gauss(R0, V, K, ell_max, p, w, pk)
+    for li in range(3):
+        ref = 2 * (4 * li + 1) * P0 ** 2 / V * oracle.eii(0.0, R0, 2 * li, K)
+        assert np.abs(C[li, :, li, :] - ref).max() <= 1e-7 * np.abs(ref).max()
+        for lj in range(3):
+            if lj != li:
+                assert np.abs(C[li, :, lj, :]).max() <= 1e-9 * np.abs(ref).max()
+    # one p node: Q_ll'(p) = (1/2) int dmu L_l L_l' (sum_l1 P_l1 L_l1)^2
+    pk1 = np.array([[300.0], [-80.0], [25.0]])
+    p1 = 0.37
+    C1 = oracle.cov_gauss(R0, V, K, ell_max, [p1], [1.0], pk1)
+    om = [oracle.omega(p1, R0, 2 * li, K) for li in range(3)]
+    mu, wmu = np.polynomial.legendre.leggauss(24)
+    Pmu = sum(pk1[m, 0] * eval_legendre(2 * m, mu) for m in range(3))
+    for li in range(3):
+        for lj in range(3):
+            Q = 0.5 * np.sum(wmu * eval_legendre(2 * li, mu) * eval_legendre(2 * lj, mu) * Pmu ** 2)
+            ref = 2 * (4 * li + 1) * (4 * lj + 1) / V * p1 ** 2 / (2 * np.pi ** 2) * Q * np.outer(om[li], om[lj])
+            assert np.allclose(C1[li, :, lj, :], ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+
+
+def test_window_theory_independent_sum():
+    # P^a_l = 4 pi (-i)^l sum_m w_m r_m^2 xi_l(r_m) W(r_m/R0) jbar^a_l(r_m), with
+    # jbar and W from the pinned special functions, in plain numpy
+    gx, gw = np.polynomial.legendre.leggauss(40)
+    r, wr = 0.5 * R0 * (gx + 1), 0.5 * R0 * gw
+    xi = np.array([5.0 * np.exp(-r / 7.0), -1.0 * np.exp(-r / 5.0) * r / 10.0, 0.1 * np.exp(-r / 9.0)])
+    got = oracle.pk_window_theory(R0, K, 4, r, wr, xi)
+    for li in range(3):
+        ell = 2 * li
+        for a in range(3):
+            s = sum(wr[m] * r[m] ** 2 * xi[li, m] * oracle.window(r[m] / R0) * oracle.jbar(ell, r[m], K[a], K[a + 1])
+                    for m in range(r.size))
+            ref = 4 * np.pi * (-1) ** li * s
+            assert abs(got[li, a] - ref) <= 1e-12 * abs(ref)
