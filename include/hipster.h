@@ -184,6 +184,41 @@ hipster_status hipster_bk_ell_analytic(hipster_ctx *ctx, const hipster_points *d
 hipster_status hipster_eii_table(hipster_ctx *ctx, double r0, int32_t n_k, const double *k_edges, int32_t ell_max,
                                  int32_t n_x, double *table);
 
+/* Theory side (Secs. 5, 6), double precision throughout.  r0, n_k, k_edges
+ * and ell_max as in hipster_params (n_k <= 128); all arrays are host memory
+ * owned by the caller; the integrals over r or p that the paper leaves to the
+ * user are the caller's quadrature (nodes and weights).  Errors:
+ * HIPSTER_EINVAL (NULL pointers, counts < 1), HIPSTER_EDOMAIN (R0 <= 0, bad
+ * edges, ell_max outside [0, 6] (or odd where even multipoles are meant),
+ * p < 0, r outside [0, R0], volume <= 0), HIPSTER_EUNSUPPORTED
+ * (max(p, k_max) R0 > 1e6). */
+
+/* omega^a_l(p; R0) = 4 pi int_0^R0 r^2 j_l(p r) jbar^a_l(r) W(r/R0) dr (Sec. 6,
+ * eq. omega-ell-a-def) at n_p momenta p, for l = 0..ell_max.
+ * out: [ell_max+1][n_p][n_k]. */
+hipster_status hipster_omega(hipster_ctx *ctx, double r0, int32_t n_k, const double *k_edges, int32_t ell_max,
+                             int32_t n_p, const double *p, double *out);
+
+/* Windowed power-spectrum multipoles of a model 2PCF (Sec. 5):
+ *   P^a_l(R0) = 4 pi (-i)^l int r^2 xi_l(r) W(r/R0) jbar^a_l(r) dr, l = 0, 2, .., ell_max,
+ * as the sum over the caller's quadrature nodes r[m] in [0, R0] with weights
+ * wr[m]: xi [ell_max/2+1][n_r] holds xi_l(r[m]).  out: [ell_max/2+1][n_k]. */
+hipster_status hipster_pk_window_theory(hipster_ctx *ctx, double r0, int32_t n_k, const double *k_edges,
+                                        int32_t ell_max, int32_t n_r, const double *r, const double *wr,
+                                        const double *xi, double *out);
+
+/* Gaussian intrinsic covariance of the binned windowed multipoles (Sec. 6, eq.
+ * cov-int), even l, l' <= ell_max:
+ *   C^ab_ll' = 2 (2l+1)(2l'+1)/V int p^2 dp/(2 pi^2) omega^a_l(p) omega^b_l'(p) Q_ll'(p),
+ *   Q_ll'(p) = sum_{L,l1,l2} (2L+1) (l l' L;0 0 0)^2 (l1 l2 L;0 0 0)^2 P_l1(p) P_l2(p),
+ * with the p integral the sum over the caller's nodes p[i], weights wp[i];
+ * pk [ell_max/2+1][n_p] holds the model multipoles P_l1(p[i]) (higher ones
+ * taken as zero); volume V.  out: [ell_max/2+1][n_k][ell_max/2+1][n_k], entry
+ * ((l/2 n_k + a)(ell_max/2+1) + l'/2) n_k + b. */
+hipster_status hipster_cov_gauss(hipster_ctx *ctx, double r0, double volume, int32_t n_k, const double *k_edges,
+                                 int32_t ell_max, int32_t n_p, const double *p, const double *wp, const double *pk,
+                                 double *out);
+
 /* Parameters of the survey-geometry power spectrum (hipster_pk_survey).
  * volume: V of the normalisation 1/(n_w^2 V), n_w = sum(w_data) / V (the
  * paper normalises by the ideal n^2 V, Sec. 2).  r0, n_k, ell_max, k_edges,

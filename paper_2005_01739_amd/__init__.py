@@ -18,7 +18,8 @@ from typing import Any
 import numpy as np
 
 __all__ = ["Context", "wtilde", "pk_ell", "bk_ell", "batch", "HipsterError", "library_path", "load_library",
-           "EXPORTED_SYMBOLS", "MIXED", "FP64", "pk_survey", "bk_ell_analytic", "eii_table"]
+           "EXPORTED_SYMBOLS", "MIXED", "FP64", "pk_survey", "bk_ell_analytic", "eii_table",
+           "omega", "pk_window_theory", "cov_gauss"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 MIXED, FP64 = 0, 1
@@ -27,7 +28,8 @@ _F32, _F64 = 0, 1
 EXPORTED_SYMBOLS = ("hipster_create", "hipster_destroy", "hipster_pk_ell", "hipster_bk_ell",
                     "hipster_batch", "hipster_last_error", "hipster_status_string",
                     "hipster_set_memory_cap", "hipster_wtilde", "hipster_pk_survey",
-                    "hipster_bk_ell_analytic", "hipster_eii_table")
+                    "hipster_bk_ell_analytic", "hipster_eii_table", "hipster_omega",
+                    "hipster_pk_window_theory", "hipster_cov_gauss")
 
 
 class HipsterError(RuntimeError):
@@ -107,6 +109,14 @@ def load_library():
                                           ct.POINTER(_Diag)]
     L.hipster_eii_table.restype = ct.c_int
     L.hipster_eii_table.argtypes = [ct.c_void_p, ct.c_double, ct.c_int32, _dp, ct.c_int32, ct.c_int32, _dp]
+    L.hipster_omega.restype = ct.c_int
+    L.hipster_omega.argtypes = [ct.c_void_p, ct.c_double, ct.c_int32, _dp, ct.c_int32, ct.c_int32, _dp, _dp]
+    L.hipster_pk_window_theory.restype = ct.c_int
+    L.hipster_pk_window_theory.argtypes = [ct.c_void_p, ct.c_double, ct.c_int32, _dp, ct.c_int32, ct.c_int32, _dp,
+                                           _dp, _dp, _dp]
+    L.hipster_cov_gauss.restype = ct.c_int
+    L.hipster_cov_gauss.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, ct.c_int32, _dp, ct.c_int32, ct.c_int32,
+                                    _dp, _dp, _dp, _dp]
     L.hipster_batch.restype = ct.c_int
     L.hipster_batch.argtypes = [ct.c_void_p, ct.c_int, ct.POINTER(_BoxJob), ct.POINTER(_Diag)]
     L.hipster_last_error.restype = ct.c_char_p
@@ -384,6 +394,49 @@ def eii_table(r0: float, k_edges, ell_max: int, n_x: int, *, ctx: Context | None
     out = np.zeros((ell_max + 1, n_k, n_k, n_x + 1))
     c = ctx or _context_for(None)
     c.check(L.hipster_eii_table(c.handle, float(r0), n_k, _ptr(k), int(ell_max), int(n_x), _ptr(out)))
+    return out
+
+
+def _host_f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def omega(p, r0: float, k_edges, ell_max: int, *, ctx: Context | None = None) -> np.ndarray:
+    """omega^a_ell(p; R0) for ell = 0..ell_max at the momenta p, computed on the
+    GPU: float64 array (ell_max + 1, len(p), n_k)."""
+    L = load_library()
+    k, p = _host_f64(k_edges), _host_f64(p)
+    out = np.zeros((ell_max + 1, p.size, k.size - 1))
+    c = ctx or _context_for(None)
+    c.check(L.hipster_omega(c.handle, float(r0), k.size - 1, _ptr(k), int(ell_max), p.size, _ptr(p), _ptr(out)))
+    return out
+
+
+def pk_window_theory(r0: float, k_edges, ell_max: int, r, wr, xi, *, ctx: Context | None = None) -> np.ndarray:
+    """Windowed P^a_ell(R0) (even ell) of model multipoles xi (ell_max/2 + 1, len(r))
+    on the quadrature (r, wr) over [0, R0]: (ell_max/2 + 1, n_k)."""
+    L = load_library()
+    k, r, wr = _host_f64(k_edges), _host_f64(r), _host_f64(wr)
+    xi = _host_f64(xi).reshape(ell_max // 2 + 1, r.size)
+    out = np.zeros((ell_max // 2 + 1, k.size - 1))
+    c = ctx or _context_for(None)
+    c.check(L.hipster_pk_window_theory(c.handle, float(r0), k.size - 1, _ptr(k), int(ell_max), r.size, _ptr(r),
+                                       _ptr(wr), _ptr(xi), _ptr(out)))
+    return out
+
+
+def cov_gauss(r0: float, volume: float, k_edges, ell_max: int, p, wp, pk, *, ctx: Context | None = None) -> np.ndarray:
+    """Gaussian covariance of the binned windowed multipoles (even ell) on the p
+    quadrature (p, wp) with model multipoles pk (ell_max/2 + 1, len(p)):
+    (n_ell, n_k, n_ell, n_k)."""
+    L = load_library()
+    k, p, wp = _host_f64(k_edges), _host_f64(p), _host_f64(wp)
+    n_ell, n_k = ell_max // 2 + 1, k.size - 1
+    pk = _host_f64(pk).reshape(n_ell, p.size)
+    out = np.zeros((n_ell, n_k, n_ell, n_k))
+    c = ctx or _context_for(None)
+    c.check(L.hipster_cov_gauss(c.handle, float(r0), float(volume), n_k, _ptr(k), int(ell_max), p.size, _ptr(p),
+                                _ptr(wp), _ptr(pk), _ptr(out)))
     return out
 
 

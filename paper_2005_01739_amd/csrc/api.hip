@@ -662,6 +662,27 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   }
 }
 
+// Arguments of the theory-side calls: R0 > 0, n_k in [1, 128], strictly
+// increasing non-negative edges, ell_max in [0, 6] (even when `even`).
+static void check_theory(double r0, int n_k, const double *k_edges, int ell_max, bool even) {
+  if (!k_edges) throw Error{HIPSTER_EINVAL, "NULL k_edges"};
+  if (!(r0 > 0.0) || !isfinite(r0)) throw Error{HIPSTER_EDOMAIN, "R0 must be finite and positive"};
+  if (n_k < 1 || n_k > kMaxNk) throw Error{HIPSTER_EUNSUPPORTED, "n_k must lie in [1, 128]"};
+  for (int a = 0; a <= n_k; ++a) {
+    if (!isfinite(k_edges[a]) || k_edges[a] < 0.0) throw Error{HIPSTER_EDOMAIN, "k edges must be finite and >= 0"};
+    if (a > 0 && !(k_edges[a] > k_edges[a - 1])) throw Error{HIPSTER_EDOMAIN, "k edges must increase strictly"};
+  }
+  if (ell_max < 0 || ell_max > kLMaxApi || (even && (ell_max & 1)))
+    throw Error{HIPSTER_EDOMAIN, even ? "ell_max must be even, <= 6" : "ell_max must lie in [0, 6]"};
+}
+
+// The table sine and cosine reduce exactly only below ~1.6e6: max(p, k) R0.
+static void theory_phase_check(double r0, int n_k, const double *k_edges, int n_p, const double *p) {
+  double m = k_edges[n_k];
+  for (int i = 0; i < n_p; ++i) m = std::max(m, p[i]);
+  if (m * r0 > kMaxPhaseMixed) throw Error{HIPSTER_EUNSUPPORTED, "theory: max(p, k_max) * R0 must be <= 1e6"};
+}
+
 // E^{II,ab}_l on the nodes m 2 R0 / n_x, copied to the host.
 static void run_eii_table(Ctx &c, double r0, int32_t n_k, const double *k_edges, int32_t ell_max, int32_t n_x,
                           double *out) {
@@ -972,7 +993,8 @@ void hipster_destroy(hipster_ctx *ctx) {
                    &c.partial, &c.merged, &c.ordered_count, &c.bbox, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out,
                    &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile, &c.eii_consts, &c.eii_tab,
                    &c.ddr2_partial, &c.ddr2_hist, &c.ddr2_counter, &c.ddr2_T, &c.ct_tab, &c.ct_consts, &c.ct_C,
-                   &c.ct_wmax};
+                   &c.ct_wmax, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
+                   &c.th_K, &c.th_out};
   for (DevBuf *b : all) free_buf(*b);
   delete ctx;
 }
@@ -1001,6 +1023,66 @@ hipster_status hipster_bk_ell_analytic(hipster_ctx *ctx, const hipster_points *d
 hipster_status hipster_eii_table(hipster_ctx *ctx, double r0, int32_t n_k, const double *k_edges, int32_t ell_max,
                                  int32_t n_x, double *table) {
   return guarded(ctx, [&] { run_eii_table(ctx->c, r0, n_k, k_edges, ell_max, n_x, table); });
+}
+
+hipster_status hipster_omega(hipster_ctx *ctx, double r0, int32_t n_k, const double *k_edges, int32_t ell_max,
+                             int32_t n_p, const double *p, double *out) {
+  return guarded(ctx, [&] {
+    Ctx &c = ctx->c;
+    check_theory(r0, n_k, k_edges, ell_max, false);
+    if (!p || !out) throw Error{HIPSTER_EINVAL, "NULL argument"};
+    if (n_p < 1) throw Error{HIPSTER_EINVAL, "n_p must be >= 1"};
+    for (int i = 0; i < n_p; ++i)
+      if (!(p[i] >= 0.0) || !isfinite(p[i])) throw Error{HIPSTER_EDOMAIN, "p must be finite and >= 0"};
+    theory_phase_check(r0, n_k, k_edges, n_p, p);
+    HIPSTER_HIP(hipSetDevice(c.device));
+    const int n_l = ell_max + 1;
+    double *om = static_cast<double *>(ensure(c, c.th_om, size_t(n_l) * n_p * n_k * 8));
+    theory_omega(c, r0, n_k, k_edges, n_l, 1, n_p, p, om);
+    HIPSTER_HIP(hipMemcpyAsync(out, om, size_t(n_l) * n_p * n_k * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+hipster_status hipster_pk_window_theory(hipster_ctx *ctx, double r0, int32_t n_k, const double *k_edges,
+                                        int32_t ell_max, int32_t n_r, const double *r, const double *wr,
+                                        const double *xi, double *out) {
+  return guarded(ctx, [&] {
+    Ctx &c = ctx->c;
+    check_theory(r0, n_k, k_edges, ell_max, true);
+    if (!r || !wr || !xi || !out) throw Error{HIPSTER_EINVAL, "NULL argument"};
+    if (n_r < 1) throw Error{HIPSTER_EINVAL, "n_r must be >= 1"};
+    for (int m = 0; m < n_r; ++m)
+      if (!(r[m] >= 0.0) || !(r[m] <= r0)) throw Error{HIPSTER_EDOMAIN, "r nodes must lie in [0, R0]"};
+    HIPSTER_HIP(hipSetDevice(c.device));
+    const int n_l = ell_max / 2 + 1;
+    double *od = static_cast<double *>(ensure(c, c.th_out, size_t(n_l) * n_k * 8));
+    theory_pk(c, r0, n_k, k_edges, n_l, n_r, r, wr, xi, od);
+    HIPSTER_HIP(hipMemcpyAsync(out, od, size_t(n_l) * n_k * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+hipster_status hipster_cov_gauss(hipster_ctx *ctx, double r0, double volume, int32_t n_k, const double *k_edges,
+                                 int32_t ell_max, int32_t n_p, const double *p, const double *wp, const double *pk,
+                                 double *out) {
+  return guarded(ctx, [&] {
+    Ctx &c = ctx->c;
+    check_theory(r0, n_k, k_edges, ell_max, true);
+    if (!p || !wp || !pk || !out) throw Error{HIPSTER_EINVAL, "NULL argument"};
+    if (n_p < 1) throw Error{HIPSTER_EINVAL, "n_p must be >= 1"};
+    if (!(volume > 0.0) || !isfinite(volume)) throw Error{HIPSTER_EDOMAIN, "volume must be finite and positive"};
+    for (int i = 0; i < n_p; ++i)
+      if (!(p[i] >= 0.0) || !isfinite(p[i])) throw Error{HIPSTER_EDOMAIN, "p must be finite and >= 0"};
+    theory_phase_check(r0, n_k, k_edges, n_p, p);
+    HIPSTER_HIP(hipSetDevice(c.device));
+    const int n_l = ell_max / 2 + 1;
+    const size_t nout = size_t(n_l) * n_k * n_l * n_k;
+    double *od = static_cast<double *>(ensure(c, c.th_out, nout * 8));
+    theory_cov(c, r0, volume, n_k, k_edges, n_l, n_p, p, wp, pk, od);
+    HIPSTER_HIP(hipMemcpyAsync(out, od, nout * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  });
 }
 
 hipster_status hipster_batch(hipster_ctx *ctx, int n_boxes, hipster_box_job *jobs, hipster_diag *diag) {

@@ -114,6 +114,7 @@ struct Ctx {
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
   DevBuf eii_consts, eii_tab, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T, ct_tab, ct_consts, ct_C, ct_wmax;
+  DevBuf th_r, th_w, th_p, th_wp, th_pk, th_ek, th_g, th_J, th_om, th_K, th_out;
   // The E^II table on the device and the (R0, n_x, ell_max, edges) it holds.
   std::vector<double> eii_key;
   // W~^a depends only on (R0, k_a, k_{a+1}); repeated calls reuse it.
@@ -211,6 +212,18 @@ int cterm_default_nodes(double r0, double k_max);
 void cterm_sweep(Ctx &c, const Sorted &s, const Sorted &b, bool cross, const Grid &g, double r0, int n_k,
                  const double *k_edges, int ell_max, int n_c, uint64_t n_ordered, double *C,
                  unsigned long long *ordered);
+
+// Theory side (Secs. 5, 6), double precision throughout.  theory_omega:
+// om_dev[l][i][a] = omega^a_{l l_step}(p_i) for n_l multipoles; theory_pk:
+// windowed P^a_l of model multipoles xi[l/2][m] on the caller's r quadrature;
+// theory_cov: Gaussian covariance [n_l][n_k][n_l][n_k] of even multipoles on
+// the caller's p quadrature with model multipoles pk[l/2][i].  Host inputs.
+void theory_omega(Ctx &c, double r0, int n_k, const double *k_edges, int n_l, int l_step, int n_p, const double *p,
+                  double *om_dev);
+void theory_pk(Ctx &c, double r0, int n_k, const double *k_edges, int n_l, int n_r, const double *r, const double *wr,
+               const double *xi, double *out_dev);
+void theory_cov(Ctx &c, double r0, double volume, int n_k, const double *k_edges, int n_l, int n_p, const double *p,
+                const double *wp, const double *pk, double *out_dev);
 
 // Host analytic terms.
 double wtilde_bin(double r0, double k1, double k2);

@@ -783,3 +783,249 @@ void cterm_sweep(Ctx &c, const Sorted &s, const Sorted &b, bool cross, const Gri
 }
 
 }  // namespace hipster
+
+namespace hipster {
+
+// ------------------------------------------------------------ theory side
+// The transforms behind the windowed theory and the covariance of the binned
+// multipoles (Secs. 5, 6):
+//   omega^a_l(p) = 4 pi int_0^R0 r^2 j_l(p r) jbar^a_l(r) W(r/R0) dr,
+// on one node set for all requested p: the three smooth pieces of W cut into
+// 16-point Gauss-Legendre panels no wider than min(R0/4, 8/max(p_max, k_max))
+// (the integrand oscillates at up to p + k, so a panel spans at most 16
+// radians).  Tables g[l][m][a] = jbar^a_l(r_m) W(r_m/R0) and
+// J[l][i][m] = w_m r_m^2 j_l(p_i r_m), then fixed-order sums.
+
+// Spherical Bessel j_l(x), double precision: the power series
+// x^l/(2l+1)!! sum_s (-x^2/2)^s/(s! (2l+3)..(2l+2s+1)) below x = l + 4 (at
+// most ~3 digits of cancellation), else j_0 = sin x/x, j_1 = sin x/x^2 -
+// cos x/x and the upward recurrence, stable for x > l.
+__device__ inline double sph_jl(int l, double x, const double2 *__restrict__ tab) {
+  if (x < double(l) + 4.0) {
+    double t = 1.0;
+    for (int q = 1; q <= l; ++q) t *= x / double(2 * q + 1);
+    double sum = 0.0;
+    const double h = -0.5 * x * x;
+    for (int s = 0; s < 40; ++s) {
+      sum += t;
+      t *= h / (double(s + 1) * double(2 * l + 2 * s + 3));
+    }
+    return sum;
+  }
+  double sn, cs;
+  sincos_tab<kSinCosTab, true>(x, tab, sn, cs);
+  const double w = 1.0 / x;
+  double j0 = sn * w, j1 = (sn * w - cs) * w;
+  if (l == 0) return j0;
+  for (int n = 1; n < l; ++n) {
+    const double j2 = double(2 * n + 1) * w * j1 - j0;
+    j0 = j1;
+    j1 = j2;
+  }
+  return j1;
+}
+
+// jbar^a_l(r) from the edge values G_l(k r): 3 (k_{a+1}^3 G(k_{a+1} r) -
+// k_a^3 G(k_a r)) / (k_{a+1}^3 - k_a^3).  ek: (k, k^3) per edge.
+__device__ inline double jbar_one(int l, int a, double r, const double *__restrict__ ek,
+                                  const double2 *__restrict__ tab) {
+  const double ka = ek[2 * a], ka3 = ek[2 * a + 1], kb = ek[2 * a + 2], kb3 = ek[2 * a + 3];
+  return 3.0 * (kb3 * G_one(l, kb * r, tab) - ka3 * G_one(l, ka * r, tab)) / (kb3 - ka3);
+}
+
+// g[l][m][a] = jbar^a_l(r_m) W(r_m / R0), one thread per entry.
+__global__ __launch_bounds__(256) void k_theory_g(const double *__restrict__ r, int n_r, int n_k, int n_l,
+                                                  int l_step, double inv_r0, const double *__restrict__ ek,
+                                                  double *__restrict__ g) {
+  __shared__ double2 tab[kSinCosTab];
+  stage_sincos_tab<kSinCosTab>(tab);
+  __syncthreads();
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= int64_t(n_l) * n_r * n_k) return;
+  const int a = int(idx % n_k), m = int((idx / n_k) % n_r), li = int(idx / (int64_t(n_k) * n_r));
+  g[idx] = jbar_one(li * l_step, a, r[m], ek, tab) * window<double>(r[m] * inv_r0);
+}
+
+// J[l][i][m] = w_m r_m^2 j_l(p_i r_m), one thread per entry.
+__global__ __launch_bounds__(256) void k_theory_j(const double *__restrict__ r, const double *__restrict__ wr,
+                                                  int n_r, const double *__restrict__ p, int n_p, int n_l, int l_step,
+                                                  double *__restrict__ J) {
+  __shared__ double2 tab[kSinCosTab];
+  stage_sincos_tab<kSinCosTab>(tab);
+  __syncthreads();
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= int64_t(n_l) * n_p * n_r) return;
+  const int m = int(idx % n_r), i = int((idx / n_r) % n_p), li = int(idx / (int64_t(n_r) * n_p));
+  J[idx] = wr[m] * r[m] * r[m] * sph_jl(li * l_step, p[i] * r[m], tab);
+}
+
+// omega[l][i][a] = 4 pi sum_m J[l][i][m] g[l][m][a], one thread per entry, m
+// in order.
+__global__ __launch_bounds__(256) void k_theory_omega(const double *__restrict__ J, const double *__restrict__ g,
+                                                      int n_r, int n_p, int n_k, int n_l, double *__restrict__ om) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= int64_t(n_l) * n_p * n_k) return;
+  const int a = int(idx % n_k), i = int((idx / n_k) % n_p), li = int(idx / (int64_t(n_k) * n_p));
+  const double *Jr = J + (int64_t(li) * n_p + i) * n_r, *gr = g + int64_t(li) * n_r * n_k + a;
+  double s = 0.0;
+  for (int m = 0; m < n_r; ++m) s = fma(Jr[m], gr[int64_t(m) * n_k], s);
+  om[idx] = 4.0 * kPi * s;
+}
+
+// Windowed multipoles of a model 2PCF: out[l][a] = 4 pi (-i)^l sum_m wr_m
+// r_m^2 xi_l(r_m) g[l][m][a] (even l), one thread per entry.
+__global__ __launch_bounds__(256) void k_theory_pk(const double *__restrict__ r, const double *__restrict__ wr,
+                                                   const double *__restrict__ xi, const double *__restrict__ g,
+                                                   int n_r, int n_k, int n_l, double *__restrict__ out) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n_l * n_k) return;
+  const int a = idx % n_k, li = idx / n_k;
+  double s = 0.0;
+  for (int m = 0; m < n_r; ++m)
+    s = fma(wr[m] * r[m] * r[m] * xi[int64_t(li) * n_r + m], g[(int64_t(li) * n_r + m) * n_k + a], s);
+  out[idx] = 4.0 * kPi * ((li & 1) ? -1.0 : 1.0) * s;
+}
+
+// Gaussian covariance: out[(l a)(l' b)] = 2 (2l+1)(2l'+1)/V sum_i
+// wp_i p_i^2/(2 pi^2) Q_ll'(p_i) omega[l][i][a] omega[l'][i][b], with
+// Q_ll'(p) = sum_{l1 l2} K[l][l'][l1][l2] P_l1(p) P_l2(p); one thread per
+// entry, i in order.
+__global__ __launch_bounds__(256) void k_theory_cov(const double *__restrict__ om, const double *__restrict__ p,
+                                                    const double *__restrict__ wp, const double *__restrict__ pk,
+                                                    const double *__restrict__ K, int n_p, int n_k, int n_l,
+                                                    double inv_volume, double *__restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t nrow = int64_t(n_l) * n_k;
+  if (idx >= nrow * nrow) return;
+  const int b = int(idx % n_k), lj = int((idx / n_k) % n_l), a = int((idx / (int64_t(n_k) * n_l)) % n_k),
+            li = int(idx / (int64_t(n_k) * n_l * n_k));
+  const double *Kll = K + (li * n_l + lj) * n_l * n_l;
+  double s = 0.0;
+  for (int i = 0; i < n_p; ++i) {
+    double Q = 0.0;
+    for (int m1 = 0; m1 < n_l; ++m1) {
+      double t = 0.0;
+      for (int m2 = 0; m2 < n_l; ++m2) t = fma(Kll[m1 * n_l + m2], pk[int64_t(m2) * n_p + i], t);
+      Q = fma(t, pk[int64_t(m1) * n_p + i], Q);
+    }
+    const double f = wp[i] * p[i] * p[i] * (1.0 / (2.0 * kPi * kPi)) * Q;
+    s = fma(f * om[(int64_t(li) * n_p + i) * n_k + a], om[(int64_t(lj) * n_p + i) * n_k + b], s);
+  }
+  out[idx] = 2.0 * double(4 * li + 1) * double(4 * lj + 1) * inv_volume * s;
+}
+
+// The r node set: 16-point Gauss-Legendre panels on [0, R0/2], [R0/2, 3R0/4],
+// [3R0/4, R0], each no wider than hmax.
+static void theory_nodes(double r0, double hmax, std::vector<double> &r, std::vector<double> &w) {
+  const GLRule gl = gauss_legendre16();
+  const double cut[4] = {0.0, 0.5 * r0, 0.75 * r0, r0};
+  for (int s = 0; s < 3; ++s) {
+    const int np = std::max(1, int(ceil((cut[s + 1] - cut[s]) / hmax)));
+    const double ph = (cut[s + 1] - cut[s]) / np;
+    for (int q = 0; q < np; ++q)
+      for (int j = 0; j < kGL; ++j) {
+        r.push_back(cut[s] + (q + 0.5) * ph + 0.5 * ph * gl.x[j]);
+        w.push_back(0.5 * ph * gl.w[j]);
+      }
+  }
+}
+
+static double *upload(Ctx &c, DevBuf &b, const double *h, size_t n) {
+  double *d = static_cast<double *>(ensure(c, b, std::max<size_t>(n, 1) * 8));
+  if (n) HIPSTER_HIP(hipMemcpyAsync(d, h, n * 8, hipMemcpyHostToDevice, c.stream));
+  return d;
+}
+
+static double *edge_table(Ctx &c, int n_k, const double *k_edges) {
+  std::vector<double> ek(static_cast<size_t>(2 * (n_k + 1)));
+  for (int e = 0; e <= n_k; ++e) {
+    ek[size_t(2 * e)] = k_edges[e];
+    ek[size_t(2 * e + 1)] = k_edges[e] * k_edges[e] * k_edges[e];
+  }
+  return upload(c, c.th_ek, ek.data(), ek.size());
+}
+
+static unsigned blocks(int64_t n) { return unsigned((n + 255) / 256); }
+
+void theory_omega(Ctx &c, double r0, int n_k, const double *k_edges, int n_l, int l_step, int n_p, const double *p,
+                  double *om_dev) {
+  double pmax = 0.0;
+  for (int i = 0; i < n_p; ++i) pmax = std::max(pmax, p[i]);
+  std::vector<double> r, w;
+  theory_nodes(r0, std::min(0.25 * r0, 8.0 / std::max(pmax, k_edges[n_k])), r, w);
+  const int n_r = int(r.size());
+  const double *rd = upload(c, c.th_r, r.data(), r.size()), *wd = upload(c, c.th_w, w.data(), w.size());
+  const double *pd = upload(c, c.th_p, p, size_t(n_p));
+  const double *ek = edge_table(c, n_k, k_edges);
+  double *g = static_cast<double *>(ensure(c, c.th_g, size_t(n_l) * n_r * n_k * 8));
+  double *J = static_cast<double *>(ensure(c, c.th_J, size_t(n_l) * n_p * n_r * 8));
+  k_theory_g<<<blocks(int64_t(n_l) * n_r * n_k), 256, 0, c.stream>>>(rd, n_r, n_k, n_l, l_step, 1.0 / r0, ek, g);
+  HIPSTER_HIP(hipGetLastError());
+  k_theory_j<<<blocks(int64_t(n_l) * n_p * n_r), 256, 0, c.stream>>>(rd, wd, n_r, pd, n_p, n_l, l_step, J);
+  HIPSTER_HIP(hipGetLastError());
+  k_theory_omega<<<blocks(int64_t(n_l) * n_p * n_k), 256, 0, c.stream>>>(J, g, n_r, n_p, n_k, n_l, om_dev);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+void theory_pk(Ctx &c, double r0, int n_k, const double *k_edges, int n_l, int n_r, const double *r, const double *wr,
+               const double *xi, double *out_dev) {
+  const double *rd = upload(c, c.th_r, r, size_t(n_r)), *wd = upload(c, c.th_w, wr, size_t(n_r));
+  const double *xd = upload(c, c.th_p, xi, size_t(n_l) * n_r);
+  const double *ek = edge_table(c, n_k, k_edges);
+  double *g = static_cast<double *>(ensure(c, c.th_g, size_t(n_l) * n_r * n_k * 8));
+  k_theory_g<<<blocks(int64_t(n_l) * n_r * n_k), 256, 0, c.stream>>>(rd, n_r, n_k, n_l, 2, 1.0 / r0, ek, g);
+  HIPSTER_HIP(hipGetLastError());
+  k_theory_pk<<<blocks(int64_t(n_l) * n_k), 256, 0, c.stream>>>(rd, wd, xd, g, n_r, n_k, n_l, out_dev);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+// K[l][l'][l1][l2] = sum_L (2L+1) (l l' L; 0 0 0)^2 (l1 l2 L; 0 0 0)^2 for even
+// l, l', l1, l2 <= 2 (n_l - 1), from the Gaunt relation
+//   (1/2) int_{-1}^{1} L_a L_b L_c L_d dmu = sum_L (2L+1) (a b L;000)^2 (c d L;000)^2,
+// taken as a Gauss-Legendre sum (exact: the integrand has degree <= 24).
+static std::vector<double> gaunt_coefficients(int n_l) {
+  constexpr int kN = 16;
+  GLRule gl = gauss_legendre16();
+  (void)kN;
+  const int lmax = 2 * (n_l - 1);
+  std::vector<double> P(size_t((lmax + 1) * kGL));
+  for (int q = 0; q < kGL; ++q) {
+    const double mu = gl.x[q];
+    double p0 = 1.0, p1 = mu;
+    P[size_t(q)] = 1.0;
+    if (lmax >= 1) P[size_t(kGL + q)] = mu;
+    for (int n = 1; n < lmax; ++n) {
+      const double p2 = ((2 * n + 1) * mu * p1 - n * p0) / (n + 1);
+      p0 = p1;
+      p1 = p2;
+      P[size_t((n + 1) * kGL + q)] = p2;
+    }
+  }
+  std::vector<double> K(size_t(n_l * n_l * n_l * n_l));
+  for (int a = 0; a < n_l; ++a)
+    for (int b = 0; b < n_l; ++b)
+      for (int c = 0; c < n_l; ++c)
+        for (int d = 0; d < n_l; ++d) {
+          double s = 0.0;
+          for (int q = 0; q < kGL; ++q)
+            s += gl.w[q] * P[size_t(2 * a * kGL + q)] * P[size_t(2 * b * kGL + q)] * P[size_t(2 * c * kGL + q)] *
+                 P[size_t(2 * d * kGL + q)];
+          K[size_t(((a * n_l + b) * n_l + c) * n_l + d)] = 0.5 * s;
+        }
+  return K;
+}
+
+void theory_cov(Ctx &c, double r0, double volume, int n_k, const double *k_edges, int n_l, int n_p, const double *p,
+                const double *wp, const double *pk, double *out_dev) {
+  double *om = static_cast<double *>(ensure(c, c.th_om, size_t(n_l) * n_p * n_k * 8));
+  theory_omega(c, r0, n_k, k_edges, n_l, 2, n_p, p, om);
+  const std::vector<double> K = gaunt_coefficients(n_l);
+  const double *Kd = upload(c, c.th_K, K.data(), K.size());
+  const double *pd = upload(c, c.th_p, p, size_t(n_p)), *wd = upload(c, c.th_wp, wp, size_t(n_p));
+  const double *pkd = upload(c, c.th_pk, pk, size_t(n_l) * n_p);
+  const int64_t nout = int64_t(n_l) * n_k * n_l * n_k;
+  k_theory_cov<<<blocks(nout), 256, 0, c.stream>>>(om, pd, wd, pkd, Kd, n_p, n_k, n_l, 1.0 / volume, out_dev);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+}  // namespace hipster
