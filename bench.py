@@ -138,7 +138,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pk",
                     choices=["pk", "pk-fp64", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64",
-                             "bk-analytic", "bk-analytic-fp64", "bk5-analytic"])
+                             "bk-analytic", "bk-analytic-fp64", "bk5-analytic", "cov"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-primaries", type=int, default=16384)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -209,6 +209,46 @@ def main():
         units_per_pair = n_k * (wl.ell_max_b + 1) ** 2
         cfg = {"workload": wl.name, "n_points": wl.n, "n_randoms": int(rnd.shape[0]), "box": wl.box, "r0": wl.r0,
                "n_k": n_k, "ell_max": wl.ell_max_b, "precision": prec}
+    elif args.workload == "cov":
+        # theory side: Gaussian covariance of the headline power spectrum's
+        # binning (40 log bins over 1-10 h/Mpc, R0 = 25, l = 0, 2, 4) on a
+        # 9600-node p quadrature over [0, 40] with a model power spectrum
+        wl = synthetic.workload(2)
+        k = wl.k_edges_p
+        gx, gw = np.polynomial.legendre.leggauss(16)
+        e = np.linspace(0.0, 40.0, 601)
+        mid, half = 0.5 * (e[:-1] + e[1:]), 0.5 * (e[1:] - e[:-1])
+        p = (mid[:, None] + half[:, None] * gx).ravel()
+        wp = (half[:, None] * gw).ravel()
+        pk = np.array([2e4 / (1 + (p / 0.1) ** 2), -4e3 / (1 + (p / 0.15) ** 2), 8e2 / (1 + (p / 0.2) ** 2)])
+        V = wl.box ** 3
+        ctx = hp.Context(0)
+        n_k, n_ell = len(k) - 1, 3
+
+        def step():
+            t = time.perf_counter()
+            hp.cov_gauss(wl.r0, V, k, 4, p, wp, pk, ctx=ctx)
+            ms = (time.perf_counter() - t) * 1e3
+            return None, {"ms_sweep": ms, "sweep_launches": 1, "n_pairs": 0}
+        for _ in range(args.warmup):
+            step()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        dt = (time.perf_counter() - t0) / args.steps
+        # the dominant kernel's algorithmic work: omega's contraction, 2 FLOP per
+        # (l, p node, bin, r node); the r node count follows the library's rule
+        hmax = min(0.25 * wl.r0, 8.0 / max(p.max(), k[-1]))
+        n_r = 16 * sum(max(1, int(np.ceil(d / hmax))) for d in (0.5 * wl.r0, 0.25 * wl.r0, 0.25 * wl.r0))
+        flops = 2.0 * n_ell * p.size * n_k * n_r
+        out = {"metric": METRIC, "value": 1.0 / dt, "unit": "covariances/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": "cov_gauss_40bins_l024", "r0": wl.r0, "n_k": n_k, "ells": [0, 2, 4],
+                          "p_nodes": int(p.size), "r_nodes": int(n_r)},
+               "omega_flops": flops}
+        print(json.dumps(out), flush=True)
+        return
     elif args.workload in ("bk-analytic", "bk-analytic-fp64", "bk5-analytic"):
         wl = synthetic.workload(5 if args.workload == "bk5-analytic" else 3)
         prec = "fp64" if args.workload == "bk-analytic-fp64" else "mixed"

@@ -886,31 +886,39 @@ __global__ __launch_bounds__(256) void k_theory_pk(const double *__restrict__ r,
   out[idx] = 4.0 * kPi * ((li & 1) ? -1.0 : 1.0) * s;
 }
 
+// fq[l][l'][i] = wp_i p_i^2/(2 pi^2) Q_ll'(p_i), Q_ll'(p) = sum_{l1 l2}
+// K[l][l'][l1][l2] P_l1(p) P_l2(p); one thread per entry.
+__global__ __launch_bounds__(256) void k_theory_q(const double *__restrict__ p, const double *__restrict__ wp,
+                                                  const double *__restrict__ pk, const double *__restrict__ K,
+                                                  int n_p, int n_l, double *__restrict__ fq) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= int64_t(n_l) * n_l * n_p) return;
+  const int i = int(idx % n_p), ll = int(idx / n_p);
+  const double *Kll = K + ll * n_l * n_l;
+  double Q = 0.0;
+  for (int m1 = 0; m1 < n_l; ++m1) {
+    double t = 0.0;
+    for (int m2 = 0; m2 < n_l; ++m2) t = fma(Kll[m1 * n_l + m2], pk[int64_t(m2) * n_p + i], t);
+    Q = fma(t, pk[int64_t(m1) * n_p + i], Q);
+  }
+  fq[idx] = wp[i] * p[i] * p[i] * (1.0 / (2.0 * kPi * kPi)) * Q;
+}
+
 // Gaussian covariance: out[(l a)(l' b)] = 2 (2l+1)(2l'+1)/V sum_i
-// wp_i p_i^2/(2 pi^2) Q_ll'(p_i) omega[l][i][a] omega[l'][i][b], with
-// Q_ll'(p) = sum_{l1 l2} K[l][l'][l1][l2] P_l1(p) P_l2(p); one thread per
-// entry, i in order.
-__global__ __launch_bounds__(256) void k_theory_cov(const double *__restrict__ om, const double *__restrict__ p,
-                                                    const double *__restrict__ wp, const double *__restrict__ pk,
-                                                    const double *__restrict__ K, int n_p, int n_k, int n_l,
-                                                    double inv_volume, double *__restrict__ out) {
+// fq[l][l'][i] omega[l][i][a] omega[l'][i][b]; one thread per entry, i in
+// order.
+__global__ __launch_bounds__(256) void k_theory_cov(const double *__restrict__ om, const double *__restrict__ fq,
+                                                    int n_p, int n_k, int n_l, double inv_volume,
+                                                    double *__restrict__ out) {
   const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const int64_t nrow = int64_t(n_l) * n_k;
   if (idx >= nrow * nrow) return;
   const int b = int(idx % n_k), lj = int((idx / n_k) % n_l), a = int((idx / (int64_t(n_k) * n_l)) % n_k),
             li = int(idx / (int64_t(n_k) * n_l * n_k));
-  const double *Kll = K + (li * n_l + lj) * n_l * n_l;
+  const double *f = fq + int64_t(li * n_l + lj) * n_p;
+  const double *oa = om + int64_t(li) * n_p * n_k + a, *ob = om + int64_t(lj) * n_p * n_k + b;
   double s = 0.0;
-  for (int i = 0; i < n_p; ++i) {
-    double Q = 0.0;
-    for (int m1 = 0; m1 < n_l; ++m1) {
-      double t = 0.0;
-      for (int m2 = 0; m2 < n_l; ++m2) t = fma(Kll[m1 * n_l + m2], pk[int64_t(m2) * n_p + i], t);
-      Q = fma(t, pk[int64_t(m1) * n_p + i], Q);
-    }
-    const double f = wp[i] * p[i] * p[i] * (1.0 / (2.0 * kPi * kPi)) * Q;
-    s = fma(f * om[(int64_t(li) * n_p + i) * n_k + a], om[(int64_t(lj) * n_p + i) * n_k + b], s);
-  }
+  for (int i = 0; i < n_p; ++i) s = fma(f[i] * oa[int64_t(i) * n_k], ob[int64_t(i) * n_k], s);
   out[idx] = 2.0 * double(4 * li + 1) * double(4 * lj + 1) * inv_volume * s;
 }
 
@@ -1023,8 +1031,11 @@ void theory_cov(Ctx &c, double r0, double volume, int n_k, const double *k_edges
   const double *Kd = upload(c, c.th_K, K.data(), K.size());
   const double *pd = upload(c, c.th_p, p, size_t(n_p)), *wd = upload(c, c.th_wp, wp, size_t(n_p));
   const double *pkd = upload(c, c.th_pk, pk, size_t(n_l) * n_p);
+  double *fq = static_cast<double *>(ensure(c, c.th_J, size_t(n_l) * n_l * n_p * 8));  // J is no longer needed
+  k_theory_q<<<blocks(int64_t(n_l) * n_l * n_p), 256, 0, c.stream>>>(pd, wd, pkd, Kd, n_p, n_l, fq);
+  HIPSTER_HIP(hipGetLastError());
   const int64_t nout = int64_t(n_l) * n_k * n_l * n_k;
-  k_theory_cov<<<blocks(nout), 256, 0, c.stream>>>(om, pd, wd, pkd, Kd, n_p, n_k, n_l, 1.0 / volume, out_dev);
+  k_theory_cov<<<blocks(nout), 256, 0, c.stream>>>(om, fq, n_p, n_k, n_l, 1.0 / volume, out_dev);
   HIPSTER_HIP(hipGetLastError());
 }
 
