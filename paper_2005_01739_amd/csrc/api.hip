@@ -662,6 +662,47 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   }
 }
 
+// ------------------------------------------------------------ autotuner
+std::string tune_key(Ctx &c, const char *kernel, std::initializer_list<int> shape) {
+  hipDeviceProp_t prop{};
+  std::string dev = "device";
+  if (hipGetDeviceProperties(&prop, c.device) == hipSuccess)
+    dev = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+  std::string k = kernel;
+  for (int v : shape) k += ":" + std::to_string(v);
+  // no spaces: one whitespace-separated (key, value) pair per line
+  for (char &ch : dev)
+    if (ch == ' ') ch = '_';
+  return k + "@" + dev;
+}
+
+int tune_lookup(Ctx &c, const std::string &key) {
+  if (!c.tune_file_read) {
+    c.tune_file_read = true;
+    if (const char *path = getenv("HIPSTER_TUNE_CACHE")) {
+      if (FILE *f = fopen(path, "r")) {
+        char kbuf[512];
+        int v = 0;
+        while (fscanf(f, "%511s %d", kbuf, &v) == 2)
+          if (v > 0) c.tune[kbuf] = v;
+        fclose(f);
+      }
+    }
+  }
+  auto it = c.tune.find(key);
+  return it == c.tune.end() ? 0 : it->second;
+}
+
+void tune_store(Ctx &c, const std::string &key, int value) {
+  c.tune[key] = value;
+  if (const char *path = getenv("HIPSTER_TUNE_CACHE")) {
+    if (FILE *f = fopen(path, "a")) {
+      fprintf(f, "%s %d\n", key.c_str(), value);
+      fclose(f);
+    }
+  }
+}
+
 // Arguments of the theory-side calls: R0 > 0, n_k in [1, 128], strictly
 // increasing non-negative edges, ell_max in [0, 6] (even when `even`).
 static void check_theory(double r0, int n_k, const double *k_edges, int ell_max, bool even) {
@@ -994,7 +1035,7 @@ void hipster_destroy(hipster_ctx *ctx) {
                    &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile, &c.eii_consts, &c.eii_tab,
                    &c.ddr2_partial, &c.ddr2_hist, &c.ddr2_counter, &c.ddr2_T, &c.ct_tab, &c.ct_consts, &c.ct_C,
                    &c.ct_wmax, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
-                   &c.th_K, &c.th_out};
+                   &c.th_K, &c.th_out, &c.tune_scratch};
   for (DevBuf *b : all) free_buf(*b);
   delete ctx;
 }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <initializer_list>
 #include <map>
 #include <string>
 #include <tuple>
@@ -117,6 +118,10 @@ struct Ctx {
   DevBuf th_r, th_w, th_p, th_wp, th_pk, th_ek, th_g, th_J, th_om, th_K, th_out;
   // The E^II table on the device and the (R0, n_x, ell_max, edges) it holds.
   std::vector<double> eii_key;
+  // Measured kernel parameters (autotuner), keyed by kernel, shape and device.
+  std::map<std::string, int> tune;
+  bool tune_file_read = false;
+  DevBuf tune_scratch;
   // W~^a depends only on (R0, k_a, k_{a+1}); repeated calls reuse it.
   std::map<std::tuple<double, double, double>, double> wtilde_cache;
 };
@@ -224,6 +229,14 @@ void theory_pk(Ctx &c, double r0, int n_k, const double *k_edges, int n_l, int n
                const double *xi, double *out_dev);
 void theory_cov(Ctx &c, double r0, double volume, int n_k, const double *k_edges, int n_l, int n_p, const double *p,
                 const double *wp, const double *pk, double *out_dev);
+
+// Autotuner cache: tune_key names a kernel, its shape and the device (name
+// and compute-unit count); tune_lookup returns a stored value (0 if none),
+// reading the file named by HIPSTER_TUNE_CACHE once; tune_store records a
+// value in the context and appends it to that file.
+std::string tune_key(Ctx &c, const char *kernel, std::initializer_list<int> shape);
+int tune_lookup(Ctx &c, const std::string &key);
+void tune_store(Ctx &c, const std::string &key, int value);
 
 // Host analytic terms.
 double wtilde_bin(double r0, double k1, double k2);

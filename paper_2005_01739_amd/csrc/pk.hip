@@ -224,16 +224,68 @@ static void launch_far_ch(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, d
 }
 
 template <int NE>
-static void launch_far(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, double inv_r0, const double *ek,
-                       int n_edges, double *partial, int nwaves) {
+static void launch_far_any(Ctx &c, int ch, const PkPairs &p, int64_t npairs, bool fp64, double inv_r0,
+                           const double *ek, int n_edges, double *partial, int nwaves) {
   constexpr bool four = NE >= 4;
   constexpr int c0 = four ? kChunksMixed4[0] : kChunksMixed3[0];
   constexpr int c1 = four ? kChunksMixed4[1] : kChunksMixed3[1];
-  constexpr int c2 = four ? kChunksMixed4[2] : kChunksMixed3[2];
-  const int ch = pick_chunk(four ? kChunksMixed4 : kChunksMixed3, n_edges);
   if (ch == c0) launch_far_ch<NE, c0>(c, p, npairs, fp64, inv_r0, ek, n_edges, partial, nwaves);
   else if (ch == c1) launch_far_ch<NE, c1>(c, p, npairs, fp64, inv_r0, ek, n_edges, partial, nwaves);
-  else launch_far_ch<NE, c2>(c, p, npairs, fp64, inv_r0, ek, n_edges, partial, nwaves);
+  else launch_far_ch<NE, (four ? kChunksMixed4[2] : kChunksMixed3[2])>(c, p, npairs, fp64, inv_r0, ek, n_edges,
+                                                                        partial, nwaves);
+}
+
+// Edge-chunk size of the far kernel, measured.  The first sweep of a shape
+// (multipoles, edges, form) with at least kTunePairs pairs times each
+// compiled size on the first kTunePairs pairs into a scratch row set (two
+// runs each, the faster counted) and keeps the fastest in the context, and
+// in the file named by HIPSTER_TUNE_CACHE if set (one line per shape, keyed
+// by the device).  Smaller sweeps use the cost model of pick_chunk.  The
+// chunk size does not change any sum (each edge adds the same pairs in the
+// same order), so the choice affects time only.
+constexpr int64_t kTunePairs = int64_t(1) << 22;
+
+template <int NE>
+static int tuned_chunk(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, double inv_r0, const double *ek,
+                       int n_edges, int nwaves) {
+  constexpr bool four = NE >= 4;
+  const int(&sizes)[3] = four ? kChunksMixed4 : kChunksMixed3;
+  const std::string key = tune_key(c, "pk_far", {NE, n_edges, fp64 ? 1 : 0});
+  const int known = tune_lookup(c, key);
+  if (known > 0) return known;
+  if (npairs < kTunePairs) return pick_chunk(sizes, n_edges);
+  const size_t rows = size_t(nwaves) * NE * n_edges;
+  double *scratch = static_cast<double *>(ensure(c, c.tune_scratch, rows * 8));
+  hipEvent_t e0, e1;
+  HIPSTER_HIP(hipEventCreate(&e0));
+  HIPSTER_HIP(hipEventCreate(&e1));
+  int best = pick_chunk(sizes, n_edges);
+  float best_ms = -1.0f;
+  for (int ch : sizes) {
+    float ms_min = -1.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIPSTER_HIP(hipMemsetAsync(scratch, 0, rows * 8, c.stream));
+      HIPSTER_HIP(hipEventRecord(e0, c.stream));
+      launch_far_any<NE>(c, ch, p, kTunePairs, fp64, inv_r0, ek, n_edges, scratch, nwaves);
+      HIPSTER_HIP(hipEventRecord(e1, c.stream));
+      HIPSTER_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPSTER_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms_min < 0.0f || ms < ms_min) ms_min = ms;
+    }
+    if (best_ms < 0.0f || ms_min < best_ms) best = ch, best_ms = ms_min;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tune_store(c, key, best);
+  return best;
+}
+
+template <int NE>
+static void launch_far(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, double inv_r0, const double *ek,
+                       int n_edges, double *partial, int nwaves) {
+  const int ch = tuned_chunk<NE>(c, p, npairs, fp64, inv_r0, ek, n_edges, nwaves);
+  launch_far_any<NE>(c, ch, p, npairs, fp64, inv_r0, ek, n_edges, partial, nwaves);
 }
 
 void pk_sweep_general(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, bool fp64, double r0, const double *ek,

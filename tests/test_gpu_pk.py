@@ -154,3 +154,24 @@ def test_far_kernel_chunk_sizes(ell_max, n_edges):
     # kernels run; mixed form against the FP64 oracle
     pos = synthetic.thomas(3000, 200.0, 10, 2.0, 3.0, 21, np.float32)
     run_case(pos, None, 200.0, 20.0, np.geomspace(1.0, 6.0, n_edges), ell_max, "mixed")
+
+
+def test_far_chunk_autotuner_cache_and_invariance(tmp_path, monkeypatch):
+    # the far kernel's edge-chunk size is measured on the first large sweep of
+    # a shape and cached (in the context and the HIPSTER_TUNE_CACHE file); any
+    # compiled size gives the same bits, so forcing each one through the cache
+    # file must reproduce the tuned result exactly
+    import torch
+    import paper_2005_01739_amd as hp
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HIPSTER_TUNE_CACHE", str(cache))
+    L = 500.0
+    pos = torch.from_numpy(synthetic.thomas(500_000, L, 10, 2.0, 3.0, 71, np.float32)).cuda()
+    k = np.geomspace(1.0, 10.0, 41)
+    run = lambda ctx: hp.pk_ell(pos, box=L, r0=25.0, k_edges=k, ell_max=4, precision="mixed", ctx=ctx)
+    ref = run(hp.Context(0))
+    lines = cache.read_text().split()
+    assert len(lines) == 2 and lines[0].startswith("pk_far:3:41:0@") and int(lines[1]) in (11, 16, 21)
+    for ch in (11, 16, 21):
+        cache.write_text(f"{lines[0]} {ch}\n")
+        assert np.array_equal(run(hp.Context(0)), ref), ch
