@@ -138,7 +138,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pk",
                     choices=["pk", "pk-fp64", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64",
-                             "bk-analytic", "bk-analytic-fp64", "bk5-analytic", "cov"])
+                             "bk-analytic", "bk-analytic-fp64", "bk5-analytic", "cov", "batch-analytic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-primaries", type=int, default=16384)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -268,12 +268,17 @@ def main():
                "ddr2": "E^II kernel table + pair sweep to 2 R0 (no randoms)"}
     else:
         boxes = synthetic.batch_boxes(64, args.scale)
+        analytic = args.workload == "batch-analytic"
         specs = []
         for b in boxes:
             pos = torch.from_numpy(b.pos).cuda()
-            rnd = torch.from_numpy(b.randoms()).cuda()
-            specs.append(dict(pos=pos, randoms=rnd, box=b.box, r0=b.r0, pk_edges=b.k_edges_p, pk_ell_max=b.ell_max_p,
-                              bk_edges=b.k_edges_b, bk_ell_max=b.ell_max_b))
+            spec = dict(pos=pos, box=b.box, r0=b.r0, pk_edges=b.k_edges_p, pk_ell_max=b.ell_max_p,
+                        bk_edges=b.k_edges_b, bk_ell_max=b.ell_max_b)
+            if analytic:
+                spec["bk_eii_nodes"] = 0  # DDR^II from the E^II kernel, default table, no randoms
+            else:
+                spec["randoms"] = torch.from_numpy(b.randoms()).cuda()
+            specs.append(spec)
         prec = "mixed"
         nkp, nkb = len(boxes[0].k_edges_p) - 1, len(boxes[0].k_edges_b) - 1
 
@@ -282,9 +287,10 @@ def main():
             info["n_pairs"] = sum(o["n_pairs"] for o in outs)
             return outs, info
         units_per_pair = None
-        cfg = {"workload": "batch_64_boxes", "n_boxes": 64, "scale": args.scale,
-               "n_points_total": int(sum(b.n for b in boxes)), "pk": {"n_k": nkp, "ells": [0, 2, 4]},
-               "bk": {"n_k": nkb, "ell_max": boxes[0].ell_max_b}, "randoms_per_point": 3, "precision": prec}
+        cfg = {"workload": "batch_64_boxes" + ("_analytic_ddr2" if analytic else ""), "n_boxes": 64,
+               "scale": args.scale, "n_points_total": int(sum(b.n for b in boxes)),
+               "pk": {"n_k": nkp, "ells": [0, 2, 4]}, "bk": {"n_k": nkb, "ell_max": boxes[0].ell_max_b},
+               "randoms_per_point": 0 if analytic else 3, "precision": prec}
 
     for _ in range(args.warmup):
         step()
@@ -332,7 +338,7 @@ def main():
                "ms_per_step_with_cold_table": ms_step + cold["ms_eii_table"]}
         print(json.dumps(out), flush=True)
         return
-    if args.workload == "batch":
+    if args.workload in ("batch", "batch-analytic"):
         value = 64 / (dt / args.steps)
         out = {"metric": METRIC, "value": value, "unit": "boxes/s", "n_gpus": 1, "steps": args.steps,
                "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",

@@ -264,6 +264,10 @@ typedef struct {
   double *pk;               /* [pk ell_max/2+1][pk n_k] */
   double *bk;               /* [bk ell_max+1][bk n_k][bk n_k] */
   uint64_t n_pairs;         /* out: ordered data-data pairs */
+  int32_t bk_eii_nodes;     /* < 0: DDR^II from `randoms` (hipster_bk_ell); >= 0: from the
+                               E^II kernel as hipster_bk_ell_analytic with this n_x
+                               (0: default), `randoms` ignored */
+  int32_t reserved;
 } hipster_box_job;
 
 /* Many independent boxes in one pass: every box's pairs are enumerated into

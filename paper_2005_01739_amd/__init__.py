@@ -71,7 +71,8 @@ class _SurveyParams(ct.Structure):
 
 class _BoxJob(ct.Structure):
     _fields_ = [("data", _Points), ("randoms", _Points), ("pk_params", _Params), ("bk_params", _Params),
-                ("pk", _dp), ("bk", _dp), ("n_pairs", ct.c_uint64)]
+                ("pk", _dp), ("bk", _dp), ("n_pairs", ct.c_uint64), ("bk_eii_nodes", ct.c_int32),
+                ("reserved", ct.c_int32)]
 
 
 _lib = None
@@ -442,8 +443,10 @@ def cov_gauss(r0: float, volume: float, k_edges, ell_max: int, p, wp, pk, *, ctx
 
 def batch(boxes, *, precision: str = "mixed", ctx: Context | None = None, return_diag: bool = False):
     """Many boxes in one pass.  `boxes` is a sequence of dicts with keys pos,
-    w (optional), randoms (optional), box, r0, pk_edges / pk_ell_max (optional)
-    and bk_edges / bk_ell_max (optional).  Returns a list of dicts with 'pk'
+    w (optional), randoms (optional), box, r0, pk_edges / pk_ell_max (optional),
+    bk_edges / bk_ell_max (optional) and bk_eii_nodes (optional: >= 0 takes the
+    bispectrum's DDR^II term from the E^II kernel with that table size, 0 for
+    the default, and ignores randoms).  Returns a list of dicts with 'pk'
     and/or 'bk' arrays and 'n_pairs'."""
     L = load_library()
     keep: list = []
@@ -453,6 +456,7 @@ def batch(boxes, *, precision: str = "mixed", ctx: Context | None = None, return
         j = jobs[b]
         j.data = _points(spec["pos"], spec.get("w"), keep)
         j.randoms = _points(spec.get("randoms"), spec.get("rw"), keep)
+        j.bk_eii_nodes = int(spec.get("bk_eii_nodes", -1))
         res = {}
         if spec.get("pk_edges") is not None:
             lm = spec.get("pk_ell_max", 4)

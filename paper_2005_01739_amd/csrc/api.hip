@@ -457,21 +457,46 @@ static void run_pk_survey(Ctx &c, const hipster_points *dp, const hipster_points
 // -------------------------------------------------------------- bispectrum
 // E^{II,ab}_l table of the analytic DDR^II term on the device, rebuilt only
 // when (R0, n_x, ell_max, edges) change; *ms is its build time (0 if reused).
+// The context keeps up to kEiiCacheBytes of tables (so the boxes of a batch,
+// each with its own R0, keep theirs across calls); the least recently used
+// table goes first.
+constexpr size_t kEiiCacheBytes = size_t(2) << 30;
+
 static const double *eii_device_table(Ctx &c, Timer &tm, double r0, int n_k, const double *k, int ell_max, int n_x,
                                       double *ms) {
   std::vector<double> key = {r0, double(n_k), double(ell_max), double(n_x)};
   key.insert(key.end(), k, k + n_k + 1);
   const size_t bytes = size_t(ell_max + 1) * n_k * n_k * (size_t(n_x) + 1) * 8;
   *ms = 0.0;
-  if (c.eii_key == key && c.eii_tab.p && c.eii_tab.cap >= bytes) return static_cast<const double *>(c.eii_tab.p);
-  c.eii_key.clear();
-  double *tab = static_cast<double *>(ensure(c, c.eii_tab, bytes));
+  ++c.eii_clock;
+  for (EiiEntry &e : c.eii_cache)
+    if (e.key == key) {
+      e.used = c.eii_clock;
+      return static_cast<const double *>(e.buf.p);
+    }
+  // make room: drop least recently used tables until the new one fits
+  size_t held = 0;
+  for (const EiiEntry &e : c.eii_cache) held += e.buf.cap;
+  while (!c.eii_cache.empty() && held + bytes > kEiiCacheBytes) {
+    size_t oldest = 0;
+    for (size_t i = 1; i < c.eii_cache.size(); ++i)
+      if (c.eii_cache[i].used < c.eii_cache[oldest].used) oldest = i;
+    held -= c.eii_cache[oldest].buf.cap;
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    c.mem_used -= c.eii_cache[oldest].buf.cap;
+    free_buf(c.eii_cache[oldest].buf);
+    c.eii_cache.erase(c.eii_cache.begin() + long(oldest));
+  }
+  c.eii_cache.push_back(EiiEntry{});
+  EiiEntry &ent = c.eii_cache.back();
+  double *tab = static_cast<double *>(ensure(c, ent.buf, bytes));
   hipEvent_t e0 = tm.mark();
   eii_table(c, r0, n_k, k, ell_max, n_x, tab);
   hipEvent_t e1 = tm.mark();
   HIPSTER_HIP(hipEventSynchronize(e1));
   *ms = Timer::ms(e0, e1);
-  c.eii_key = key;
+  ent.key = key;
+  ent.used = c.eii_clock;
   return tab;
 }
 
@@ -769,7 +794,7 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
     if (j.bk_params.n_k > 0) {
       check_params(&j.bk_params, true);
       if (!j.bk) throw Error{HIPSTER_EINVAL, "batch: NULL bk output"};
-      if (j.randoms.n > 0) check_points(&j.randoms, "batch randoms", j.bk_params.box);
+      if (j.bk_eii_nodes < 0 && j.randoms.n > 0) check_points(&j.randoms, "batch randoms", j.bk_params.box);
     }
   }
   HIPSTER_HIP(hipSetDevice(c.device));
@@ -961,7 +986,10 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
     hipster_box_job &j = jobs[b];
     if (j.bk_params.n_k <= 0) continue;
     hipster_diag d{};
-    run_bk(c, &j.data, j.randoms.n > 0 ? &j.randoms : nullptr, &j.bk_params, j.bk, &d);
+    if (j.bk_eii_nodes >= 0)
+      run_bk(c, &j.data, nullptr, &j.bk_params, j.bk, &d, j.bk_eii_nodes);
+    else
+      run_bk(c, &j.data, j.randoms.n > 0 ? &j.randoms : nullptr, &j.bk_params, j.bk, &d);
     ms_build += d.ms_build;
     ms_pairs += d.ms_pairs;
     ms_sweep += d.ms_sweep;
@@ -1032,11 +1060,12 @@ void hipster_destroy(hipster_ctx *ctx) {
   DevBuf *all[] = {&c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in, &c.rmask_in, &c.pair_cnt, &c.pair_cnt_b,
                    &c.pair_ord, &c.pair_off, &c.pair_off_b, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
                    &c.partial, &c.merged, &c.ordered_count, &c.bbox, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out,
-                   &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile, &c.eii_consts, &c.eii_tab,
+                   &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile, &c.eii_consts,
                    &c.ddr2_partial, &c.ddr2_hist, &c.ddr2_counter, &c.ddr2_T, &c.ct_tab, &c.ct_consts, &c.ct_C,
                    &c.ct_wmax, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
                    &c.th_K, &c.th_out, &c.tune_scratch};
   for (DevBuf *b : all) free_buf(*b);
+  for (EiiEntry &e : c.eii_cache) free_buf(e.buf);
   delete ctx;
 }
 

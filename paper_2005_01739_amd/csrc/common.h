@@ -95,6 +95,13 @@ struct BoxSweep {
   int n_edges;
 };
 
+// A cached E^II table (analytic DDR^II).
+struct EiiEntry {
+  std::vector<double> key;
+  DevBuf buf;
+  uint64_t used = 0;
+};
+
 // Scratch of one catalogue's cell list.
 struct CellScratch {
   DevBuf cell, count, start, cursor, idx, x, y, z, w, m, bad, scan_tmp, scell, sort_tmp;
@@ -114,10 +121,11 @@ struct Ctx {
   DevBuf unit_tiles, unit_base, unit_cell, unit_tile;
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
-  DevBuf eii_consts, eii_tab, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T, ct_tab, ct_consts, ct_C, ct_wmax;
+  DevBuf eii_consts, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T, ct_tab, ct_consts, ct_C, ct_wmax;
   DevBuf th_r, th_w, th_p, th_wp, th_pk, th_ek, th_g, th_J, th_om, th_K, th_out;
-  // The E^II table on the device and the (R0, n_x, ell_max, edges) it holds.
-  std::vector<double> eii_key;
+  // E^II tables on the device, keyed by (R0, n_x, ell_max, edges).
+  std::vector<EiiEntry> eii_cache;
+  uint64_t eii_clock = 0;
   // Measured kernel parameters (autotuner), keyed by kernel, shape and device.
   std::map<std::string, int> tune;
   bool tune_file_read = false;

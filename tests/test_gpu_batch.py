@@ -81,3 +81,26 @@ def test_batch_deterministic():
     b = hp.batch(specs)
     for x, y in zip(a, b):
         assert np.array_equal(x["pk"], y["pk"])
+
+
+def test_batch_analytic_ddr2_matches_oracle():
+    # the randoms-free bispectrum in a batch: each box's B against the oracle's
+    # analytic estimator (its own table), and bitwise against the single call
+    import paper_2005_01739_amd as hp
+    specs = []
+    rng = np.random.default_rng(5)
+    for b in range(4):
+        n = int(rng.integers(400, 1500)) // 10 * 10
+        L = float(rng.uniform(60, 120))
+        r0 = float(rng.uniform(8, 15))
+        pos = synthetic.thomas(n, L, 10, 2.0, 0.0, [5, b], np.float32)
+        specs.append(dict(pos=pos, box=L, r0=r0, bk_edges=np.linspace(0.2, 1.0, 5), bk_ell_max=2,
+                          bk_eii_nodes=64, randoms=synthetic.poisson(n, L, [5, b, 1], np.float32)))
+    outs = hp.batch(specs, precision="mixed")
+    for spec, res in zip(specs, outs):
+        single = hp.bk_ell_analytic(spec["pos"], box=spec["box"], r0=spec["r0"], k_edges=spec["bk_edges"],
+                                    ell_max=2, n_x=64, precision="mixed")
+        assert np.array_equal(res["bk"], single)
+        ref = oracle.bk_ell_analytic(spec["pos"], None, spec["box"], spec["r0"], spec["bk_edges"], 2, 64)
+        scale = np.abs(ref["bk"]).max()
+        assert np.allclose(res["bk"], ref["bk"], rtol=1e-6, atol=1e-7 * scale)
