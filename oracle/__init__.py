@@ -86,6 +86,9 @@ def lib():
         L.oracle_cov_gauss.restype = ct.c_int
         L.oracle_cov_gauss.argtypes = [ct.c_double, ct.c_double, ct.c_int, _dp, ct.c_int, ct.c_int, _dp, _dp, _dp,
                                        _dp, ct.c_int]
+        L.oracle_cov_poisson2.restype = ct.c_int
+        L.oracle_cov_poisson2.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_int, _dp, ct.c_int, ct.c_int,
+                                          _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -332,4 +335,18 @@ def cov_gauss(r0, volume, k_edges, ell_max, p, wp, pk, nthreads=0):
     if lib().oracle_cov_gauss(float(r0), float(volume), n_k, _ptr(k), int(ell_max), p.size, _ptr(p), _ptr(wp),
                               _ptr(pk), _ptr(out), int(nthreads)) != 0:
         raise ValueError("oracle_cov_gauss: argument outside the oracle's range")
+    return out
+
+
+def cov_poisson2(r0, nbar, volume, k_edges, ell_max, r, wr, xi):
+    """Poisson two-point covariance term on the x quadrature (r, wr) with model
+    multipoles xi [ell_max/2+1, n_r]: [n_ell, n_k, n_ell, n_k]."""
+    k = _f64(k_edges)
+    r, wr = _f64(r), _f64(wr)
+    n_ell, n_k = ell_max // 2 + 1, k.size - 1
+    xi = _f64(xi).reshape(n_ell, r.size)
+    out = np.zeros((n_ell, n_k, n_ell, n_k))
+    if lib().oracle_cov_poisson2(float(r0), float(nbar), float(volume), n_k, _ptr(k), int(ell_max), r.size,
+                                 _ptr(r), _ptr(wr), _ptr(xi), _ptr(out)) != 0:
+        raise ValueError("oracle_cov_poisson2: argument outside the oracle's range")
     return out

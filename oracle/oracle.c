@@ -1147,3 +1147,47 @@ int oracle_cov_gauss(double r0, double volume, int n_k, const double *k, int ell
     free(om);
     return 0;
 }
+
+/* Poisson two-point covariance of the binned multipoles (Sec. 6, eq.
+ * cov-poiss, the 2C term), even l, l' <= ell_max:
+ *   C^ab_ll' = 2/(n^2 V) (2l+1)(2l'+1) (-i)^(l+l') 4 pi int x^2 W^2 jbar^a_l jbar^b_l'
+ *              [delta_ll'/(2l+1) + sum_L (L l l'; 0 0 0)^2 xi_L(x)] dx,
+ * with the x integral the caller's quadrature (nodes r[m] in [0, R0],
+ * weights wr[m]) and xi [ell_max/2+1][n_r] the model multipoles xi_L(r[m]) for
+ * even L <= ell_max (higher ones taken as zero).  Reading: the prefactor 2
+ * (the paper prints 4 here and 2 elsewhere); with xi = 0 it is the
+ * infinite-volume limit of the exact fixed-N variance of the estimator.
+ * out [n_ell][n_k][n_ell][n_k]. */
+int oracle_cov_poisson2(double r0, double nbar, double volume, int n_k, const double *k, int ell_max, int n_r,
+                        const double *r, const double *wr, const double *xi, double *out)
+{
+    if (!(r0 > 0.0) || !(nbar > 0.0) || !(volume > 0.0) || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 ||
+        ell_max > ORACLE_ELL_MAX || (ell_max & 1) || n_r < 1)
+        return -1;
+    const int n_ell = ell_max / 2 + 1;
+    double *g = malloc(sizeof(double) * (size_t)n_ell * n_r * n_k);
+    for (int li = 0; li < n_ell; ++li)
+        for (int m = 0; m < n_r; ++m) eii_g(2 * li, r[m], r0, n_k, k, g + ((size_t)li * n_r + m) * n_k);
+    for (int li = 0; li < n_ell; ++li)
+        for (int lj = 0; lj < n_ell; ++lj) {
+            const int l = 2 * li, lp = 2 * lj;
+            const double ph = ((li + lj) & 1) ? -1.0 : 1.0; /* (-i)^(l+l') for even l, l' */
+            const double pref = 2.0 / (nbar * nbar * volume) * (2.0 * l + 1.0) * (2.0 * lp + 1.0) * ph * 4.0 * PI;
+            for (int a = 0; a < n_k; ++a)
+                for (int b = 0; b < n_k; ++b) {
+                    double s = 0.0;
+                    for (int m = 0; m < n_r; ++m) {
+                        double br = (li == lj) ? 1.0 / (2.0 * l + 1.0) : 0.0;
+                        for (int L = 0; L < n_ell; ++L) {
+                            double t = oracle_wigner3j_000(2 * L, l, lp);
+                            br += t * t * xi[(size_t)L * n_r + m];
+                        }
+                        s += wr[m] * r[m] * r[m] * g[((size_t)li * n_r + m) * n_k + a] *
+                             g[((size_t)lj * n_r + m) * n_k + b] * br;
+                    }
+                    out[(((size_t)li * n_k + a) * n_ell + lj) * n_k + b] = pref * s;
+                }
+        }
+    free(g);
+    return 0;
+}

@@ -105,3 +105,63 @@ def test_window_theory_independent_sum():
                     for m in range(r.size))
             ref = 4 * np.pi * (-1) ** li * s
             assert abs(got[li, a] - ref) <= 1e-12 * abs(ref)
+
+
+def _x_quadrature(r0, panels=24, n=16):
+    gx, gw = np.polynomial.legendre.leggauss(n)
+    cuts = [0.0, 0.5 * r0, 0.75 * r0, r0]
+    xs, ws = [], []
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        e = np.linspace(lo, hi, panels + 1)
+        mid, half = 0.5 * (e[:-1] + e[1:]), 0.5 * (e[1:] - e[:-1])
+        xs.append((mid[:, None] + half[:, None] * gx).ravel())
+        ws.append((half[:, None] * gw).ravel())
+    return np.concatenate(xs), np.concatenate(ws)
+
+
+def test_poisson2_equals_exact_fixed_n_covariance():
+    # xi = 0: for N unit-weight uniform points the estimator's exact covariance is
+    #   2 (N^2 - N) / (n^2 V)^2 [delta_ll' (2l+1) 4 pi int r^2 W^2 jbar^a jbar^b dr / V
+    #                            - delta_l0 delta_l'0 W~^a W~^b / V^2]
+    # (the degenerate U-statistic whose variance the Poisson-null simulation pins),
+    # so C2 = exact / (1 - 1/N) + 2 delta delta W~^a W~^b / (n^2 V^2)
+    N, L = 500, 200.0
+    V, nbar = L ** 3, 500 / 200.0 ** 3
+    x, w = _x_quadrature(R0)
+    C2 = oracle.cov_poisson2(R0, nbar, V, K, 4, x, w, np.zeros((3, x.size)))
+    wt = np.array([oracle.wtilde(R0, K[a], K[a + 1]) for a in range(3)])
+    for li in range(3):
+        ell = 2 * li
+        I = np.array([[np.sum(w * x * x * np.array([oracle.window(xx / R0) ** 2 * oracle.jbar(ell, xx, K[a], K[a + 1])
+                                                      * oracle.jbar(ell, xx, K[b], K[b + 1]) for xx in x]))
+                       for b in range(3)] for a in range(3)])
+        zeta = (2 * ell + 1) * 4 * np.pi * I / V
+        if ell == 0:
+            zeta = zeta - np.outer(wt, wt) / V ** 2
+        exact = 2 * (N * N - N) / (nbar * nbar * V) ** 2 * zeta
+        ref = exact / (1 - 1 / N) + (2 * np.outer(wt, wt) / (nbar ** 2 * V ** 2) if ell == 0 else 0.0)
+        assert np.allclose(C2[li, :, li, :], ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+        for lj in range(3):
+            if lj != li:
+                assert np.all(C2[li, :, lj, :] == 0.0)
+
+
+def test_poisson2_xi_term_is_the_angular_average():
+    # the xi part: (1/2) int dmu L_l L_l' xi(x, mu) = sum_L (L l l'; 000)^2 xi_L(x)
+    x, w = _x_quadrature(R0, panels=4)
+    xi = np.array([3.0 * np.exp(-x / 6.0), -0.8 * np.exp(-x / 4.0), 0.2 * np.exp(-x / 3.0)])
+    nbar, V = 1e-3, 1e6
+    C0 = oracle.cov_poisson2(R0, nbar, V, K, 4, x, w, np.zeros_like(xi))
+    C = oracle.cov_poisson2(R0, nbar, V, K, 4, x, w, xi) - C0
+    mu, wmu = np.polynomial.legendre.leggauss(24)
+    for li in range(3):
+        for lj in range(3):
+            ang = np.array([0.5 * np.sum(wmu * eval_legendre(2 * li, mu) * eval_legendre(2 * lj, mu)
+                                         * sum(xi[L, m] * eval_legendre(2 * L, mu) for L in range(3)))
+                            for m in range(x.size)])
+            g = lambda ell: np.array([[oracle.window(xx / R0) * oracle.jbar(ell, xx, K[a], K[a + 1]) for a in range(3)]
+                                      for xx in x])
+            ga, gb = g(2 * li), g(2 * lj)
+            ref = (2 / (nbar ** 2 * V) * (4 * li + 1) * (4 * lj + 1) * (-1) ** (li + lj) * 4 * np.pi
+                   * np.einsum("m,ma,mb->ab", w * x * x * ang, ga, gb))
+            assert np.allclose(C[li, :, lj, :], ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
