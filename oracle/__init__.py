@@ -89,6 +89,9 @@ def lib():
         L.oracle_cov_poisson2.restype = ct.c_int
         L.oracle_cov_poisson2.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_int, _dp, ct.c_int, ct.c_int,
                                           _dp, _dp, _dp, _dp]
+        L.oracle_cov_poisson3.restype = ct.c_int
+        L.oracle_cov_poisson3.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_int, _dp, ct.c_int, ct.c_int,
+                                          _dp, _dp, _dp, _dp, _dp, _dp, ct.c_int]
         _lib = L
     return _lib
 
@@ -335,6 +338,25 @@ def cov_gauss(r0, volume, k_edges, ell_max, p, wp, pk, nthreads=0):
     if lib().oracle_cov_gauss(float(r0), float(volume), n_k, _ptr(k), int(ell_max), p.size, _ptr(p), _ptr(wp),
                               _ptr(pk), _ptr(out), int(nthreads)) != 0:
         raise ValueError("oracle_cov_gauss: argument outside the oracle's range")
+    return out
+
+
+def cov_poisson3(r0, nbar, volume, k_edges, ell_max, p, wp, pk, pbin=None, bk=None, nthreads=0):
+    """Poisson three-point covariance term on the p quadrature (p, wp) with
+    model P_L(p) [ell_max/2+1, n_p], windowed binned multipoles pbin
+    [ell_max/2+1, n_k] and bispectrum bk [ell_max/2+1, n_k, n_k] (either
+    None: zero): [n_ell, n_k, n_ell, n_k]."""
+    k = _f64(k_edges)
+    p, wp = _f64(p), _f64(wp)
+    n_ell, n_k = ell_max // 2 + 1, k.size - 1
+    pk = _f64(pk).reshape(n_ell, p.size)
+    pb = None if pbin is None else _f64(pbin).reshape(n_ell, n_k)
+    bb = None if bk is None else _f64(bk).reshape(n_ell, n_k, n_k)
+    out = np.zeros((n_ell, n_k, n_ell, n_k))
+    if lib().oracle_cov_poisson3(float(r0), float(nbar), float(volume), n_k, _ptr(k), int(ell_max), p.size, _ptr(p),
+                                 _ptr(wp), _ptr(pk), None if pb is None else _ptr(pb),
+                                 None if bb is None else _ptr(bb), _ptr(out), int(nthreads)) != 0:
+        raise ValueError("oracle_cov_poisson3: argument outside the oracle's range")
     return out
 
 

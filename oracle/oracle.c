@@ -36,7 +36,14 @@
  * fine lattice and against per-pair kernel values.  The theory side
  * (oracle_omega, oracle_cov_gauss, oracle_pk_window_theory) is pinned against
  * scipy quadrature, Parseval's relation with the E^II kernel at zero
- * separation, and the Gaunt integral of Q by direct angular quadrature.
+ * separation, and the Gaunt integral of Q by direct angular quadrature.  The
+ * Poisson terms (oracle_cov_poisson2, oracle_cov_poisson3) are pinned, at
+ * xi = 0, against the exact variance of the estimator for a uniform catalogue
+ * with a fixed or a Poisson-distributed number of points (a degenerate
+ * U-statistic, with the Poisson moments of N summed from the distribution);
+ * their xi and P_L parts by direct angular quadrature and Parseval's relation.
+ * The bispectrum term of 3C is added as printed: only the symmetry of the
+ * result under (l, a) <-> (l', b) pins it (parity unpinned for that term).
  */
 #include <complex.h>
 #include <math.h>
@@ -1189,5 +1196,58 @@ int oracle_cov_poisson2(double r0, double nbar, double volume, int n_k, const do
                 }
         }
     free(g);
+    return 0;
+}
+
+/* Poisson three-point covariance of the binned multipoles (Sec. 6, eq.
+ * cov-poiss, the 3C term), even l, l' <= ell_max:
+ *   C^ab_ll' = 4/(n V) [W~^a W~^b d_l0 d_l'0 + W~^a P^b_l' d_l0 + W~^b P^a_l d_l'0 + B^ab_l d_ll']
+ *            + 4/(n V) (2l+1)(2l'+1)(-1)^l sum_L (L l l'; 0 0 0)^2
+ *                int p^2 dp/(2 pi^2) P_L(p) omega^a_l(p) omega^b_l'(p),
+ * with the p integral the caller's quadrature (nodes p[i], weights wp[i]),
+ * pk [ell_max/2+1][n_p] the model multipoles P_L(p[i]) for even L <= ell_max
+ * (higher ones taken as zero), pbin [ell_max/2+1][n_k] the windowed binned
+ * multipoles P^a_l and bk [ell_max/2+1][n_k][n_k] the binned bispectrum
+ * B^ab_l at even l (either NULL: zero).  The B term is added as printed.
+ * out [n_ell][n_k][n_ell][n_k]. */
+int oracle_cov_poisson3(double r0, double nbar, double volume, int n_k, const double *k, int ell_max, int n_p,
+                        const double *p, const double *wp, const double *pk, const double *pbin, const double *bk,
+                        double *out, int nthreads)
+{
+    if (!(r0 > 0.0) || !(nbar > 0.0) || !(volume > 0.0) || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 ||
+        ell_max > ORACLE_ELL_MAX || (ell_max & 1) || n_p < 1)
+        return -1;
+    const int n_ell = ell_max / 2 + 1, nt = nthreads_or_default(nthreads);
+    const double f0 = 4.0 / (nbar * volume);
+    double Wt[ORACLE_NK_MAX];
+    for (int a = 0; a < n_k; ++a) Wt[a] = oracle_wtilde(r0, k[a], k[a + 1], 4.0);
+    double *om = malloc(sizeof(double) * (size_t)n_p * n_ell * n_k);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+    for (int i = 0; i < n_p; ++i)
+        for (int li = 0; li < n_ell; ++li) oracle_omega(p[i], r0, 2 * li, n_k, k, om + ((size_t)i * n_ell + li) * n_k);
+    for (int li = 0; li < n_ell; ++li)
+        for (int lj = 0; lj < n_ell; ++lj) {
+            const int l = 2 * li, lp = 2 * lj;
+            for (int a = 0; a < n_k; ++a)
+                for (int b = 0; b < n_k; ++b) {
+                    double s = 0.0;
+                    for (int i = 0; i < n_p; ++i) {
+                        double pl = 0.0;
+                        for (int L = 0; L < n_ell; ++L) {
+                            double t = oracle_wigner3j_000(2 * L, l, lp);
+                            pl += t * t * pk[(size_t)L * n_p + i];
+                        }
+                        s += wp[i] * p[i] * p[i] / (2.0 * PI * PI) * pl * om[((size_t)i * n_ell + li) * n_k + a] *
+                             om[((size_t)i * n_ell + lj) * n_k + b];
+                    }
+                    double c = f0 * (2.0 * l + 1.0) * (2.0 * lp + 1.0) * ((l & 1) ? -1.0 : 1.0) * s;
+                    if (li == 0 && lj == 0) c += f0 * Wt[a] * Wt[b];
+                    if (pbin && li == 0) c += f0 * Wt[a] * pbin[(size_t)lj * n_k + b];
+                    if (pbin && lj == 0) c += f0 * Wt[b] * pbin[(size_t)li * n_k + a];
+                    if (bk && li == lj) c += f0 * bk[((size_t)li * n_k + a) * n_k + b];
+                    out[(((size_t)li * n_k + a) * n_ell + lj) * n_k + b] = c;
+                }
+        }
+    free(om);
     return 0;
 }

@@ -165,3 +165,110 @@ def test_poisson2_xi_term_is_the_angular_average():
             ref = (2 / (nbar ** 2 * V) * (4 * li + 1) * (4 * lj + 1) * (-1) ** (li + lj) * 4 * np.pi
                    * np.einsum("m,ma,mb->ab", w * x * x * ang, ga, gb))
             assert np.allclose(C[li, :, lj, :], ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def _poisson_moments(lam):
+    # E[N(N-1)] and Var[N(N-1)] summed from the Poisson distribution itself
+    from scipy.stats import poisson
+    n = np.arange(0, int(lam + 40 * np.sqrt(lam) + 50))
+    pmf = poisson.pmf(n, lam)
+    pmf = pmf / np.sum(pmf)
+    f = n * (n - 1.0)
+    m1 = np.sum(pmf * f)
+    return m1, np.sum(pmf * (f - m1) ** 2)
+
+
+def test_poisson_terms_give_exact_variance_of_poisson_catalogue():
+    # xi = 0, N ~ Poisson(nV): by the law of total covariance the estimator's
+    # covariance is E_N[2 N(N-1)] zeta / (n^2 V)^2 + Var_N[N(N-1)] W~^a W~^b
+    # d_l0 d_l'0 / (n^2 V^2)^2, with zeta the per-pair covariance of the
+    # fixed-N U-statistic; 2C + 3C must equal it exactly
+    L, nbar = 150.0, 0.1
+    V = L ** 3
+    lam = nbar * V
+    x, w = _x_quadrature(R0)
+    p, wp = _p_quadrature(12.0, panels=40)
+    C2 = oracle.cov_poisson2(R0, nbar, V, K, 4, x, w, np.zeros((3, x.size)))
+    C3 = oracle.cov_poisson3(R0, nbar, V, K, 4, p, wp, np.zeros((3, p.size)))
+    m1, var = _poisson_moments(lam)
+    wt = np.array([oracle.wtilde(R0, K[a], K[a + 1]) for a in range(3)])
+    for li in range(3):
+        ell = 2 * li
+        I = np.array([[np.sum(w * x * x * np.array([oracle.window(xx / R0) ** 2 * oracle.jbar(ell, xx, K[a], K[a + 1])
+                                                      * oracle.jbar(ell, xx, K[b], K[b + 1]) for xx in x]))
+                       for b in range(3)] for a in range(3)])
+        zeta = (2 * ell + 1) * 4 * np.pi * I / V
+        if ell == 0:
+            zeta = zeta - np.outer(wt, wt) / V ** 2
+        ref = 2 * m1 * zeta / (nbar * nbar * V) ** 2
+        if ell == 0:
+            ref = ref + var * np.outer(wt, wt) / (nbar * nbar * V * V) ** 2
+        got = C2[li, :, li, :] + C3[li, :, li, :]
+        assert np.allclose(got, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+        for lj in range(3):
+            if lj != li:
+                assert np.all(C2[li, :, lj, :] + C3[li, :, lj, :] == 0.0)
+
+
+def test_poisson3_constant_power_and_single_node():
+    V, nbar = 1e6, 2e-3
+    f0 = 4 / (nbar * V)
+    wt = np.array([oracle.wtilde(R0, K[a], K[a + 1]) for a in range(3)])
+    # constant monopole P0: the P_L part is f0 (2l+1) P0 E^{II,ab}_l(0) delta_ll' (Parseval)
+    p, w = _p_quadrature(12.0)
+    P0 = 250.0
+    pk = np.zeros((3, p.size))
+    pk[0] = P0
+    C = oracle.cov_poisson3(R0, nbar, V, K, 4, p, w, pk)
+    for li in range(3):
+        ref = f0 * (4 * li + 1) * P0 * oracle.eii(0.0, R0, 2 * li, K)
+        if li == 0:
+            ref = ref + f0 * np.outer(wt, wt)
+        assert np.abs(C[li, :, li, :] - ref).max() <= 1e-7 * np.abs(ref).max()
+        for lj in range(3):
+            if lj != li:
+                assert np.abs(C[li, :, lj, :]).max() <= 1e-9 * np.abs(ref).max()
+    # one p node: (1/2) int dmu L_l L_l' P(p, mu) by direct angular quadrature
+    pk1 = np.array([[300.0], [-80.0], [25.0]])
+    p1 = 0.37
+    C1 = oracle.cov_poisson3(R0, nbar, V, K, 4, [p1], [1.0], pk1)
+    om = [oracle.omega(p1, R0, 2 * li, K) for li in range(3)]
+    mu, wmu = np.polynomial.legendre.leggauss(24)
+    Pmu = sum(pk1[m, 0] * eval_legendre(2 * m, mu) for m in range(3))
+    for li in range(3):
+        for lj in range(3):
+            ang = 0.5 * np.sum(wmu * eval_legendre(2 * li, mu) * eval_legendre(2 * lj, mu) * Pmu)
+            ref = f0 * (4 * li + 1) * (4 * lj + 1) * p1 ** 2 / (2 * np.pi ** 2) * ang * np.outer(om[li], om[lj])
+            if li == 0 and lj == 0:
+                ref = ref + f0 * np.outer(wt, wt)
+            assert np.allclose(C1[li, :, lj, :], ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+
+
+def test_poisson3_mean_fluctuation_terms():
+    # a catalogue whose conditional mean given N is N(N-1)/(nV)^2 (P^a_l + W~^a
+    # d_l0) - W~^a d_l0 gets, from Poisson fluctuations of N, the covariance
+    # Var_N[N(N-1)]/(nV)^4 (P^a_l + W~^a d_l0)(P^b_l' + W~^b d_l'0), whose
+    # 1/(nV) part is 4/(nV) times that product less P^a P^b: the first three
+    # 3C terms.  The B term only enters symmetrically.
+    V, nbar = 1e5, 1e-2
+    lam = nbar * V
+    rng = np.random.default_rng(3)
+    pbin = rng.normal(size=(3, 3)) * 50.0
+    B = rng.normal(size=(3, 3, 3)) * 1e3
+    B = B + B.transpose(0, 2, 1)
+    p, w = np.array([0.2]), np.array([0.0])  # the P_L part is zero here
+    C = oracle.cov_poisson3(R0, nbar, V, K, 4, p, w, np.zeros((3, 1)), pbin=pbin)
+    wt = np.array([oracle.wtilde(R0, K[a], K[a + 1]) for a in range(3)])
+    m = pbin.copy()
+    m[0] += wt
+    _, var = _poisson_moments(lam)
+    lead = (var / lam ** 4 - 2 / lam ** 2)  # the 1/(nV) coefficient times 1/(nV)
+    assert abs(lead * lam - 4.0) < 1e-8
+    for li in range(3):
+        for lj in range(3):
+            ref = lead * (np.outer(m[li], m[lj]) - np.outer(pbin[li], pbin[lj]))
+            assert np.allclose(C[li, :, lj, :], ref, rtol=1e-7, atol=1e-9 * np.abs(ref).max() + 1e-300)
+    CB = oracle.cov_poisson3(R0, nbar, V, K, 4, p, w, np.zeros((3, 1)), pbin=pbin, bk=B)
+    T = CB.transpose(2, 3, 0, 1)
+    assert np.allclose(CB, T, rtol=1e-14, atol=0)
+    assert not np.allclose(CB, C)
