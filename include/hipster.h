@@ -219,6 +219,42 @@ hipster_status hipster_cov_gauss(hipster_ctx *ctx, double r0, double volume, int
                                  int32_t ell_max, int32_t n_p, const double *p, const double *wp, const double *pk,
                                  double *out);
 
+/* Poisson two-point covariance term of the binned windowed multipoles (Sec. 6,
+ * eq. cov-poiss, the 2C term), even l, l' <= ell_max:
+ *   C^ab_ll' = 2/(n^2 V) (2l+1)(2l'+1) (-i)^(l+l') 4 pi int x^2 W^2 jbar^a_l jbar^b_l'
+ *              [delta_ll'/(2l+1) + sum_L (L l l'; 0 0 0)^2 xi_L(x)] dx,
+ * as the sum over the caller's nodes r[m] in [0, R0] with weights wr[m]; xi
+ * [ell_max/2+1][n_r] holds xi_L(r[m]) for even L <= ell_max (higher ones taken
+ * as zero); nbar the mean density, volume V.  The prefactor is 2, where the
+ * paper prints 4 in this term and 2 in its unbinned form: with xi = 0 the
+ * sum of this term and hipster_cov_poisson3 is then the estimator's exact
+ * covariance for a uniform catalogue with a Poisson-distributed number of
+ * points.  out: as hipster_cov_gauss.  Errors as the other
+ * theory calls; nbar <= 0 is HIPSTER_EDOMAIN. */
+hipster_status hipster_cov_poisson2(hipster_ctx *ctx, double r0, double nbar, double volume, int32_t n_k,
+                                    const double *k_edges, int32_t ell_max, int32_t n_r, const double *r,
+                                    const double *wr, const double *xi, double *out);
+
+/* Poisson three-point covariance term of the binned windowed multipoles
+ * (Sec. 6, eq. cov-poiss, the 3C term), even l, l' <= ell_max:
+ *   C^ab_ll' = 4/(n V) [W~^a W~^b d_l0 d_l'0 + W~^a P^b_l' d_l0 + W~^b P^a_l d_l'0 + B^ab_l d_ll']
+ *            + 4/(n V) (2l+1)(2l'+1) sum_L (L l l'; 0 0 0)^2
+ *                int p^2 dp/(2 pi^2) P_L(p) omega^a_l(p) omega^b_l'(p),
+ * the p integral the sum over the caller's nodes p[i], weights wp[i]; pk
+ * [ell_max/2+1][n_p] holds P_L(p[i]) for even L <= ell_max (higher ones taken
+ * as zero); pbin [ell_max/2+1][n_k] the windowed binned multipoles P^a_l (as
+ * hipster_pk_ell or hipster_pk_window_theory return them) and bk
+ * [ell_max/2+1][n_k][n_k] the binned bispectrum B^ab_l at even l (as
+ * hipster_bk_ell returns it); either may be NULL (taken as zero).  With xi = 0
+ * the sum of this term and hipster_cov_poisson2 is the exact covariance of the
+ * estimator for a uniform catalogue with a Poisson-distributed number of
+ * points.  out: as hipster_cov_gauss.  Errors as hipster_cov_gauss; nbar <= 0
+ * is HIPSTER_EDOMAIN. */
+hipster_status hipster_cov_poisson3(hipster_ctx *ctx, double r0, double nbar, double volume, int32_t n_k,
+                                    const double *k_edges, int32_t ell_max, int32_t n_p, const double *p,
+                                    const double *wp, const double *pk, const double *pbin, const double *bk,
+                                    double *out);
+
 /* Parameters of the survey-geometry power spectrum (hipster_pk_survey).
  * volume: V of the normalisation 1/(n_w^2 V), n_w = sum(w_data) / V (the
  * paper normalises by the ideal n^2 V, Sec. 2).  r0, n_k, ell_max, k_edges,

@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = ["Context", "wtilde", "pk_ell", "bk_ell", "batch", "HipsterError", "library_path", "load_library",
            "EXPORTED_SYMBOLS", "MIXED", "FP64", "pk_survey", "bk_ell_analytic", "eii_table",
-           "omega", "pk_window_theory", "cov_gauss"]
+           "omega", "pk_window_theory", "cov_gauss", "cov_poisson2", "cov_poisson3"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 MIXED, FP64 = 0, 1
@@ -29,7 +29,8 @@ EXPORTED_SYMBOLS = ("hipster_create", "hipster_destroy", "hipster_pk_ell", "hips
                     "hipster_batch", "hipster_last_error", "hipster_status_string",
                     "hipster_set_memory_cap", "hipster_wtilde", "hipster_pk_survey",
                     "hipster_bk_ell_analytic", "hipster_eii_table", "hipster_omega",
-                    "hipster_pk_window_theory", "hipster_cov_gauss")
+                    "hipster_pk_window_theory", "hipster_cov_gauss", "hipster_cov_poisson2",
+                    "hipster_cov_poisson3")
 
 
 class HipsterError(RuntimeError):
@@ -118,6 +119,12 @@ def load_library():
     L.hipster_cov_gauss.restype = ct.c_int
     L.hipster_cov_gauss.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, ct.c_int32, _dp, ct.c_int32, ct.c_int32,
                                     _dp, _dp, _dp, _dp]
+    L.hipster_cov_poisson2.restype = ct.c_int
+    L.hipster_cov_poisson2.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, ct.c_double, ct.c_int32, _dp, ct.c_int32,
+                                       ct.c_int32, _dp, _dp, _dp, _dp]
+    L.hipster_cov_poisson3.restype = ct.c_int
+    L.hipster_cov_poisson3.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, ct.c_double, ct.c_int32, _dp, ct.c_int32,
+                                       ct.c_int32, _dp, _dp, _dp, _dp, _dp, _dp]
     L.hipster_batch.restype = ct.c_int
     L.hipster_batch.argtypes = [ct.c_void_p, ct.c_int, ct.POINTER(_BoxJob), ct.POINTER(_Diag)]
     L.hipster_last_error.restype = ct.c_char_p
@@ -438,6 +445,42 @@ def cov_gauss(r0: float, volume: float, k_edges, ell_max: int, p, wp, pk, *, ctx
     c = ctx or _context_for(None)
     c.check(L.hipster_cov_gauss(c.handle, float(r0), float(volume), n_k, _ptr(k), int(ell_max), p.size, _ptr(p),
                                 _ptr(wp), _ptr(pk), _ptr(out)))
+    return out
+
+
+def cov_poisson2(r0: float, nbar: float, volume: float, k_edges, ell_max: int, r, wr, xi, *,
+                 ctx: Context | None = None) -> np.ndarray:
+    """Poisson two-point covariance term (even ell) on the x quadrature (r, wr)
+    over [0, R0] with model multipoles xi (ell_max/2 + 1, len(r)):
+    (n_ell, n_k, n_ell, n_k)."""
+    L = load_library()
+    k, r, wr = _host_f64(k_edges), _host_f64(r), _host_f64(wr)
+    n_ell, n_k = ell_max // 2 + 1, k.size - 1
+    xi = _host_f64(xi).reshape(n_ell, r.size)
+    out = np.zeros((n_ell, n_k, n_ell, n_k))
+    c = ctx or _context_for(None)
+    c.check(L.hipster_cov_poisson2(c.handle, float(r0), float(nbar), float(volume), n_k, _ptr(k), int(ell_max),
+                                   r.size, _ptr(r), _ptr(wr), _ptr(xi), _ptr(out)))
+    return out
+
+
+def cov_poisson3(r0: float, nbar: float, volume: float, k_edges, ell_max: int, p, wp, pk, pbin=None, bk=None, *,
+                 ctx: Context | None = None) -> np.ndarray:
+    """Poisson three-point covariance term (even ell) on the p quadrature
+    (p, wp) with model P_L(p) (ell_max/2 + 1, len(p)), windowed binned
+    multipoles pbin (ell_max/2 + 1, n_k) and bispectrum bk (ell_max/2 + 1,
+    n_k, n_k), either None for zero: (n_ell, n_k, n_ell, n_k)."""
+    L = load_library()
+    k, p, wp = _host_f64(k_edges), _host_f64(p), _host_f64(wp)
+    n_ell, n_k = ell_max // 2 + 1, k.size - 1
+    pk = _host_f64(pk).reshape(n_ell, p.size)
+    pb = None if pbin is None else _host_f64(pbin).reshape(n_ell, n_k)
+    bb = None if bk is None else _host_f64(bk).reshape(n_ell, n_k, n_k)
+    out = np.zeros((n_ell, n_k, n_ell, n_k))
+    c = ctx or _context_for(None)
+    c.check(L.hipster_cov_poisson3(c.handle, float(r0), float(nbar), float(volume), n_k, _ptr(k), int(ell_max),
+                                   p.size, _ptr(p), _ptr(wp), _ptr(pk), None if pb is None else _ptr(pb),
+                                   None if bb is None else _ptr(bb), _ptr(out)))
     return out
 
 

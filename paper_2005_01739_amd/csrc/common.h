@@ -122,7 +122,7 @@ struct Ctx {
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
   DevBuf eii_consts, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T, ct_tab, ct_consts, ct_C, ct_wmax;
-  DevBuf th_r, th_w, th_p, th_wp, th_pk, th_ek, th_g, th_J, th_om, th_K, th_out;
+  DevBuf th_r, th_w, th_p, th_wp, th_pk, th_ek, th_g, th_J, th_om, th_K, th_out, th_wt, th_pb, th_bk;
   // E^II tables on the device, keyed by (R0, n_x, ell_max, edges).
   std::vector<EiiEntry> eii_cache;
   uint64_t eii_clock = 0;
@@ -237,6 +237,15 @@ void theory_pk(Ctx &c, double r0, int n_k, const double *k_edges, int n_l, int n
                const double *xi, double *out_dev);
 void theory_cov(Ctx &c, double r0, double volume, int n_k, const double *k_edges, int n_l, int n_p, const double *p,
                 const double *wp, const double *pk, double *out_dev);
+// Poisson two-point covariance term of even multipoles on the caller's x
+// quadrature with model multipoles xi[L/2][m] (even L < 2 n_l).
+void theory_c2(Ctx &c, double r0, double nbar, double volume, int n_k, const double *k_edges, int n_l, int n_r,
+               const double *r, const double *wr, const double *xi, double *out_dev);
+// Poisson three-point covariance term on the caller's p quadrature; wt the
+// host W~ per bin, pbin [n_l][n_k] and bk [n_l][n_k][n_k] host arrays or null.
+void theory_c3(Ctx &c, double r0, double nbar, double volume, int n_k, const double *k_edges, int n_l, int n_p,
+               const double *p, const double *wp, const double *pk, const double *wt, const double *pbin,
+               const double *bk, double *out_dev);
 
 // Autotuner cache: tune_key names a kernel, its shape and the device (name
 // and compute-unit count); tune_lookup returns a stored value (0 if none),

@@ -922,6 +922,62 @@ __global__ __launch_bounds__(256) void k_theory_cov(const double *__restrict__ o
   out[idx] = 2.0 * double(4 * li + 1) * double(4 * lj + 1) * inv_volume * s;
 }
 
+// Poisson two-point covariance: out[(l a)(l' b)] = pref_ll' sum_m wr_m r_m^2
+// g[l][m][a] g[l'][m][b] (delta_ll'/(2l+1) + sum_L K3[L][l][l'] xi_L(r_m)),
+// pref_ll' = 2/(n^2 V) (2l+1)(2l'+1)(-1)^((l+l')/2) 4 pi; one thread per
+// entry, m in order.
+__global__ __launch_bounds__(256) void k_theory_c2(const double *__restrict__ r, const double *__restrict__ wr,
+                                                   const double *__restrict__ xi, const double *__restrict__ g,
+                                                   const double *__restrict__ K3, int n_r, int n_k, int n_l,
+                                                   double scale, double *__restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t nrow = int64_t(n_l) * n_k;
+  if (idx >= nrow * nrow) return;
+  const int b = int(idx % n_k), lj = int((idx / n_k) % n_l), a = int((idx / (int64_t(n_k) * n_l)) % n_k),
+            li = int(idx / (int64_t(n_k) * n_l * n_k));
+  const double diag = li == lj ? 1.0 / double(4 * li + 1) : 0.0;
+  double s = 0.0;
+  for (int m = 0; m < n_r; ++m) {
+    double br = diag;
+    for (int L = 0; L < n_l; ++L) br = fma(K3[(L * n_l + li) * n_l + lj], xi[int64_t(L) * n_r + m], br);
+    s = fma(wr[m] * r[m] * r[m] * g[(int64_t(li) * n_r + m) * n_k + a] * br, g[(int64_t(lj) * n_r + m) * n_k + b], s);
+  }
+  const double pref = scale * double(4 * li + 1) * double(4 * lj + 1) * (((li + lj) & 1) ? -1.0 : 1.0) * 4.0 * kPi;
+  out[idx] = pref * s;
+}
+
+// fq[l][l'][i] = wp_i p_i^2/(2 pi^2) sum_L K3[L][l][l'] P_L(p_i): the P_L
+// part of the Poisson three-point term, one thread per entry.
+__global__ __launch_bounds__(256) void k_theory_q3(const double *__restrict__ p, const double *__restrict__ wp,
+                                                   const double *__restrict__ pk, const double *__restrict__ K3,
+                                                   int n_p, int n_l, double *__restrict__ fq) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= int64_t(n_l) * n_l * n_p) return;
+  const int i = int(idx % n_p), ll = int(idx / n_p);
+  double s = 0.0;
+  for (int L = 0; L < n_l; ++L) s = fma(K3[L * n_l * n_l + ll], pk[int64_t(L) * n_p + i], s);
+  fq[idx] = wp[i] * p[i] * p[i] * (1.0 / (2.0 * kPi * kPi)) * s;
+}
+
+// The measured-quantity terms of the Poisson three-point covariance:
+// out[(l a)(l' b)] += f0 [W~_a W~_b d_l0 d_l'0 + W~_a P[l'][b] d_l0
+// + W~_b P[l][a] d_l'0 + B[l][a][b] d_ll'] (P, B may be null: zero).
+__global__ __launch_bounds__(256) void k_theory_c3_add(const double *__restrict__ wt, const double *__restrict__ pb,
+                                                       const double *__restrict__ bk, int n_k, int n_l, double f0,
+                                                       double *__restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t nrow = int64_t(n_l) * n_k;
+  if (idx >= nrow * nrow) return;
+  const int b = int(idx % n_k), lj = int((idx / n_k) % n_l), a = int((idx / (int64_t(n_k) * n_l)) % n_k),
+            li = int(idx / (int64_t(n_k) * n_l * n_k));
+  double t = 0.0;
+  if (li == 0 && lj == 0) t += wt[a] * wt[b];
+  if (pb && li == 0) t += wt[a] * pb[lj * n_k + b];
+  if (pb && lj == 0) t += wt[b] * pb[li * n_k + a];
+  if (bk && li == lj) t += bk[(int64_t(li) * n_k + a) * n_k + b];
+  out[idx] += f0 * t;
+}
+
 // The r node set: 16-point Gauss-Legendre panels on [0, R0/2], [R0/2, 3R0/4],
 // [3R0/4, R0], each no wider than hmax.
 static void theory_nodes(double r0, double hmax, std::vector<double> &r, std::vector<double> &w) {
@@ -1023,6 +1079,52 @@ static std::vector<double> gaunt_coefficients(int n_l) {
   return K;
 }
 
+// K3[L][l][l'] = (L l l'; 0 0 0)^2 = (1/2) int_{-1}^{1} L_L L_l L_l' dmu for
+// even L, l, l' <= 2 (n_l - 1), as an exact 16-point Gauss-Legendre sum.
+static std::vector<double> gaunt3(int n_l) {
+  const GLRule gl = gauss_legendre16();
+  const int lmax = 2 * (n_l - 1);
+  std::vector<double> P(size_t((lmax + 1) * kGL));
+  for (int q = 0; q < kGL; ++q) {
+    const double mu = gl.x[q];
+    double p0 = 1.0, p1 = mu;
+    P[size_t(q)] = 1.0;
+    if (lmax >= 1) P[size_t(kGL + q)] = mu;
+    for (int n = 1; n < lmax; ++n) {
+      const double p2 = ((2 * n + 1) * mu * p1 - n * p0) / (n + 1);
+      p0 = p1;
+      p1 = p2;
+      P[size_t((n + 1) * kGL + q)] = p2;
+    }
+  }
+  std::vector<double> K(size_t(n_l * n_l * n_l));
+  for (int L = 0; L < n_l; ++L)
+    for (int a = 0; a < n_l; ++a)
+      for (int b = 0; b < n_l; ++b) {
+        double s = 0.0;
+        for (int q = 0; q < kGL; ++q)
+          s += gl.w[q] * P[size_t(2 * L * kGL + q)] * P[size_t(2 * a * kGL + q)] * P[size_t(2 * b * kGL + q)];
+        K[size_t((L * n_l + a) * n_l + b)] = 0.5 * s;
+      }
+  return K;
+}
+
+void theory_c2(Ctx &c, double r0, double nbar, double volume, int n_k, const double *k_edges, int n_l, int n_r,
+               const double *r, const double *wr, const double *xi, double *out_dev) {
+  const double *rd = upload(c, c.th_r, r, size_t(n_r)), *wd = upload(c, c.th_w, wr, size_t(n_r));
+  const double *xd = upload(c, c.th_p, xi, size_t(n_l) * n_r);
+  const double *ek = edge_table(c, n_k, k_edges);
+  const std::vector<double> K3 = gaunt3(n_l);
+  const double *Kd = upload(c, c.th_K, K3.data(), K3.size());
+  double *g = static_cast<double *>(ensure(c, c.th_g, size_t(n_l) * n_r * n_k * 8));
+  k_theory_g<<<blocks(int64_t(n_l) * n_r * n_k), 256, 0, c.stream>>>(rd, n_r, n_k, n_l, 2, 1.0 / r0, ek, g);
+  HIPSTER_HIP(hipGetLastError());
+  const int64_t nout = int64_t(n_l) * n_k * n_l * n_k;
+  k_theory_c2<<<blocks(nout), 256, 0, c.stream>>>(rd, wd, xd, g, Kd, n_r, n_k, n_l, 2.0 / (nbar * nbar * volume),
+                                                   out_dev);
+  HIPSTER_HIP(hipGetLastError());
+}
+
 void theory_cov(Ctx &c, double r0, double volume, int n_k, const double *k_edges, int n_l, int n_p, const double *p,
                 const double *wp, const double *pk, double *out_dev) {
   double *om = static_cast<double *>(ensure(c, c.th_om, size_t(n_l) * n_p * n_k * 8));
@@ -1036,6 +1138,30 @@ void theory_cov(Ctx &c, double r0, double volume, int n_k, const double *k_edges
   HIPSTER_HIP(hipGetLastError());
   const int64_t nout = int64_t(n_l) * n_k * n_l * n_k;
   k_theory_cov<<<blocks(nout), 256, 0, c.stream>>>(om, fq, n_p, n_k, n_l, 1.0 / volume, out_dev);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+void theory_c3(Ctx &c, double r0, double nbar, double volume, int n_k, const double *k_edges, int n_l, int n_p,
+               const double *p, const double *wp, const double *pk, const double *wt, const double *pbin,
+               const double *bk, double *out_dev) {
+  double *om = static_cast<double *>(ensure(c, c.th_om, size_t(n_l) * n_p * n_k * 8));
+  theory_omega(c, r0, n_k, k_edges, n_l, 2, n_p, p, om);
+  const std::vector<double> K3 = gaunt3(n_l);
+  const double *Kd = upload(c, c.th_K, K3.data(), K3.size());
+  const double *pd = upload(c, c.th_p, p, size_t(n_p)), *wd = upload(c, c.th_wp, wp, size_t(n_p));
+  const double *pkd = upload(c, c.th_pk, pk, size_t(n_l) * n_p);
+  double *fq = static_cast<double *>(ensure(c, c.th_J, size_t(n_l) * n_l * n_p * 8));
+  k_theory_q3<<<blocks(int64_t(n_l) * n_l * n_p), 256, 0, c.stream>>>(pd, wd, pkd, Kd, n_p, n_l, fq);
+  HIPSTER_HIP(hipGetLastError());
+  const int64_t nout = int64_t(n_l) * n_k * n_l * n_k;
+  // k_theory_cov scales by 2 (2l+1)(2l'+1) x its last factor: 2/(n V) gives
+  // 4/(n V); (-1)^l is 1 for the even multipoles
+  k_theory_cov<<<blocks(nout), 256, 0, c.stream>>>(om, fq, n_p, n_k, n_l, 2.0 / (nbar * volume), out_dev);
+  HIPSTER_HIP(hipGetLastError());
+  const double *wtd = upload(c, c.th_wt, wt, size_t(n_k));
+  const double *pbd = pbin ? upload(c, c.th_pb, pbin, size_t(n_l) * n_k) : nullptr;
+  const double *bkd = bk ? upload(c, c.th_bk, bk, size_t(n_l) * n_k * n_k) : nullptr;
+  k_theory_c3_add<<<blocks(nout), 256, 0, c.stream>>>(wtd, pbd, bkd, n_k, n_l, 4.0 / (nbar * volume), out_dev);
   HIPSTER_HIP(hipGetLastError());
 }
 

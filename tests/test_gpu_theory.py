@@ -1,11 +1,14 @@
 """GPU parity of the theory side (hipster_omega, hipster_pk_window_theory,
-hipster_cov_gauss) against the FP64 oracle.  Both sides are double-precision
+hipster_cov_gauss, hipster_cov_poisson2, hipster_cov_poisson3) against the
+FP64 oracle.  Both sides are double-precision
 quadratures of the same integrals with different rules (omega) or the same
 caller quadrature (the windowed P, the covariance's p sum), so:
 * omega agrees to 1e-10 of the largest |omega| of its multipole;
 * the windowed P to 1e-11 relative per bin (only the bin averages differ in
   how they are evaluated);
-* the covariance to 1e-9 of its largest entry.
+* the covariance and the Poisson three-point term to 1e-9 of the largest
+  entry, the Poisson two-point term (same caller quadrature, no omega) to
+  1e-11.
 At the 40-bin size of the headline power spectrum, where the oracle's omega
 quadrature is too slow, the covariance is checked through an identity that
 holds at any size: for a constant monopole power P0 (higher multipoles
@@ -93,3 +96,35 @@ def test_theory_errors():
     with pytest.raises(hp.HipsterError) as e:
         hp.omega([1e6], R0, K, 2)
     assert e.value.name == "HIPSTER_EUNSUPPORTED"
+
+
+def test_poisson2_parity():
+    import paper_2005_01739_amd as hp
+    gx, gw = np.polynomial.legendre.leggauss(16)
+    cuts = [0.0, 0.5 * R0, 0.75 * R0, R0]
+    x = np.concatenate([0.5 * (hi - lo) * gx + 0.5 * (hi + lo) for lo, hi in zip(cuts[:-1], cuts[1:])])
+    w = np.concatenate([0.5 * (hi - lo) * gw for lo, hi in zip(cuts[:-1], cuts[1:])])
+    xi = np.array([3.0 * np.exp(-x / 6.0), -0.8 * np.exp(-x / 4.0), 0.2 * np.exp(-x / 3.0)])
+    k = np.geomspace(0.05, 2.0, 9)
+    got = hp.cov_poisson2(R0, 1e-3, 1e6, k, 4, x, w, xi)
+    ref = oracle.cov_poisson2(R0, 1e-3, 1e6, k, 4, x, w, xi)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_poisson3_parity():
+    import paper_2005_01739_amd as hp
+    p, w = _p_quadrature(6.0, panels=60)
+    pk = np.array([800.0 / (1 + (p / 0.2) ** 2), -200.0 / (1 + (p / 0.3) ** 2), 40.0 / (1 + (p / 0.5) ** 2)])
+    rng = np.random.default_rng(11)
+    pbin = rng.normal(size=(3, 3)) * 30.0
+    B = rng.normal(size=(3, 3, 3)) * 500.0
+    for pb, bk in ((None, None), (pbin, B)):
+        got = hp.cov_poisson3(R0, 1e-3, 1e6, K, 4, p, w, pk, pb, bk)
+        ref = oracle.cov_poisson3(R0, 1e-3, 1e6, K, 4, p, w, pk, pbin=pb, bk=bk)
+        assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
+    with pytest.raises(hp.HipsterError) as e:
+        hp.cov_poisson3(R0, 0.0, 1e6, K, 2, [0.1], [1.0], np.zeros((2, 1)))
+    assert e.value.name == "HIPSTER_EDOMAIN"
+    with pytest.raises(hp.HipsterError) as e:
+        hp.cov_poisson2(R0, -1.0, 1e6, K, 2, [1.0], [1.0], np.zeros((2, 1)))
+    assert e.value.name == "HIPSTER_EDOMAIN"
