@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pk",
-                    choices=["pk", "pk-fp64", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64",
+                    choices=["pk", "pk-fp64", "pk-table", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64",
                              "bk-analytic", "bk-analytic-fp64", "bk5-analytic", "cov", "batch-analytic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-primaries", type=int, default=16384)
@@ -163,9 +163,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.synchronize()
 
-    if args.workload in ("pk", "pk-fp64", "pk5"):
+    if args.workload in ("pk", "pk-fp64", "pk5", "pk-table"):
         wl = synthetic.workload(5 if args.workload == "pk5" else 2)
-        prec = "fp64" if args.workload == "pk-fp64" else "mixed"
+        prec = {"pk-fp64": "fp64", "pk-table": "table"}.get(args.workload, "mixed")
         pos = torch.from_numpy(wl.pos).cuda()
         w = None if wl.weights is None else torch.from_numpy(wl.weights).cuda()
         n_k, n_ell = len(wl.k_edges_p) - 1, wl.ell_max_p // 2 + 1
@@ -352,8 +352,14 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64+f32" if prec == "mixed" else "f64", "data": "synthetic",
            "config": cfg}
+    if prec == "table":
+        out["dtype"] = "f64+i64"
     avg_launch_ms = sweep_ms / max(launches, 1)
-    if args.workload in ("pk", "pk-fp64", "pk5", "survey", "survey-fp64"):
+    if args.workload == "pk-table":
+        out["roofline"] = None
+        out["avg_sweep_ms"] = sweep_ms / args.steps
+        out["avg_build_ms"] = None
+    elif args.workload in ("pk", "pk-fp64", "pk5", "survey", "survey-fp64"):
         unordered = (pairs + pairs_r) / 2.0
         per_pair = pk_flops_per_pair(n_k, n_ell)
         flops = unordered * per_pair / (launches / args.steps)

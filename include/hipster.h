@@ -63,8 +63,18 @@ typedef enum { HIPSTER_F32 = 0, HIPSTER_F64 = 1 } hipster_dtype;
  * and cosine (table-driven) and all accumulation in double precision, the
  * sine integral's auxiliary functions in single precision; it requires
  * k_edges[n_k] * R0 <= 1e6 (the table reduction's exact range), else
- * HIPSTER_EUNSUPPORTED.  FP64: every step in double precision, no limit. */
-typedef enum { HIPSTER_MIXED = 0, HIPSTER_FP64 = 1 } hipster_precision;
+ * HIPSTER_EUNSUPPORTED.  FP64: every step in double precision, no limit.
+ * TABLE (hipster_pk_ell only): the pair sum of Sec. 3 with jbar^a_l(r) taken
+ * from its quintic interpolant on n_c = max(64, 64 ceil(k_max R0 / 8.32))
+ * intervals of [0, R0] (k_max h <= 0.13, interpolation error ~2.4e-8 of
+ * jbar), built once per (R0, bins, ell_max) in double precision; each pair
+ * adds w_i w_j W(r/R0) L_l(mu) times its six Lagrange weights to a 64-bit
+ * fixed-point histogram per l, which is then contracted with the table.  The
+ * cost per pair no longer grows with n_k; pair counts stay exact and the sums
+ * do not depend on the order of the adds.  The histograms must fit the
+ * device's LDS: (ell_max/2 + 1)(n_c + 3) <= ~16000 nodes, else
+ * HIPSTER_EUNSUPPORTED.  diag->eii_nodes reports n_c. */
+typedef enum { HIPSTER_MIXED = 0, HIPSTER_FP64 = 1, HIPSTER_TABLE = 2 } hipster_precision;
 
 /* A catalogue.  pos: n x 3 row-major coordinates of `dtype`, each in [0, L).
  * w: n weights of `dtype`, or NULL for unit weights.  on_device: 1 if pos and

@@ -18,11 +18,11 @@ from typing import Any
 import numpy as np
 
 __all__ = ["Context", "wtilde", "pk_ell", "bk_ell", "batch", "HipsterError", "library_path", "load_library",
-           "EXPORTED_SYMBOLS", "MIXED", "FP64", "pk_survey", "bk_ell_analytic", "eii_table",
+           "EXPORTED_SYMBOLS", "MIXED", "FP64", "TABLE", "pk_survey", "bk_ell_analytic", "eii_table",
            "omega", "pk_window_theory", "cov_gauss", "cov_poisson2", "cov_poisson3"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-MIXED, FP64 = 0, 1
+MIXED, FP64, TABLE = 0, 1, 2
 _F32, _F64 = 0, 1
 
 EXPORTED_SYMBOLS = ("hipster_create", "hipster_destroy", "hipster_pk_ell", "hipster_bk_ell",
@@ -241,7 +241,7 @@ def _params(box, r0, k_edges, ell_max, los_axis, precision, mask, rmask, keep) -
     k = np.ascontiguousarray(k_edges, dtype=np.float64)
     if k.ndim != 1 or k.size < 2:
         raise ValueError("k_edges must be 1-D with at least two entries")
-    prec = {"mixed": MIXED, "fp64": FP64, MIXED: MIXED, FP64: FP64}[precision]
+    prec = {"mixed": MIXED, "fp64": FP64, "table": TABLE, MIXED: MIXED, FP64: FP64, TABLE: TABLE}[precision]
     m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
     rm = None if rmask is None else np.ascontiguousarray(rmask, dtype=np.uint8)
     keep += [k, m, rm]
@@ -288,7 +288,7 @@ def pk_ell(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, los
     return out, {"raw": raw, "wtilde": wt, "n_pairs": int(d.n_pairs), "ms_build": d.ms_build,
                  "ms_pairs": d.ms_pairs, "ms_sweep": d.ms_sweep, "ms_total": d.ms_total,
                  "sweep_launches": int(d.sweep_launches), "ms_sweep_far": d.ms_sweep_far,
-                 "n_pairs_far": int(d.n_pairs_far)}
+                 "n_pairs_far": int(d.n_pairs_far), "table_nodes": int(d.eii_nodes)}
 
 
 def pk_survey(pos, w=None, randoms=None, rw=None, *, volume: float, r0: float, k_edges, ell_max: int = 4,

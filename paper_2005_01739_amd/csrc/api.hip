@@ -76,7 +76,7 @@ static void check_points(const hipster_points *p, const char *what, double box) 
   (void)box;
 }
 
-static void check_params(const hipster_params *q, bool bispectrum) {
+static void check_params(const hipster_params *q, bool bispectrum, bool allow_table = false) {
   if (!q) throw Error{HIPSTER_EINVAL, "NULL parameters"};
   if (!(q->box > 0.0) || !isfinite(q->box)) throw Error{HIPSTER_EDOMAIN, "box size must be finite and positive"};
   if (!(q->r0 > 0.0) || !(q->r0 <= 0.5 * q->box)) throw Error{HIPSTER_EDOMAIN, "R0 must lie in (0, L/2]"};
@@ -91,7 +91,10 @@ static void check_params(const hipster_params *q, bool bispectrum) {
   if (q->ell_max < 0 || q->ell_max > kLMaxApi) throw Error{HIPSTER_EDOMAIN, "ell_max must lie in [0, 6]"};
   if (!bispectrum && (q->ell_max & 1)) throw Error{HIPSTER_EDOMAIN, "power spectrum: ell_max must be even"};
   if (!bispectrum && (q->los_axis < 0 || q->los_axis > 2)) throw Error{HIPSTER_EINVAL, "los_axis must be 0, 1 or 2"};
-  if (q->precision != HIPSTER_MIXED && q->precision != HIPSTER_FP64) throw Error{HIPSTER_EINVAL, "bad precision"};
+  if (q->precision == HIPSTER_TABLE && !allow_table)
+    throw Error{HIPSTER_EUNSUPPORTED, "HIPSTER_TABLE is available for hipster_pk_ell only"};
+  if (q->precision != HIPSTER_MIXED && q->precision != HIPSTER_FP64 && q->precision != HIPSTER_TABLE)
+    throw Error{HIPSTER_EINVAL, "bad precision"};
   // the mixed form's table-driven sine and cosine reduce u = k r exactly only
   // below ~1.6e6 (a 27-bit pi/128 times the table index)
   if (q->precision == HIPSTER_MIXED && q->k_edges[q->n_k] * q->r0 > kMaxPhaseMixed)
@@ -288,9 +291,12 @@ static std::vector<double> bin_sums(Ctx &c, double *partial, int nwaves, int n_e
 
 static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, double *pk, hipster_diag *diag) {
   check_points(pts, "data", q ? q->box : 0.0);
-  check_params(q, false);
+  check_params(q, false, true);
   if (!pk) throw Error{HIPSTER_EINVAL, "NULL output"};
   if (pts->n < 2) throw Error{HIPSTER_EINVAL, "need at least two points"};
+  const int n_c_tab = q->precision == HIPSTER_TABLE ? pktab_default_nodes(q->r0, q->k_edges[q->n_k]) : 0;
+  if (q->precision == HIPSTER_TABLE && size_t(q->ell_max / 2 + 1) * size_t(n_c_tab + 3) > ddr2_max_nodes(c))
+    throw Error{HIPSTER_EUNSUPPORTED, "table form: k_max R0 too large for the LDS histogram; use HIPSTER_MIXED"};
   HIPSTER_HIP(hipSetDevice(c.device));
   Timer tm(c);
   hipEvent_t t0 = tm.mark();
@@ -304,11 +310,51 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
   const Sorted s = build_cells(c, c.cells_d, g, pos, w, mask, n, pts->dtype);
   hipEvent_t t1 = tm.mark();
 
+  const int n_ell = q->ell_max / 2 + 1, n_edges = q->n_k + 1;
+  if (q->precision == HIPSTER_TABLE) {
+    // one histogram sweep of the ordered pairs and its contraction with
+    // the jbar table: S^a_l = (2l+1) (-i)^l T^a_l
+    unsigned long long *ord = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 8));
+    HIPSTER_HIP(hipMemsetAsync(ord, 0, 8, c.stream));
+    double *Td = static_cast<double *>(ensure(c, c.pt_T, size_t(n_ell) * q->n_k * 8));
+    hipEvent_t ts = tm.mark();
+    pktab_sweep(c, s, g, q->r0, q->n_k, q->k_edges, n_ell, q->los_axis, n_c_tab, Td, ord);
+    hipEvent_t te = tm.mark();
+    std::vector<double> T(size_t(n_ell) * q->n_k);
+    unsigned long long ordered = 0;
+    HIPSTER_HIP(hipMemcpyAsync(T.data(), Td, T.size() * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipMemcpyAsync(&ordered, ord, 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    const double p1 = weight_sum(pts);
+    const double V = q->box * q->box * q->box, nw = p1 / V, norm = 1.0 / (nw * nw * V);
+    std::vector<double> wt(static_cast<size_t>(q->n_k));
+    wtilde_bins(c, q->r0, q->n_k, q->k_edges, wt.data());
+    for (int li = 0; li < n_ell; ++li)
+      for (int a = 0; a < q->n_k; ++a) {
+        const double Sa = (4.0 * li + 1.0) * ((li & 1) ? -1.0 : 1.0) * T[size_t(li * q->n_k + a)];
+        if (diag && diag->raw) diag->raw[li * q->n_k + a] = Sa;
+        pk[li * q->n_k + a] = Sa * norm - (li == 0 ? wt[size_t(a)] : 0.0);
+      }
+    if (diag) {
+      diag->n_pairs = ordered;
+      diag->n_pairs_rand = 0;
+      diag->n_pairs_rr = 0;
+      if (diag->wtilde) memcpy(diag->wtilde, wt.data(), size_t(q->n_k) * 8);
+      diag->ms_build = Timer::ms(t0, t1);
+      diag->ms_pairs = 0.0;
+      diag->ms_sweep = Timer::ms(ts, te);
+      diag->ms_total = Timer::ms(t0, te);
+      diag->sweep_launches = 1;
+      diag->ms_sweep_far = 0.0;
+      diag->n_pairs_far = 0;
+      diag->eii_nodes = n_c_tab;
+    }
+    return;
+  }
   const bool fp64 = q->precision == HIPSTER_FP64;
   // pairs with r >= U_BIG / k_0 evaluate every edge on the large-argument
   // path (closed form with the Si auxiliaries); the near bucket holds the rest
   const double r_split = q->k_edges[0] > 0.0 ? HIPSTER_U_BIG / q->k_edges[0] : 0.0;
-  const int n_ell = q->ell_max / 2 + 1, n_edges = q->n_k + 1;
   double *edges = upload_edges(c, q->n_k, q->k_edges);
   const int nwaves = pk_sweep_waves(c);
   const int cols = n_ell * n_edges;
@@ -1063,7 +1109,8 @@ void hipster_destroy(hipster_ctx *ctx) {
                    &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile, &c.eii_consts,
                    &c.ddr2_partial, &c.ddr2_hist, &c.ddr2_counter, &c.ddr2_T, &c.ct_tab, &c.ct_consts, &c.ct_C,
                    &c.ct_wmax, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
-                   &c.th_K, &c.th_out, &c.th_wt, &c.th_pb, &c.th_bk, &c.tune_scratch};
+                   &c.th_K, &c.th_out, &c.th_wt, &c.th_pb, &c.th_bk, &c.pt_tab, &c.pt_consts, &c.pt_T,
+                   &c.tune_scratch};
   for (DevBuf *b : all) free_buf(*b);
   for (EiiEntry &e : c.eii_cache) free_buf(e.buf);
   delete ctx;

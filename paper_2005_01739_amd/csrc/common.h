@@ -122,6 +122,8 @@ struct Ctx {
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
   DevBuf eii_consts, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T, ct_tab, ct_consts, ct_C, ct_wmax;
+  DevBuf pt_tab, pt_consts, pt_T;  // power spectrum, table form
+  std::vector<double> pt_key;      // (R0, n_k, n_l, n_c, edges) of the table in pt_tab
   DevBuf th_r, th_w, th_p, th_wp, th_pk, th_ek, th_g, th_J, th_om, th_K, th_out, th_wt, th_pb, th_bk;
   // E^II tables on the device, keyed by (R0, n_x, ell_max, edges).
   std::vector<EiiEntry> eii_cache;
@@ -212,6 +214,12 @@ void eii_table(Ctx &c, double r0, int n_k, const double *k_edges, int ell_max, i
 void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, const double *table, int rows,
                 double *T, unsigned long long *ordered);
 size_t ddr2_max_nodes(Ctx &c);
+// Power spectrum, table form: T[li][a] = sum over ordered pairs inside R0 of
+// w_i w_j W(r/R0) L_{2 li}(mu) jbar^a_{2 li}(r), with jbar through a quintic
+// table on n_c intervals of [0, R0] (device output, n_l n_k doubles).
+int pktab_default_nodes(double r0, double k_max);
+void pktab_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, const double *k_edges, int n_l, int los,
+                 int n_c, double *T, unsigned long long *ordered);
 // C term of the bispectrum in the mixed form:
 // C^ab_l = sum over ordered pairs (p, q != p) inside R0, p selected by the
 // mask, of w_p w_q^2 W(r/R0)^2 jbar^a_l(r) jbar^b_l(r), from a pair histogram

@@ -308,6 +308,7 @@ __device__ inline void wave_sync() {
 enum HistKind {
   kHistDdr2 = 0,   // pairs inside 2 R0, weight w_i w_j per orientation
   kHistCterm = 1,  // pairs inside R0, weight w_p w_q^2 W(r/R0)^2 per orientation (p, q)
+  kHistPk = 2,     // pairs inside R0, weight w_i w_j W(r/R0) L_l(mu) per orientation, one section per even l
 };
 
 // CROSS: the home points (primaries) come from `s` and the neighbours from
@@ -317,14 +318,16 @@ enum HistKind {
 // n_x: table intervals (the interval index is clamped to n_x - 1); nodes
 // below n_keep receive weights, the others hold a zero kernel value;
 // n_hist: histogram entries.  kHistDdr2: n_keep = n_x, n_hist = n_x + 1;
-// kHistCterm: n_keep = n_hist = n_x + 3 (the table runs past R0).  Both sum
-// in 64-bit fixed point with scale fix_scale, so the histogram does not
-// depend on the order of the adds (bitwise reproducible).
-template <bool MASKED, int KIND, bool CROSS>
+// kHistCterm: n_keep = n_hist = n_x + 3 (the table runs past R0); kHistPk:
+// NLP sections (l = 0, 2, ..) of n_keep = n_x + 3 nodes each, n_hist = NLP
+// n_keep, and `los` the line-of-sight axis of mu.  All sum in 64-bit fixed
+// point with scale fix_scale, so the histogram does not depend on the order
+// of the adds (bitwise reproducible).
+template <bool MASKED, int KIND, bool CROSS, int NLP = 1>
 __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
                                                             double inv_h,
                                                             int n_x, int n_keep, int n_hist, double inv_r0,
-                                                            double fix_scale,
+                                                            double fix_scale, int los,
                                                             const int *__restrict__ unit_cell,
                                                             const int *__restrict__ unit_tile, int64_t n_units,
                                                             unsigned long long *__restrict__ counter,
@@ -341,10 +344,11 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
   constexpr int kWaves = kHistThreads / 64;
   // single-precision home coordinates for the prefilter
   __shared__ float4 homef[kHistTile];
-  // per wave: candidates (home index, neighbour lane) that passed the
-  // prefilter, and the neighbour tile (coordinates, weight) they refer to
-  __shared__ int q_i[kWaves][128], q_j[kWaves][128];
-  __shared__ double4 jt[kWaves][kHistTile];
+  // per wave: candidates (home index * 64 + neighbour lane) that passed the
+  // prefilter; the neighbour tile itself stays in registers, one point per
+  // lane, and is read across lanes
+  __shared__ unsigned short qc[kWaves][128];
+  double4 qreg = make_double4(0.0, 0.0, 0.0, 0.0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long below = (1ull << lane) - 1ull;
   // prefilter bound: (sqrt(lim2) + delta)^2 in single precision, delta = 2^-17 L
@@ -355,9 +359,10 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
   unsigned long long ord = 0;
   int qn = 0;  // queued candidates of this wave (uniform over the wave)
   // one (pair, image) at x = sqrt(r2): six-point Lagrange weights of the
-  // nodes m-2 .. m+3 times ww; nodes below 0 fold onto their mirror (both
-  // kernels are even in x), nodes >= n_keep hold a zero kernel
-  auto spread = [&](double r2, double ww) {
+  // nodes m-2 .. m+3 times ww[sec] into each section; nodes below 0 fold onto
+  // their mirror (every tabulated kernel is even in x), nodes >= n_keep hold
+  // a zero kernel
+  auto spread = [&](double r2, const double (&ww)[NLP]) {
     const double sx = sqrt(r2) * inv_h;
     int mi = int(sx);
     if (mi > n_x - 1) mi = n_x - 1;
@@ -372,19 +377,35 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
       int node = mi + q - 2;
       node = node < 0 ? -node : node;
       if (node < n_keep) {
-        {
+#pragma unroll
+        for (int sec = 0; sec < NLP; ++sec) {
           // fixed point (scale 2^e chosen on the host so no sum can
-          // overflow): integer sums do not depend on the order of the adds
-          const long long iv = llrint(ww * lw[q] * fix_scale);
-          atomicAdd(reinterpret_cast<unsigned long long *>(&hist[node]), static_cast<unsigned long long>(iv));
+          // overflow): integer sums do not depend on the order of the adds.
+          // kHistPk's scale keeps every single add below 2^30 in size, so it
+          // rounds with the native 32-bit conversion
+          long long iv;
+          if constexpr (KIND == kHistPk)
+            iv = __double2int_rn(ww[sec] * lw[q] * fix_scale);
+          else
+            iv = llrint(ww[sec] * lw[q] * fix_scale);
+          atomicAdd(reinterpret_cast<unsigned long long *>(&hist[sec * n_keep + node]),
+                    static_cast<unsigned long long>(iv));
         }
       }
     }
   };
   // the exact double-precision test of candidate (home ii, neighbour
-  // jbase + jl) and, inside 2 R0, its ordered-pair multiplicity and weight
-  auto exact = [&](int ii, int jl, int64_t jbase, double offx, double offy, double offz) {
-    const double4 p = home[ii], q = jt[wave][jl];
+  // jbase + jl) and, inside the radius, its ordered-pair multiplicity and
+  // weight; called by the whole wave (the neighbour is fetched from lane jl),
+  // lanes with valid = false only take part in the fetch
+  auto exact = [&](int ii, int jl, bool valid, int64_t jbase, double offx, double offy, double offz) {
+    double4 q;
+    q.x = __shfl(qreg.x, jl);
+    q.y = __shfl(qreg.y, jl);
+    q.z = __shfl(qreg.z, jl);
+    q.w = __shfl(qreg.w, jl);
+    if (!valid) return;
+    const double4 p = home[ii];
     const int64_t j = jbase + jl;
     double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
     dx -= offx;
@@ -400,17 +421,29 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
       const int mi_ = MASKED ? hm[ii] : 1, mj_ = CROSS ? 0 : (MASKED ? (b.m ? int(b.m[j]) : 1) : 1);
       ord += unsigned(mi_ + mj_);
       if (mi_ + mj_ > 0) {
+        double wv[NLP];
         if constexpr (CROSS) {
           // (primary i, neighbour j) only
           const double W = window<double>(sqrt(r2) * inv_r0);
-          spread(r2, p.w * q.w * q.w * double(mi_) * (W * W));
+          wv[0] = p.w * q.w * q.w * double(mi_) * (W * W);
         } else if constexpr (KIND == kHistDdr2) {
-          spread(r2, p.w * q.w * double(mi_ + mj_));
+          wv[0] = p.w * q.w * double(mi_ + mj_);
+        } else if constexpr (KIND == kHistPk) {
+          // both orientations have the same |mu|, and L_l is even
+          const double r = sqrt(r2);
+          const double d = los == 0 ? dx : (los == 1 ? dy : dz);
+          const double mu = r2 > 0.0 ? d / r : 0.0, m2 = mu * mu;
+          const double base = p.w * q.w * double(mi_ + mj_) * window<double>(r * inv_r0);
+          wv[0] = base;
+          if constexpr (NLP > 1) wv[1] = base * (1.5 * m2 - 0.5);
+          if constexpr (NLP > 2) wv[2] = base * (((35.0 * m2 - 30.0) * m2 + 3.0) * 0.125);
+          if constexpr (NLP > 3) wv[3] = base * ((((231.0 * m2 - 315.0) * m2 + 105.0) * m2 - 5.0) * 0.0625);
         } else {
           // (i, j) as (p, q) if i is selected, and (j, i) if j is
           const double W = window<double>(sqrt(r2) * inv_r0);
-          spread(r2, p.w * q.w * (double(mi_) * q.w + double(mj_) * p.w) * (W * W));
+          wv[0] = p.w * q.w * (double(mi_) * q.w + double(mj_) * p.w) * (W * W);
         }
+        spread(r2, wv);
       }
     }
   };
@@ -482,13 +515,13 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
       const int64_t jbase = nb_start[st] + j0;
       // single-precision copy of this lane's neighbour image for the prefilter
       float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+      qreg = make_double4(0.0, 0.0, 0.0, 0.0);
       if (lane < tj) {
         const int64_t j = jbase + lane;
-        const double4 q = make_double4(b.x[j], b.y[j], b.z[j], b.w[j]);
-        jt[wave][lane] = q;
-        fx = float(q.x + offx);
-        fy = float(q.y + offy);
-        fz = float(q.z + offz);
+        qreg = make_double4(b.x[j], b.y[j], b.z[j], b.w[j]);
+        fx = float(qreg.x + offx);
+        fy = float(qreg.y + offy);
+        fz = float(qreg.z + offz);
       }
       wave_sync();
       const int jg = j0 + lane;  // index of this lane's point within its cell
@@ -504,24 +537,18 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
         if (bal) {
           if (cand) {
             const int at = qn + __popcll(bal & below);
-            q_i[wave][at] = ii;
-            q_j[wave][at] = lane;
+            qc[wave][at] = static_cast<unsigned short>(ii * 64 + lane);
           }
           qn += __popcll(bal);
           if (qn >= 64) {
             wave_sync();
-            exact(q_i[wave][lane], q_j[wave][lane], jbase, offx, offy, offz);
+            const int e = qc[wave][lane];
+            exact(e >> 6, e & 63, true, jbase, offx, offy, offz);
             const int rest = qn - 64;
-            int a = 0, b = 0;
-            if (lane < rest) {
-              a = q_i[wave][64 + lane];
-              b = q_j[wave][64 + lane];
-            }
+            int a = 0;
+            if (lane < rest) a = qc[wave][64 + lane];
             wave_sync();
-            if (lane < rest) {
-              q_i[wave][lane] = a;
-              q_j[wave][lane] = b;
-            }
+            if (lane < rest) qc[wave][lane] = static_cast<unsigned short>(a);
             qn = rest;
             wave_sync();
           }
@@ -529,7 +556,10 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
       }
       // the queue refers to this neighbour tile: drain it before the next
       wave_sync();
-      if (lane < qn) exact(q_i[wave][lane], q_j[wave][lane], jbase, offx, offy, offz);
+      if (qn > 0) {
+        const int e = lane < qn ? int(qc[wave][lane]) : 0;
+        exact(e >> 6, e & 63, lane < qn, jbase, offx, offy, offz);
+      }
       qn = 0;
       wave_sync();
     }
@@ -564,12 +594,13 @@ __global__ void k_absmax(const double *__restrict__ w, int64_t n, unsigned long 
   if ((threadIdx.x & 63) == 0) atomicMax(out, best);
 }
 
-// T[row] = sum_m table[row][m] H[m]; one workgroup per (l, a, b) row, a
-// fixed-order tree reduction.
+// T[row] = sum_m table[row][m] H_s[m], H_s the histogram section
+// row / rows_per_hist; one workgroup per row, a fixed-order tree reduction.
 __global__ __launch_bounds__(256) void k_ddr2_contract(const double *__restrict__ table, const double *__restrict__ H,
-                                                       int n_nodes, double *__restrict__ T) {
+                                                       int n_nodes, int rows_per_hist, double *__restrict__ T) {
   __shared__ double red[256];
   const double *row = table + size_t(blockIdx.x) * n_nodes;
+  H += size_t(blockIdx.x / rows_per_hist) * n_nodes;
   double s = 0.0;
   for (int m = threadIdx.x; m < n_nodes; m += 256) s = fma(row[m], H[m], s);
   red[threadIdx.x] = s;
@@ -638,12 +669,12 @@ static void hist_sweep(Ctx &c, const Sorted &s, const Sorted &b, const Grid &g, 
   if (u.n > 0) {
     if (s.m || (!CROSS && b.m))
       k_ddr2_hist<true, KIND, CROSS><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
-          s, b, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, u.cell, u.tile, u.n, counter, ordered,
-          partial);
+          s, b, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, 0, u.cell, u.tile, u.n, counter,
+          ordered, partial);
     else
       k_ddr2_hist<false, KIND, CROSS><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
-          s, b, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, u.cell, u.tile, u.n, counter, ordered,
-          partial);
+          s, b, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, 0, u.cell, u.tile, u.n, counter,
+          ordered, partial);
     HIPSTER_HIP(hipGetLastError());
   } else {
     HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_hist * 8, c.stream));
@@ -651,7 +682,7 @@ static void hist_sweep(Ctx &c, const Sorted &s, const Sorted &b, const Grid &g, 
   k_hist_reduce_fix<<<dim3(unsigned((n_hist + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_hist,
                                                                                         1.0 / fix_scale, H);
   HIPSTER_HIP(hipGetLastError());
-  k_ddr2_contract<<<dim3(unsigned(rows)), dim3(256), 0, c.stream>>>(table, H, n_hist, out);
+  k_ddr2_contract<<<dim3(unsigned(rows)), dim3(256), 0, c.stream>>>(table, H, n_hist, rows, out);
   HIPSTER_HIP(hipGetLastError());
 }
 
@@ -780,6 +811,140 @@ void cterm_sweep(Ctx &c, const Sorted &s, const Sorted &b, bool cross, const Gri
   else
     hist_sweep<kHistCterm, false>(c, s, s, g, r0 * r0, 1.0 / h, n_c, n_nodes, n_nodes, 1.0 / r0, fix_scale, F, rows,
                                   C, ordered);
+}
+
+// ------------------------------------------------- power spectrum, table form
+// F^a_l(x_m) = jbar^a_l(x_m) on the nodes x_m = m R0 / n_c, m = 0 .. n_c + 2,
+// for even l = 2 li; one thread per (li, a, m).  jbar_l is entire and even in
+// x; the window is applied to each pair exactly in the sweep.
+__global__ __launch_bounds__(256) void k_pktab_table(double h, int n_nodes, int n_k, int n_l,
+                                                     const double *__restrict__ ek, const double *__restrict__ coef,
+                                                     double *__restrict__ F) {
+  __shared__ double2 tab[kSinCosTab];
+  stage_sincos_tab<kSinCosTab>(tab);
+  __syncthreads();
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= int64_t(n_l) * n_k * n_nodes) return;
+  const int m = int(idx % n_nodes), a = int((idx / n_nodes) % n_k), li = int(idx / (int64_t(n_nodes) * n_k));
+  const double x = m * h;
+  const double lo = ek[2 * a + 1] * G_one(2 * li, ek[2 * a] * x, tab);
+  const double hi = ek[2 * a + 3] * G_one(2 * li, ek[2 * a + 2] * x, tab);
+  F[idx] = coef[a] * (hi - lo);
+}
+
+int pktab_default_nodes(double r0, double k_max) {
+  // k_max h <= 0.13: the quintic's error is ~5e-3 (0.13)^6 = 2.4e-8 of jbar.
+  // Not capped: a count the LDS cannot hold is rejected by the caller.
+  const double want = std::min(1e7, k_max * r0 / 0.13);
+  return std::max(64, int(ceil(want / 64.0) * 64.0));
+}
+
+template <bool MASKED, int NLP>
+static void launch_pktab(Ctx &c, const Sorted &s, const Grid &g, const PairUnits &u, double lim2, double inv_h,
+                         int n_c, int n_nodes, double inv_r0, double fix_scale, int los,
+                         unsigned long long *counter, unsigned long long *ordered, double *partial, int nwg) {
+  const size_t lds = size_t(NLP) * n_nodes * 8;
+  k_ddr2_hist<MASKED, kHistPk, false, NLP><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
+      s, s, g.nc, g.L, lim2, inv_h, n_c, n_nodes, NLP * n_nodes, inv_r0, fix_scale, los, u.cell, u.tile, u.n, counter,
+      ordered, partial);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+template <int NLP>
+static int pktab_blocks_per_cu(int n_nodes) {
+  int per = 0;
+  HIPSTER_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per, reinterpret_cast<const void *>(&k_ddr2_hist<false, kHistPk, false, NLP>), kHistThreads,
+      size_t(NLP) * n_nodes * 8));
+  return std::max(1, per);
+}
+
+void pktab_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, const double *k_edges, int n_l, int los,
+                 int n_c, double *T, unsigned long long *ordered) {
+  const int n_nodes = n_c + 3, rows = n_l * n_k;
+  if (size_t(n_l) * n_nodes > ddr2_max_nodes(c))
+    throw Error{HIPSTER_EUNSUPPORTED, "table form: k_max R0 too large for the LDS histogram; use HIPSTER_MIXED"};
+  const double h = r0 / n_c;
+  // the table, kept while (R0, bins, multipoles, nodes) repeat
+  std::vector<double> key{r0, double(n_k), double(n_l), double(n_c)};
+  key.insert(key.end(), k_edges, k_edges + n_k + 1);
+  double *F = static_cast<double *>(ensure(c, c.pt_tab, size_t(rows) * n_nodes * 8));
+  if (key != c.pt_key) {
+    c.pt_key.clear();
+    std::vector<double> ek(static_cast<size_t>(2 * (n_k + 1))), coef(static_cast<size_t>(n_k));
+    for (int e = 0; e <= n_k; ++e) {
+      ek[size_t(2 * e)] = k_edges[e];
+      ek[size_t(2 * e + 1)] = k_edges[e] * k_edges[e] * k_edges[e];
+    }
+    for (int b = 0; b < n_k; ++b) coef[size_t(b)] = 3.0 / (ek[size_t(2 * b + 3)] - ek[size_t(2 * b + 1)]);
+    double *dk = static_cast<double *>(ensure(c, c.pt_consts, size_t(3 * n_k + 2) * 8));
+    HIPSTER_HIP(hipMemcpyAsync(dk, ek.data(), ek.size() * 8, hipMemcpyHostToDevice, c.stream));
+    HIPSTER_HIP(hipMemcpyAsync(dk + ek.size(), coef.data(), coef.size() * 8, hipMemcpyHostToDevice, c.stream));
+    const int64_t nt = int64_t(rows) * n_nodes;
+    k_pktab_table<<<dim3(unsigned((nt + 255) / 256)), dim3(256), 0, c.stream>>>(h, n_nodes, n_k, n_l, dk,
+                                                                               dk + ek.size(), F);
+    HIPSTER_HIP(hipGetLastError());
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));  // the host arrays above go out of scope
+    c.pt_key = key;
+  }
+  // fixed-point scale from the candidate bound: every node's sum of
+  // |w_i w_j W L_l l_q(t)| is at most (ordered candidates) * w_max^2 * 2.5
+  // (|W|, |L_l| <= 1; a node takes at most two basis values of a pair, each
+  // below 1.25 in size), kept below 2^61; and one add, at most 2 w_max^2
+  // 1.25 (both orientations), below 2^30.  The unit of the sums is then at
+  // most 2^-29 of the largest add, so the rounding stays below ~2e-9 of the
+  // bin's L1 mass
+  unsigned long long *cb = static_cast<unsigned long long *>(ensure(c, c.ct_wmax, 8));
+  HIPSTER_HIP(hipMemsetAsync(cb, 0, 8, c.stream));
+  const int64_t ncell = g.ncells();
+  k_candidate_bound<<<dim3(unsigned(std::min<int64_t>((ncell + 255) / 256, 1024))), dim3(256), 0, c.stream>>>(
+      s.cell_start, g.nc, cb);
+  HIPSTER_HIP(hipGetLastError());
+  unsigned long long cand = 0;
+  HIPSTER_HIP(hipMemcpyAsync(&cand, cb, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  const double wm = weight_max(c, s);
+  const double bound = (double(cand) + 1.0) * 2.5 * std::max(wm * wm, 1e-300);
+  const double one_add = 2.5 * std::max(wm * wm, 1e-300);
+  const int e = std::min(61 - int(ceil(log2(bound))), 30 - int(ceil(log2(one_add))));
+  const double fix_scale = ldexp(1.0, e);
+
+  const PairUnits u = make_pair_units(c, s, g);
+  int cus = 0;
+  HIPSTER_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
+  int per = 1;
+  switch (n_l) {
+    case 1: per = pktab_blocks_per_cu<1>(n_nodes); break;
+    case 2: per = pktab_blocks_per_cu<2>(n_nodes); break;
+    case 3: per = pktab_blocks_per_cu<3>(n_nodes); break;
+    default: per = pktab_blocks_per_cu<4>(n_nodes); break;
+  }
+  const int nwg = std::max(1, cus) * per;
+  const int n_hist = n_l * n_nodes;
+  double *partial = static_cast<double *>(ensure(c, c.ddr2_partial, size_t(nwg) * n_hist * 8));
+  double *H = static_cast<double *>(ensure(c, c.ddr2_hist, size_t(n_hist) * 8));
+  unsigned long long *counter = static_cast<unsigned long long *>(ensure(c, c.ddr2_counter, 8));
+  HIPSTER_HIP(hipMemsetAsync(counter, 0, 8, c.stream));
+  const double lim2 = r0 * r0, inv_h = 1.0 / h, inv_r0 = 1.0 / r0;
+  if (u.n > 0) {
+    const bool masked = s.m != nullptr;
+#define HIPSTER_PKTAB(M, N)                                                                                          \
+  launch_pktab<M, N>(c, s, g, u, lim2, inv_h, n_c, n_nodes, inv_r0, fix_scale, los, counter, ordered, partial, nwg)
+    switch (n_l) {
+      case 1: if (masked) HIPSTER_PKTAB(true, 1); else HIPSTER_PKTAB(false, 1); break;
+      case 2: if (masked) HIPSTER_PKTAB(true, 2); else HIPSTER_PKTAB(false, 2); break;
+      case 3: if (masked) HIPSTER_PKTAB(true, 3); else HIPSTER_PKTAB(false, 3); break;
+      default: if (masked) HIPSTER_PKTAB(true, 4); else HIPSTER_PKTAB(false, 4); break;
+    }
+#undef HIPSTER_PKTAB
+  } else {
+    HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_hist * 8, c.stream));
+  }
+  k_hist_reduce_fix<<<dim3(unsigned((n_hist + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_hist,
+                                                                                        1.0 / fix_scale, H);
+  HIPSTER_HIP(hipGetLastError());
+  k_ddr2_contract<<<dim3(unsigned(rows)), dim3(256), 0, c.stream>>>(F, H, n_nodes, n_k, T);
+  HIPSTER_HIP(hipGetLastError());
 }
 
 }  // namespace hipster

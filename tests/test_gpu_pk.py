@@ -15,7 +15,7 @@ import synthetic
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-14), "mixed": (1e-6, 2.0 ** -24)}
+TOL = {"fp64": (1e-12, 1e-14), "mixed": (1e-6, 2.0 ** -24), "table": (1e-6, 2.0 ** -24)}
 
 
 def _hp():
