@@ -323,8 +323,11 @@ enum HistKind {
 // n_keep, and `los` the line-of-sight axis of mu.  All sum in 64-bit fixed
 // point with scale fix_scale, so the histogram does not depend on the order
 // of the adds (bitwise reproducible).
+// The table form with up to three sections: six waves per SIMD (at most 80
+// VGPRs), three 8-wave workgroups per CU, which is what its LDS allows.
 template <bool MASKED, int KIND, bool CROSS, int NLP = 1>
-__global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
+__global__ __launch_bounds__(kHistThreads) __attribute__((amdgpu_waves_per_eu(KIND == 2 && NLP <= 3 ? 6 : 1))) void
+k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
                                                             double inv_h,
                                                             int n_x, int n_keep, int n_hist, double inv_r0,
                                                             double fix_scale, int los,
@@ -336,10 +339,17 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
   extern __shared__ double hist[];  // n_hist nodes
   __shared__ double4 home[kHistTile];
   __shared__ int hm[kHistTile];
-  constexpr int kStencil = CROSS ? 27 : 14;
-  __shared__ int64_t nb_start[kStencil];
-  __shared__ int nb_count[kStencil], nb_first[kStencil + 1];
-  __shared__ double nb_off[kStencil][3];
+  // the neighbour cells as runs contiguous in memory: cells are numbered
+  // with z fastest, so each (x, y) row of the stencil is one z-run, cut
+  // where it wraps round the box in z into up to three runs (the wrapped cell
+  // below, the cells inside, the wrapped cell above; with one cell per axis
+  // all three are that cell).  Half stencil: the rows (0, 0) from the home
+  // cell's z up, (0, +1) and (+1, -1..+1); full stencil: all nine rows.
+  constexpr int kRows = CROSS ? 9 : 5;
+  constexpr int kRuns = 3 * kRows;
+  __shared__ int64_t nb_start[kRuns];
+  __shared__ int nb_count[kRuns], nb_first[kRuns + 1], nb_self[kRuns];
+  __shared__ double nb_off[kRuns][3];
   __shared__ int64_t cur_unit;
   constexpr int kWaves = kHistThreads / 64;
   // single-precision home coordinates for the prefilter
@@ -447,6 +457,9 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
       }
     }
   };
+  // the unit index is taken and published between two barriers (publishing
+  // it at the end of the loop body instead, for a barrier at the top, let
+  // waves read a stale index: the barrier did not wait for the store)
   for (;;) {
     __syncthreads();
     if (tid == 0) cur_unit = int64_t(atomicAdd(counter, 1ull));
@@ -465,52 +478,95 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
       homef[tid] = make_float4(float(s.x[i]), float(s.y[i]), float(s.z[i]), 0.0f);
       if (MASKED) hm[tid] = s.m ? int(s.m[i]) : 1;
     }
-    if (tid < kStencil) {
-      int ox, oy, oz;
-      if (CROSS) {
-        ox = tid / 9 - 1;
-        oy = (tid / 3) % 3 - 1;
-        oz = tid % 3 - 1;
-      } else if (tid == 0) {
-        ox = oy = oz = 0;
-      } else {
-        const int t = tid + 13;
-        ox = t / 9 - 1;
-        oy = (t / 3) % 3 - 1;
-        oz = t % 3 - 1;
+    if (wave == 0) {
+      // lane r < kRows sets up stencil row r as runs 3r .. 3r+2; the wave
+      // then numbers the neighbour tiles with a prefix sum.  The self row's
+      // inside run (run 1) starts at the home cell, whose tiles before the
+      // home tile hold no pairs j > i and are skipped.
+      int tiles_lo = 0, tiles_in = 0, tiles_hi = 0;
+      if (lane < kRows) {
+        int ox, oy, zlo;
+        if (CROSS) {
+          ox = lane / 3 - 1;
+          oy = lane % 3 - 1;
+          zlo = cz - 1;
+        } else if (lane == 0) {
+          ox = 0;
+          oy = 0;
+          zlo = cz;
+        } else if (lane == 1) {
+          ox = 0;
+          oy = 1;
+          zlo = cz - 1;
+        } else {
+          ox = 1;
+          oy = lane - 3;
+          zlo = cz - 1;
+        }
+        const int zhi = cz + 1;
+        int sx = 0, sy = 0;
+        int nx = cx + ox, ny = cy + oy;
+        if (nx >= nc) { nx -= nc; sx = 1; } else if (nx < 0) { nx += nc; sx = -1; }
+        if (ny >= nc) { ny -= nc; sy = 1; } else if (ny < 0) { ny += nc; sy = -1; }
+        const int64_t rowbase = (int64_t(nx) * nc + ny) * nc;
+        // zlo >= -1 and zhi <= nc: the wrapped cells are z = -1 (cell nc - 1
+        // shifted down) and z = nc (cell 0 shifted up); the inside run
+        // [max(zlo, 0), min(zhi, nc - 1)] always holds z = cz
+        const int in0 = max(zlo, 0), in1 = min(zhi, nc - 1);
+        const int64_t s_in = b.cell_start[rowbase + in0];
+        const int cnt_in = int(b.cell_start[rowbase + in1 + 1] - s_in);
+        int64_t s_lo = 0, s_hi = 0;
+        int cnt_lo = 0, cnt_hi = 0;
+        if (zlo < 0) {
+          s_lo = b.cell_start[rowbase + nc - 1];
+          cnt_lo = int(b.cell_start[rowbase + nc] - s_lo);
+        }
+        if (zhi >= nc) {
+          s_hi = b.cell_start[rowbase];
+          cnt_hi = int(b.cell_start[rowbase + 1] - s_hi);
+        }
+        const bool self_row = !CROSS && lane == 0;
+        const int r = 3 * lane;
+        nb_start[r] = s_lo;
+        nb_count[r] = cnt_lo;
+        nb_self[r] = 0;
+        nb_start[r + 1] = s_in;
+        nb_count[r + 1] = cnt_in;
+        nb_self[r + 1] = self_row ? ni : 0;
+        nb_start[r + 2] = s_hi;
+        nb_count[r + 2] = cnt_hi;
+        nb_self[r + 2] = 0;
+        for (int q = 0; q < 3; ++q) {
+          nb_off[r + q][0] = double(sx) * L;
+          nb_off[r + q][1] = double(sy) * L;
+          nb_off[r + q][2] = double(q - 1) * L;
+        }
+        const int t0 = self_row ? i0 / kHistTile : 0;
+        tiles_lo = (cnt_lo + kHistTile - 1) / kHistTile;
+        tiles_in = max(0, (cnt_in + kHistTile - 1) / kHistTile - t0);
+        tiles_hi = (cnt_hi + kHistTile - 1) / kHistTile;
       }
-      int sx = 0, sy = 0, sz = 0;
-      int nx = cx + ox, ny = cy + oy, nz = cz + oz;
-      if (nx >= nc) { nx -= nc; sx = 1; } else if (nx < 0) { nx += nc; sx = -1; }
-      if (ny >= nc) { ny -= nc; sy = 1; } else if (ny < 0) { ny += nc; sy = -1; }
-      if (nz >= nc) { nz -= nc; sz = 1; } else if (nz < 0) { nz += nc; sz = -1; }
-      const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
-      nb_start[tid] = b.cell_start[nb];
-      nb_count[tid] = int(b.cell_start[nb + 1] - b.cell_start[nb]);
-      nb_off[tid][0] = double(sx) * L;
-      nb_off[tid][1] = double(sy) * L;
-      nb_off[tid][2] = double(sz) * L;
+      int incl = tiles_lo + tiles_in + tiles_hi;
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+      }
+      if (lane < kRows) {
+        nb_first[3 * lane] = incl - tiles_lo - tiles_in - tiles_hi;
+        nb_first[3 * lane + 1] = incl - tiles_in - tiles_hi;
+        nb_first[3 * lane + 2] = incl - tiles_hi;
+      }
+      if (lane == kRows - 1) nb_first[kRuns] = incl;
     }
     __syncthreads();
-    if (tid == 0) {
-      // neighbour tiles; in the home cell only tiles from the home tile on
-      // hold pairs j > i
-      int tot = 0;
-      for (int st = 0; st < kStencil; ++st) {
-        nb_first[st] = tot;
-        const int t0 = !CROSS && st == 0 ? i0 / kHistTile : 0;
-        tot += max(0, (nb_count[st] + kHistTile - 1) / kHistTile - t0);
-      }
-      nb_first[kStencil] = tot;
-    }
-    __syncthreads();
-    const int items = nb_first[kStencil];
+    const int items = nb_first[kRuns];
     for (int it = wave; it < items; it += kWaves) {
       int st = 0;
       while (it >= nb_first[st + 1]) ++st;
-      const int j0 = ((!CROSS && st == 0 ? i0 / kHistTile : 0) + it - nb_first[st]) * kHistTile;
+      const int j0 = ((!CROSS && st == 1 ? i0 / kHistTile : 0) + it - nb_first[st]) * kHistTile;
       const int tj = min(kHistTile, nb_count[st] - j0);
-      const bool self = !CROSS && st == 0;
+      const int self_n = nb_self[st];  // leading points of the run in the home cell
       const double offx = nb_off[st][0], offy = nb_off[st][1], offz = nb_off[st][2];
       const int64_t jbase = nb_start[st] + j0;
       // single-precision copy of this lane's neighbour image for the prefilter
@@ -524,33 +580,43 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
         fz = float(qreg.z + offz);
       }
       wave_sync();
-      const int jg = j0 + lane;  // index of this lane's point within its cell
-      for (int ii = 0; ii < ti; ++ii) {
-        bool cand = false;
-        if (lane < tj && !(self && jg <= i0 + ii)) {
+      const int jg = j0 + lane;  // index of this lane's point within its run
+      // four home points per step: their LDS reads issue together, so the
+      // wave waits on one read latency per four points (ii < 64 always
+      // indexes homef in bounds; entries from ti on are masked out)
+      constexpr int kStep = 4;
+      for (int ii0 = 0; ii0 < ti; ii0 += kStep) {
+        bool cand[kStep];
+#pragma unroll
+        for (int u = 0; u < kStep; ++u) {
+          const int ii = ii0 + u;
           const float4 p = homef[ii];
           const float dx = p.x - fx, dy = p.y - fy, dz = p.z - fz;
-          cand = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim2f;
+          cand[u] = ii < ti && lane < tj && !(jg < self_n && jg <= i0 + ii) &&
+                    fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim2f;
         }
-        // compact the candidates into the wave's queue; test and weigh 64 at a time
-        const unsigned long long bal = __ballot(cand);
-        if (bal) {
-          if (cand) {
-            const int at = qn + __popcll(bal & below);
-            qc[wave][at] = static_cast<unsigned short>(ii * 64 + lane);
-          }
-          qn += __popcll(bal);
-          if (qn >= 64) {
-            wave_sync();
-            const int e = qc[wave][lane];
-            exact(e >> 6, e & 63, true, jbase, offx, offy, offz);
-            const int rest = qn - 64;
-            int a = 0;
-            if (lane < rest) a = qc[wave][64 + lane];
-            wave_sync();
-            if (lane < rest) qc[wave][lane] = static_cast<unsigned short>(a);
-            qn = rest;
-            wave_sync();
+#pragma unroll
+        for (int u = 0; u < kStep; ++u) {
+          // compact the candidates into the wave's queue; test and weigh 64 at a time
+          const unsigned long long bal = __ballot(cand[u]);
+          if (bal) {
+            if (cand[u]) {
+              const int at = qn + __popcll(bal & below);
+              qc[wave][at] = static_cast<unsigned short>((ii0 + u) * 64 + lane);
+            }
+            qn += __popcll(bal);
+            if (qn >= 64) {
+              wave_sync();
+              const int e = qc[wave][lane];
+              exact(e >> 6, e & 63, true, jbase, offx, offy, offz);
+              const int rest = qn - 64;
+              int a = 0;
+              if (lane < rest) a = qc[wave][64 + lane];
+              wave_sync();
+              if (lane < rest) qc[wave][lane] = static_cast<unsigned short>(a);
+              qn = rest;
+              wave_sync();
+            }
           }
         }
       }
@@ -574,14 +640,35 @@ __global__ __launch_bounds__(kHistThreads) void k_ddr2_hist(Sorted s, Sorted b, 
 
 // H[m] = sum over workgroups of partial[wg][m] (the rows hold the int64 bit
 // patterns of fixed-point sums): an exact integer sum, then H[m] = sum / scale.
-__global__ void k_hist_reduce_fix(const double *__restrict__ partial, int nwg, int n_nodes, double inv_scale,
-                                  double *__restrict__ H) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n_nodes) return;
+// A block takes 64 nodes (one per lane, so every row read is one coalesced
+// 512-byte segment); its 16 waves split the rows and add their integer
+// partial sums in LDS, which gives the same bits in any order.
+constexpr int kReduceWaves = 16;
+__global__ __launch_bounds__(64 * kReduceWaves) void k_hist_reduce_fix(const double *__restrict__ partial, int nwg,
+                                                                      int n_nodes, double inv_scale,
+                                                                      double *__restrict__ H) {
+  __shared__ long long red[kReduceWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = blockIdx.x * 64 + lane;
   const long long *p = reinterpret_cast<const long long *>(partial);
   long long s = 0;
-  for (int g = 0; g < nwg; ++g) s += p[size_t(g) * n_nodes + m];
-  H[m] = double(s) * inv_scale;
+  if (m < n_nodes) {
+#pragma unroll 4
+    for (int g = wave; g < nwg; g += kReduceWaves) s += p[size_t(g) * n_nodes + m];
+  }
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0) {
+    long long t = 0;
+    for (int w = 0; w < kReduceWaves; ++w) t += red[w][lane];
+    if (m < n_nodes) H[m] = double(t) * inv_scale;
+  }
+}
+
+static void hist_reduce(Ctx &c, const double *partial, int nwg, int n_hist, double inv_scale, double *H) {
+  k_hist_reduce_fix<<<dim3(unsigned((n_hist + 63) / 64)), dim3(64 * kReduceWaves), 0, c.stream>>>(partial, nwg,
+                                                                                                  n_hist, inv_scale, H);
+  HIPSTER_HIP(hipGetLastError());
 }
 
 // Largest |w| of n doubles, as the bit pattern of a non-negative double
@@ -679,9 +766,7 @@ static void hist_sweep(Ctx &c, const Sorted &s, const Sorted &b, const Grid &g, 
   } else {
     HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_hist * 8, c.stream));
   }
-  k_hist_reduce_fix<<<dim3(unsigned((n_hist + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_hist,
-                                                                                        1.0 / fix_scale, H);
-  HIPSTER_HIP(hipGetLastError());
+  hist_reduce(c, partial, nwg, n_hist, 1.0 / fix_scale, H);
   k_ddr2_contract<<<dim3(unsigned(rows)), dim3(256), 0, c.stream>>>(table, H, n_hist, rows, out);
   HIPSTER_HIP(hipGetLastError());
 }
@@ -940,9 +1025,7 @@ void pktab_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, con
   } else {
     HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_hist * 8, c.stream));
   }
-  k_hist_reduce_fix<<<dim3(unsigned((n_hist + 255) / 256)), dim3(256), 0, c.stream>>>(partial, nwg, n_hist,
-                                                                                        1.0 / fix_scale, H);
-  HIPSTER_HIP(hipGetLastError());
+  hist_reduce(c, partial, nwg, n_hist, 1.0 / fix_scale, H);
   k_ddr2_contract<<<dim3(unsigned(rows)), dim3(256), 0, c.stream>>>(F, H, n_nodes, n_k, T);
   HIPSTER_HIP(hipGetLastError());
 }

@@ -78,6 +78,26 @@ def test_full_size_headline_workload():
     assert rel.max() <= 1e-6, rel.max()
 
 
+def test_dense_box_counts_exact_on_every_call():
+    # 4e5 clustered points in L = 500 (about 100 per cell of the R0 = 25 grid,
+    # several home tiles per cell, runs of up to three cells): the ordered
+    # pair count equals the FP64 form's on every one of several calls, and
+    # the multipoles repeat bitwise (a workgroup whose waves disagreed on the
+    # unit being swept would lose or repeat pairs, differently each call)
+    import torch
+    import paper_2005_01739_amd as hp
+    pos = torch.from_numpy(synthetic.thomas(400000, 500.0, 10, 2.0, 4.0, 6, np.float64)).cuda()
+    k = np.geomspace(1.0, 10.0, 41)
+    _, ref = hp.pk_ell(pos, box=500.0, r0=25.0, k_edges=k, precision="fp64", return_diag=True)
+    first = None
+    for _ in range(4):
+        got, info = hp.pk_ell(pos, box=500.0, r0=25.0, k_edges=k, precision="table", return_diag=True)
+        assert info["n_pairs"] == ref["n_pairs"]
+        if first is None:
+            first = got
+        assert np.array_equal(got, first)
+
+
 def test_errors():
     import paper_2005_01739_amd as hp
     pos = synthetic.poisson(200, 100.0, 4, np.float64)
