@@ -65,6 +65,14 @@ def sweep_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def pktab_flops_per_pair(n_ell: int) -> float:
+    """Algorithmic FP64 FLOPs per unordered pair of the table form: the
+    separation and r^2 (8), sqrt, window and mu (16), the Legendre
+    polynomials (3 per multipole above 0), the six Lagrange weights (25) and
+    two multiplies per (multipole, node) (12 per multipole)."""
+    return 49.0 + 3.0 * (n_ell - 1) + 12.0 * n_ell
+
+
 def pk_flops_per_pair(n_k: int, n_ell: int) -> float:
     """Algorithmic FLOPs per unordered pair for the power-spectrum weights."""
     return 40.0 + 80.0 * (n_k + 1) + 5.0 * n_k * n_ell
@@ -94,6 +102,31 @@ def traffic_from_profile():
     if d.get("source_hash") != sweep_source_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def table_form(hp, pos, wl, steps: int, warmup: int):
+    """The same workload in the table form (HIPSTER_TABLE): time per call
+    over `steps` calls after `warmup`, and its largest relative deviation
+    from the FP64 form over every output bin, measured here."""
+    import torch
+    kw = dict(box=wl.box, r0=wl.r0, k_edges=wl.k_edges_p, ell_max=wl.ell_max_p)
+    for _ in range(warmup):
+        hp.pk_ell(pos, precision="table", **kw)
+    torch.cuda.synchronize()
+    sweep_ms, pairs = 0.0, 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        got, info = hp.pk_ell(pos, precision="table", return_diag=True, **kw)
+        sweep_ms += info["ms_sweep"]
+        pairs = info["n_pairs"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ref, rinfo = hp.pk_ell(pos, precision="fp64", return_diag=True, **kw)
+    n_k, n_ell = len(wl.k_edges_p) - 1, wl.ell_max_p // 2 + 1
+    return {"precision": "table", "value": pairs * n_k * n_ell / dt, "unit": "pair-weights/s",
+            "ms_per_step": dt * 1e3, "avg_sweep_ms": sweep_ms / steps, "table_nodes": info["table_nodes"],
+            "pair_count_equals_fp64": bool(pairs == rinfo["n_pairs"]),
+            "max_rel_err_vs_fp64": float(np.max(np.abs(got - ref) / np.abs(ref)))}
 
 
 def cpu_baseline(wl, n_primaries: int = 16384, seed: int = 0):
@@ -140,6 +173,8 @@ def main():
                     choices=["pk", "pk-fp64", "pk-table", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64",
                              "bk-analytic", "bk-analytic-fp64", "bk5-analytic", "cov", "batch-analytic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-table-form", action="store_true",
+                    help="pk workload: leave out the table-form measurement (for profiling the mixed path alone)")
     ap.add_argument("--cpu-primaries", type=int, default=16384)
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--scale", type=float, default=0.1,
@@ -356,9 +391,16 @@ def main():
         out["dtype"] = "f64+i64"
     avg_launch_ms = sweep_ms / max(launches, 1)
     if args.workload == "pk-table":
-        out["roofline"] = None
-        out["avg_sweep_ms"] = sweep_ms / args.steps
-        out["avg_build_ms"] = None
+        # one histogram-sweep launch per call; its algorithmic FP64 work per
+        # unordered pair inside R0 (pktab_flops_per_pair), against the FP64
+        # vector peak: the kernel is bound by LDS atomics and pair-finding
+        # latency, not by this arithmetic
+        flops = (pairs / 2.0) * pktab_flops_per_pair(n_ell)
+        avg_launch_ms = sweep_ms / max(launches, 1)
+        achieved = flops / (avg_launch_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": "k_ddr2_hist<kHistPk>", "achieved": achieved,
+                           "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                           "traffic": None, "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
     elif args.workload in ("pk", "pk-fp64", "pk5", "survey", "survey-fp64"):
         unordered = (pairs + pairs_r) / 2.0
         per_pair = pk_flops_per_pair(n_k, n_ell)
@@ -393,6 +435,8 @@ def main():
                            "frac_fp64": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                            "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
     out["pairs_per_step"] = pairs + pairs_r
+    if args.workload == "pk" and not args.no_table_form:
+        out["table_form"] = table_form(hp, pos, wl, args.steps, args.warmup)
     if not args.no_cpu_baseline and args.workload == "pk":
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_primaries)
     print(json.dumps(out), flush=True)
