@@ -170,7 +170,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pk",
-                    choices=["pk", "pk-fp64", "pk-table", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64",
+                    choices=["pk", "pk-fp64", "pk-table", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64", "survey-table",
                              "bk-analytic", "bk-analytic-fp64", "bk5-analytic", "cov", "batch-analytic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-table-form", action="store_true",
@@ -212,9 +212,9 @@ def main():
         cfg = {"workload": wl.name, "n_points": wl.n, "box": wl.box, "r0": wl.r0, "n_k": n_k,
                "ells": list(range(0, wl.ell_max_p + 1, 2)), "k_range": [float(wl.k_edges_p[0]), float(wl.k_edges_p[-1])],
                "precision": prec, "weights": wl.weights is not None}
-    elif args.workload in ("survey", "survey-fp64"):
+    elif args.workload in ("survey", "survey-fp64", "survey-table"):
         sv = synthetic.survey()
-        prec = "fp64" if args.workload == "survey-fp64" else "mixed"
+        prec = {"survey-fp64": "fp64", "survey-table": "table"}.get(args.workload, "mixed")
         pos = torch.from_numpy(sv.pos).cuda()
         rnd = torch.from_numpy(sv.randoms).cuda()
         n_k, n_ell = len(sv.k_edges) - 1, sv.ell_max // 2 + 1
@@ -390,12 +390,12 @@ def main():
     if prec == "table":
         out["dtype"] = "f64+i64"
     avg_launch_ms = sweep_ms / max(launches, 1)
-    if args.workload == "pk-table":
-        # one histogram-sweep launch per call; its algorithmic FP64 work per
-        # unordered pair inside R0 (pktab_flops_per_pair), against the FP64
-        # vector peak: the kernel is bound by LDS atomics and pair-finding
-        # latency, not by this arithmetic
-        flops = (pairs / 2.0) * pktab_flops_per_pair(n_ell)
+    if args.workload in ("pk-table", "survey-table"):
+        # histogram-sweep launches (one per pair set); their algorithmic FP64
+        # work per unordered pair inside R0 (pktab_flops_per_pair), against
+        # the FP64 vector peak: the kernel is bound by LDS atomics and
+        # pair-finding latency, not by this arithmetic
+        flops = ((pairs + pairs_r) / 2.0) * pktab_flops_per_pair(n_ell) / (launches / args.steps)
         avg_launch_ms = sweep_ms / max(launches, 1)
         achieved = flops / (avg_launch_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "kernel": "k_ddr2_hist<kHistPk>", "achieved": achieved,

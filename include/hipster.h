@@ -64,7 +64,7 @@ typedef enum { HIPSTER_F32 = 0, HIPSTER_F64 = 1 } hipster_dtype;
  * sine integral's auxiliary functions in single precision; it requires
  * k_edges[n_k] * R0 <= 1e6 (the table reduction's exact range), else
  * HIPSTER_EUNSUPPORTED.  FP64: every step in double precision, no limit.
- * TABLE (hipster_pk_ell only): the pair sum of Sec. 3 with jbar^a_l(r) taken
+ * TABLE (hipster_pk_ell and hipster_pk_survey): the pair sum of Sec. 3 with jbar^a_l(r) taken
  * from its quintic interpolant on n_c = max(64, 64 ceil(k_max R0 / 8.32))
  * intervals of [0, R0] (k_max h <= 0.13, interpolation error ~2.4e-8 of
  * jbar), built once per (R0, bins, ell_max) in double precision; each pair

@@ -307,7 +307,7 @@ def pk_survey(pos, w=None, randoms=None, rw=None, *, volume: float, r0: float, k
     k = np.ascontiguousarray(k_edges, dtype=np.float64)
     if k.ndim != 1 or k.size < 2:
         raise ValueError("k_edges must be 1-D with at least two entries")
-    prec = {"mixed": MIXED, "fp64": FP64, MIXED: MIXED, FP64: FP64}[precision]
+    prec = {"mixed": MIXED, "fp64": FP64, "table": TABLE, MIXED: MIXED, FP64: FP64, TABLE: TABLE}[precision]
     m = None if primary_mask is None else np.ascontiguousarray(primary_mask, dtype=np.uint8)
     rm = None if random_mask is None else np.ascontiguousarray(random_mask, dtype=np.uint8)
     keep += [k, m, rm]

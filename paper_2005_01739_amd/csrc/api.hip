@@ -92,7 +92,7 @@ static void check_params(const hipster_params *q, bool bispectrum, bool allow_ta
   if (!bispectrum && (q->ell_max & 1)) throw Error{HIPSTER_EDOMAIN, "power spectrum: ell_max must be even"};
   if (!bispectrum && (q->los_axis < 0 || q->los_axis > 2)) throw Error{HIPSTER_EINVAL, "los_axis must be 0, 1 or 2"};
   if (q->precision == HIPSTER_TABLE && !allow_table)
-    throw Error{HIPSTER_EUNSUPPORTED, "HIPSTER_TABLE is available for hipster_pk_ell only"};
+    throw Error{HIPSTER_EUNSUPPORTED, "HIPSTER_TABLE is available for the power spectra only"};
   if (q->precision != HIPSTER_MIXED && q->precision != HIPSTER_FP64 && q->precision != HIPSTER_TABLE)
     throw Error{HIPSTER_EINVAL, "bad precision"};
   // the mixed form's table-driven sine and cosine reduce u = k r exactly only
@@ -422,7 +422,7 @@ static void run_pk_survey(Ctx &c, const hipster_points *dp, const hipster_points
     pp.k_edges = q->k_edges;
     pp.los_axis = 2;
     pp.precision = q->precision;
-    check_params(&pp, false);
+    check_params(&pp, false, true);
   }
   HIPSTER_HIP(hipSetDevice(c.device));
   Timer tm(c);
@@ -445,6 +445,52 @@ static void run_pk_survey(Ctx &c, const hipster_points *dp, const hipster_points
   hipEvent_t t1 = tm.mark();
 
   const double p1 = weight_sum(dp), pr1 = weight_sum(rp), sR = p1 / pr1;
+  if (q->precision == HIPSTER_TABLE) {
+    // DD (+1), DR + RD (-s_R), RR (+s_R^2), each a histogram sweep with its
+    // own fixed-point scale, contracted with the jbar table and summed here
+    const int n_ell_t = q->ell_max / 2 + 1, n_c = pktab_default_nodes(q->r0, q->k_edges[q->n_k]);
+    if (size_t(n_ell_t) * size_t(n_c + 3) > ddr2_max_nodes(c))
+      throw Error{HIPSTER_EUNSUPPORTED, "table form: k_max R0 too large for the LDS histogram; use HIPSTER_MIXED"};
+    double cb = 0.0;
+    for (int d = 0; d < 3; ++d) cb = std::max(cb, std::max(fabs(lo[d]), fabs(hi[d])));
+    const size_t nt = size_t(n_ell_t) * q->n_k;
+    double *Td = static_cast<double *>(ensure(c, c.pt_T, 3 * nt * 8));
+    unsigned long long *ord = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 3 * 8));
+    HIPSTER_HIP(hipMemsetAsync(ord, 0, 3 * 8, c.stream));
+    hipEvent_t ts = tm.mark();
+    pktab_survey_sweep(c, sd, sd, false, g, cb, 1.0, q->r0, q->n_k, q->k_edges, n_ell_t, n_c, Td, ord);
+    pktab_survey_sweep(c, sd, sr, true, g, cb, -sR, q->r0, q->n_k, q->k_edges, n_ell_t, n_c, Td + nt, ord + 1);
+    pktab_survey_sweep(c, sr, sr, false, g, cb, sR * sR, q->r0, q->n_k, q->k_edges, n_ell_t, n_c, Td + 2 * nt,
+                       ord + 2);
+    hipEvent_t te = tm.mark();
+    std::vector<double> T(3 * nt);
+    unsigned long long oc[3] = {0, 0, 0};
+    HIPSTER_HIP(hipMemcpyAsync(T.data(), Td, T.size() * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipMemcpyAsync(oc, ord, 3 * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    const double nw = p1 / q->volume, norm = 1.0 / (nw * nw * q->volume);
+    for (int li = 0; li < n_ell_t; ++li)
+      for (int a = 0; a < q->n_k; ++a) {
+        const size_t i = size_t(li) * q->n_k + a;
+        const double Sa = (4.0 * li + 1.0) * ((li & 1) ? -1.0 : 1.0) * ((T[i] + T[nt + i]) + T[2 * nt + i]);
+        if (diag && diag->raw) diag->raw[i] = Sa;
+        pk[i] = Sa * norm;
+      }
+    if (diag) {
+      diag->n_pairs = oc[0];
+      diag->n_pairs_rand = oc[1];
+      diag->n_pairs_rr = oc[2];
+      diag->ms_build = Timer::ms(t0, t1);
+      diag->ms_pairs = 0.0;
+      diag->ms_sweep = Timer::ms(ts, te);
+      diag->ms_total = Timer::ms(t0, te);
+      diag->sweep_launches = 3;
+      diag->ms_sweep_far = 0.0;
+      diag->n_pairs_far = 0;
+      diag->eii_nodes = n_c;
+    }
+    return;
+  }
   const bool fp64 = q->precision == HIPSTER_FP64;
   const double r_split = q->k_edges[0] > 0.0 ? HIPSTER_U_BIG / q->k_edges[0] : 0.0;
   const int n_ell = q->ell_max / 2 + 1, n_edges = q->n_k + 1;

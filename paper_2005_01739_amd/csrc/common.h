@@ -220,6 +220,13 @@ size_t ddr2_max_nodes(Ctx &c);
 int pktab_default_nodes(double r0, double k_max);
 void pktab_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, const double *k_edges, int n_l, int los,
                  int n_c, double *T, unsigned long long *ordered);
+// The same for the survey geometry: `a` against `b` (cross: every (a, b) pair
+// once, both orientations counted; else the unordered pairs of a), no
+// periodicity, the pair-midpoint line of sight from the origin, every pair
+// weight times pair_scale; coord_bound bounds every |coordinate|.
+void pktab_survey_sweep(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, double coord_bound,
+                        double pair_scale, double r0, int n_k, const double *k_edges, int n_l, int n_c, double *T,
+                        unsigned long long *ordered);
 // C term of the bispectrum in the mixed form:
 // C^ab_l = sum over ordered pairs (p, q != p) inside R0, p selected by the
 // mask, of w_p w_q^2 W(r/R0)^2 jbar^a_l(r) jbar^b_l(r), from a pair histogram

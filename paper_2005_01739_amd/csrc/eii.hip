@@ -320,9 +320,13 @@ enum HistKind {
 // n_hist: histogram entries.  kHistDdr2: n_keep = n_x, n_hist = n_x + 1;
 // kHistCterm: n_keep = n_hist = n_x + 3 (the table runs past R0); kHistPk:
 // NLP sections (l = 0, 2, ..) of n_keep = n_x + 3 nodes each, n_hist = NLP
-// n_keep, and `los` the line-of-sight axis of mu.  All sum in 64-bit fixed
-// point with scale fix_scale, so the histogram does not depend on the order
-// of the adds (bitwise reproducible).
+// n_keep, `los` the line-of-sight axis of mu (0, 1, 2) or 3 for the pair
+// midpoint seen from an observer at the origin, and every pair's weight
+// times pair_scale.  periodic = 0: no images, neighbour cells outside the
+// grid are empty (the survey geometry).  pref_scale bounds the magnitude of
+// every coordinate (with its image shift), for the prefilter's margin.  All
+// sum in 64-bit fixed point with scale fix_scale, so the histogram does not
+// depend on the order of the adds (bitwise reproducible).
 // The table form with up to three sections: six waves per SIMD (at most 80
 // VGPRs), three 8-wave workgroups per CU, which is what its LDS allows.
 template <bool MASKED, int KIND, bool CROSS, int NLP = 1>
@@ -330,7 +334,8 @@ __global__ __launch_bounds__(kHistThreads) __attribute__((amdgpu_waves_per_eu(KI
 k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
                                                             double inv_h,
                                                             int n_x, int n_keep, int n_hist, double inv_r0,
-                                                            double fix_scale, int los,
+                                                            double fix_scale, int los, int periodic,
+                                                            double pref_scale, double pair_scale,
                                                             const int *__restrict__ unit_cell,
                                                             const int *__restrict__ unit_tile, int64_t n_units,
                                                             unsigned long long *__restrict__ counter,
@@ -361,10 +366,12 @@ k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
   double4 qreg = make_double4(0.0, 0.0, 0.0, 0.0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long below = (1ull << lane) - 1ull;
-  // prefilter bound: (sqrt(lim2) + delta)^2 in single precision, delta = 2^-17 L
-  // covers the rounding of coordinates below 2 L to single precision (each
-  // within 2^-24 of its magnitude) and of the single-precision distance
-  const float lim2f = float((sqrt(lim2) + 0x1p-17 * L) * (sqrt(lim2) + 0x1p-17 * L));
+  // prefilter bound: (sqrt(lim2) + delta)^2 in single precision, delta =
+  // 2^-17 pref_scale covers the rounding of coordinates below pref_scale in
+  // size to single precision (each within 2^-24 of its magnitude) and of the
+  // single-precision distance
+  const float lim2f =
+      float((sqrt(lim2) + 0x1p-17 * pref_scale) * (sqrt(lim2) + 0x1p-17 * pref_scale));
   for (int i = tid; i < n_hist; i += kHistThreads) hist[i] = 0.0;
   unsigned long long ord = 0;
   int qn = 0;  // queued candidates of this wave (uniform over the wave)
@@ -428,26 +435,38 @@ k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
       r2 = (a + b) + c;
     }
     if (r2 < lim2) {
-      const int mi_ = MASKED ? hm[ii] : 1, mj_ = CROSS ? 0 : (MASKED ? (b.m ? int(b.m[j]) : 1) : 1);
+      // the cross sweep of the power spectrum counts both orientations of a
+      // (primary, neighbour) pair; that of the C term only the first
+      const int mi_ = MASKED ? hm[ii] : 1,
+                mj_ = (CROSS && KIND != kHistPk) ? 0 : (MASKED ? (b.m ? int(b.m[j]) : 1) : 1);
       ord += unsigned(mi_ + mj_);
       if (mi_ + mj_ > 0) {
         double wv[NLP];
-        if constexpr (CROSS) {
+        if constexpr (KIND == kHistPk) {
+          // both orientations have the same |mu|, and L_l is even
+          const double r = sqrt(r2);
+          double mu = 0.0;
+          if (los < 3) {
+            const double d = los == 0 ? dx : (los == 1 ? dy : dz);
+            mu = r2 > 0.0 ? d / r : 0.0;
+          } else {
+            // line of sight along the pair midpoint (x_i + x_j) / 2
+            const double mx = p.x + (q.x + offx), my = p.y + (q.y + offy), mz = p.z + (q.z + offz);
+            const double mn = sqrt((mx * mx + my * my) + mz * mz);
+            mu = (r > 0.0 && mn > 0.0) ? ((dx * mx + dy * my) + dz * mz) / (r * mn) : 0.0;
+          }
+          const double m2 = mu * mu;
+          const double base = pair_scale * p.w * q.w * double(mi_ + mj_) * window<double>(r * inv_r0);
+          wv[0] = base;
+          if constexpr (NLP > 1) wv[1] = base * (1.5 * m2 - 0.5);
+          if constexpr (NLP > 2) wv[2] = base * (((35.0 * m2 - 30.0) * m2 + 3.0) * 0.125);
+          if constexpr (NLP > 3) wv[3] = base * ((((231.0 * m2 - 315.0) * m2 + 105.0) * m2 - 5.0) * 0.0625);
+        } else if constexpr (CROSS) {
           // (primary i, neighbour j) only
           const double W = window<double>(sqrt(r2) * inv_r0);
           wv[0] = p.w * q.w * q.w * double(mi_) * (W * W);
         } else if constexpr (KIND == kHistDdr2) {
           wv[0] = p.w * q.w * double(mi_ + mj_);
-        } else if constexpr (KIND == kHistPk) {
-          // both orientations have the same |mu|, and L_l is even
-          const double r = sqrt(r2);
-          const double d = los == 0 ? dx : (los == 1 ? dy : dz);
-          const double mu = r2 > 0.0 ? d / r : 0.0, m2 = mu * mu;
-          const double base = p.w * q.w * double(mi_ + mj_) * window<double>(r * inv_r0);
-          wv[0] = base;
-          if constexpr (NLP > 1) wv[1] = base * (1.5 * m2 - 0.5);
-          if constexpr (NLP > 2) wv[2] = base * (((35.0 * m2 - 30.0) * m2 + 3.0) * 0.125);
-          if constexpr (NLP > 3) wv[3] = base * ((((231.0 * m2 - 315.0) * m2 + 105.0) * m2 - 5.0) * 0.0625);
         } else {
           // (i, j) as (p, q) if i is selected, and (j, i) if j is
           const double W = window<double>(sqrt(r2) * inv_r0);
@@ -506,6 +525,9 @@ k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
         const int zhi = cz + 1;
         int sx = 0, sy = 0;
         int nx = cx + ox, ny = cy + oy;
+        // without periodicity a row outside the grid holds nothing, and only
+        // a row's inside run exists
+        const bool row_out = !periodic && (nx < 0 || nx >= nc || ny < 0 || ny >= nc);
         if (nx >= nc) { nx -= nc; sx = 1; } else if (nx < 0) { nx += nc; sx = -1; }
         if (ny >= nc) { ny -= nc; sy = 1; } else if (ny < 0) { ny += nc; sy = -1; }
         const int64_t rowbase = (int64_t(nx) * nc + ny) * nc;
@@ -513,17 +535,19 @@ k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
         // shifted down) and z = nc (cell 0 shifted up); the inside run
         // [max(zlo, 0), min(zhi, nc - 1)] always holds z = cz
         const int in0 = max(zlo, 0), in1 = min(zhi, nc - 1);
-        const int64_t s_in = b.cell_start[rowbase + in0];
-        const int cnt_in = int(b.cell_start[rowbase + in1 + 1] - s_in);
-        int64_t s_lo = 0, s_hi = 0;
-        int cnt_lo = 0, cnt_hi = 0;
-        if (zlo < 0) {
-          s_lo = b.cell_start[rowbase + nc - 1];
-          cnt_lo = int(b.cell_start[rowbase + nc] - s_lo);
-        }
-        if (zhi >= nc) {
-          s_hi = b.cell_start[rowbase];
-          cnt_hi = int(b.cell_start[rowbase + 1] - s_hi);
+        int64_t s_in = 0, s_lo = 0, s_hi = 0;
+        int cnt_in = 0, cnt_lo = 0, cnt_hi = 0;
+        if (!row_out) {
+          s_in = b.cell_start[rowbase + in0];
+          cnt_in = int(b.cell_start[rowbase + in1 + 1] - s_in);
+          if (periodic && zlo < 0) {
+            s_lo = b.cell_start[rowbase + nc - 1];
+            cnt_lo = int(b.cell_start[rowbase + nc] - s_lo);
+          }
+          if (periodic && zhi >= nc) {
+            s_hi = b.cell_start[rowbase];
+            cnt_hi = int(b.cell_start[rowbase + 1] - s_hi);
+          }
         }
         const bool self_row = !CROSS && lane == 0;
         const int r = 3 * lane;
@@ -756,12 +780,12 @@ static void hist_sweep(Ctx &c, const Sorted &s, const Sorted &b, const Grid &g, 
   if (u.n > 0) {
     if (s.m || (!CROSS && b.m))
       k_ddr2_hist<true, KIND, CROSS><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
-          s, b, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, 0, u.cell, u.tile, u.n, counter,
-          ordered, partial);
+          s, b, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, 0, 1, g.L, 1.0, u.cell, u.tile, u.n,
+          counter, ordered, partial);
     else
       k_ddr2_hist<false, KIND, CROSS><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
-          s, b, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, 0, u.cell, u.tile, u.n, counter,
-          ordered, partial);
+          s, b, g.nc, g.L, lim2, inv_h, n_x, n_keep, n_hist, inv_r0, fix_scale, 0, 1, g.L, 1.0, u.cell, u.tile, u.n,
+          counter, ordered, partial);
     HIPSTER_HIP(hipGetLastError());
   } else {
     HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_hist * 8, c.stream));
@@ -924,28 +948,81 @@ int pktab_default_nodes(double r0, double k_max) {
   return std::max(64, int(ceil(want / 64.0) * 64.0));
 }
 
-template <bool MASKED, int NLP>
-static void launch_pktab(Ctx &c, const Sorted &s, const Grid &g, const PairUnits &u, double lim2, double inv_h,
-                         int n_c, int n_nodes, double inv_r0, double fix_scale, int los,
-                         unsigned long long *counter, unsigned long long *ordered, double *partial, int nwg) {
+struct PkTabSweep {
+  const Sorted *s, *b;  // primaries and neighbours (b == s unless cross)
+  bool cross, periodic;
+  int los;               // 0, 1, 2: axis; 3: pair midpoint from the origin
+  double pair_scale;     // signed factor of every pair weight
+  double pref_scale;     // bound on |coordinate| (with image shift)
+};
+
+template <bool MASKED, bool CROSS, int NLP>
+static void launch_pktab(Ctx &c, const PkTabSweep &z, const Grid &g, const PairUnits &u, double lim2, double inv_h,
+                         int n_c, int n_nodes, double inv_r0, double fix_scale, unsigned long long *counter,
+                         unsigned long long *ordered, double *partial, int nwg) {
   const size_t lds = size_t(NLP) * n_nodes * 8;
-  k_ddr2_hist<MASKED, kHistPk, false, NLP><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
-      s, s, g.nc, g.L, lim2, inv_h, n_c, n_nodes, NLP * n_nodes, inv_r0, fix_scale, los, u.cell, u.tile, u.n, counter,
-      ordered, partial);
+  k_ddr2_hist<MASKED, kHistPk, CROSS, NLP><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
+      *z.s, *z.b, g.nc, g.L, lim2, inv_h, n_c, n_nodes, NLP * n_nodes, inv_r0, fix_scale, z.los, z.periodic ? 1 : 0,
+      z.pref_scale, z.pair_scale, u.cell, u.tile, u.n, counter, ordered, partial);
   HIPSTER_HIP(hipGetLastError());
 }
 
-template <int NLP>
+// Upper bound of the ordered pair terms of a sweep of `a` against `b`: twice
+// the candidate pairs, the sum over cells of n_a times the points of b in its
+// stencil (27 cells when cross, else the 14 of the half stencil), without
+// the cells outside the grid when not periodic.
+__global__ void k_candidate_bound_ab(const int64_t *__restrict__ cs_a, const int64_t *__restrict__ cs_b, int nc,
+                                     int cross, int periodic, unsigned long long *__restrict__ out) {
+  const int64_t ncell = int64_t(nc) * nc * nc;
+  unsigned long long acc = 0;
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < ncell; c += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t n = cs_a[c + 1] - cs_a[c];
+    if (n == 0) continue;
+    const int cz = int(c % nc), cy = int((c / nc) % nc), cx = int(c / (int64_t(nc) * nc));
+    int64_t m = 0;
+    for (int t = cross ? 0 : 13; t < 27; ++t) {
+      int nx = cx + t / 9 - 1, ny = cy + (t / 3) % 3 - 1, nz = cz + t % 3 - 1;
+      if (!periodic && (nx < 0 || nx >= nc || ny < 0 || ny >= nc || nz < 0 || nz >= nc)) continue;
+      nx = (nx + nc) % nc;
+      ny = (ny + nc) % nc;
+      nz = (nz + nc) % nc;
+      const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
+      m += cs_b[nb + 1] - cs_b[nb];
+    }
+    acc += static_cast<unsigned long long>(2 * n * m);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+}
+
+template <bool CROSS, int NLP>
 static int pktab_blocks_per_cu(int n_nodes) {
   int per = 0;
   HIPSTER_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per, reinterpret_cast<const void *>(&k_ddr2_hist<false, kHistPk, false, NLP>), kHistThreads,
+      &per, reinterpret_cast<const void *>(&k_ddr2_hist<false, kHistPk, CROSS, NLP>), kHistThreads,
       size_t(NLP) * n_nodes * 8));
   return std::max(1, per);
 }
 
+static void pktab_sweep_one(Ctx &c, const PkTabSweep &z, const Grid &g, double r0, int n_k, const double *k_edges,
+                            int n_l, int n_c, double *T, unsigned long long *ordered);
+
 void pktab_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, const double *k_edges, int n_l, int los,
                  int n_c, double *T, unsigned long long *ordered) {
+  const PkTabSweep z{&s, &s, false, true, los, 1.0, g.L};
+  pktab_sweep_one(c, z, g, r0, n_k, k_edges, n_l, n_c, T, ordered);
+}
+
+void pktab_survey_sweep(Ctx &c, const Sorted &a, const Sorted &b, bool cross, const Grid &g, double coord_bound,
+                        double pair_scale, double r0, int n_k, const double *k_edges, int n_l, int n_c, double *T,
+                        unsigned long long *ordered) {
+  const PkTabSweep z{&a, &b, cross, false, 3, pair_scale, coord_bound};
+  pktab_sweep_one(c, z, g, r0, n_k, k_edges, n_l, n_c, T, ordered);
+}
+
+static void pktab_sweep_one(Ctx &c, const PkTabSweep &z, const Grid &g, double r0, int n_k, const double *k_edges,
+                            int n_l, int n_c, double *T, unsigned long long *ordered) {
+  const Sorted &s = *z.s;
   const int n_nodes = n_c + 3, rows = n_l * n_k;
   if (size_t(n_l) * n_nodes > ddr2_max_nodes(c))
     throw Error{HIPSTER_EUNSUPPORTED, "table form: k_max R0 too large for the LDS histogram; use HIPSTER_MIXED"};
@@ -973,24 +1050,25 @@ void pktab_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, con
     c.pt_key = key;
   }
   // fixed-point scale from the candidate bound: every node's sum of
-  // |w_i w_j W L_l l_q(t)| is at most (ordered candidates) * w_max^2 * 2.5
+  // |s w_i w_j W L_l l_q(t)| is at most (ordered candidates) * |s| w_a w_b * 2.5
   // (|W|, |L_l| <= 1; a node takes at most two basis values of a pair, each
-  // below 1.25 in size), kept below 2^61; and one add, at most 2 w_max^2
+  // below 1.25 in size), kept below 2^61; and one add, at most 2 |s| w_a w_b
   // 1.25 (both orientations), below 2^30.  The unit of the sums is then at
   // most 2^-29 of the largest add, so the rounding stays below ~2e-9 of the
   // bin's L1 mass
   unsigned long long *cb = static_cast<unsigned long long *>(ensure(c, c.ct_wmax, 8));
   HIPSTER_HIP(hipMemsetAsync(cb, 0, 8, c.stream));
   const int64_t ncell = g.ncells();
-  k_candidate_bound<<<dim3(unsigned(std::min<int64_t>((ncell + 255) / 256, 1024))), dim3(256), 0, c.stream>>>(
-      s.cell_start, g.nc, cb);
+  k_candidate_bound_ab<<<dim3(unsigned(std::min<int64_t>((ncell + 255) / 256, 1024))), dim3(256), 0, c.stream>>>(
+      s.cell_start, z.b->cell_start, g.nc, z.cross ? 1 : 0, z.periodic ? 1 : 0, cb);
   HIPSTER_HIP(hipGetLastError());
   unsigned long long cand = 0;
   HIPSTER_HIP(hipMemcpyAsync(&cand, cb, 8, hipMemcpyDeviceToHost, c.stream));
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
-  const double wm = weight_max(c, s);
-  const double bound = (double(cand) + 1.0) * 2.5 * std::max(wm * wm, 1e-300);
-  const double one_add = 2.5 * std::max(wm * wm, 1e-300);
+  const double wa = weight_max(c, s), wb = z.cross ? weight_max(c, *z.b) : wa;
+  const double wab = std::max(fabs(z.pair_scale) * wa * wb, 1e-300);
+  const double bound = (double(cand) + 1.0) * 2.5 * wab;
+  const double one_add = 2.5 * wab;
   const int e = std::min(61 - int(ceil(log2(bound))), 30 - int(ceil(log2(one_add))));
   const double fix_scale = ldexp(1.0, e);
 
@@ -999,10 +1077,10 @@ void pktab_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, con
   HIPSTER_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
   int per = 1;
   switch (n_l) {
-    case 1: per = pktab_blocks_per_cu<1>(n_nodes); break;
-    case 2: per = pktab_blocks_per_cu<2>(n_nodes); break;
-    case 3: per = pktab_blocks_per_cu<3>(n_nodes); break;
-    default: per = pktab_blocks_per_cu<4>(n_nodes); break;
+    case 1: per = z.cross ? pktab_blocks_per_cu<true, 1>(n_nodes) : pktab_blocks_per_cu<false, 1>(n_nodes); break;
+    case 2: per = z.cross ? pktab_blocks_per_cu<true, 2>(n_nodes) : pktab_blocks_per_cu<false, 2>(n_nodes); break;
+    case 3: per = z.cross ? pktab_blocks_per_cu<true, 3>(n_nodes) : pktab_blocks_per_cu<false, 3>(n_nodes); break;
+    default: per = z.cross ? pktab_blocks_per_cu<true, 4>(n_nodes) : pktab_blocks_per_cu<false, 4>(n_nodes); break;
   }
   const int nwg = std::max(1, cus) * per;
   const int n_hist = n_l * n_nodes;
@@ -1012,15 +1090,25 @@ void pktab_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_k, con
   HIPSTER_HIP(hipMemsetAsync(counter, 0, 8, c.stream));
   const double lim2 = r0 * r0, inv_h = 1.0 / h, inv_r0 = 1.0 / r0;
   if (u.n > 0) {
-    const bool masked = s.m != nullptr;
-#define HIPSTER_PKTAB(M, N)                                                                                          \
-  launch_pktab<M, N>(c, s, g, u, lim2, inv_h, n_c, n_nodes, inv_r0, fix_scale, los, counter, ordered, partial, nwg)
+    const bool masked = s.m != nullptr || z.b->m != nullptr;
+#define HIPSTER_PKTAB(M, X, N)                                                                                       \
+  launch_pktab<M, X, N>(c, z, g, u, lim2, inv_h, n_c, n_nodes, inv_r0, fix_scale, counter, ordered, partial, nwg)
+#define HIPSTER_PKTAB_M(X, N)                                                                                        \
+  do {                                                                                                               \
+    if (masked) HIPSTER_PKTAB(true, X, N); else HIPSTER_PKTAB(false, X, N);                                          \
+  } while (0)
+#define HIPSTER_PKTAB_XM(N)                                                                                          \
+  do {                                                                                                               \
+    if (z.cross) HIPSTER_PKTAB_M(true, N); else HIPSTER_PKTAB_M(false, N);                                           \
+  } while (0)
     switch (n_l) {
-      case 1: if (masked) HIPSTER_PKTAB(true, 1); else HIPSTER_PKTAB(false, 1); break;
-      case 2: if (masked) HIPSTER_PKTAB(true, 2); else HIPSTER_PKTAB(false, 2); break;
-      case 3: if (masked) HIPSTER_PKTAB(true, 3); else HIPSTER_PKTAB(false, 3); break;
-      default: if (masked) HIPSTER_PKTAB(true, 4); else HIPSTER_PKTAB(false, 4); break;
+      case 1: HIPSTER_PKTAB_XM(1); break;
+      case 2: HIPSTER_PKTAB_XM(2); break;
+      case 3: HIPSTER_PKTAB_XM(3); break;
+      default: HIPSTER_PKTAB_XM(4); break;
     }
+#undef HIPSTER_PKTAB_XM
+#undef HIPSTER_PKTAB_M
 #undef HIPSTER_PKTAB
   } else {
     HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_hist * 8, c.stream));

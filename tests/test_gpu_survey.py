@@ -1,6 +1,7 @@
 """GPU parity of the survey-geometry power spectrum (DD - 2DR + RR, pair-midpoint
 line of sight, no periodicity; C ABI via the binding) against the FP64
-oracle.  The ordered DD, DR + RD and RR pair counts must match exactly.  Per
+oracle, in the FP64, mixed and table forms (the table form to the mixed
+form's bound).  The ordered DD, DR + RD and RR pair counts must match exactly.  Per
 bin the FP64 form must agree to 1e-12 relative and the mixed form to 1e-6
 relative, or, for a bin dominated by cancellation (DD - 2DR + RR nearly
 cancels), meet |err| / L1 <= 1e-14 (FP64) or 2^-24 (mixed), with L1 the sum of
@@ -13,7 +14,7 @@ import synthetic
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-14), "mixed": (1e-6, 2.0 ** -24)}
+TOL = {"fp64": (1e-12, 1e-14), "mixed": (1e-6, 2.0 ** -24), "table": (1e-6, 2.0 ** -24)}
 
 
 def check(got, ref, l1, precision, what=""):
@@ -53,7 +54,7 @@ def _region(n, lo, side, seed, dtype=np.float32, thomas=True):
     return np.ascontiguousarray((x + np.asarray(lo)).astype(dtype))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "table"])
 def test_wide_angle_region(precision):
     # A region close to the observer, so the line of sight turns by tens of
     # degrees across it; 40 log bins, l = 0, 2, 4.
@@ -63,7 +64,7 @@ def test_wide_angle_region(precision):
     run_case(pos, None, rnd, None, 200.0 ** 3, 20.0, np.geomspace(0.5, 8.0, 41), 4, precision)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "table"])
 def test_weighted_masked_host_input_l6(precision):
     lo = [30.0, -80.0, -60.0]
     pos = _region(2000, lo, 150.0, 13)
@@ -84,7 +85,7 @@ def test_observer_inside_region_and_symmetric_pairs():
     half = rng.uniform(-6.0, 6.0, (150, 3))
     pos = np.concatenate([half, -half, rng.uniform(-60.0, 60.0, (1500, 3)), half[:20]])
     rnd = rng.uniform(-60.0, 60.0, (4000, 3))
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "table"):
         run_case(pos, None, rnd, None, 120.0 ** 3, 15.0, np.linspace(0.0, 2.0, 11), 4, prec)
 
 
@@ -120,3 +121,38 @@ def test_deterministic_bitwise():
     a = hp.pk_survey(p, None, r, volume=s.volume, r0=s.r0, k_edges=s.k_edges)
     b = hp.pk_survey(p, None, r, volume=s.volume, r0=s.r0, k_edges=s.k_edges)
     assert np.array_equal(a, b)
+
+
+def test_table_form_far_region():
+    # a region far from the observer (coordinates ~2000 Mpc/h, so the
+    # single-precision prefilter works at 16 times the region's size)
+    lo = [1800.0, 1500.0, 900.0]
+    pos = _region(3000, lo, 150.0, 21, np.float64)
+    rnd = _region(9000, lo, 150.0, 22, np.float64, thomas=False)
+    run_case(pos, None, rnd, None, 150.0 ** 3, 15.0, np.geomspace(1.0, 10.0, 31), 4, "table")
+
+
+def test_table_form_full_size_against_fp64():
+    # the 1e6-point survey workload and its 3e6 randoms: a subset of
+    # primaries against the oracle, and every bin of the whole call against
+    # the FP64 form (pair counts equal, 1e-6 relative); repeated calls give
+    # the same bits
+    import torch
+    import paper_2005_01739_amd as hp
+    s = synthetic.survey()
+    rng = np.random.default_rng(20)
+    mask = np.zeros(s.n, np.uint8)
+    mask[rng.choice(s.n, 64, replace=False)] = 1
+    rmask = np.zeros(len(s.randoms), np.uint8)
+    rmask[rng.choice(len(s.randoms), 64, replace=False)] = 1
+    run_case(s.pos, None, s.randoms, None, s.volume, s.r0, s.k_edges, s.ell_max, "table", mask, rmask)
+    p, r = torch.from_numpy(s.pos).cuda(), torch.from_numpy(s.randoms).cuda()
+    kw = dict(volume=s.volume, r0=s.r0, k_edges=s.k_edges, ell_max=s.ell_max, return_diag=True)
+    t, it = hp.pk_survey(p, None, r, precision="table", **kw)
+    t2, _ = hp.pk_survey(p, None, r, precision="table", **kw)
+    f, i64 = hp.pk_survey(p, None, r, precision="fp64", **kw)
+    assert (it["n_pairs"], it["n_pairs_rand"], it["n_pairs_rr"]) == (i64["n_pairs"], i64["n_pairs_rand"],
+                                                                     i64["n_pairs_rr"])
+    assert np.array_equal(t, t2)
+    rel = np.abs(t - f) / np.abs(f)
+    assert rel.max() <= 1e-6, rel.max()
