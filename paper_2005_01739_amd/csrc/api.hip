@@ -92,7 +92,7 @@ static void check_params(const hipster_params *q, bool bispectrum, bool allow_ta
   if (!bispectrum && (q->ell_max & 1)) throw Error{HIPSTER_EDOMAIN, "power spectrum: ell_max must be even"};
   if (!bispectrum && (q->los_axis < 0 || q->los_axis > 2)) throw Error{HIPSTER_EINVAL, "los_axis must be 0, 1 or 2"};
   if (q->precision == HIPSTER_TABLE && !allow_table)
-    throw Error{HIPSTER_EUNSUPPORTED, "HIPSTER_TABLE is available for the power spectra only"};
+    throw Error{HIPSTER_EUNSUPPORTED, "HIPSTER_TABLE is available for hipster_pk_ell and hipster_pk_survey only"};
   if (q->precision != HIPSTER_MIXED && q->precision != HIPSTER_FP64 && q->precision != HIPSTER_TABLE)
     throw Error{HIPSTER_EINVAL, "bad precision"};
   // the mixed form's table-driven sine and cosine reduce u = k r exactly only
