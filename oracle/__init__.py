@@ -89,6 +89,9 @@ def lib():
         L.oracle_cov_poisson2.restype = ct.c_int
         L.oracle_cov_poisson2.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_int, _dp, ct.c_int, ct.c_int,
                                           _dp, _dp, _dp, _dp]
+        L.oracle_cov_nongauss.restype = ct.c_int
+        L.oracle_cov_nongauss.argtypes = [ct.c_double, ct.c_double, ct.c_int, _dp, ct.c_int, ct.c_int, _dp, _dp, _dp,
+                                          _dp, ct.c_int]
         L.oracle_cov_poisson3.restype = ct.c_int
         L.oracle_cov_poisson3.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_int, _dp, ct.c_int, ct.c_int,
                                           _dp, _dp, _dp, _dp, _dp, _dp, ct.c_int]
@@ -338,6 +341,21 @@ def cov_gauss(r0, volume, k_edges, ell_max, p, wp, pk, nthreads=0):
     if lib().oracle_cov_gauss(float(r0), float(volume), n_k, _ptr(k), int(ell_max), p.size, _ptr(p), _ptr(wp),
                               _ptr(pk), _ptr(out), int(nthreads)) != 0:
         raise ValueError("oracle_cov_gauss: argument outside the oracle's range")
+    return out
+
+
+def cov_nongauss(r0, volume, k_edges, ell_max, p, wp, tbar, nthreads=0):
+    """Non-Gaussian intrinsic covariance term on the p quadrature (p, wp) with
+    collapsed-trispectrum multipoles tbar [n_ell, n_ell, n_p, n_p]:
+    [n_ell, n_k, n_ell, n_k]."""
+    k = _f64(k_edges)
+    p, wp = _f64(p), _f64(wp)
+    n_ell, n_k = ell_max // 2 + 1, k.size - 1
+    tb = _f64(tbar).reshape(n_ell, n_ell, p.size, p.size)
+    out = np.zeros((n_ell, n_k, n_ell, n_k))
+    if lib().oracle_cov_nongauss(float(r0), float(volume), n_k, _ptr(k), int(ell_max), p.size, _ptr(p), _ptr(wp),
+                                 _ptr(tb), _ptr(out), int(nthreads)) != 0:
+        raise ValueError("oracle_cov_nongauss: argument outside the oracle's range")
     return out
 
 

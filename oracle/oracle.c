@@ -44,6 +44,9 @@
  * their xi and P_L parts by direct angular quadrature and Parseval's relation.
  * The bispectrum term of 3C is added as printed: only the symmetry of the
  * result under (l, a) <-> (l', b) pins it (parity unpinned for that term).
+ * The non-Gaussian term (oracle_cov_nongauss) is pinned by its reduction to
+ * the (pinned) Gaussian term for a trispectrum diagonal on the quadrature
+ * grid, and by its symmetry.
  */
 #include <complex.h>
 #include <math.h>
@@ -1251,3 +1254,45 @@ int oracle_cov_poisson3(double r0, double nbar, double volume, int n_k, const do
     free(om);
     return 0;
 }
+
+/* Non-Gaussian intrinsic covariance of the binned multipoles (Sec. 6, the
+ * 4C^NG term), even l, l' <= ell_max:
+ *   C^ab_ll' = (2l+1)(2l'+1)/V (-1)^(l+l') sum_i sum_j u_i u_j T_ll'(p_i, p_j)
+ *              omega^a_l(p_i) omega^b_l'(p_j),   u_i = wp[i] p_i^2 / (2 pi^2),
+ * the double p integral as the caller's quadrature (nodes p[i], weights
+ * wp[i]) and tbar [n_ell][n_ell][n_p][n_p] the collapsed-trispectrum
+ * multipoles T_ll'(p_i, p_j).  out [n_ell][n_k][n_ell][n_k]. */
+int oracle_cov_nongauss(double r0, double volume, int n_k, const double *k, int ell_max, int n_p, const double *p,
+                        const double *wp, const double *tbar, double *out, int nthreads)
+{
+    if (!(r0 > 0.0) || !(volume > 0.0) || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 ||
+        ell_max > ORACLE_ELL_MAX || (ell_max & 1) || n_p < 1)
+        return -1;
+    const int n_ell = ell_max / 2 + 1, nt = nthreads_or_default(nthreads);
+    double *om = malloc(sizeof(double) * (size_t)n_p * n_ell * n_k);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+    for (int i = 0; i < n_p; ++i)
+        for (int li = 0; li < n_ell; ++li) oracle_omega(p[i], r0, 2 * li, n_k, k, om + ((size_t)i * n_ell + li) * n_k);
+    for (int li = 0; li < n_ell; ++li)
+        for (int lj = 0; lj < n_ell; ++lj) {
+            const int l = 2 * li, lp = 2 * lj;
+            const double pref = (2.0 * l + 1.0) * (2.0 * lp + 1.0) / volume * (((l + lp) & 1) ? -1.0 : 1.0);
+            const double *T = tbar + ((size_t)li * n_ell + lj) * n_p * n_p;
+            for (int a = 0; a < n_k; ++a)
+                for (int b = 0; b < n_k; ++b) {
+                    double s = 0.0;
+                    for (int i = 0; i < n_p; ++i) {
+                        const double ui = wp[i] * p[i] * p[i] / (2.0 * PI * PI);
+                        for (int j = 0; j < n_p; ++j) {
+                            const double uj = wp[j] * p[j] * p[j] / (2.0 * PI * PI);
+                            s += ui * uj * T[(size_t)i * n_p + j] * om[((size_t)i * n_ell + li) * n_k + a] *
+                                 om[((size_t)j * n_ell + lj) * n_k + b];
+                        }
+                    }
+                    out[(((size_t)li * n_k + a) * n_ell + lj) * n_k + b] = pref * s;
+                }
+        }
+    free(om);
+    return 0;
+}
+

@@ -272,3 +272,42 @@ def test_poisson3_mean_fluctuation_terms():
     T = CB.transpose(2, 3, 0, 1)
     assert np.allclose(CB, T, rtol=1e-14, atol=0)
     assert not np.allclose(CB, C)
+
+
+def test_nongauss_reduces_to_gaussian_for_diagonal_trispectrum():
+    # with T_ll'(p_i, p_j) = delta_ij 2 Q_ll'(p_i) / u_i, u_i = w_i p_i^2/(2 pi^2),
+    # the double sum collapses onto the single sum of the Gaussian term:
+    # 4C^NG = 2 (2l+1)(2l'+1)/V sum_i u_i Q_ll'(p_i) omega omega = 4C^G, with
+    # Q_ll' the direct angular integral (1/2) int dmu L_l L_l' P(p, mu)^2
+    V = 1e6
+    p, w = _p_quadrature(4.0, panels=6, n=8)
+    pk = np.array([300.0 / (1 + (p / 0.2) ** 2), -80.0 / (1 + (p / 0.3) ** 2), 25.0 / (1 + (p / 0.4) ** 2)])
+    mu, wmu = np.polynomial.legendre.leggauss(24)
+    Pmu = sum(pk[m][:, None] * eval_legendre(2 * m, mu)[None, :] for m in range(3))  # [n_p, n_mu]
+    u = w * p * p / (2 * np.pi ** 2)
+    T = np.zeros((3, 3, p.size, p.size))
+    for li in range(3):
+        for lj in range(3):
+            Q = 0.5 * np.sum(wmu * eval_legendre(2 * li, mu) * eval_legendre(2 * lj, mu) * Pmu ** 2, axis=1)
+            T[li, lj] = np.diag(2.0 * Q / u)
+    ng = oracle.cov_nongauss(R0, V, K, 4, p, w, T)
+    g = oracle.cov_gauss(R0, V, K, 4, p, w, pk)
+    assert np.allclose(ng, g, rtol=1e-11, atol=1e-13 * np.abs(g).max())
+
+
+def test_nongauss_symmetry_and_separable_trispectrum():
+    # T_ll'(p1, p2) = T_l'l(p2, p1) makes C^ab_ll' = C^ba_l'l; a separable
+    # T_ll' = f_l(p1) f_l'(p2) factorises the double sum into two single sums
+    V = 5e5
+    p, w = _p_quadrature(3.0, panels=4, n=8)
+    f = np.array([np.exp(-p), 0.5 * p * np.exp(-p / 2), 0.1 / (1 + p * p)])
+    T = np.einsum("li,mj->lmij", f, f)
+    C = oracle.cov_nongauss(R0, V, K, 4, p, w, T)
+    assert np.allclose(C, C.transpose(2, 3, 0, 1), rtol=1e-12, atol=0)
+    u = w * p * p / (2 * np.pi ** 2)
+    om = np.array([[oracle.omega(pi, R0, 2 * li, K) for pi in p] for li in range(3)])  # [l, i, a]
+    v = np.einsum("i,li,lia->la", u, f, om)
+    for li in range(3):
+        for lj in range(3):
+            ref = (4 * li + 1) * (4 * lj + 1) / V * np.outer(v[li], v[lj])
+            assert np.allclose(C[li, :, lj, :], ref, rtol=1e-11, atol=1e-14 * np.abs(ref).max())
