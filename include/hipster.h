@@ -229,6 +229,18 @@ hipster_status hipster_cov_gauss(hipster_ctx *ctx, double r0, double volume, int
                                  int32_t ell_max, int32_t n_p, const double *p, const double *wp, const double *pk,
                                  double *out);
 
+/* Non-Gaussian intrinsic covariance of the binned windowed multipoles (Sec. 6,
+ * the 4C^NG term), even l, l' <= ell_max:
+ *   C^ab_ll' = (2l+1)(2l'+1)/V (-1)^(l+l') int p1^2 dp1/(2 pi^2) p2^2 dp2/(2 pi^2)
+ *              Tbar_ll'(p1, p2) omega^a_l(p1) omega^b_l'(p2),
+ * both p integrals as sums over the caller's nodes p[i] with weights wp[i];
+ * tbar [ell_max/2+1][ell_max/2+1][n_p][n_p] holds the collapsed-trispectrum
+ * multipoles Tbar_ll'(p[i], p[j]) (higher multipoles taken as zero); volume
+ * V.  out: as hipster_cov_gauss.  Errors as hipster_cov_gauss. */
+hipster_status hipster_cov_nongauss(hipster_ctx *ctx, double r0, double volume, int32_t n_k, const double *k_edges,
+                                    int32_t ell_max, int32_t n_p, const double *p, const double *wp,
+                                    const double *tbar, double *out);
+
 /* Poisson two-point covariance term of the binned windowed multipoles (Sec. 6,
  * eq. cov-poiss, the 2C term), even l, l' <= ell_max:
  *   C^ab_ll' = 2/(n^2 V) (2l+1)(2l'+1) (-i)^(l+l') 4 pi int x^2 W^2 jbar^a_l jbar^b_l'

@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = ["Context", "wtilde", "pk_ell", "bk_ell", "batch", "HipsterError", "library_path", "load_library",
            "EXPORTED_SYMBOLS", "MIXED", "FP64", "TABLE", "pk_survey", "bk_ell_analytic", "eii_table",
-           "omega", "pk_window_theory", "cov_gauss", "cov_poisson2", "cov_poisson3"]
+           "omega", "pk_window_theory", "cov_gauss", "cov_poisson2", "cov_poisson3", "cov_nongauss"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 MIXED, FP64, TABLE = 0, 1, 2
@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = ("hipster_create", "hipster_destroy", "hipster_pk_ell", "hips
                     "hipster_set_memory_cap", "hipster_wtilde", "hipster_pk_survey",
                     "hipster_bk_ell_analytic", "hipster_eii_table", "hipster_omega",
                     "hipster_pk_window_theory", "hipster_cov_gauss", "hipster_cov_poisson2",
-                    "hipster_cov_poisson3")
+                    "hipster_cov_poisson3", "hipster_cov_nongauss")
 
 
 class HipsterError(RuntimeError):
@@ -125,6 +125,9 @@ def load_library():
     L.hipster_cov_poisson3.restype = ct.c_int
     L.hipster_cov_poisson3.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, ct.c_double, ct.c_int32, _dp, ct.c_int32,
                                        ct.c_int32, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.hipster_cov_nongauss.restype = ct.c_int
+    L.hipster_cov_nongauss.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, ct.c_int32, _dp, ct.c_int32, ct.c_int32,
+                                       _dp, _dp, _dp, _dp]
     L.hipster_batch.restype = ct.c_int
     L.hipster_batch.argtypes = [ct.c_void_p, ct.c_int, ct.POINTER(_BoxJob), ct.POINTER(_Diag)]
     L.hipster_last_error.restype = ct.c_char_p
@@ -481,6 +484,22 @@ def cov_poisson3(r0: float, nbar: float, volume: float, k_edges, ell_max: int, p
     c.check(L.hipster_cov_poisson3(c.handle, float(r0), float(nbar), float(volume), n_k, _ptr(k), int(ell_max),
                                    p.size, _ptr(p), _ptr(wp), _ptr(pk), None if pb is None else _ptr(pb),
                                    None if bb is None else _ptr(bb), _ptr(out)))
+    return out
+
+
+def cov_nongauss(r0: float, volume: float, k_edges, ell_max: int, p, wp, tbar, *,
+                 ctx: Context | None = None) -> np.ndarray:
+    """Non-Gaussian intrinsic covariance term (even ell) on the p quadrature
+    (p, wp) with collapsed-trispectrum multipoles tbar (n_ell, n_ell, len(p),
+    len(p)): (n_ell, n_k, n_ell, n_k)."""
+    L = load_library()
+    k, p, wp = _host_f64(k_edges), _host_f64(p), _host_f64(wp)
+    n_ell, n_k = ell_max // 2 + 1, k.size - 1
+    tb = _host_f64(tbar).reshape(n_ell, n_ell, p.size, p.size)
+    out = np.zeros((n_ell, n_k, n_ell, n_k))
+    c = ctx or _context_for(None)
+    c.check(L.hipster_cov_nongauss(c.handle, float(r0), float(volume), n_k, _ptr(k), int(ell_max), p.size, _ptr(p),
+                                   _ptr(wp), _ptr(tb), _ptr(out)))
     return out
 
 

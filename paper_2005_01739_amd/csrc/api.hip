@@ -1155,7 +1155,8 @@ void hipster_destroy(hipster_ctx *ctx) {
                    &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile, &c.eii_consts,
                    &c.ddr2_partial, &c.ddr2_hist, &c.ddr2_counter, &c.ddr2_T, &c.ct_tab, &c.ct_consts, &c.ct_C,
                    &c.ct_wmax, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
-                   &c.th_K, &c.th_out, &c.th_wt, &c.th_pb, &c.th_bk, &c.pt_tab, &c.pt_consts, &c.pt_T,
+                   &c.th_K, &c.th_out, &c.th_wt, &c.th_pb, &c.th_bk, &c.th_T, &c.th_X, &c.pt_tab, &c.pt_consts,
+                   &c.pt_T,
                    &c.tune_scratch};
   for (DevBuf *b : all) free_buf(*b);
   for (EiiEntry &e : c.eii_cache) free_buf(e.buf);
@@ -1291,6 +1292,28 @@ hipster_status hipster_cov_poisson3(hipster_ctx *ctx, double r0, double nbar, do
     const size_t nout = size_t(n_l) * n_k * n_l * n_k;
     double *od = static_cast<double *>(ensure(c, c.th_out, nout * 8));
     theory_c3(c, r0, nbar, volume, n_k, k_edges, n_l, n_p, p, wp, pk, wt.data(), pbin, bk, od);
+    HIPSTER_HIP(hipMemcpyAsync(out, od, nout * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+hipster_status hipster_cov_nongauss(hipster_ctx *ctx, double r0, double volume, int32_t n_k, const double *k_edges,
+                                    int32_t ell_max, int32_t n_p, const double *p, const double *wp,
+                                    const double *tbar, double *out) {
+  return guarded(ctx, [&] {
+    Ctx &c = ctx->c;
+    check_theory(r0, n_k, k_edges, ell_max, true);
+    if (!p || !wp || !tbar || !out) throw Error{HIPSTER_EINVAL, "NULL argument"};
+    if (n_p < 1) throw Error{HIPSTER_EINVAL, "n_p must be >= 1"};
+    if (!(volume > 0.0) || !isfinite(volume)) throw Error{HIPSTER_EDOMAIN, "volume must be finite and positive"};
+    for (int i = 0; i < n_p; ++i)
+      if (!(p[i] >= 0.0) || !isfinite(p[i])) throw Error{HIPSTER_EDOMAIN, "p must be finite and >= 0"};
+    theory_phase_check(r0, n_k, k_edges, n_p, p);
+    HIPSTER_HIP(hipSetDevice(c.device));
+    const int n_l = ell_max / 2 + 1;
+    const size_t nout = size_t(n_l) * n_k * n_l * n_k;
+    double *od = static_cast<double *>(ensure(c, c.th_out, nout * 8));
+    theory_ng(c, r0, volume, n_k, k_edges, n_l, n_p, p, wp, tbar, od);
     HIPSTER_HIP(hipMemcpyAsync(out, od, nout * 8, hipMemcpyDeviceToHost, c.stream));
     HIPSTER_HIP(hipStreamSynchronize(c.stream));
   });

@@ -124,7 +124,7 @@ struct Ctx {
   DevBuf eii_consts, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T, ct_tab, ct_consts, ct_C, ct_wmax;
   DevBuf pt_tab, pt_consts, pt_T;  // power spectrum, table form
   std::vector<double> pt_key;      // (R0, n_k, n_l, n_c, edges) of the table in pt_tab
-  DevBuf th_r, th_w, th_p, th_wp, th_pk, th_ek, th_g, th_J, th_om, th_K, th_out, th_wt, th_pb, th_bk;
+  DevBuf th_r, th_w, th_p, th_wp, th_pk, th_ek, th_g, th_J, th_om, th_K, th_out, th_wt, th_pb, th_bk, th_T, th_X;
   // E^II tables on the device, keyed by (R0, n_x, ell_max, edges).
   std::vector<EiiEntry> eii_cache;
   uint64_t eii_clock = 0;
@@ -256,6 +256,10 @@ void theory_cov(Ctx &c, double r0, double volume, int n_k, const double *k_edges
 // quadrature with model multipoles xi[L/2][m] (even L < 2 n_l).
 void theory_c2(Ctx &c, double r0, double nbar, double volume, int n_k, const double *k_edges, int n_l, int n_r,
                const double *r, const double *wr, const double *xi, double *out_dev);
+// Non-Gaussian intrinsic covariance term on the caller's p quadrature with
+// the collapsed-trispectrum multipoles tbar [n_l][n_l][n_p][n_p] (host).
+void theory_ng(Ctx &c, double r0, double volume, int n_k, const double *k_edges, int n_l, int n_p, const double *p,
+               const double *wp, const double *tbar, double *out_dev);
 // Poisson three-point covariance term on the caller's p quadrature; wt the
 // host W~ per bin, pbin [n_l][n_k] and bk [n_l][n_k][n_k] host arrays or null.
 void theory_c3(Ctx &c, double r0, double nbar, double volume, int n_k, const double *k_edges, int n_l, int n_p,

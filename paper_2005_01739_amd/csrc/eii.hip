@@ -1314,6 +1314,42 @@ __global__ __launch_bounds__(256) void k_theory_c3_add(const double *__restrict_
   out[idx] += f0 * t;
 }
 
+// Non-Gaussian term, first contraction: X[l l'][i][b] = sum_j T[l l'][i][j]
+// u_j omega[l'][j][b], u_j = wp_j p_j^2/(2 pi^2); one thread per entry, j in
+// order.
+__global__ __launch_bounds__(256) void k_theory_ng_x(const double *__restrict__ p, const double *__restrict__ wp,
+                                                     const double *__restrict__ T, const double *__restrict__ om,
+                                                     int n_p, int n_k, int n_l, double *__restrict__ X) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= int64_t(n_l) * n_l * n_p * n_k) return;
+  const int b = int(idx % n_k), i = int((idx / n_k) % n_p), ll = int(idx / (int64_t(n_k) * n_p));
+  const int lj = ll % n_l;
+  const double *Ti = T + (int64_t(ll) * n_p + i) * n_p, *ob = om + int64_t(lj) * n_p * n_k + b;
+  double s = 0.0;
+  for (int j = 0; j < n_p; ++j)
+    s = fma(Ti[j] * (wp[j] * p[j] * p[j] * (1.0 / (2.0 * kPi * kPi))), ob[int64_t(j) * n_k], s);
+  X[idx] = s;
+}
+
+// Non-Gaussian term: out[(l a)(l' b)] = (2l+1)(2l'+1)/V sum_i u_i
+// omega[l][i][a] X[l l'][i][b] ((-1)^(l+l') = 1 for even l, l'); one thread
+// per entry, i in order.
+__global__ __launch_bounds__(256) void k_theory_ng_c(const double *__restrict__ p, const double *__restrict__ wp,
+                                                     const double *__restrict__ om, const double *__restrict__ X,
+                                                     int n_p, int n_k, int n_l, double inv_volume,
+                                                     double *__restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t nrow = int64_t(n_l) * n_k;
+  if (idx >= nrow * nrow) return;
+  const int b = int(idx % n_k), lj = int((idx / n_k) % n_l), a = int((idx / (int64_t(n_k) * n_l)) % n_k),
+            li = int(idx / (int64_t(n_k) * n_l * n_k));
+  const double *oa = om + int64_t(li) * n_p * n_k + a, *xb = X + int64_t(li * n_l + lj) * n_p * n_k + b;
+  double s = 0.0;
+  for (int i = 0; i < n_p; ++i)
+    s = fma((wp[i] * p[i] * p[i] * (1.0 / (2.0 * kPi * kPi))) * oa[int64_t(i) * n_k], xb[int64_t(i) * n_k], s);
+  out[idx] = double(4 * li + 1) * double(4 * lj + 1) * inv_volume * s;
+}
+
 // The r node set: 16-point Gauss-Legendre panels on [0, R0/2], [R0/2, 3R0/4],
 // [3R0/4, R0], each no wider than hmax.
 static void theory_nodes(double r0, double hmax, std::vector<double> &r, std::vector<double> &w) {
@@ -1498,6 +1534,21 @@ void theory_c3(Ctx &c, double r0, double nbar, double volume, int n_k, const dou
   const double *pbd = pbin ? upload(c, c.th_pb, pbin, size_t(n_l) * n_k) : nullptr;
   const double *bkd = bk ? upload(c, c.th_bk, bk, size_t(n_l) * n_k * n_k) : nullptr;
   k_theory_c3_add<<<blocks(nout), 256, 0, c.stream>>>(wtd, pbd, bkd, n_k, n_l, 4.0 / (nbar * volume), out_dev);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+void theory_ng(Ctx &c, double r0, double volume, int n_k, const double *k_edges, int n_l, int n_p, const double *p,
+               const double *wp, const double *tbar, double *out_dev) {
+  double *om = static_cast<double *>(ensure(c, c.th_om, size_t(n_l) * n_p * n_k * 8));
+  theory_omega(c, r0, n_k, k_edges, n_l, 2, n_p, p, om);
+  const double *pd = upload(c, c.th_p, p, size_t(n_p)), *wd = upload(c, c.th_wp, wp, size_t(n_p));
+  const double *Td = upload(c, c.th_T, tbar, size_t(n_l) * n_l * n_p * n_p);
+  const int64_t nx = int64_t(n_l) * n_l * n_p * n_k;
+  double *X = static_cast<double *>(ensure(c, c.th_X, size_t(nx) * 8));
+  k_theory_ng_x<<<blocks(nx), 256, 0, c.stream>>>(pd, wd, Td, om, n_p, n_k, n_l, X);
+  HIPSTER_HIP(hipGetLastError());
+  const int64_t nout = int64_t(n_l) * n_k * n_l * n_k;
+  k_theory_ng_c<<<blocks(nout), 256, 0, c.stream>>>(pd, wd, om, X, n_p, n_k, n_l, 1.0 / volume, out_dev);
   HIPSTER_HIP(hipGetLastError());
 }
 

@@ -1,13 +1,13 @@
 """GPU parity of the theory side (hipster_omega, hipster_pk_window_theory,
-hipster_cov_gauss, hipster_cov_poisson2, hipster_cov_poisson3) against the
-FP64 oracle.  Both sides are double-precision
+hipster_cov_gauss, hipster_cov_nongauss, hipster_cov_poisson2,
+hipster_cov_poisson3) against the FP64 oracle.  Both sides are double-precision
 quadratures of the same integrals with different rules (omega) or the same
 caller quadrature (the windowed P, the covariance's p sum), so:
 * omega agrees to 1e-10 of the largest |omega| of its multipole;
 * the windowed P to 1e-11 relative per bin (only the bin averages differ in
   how they are evaluated);
-* the covariance and the Poisson three-point term to 1e-9 of the largest
-  entry, the Poisson two-point term (same caller quadrature, no omega) to
+* the covariance, its non-Gaussian term and the Poisson three-point term
+  to 1e-9 of the largest entry, the Poisson two-point term (same caller quadrature, no omega) to
   1e-11.
 At the 40-bin size of the headline power spectrum, where the oracle's omega
 quadrature is too slow, the covariance is checked through an identity that
@@ -127,4 +127,18 @@ def test_poisson3_parity():
     assert e.value.name == "HIPSTER_EDOMAIN"
     with pytest.raises(hp.HipsterError) as e:
         hp.cov_poisson2(R0, -1.0, 1e6, K, 2, [1.0], [1.0], np.zeros((2, 1)))
+    assert e.value.name == "HIPSTER_EDOMAIN"
+
+
+def test_nongauss_parity():
+    import paper_2005_01739_amd as hp
+    p, w = _p_quadrature(4.0, panels=10, n=8)
+    f = np.array([400.0 * np.exp(-p), 60.0 * p * np.exp(-p / 2), 10.0 / (1 + p * p)])
+    rng = np.random.default_rng(5)
+    T = np.einsum("li,mj->lmij", f, f) * (1.0 + 0.1 * rng.standard_normal((3, 3, p.size, p.size)))
+    got = hp.cov_nongauss(R0, 1e6, K, 4, p, w, T)
+    ref = oracle.cov_nongauss(R0, 1e6, K, 4, p, w, T)
+    assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
+    with pytest.raises(hp.HipsterError) as e:
+        hp.cov_nongauss(R0, -1.0, K, 2, [0.1], [1.0], np.zeros((2, 2, 1, 1)))
     assert e.value.name == "HIPSTER_EDOMAIN"
