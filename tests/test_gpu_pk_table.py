@@ -98,6 +98,22 @@ def test_dense_box_counts_exact_on_every_call():
         assert np.array_equal(got, first)
 
 
+def test_largest_binning_from_zero():
+    # 128 bins from k = 0 (the largest binning; jbar_0(0) = 1 at every node
+    # of the first bin), l <= 6 (four sections at the node count of
+    # k_max R0 = 80)
+    pos = synthetic.thomas(3000, 160.0, 10, 2.0, 2.0, 23, np.float32)
+    run_case(pos, None, 160.0, 20.0, np.linspace(0.0, 4.0, 129), 6, "table")
+
+
+def test_signed_weights():
+    # weights of both signs: the fixed-point adds are signed and the scale
+    # follows the largest |w|
+    pos = synthetic.thomas(2500, 150.0, 10, 2.0, 0.0, 24, np.float64)
+    w = np.random.default_rng(25).uniform(-1.5, 2.0, 2500)
+    run_case(pos, w, 150.0, 15.0, np.geomspace(1.0, 12.0, 25), 4, "table", los=1)
+
+
 def test_errors():
     import paper_2005_01739_amd as hp
     pos = synthetic.poisson(200, 100.0, 4, np.float64)
