@@ -272,8 +272,11 @@ def pk_ell(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, los
            precision: str = "mixed", primary_mask=None, ctx: Context | None = None,
            return_diag: bool = False) -> Any:
     """Power-spectrum multipoles P^a_ell, ell = 0, 2, .., ell_max: float64 array
-    of shape (ell_max/2 + 1, n_k).  With return_diag, also a dict of the raw
-    pair sums, W~^a, the ordered pair count and device timings."""
+    of shape (ell_max/2 + 1, n_k).  precision: "mixed", "fp64" or "table"
+    (jbar from a quintic table, fixed-point histograms; see HIPSTER_TABLE).
+    With return_diag, also a dict of the raw pair sums, W~^a, the ordered pair
+    count and device timings (and "table_nodes", the table's interval count,
+    in the table form)."""
     L = load_library()
     keep: list = []
     pts = _points(pos, w, keep)
@@ -299,8 +302,9 @@ def pk_survey(pos, w=None, randoms=None, rw=None, *, volume: float, r0: float, k
               return_diag: bool = False) -> Any:
     """Survey-geometry power-spectrum multipoles (DD - 2DR + RR, pair-midpoint
     line of sight, observer at the origin, no periodicity): float64 array of
-    shape (ell_max/2 + 1, n_k).  `randoms` is required.  With return_diag, also
-    the raw pair sums, the DD, DR + RD and RR pair counts and timings."""
+    shape (ell_max/2 + 1, n_k).  `randoms` is required.  precision: "mixed",
+    "fp64" or "table".  With return_diag, also the raw pair sums, the DD,
+    DR + RD and RR pair counts and timings."""
     L = load_library()
     if randoms is None:
         raise ValueError("pk_survey needs a random catalogue")
