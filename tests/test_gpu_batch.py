@@ -57,6 +57,14 @@ def test_batch_matches_oracle(precision):
     _check_boxes(specs, outs, precision)
 
 
+def test_batch_rejects_table_form():
+    # the table form is offered by hipster_pk_ell and hipster_pk_survey only
+    import paper_2005_01739_amd as hp
+    with pytest.raises(hp.HipsterError) as e:
+        hp.batch(_boxes(1)[:1], precision="table")
+    assert e.value.name == "HIPSTER_EUNSUPPORTED"
+
+
 def test_batch_split_across_stream_chunks():
     # A tiny pair-stream capacity splits boxes across several work-queue
     # launches; results must agree with the unsplit run to rounding.
