@@ -88,8 +88,11 @@ typedef struct {
 } hipster_points;
 
 /* Estimator parameters.  k_edges: n_k + 1 strictly increasing host doubles,
- * k_edges[0] >= 0.  ell_max: P uses even ell = 0, 2, .., ell_max (ell_max
- * even, <= 6); B uses ell = 0 .. ell_max (<= 6).  los_axis: 0, 1 or 2 (P only).
+ * k_edges[0] >= 0; n_k <= 128 for P, <= 64 for B (<= 16 for the analytic
+ * DDR^II form and for B's FP64 form).  ell_max: P uses even ell = 0, 2, ..,
+ * ell_max (ell_max even, <= 6); B uses ell = 0 .. ell_max (<= 6).  The limit 6
+ * covers every multipole the paper evaluates (B to ell = 6 in Sec. 9); larger
+ * ell_max is HIPSTER_EDOMAIN.  los_axis: 0, 1 or 2 (P only).
  * primary_mask: NULL, or n host bytes; only primaries i with mask[i] != 0
  * contribute their ordered pairs (i, j) -- a hook for checking a subset of a
  * large catalogue against a brute-force reference. */
@@ -110,6 +113,16 @@ typedef struct {
  * normalisation.  For B: gd, cd, gr, cr [ell_max+1][n_k][n_k] = the data and
  * random primary sums of w_p (4 pi/(2l+1)) sum_m A^a_lm A^b_lm and of
  * w_p C^ab_l; s0 [n_k] = sum_{i!=j} w_i w_j jbar^b_0 W.  wtilde [n_k] = W~^a.
+ * l1_mass: the size against which a cancelling bin's error is judged.  For
+ * hipster_pk_ell, [n_ell][n_k] = sum over ordered pairs of
+ * |w_i w_j (2l+1) W jbar^a_l L_l(mu)|, the L1 mass of raw, evaluated in
+ * double precision by an extra sweep over the pairs (requested only when the
+ * pointer is set; its time is not in ms_sweep).  For hipster_bk_ell(_analytic),
+ * [ell_max+1][n_k][n_k] = (2l+1)/(V n_w^3) [sqrt(G_D^aa G_D^bb) +
+ * sqrt(C_D^aa C_D^bb) + s_R (sqrt(G_R^aa G_R^bb) + sqrt(C_R^aa C_R^bb))]
+ * + delta_l0 [(W~^a |S0^b| + W~^b |S0^a|)/(V n_w^2) + 2 W~^a W~^b], a
+ * Cauchy-Schwarz bound on the terms of B^ab_l (with n_w |T^ab| in place of the
+ * random-primary Gram in the analytic form).  Unused by hipster_pk_survey.
  * Timings are wall-clock milliseconds of the device work measured with HIP
  * events on the context stream. */
 typedef struct {
@@ -131,6 +144,8 @@ typedef struct {
   uint64_t n_pairs_2r0;   /* B analytic: ordered (pair, periodic image) terms inside 2 R0 */
   int64_t eii_nodes;      /* B analytic: the table's n_x (intervals over [0, 2 R0]) */
   double ms_cterm;        /* B, mixed form: the C-term pair sweep of the data primaries */
+  double *l1_mass;        /* see above */
+  uint64_t n_rand;        /* B: random primaries used (given or generated) */
 } hipster_diag;
 
 typedef struct hipster_ctx hipster_ctx;
@@ -147,13 +162,22 @@ void hipster_destroy(hipster_ctx *ctx);
 hipster_status hipster_pk_ell(hipster_ctx *ctx, const hipster_points *pts,
                               const hipster_params *prm, double *pk, hipster_diag *diag);
 
-/* Bispectrum multipoles (Sec. 4, summary estimator).  randoms: the uniform
- * random catalogue used as primaries for the DDR^II term (Sec. 4, f_rand
- * times the data), or NULL / n = 0 to leave that term out.
- * bk: host output, [ell_max + 1][n_k][n_k] doubles (symmetric in a, b). */
+/* Bispectrum multipoles (Sec. 4, summary estimator).  The DDR^II term is
+ * sampled with uniform random primaries (Sec. 4, a random catalogue f_rand
+ * times the size of the data): randoms, if non-NULL with n > 0, is that
+ * catalogue (f_rand and seed are then ignored); otherwise the library draws
+ * n_R = llround(f_rand * data->n) unit-weight points on the device, point i
+ * taking block i + 1 of the Philox4x64-10 counter-based generator (Salmon et
+ * al. 2011) with key (seed, 0) and the counter starting at 0 -- the stream of
+ * numpy's Philox(key=[seed, 0]) -- as x_d = L * (word_d >> 11) * 2^-53,
+ * d = 0, 1, 2 (a coordinate that rounds to L becomes 0).  With no catalogue
+ * and f_rand <= 0 (or not finite) the call returns HIPSTER_EINVAL: the term
+ * is never dropped (hipster_bk_ell_analytic computes it without randoms).
+ * diag->n_rand reports n_R.  bk: host output, [ell_max + 1][n_k][n_k]
+ * doubles (symmetric in a, b). */
 hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data,
-                              const hipster_points *randoms, const hipster_params *prm,
-                              double *bk, hipster_diag *diag);
+                              const hipster_points *randoms, double f_rand, uint64_t seed,
+                              const hipster_params *prm, double *bk, hipster_diag *diag);
 
 /* Bispectrum multipoles with the DDR^II term computed without randoms
  * (Sec. 4, eq. EII-intro; Appendix A, eq. DDRII-kernel and its binned form;
@@ -322,10 +346,12 @@ typedef struct {
   double *pk;               /* [pk ell_max/2+1][pk n_k] */
   double *bk;               /* [bk ell_max+1][bk n_k][bk n_k] */
   uint64_t n_pairs;         /* out: ordered data-data pairs */
-  int32_t bk_eii_nodes;     /* < 0: DDR^II from `randoms` (hipster_bk_ell); >= 0: from the
-                               E^II kernel as hipster_bk_ell_analytic with this n_x
-                               (0: default), `randoms` ignored */
+  int32_t bk_eii_nodes;     /* < 0: DDR^II from random primaries as hipster_bk_ell (`randoms`,
+                               or f_rand and seed below); >= 0: from the E^II kernel as
+                               hipster_bk_ell_analytic with this n_x (0: default), no randoms */
   int32_t reserved;
+  double f_rand;            /* as hipster_bk_ell, used when randoms.n = 0 */
+  uint64_t seed;
 } hipster_box_job;
 
 /* Many independent boxes in one pass: every box's pairs are enumerated into

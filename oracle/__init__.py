@@ -31,8 +31,6 @@ def lib():
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
             _build.build()
         L = ct.CDLL(path)
-        for name in ("oracle_window", "oracle_si", "oracle_legendre"):
-            pass
         L.oracle_window.restype = ct.c_double
         L.oracle_window.argtypes = [ct.c_double]
         L.oracle_si.restype = ct.c_double
@@ -97,6 +95,21 @@ def lib():
                                           _dp, _dp, _dp, _dp, _dp, _dp, ct.c_int]
         _lib = L
     return _lib
+
+
+def philox_randoms(n: int, box: float, seed: int) -> np.ndarray:
+    """The uniform random catalogue that hipster_bk_ell draws when it is given
+    none, restated here independently of the library: point i takes block
+    i + 1 of the Philox4x64-10 counter-based generator (Salmon, Moraes, Dror
+    and Shaw 2011) keyed by (seed, 0), and x_d = box * (word_d >> 11) * 2^-53
+    for d = 0, 1, 2, a coordinate that rounds to box set to 0.  numpy's Philox
+    bit generator is that generator (its counter is incremented before each
+    block); the tests pin it to the published round function and its
+    known-answer vectors.  Returns float64 (n, 3)."""
+    raw = np.random.Philox(key=np.array([int(seed) & (2 ** 64 - 1), 0], dtype=np.uint64)).random_raw(4 * int(n)).reshape(int(n), 4)[:, :3]
+    x = float(box) * ((raw >> np.uint64(11)).astype(np.float64) * 2.0 ** -53)
+    x[x >= box] = 0.0
+    return np.ascontiguousarray(x)
 
 
 def _ptr(a, t=_dp):

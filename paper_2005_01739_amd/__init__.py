@@ -61,7 +61,7 @@ class _Diag(ct.Structure):
                 ("ms_total", ct.c_double), ("sweep_launches", ct.c_uint64), ("n_pairs_rr", ct.c_uint64),
                 ("ms_sweep_far", ct.c_double), ("n_pairs_far", ct.c_uint64), ("ms_eii_table", ct.c_double),
                 ("ms_ddr2", ct.c_double), ("n_pairs_2r0", ct.c_uint64), ("eii_nodes", ct.c_int64),
-                ("ms_cterm", ct.c_double)]
+                ("ms_cterm", ct.c_double), ("l1_mass", _dp), ("n_rand", ct.c_uint64)]
 
 
 class _SurveyParams(ct.Structure):
@@ -73,7 +73,7 @@ class _SurveyParams(ct.Structure):
 class _BoxJob(ct.Structure):
     _fields_ = [("data", _Points), ("randoms", _Points), ("pk_params", _Params), ("bk_params", _Params),
                 ("pk", _dp), ("bk", _dp), ("n_pairs", ct.c_uint64), ("bk_eii_nodes", ct.c_int32),
-                ("reserved", ct.c_int32)]
+                ("reserved", ct.c_int32), ("f_rand", ct.c_double), ("seed", ct.c_uint64)]
 
 
 _lib = None
@@ -104,8 +104,8 @@ def load_library():
     L.hipster_pk_survey.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Points), ct.POINTER(_SurveyParams),
                                     _dp, ct.POINTER(_Diag)]
     L.hipster_bk_ell.restype = ct.c_int
-    L.hipster_bk_ell.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Points), ct.POINTER(_Params),
-                                 _dp, ct.POINTER(_Diag)]
+    L.hipster_bk_ell.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Points), ct.c_double, ct.c_uint64,
+                                 ct.POINTER(_Params), _dp, ct.POINTER(_Diag)]
     L.hipster_bk_ell_analytic.restype = ct.c_int
     L.hipster_bk_ell_analytic.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Params), ct.c_int32, _dp,
                                           ct.POINTER(_Diag)]
@@ -270,13 +270,14 @@ def wtilde(r0: float, k_edges) -> np.ndarray:
 
 def pk_ell(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, los_axis: int = 2,
            precision: str = "mixed", primary_mask=None, ctx: Context | None = None,
-           return_diag: bool = False) -> Any:
+           return_diag: bool = False, l1_mass: bool = False) -> Any:
     """Power-spectrum multipoles P^a_ell, ell = 0, 2, .., ell_max: float64 array
     of shape (ell_max/2 + 1, n_k).  precision: "mixed", "fp64" or "table"
     (jbar from a quintic table, fixed-point histograms; see HIPSTER_TABLE).
     With return_diag, also a dict of the raw pair sums, W~^a, the ordered pair
     count and device timings (and "table_nodes", the table's interval count,
-    in the table form)."""
+    in the table form); with l1_mass as well, "l1_mass", the L1 mass of the
+    raw sums per bin (an extra double-precision pass of the library)."""
     L = load_library()
     keep: list = []
     pts = _points(pos, w, keep)
@@ -285,16 +286,20 @@ def pk_ell(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, los
     out = np.zeros((n_ell, n_k))
     raw = np.zeros((n_ell, n_k))
     wt = np.zeros(n_k)
+    l1 = np.zeros((n_ell, n_k)) if l1_mass else None
     d = _Diag()
-    d.raw, d.wtilde = _ptr(raw), _ptr(wt)
+    d.raw, d.wtilde, d.l1_mass = _ptr(raw), _ptr(wt), _ptr(l1)
     c = ctx or _context_for(pos)
     c.check(L.hipster_pk_ell(c.handle, ct.byref(pts), ct.byref(prm), _ptr(out), ct.byref(d)))
     if not return_diag:
         return out
-    return out, {"raw": raw, "wtilde": wt, "n_pairs": int(d.n_pairs), "ms_build": d.ms_build,
-                 "ms_pairs": d.ms_pairs, "ms_sweep": d.ms_sweep, "ms_total": d.ms_total,
-                 "sweep_launches": int(d.sweep_launches), "ms_sweep_far": d.ms_sweep_far,
-                 "n_pairs_far": int(d.n_pairs_far), "table_nodes": int(d.eii_nodes)}
+    info = {"raw": raw, "wtilde": wt, "n_pairs": int(d.n_pairs), "ms_build": d.ms_build,
+            "ms_pairs": d.ms_pairs, "ms_sweep": d.ms_sweep, "ms_total": d.ms_total,
+            "sweep_launches": int(d.sweep_launches), "ms_sweep_far": d.ms_sweep_far,
+            "n_pairs_far": int(d.n_pairs_far), "table_nodes": int(d.eii_nodes)}
+    if l1_mass:
+        info["l1_mass"] = l1
+    return out, info
 
 
 def pk_survey(pos, w=None, randoms=None, rw=None, *, volume: float, r0: float, k_edges, ell_max: int = 4,
@@ -337,12 +342,14 @@ def pk_survey(pos, w=None, randoms=None, rw=None, *, volume: float, r0: float, k
 
 
 def bk_ell(pos, w=None, randoms=None, rw=None, *, box: float, r0: float, k_edges, ell_max: int = 4,
-           precision: str = "mixed", primary_mask=None, random_mask=None, ctx: Context | None = None,
-           return_diag: bool = False) -> Any:
+           precision: str = "mixed", primary_mask=None, random_mask=None, f_rand: float = 0.0, seed: int = 0,
+           ctx: Context | None = None, return_diag: bool = False) -> Any:
     """Bispectrum multipoles B^ab_ell, ell = 0..ell_max: float64 array of shape
     (ell_max + 1, n_k, n_k).  `randoms` are the random primaries of the DDR^II
-    term (None leaves that term out).  With return_diag, also the raw
-    components (gd, cd, gr, cr, s0), W~^a, pair counts and timings."""
+    term; without them the library draws round(f_rand N) uniform randoms from
+    `seed` (Philox4x64-10, see hipster_bk_ell), and f_rand <= 0 is an error.
+    With return_diag, also the raw components (gd, cd, gr, cr, s0), W~^a,
+    l1_mass, pair counts, the random count and timings."""
     L = load_library()
     keep: list = []
     pts = _points(pos, w, keep)
@@ -354,17 +361,19 @@ def bk_ell(pos, w=None, randoms=None, rw=None, *, box: float, r0: float, k_edges
     parts = {k: np.zeros(shp) for k in ("gd", "cd", "gr", "cr")}
     s0 = np.zeros(n_k)
     wt = np.zeros(n_k)
+    l1 = np.zeros(shp)
     d = _Diag()
     d.gd, d.cd, d.gr, d.cr = (_ptr(parts[k]) for k in ("gd", "cd", "gr", "cr"))
-    d.s0, d.wtilde = _ptr(s0), _ptr(wt)
+    d.s0, d.wtilde, d.l1_mass = _ptr(s0), _ptr(wt), _ptr(l1)
     c = ctx or _context_for(pos)
-    c.check(L.hipster_bk_ell(c.handle, ct.byref(pts), ct.byref(rpts), ct.byref(prm), _ptr(out), ct.byref(d)))
+    c.check(L.hipster_bk_ell(c.handle, ct.byref(pts), ct.byref(rpts), float(f_rand), int(seed) & (2 ** 64 - 1),
+                             ct.byref(prm), _ptr(out), ct.byref(d)))
     if not return_diag:
         return out
     info = dict(parts)
-    info.update(s0=s0, wtilde=wt, n_pairs=int(d.n_pairs), n_pairs_rand=int(d.n_pairs_rand), ms_build=d.ms_build,
-                ms_pairs=d.ms_pairs, ms_sweep=d.ms_sweep, ms_total=d.ms_total, sweep_launches=int(d.sweep_launches),
-                ms_cterm=d.ms_cterm)
+    info.update(s0=s0, wtilde=wt, l1_mass=l1, n_pairs=int(d.n_pairs), n_pairs_rand=int(d.n_pairs_rand),
+                n_rand=int(d.n_rand), ms_build=d.ms_build, ms_pairs=d.ms_pairs, ms_sweep=d.ms_sweep,
+                ms_total=d.ms_total, sweep_launches=int(d.sweep_launches), ms_cterm=d.ms_cterm)
     return out, info
 
 
@@ -386,15 +395,16 @@ def bk_ell_analytic(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int
     parts = {k: np.zeros(shp) for k in ("gd", "cd", "gr", "cr")}
     s0 = np.zeros(n_k)
     wt = np.zeros(n_k)
+    l1 = np.zeros(shp)
     d = _Diag()
     d.gd, d.cd, d.gr, d.cr = (_ptr(parts[k]) for k in ("gd", "cd", "gr", "cr"))
-    d.s0, d.wtilde = _ptr(s0), _ptr(wt)
+    d.s0, d.wtilde, d.l1_mass = _ptr(s0), _ptr(wt), _ptr(l1)
     c = ctx or _context_for(pos)
     c.check(L.hipster_bk_ell_analytic(c.handle, ct.byref(pts), ct.byref(prm), int(n_x), _ptr(out), ct.byref(d)))
     if not return_diag:
         return out
     info = {"gd": parts["gd"], "cd": parts["cd"], "t2": parts["gr"]}
-    info.update(s0=s0, wtilde=wt, n_pairs=int(d.n_pairs), n_pairs_2r0=int(d.n_pairs_2r0), ms_build=d.ms_build,
+    info.update(s0=s0, wtilde=wt, l1_mass=l1, n_pairs=int(d.n_pairs), n_pairs_2r0=int(d.n_pairs_2r0), ms_build=d.ms_build,
                 ms_sweep=d.ms_sweep, ms_eii_table=d.ms_eii_table, ms_ddr2=d.ms_ddr2, ms_total=d.ms_total,
                 eii_nodes=int(d.eii_nodes), ms_cterm=d.ms_cterm)
     return out, info
@@ -510,9 +520,11 @@ def cov_nongauss(r0: float, volume: float, k_edges, ell_max: int, p, wp, tbar, *
 def batch(boxes, *, precision: str = "mixed", ctx: Context | None = None, return_diag: bool = False):
     """Many boxes in one pass.  `boxes` is a sequence of dicts with keys pos,
     w (optional), randoms (optional), box, r0, pk_edges / pk_ell_max (optional),
-    bk_edges / bk_ell_max (optional) and bk_eii_nodes (optional: >= 0 takes the
-    bispectrum's DDR^II term from the E^II kernel with that table size, 0 for
-    the default, and ignores randoms).  Returns a list of dicts with 'pk'
+    bk_edges / bk_ell_max (optional), mask / rmask (optional primary masks of
+    the data, for P and B, and of the randoms), f_rand / seed (optional: randoms drawn by
+    the library when a bispectrum box has none) and bk_eii_nodes (optional:
+    >= 0 takes the bispectrum's DDR^II term from the E^II kernel with that
+    table size, 0 for the default, and ignores randoms).  Returns a list of dicts with 'pk'
     and/or 'bk' arrays and 'n_pairs'."""
     L = load_library()
     keep: list = []
@@ -523,18 +535,21 @@ def batch(boxes, *, precision: str = "mixed", ctx: Context | None = None, return
         j.data = _points(spec["pos"], spec.get("w"), keep)
         j.randoms = _points(spec.get("randoms"), spec.get("rw"), keep)
         j.bk_eii_nodes = int(spec.get("bk_eii_nodes", -1))
+        j.f_rand = float(spec.get("f_rand", 0.0))
+        j.seed = int(spec.get("seed", 0)) & (2 ** 64 - 1)
         res = {}
         if spec.get("pk_edges") is not None:
             lm = spec.get("pk_ell_max", 4)
             j.pk_params = _params(spec["box"], spec["r0"], spec["pk_edges"], lm, spec.get("los_axis", 2), precision,
-                                  None, None, keep)
+                                  spec.get("mask"), None, keep)
             res["pk"] = np.zeros((lm // 2 + 1, j.pk_params.n_k))
             j.pk = _ptr(res["pk"])
         else:
             j.pk_params = _Params(float(spec["box"]), float(spec["r0"]), 0, 0, None, 2, 0, None, None)
         if spec.get("bk_edges") is not None:
             lm = spec.get("bk_ell_max", 4)
-            j.bk_params = _params(spec["box"], spec["r0"], spec["bk_edges"], lm, 2, precision, None, None, keep)
+            j.bk_params = _params(spec["box"], spec["r0"], spec["bk_edges"], lm, 2, precision, spec.get("mask"),
+                                  spec.get("rmask"), keep)
             nk = j.bk_params.n_k
             res["bk"] = np.zeros((lm + 1, nk, nk))
             j.bk = _ptr(res["bk"])

@@ -185,7 +185,7 @@ struct SweepStats {
 template <typename CountF, typename WriteF>
 static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t nunits, CountF &&count, WriteF &&write, int n_ell,
                                  bool fp64, double r0, const double *edges, int n_edges, bool far_ok,
-                                 double *partial, int nwaves) {
+                                 double *partial, int nwaves, double *l1_rows = nullptr, bool main_sweep = true) {
   SweepStats st;
   int64_t *cnt_a = static_cast<int64_t *>(ensure(c, c.pair_cnt, size_t(nunits) * 8));
   int64_t *cnt_b = static_cast<int64_t *>(ensure(c, c.pair_cnt_b, size_t(nunits) * 8));
@@ -226,10 +226,10 @@ static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t nunits, CountF &&cou
       hipEvent_t b = tm.mark();
       // near bucket (or every pair) through the general kernel, the far
       // bucket through the far kernel
-      const int64_t n_gen = far_ok ? n_a : np;
-      pk_sweep_general(c, pp, n_gen, n_ell, fp64, r0, edges, n_edges, partial, nwaves);
+      const int64_t n_gen = main_sweep ? (far_ok ? n_a : np) : np;
+      if (main_sweep) pk_sweep_general(c, pp, n_gen, n_ell, fp64, r0, edges, n_edges, partial, nwaves);
       hipEvent_t m = tm.mark();
-      if (n_gen < np) {
+      if (main_sweep && n_gen < np) {
         PkPairs far;
         far.r = pp.r + n_gen;
         far.mu = static_cast<double *>(pp.mu) + n_gen;
@@ -237,6 +237,8 @@ static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t nunits, CountF &&cou
         pk_sweep_far(c, far, np - n_gen, n_ell, fp64, r0, edges, n_edges, partial, nwaves);
       }
       hipEvent_t d = tm.mark();
+      // the L1 mass, an extra double-precision pass over the same pairs
+      if (l1_rows) pk_l1_sweep(c, pp, np, n_ell, r0, edges, n_edges, l1_rows, nwaves);
       HIPSTER_HIP(hipEventSynchronize(d));
       st.ms_pairs += Timer::ms(a, b);
       st.ms_sweep += Timer::ms(b, d);
@@ -289,6 +291,31 @@ static std::vector<double> bin_sums(Ctx &c, double *partial, int nwaves, int n_e
   return S;
 }
 
+// diag->l1_mass of the power spectrum: the pair stream enumerated once more and
+// swept by the double-precision L1 kernel only.
+static void pk_l1_mass(Ctx &c, Timer &tm, const Sorted &s, const Grid &g, const hipster_params *q, double *out) {
+  const int n_ell = q->ell_max / 2 + 1, n_edges = q->n_k + 1;
+  const double r_split = q->k_edges[0] > 0.0 ? HIPSTER_U_BIG / q->k_edges[0] : 0.0;
+  double *edges = upload_edges(c, q->n_k, q->k_edges);
+  const int nwaves = pk_sweep_waves(c);
+  const int cols = n_ell * q->n_k;
+  double *rows = static_cast<double *>(ensure(c, c.pk_l1, size_t(nwaves) * cols * 8));
+  HIPSTER_HIP(hipMemsetAsync(rows, 0, size_t(nwaves) * cols * 8, c.stream));
+  const PairUnits units = make_pair_units(c, s, g);
+  sweep_pair_set(
+      c, tm, units.n,
+      [&](int64_t *ca, int64_t *cb, unsigned long long *ord) {
+        pk_pairs_count(c, s, g, units, q->r0, r_split, ca, cb, ord);
+      },
+      [&](const int64_t *oa, const int64_t *ob, int64_t ba, int64_t bb, int64_t na, int64_t u0, int64_t u1,
+          PkPairs pp) { pk_pairs_write(c, s, g, units, q->r0, r_split, q->los_axis, oa, ob, ba, bb, na, u0, u1, pp); },
+      n_ell, true, q->r0, edges, n_edges, false, nullptr, nwaves, rows, false);
+  double *merged = static_cast<double *>(ensure(c, c.merged, size_t(cols) * 8));
+  merge_partials(c, rows, nwaves, cols, merged);
+  HIPSTER_HIP(hipMemcpyAsync(out, merged, size_t(cols) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+}
+
 static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, double *pk, hipster_diag *diag) {
   check_points(pts, "data", q ? q->box : 0.0);
   check_params(q, false, true);
@@ -325,6 +352,7 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
     HIPSTER_HIP(hipMemcpyAsync(T.data(), Td, T.size() * 8, hipMemcpyDeviceToHost, c.stream));
     HIPSTER_HIP(hipMemcpyAsync(&ordered, ord, 8, hipMemcpyDeviceToHost, c.stream));
     HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    if (diag && diag->l1_mass) pk_l1_mass(c, tm, s, g, q, diag->l1_mass);
     const double p1 = weight_sum(pts);
     const double V = q->box * q->box * q->box, nw = p1 / V, norm = 1.0 / (nw * nw * V);
     std::vector<double> wt(static_cast<size_t>(q->n_k));
@@ -372,6 +400,7 @@ static void run_pk(Ctx &c, const hipster_points *pts, const hipster_params *q, d
   const std::vector<double> S = bin_sums(c, partial, nwaves, n_ell, q->n_k, q->k_edges);
   hipEvent_t t3 = tm.mark();
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  if (diag && diag->l1_mass) pk_l1_mass(c, tm, s, g, q, diag->l1_mass);
 
   // finalize (host, FP64): P^a_l = S^a_l / (n_w^2 V) - delta_l0 W~^a
   const double p1 = weight_sum(pts);
@@ -607,19 +636,46 @@ static int check_eii_nodes(Ctx &c, const hipster_params *q, int n_x) {
 // analytic_nx < 0: the DDR^II term from the random primaries `rp`;
 // otherwise from the E^II kernel with that many table intervals (0: default)
 // and no randoms.
-static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, const hipster_params *q, double *bk,
-                   hipster_diag *diag, int analytic_nx = -1) {
+static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, double f_rand, uint64_t seed,
+                   const hipster_params *q, double *bk, hipster_diag *diag, int analytic_nx = -1) {
   check_points(dp, "data", q ? q->box : 0.0);
   check_params(q, true);
   if (!bk) throw Error{HIPSTER_EINVAL, "NULL output"};
   if (dp->n < 2) throw Error{HIPSTER_EINVAL, "need at least two points"};
   const bool analytic = analytic_nx >= 0;
-  if (analytic) analytic_nx = check_eii_nodes(c, q, analytic_nx);
-  const bool have_r = !analytic && rp && rp->n > 0;
-  if (have_r) check_points(rp, "randoms", q->box);
+  if (analytic) {
+    if (q->n_k > kEiiMaxNkApi)
+      throw Error{HIPSTER_EUNSUPPORTED, "analytic DDR^II: n_k must lie in [1, " + std::to_string(kEiiMaxNkApi) + "]"};
+    analytic_nx = check_eii_nodes(c, q, analytic_nx);
+  }
+  const bool given_r = !analytic && rp && rp->n > 0;
+  if (given_r) check_points(rp, "randoms", q->box);
+  const bool gen_r = !analytic && !given_r;
+  int64_t n_gen = 0;
+  if (gen_r) {
+    if (!(f_rand > 0.0) || !isfinite(f_rand))
+      throw Error{HIPSTER_EINVAL,
+                  "bispectrum: no random catalogue and f_rand <= 0; the DDR^II term needs random primaries "
+                  "(or use hipster_bk_ell_analytic)"};
+    const double want = std::llround(f_rand * double(dp->n));
+    if (want < 1.0 || want > 2147483647.0) throw Error{HIPSTER_EINVAL, "bispectrum: f_rand * N must round into [1, 2^31)"};
+    n_gen = int64_t(want);
+  }
+  const bool have_r = given_r || gen_r;
   HIPSTER_HIP(hipSetDevice(c.device));
   Timer tm(c);
   hipEvent_t t0 = tm.mark();
+  hipster_points genp{};
+  if (gen_r) {
+    double *gp = static_cast<double *>(ensure(c, c.rgen, size_t(n_gen) * 24));
+    random_points(c, seed, n_gen, q->box, gp);
+    genp.n = n_gen;
+    genp.dtype = HIPSTER_F64;
+    genp.on_device = 1;
+    genp.pos = gp;
+    genp.w = nullptr;
+    rp = &genp;
+  }
 
   const int64_t n = dp->n, nr = have_r ? rp->n : 0;
   const size_t esz = dp->dtype == HIPSTER_F32 ? 4 : 8;
@@ -638,7 +694,7 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   }
   hipEvent_t t1 = tm.mark();
 
-  const int NK = q->n_k, NL = q->ell_max + 1, nT = NL * 256, rowlen = 2 * nT + 16;
+  const int NK = q->n_k, NL = q->ell_max + 1;
   const bool fp64 = q->precision == HIPSTER_FP64;
   std::vector<double> coef(static_cast<size_t>(NK));
   for (int a = 0; a < NK; ++a) {
@@ -649,31 +705,24 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   double *coef_d = static_cast<double *>(ensure(c, c.bk_coef, size_t(NK) * 8));
   HIPSTER_HIP(hipMemcpyAsync(edges, q->k_edges, size_t(NK + 1) * 8, hipMemcpyHostToDevice, c.stream));
   HIPSTER_HIP(hipMemcpyAsync(coef_d, coef.data(), size_t(NK) * 8, hipMemcpyHostToDevice, c.stream));
-  const int nwaves = device_cus(c) * 8;
-  double *part[2];
-  part[0] = static_cast<double *>(ensure(c, c.bk_partial, size_t(nwaves) * rowlen * 8));
-  part[1] = static_cast<double *>(ensure(c, c.bk_partial_r, size_t(nwaves) * rowlen * 8));
-  HIPSTER_HIP(hipMemsetAsync(part[0], 0, size_t(nwaves) * rowlen * 8, c.stream));
-  HIPSTER_HIP(hipMemsetAsync(part[1], 0, size_t(nwaves) * rowlen * 8, c.stream));
   unsigned long long *cnt = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 24));
   HIPSTER_HIP(hipMemsetAsync(cnt, 0, 24, c.stream));
-  // the mixed form takes C of the data primaries from the C-term pair
-  // histogram (exact window, tabulated jbar^a jbar^b) instead of the fused
-  // kernel's matrix instructions; the FP64 form keeps C in the fused kernel
+  // the mixed form takes C from the C-term pair histogram (exact window,
+  // tabulated jbar^a jbar^b); the FP64 form sums C in the pair sweep
   const bool c_hist = !fp64;
 
   double ms_sweep = 0.0;
   const double ms_pairs = 0.0;  // enumeration is fused into the sweep
   uint64_t launches = 0;
+  BkSums sums[2];
   for (int set = 0; set < (have_r ? 2 : 1); ++set) {
     const Sorted &prim = set == 0 ? sd : sr;
     hipEvent_t b1 = tm.mark();
-    bk_fused(c, prim, sd, g, q->r0, set == 0, edges, coef_d, NK, q->ell_max, fp64, !c_hist, part[set], rowlen, nwaves,
-             cnt + set);
+    bk_sweep(c, prim, sd, g, q->r0, set == 0, edges, coef_d, NK, q->ell_max, fp64, !c_hist, cnt + set, sums[set]);
     hipEvent_t b2 = tm.mark();
     HIPSTER_HIP(hipEventSynchronize(b2));
     ms_sweep += Timer::ms(b1, b2);
-    ++launches;
+    launches += sums[set].launches;
   }
   // C of the data primaries (Ch[0]) and of the random primaries (Ch[1])
   std::vector<double> Ch[2];
@@ -717,39 +766,58 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
   }
   unsigned long long hcnt[2] = {0, 0};
   HIPSTER_HIP(hipMemcpyAsync(hcnt, cnt, 16, hipMemcpyDeviceToHost, c.stream));
-  double *merged = static_cast<double *>(ensure(c, c.merged, size_t(2 * rowlen) * 8));
-  merge_partials(c, part[0], nwaves, rowlen, merged);
-  merge_partials(c, part[1], nwaves, rowlen, merged + rowlen);
-  std::vector<double> M(static_cast<size_t>(2 * rowlen));
-  HIPSTER_HIP(hipMemcpyAsync(M.data(), merged, size_t(2 * rowlen) * 8, hipMemcpyDeviceToHost, c.stream));
   hipEvent_t t3 = tm.mark();
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
 
   // assembly (Sec. 4 summary estimator), host FP64
-  const double p1 = weight_sum(dp), pr = have_r ? weight_sum(rp) : 0.0;
+  const double p1 = weight_sum(dp), pr = have_r ? (gen_r ? double(n_gen) : weight_sum(rp)) : 0.0;
   const double V = q->box * q->box * q->box, nw = p1 / V, sR = have_r ? p1 / pr : 0.0;
   std::vector<double> wt(static_cast<size_t>(NK));
   wtilde_bins(c, q->r0, NK, q->k_edges, wt.data());
-  const double *Md = M.data(), *Mr = M.data() + rowlen;
-  // tiles are 16 x 16 per l; the Gram sums are symmetric up to rounding, so
-  // the upper triangle is mirrored to make the output exactly symmetric
+  // S0 from the data primaries' A_00 sums: sum_q w_q W jbar_0 = A_00 / y_00
+  constexpr double kInvY00 = 3.5449077018110320546;  // 2 sqrt(pi)
+  std::vector<double> S0(static_cast<size_t>(NK));
+  for (int b = 0; b < NK; ++b) S0[size_t(b)] = sums[0].S0[size_t(b)] * kInvY00;
   for (int l = 0; l < NL; ++l)
     for (int a = 0; a < NK; ++a)
       for (int b = 0; b < NK; ++b) {
-        const int t = l * 256 + std::min(a, b) * 16 + std::max(a, b);
         const size_t o = (size_t(l) * NK + a) * NK + b;
-        const double GD = Md[t];
         const size_t tc = (size_t(l) * NK + std::min(a, b)) * NK + std::max(a, b);
-        const double CD = c_hist ? Ch[0][tc] : Md[nT + t];
+        const double GD = sums[0].G[o];
+        const double CD = c_hist ? Ch[0][tc] : sums[0].C[o];
         // the random-primary term s_R (G_R - C_R) estimates n_w T, T = sum_{i!=j} w_i w_j E^II
-        const double GR = analytic ? T[(size_t(l) * NK + std::min(a, b)) * NK + std::max(a, b)] : Mr[t];
-        const double CR = analytic ? 0.0 : (c_hist && have_r ? Ch[1][tc] : Mr[nT + t]);
+        const double GR = analytic ? T[tc] : (have_r ? sums[1].G[o] : 0.0);
+        const double CR = analytic ? 0.0 : (have_r ? (c_hist ? Ch[1][tc] : sums[1].C[o]) : 0.0);
         const double sgn = (l & 1) ? -1.0 : 1.0;
         const double ddr2 = analytic ? nw * GR : sR * (GR - CR);
         double v = sgn * (2.0 * l + 1.0) / (V * nw * nw * nw) * ((GD - CD) - ddr2);
-        if (l == 0) v += -(wt[size_t(a)] * Md[2 * nT + b] + wt[size_t(b)] * Md[2 * nT + a]) / (V * nw * nw) +
+        if (l == 0) v += -(wt[size_t(a)] * S0[size_t(b)] + wt[size_t(b)] * S0[size_t(a)]) / (V * nw * nw) +
                          2.0 * wt[size_t(a)] * wt[size_t(b)];
         bk[o] = v;
+        if (diag && diag->l1_mass) {
+          auto sq = [&](auto get) { return sqrt(fabs(get(a, a)) * fabs(get(b, b))); };
+          const double sGD = sq([&](int x, int y) { return sums[0].G[(size_t(l) * NK + x) * NK + y]; });
+          const double sCD = sq([&](int x, int y) {
+            return c_hist ? Ch[0][(size_t(l) * NK + std::min(x, y)) * NK + std::max(x, y)]
+                          : sums[0].C[(size_t(l) * NK + x) * NK + y];
+          });
+          double sR2 = 0.0;
+          if (analytic) {
+            sR2 = nw * fabs(GR);
+          } else if (have_r) {
+            const double sGR = sq([&](int x, int y) { return sums[1].G[(size_t(l) * NK + x) * NK + y]; });
+            const double sCR = sq([&](int x, int y) {
+              return c_hist ? Ch[1][(size_t(l) * NK + std::min(x, y)) * NK + std::max(x, y)]
+                            : sums[1].C[(size_t(l) * NK + x) * NK + y];
+            });
+            sR2 = sR * (sGR + sCR);
+          }
+          double m = (2.0 * l + 1.0) / (V * nw * nw * nw) * (sGD + sCD + sR2);
+          if (l == 0)
+            m += (wt[size_t(a)] * fabs(S0[size_t(b)]) + wt[size_t(b)] * fabs(S0[size_t(a)])) / (V * nw * nw) +
+                 2.0 * fabs(wt[size_t(a)] * wt[size_t(b)]);
+          diag->l1_mass[o] = m;
+        }
         if (diag) {
           if (diag->gd) diag->gd[o] = GD;
           if (diag->cd) diag->cd[o] = CD;
@@ -759,11 +827,12 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, c
       }
   if (diag) {
     if (diag->s0)
-      for (int b = 0; b < NK; ++b) diag->s0[b] = Md[2 * nT + b];
+      for (int b = 0; b < NK; ++b) diag->s0[b] = S0[size_t(b)];
     if (diag->wtilde) memcpy(diag->wtilde, wt.data(), size_t(NK) * 8);
     diag->n_pairs = hcnt[0];
     diag->n_pairs_rr = 0;
     diag->n_pairs_rand = analytic ? 0 : hcnt[1];
+    diag->n_rand = have_r ? uint64_t(rp->n) : 0;
     diag->ms_build = Timer::ms(t0, t1);
     diag->ms_pairs = ms_pairs;
     diag->ms_sweep = ms_sweep;
@@ -887,6 +956,8 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
       check_params(&j.bk_params, true);
       if (!j.bk) throw Error{HIPSTER_EINVAL, "batch: NULL bk output"};
       if (j.bk_eii_nodes < 0 && j.randoms.n > 0) check_points(&j.randoms, "batch randoms", j.bk_params.box);
+      if (j.bk_eii_nodes < 0 && j.randoms.n <= 0 && (!(j.f_rand > 0.0) || !isfinite(j.f_rand)))
+        throw Error{HIPSTER_EINVAL, "batch: a bispectrum box needs randoms, f_rand > 0 or bk_eii_nodes >= 0"};
     }
   }
   HIPSTER_HIP(hipSetDevice(c.device));
@@ -1079,9 +1150,9 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
     if (j.bk_params.n_k <= 0) continue;
     hipster_diag d{};
     if (j.bk_eii_nodes >= 0)
-      run_bk(c, &j.data, nullptr, &j.bk_params, j.bk, &d, j.bk_eii_nodes);
+      run_bk(c, &j.data, nullptr, 0.0, 0, &j.bk_params, j.bk, &d, j.bk_eii_nodes);
     else
-      run_bk(c, &j.data, j.randoms.n > 0 ? &j.randoms : nullptr, &j.bk_params, j.bk, &d);
+      run_bk(c, &j.data, j.randoms.n > 0 ? &j.randoms : nullptr, j.f_rand, j.seed, &j.bk_params, j.bk, &d);
     ms_build += d.ms_build;
     ms_pairs += d.ms_pairs;
     ms_sweep += d.ms_sweep;
@@ -1151,10 +1222,10 @@ void hipster_destroy(hipster_ctx *ctx) {
   free_cells(c.cells_r);
   DevBuf *all[] = {&c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in, &c.rmask_in, &c.pair_cnt, &c.pair_cnt_b,
                    &c.pair_ord, &c.pair_off, &c.pair_off_b, &c.pair_total, &c.pr, &c.pmu, &c.pww, &c.pux, &c.puy, &c.puz, &c.edges,
-                   &c.partial, &c.merged, &c.ordered_count, &c.bbox, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out,
+                   &c.partial, &c.merged, &c.ordered_count, &c.bbox, &c.bk_partial, &c.bk_partial_r, &c.bk_coef, &c.bq_count, &c.bq_off, &c.bq_scan, &c.bq_quads, &c.bk_abuf, &c.bk_wbuf, &c.bk_tiles, &c.bk_gpart, &c.bk_gmerged, &c.bt_tasks, &c.bt_boxes, &c.bt_counter, &c.bt_rows, &c.bt_first, &c.bt_out,
                    &c.unit_tiles, &c.unit_base, &c.unit_cell, &c.unit_tile, &c.eii_consts,
                    &c.ddr2_partial, &c.ddr2_hist, &c.ddr2_counter, &c.ddr2_T, &c.ct_tab, &c.ct_consts, &c.ct_C,
-                   &c.ct_wmax, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
+                   &c.ct_wmax, &c.ct_jbar, &c.ct_sel, &c.rgen, &c.pk_l1, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
                    &c.th_K, &c.th_out, &c.th_wt, &c.th_pb, &c.th_bk, &c.th_T, &c.th_X, &c.pt_tab, &c.pt_consts,
                    &c.pt_T,
                    &c.tune_scratch};
@@ -1174,14 +1245,15 @@ hipster_status hipster_pk_survey(hipster_ctx *ctx, const hipster_points *data, c
 }
 
 hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data, const hipster_points *randoms,
-                              const hipster_params *prm, double *bk, hipster_diag *diag) {
-  return guarded(ctx, [&] { run_bk(ctx->c, data, randoms, prm, bk, diag); });
+                              double f_rand, uint64_t seed, const hipster_params *prm, double *bk,
+                              hipster_diag *diag) {
+  return guarded(ctx, [&] { run_bk(ctx->c, data, randoms, f_rand, seed, prm, bk, diag); });
 }
 
 hipster_status hipster_bk_ell_analytic(hipster_ctx *ctx, const hipster_points *data, const hipster_params *prm,
                                        int32_t n_x, double *bk, hipster_diag *diag) {
   if (n_x < 0) return HIPSTER_EINVAL;
-  return guarded(ctx, [&] { run_bk(ctx->c, data, nullptr, prm, bk, diag, n_x); });
+  return guarded(ctx, [&] { run_bk(ctx->c, data, nullptr, 0.0, 0, prm, bk, diag, n_x); });
 }
 
 hipster_status hipster_eii_table(hipster_ctx *ctx, double r0, int32_t n_k, const double *k_edges, int32_t ell_max,

@@ -2,47 +2,37 @@
 //   A^a_lm(x_p) = sum_j w_j jbar^a_l(r_pj) W(r_pj/R0) y_lm(xhat_pj)      (eq. AC-def)
 //   C^ab_l(x_p) = sum_j w_j^2 jbar^a_l jbar^b_l W^2
 // for data primaries (j != p) and random primaries (all data j), contracted
-// per primary into G^ab_l += w_p (4 pi/(2l+1)) sum_m A^a_lm A^b_lm, with
-// real orthonormal harmonics y_lm (the sum over m is basis independent).
+// into G^ab_l = sum_p w_p (4 pi/(2l+1)) sum_m A^a_lm A^b_lm, with real
+// orthonormal harmonics y_lm (the sum over m does not depend on the basis).
 // Data primaries also give S0^b = sum_{p != j} w_p w_j jbar^b_0 W, the pair sum
 // of the analytic DDR^I term.
 //
-// One fused kernel per primary catalogue: each wave takes runs of primaries,
-// enumerates the data neighbours of each inside R0 from the 27 surrounding
-// cells, and contracts them on the FP64 matrix cores (see k_bk_fused).  The
-// candidate order and the primary-to-wave assignment are fixed, so every sum
-// is deterministic.
+// Work unit: a quad, up to four primaries of one home cell.  A wave takes a
+// quad, one primary per 16-lane row, so each candidate secondary loaded from
+// the 27 neighbour cells is tested against four primaries.  Hits go to one
+// ring buffer per row; batches of up to 16 pairs per row are staged (lane =
+// (row, pair): geometry, y_lm times w_q W, the top bin edge) and then swept in
+// steps of one pair per row.  In a step lane (col, row) evaluates G_l at bin
+// edge 16 g + col for its row's pair, takes the next edge's value from lane
+// col + 1 by DPP, forms the bin average, and adds it times every y_lm into
+// FP64 accumulators A^{16g+col}_lm of its row's primary.  The y_lm of the
+// step's pair reach all lanes of a row as 64-bit DPP broadcasts
+// (row_newbcast) fused into the multiply-adds (fmac_dpp.h).
+//
+// Up to 16 bins: after the quad, G_l += A_l A_l^T on the FP64 matrix cores,
+// the four primaries of the quad forming the instruction's K = 4 dimension.
+// More bins: one pass over the quads per group of 16 bins, A written to a
+// buffer, then the Gram as a separate matrix-core contraction (k_bk_gram).
+//
+// Quads go to waves by a fixed rule and every sum is taken in a fixed order,
+// so results are bitwise reproducible.
 #include <type_traits>
 
 #include "common.h"
+#include "fmac_dpp.h"
 #include "specfun.h"
 
 namespace hipster {
-
-__device__ inline int bk_wrap(int v, int nc, int &shift) {
-  shift = 0;
-  if (v >= nc) {
-    shift = 1;
-    return v - nc;
-  }
-  if (v < 0) {
-    shift = -1;
-    return v + nc;
-  }
-  return v;
-}
-
-__device__ inline double bk_image(double d, int shift, double L) {
-  return shift > 0 ? d - L : (shift < 0 ? d + L : d);
-}
-
-__device__ inline double bk_sq_norm(double dx, double dy, double dz) {
-#pragma clang fp contract(off)
-  double a = dx * dx;
-  double b = dy * dy;
-  double c = dz * dz;
-  return (a + b) + c;
-}
 
 // Real orthonormal spherical harmonics y_lm of a unit vector, index l*l+l+m:
 // y_l0 = N_l0 Q_l^0(z), y_lm = N_lm Q_l^m(z) Re (x+iy)^m, y_l-m = N_lm Q_l^m(z) Im (x+iy)^m,
@@ -81,52 +71,11 @@ __device__ inline void real_ylm(double x, double y, double z, Out Y) {
   }
 }
 
-// ------------------------------------------------- fused enumerate + MFMA
-// One wave per workgroup.  Each wave takes runs of kPrimRun consecutive
-// primaries (cell order) from its XCD's slab (see the loop below);
-// consecutive primaries mostly share a home cell, whose 27 neighbour cells are
-// merged into at most 27 contiguous runs of the sorted secondaries (cells
-// adjacent along z are adjacent in memory).  The runs are scanned 64
-// candidates at a time, the loads of the next 64 issued before the current
-// ones are tested; pairs inside R0 go to an LDS hit buffer, and every kBatch
-// hits form a batch: y_lm of each pair into LDS, then kBatch/4 steps of 4
-// pairs contracted on v_mfma_f64_16x16x4f64:
-//   A_l[a][m] += sum_q g_l[q][a] y_lm[q]            (l >= 1; A operand: bins x pairs)
-//   C_l[a][b] += w_p sum_q g_l[q][a] g_l[q][b]      (both operands the same register)
-// where g_l[q][a] = w_q W(r_q) jbar^a_l(r_q).  In step s lane L holds pair
-// q = 4s + L/16 and bin a = L%16, the operand layout of the instruction, so
-// each lane evaluates G_l at one bin edge and takes the next edge's value
-// from lane L+1 (the 17th edge of a 16-bin set is evaluated per pair with the
-// harmonics).  A_00 has a single column, so its sum Sigma_q g_0 is kept on
-// the vector unit; it also gives S0 and the l = 0 Gram directly.  (FP64
-// matrix and vector instructions do not execute concurrently on this chip --
-// the co-execution counter reads zero -- so nothing is gained by
-// interleaving them.)
-//
-// After a primary's last batch, G_l += w_p (4 pi/(2l+1)) A_l A_l^T through an
-// LDS transpose of the A tile.  G, C and S0 stay in registers until the wave
-// ends.  Operand layout (gfx950): A lane L -> A[L%16][L/16]; B lane L ->
-// B[L/16][L%16]; result lane L, register v -> D[L/16 + 4v][L%16].
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline d4_t mfma_f64(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-
-constexpr int kBatch = 64;           // pairs per contraction batch
-constexpr int kHitCap = kBatch + 64; // < kBatch left over + at most 64 hits per scan step
-constexpr int kPrimRun = 16;         // consecutive primaries per wave assignment
-constexpr int kXcds = 8;             // accelerator complex dies of the MI355X (the grid is a multiple)
-
-// Minimum waves per SIMD the compiler must fit the fused kernel into (1 lets
-// it use all 512 registers; 2 trades spills for twice the occupancy).
-#ifndef HIPSTER_BK_WAVES_PER_EU
-#define HIPSTER_BK_WAVES_PER_EU 1
-#endif
-// Occupancy hint of the variant without the C sums (fewer accumulators).
-#ifndef HIPSTER_BK_WAVES_PER_EU_NOC
-#define HIPSTER_BK_WAVES_PER_EU_NOC 1
-#endif
 
 // The value held by lane L+1 of the same 16-lane row (lane 15 of a row gets
 // 0): a DPP row shift, no LDS round trip.
@@ -137,120 +86,204 @@ __device__ inline double from_next_lane_in_row(double v) {
   return __hiloint2double(nhi, nlo);
 }
 
-// y_lm staging of one lane's pair: element idx of pair q at ylds[idx][q],
-// rows padded to kBatch + 1 doubles so that lanes write distinct banks.
-struct YRow {
-  double *base;
-  __device__ double &operator[](int idx) const { return base[idx * (64 + 1)]; }
-};
-
 __device__ inline int64_t uniform_i64(int64_t v) {
   const int lo = __builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(v))));
   const int hi = __builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(v) >> 32)));
   return int64_t((uint64_t(uint32_t(hi)) << 32) | uint64_t(uint32_t(lo)));
 }
 
-constexpr int kSinCosTabBk = 64;      // sine/cosine table entries (LDS)
-constexpr int kYStride = kBatch + 1;  // row stride of the y_lm staging
-static_assert(kYStride == 64 + 1, "YRow assumes kBatch = 64");
-
-size_t bk_fused_lds(int NL, int NK) {
-  // y_lm [NL^2][kYStride], one row of zeros, then a region that holds the
-  // top-edge values [NL][kBatch] (16 bins) during batches and the A tile
-  // [NL][16][16] after them
-  (void)NK;
-  return (size_t(kYStride) * (NL * NL + 1) + size_t(256) * NL) * 8;
+__device__ inline double uniform_f64(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
 }
 
-// G_l(u) of the mixed form for the closed-form lanes, with lanes below
-// kUSmall replaced by the Taylor branch (a uniform branch, taken only when
-// some lane needs it).
-// WITH_C = false leaves the C sums out (their partial-row entries stay zero):
-// the mixed form takes C from the pair histogram of the C-term sweep instead
-// (k_ddr2_hist), which saves the NL matrix instructions per step that C costs
-// here.
-template <int NL, bool FP64, bool WITH_C>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WITH_C ? HIPSTER_BK_WAVES_PER_EU
-                                                                             : HIPSTER_BK_WAVES_PER_EU_NOC))) void
-k_bk_fused(
-    Sorted prim, Sorted sec, int nc, double L, double r02, int self_set, int64_t p_lo, int64_t p_hi,
-    double inv_r0, const double *__restrict__ edges, const double *__restrict__ coef, int NK,
-    double *__restrict__ partial, int rowlen, unsigned long long *__restrict__ npairs) {
-  constexpr int NLM = NL * NL;
-  extern __shared__ __align__(16) double lds[];
-  double *ylds = lds;                          // [NLM + 1][kYStride], row NLM all zeros
-  double *gtop = lds + kYStride * (NLM + 1);   // [NL][kBatch]: k_NK^3 G_l(k_NK r_q), 16 bins
-  double *atile = gtop;                        // [NL][16][16] between primaries
-  // hit buffer; slot kHitCap is a neutral pair (weight 0) read by lanes
-  // past the end of a batch, so that no operand load needs a condition
-  __shared__ double hb_r[kHitCap + 1], hb_ir[kHitCap + 1], hb_f[kHitCap + 1], hb_x[kHitCap], hb_y[kHitCap],
-      hb_z[kHitCap];
-  __shared__ int64_t nb_beg[27], nb_end[27], run_beg[27], run_end[27];
-  // sine/cosine table for the mixed form's closed branch (64 entries: the
-  // LDS of four one-wave workgroups per CU has room for 1 KB more)
-  __shared__ double2 sc_tab[FP64 ? 1 : kSinCosTabBk];
-  if constexpr (!FP64) {
-    stage_sincos_tab<kSinCosTabBk>(sc_tab);
-    __syncthreads();
-  }
-  __shared__ int nb_sh[27], run_sh[27], n_runs_s;
-  const int lane = threadIdx.x, t4 = lane >> 4, col = lane & 15;
-  // per-lane edge constants: this lane evaluates edge `col`, bin `col`
-  const bool has_bin = col < NK;
-  const double ke = edges[col <= NK ? col : NK];
-  const double ke3 = ke * ke * ke;
-  const double ike = ke > 0.0 ? 1.0 / ke : 0.0;
-  const double kn = edges[col + 1 <= NK ? col + 1 : NK];
-  const double kn3 = kn * kn * kn;
-  const double cfb = has_bin ? coef[col] : 0.0;
-  const bool top16 = NK == kMaxNkB;             // the 17th edge is evaluated per pair
-  const bool top_lane = top16 && col == kMaxNkB - 1;
-  const double ktop = edges[NK], ktop3 = ktop * ktop * ktop, iktop = ktop > 0.0 ? 1.0 / ktop : 0.0;
-  const int src = (lane & 48) | ((col + 1) & 15);
-  constexpr double kY00 = 0.28209479177387814347;  // y_00 = 1/(2 sqrt(pi))
+__device__ inline double bk_sq_norm(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  double a = dx * dx;
+  double b = dy * dy;
+  double c = dz * dz;
+  return (a + b) + c;
+}
 
-  d4_t accA[NL], accC[NL], accG[NL];
+// Orders the wave's LDS accesses: every lane's earlier LDS writes are visible
+// to every lane's later LDS reads (one wave per workgroup).
+__device__ inline void wave_sync() { __syncthreads(); }
+
+constexpr int kXcds = 8;             // accelerator complex dies of the MI355X (the grid is a multiple)
+constexpr int kQuadRun = 4;          // consecutive quads per wave assignment
+constexpr int kHitCap = 128;         // hit ring buffer per row (power of two)
+constexpr int kRowBatch = 16;        // pairs per row per batch
+constexpr int kYStride = 65;         // y staging row stride (slots 0..63, odd: conflict-free reads)
+constexpr int kSinCosTabBk = 64;     // sine/cosine table entries (LDS)
+
+// Writes w_q W y_lm of one slot into the y staging as real_ylm produces it:
+// element idx goes to base[idx * kYStride], scaled by f.
+template <typename YT>
+struct YStore {
+  YT *base;
+  double f;
+  struct Ref {
+    YT *p;
+    double f;
+    __device__ void operator=(double v) const { *p = YT(f * v); }
+  };
+  __device__ Ref operator[](int idx) const { return Ref{base + idx * kYStride, f}; }
+};
+
+// Four primaries of one home cell (sorted indices; -1 = none, never first).
+struct BkQuad {
+  int p[4];
+};
+
+// Arguments of one sweep launch.
+struct BkArgs {
+  Sorted prim, sec;
+  const BkQuad *quads;
+  int64_t q_lo, q_hi;  // quads of this launch
+  int nc;
+  double L, r02, inv_r0;
+  int self_set;
+  const double *edges;  // n_k + 1
+  const double *coef;   // n_k: 3 / (k_{a+1}^3 - k_a^3)
+  int n_k, group;       // bins 16 group .. 16 group + 15 of this pass
+  double *partial;      // per-wave rows
+  int rowlen;
+  double *abuf;         // more than 16 bins: A of slot 4 (q - q_lo) + row, [NL^2][ld]
+  double *wbuf;         // and w_p of that slot
+  int ld;               // 16 * groups
+  unsigned long long *npairs;
+};
+
+// Per-wave row layout.  Up to 16 bins: [G tiles NL*256 | C tiles NL*256 | S0 64];
+// more: [S0 64 per group].  S0 entries are (row, bin) = 16 row + bin; their sum
+// over rows is the S0 sum times 1/y_00.
+__host__ __device__ inline int bk_rowlen(int NL, int groups) { return groups == 1 ? 2 * NL * 256 + 64 : 64 * groups; }
+
+// y staging element: double in both forms (single-precision staging of
+// w_q W y_lm left B errors at ~1 unit of 2^-24 of its scale on small boxes)
+template <bool FP64>
+using YStage = double;
+
+template <int NL, bool FP64>
+size_t bk_lds_bytes() {
+  return size_t(NL * NL) * kYStride * sizeof(YStage<FP64>);
+}
+
+// G_l(u), l = 0 .. NL-1: the mixed form (double-precision table sine/cosine,
+// single-precision sine-integral auxiliaries; Taylor series below u = 2) or
+// the FP64 form.
+template <int NL, bool FP64>
+__device__ inline Gv<double, NL> G_any(double u, double wd, const double2 *tab) {
+  if constexpr (FP64) return G_fp64<NL, 1>(u);
+  else return G_mixed_w<NL, 1, kSinCosTabBk, false>(u, wd, tab);
+}
+
+// Every lane's u >= U_BIG: closed form without branches.
+template <int NL>
+__device__ inline Gv<double, NL> G_far(double u, double wd, const double2 *tab) {
+  Gv<double, NL> D = Dt_far<NL, 1, false, kSinCosTabBk>(u, wd, tab);
+  const double w3 = wd * wd * wd;
+#pragma unroll
+  for (int l = 0; l < NL; ++l) D.v[l] *= w3;
+  return D;
+}
+
+// fmac_block for l = L .. NL-1 (compile-time recursion).
+template <int L, int NL, int NA, int NY>
+__device__ __forceinline__ void fmac_all(double (&acc)[NA], const double (&yr)[NY], const double (&gl)[NL]) {
+  if constexpr (L < NL) {
+    fmac_block<L>(acc, yr, gl[L]);
+    fmac_all<L + 1>(acc, yr, gl);
+  }
+}
+
+// Waves per SIMD the compiler must fit the sweep into (registers); more
+// waves hide the latency of the candidate and staging loads.
+#ifndef HIPSTER_BK_WAVES
+#define HIPSTER_BK_WAVES 2
+#endif
+
+template <int NL, bool FP64, bool WITH_C, bool GRAM>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HIPSTER_BK_WAVES : 1))) void k_bk_quad(
+    BkArgs A) {
+  constexpr int NLM = NL * NL;
+  constexpr int NY = (NLM + 15) / 16;
+  using YT = YStage<FP64>;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  YT *ylds = reinterpret_cast<YT *>(lds_raw);  // [NLM][kYStride]: w_q W y_lm of slot 16 row + i
+  __shared__ double s_r[64], s_ir[64], s_f[64], s_gt[NL][64];
+  __shared__ int hl_j[4][kHitCap];
+  __shared__ unsigned char hl_s[4][kHitCap];
+  __shared__ int64_t nb_beg[27], nb_end[27], run_beg[27], run_end[27];
+  __shared__ int nb_sh[27], run_sh[27], n_runs_s;
+  __shared__ double2 sc_tab[FP64 ? 1 : kSinCosTabBk];
+  if constexpr (!FP64) stage_sincos_tab<kSinCosTabBk>(sc_tab);
+
+  const int lane = threadIdx.x, row = lane >> 4, col = lane & 15;
+  const int64_t e0 = int64_t(16) * A.group;
+  const int NK = A.n_k;
+  // this lane's edge e = 16 g + col (clamped) and bin e (if it exists)
+  const int e = int(e0) + col;
+  const bool has_bin = e < NK;
+  const double ke = A.edges[e <= NK ? e : NK];
+  const double ke3 = ke * ke * ke, ike = ke > 0.0 ? 1.0 / ke : 0.0;
+  const double kn = A.edges[e + 1 <= NK ? e + 1 : NK];
+  const double kn3 = kn * kn * kn;
+  const double cfb = has_bin ? A.coef[e] : 0.0;
+  // a full group of 16 bins takes its top edge 16 g + 16 from the staging
+  const bool top = e0 + 16 <= NK;
+  const bool top_lane = top && col == 15;
+  const double ktop = top ? A.edges[e0 + 16] : 0.0;
+  const double ktop3 = ktop * ktop * ktop, iktop = ktop > 0.0 ? 1.0 / ktop : 0.0;
+  const double r_neutral = 0.5 / A.inv_r0, ir_neutral = 2.0 * A.inv_r0;
+  const double L = A.L;
+
+  d4_t accG[NL], accC[NL];
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
-    accC[l] = d4_t{0.0, 0.0, 0.0, 0.0};
     accG[l] = d4_t{0.0, 0.0, 0.0, 0.0};
+    accC[l] = d4_t{0.0, 0.0, 0.0, 0.0};
   }
-  double accS0 = 0.0;
+  double s0acc = 0.0;
+  // an AGPR operand makes the backend choose the matrix instructions' AGPR
+  // form, so the Gram accumulators live in AGPRs, not in the VGPRs the sweep needs
+  if constexpr (GRAM) asm volatile("" ::"a"(accG[0]));
   unsigned long long pcount = 0;
   int64_t cur_cell = -1;
-  if (lane == 0) {
-    hb_r[kHitCap] = 0.5 / inv_r0;
-    hb_ir[kHitCap] = 2.0 * inv_r0;
-    hb_f[kHitCap] = 0.0;
-  }
-  ylds[NLM * kYStride + lane] = 0.0;
+  wave_sync();
 
   // XCD-aware assignment: workgroups are dealt to the 8 XCDs round-robin, so
   // the waves of XCD x (blockIdx % 8 == x) share one contiguous eighth of the
-  // primaries (a slab of cells), whose neighbour data then stays in that
-  // XCD's L2.  Within the slab, runs of kPrimRun go round-robin to its waves.
+  // quads (a slab of cells), whose neighbour data then stays in that XCD's
+  // L2.  Within the slab, runs of kQuadRun quads go round-robin to its waves.
   const int xcd = int(blockIdx.x % kXcds), wx = int(blockIdx.x / kXcds), nwx = int(gridDim.x / kXcds);
-  const int64_t np = p_hi - p_lo;
-  const int64_t s_lo = p_lo + np * xcd / kXcds, s_hi = p_lo + np * (xcd + 1) / kXcds;
-  for (int64_t c0 = s_lo + int64_t(wx) * kPrimRun; c0 < s_hi; c0 += int64_t(nwx) * kPrimRun) {
-    const int64_t c1 = c0 + kPrimRun < s_hi ? c0 + kPrimRun : s_hi;
-    for (int64_t p = c0; p < c1; ++p) {
-      if (prim.m && !prim.m[p]) continue;
-      const int64_t cell = prim.scell[p];
+  const int64_t nq = A.q_hi - A.q_lo;
+  const int64_t s_lo = A.q_lo + nq * xcd / kXcds, s_hi = A.q_lo + nq * (xcd + 1) / kXcds;
+  for (int64_t c0 = s_lo + int64_t(wx) * kQuadRun; c0 < s_hi; c0 += int64_t(nwx) * kQuadRun) {
+    const int64_t c1 = c0 + kQuadRun < s_hi ? c0 + kQuadRun : s_hi;
+    for (int64_t qi = c0; qi < c1; ++qi) {
+      const BkQuad qd = A.quads[qi];
+      int qp[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) qp[r] = __builtin_amdgcn_readfirstlane(qd.p[r]);
+      const int64_t cell = A.prim.scell[qp[0]];
       if (cell != cur_cell) {
-        // neighbour cells in (dx, dy, dz) order, then merged into runs
+        // neighbour cells in (dx, dy, dz) order, merged into runs of the
+        // sorted secondaries (cells adjacent along z are adjacent in memory)
+        const int nc = A.nc;
         const int cz = int(cell % nc), cy = int((cell / nc) % nc), cx = int(cell / (int64_t(nc) * nc));
-        __syncthreads();
         if (lane < 27) {
-          int sx, sy, sz;
-          const int nx = bk_wrap(cx + lane / 9 - 1, nc, sx), ny = bk_wrap(cy + (lane / 3) % 3 - 1, nc, sy),
-                    nz = bk_wrap(cz + lane % 3 - 1, nc, sz);
+          int sx = 0, sy = 0, sz = 0;
+          int nx = cx + lane / 9 - 1, ny = cy + (lane / 3) % 3 - 1, nz = cz + lane % 3 - 1;
+          if (nx >= nc) { nx -= nc; sx = 1; } else if (nx < 0) { nx += nc; sx = -1; }
+          if (ny >= nc) { ny -= nc; sy = 1; } else if (ny < 0) { ny += nc; sy = -1; }
+          if (nz >= nc) { nz -= nc; sz = 1; } else if (nz < 0) { nz += nc; sz = -1; }
           const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
-          nb_beg[lane] = sec.cell_start[nb];
-          nb_end[lane] = sec.cell_start[nb + 1];
+          nb_beg[lane] = A.sec.cell_start[nb];
+          nb_end[lane] = A.sec.cell_start[nb + 1];
           nb_sh[lane] = (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1);
         }
-        __syncthreads();
+        wave_sync();
         if (lane == 0) {
           int nr = 0;
           for (int k = 0; k < 27; ++k) {
@@ -266,85 +299,135 @@ k_bk_fused(
           }
           n_runs_s = nr;
         }
-        __syncthreads();
+        wave_sync();
         cur_cell = cell;
       }
       const int n_runs = __builtin_amdgcn_readfirstlane(n_runs_s);
-      const double xi = prim.x[p], yi = prim.y[p], zi = prim.z[p], wp = prim.w[p];
+      // the four primaries (uniform), and this row's
+      double qx[4], qy[4], qz[4];
 #pragma unroll
-      for (int l = 0; l < NL; ++l) accA[l] = d4_t{0.0, 0.0, 0.0, 0.0};
-      double a0 = 0.0;  // sum over this lane's pairs of g_0 for bin col
-      int nh = 0;
+      for (int r = 0; r < 4; ++r) {
+        const int pp = qp[r] >= 0 ? qp[r] : qp[0];
+        qx[r] = uniform_f64(A.prim.x[pp]);
+        qy[r] = uniform_f64(A.prim.y[pp]);
+        qz[r] = uniform_f64(A.prim.z[pp]);
+      }
+      const int my_p = row == 0 ? qp[0] : row == 1 ? qp[1] : row == 2 ? qp[2] : qp[3];
+      const bool my_valid = my_p >= 0;
+      const int my_pp = my_valid ? my_p : qp[0];
+      const double px = A.prim.x[my_pp], py = A.prim.y[my_pp], pz = A.prim.z[my_pp];
+      const double wp = my_valid ? A.prim.w[my_pp] : 0.0;
 
-      auto batch = [&](int nv) {
-        // y_lm of pair `lane` (zeros past the batch), and for 16 bins the
-        // value at the top edge
-        if (lane < nv) {
-          real_ylm<NL - 1>(hb_x[lane], hb_y[lane], hb_z[lane], YRow{ylds + lane});
-        } else {
+      double acc[NLM];
 #pragma unroll
-          for (int k = 0; k < NLM; ++k) ylds[k * kYStride + lane] = 0.0;
-        }
-        if (top16) {
-          const bool v = lane < nv;
-          const double rq = v ? hb_r[lane] : 0.0, irq = v ? hb_ir[lane] : 0.0;
-          Gv<double, NL> T;
-          if constexpr (FP64) T = G_fp64<NL, 1>(ktop * rq);
-          else T = G_mixed_w<NL, 1, kSinCosTabBk>(ktop * rq, iktop * irq, sc_tab);
+      for (int k = 0; k < NLM; ++k) acc[k] = 0.0;
+      int hn[4] = {0, 0, 0, 0}, hh[4] = {0, 0, 0, 0};  // per-row hit count and ring head (uniform)
+
+      // one batch: up to kRowBatch pairs of each row
+      auto batch = [&]() {
+        int cnt[4];
+        int cmax = 0;
 #pragma unroll
-          for (int l = 0; l < NL; ++l) gtop[l * kBatch + lane] = ktop3 * T.v[l];
+        for (int r = 0; r < 4; ++r) {
+          cnt[r] = hn[r] < kRowBatch ? hn[r] : kRowBatch;
+          cmax = cnt[r] > cmax ? cnt[r] : cmax;
         }
-        __syncthreads();
-        // 4 pairs per step: lane (col, t4) evaluates G_l at edge col for pair
-        // q = 4s + t4, takes edge col+1 from the next lane, and feeds bin col
-        // of pair q to the matrix instructions.  Lanes past the batch read the
-        // neutral slot, and columns outside an l block read the zero row, so
-        // every load is unconditional.
-        const int nsteps = (nv + 3) >> 2;
-        for (int s = 0; s < nsteps; ++s) {
-          const int q = 4 * s + t4;
-          const int qe = q < nv ? q : kHitCap;
-          const double rq = hb_r[qe], irq = hb_ir[qe];
-          const double fb = hb_f[qe] * cfb;
+        const int my_cnt = row == 0 ? cnt[0] : row == 1 ? cnt[1] : row == 2 ? cnt[2] : cnt[3];
+        const int my_head = row == 0 ? hh[0] : row == 1 ? hh[1] : row == 2 ? hh[2] : hh[3];
+        // staging, lane = slot (row, i = col)
+        {
+          double r = r_neutral, ir = ir_neutral, f = 0.0, ux = 0.0, uy = 0.0, uz = 1.0;
+          if (col < my_cnt) {
+            const int idx = (my_head + col) & (kHitCap - 1);
+            const int j = hl_j[row][idx];
+            const int sh = hl_s[row][idx];
+            const double ox = double(sh / 9 - 1) * L, oy = double((sh / 3) % 3 - 1) * L, oz = double(sh % 3 - 1) * L;
+            const double dx = (px - A.sec.x[j]) - ox;
+            const double dy = (py - A.sec.y[j]) - oy;
+            const double dz = (pz - A.sec.z[j]) - oz;
+            const double r2 = bk_sq_norm(dx, dy, dz);
+            r = sqrt(r2);
+            ir = r > 0.0 ? 1.0 / r : 0.0;
+            f = A.sec.w[j] * window<double>(r * A.inv_r0);
+            if (r > 0.0) {
+              ux = dx * ir;
+              uy = dy * ir;
+              uz = dz * ir;
+            }
+          }
+          real_ylm<NL - 1>(ux, uy, uz, YStore<YT>{ylds + lane, f});
+          s_r[lane] = r;
+          s_ir[lane] = ir;
+          s_f[lane] = f;
+          if (top) {
+            const Gv<double, NL> T = G_any<NL, FP64>(ktop * r, iktop * ir, sc_tab);
+#pragma unroll
+            for (int l = 0; l < NL; ++l) s_gt[l][lane] = ktop3 * T.v[l];
+          }
+        }
+        wave_sync();
+        // steps: one pair per row
+        for (int s = 0; s < cmax; ++s) {
+          const int slot = 16 * row + s;
+          const double rq = s_r[slot], irq = s_ir[slot];
+          double yr[NY];
+#pragma unroll
+          for (int i = 0; i < NY; ++i) {
+            const int k = col + 16 * i;
+            yr[i] = k < NLM ? double(ylds[k * kYStride + slot]) : 0.0;
+          }
+          const double u = ke * rq, wd = ike * irq;
           Gv<double, NL> Ge;
-          if constexpr (FP64) Ge = G_fp64<NL, 1>(ke * rq);
-          else Ge = G_mixed_w<NL, 1, kSinCosTabBk>(ke * rq, ike * irq, sc_tab);
+          if constexpr (FP64) {
+            Ge = G_any<NL, true>(u, wd, sc_tab);
+          } else {
+            if (__ballot(u < HIPSTER_U_BIG) == 0ull) Ge = G_far<NL>(u, wd, sc_tab);
+            else Ge = G_any<NL, false>(u, wd, sc_tab);
+          }
+          double gl[NL];
 #pragma unroll
           for (int l = 0; l < NL; ++l) {
             const double gn = from_next_lane_in_row(Ge.v[l]);
-            const double hi = top_lane ? gtop[l * kBatch + q] : kn3 * gn;
-            const double g = fb * (hi - ke3 * Ge.v[l]);
-            if (l == 0) {
-              a0 += g;
-            } else {
-              const int row = col < 2 * l + 1 ? l * l + col : NLM;
-              const double y = ylds[row * kYStride + q];
-              accA[l] = mfma_f64(g, y, accA[l]);
+            const double hi = top_lane ? s_gt[l][slot] : kn3 * gn;
+            gl[l] = cfb * (hi - ke3 * Ge.v[l]);
+          }
+          // acc[l*l+m] += (w_q W y_lm)(pair) * jbar^a_l(pair)
+          fmac_all<0>(acc, yr, gl);
+          if constexpr (WITH_C) {
+            const double fq = s_f[slot];
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+              const double gq = gl[l] * fq;
+              accC[l] = mfma_f64(gq, wp * gq, accC[l]);
             }
-            if constexpr (WITH_C) accC[l] = mfma_f64(g * wp, g, accC[l]);
           }
         }
-        __syncthreads();
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          hh[r] = (hh[r] + cnt[r]) & (kHitCap - 1);
+          hn[r] -= cnt[r];
+        }
       };
 
       // scan: runs of candidates, 64 at a time, the next step's loads in flight
       int ri = 0;
       int64_t pos = n_runs > 0 ? uniform_i64(run_beg[0]) : 0;
       bool have = n_runs > 0;
-      double cx = 0.0, cy = 0.0, cz = 0.0, cw = 0.0;
-      int64_t cj = 0;
+      double cx = 0.0, cy = 0.0, cz = 0.0;
+      int cj = 0;
       bool cok = false;
       int csh = 13;
-      auto fetch = [&](double &x, double &y, double &z, double &w, int64_t &j, bool &ok, int &sh) {
+      auto fetch = [&](double &x, double &y, double &z, int &j, bool &ok, int &sh) {
         const int64_t end = uniform_i64(run_end[ri]);
         sh = __builtin_amdgcn_readfirstlane(run_sh[ri]);
-        j = pos + lane;
-        ok = j < end;
+        const int64_t jj = pos + lane;
+        ok = jj < end;
+        j = int(jj);
         if (ok) {
-          x = sec.x[j];
-          y = sec.y[j];
-          z = sec.z[j];
-          w = sec.w[j];
+          x = A.sec.x[jj];
+          y = A.sec.y[jj];
+          z = A.sec.z[jj];
         }
         pos += 64;
         if (pos >= end) {
@@ -352,154 +435,343 @@ k_bk_fused(
           if (ri < n_runs) pos = uniform_i64(run_beg[ri]);
         }
       };
-      if (have) fetch(cx, cy, cz, cw, cj, cok, csh);
+      if (have) fetch(cx, cy, cz, cj, cok, csh);
       while (have) {
         const bool have_next = ri < n_runs;
-        double nx = 0.0, ny = 0.0, nz = 0.0, nw = 0.0;
-        int64_t nj = 0;
+        double nx = 0.0, ny = 0.0, nz = 0.0;
+        int nj = 0;
         bool nok = false;
         int nsh = 13;
-        if (have_next) fetch(nx, ny, nz, nw, nj, nok, nsh);
-        bool hit = false;
-        double dx = 0.0, dy = 0.0, dz = 0.0, r2 = 0.0;
-        if (cok) {
-          dx = bk_image(xi - cx, csh / 9 - 1, L);
-          dy = bk_image(yi - cy, (csh / 3) % 3 - 1, L);
-          dz = bk_image(zi - cz, csh % 3 - 1, L);
-          r2 = bk_sq_norm(dx, dy, dz);
-          hit = r2 < r02 && !(self_set && csh == 13 && cj == p);
-        }
-        const unsigned long long bal = __ballot(hit);
-        if (hit) {
-          const int k = nh + __popcll(bal & ((1ull << lane) - 1ull));
-          const double r = sqrt(r2);
-          const double inv = r > 0.0 ? 1.0 / r : 0.0;
-          hb_r[k] = r;
-          hb_ir[k] = inv;
-          hb_f[k] = cw * window<double>(r * inv_r0);
-          hb_x[k] = r > 0.0 ? dx * inv : 0.0;
-          hb_y[k] = r > 0.0 ? dy * inv : 0.0;
-          hb_z[k] = r > 0.0 ? dz * inv : 1.0;
-        }
-        const int added = __popcll(bal);
-        nh += added;
-        pcount += unsigned(added);
-        // a step can leave up to kBatch - 1 + 64 hits: run batches until
-        // fewer than kBatch remain, so the next step fits in the buffer
-        while (nh >= kBatch) {
-          __syncthreads();
-          batch(kBatch);
-          // keep the overflow: entries [kBatch, nh) move to the front
-          const int rest = nh - kBatch;
-          double vr = 0, vi = 0, vf = 0, vx = 0, vy = 0, vz = 0;
-          if (lane < rest) {
-            vr = hb_r[kBatch + lane];
-            vi = hb_ir[kBatch + lane];
-            vf = hb_f[kBatch + lane];
-            vx = hb_x[kBatch + lane];
-            vy = hb_y[kBatch + lane];
-            vz = hb_z[kBatch + lane];
+        if (have_next) fetch(nx, ny, nz, nj, nok, nsh);
+        const double ox = double(csh / 9 - 1) * L, oy = double((csh / 3) % 3 - 1) * L, oz = double(csh % 3 - 1) * L;
+        const bool self_run = A.self_set && csh == 13;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          bool hit = false;
+          if (cok && qp[r] >= 0) {
+            const double dx = (qx[r] - cx) - ox;
+            const double dy = (qy[r] - cy) - oy;
+            const double dz = (qz[r] - cz) - oz;
+            hit = bk_sq_norm(dx, dy, dz) < A.r02 && !(self_run && cj == qp[r]);
           }
-          __syncthreads();
-          if (lane < rest) {
-            hb_r[lane] = vr;
-            hb_ir[lane] = vi;
-            hb_f[lane] = vf;
-            hb_x[lane] = vx;
-            hb_y[lane] = vy;
-            hb_z[lane] = vz;
+          const unsigned long long bal = __ballot(hit);
+          if (hit) {
+            const int k = (hh[r] + hn[r] + __popcll(bal & ((1ull << lane) - 1ull))) & (kHitCap - 1);
+            hl_j[r][k] = cj;
+            hl_s[r][k] = (unsigned char)csh;
           }
-          nh = rest;
+          const int added = __popcll(bal);
+          hn[r] += added;
+          pcount += unsigned(added);
+        }
+        // a batch when every row has a full batch, or before a row could
+        // overflow in the next step (each step adds at most 64 hits per row)
+        for (;;) {
+          const int mn = min(min(hn[0], hn[1]), min(hn[2], hn[3]));
+          const int mx = max(max(hn[0], hn[1]), max(hn[2], hn[3]));
+          if (!(mn >= kRowBatch || mx > kHitCap - 64)) break;
+          wave_sync();
+          batch();
         }
         cx = nx;
         cy = ny;
         cz = nz;
-        cw = nw;
         cj = nj;
         cok = nok;
         csh = nsh;
         have = have_next;
       }
-      if (nh > 0) {
-        __syncthreads();
-        batch(nh);
-      }
-      // l = 0: A_00[a] = y_00 S_a with S_a = sum_q g_0[q][a]; the Gram term
-      // w_p 4 pi y_00^2 S_a S_b = w_p S_a S_b and the S0 sum w_p S_b follow
-      double sa = a0;
-      sa += __shfl_xor(sa, 16);
-      sa += __shfl_xor(sa, 32);
-      accS0 = fma(wp, sa, accS0);
-      const double wsa = wp * sa;
+      wave_sync();
+      while (max(max(hn[0], hn[1]), max(hn[2], hn[3])) > 0) batch();
+
+      // the quad's contribution
+      if constexpr (GRAM) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) accG[0][v] = fma(__shfl(sa, t4 + 4 * v), wsa, accG[0][v]);
-      // l >= 1: G_l += w_p (4 pi/(2l+1)) A_l A_l^T through an LDS transpose of A
-      if constexpr (NL > 1) {
+        for (int l = 0; l < NL; ++l) {
+          const double wsc = wp * (4.0 * kPi / double(2 * l + 1));
 #pragma unroll
-        for (int l = 1; l < NL; ++l)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) atile[l * 256 + (t4 + 4 * v) * 16 + col] = accA[l][v];
-        __syncthreads();
-#pragma unroll
-        for (int l = 1; l < NL; ++l) {
-          const double sc = wp * (4.0 * kPi / double(2 * l + 1));
-#pragma unroll
-          for (int s2 = 0; s2 < 4; ++s2) {
-            const double x = atile[l * 256 + col * 16 + 4 * s2 + t4];
-            accG[l] = mfma_f64(x * sc, x, accG[l]);
-          }
+          for (int m = 0; m < 2 * l + 1; ++m) accG[l] = mfma_f64(acc[l * l + m], wsc * acc[l * l + m], accG[l]);
         }
-        __syncthreads();
+      } else {
+        const int64_t slot = (qi - A.q_lo) * 4 + row;
+        double *ap = A.abuf + slot * NLM * A.ld + e0 + col;
+#pragma unroll
+        for (int k = 0; k < NLM; ++k) ap[int64_t(k) * A.ld] = acc[k];
+        if (col == 0) A.wbuf[slot] = wp;
       }
+      s0acc = fma(wp, acc[0], s0acc);
     }
   }
-  (void)kY00;
-  // per-wave partial row: [G tiles NL*256 | C tiles NL*256 | S0 16], zeroed by the host
-  double *row = partial + int64_t(blockIdx.x) * rowlen;
+  double *out = A.partial + int64_t(blockIdx.x) * A.rowlen;
+  if constexpr (GRAM) {
 #pragma unroll
-  for (int l = 0; l < NL; ++l)
+    for (int l = 0; l < NL; ++l)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int e = (t4 + 4 * v) * 16 + col;
-      row[l * 256 + e] += accG[l][v];
-      if constexpr (WITH_C) row[NL * 256 + l * 256 + e] += accC[l][v];
-    }
-  if (t4 == 0) row[2 * NL * 256 + col] += accS0;
-  if (lane == 0 && pcount) atomicAdd(npairs, pcount);
+      for (int v = 0; v < 4; ++v) {
+        const int t = (row + 4 * v) * 16 + col;
+        out[l * 256 + t] += accG[l][v];
+        if constexpr (WITH_C) out[NL * 256 + l * 256 + t] += accC[l][v];
+      }
+    out[2 * NL * 256 + lane] += s0acc;
+  } else {
+    out[64 * A.group + lane] += s0acc;
+  }
+  if (lane == 0 && pcount && A.group == 0) atomicAdd(A.npairs, pcount);
 }
 
-template <int NL>
-static void launch_fused(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
-                         const double *edges, const double *coef, int NK, bool fp64, bool with_c, double *partial,
-                         int rowlen, int nwaves, unsigned long long *npairs) {
-  const size_t lds = bk_fused_lds(NL, NK);
-  if (prim.n == 0) return;
-  if (NK < 1 || NK > kMaxNkB) throw Error{HIPSTER_EUNSUPPORTED, "bispectrum: n_k outside [1, 16]"};
-  if (nwaves < kXcds || nwaves % kXcds) throw Error{HIPSTER_EINVAL, "bispectrum: wave count must be a multiple of 8"};
-  if (fp64 && !with_c) throw Error{HIPSTER_EINVAL, "bispectrum: the FP64 form sums C in the fused kernel"};
-  if (fp64)
-    k_bk_fused<NL, true, true><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(
-        prim, sec, g.nc, g.L, r0 * r0, self_set ? 1 : 0, 0, prim.n, 1.0 / r0, edges, coef, NK, partial, rowlen, npairs);
-  else if (with_c)
-    k_bk_fused<NL, false, true><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(
-        prim, sec, g.nc, g.L, r0 * r0, self_set ? 1 : 0, 0, prim.n, 1.0 / r0, edges, coef, NK, partial, rowlen, npairs);
-  else
-    k_bk_fused<NL, false, false><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(
-        prim, sec, g.nc, g.L, r0 * r0, self_set ? 1 : 0, 0, prim.n, 1.0 / r0, edges, coef, NK, partial, rowlen, npairs);
+// Gram of the A buffer: one wave per (tile, chunk of slots), tile = (l, ga,
+// gb), ga <= gb; the K dimension runs over (slot, m), four at a time.
+// gpart[chunk][tile][256] += the tile's sum over the chunk (one wave per
+// entry per launch, launches in stream order: deterministic).
+struct GramTile {
+  int l, ga, gb, pad;
+};
+
+__global__ __launch_bounds__(64) void k_bk_gram(const double *__restrict__ abuf, const double *__restrict__ wbuf,
+                                                int64_t nslots, int NLM, int ld, const GramTile *__restrict__ tiles,
+                                                int ntiles, int nchunks, double *__restrict__ gpart) {
+  const int t = int(blockIdx.x % unsigned(ntiles)), ch = int(blockIdx.x / unsigned(ntiles));
+  const int lane = threadIdx.x, row = lane >> 4, col = lane & 15;
+  const GramTile T = tiles[t];
+  const int nm = 2 * T.l + 1;
+  const double sc = 4.0 * kPi / double(nm);
+  const int64_t s_lo = nslots * ch / nchunks, s_hi = nslots * (ch + 1) / nchunks;
+  const int64_t k_lo = s_lo * nm, k_hi = s_hi * nm;
+  d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = k_lo; k0 < k_hi; k0 += 4) {
+    const int64_t K = k0 + row;
+    double a = 0.0, b = 0.0;
+    if (K < k_hi) {
+      const int64_t slot = K / nm;
+      const int m = int(K - slot * nm);
+      const double *base = abuf + (slot * NLM + T.l * T.l + m) * ld;
+      a = base[16 * T.ga + col];
+      b = wbuf[slot] * sc * base[16 * T.gb + col];
+    }
+    acc = mfma_f64(a, b, acc);
+  }
+  double *o = gpart + (int64_t(ch) * ntiles + t) * 256;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) o[(row + 4 * v) * 16 + col] += acc[v];
+}
+
+// ------------------------------------------------------------------ quads
+// Quads of a catalogue: per cell, its (selected) primaries in sorted order,
+// four at a time.
+__global__ __launch_bounds__(256) void k_quad_count(const int64_t *__restrict__ cell_start,
+                                                    const uint8_t *__restrict__ mask, int64_t ncells,
+                                                    int64_t *__restrict__ qcount) {
+  const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (c >= ncells) return;
+  const int64_t b = cell_start[c], e = cell_start[c + 1];
+  int64_t n = e - b;
+  if (mask) {
+    n = 0;
+    for (int64_t p = b; p < e; ++p) n += mask[p] ? 1 : 0;
+  }
+  qcount[c] = (n + 3) / 4;
+}
+
+__global__ __launch_bounds__(256) void k_quad_fill(const int64_t *__restrict__ cell_start,
+                                                   const uint8_t *__restrict__ mask, int64_t ncells,
+                                                   const int64_t *__restrict__ qoff, BkQuad *__restrict__ quads) {
+  const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (c >= ncells) return;
+  const int64_t b = cell_start[c], e = cell_start[c + 1];
+  int64_t o = qoff[c];
+  BkQuad q{{-1, -1, -1, -1}};
+  int k = 0;
+  for (int64_t p = b; p < e; ++p) {
+    if (mask && !mask[p]) continue;
+    q.p[k++] = int(p);
+    if (k == 4) {
+      quads[o++] = q;
+      q = BkQuad{{-1, -1, -1, -1}};
+      k = 0;
+    }
+  }
+  if (k) quads[o] = q;
+}
+
+// ------------------------------------------------------------------- host
+template <int NL, bool FP64, bool WITH_C, bool GRAM>
+static void launch_quad(Ctx &c, const BkArgs &a, int nwaves) {
+  const size_t lds = bk_lds_bytes<NL, FP64>();
+  k_bk_quad<NL, FP64, WITH_C, GRAM><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(a);
   HIPSTER_HIP(hipGetLastError());
 }
 
-void bk_fused(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
-              const double *edges, const double *coef, int NK, int ell_max, bool fp64, bool with_c, double *partial,
-              int rowlen, int nwaves, unsigned long long *npairs) {
+template <int NL, bool FP64, bool WITH_C, bool GRAM>
+static int quad_waves(Ctx &c) {
+  int per_cu = 0;
+  const size_t lds = bk_lds_bytes<NL, FP64>();
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bk_quad<NL, FP64, WITH_C, GRAM>, 64, lds) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  hipDeviceProp_t prop{};
+  int cus = 256;
+  if (hipGetDeviceProperties(&prop, c.device) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  int n = cus * per_cu;
+  return std::max(kXcds, n / kXcds * kXcds);
+}
+
+template <int NL>
+static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
+                        const double *edges, const double *coef, int NK, bool fp64, bool with_c,
+                        unsigned long long *npairs, BkSums &out) {
+  const int groups = (NK + 15) / 16;
+  if (fp64 && groups > 1)
+    throw Error{HIPSTER_EUNSUPPORTED, "bispectrum: the FP64 form takes at most 16 bins (its C sums are per pair)"};
+  if (with_c && !fp64) throw Error{HIPSTER_EINVAL, "bispectrum: the mixed form takes C from the pair histogram"};
+  out.NL = NL;
+  out.NK = NK;
+  out.G.assign(size_t(NL) * NK * NK, 0.0);
+  out.C.assign(size_t(NL) * NK * NK, 0.0);
+  out.S0.assign(size_t(NK), 0.0);
+  if (prim.n == 0) return;
+  // quads
+  const int64_t ncells = g.ncells();
+  int64_t *qcount = static_cast<int64_t *>(ensure(c, c.bq_count, size_t(ncells + 1) * 8));
+  int64_t *qoff = static_cast<int64_t *>(ensure(c, c.bq_off, size_t(ncells + 1) * 8));
+  const unsigned cb = unsigned((ncells + 255) / 256);
+  k_quad_count<<<dim3(cb), dim3(256), 0, c.stream>>>(prim.cell_start, prim.m, ncells, qcount);
+  HIPSTER_HIP(hipGetLastError());
+  scan_i64(c, qcount, qoff, ncells, c.bq_scan);
+  int64_t nq = 0;
+  HIPSTER_HIP(hipMemcpyAsync(&nq, qoff + ncells, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  if (nq == 0) return;
+  BkQuad *quads = static_cast<BkQuad *>(ensure(c, c.bq_quads, size_t(nq) * sizeof(BkQuad)));
+  k_quad_fill<<<dim3(cb), dim3(256), 0, c.stream>>>(prim.cell_start, prim.m, ncells, qoff, quads);
+  HIPSTER_HIP(hipGetLastError());
+
+  BkArgs a{};
+  a.prim = prim;
+  a.sec = sec;
+  a.quads = quads;
+  a.nc = g.nc;
+  a.L = g.L;
+  a.r02 = r0 * r0;
+  a.inv_r0 = 1.0 / r0;
+  a.self_set = self_set ? 1 : 0;
+  a.edges = edges;
+  a.coef = coef;
+  a.n_k = NK;
+  a.npairs = npairs;
+  a.rowlen = bk_rowlen(NL, groups);
+  a.ld = 16 * groups;
+
+  if (groups == 1) {
+    const int nwaves = fp64 ? quad_waves<NL, true, true, true>(c)
+                            : (with_c ? quad_waves<NL, false, true, true>(c) : quad_waves<NL, false, false, true>(c));
+    double *part = static_cast<double *>(ensure(c, c.bk_partial, size_t(nwaves) * a.rowlen * 8));
+    HIPSTER_HIP(hipMemsetAsync(part, 0, size_t(nwaves) * a.rowlen * 8, c.stream));
+    a.partial = part;
+    a.q_lo = 0;
+    a.q_hi = nq;
+    a.group = 0;
+    if (fp64) launch_quad<NL, true, true, true>(c, a, nwaves);
+    else if (with_c) launch_quad<NL, false, true, true>(c, a, nwaves);
+    else launch_quad<NL, false, false, true>(c, a, nwaves);
+    double *merged = static_cast<double *>(ensure(c, c.merged, size_t(a.rowlen) * 8));
+    merge_partials(c, part, nwaves, a.rowlen, merged);
+    std::vector<double> M(size_t(a.rowlen));
+    HIPSTER_HIP(hipMemcpyAsync(M.data(), merged, size_t(a.rowlen) * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    // tiles are 16 x 16 per l; the Gram sums are symmetric up to rounding, so
+    // the upper triangle is mirrored to make the output exactly symmetric
+    for (int l = 0; l < NL; ++l)
+      for (int x = 0; x < NK; ++x)
+        for (int y = 0; y < NK; ++y) {
+          const int t = l * 256 + std::min(x, y) * 16 + std::max(x, y);
+          const size_t o = (size_t(l) * NK + x) * NK + y;
+          out.G[o] = M[size_t(t)];
+          out.C[o] = M[size_t(NL * 256 + t)];
+        }
+    for (int b = 0; b < NK; ++b) {
+      double s = 0.0;
+      for (int r = 0; r < 4; ++r) s += M[size_t(2 * NL * 256 + 16 * r + b)];
+      out.S0[size_t(b)] = s;
+    }
+    out.launches = 1;
+    return;
+  }
+
+  // more than 16 bins: A through a buffer, one pass per bin group
+  constexpr int NLM = NL * NL;
+  const int ld = 16 * groups;
+  const int64_t bytes_per_quad = int64_t(4) * NLM * ld * 8;
+  const int64_t budget = int64_t(1) << 30;
+  const int64_t qchunk = std::max<int64_t>(1, std::min<int64_t>(nq, budget / bytes_per_quad));
+  const int nwaves = quad_waves<NL, false, false, false>(c);
+  double *part = static_cast<double *>(ensure(c, c.bk_partial, size_t(nwaves) * a.rowlen * 8));
+  HIPSTER_HIP(hipMemsetAsync(part, 0, size_t(nwaves) * a.rowlen * 8, c.stream));
+  a.partial = part;
+  a.abuf = static_cast<double *>(ensure(c, c.bk_abuf, size_t(qchunk) * size_t(bytes_per_quad)));
+  a.wbuf = static_cast<double *>(ensure(c, c.bk_wbuf, size_t(qchunk) * 4 * 8));
+  std::vector<GramTile> tl;
+  for (int l = 0; l < NL; ++l)
+    for (int ga = 0; ga < groups; ++ga)
+      for (int gb = ga; gb < groups; ++gb) tl.push_back(GramTile{l, ga, gb, 0});
+  const int ntiles = int(tl.size());
+  GramTile *tiles = static_cast<GramTile *>(ensure(c, c.bk_tiles, tl.size() * sizeof(GramTile)));
+  HIPSTER_HIP(hipMemcpyAsync(tiles, tl.data(), tl.size() * sizeof(GramTile), hipMemcpyHostToDevice, c.stream));
+  const int nchunks = std::max(1, std::min(256, 4096 / ntiles));
+  double *gpart = static_cast<double *>(ensure(c, c.bk_gpart, size_t(nchunks) * ntiles * 256 * 8));
+  HIPSTER_HIP(hipMemsetAsync(gpart, 0, size_t(nchunks) * ntiles * 256 * 8, c.stream));
+  uint64_t launches = 0;
+  for (int64_t q0 = 0; q0 < nq; q0 += qchunk) {
+    a.q_lo = q0;
+    a.q_hi = std::min(nq, q0 + qchunk);
+    for (int gi = 0; gi < groups; ++gi) {
+      a.group = gi;
+      launch_quad<NL, false, false, false>(c, a, nwaves);
+      ++launches;
+    }
+    k_bk_gram<<<dim3(unsigned(ntiles * nchunks)), dim3(64), 0, c.stream>>>(a.abuf, a.wbuf, (a.q_hi - a.q_lo) * 4, NLM,
+                                                                           ld, tiles, ntiles, nchunks, gpart);
+    HIPSTER_HIP(hipGetLastError());
+  }
+  double *merged = static_cast<double *>(ensure(c, c.merged, size_t(std::max(a.rowlen, ntiles * 256)) * 8));
+  double *gmerged = static_cast<double *>(ensure(c, c.bk_gmerged, size_t(ntiles) * 256 * 8));
+  merge_partials(c, part, nwaves, a.rowlen, merged);
+  merge_partials(c, gpart, nchunks, ntiles * 256, gmerged);
+  std::vector<double> M(size_t(a.rowlen)), GM(size_t(ntiles) * 256);
+  HIPSTER_HIP(hipMemcpyAsync(M.data(), merged, size_t(a.rowlen) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(GM.data(), gmerged, GM.size() * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  std::vector<int> tindex(size_t(NL) * groups * groups, -1);
+  for (int t = 0; t < ntiles; ++t) tindex[(size_t(tl[t].l) * groups + tl[t].ga) * groups + tl[t].gb] = t;
+  for (int l = 0; l < NL; ++l)
+    for (int x = 0; x < NK; ++x)
+      for (int y = 0; y < NK; ++y) {
+        const int lo = std::min(x, y), hi = std::max(x, y);
+        const int t = tindex[(size_t(l) * groups + lo / 16) * groups + hi / 16];
+        out.G[(size_t(l) * NK + x) * NK + y] = GM[size_t(t) * 256 + (lo % 16) * 16 + hi % 16];
+      }
+  for (int b = 0; b < NK; ++b) {
+    double s = 0.0;
+    for (int r = 0; r < 4; ++r) s += M[size_t(64 * (b / 16) + 16 * r + b % 16)];
+    out.S0[size_t(b)] = s;
+  }
+  out.launches = launches;
+}
+
+void bk_sweep(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
+              const double *edges, const double *coef, int NK, int ell_max, bool fp64, bool with_c,
+              unsigned long long *npairs, BkSums &out) {
+  if (NK < 1 || NK > kMaxNkB)
+    throw Error{HIPSTER_EUNSUPPORTED, "bispectrum: n_k outside [1, " + std::to_string(kMaxNkB) + "]"};
   switch (ell_max) {
-    case 0: launch_fused<1>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
-    case 1: launch_fused<2>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
-    case 2: launch_fused<3>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
-    case 3: launch_fused<4>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
-    case 4: launch_fused<5>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
-    case 5: launch_fused<6>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
-    default: launch_fused<7>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, partial, rowlen, nwaves, npairs); break;
+    case 0: bk_sweep_nl<1>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, npairs, out); break;
+    case 1: bk_sweep_nl<2>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, npairs, out); break;
+    case 2: bk_sweep_nl<3>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, npairs, out); break;
+    case 3: bk_sweep_nl<4>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, npairs, out); break;
+    case 4: bk_sweep_nl<5>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, npairs, out); break;
+    case 5: bk_sweep_nl<6>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, npairs, out); break;
+    default: bk_sweep_nl<7>(c, prim, sec, g, r0, self_set, edges, coef, NK, fp64, with_c, npairs, out); break;
   }
 }
 

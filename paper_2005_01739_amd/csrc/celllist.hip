@@ -141,6 +141,49 @@ __global__ void k_gather(const T *__restrict__ pos, const T *__restrict__ w, con
   if (ms) ms[k] = mask[i] ? 1 : 0;
 }
 
+// Philox4x64-10 (Salmon, Moraes, Dror and Shaw 2011, "Parallel random numbers:
+// as easy as 1, 2, 3"): ten rounds of two 64 x 64 -> 128-bit products of the
+// counter words with the round multipliers, the high halves mixed into the
+// other words with the key, the key bumped by the Weyl constants between
+// rounds.
+__device__ inline void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uint64_t k1) {
+  constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += kW0;
+      k1 += kW1;
+    }
+    const uint64_t hi0 = __umul64hi(kM0, c[0]), lo0 = kM0 * c[0];
+    const uint64_t hi1 = __umul64hi(kM1, c[2]), lo1 = kM1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_random_points(uint64_t seed, int64_t n, double L, double *__restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  uint64_t c[4] = {uint64_t(i) + 1, 0, 0, 0};
+  philox4x64_10(c, seed, 0);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double x = L * (double(c[d] >> 11) * 0x1.0p-53);
+    if (x >= L) x = 0.0;
+    out[3 * i + d] = x;
+  }
+}
+
+void random_points(Ctx &c, uint64_t seed, int64_t n, double L, double *out) {
+  if (n <= 0) return;
+  k_random_points<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, c.stream>>>(seed, n, L, out);
+  HIPSTER_HIP(hipGetLastError());
+}
+
 void widen_i32(Ctx &c, const int *in, int64_t *out, int64_t n) {
   if (n <= 0) return;
   k_widen<<<dim3(unsigned((n + 255) / 256)), 256, 0, c.stream>>>(in, out, n);

@@ -15,11 +15,12 @@ namespace hipster {
 
 // Largest sizes the kernels are compiled for.
 constexpr int kMaxNk = 128;        // power-spectrum bins
-constexpr int kMaxNkB = 16;        // bispectrum bins
+constexpr int kMaxNkB = 64;        // bispectrum bins (more than 16: in groups of 16)
 constexpr int kMaxCellsPerAxis = 160;
 constexpr int kLMaxApi = 6;          // largest multipole
 constexpr double kMaxPhaseMixed = 1e6;  // largest k * R0 of the mixed form
 constexpr int kEiiMaxNodes = 8192;      // largest E^II table (intervals over [0, 2 R0])
+constexpr int kEiiMaxNkApi = 16;        // bins of the E^II table (analytic DDR^II)
 
 struct Error {
   hipster_status status;
@@ -120,8 +121,10 @@ struct Ctx {
   DevBuf edges, partial, merged, ordered_count, bbox;
   DevBuf unit_tiles, unit_base, unit_cell, unit_tile;
   DevBuf bk_partial, bk_partial_r, bk_coef;
+  DevBuf bq_count, bq_off, bq_scan, bq_quads, bk_abuf, bk_wbuf, bk_tiles, bk_gpart, bk_gmerged;
+  DevBuf rgen, pk_l1;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
-  DevBuf eii_consts, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T, ct_tab, ct_consts, ct_C, ct_wmax;
+  DevBuf eii_consts, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T, ct_tab, ct_consts, ct_C, ct_wmax, ct_jbar, ct_sel;
   DevBuf pt_tab, pt_consts, pt_T;  // power spectrum, table form
   std::vector<double> pt_key;      // (R0, n_k, n_l, n_c, edges) of the table in pt_tab
   DevBuf th_r, th_w, th_p, th_wp, th_pk, th_ek, th_g, th_J, th_om, th_K, th_out, th_wt, th_pb, th_bk, th_T, th_X;
@@ -196,13 +199,32 @@ void pk_sweep_tasks(Ctx &c, const PkPairs &p, const PkTask *tasks, int ntasks, i
 void merge_boxes(Ctx &c, const double *rows, int cols, const int *first, int nboxes, double *out);
 void merge_partials(Ctx &c, const double *partial, int rows, int cols, double *out);
 
-// Bispectrum: fused enumeration and MFMA contraction over one primary catalogue.
-// with_c = false (mixed form only): the C sums are left out (zero rows).
-void bk_fused(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
-              const double *edges, const double *coef, int NK, int ell_max, bool fp64, bool with_c, double *partial,
-              int rowlen, int nwaves, unsigned long long *npairs);
-size_t bk_fused_lds(int NL, int NK);
+// Bispectrum sums of one primary catalogue against the data (Sec. 4), host
+// arrays: G [NL][NK][NK] = sum_p w_p (4 pi/(2l+1)) sum_m A^a_lm A^b_lm,
+// C [NL][NK][NK] = sum_p w_p C^ab_l (with_c, FP64 form only; zeros
+// otherwise), S0 [NK] = sum_p w_p sum_q w_q W jbar^b_0 (primaries p selected by
+// prim.m, pairs q != p when self_set).  edges / coef: device n_k + 1 edges and
+// n_k values 3 / (k_{a+1}^3 - k_a^3).  npairs (device) gains the ordered pairs.
+struct BkSums {
+  int NL = 0, NK = 0;
+  std::vector<double> G, C, S0;
+  uint64_t launches = 0;
+};
+void bk_sweep(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
+              const double *edges, const double *coef, int NK, int ell_max, bool fp64, bool with_c,
+              unsigned long long *npairs, BkSums &out);
 void widen_i32(Ctx &c, const int *in, int64_t *out, int64_t n);
+
+// n uniform points in [0, L)^3 (device, [n][3] doubles), point i from block
+// i + 1 of the Philox4x64-10 generator keyed by (seed, 0): x_d = L (word_d >> 11)
+// 2^-53, a coordinate that rounds to L set to 0.
+void random_points(Ctx &c, uint64_t seed, int64_t n, double L, double *out);
+
+// L1 mass of the power-spectrum pair sums in double precision: rows
+// [nwaves][n_ell][n_k] += sum over the stream's pairs of
+// |ww| W(r/R0) (2l+1) |L_l(mu)| |jbar^a_l(r)|, l = 0, 2, .. (zeroed by the caller).
+void pk_l1_sweep(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, double r0, const double *edges, int n_edges,
+                 double *rows, int nwaves);
 
 // Analytic DDR^II term: the E^{II,ab}_l table on the nodes m 2 R0 / n_x
 // (device, [ell_max+1][n_k][n_k][n_x+1]); the 2 R0 pair sweep of the

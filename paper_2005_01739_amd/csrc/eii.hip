@@ -799,8 +799,10 @@ static double weight_max(Ctx &c, const Sorted &s);
 
 // Upper bound of the ordered (pair, image) terms of a half-stencil sweep:
 // twice the candidate pairs, sum over cells of n_cell times the points of
-// its 14 half-stencil cells.
-__global__ void k_candidate_bound(const int64_t *__restrict__ cell_start, int nc,
+// its 14 half-stencil cells; with a primary mask (sel = selected points per
+// cell) the sum of the pairs' multiplicities, sel_c m + n_c sel_m over the
+// same cells, which is what the masked sweep adds.
+__global__ void k_candidate_bound(const int64_t *__restrict__ cell_start, const int64_t *__restrict__ sel, int nc,
                                   unsigned long long *__restrict__ out) {
   const int64_t ncell = int64_t(nc) * nc * nc;
   unsigned long long acc = 0;
@@ -808,16 +810,28 @@ __global__ void k_candidate_bound(const int64_t *__restrict__ cell_start, int nc
     const int64_t n = cell_start[c + 1] - cell_start[c];
     if (n == 0) continue;
     const int cz = int(c % nc), cy = int((c / nc) % nc), cx = int(c / (int64_t(nc) * nc));
-    int64_t m = 0;
+    int64_t m = 0, ms = 0;
     for (int t = 13; t < 27; ++t) {
       const int nx = (cx + t / 9 - 1 + nc) % nc, ny = (cy + (t / 3) % 3 - 1 + nc) % nc, nz = (cz + t % 3 - 1 + nc) % nc;
       const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
       m += cell_start[nb + 1] - cell_start[nb];
+      if (sel) ms += sel[nb];
     }
-    acc += static_cast<unsigned long long>(2 * n * m);
+    acc += sel ? static_cast<unsigned long long>(sel[c] * m + n * ms) : static_cast<unsigned long long>(2 * n * m);
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+}
+
+// Selected points per cell (primary mask).
+__global__ __launch_bounds__(256) void k_cell_selected(const int64_t *__restrict__ cell_start,
+                                                       const uint8_t *__restrict__ mask, int64_t ncell,
+                                                       int64_t *__restrict__ sel) {
+  const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (c >= ncell) return;
+  int64_t k = 0;
+  for (int64_t p = cell_start[c]; p < cell_start[c + 1]; ++p) k += mask[p] ? 1 : 0;
+  sel[c] = k;
 }
 
 void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, const double *table, int rows,
@@ -828,8 +842,14 @@ void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, cons
   unsigned long long *cb = static_cast<unsigned long long *>(ensure(c, c.ct_wmax, 8));
   HIPSTER_HIP(hipMemsetAsync(cb, 0, 8, c.stream));
   const int64_t ncell = g.ncells();
+  int64_t *sel = nullptr;
+  if (s.m) {
+    sel = static_cast<int64_t *>(ensure(c, c.ct_sel, size_t(ncell) * 8));
+    k_cell_selected<<<dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, c.stream>>>(s.cell_start, s.m, ncell, sel);
+    HIPSTER_HIP(hipGetLastError());
+  }
   k_candidate_bound<<<dim3(unsigned(std::min<int64_t>((ncell + 255) / 256, 1024))), dim3(256), 0, c.stream>>>(
-      s.cell_start, g.nc, cb);
+      s.cell_start, sel, g.nc, cb);
   HIPSTER_HIP(hipGetLastError());
   unsigned long long cand = 0;
   HIPSTER_HIP(hipMemcpyAsync(&cand, cb, 8, hipMemcpyDeviceToHost, c.stream));
@@ -848,22 +868,32 @@ void ddr2_sweep(Ctx &c, const Sorted &s, const Grid &g, double r0, int n_x, cons
 // is not in the table: the sweep applies W(r/R0)^2 to each pair exactly, so
 // the tabulated function is entire and the interpolation error stays at
 // ~5e-3 (2 k_max h)^6 of it.
-__global__ __launch_bounds__(256) void k_cterm_table(double h, int n_nodes, int n_k, int n_l,
-                                                     const double *__restrict__ ek_g,
-                                                     const double *__restrict__ coef_g, double *__restrict__ F) {
+// jbar^a_l(x_m) on the nodes x_m = m h for l = 0 .. n_l - 1 (plain jbar: the
+// window is applied per pair), one thread per (l, a, m): J[(l n_k + a) n_nodes + m].
+__global__ __launch_bounds__(256) void k_cterm_jbar(double h, int n_nodes, int n_k, int n_l,
+                                                    const double *__restrict__ ek, const double *__restrict__ coef,
+                                                    double *__restrict__ J) {
   __shared__ double2 tab[kSinCosTab];
-  __shared__ double ek[2 * (kEiiMaxNk + 1)], coef[kEiiMaxNk];
   stage_sincos_tab<kSinCosTab>(tab);
-  for (int i = threadIdx.x; i < 2 * (n_k + 1); i += 256) ek[i] = ek_g[i];
-  for (int i = threadIdx.x; i < n_k; i += 256) coef[i] = coef_g[i];
   __syncthreads();
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= n_nodes * n_l) return;
-  const int l = idx / n_nodes, m = idx - l * n_nodes;
-  double g[kEiiMaxNk];
-  g_bins(l, m * h, 0.0, n_k, ek, coef, tab, g);  // W(0) = 1: plain jbar
-  for (int a = 0; a < n_k; ++a)
-    for (int b = 0; b < n_k; ++b) F[((size_t(l) * n_k + a) * n_k + b) * n_nodes + m] = g[a] * g[b];
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= int64_t(n_l) * n_k * n_nodes) return;
+  const int m = int(idx % n_nodes), a = int((idx / n_nodes) % n_k), l = int(idx / (int64_t(n_nodes) * n_k));
+  const double x = m * h;
+  const double lo = ek[2 * a + 1] * G_one(l, ek[2 * a] * x, tab);
+  const double hi = ek[2 * a + 3] * G_one(l, ek[2 * a + 2] * x, tab);
+  J[idx] = coef[a] * (hi - lo);
+}
+
+// F[((l n_k + a) n_k + b) n_nodes + m] = jbar^a_l(x_m) jbar^b_l(x_m).
+__global__ __launch_bounds__(256) void k_cterm_table(int n_nodes, int n_k, int n_l, const double *__restrict__ J,
+                                                     double *__restrict__ F) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= int64_t(n_l) * n_k * n_k * n_nodes) return;
+  const int m = int(idx % n_nodes);
+  const int64_t r = idx / n_nodes;
+  const int b = int(r % n_k), a = int((r / n_k) % n_k), l = int(r / (int64_t(n_k) * n_k));
+  F[idx] = J[(int64_t(l) * n_k + a) * n_nodes + m] * J[(int64_t(l) * n_k + b) * n_nodes + m];
 }
 
 int cterm_default_nodes(double r0, double k_max) {
@@ -903,9 +933,13 @@ void cterm_sweep(Ctx &c, const Sorted &s, const Sorted &b, bool cross, const Gri
   HIPSTER_HIP(hipMemcpyAsync(dk, ek.data(), ek.size() * 8, hipMemcpyHostToDevice, c.stream));
   HIPSTER_HIP(hipMemcpyAsync(dk + ek.size(), coef.data(), coef.size() * 8, hipMemcpyHostToDevice, c.stream));
   double *F = static_cast<double *>(ensure(c, c.ct_tab, size_t(rows) * n_nodes * 8));
+  double *J = static_cast<double *>(ensure(c, c.ct_jbar, size_t(n_l) * n_k * n_nodes * 8));
   const double h = r0 / n_c;
-  k_cterm_table<<<dim3(unsigned((n_nodes * n_l + 255) / 256)), dim3(256), 0, c.stream>>>(h, n_nodes, n_k, n_l, dk,
-                                                                                         dk + ek.size(), F);
+  const int64_t nj = int64_t(n_l) * n_k * n_nodes, nf = int64_t(rows) * n_nodes;
+  k_cterm_jbar<<<dim3(unsigned((nj + 255) / 256)), dim3(256), 0, c.stream>>>(h, n_nodes, n_k, n_l, dk, dk + ek.size(),
+                                                                            J);
+  HIPSTER_HIP(hipGetLastError());
+  k_cterm_table<<<dim3(unsigned((nf + 255) / 256)), dim3(256), 0, c.stream>>>(n_nodes, n_k, n_l, J, F);
   HIPSTER_HIP(hipGetLastError());
   // fixed-point scale: every node's sum of |w_p w_q^2 W^2 l_q(t)| is at most
   // n_ordered * max w_p * (max w_q)^2 * 2.5 (a node takes at most two basis

@@ -450,3 +450,71 @@ void merge_boxes(Ctx &c, const double *rows, int cols, const int *first, int nbo
 }
 
 }  // namespace hipster
+
+namespace hipster {
+
+// ------------------------------------------------------------- L1 mass
+// sum over the stream's pairs of |ww| W(r/R0) (2l+1) |L_l(mu)| |jbar^a_l(r)|,
+// l = 0, 2, .., in double precision (G_fp64 per edge), bins in chunks of 8
+// with one pass over the pairs per chunk; wave sums added to the wave's row.
+template <int NE>
+__global__ __launch_bounds__(256) void k_pk_l1(const double *__restrict__ pr, const double *__restrict__ pmu,
+                                               const double *__restrict__ pww, int64_t n, double inv_r0,
+                                               const double *__restrict__ ek, int n_edges,
+                                               double *__restrict__ rows) {
+  constexpr int kB = 8;
+  const int n_k = n_edges - 1;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const double *k = ek, *k3 = ek + 2 * n_edges;
+  for (int a0 = 0; a0 < n_k; a0 += kB) {
+    double acc[NE][kB];
+#pragma unroll
+    for (int i = 0; i < NE; ++i)
+#pragma unroll
+      for (int b = 0; b < kB; ++b) acc[i][b] = 0.0;
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += stride) {
+      const double r = pr[p];
+      const double wt = fabs(pww[p]) * window<double>(r * inv_r0);
+      double L[NE];
+      legendre_even<double, NE>(pmu[p], L);
+      Gv<double, NE> prev = G_fp64<NE, 2>(k[a0] * r);
+#pragma unroll
+      for (int b = 0; b < kB; ++b) {
+        const int a = a0 + b;
+        if (a < n_k) {
+          const Gv<double, NE> cur = G_fp64<NE, 2>(k[a + 1] * r);
+          const double cf = 3.0 / (k3[a + 1] - k3[a]);
+#pragma unroll
+          for (int i = 0; i < NE; ++i)
+            acc[i][b] += wt * double(4 * i + 1) * fabs(L[i]) * fabs(cf * (k3[a + 1] * cur.v[i] - k3[a] * prev.v[i]));
+          prev = cur;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i)
+#pragma unroll
+      for (int b = 0; b < kB; ++b) {
+        const double v = wave_sum(acc[i][b]);
+        if (lane == 0 && a0 + b < n_k) rows[(wave * NE + i) * n_k + a0 + b] += v;
+      }
+  }
+}
+
+void pk_l1_sweep(Ctx &c, const PkPairs &p, int64_t npairs, int n_ell, double r0, const double *edges, int n_edges,
+                 double *rows, int nwaves) {
+  if (npairs <= 0) return;
+  const dim3 grid(unsigned(nwaves / 4)), block(256);
+  const double *mu = static_cast<const double *>(p.mu), *ww = static_cast<const double *>(p.ww);
+  switch (n_ell) {
+    case 1: k_pk_l1<1><<<grid, block, 0, c.stream>>>(p.r, mu, ww, npairs, 1.0 / r0, edges, n_edges, rows); break;
+    case 2: k_pk_l1<2><<<grid, block, 0, c.stream>>>(p.r, mu, ww, npairs, 1.0 / r0, edges, n_edges, rows); break;
+    case 3: k_pk_l1<3><<<grid, block, 0, c.stream>>>(p.r, mu, ww, npairs, 1.0 / r0, edges, n_edges, rows); break;
+    default: k_pk_l1<4><<<grid, block, 0, c.stream>>>(p.r, mu, ww, npairs, 1.0 / r0, edges, n_edges, rows); break;
+  }
+  HIPSTER_HIP(hipGetLastError());
+}
+
+}  // namespace hipster

@@ -280,14 +280,14 @@ __device__ inline Gv<double, NL> G_mixed_w(double u, double wd, const double2 *_
 // (exact scalings by powers of two for U_BIG = 8).
 // FP64 = true gives the FP64 form of the same path: sin and cos from the table
 // with longer remainder polynomials, f and g from their 22-term double
-// fits (as G_fp64).
-template <int NL, int LSTEP, bool FP64 = false>
+// fits (as G_fp64).  NTAB: entries of the sine/cosine table (256 or 64).
+template <int NL, int LSTEP, bool FP64 = false, int NTAB = kSinCosTab>
 __device__ inline Gv<double, NL> Dt_far(double u, double wd, const double2 *__restrict__ tab) {
   constexpr bool kNeedSi = (NL - 1) * LSTEP >= 2;
   static_assert(HIPSTER_U_BIG == 8.0, "the coefficient scalings assume U_BIG = 8");
   Gv<double, NL> D;
   double s, c;
-  sincos_tab<kSinCosTab, FP64>(u, tab, s, c);
+  sincos_tab<NTAB, FP64>(u, tab, s, c);
   double si = 0.0;
   if constexpr (kNeedSi && FP64) {
     const double t = HIPSTER_U_BIG * wd;

@@ -84,7 +84,7 @@ def test_create_without_device_fails_cleanly():
     assert not h.value
     # NULL context calls are rejected without touching a device
     assert L.hipster_pk_ell(None, None, None, None, None) == 1
-    assert L.hipster_bk_ell(None, None, None, None, None, None) == 1
+    assert L.hipster_bk_ell(None, None, None, 0.0, 0, None, None, None) == 1
     assert L.hipster_batch(None, 0, None, None) == 1
     L.hipster_destroy(None)
 

@@ -1,6 +1,6 @@
 """GPU parity of the batched path: many boxes of uneven size, shape and R0
-in one call; every box's P_ell checked against the FP64 oracle and its B_ell
-against the per-box bispectrum call (the same kernels)."""
+in one call; every box's P_ell and B_ell checked against the FP64 oracle,
+including boxes drawn from the 64-box recipe (with primary subsets)."""
 import os
 
 import numpy as np
@@ -9,6 +9,7 @@ import pytest
 import oracle
 import synthetic
 from test_gpu_pk import TOL, check, wtilde_mass
+import test_gpu_bk as tbk
 
 pytestmark = pytest.mark.gpu
 
@@ -30,10 +31,20 @@ def _boxes(seed=0):
     return out
 
 
-def _check_boxes(specs, outs, precision, exact_bk=True):
-    import paper_2005_01739_amd as hp
+def bk_scale(ref, lmax, L, nw, sR):
+    """Scale of each B^ab_l entry: the sum of its terms' Cauchy-Schwarz scales."""
+    sc = {k: tbk._scale(ref[k]) for k in ("gd", "cd", "gr", "cr")}
+    fac = np.array([(2 * l + 1) for l in range(lmax + 1)])[:, None, None] / (L ** 3 * nw ** 3)
+    out = fac * (sc["gd"] + sc["cd"] + sR * (sc["gr"] + sc["cr"]))
+    wt = np.abs(ref["wtilde"])
+    out[0] += (np.outer(wt, np.abs(ref["s0"])) + np.outer(np.abs(ref["s0"]), wt)) / (L ** 3 * nw ** 2) + 2 * np.outer(wt, wt)
+    return out
+
+
+def _check_boxes(specs, outs, precision):
     for spec, res in zip(specs, outs):
-        ref = oracle.pk_ell(spec["pos"], None, spec["box"], spec["r0"], spec["pk_edges"], 4)
+        mask = spec.get("mask")
+        ref = oracle.pk_ell(spec["pos"], None, spec["box"], spec["r0"], spec["pk_edges"], 4, primary_mask=mask)
         assert res["n_pairs"] == ref["n_pairs"]
         V = spec["box"] ** 3
         nw = len(spec["pos"]) / V
@@ -41,12 +52,14 @@ def _check_boxes(specs, outs, precision, exact_bk=True):
         l1[0] += wtilde_mass(spec["r0"], spec["pk_edges"])
         check(res["pk"], ref["pk"], l1, precision, "batch pk")
         if "bk" in res:
-            single = hp.bk_ell(spec["pos"], None, spec["randoms"], box=spec["box"], r0=spec["r0"],
-                               k_edges=spec["bk_edges"], ell_max=spec["bk_ell_max"], precision=precision)
-            if exact_bk:
-                assert np.array_equal(res["bk"], single)
-            else:  # different chunking, so a different summation order
-                assert np.allclose(res["bk"], single, rtol=1e-10, atol=1e-10 * np.abs(single).max())
+            rpos = spec.get("randoms")
+            if rpos is None:
+                rpos = oracle.philox_randoms(int(round(spec["f_rand"] * len(spec["pos"]))), spec["box"], spec["seed"])
+            lm = spec["bk_ell_max"]
+            rb = oracle.bk_ell(spec["pos"], None, rpos, None, spec["box"], spec["r0"], spec["bk_edges"], lm,
+                               mask_d=mask, mask_r=spec.get("rmask"))
+            sc = bk_scale(rb, lm, spec["box"], nw, len(spec["pos"]) / len(rpos))
+            tbk.check(res["bk"], rb["bk"], sc, precision, "batch bk")
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
@@ -79,7 +92,41 @@ def test_batch_split_across_stream_chunks():
     for x, y in zip(a, b):
         assert x["n_pairs"] == y["n_pairs"]
         assert np.allclose(x["pk"], y["pk"], rtol=1e-12, atol=1e-12 * np.abs(x["pk"]).max())
-    _check_boxes(specs, b, "mixed", exact_bk=False)
+    _check_boxes(specs, b, "mixed")
+
+
+def test_batch_generated_randoms():
+    # bispectrum boxes without a catalogue draw f_rand N randoms from their seed
+    import paper_2005_01739_amd as hp
+    specs = _boxes(3)
+    for b, spec in enumerate(specs):
+        if "randoms" in spec:
+            del spec["randoms"]
+            spec.update(f_rand=2.0, seed=100 + b)
+    outs = hp.batch(specs, precision="mixed")
+    _check_boxes(specs, outs, "mixed")
+
+
+def test_batch_64_box_recipe_subset():
+    # The 64-box recipe (N log-uniform in [1e5, 4e6] scaled by 0.1, L in
+    # [250, 1500], R0 in [15, 50], half Poisson, half Thomas; P with 30 log
+    # bins, B with 10 linear bins and ell_max = 4, f_rand = 3 randoms drawn by
+    # the library), every box checked against the oracle on 24 data and 24
+    # random primaries.
+    import paper_2005_01739_amd as hp
+    specs = []
+    for b, wl in enumerate(synthetic.batch_boxes(64, scale=0.1)):
+        rng = np.random.default_rng([9, b])
+        mask = np.zeros(wl.n, np.uint8)
+        mask[rng.choice(wl.n, min(24, wl.n), replace=False)] = 1
+        n_r = int(round(3.0 * wl.n))
+        rmask = np.zeros(n_r, np.uint8)
+        rmask[rng.choice(n_r, min(24, n_r), replace=False)] = 1
+        specs.append(dict(pos=wl.pos, box=wl.box, r0=wl.r0, pk_edges=wl.k_edges_p, pk_ell_max=wl.ell_max_p,
+                          bk_edges=wl.k_edges_b, bk_ell_max=wl.ell_max_b, f_rand=3.0, seed=wl.seed, mask=mask,
+                          rmask=rmask))
+    outs = hp.batch(specs, precision="mixed")
+    _check_boxes(specs, outs, "mixed")
 
 
 def test_batch_deterministic():

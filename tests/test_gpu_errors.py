@@ -47,8 +47,9 @@ def test_power_spectrum_argument_errors():
 def test_bispectrum_argument_errors():
     import paper_2005_01739_amd as hp
     x = _pts()
-    bk = lambda pos=x, **kw: hp.bk_ell(pos, **{"box": 100.0, "r0": 10.0, "k_edges": K, **kw})
-    assert _status(lambda: bk(k_edges=np.linspace(0.1, 1.0, 18))) == "HIPSTER_EUNSUPPORTED"  # n_k > 16
+    bk = lambda pos=x, **kw: hp.bk_ell(pos, **{"box": 100.0, "r0": 10.0, "k_edges": K, "f_rand": 2.0, **kw})
+    assert _status(lambda: bk(k_edges=np.linspace(0.1, 1.0, 66))) == "HIPSTER_EUNSUPPORTED"  # n_k > 64
+    assert _status(lambda: bk(f_rand=0.0)) == "HIPSTER_EINVAL"  # no randoms, none to draw
     assert _status(lambda: bk(ell_max=7)) == "HIPSTER_EDOMAIN"
     assert _status(lambda: bk(r0=51.0)) == "HIPSTER_EDOMAIN"
     bad = x.copy()
