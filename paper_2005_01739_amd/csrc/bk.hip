@@ -10,9 +10,10 @@
 // Work unit: a quad, up to four primaries of one home cell.  A wave takes a
 // quad, one primary per 16-lane row, so each candidate secondary loaded from
 // the 27 neighbour cells is tested against four primaries.  Hits go to one
-// ring buffer per row; batches of up to 16 pairs per row are staged (lane =
+// ring buffer per row; batches of up to 8 pairs per row are staged (lane =
 // (row, pair): geometry, y_lm times w_q W, the top bin edge) and then swept in
-// steps of one pair per row.  In a step lane (col, row) evaluates G_l at bin
+// steps of one pair per row.  (Eight, not sixteen: the staging's LDS is what
+// limits the waves per CU.)  In a step lane (col, row) evaluates G_l at bin
 // edge 16 g + col for its row's pair, takes the next edge's value from lane
 // col + 1 by DPP, forms the bin average, and adds it times every y_lm into
 // FP64 accumulators A^{16g+col}_lm of its row's primary.  The y_lm of the
@@ -28,6 +29,8 @@
 // so results are bitwise reproducible.
 #include <type_traits>
 
+// the special functions' Horner steps as plain fma (see fma3)
+#define HIPSTER_PLAIN_FMA
 #include "common.h"
 #include "fmac_dpp.h"
 #include "specfun.h"
@@ -112,9 +115,10 @@ __device__ inline void wave_sync() { __syncthreads(); }
 constexpr int kXcds = 8;             // accelerator complex dies of the MI355X (the grid is a multiple)
 constexpr int kQuadRun = 4;          // consecutive quads per wave assignment
 constexpr int kHitCap = 128;         // hit ring buffer per row (power of two)
-constexpr int kRowBatch = 16;        // pairs per row per batch
-constexpr int kYStride = 65;         // y staging row stride (slots 0..63, odd: conflict-free reads)
-constexpr int kSinCosTabBk = 64;     // sine/cosine table entries (LDS)
+constexpr int kRowBatch = 8;         // pairs per row per batch
+constexpr int kSlots = 4 * kRowBatch;  // staged pairs per batch, slot = kRowBatch row + i
+constexpr int kYStride = kSlots + 1;   // y staging row stride (odd)
+constexpr int kSinCosTabBk = 256;    // sine/cosine table entries (LDS)
 
 // Writes w_q W y_lm of one slot into the y staging as real_ylm produces it:
 // element idx goes to base[idx * kYStride], scaled by f.
@@ -178,16 +182,6 @@ __device__ inline Gv<double, NL> G_any(double u, double wd, const double2 *tab) 
   else return G_mixed_w<NL, 1, kSinCosTabBk, false>(u, wd, tab);
 }
 
-// Every lane's u >= U_BIG: closed form without branches.
-template <int NL>
-__device__ inline Gv<double, NL> G_far(double u, double wd, const double2 *tab) {
-  Gv<double, NL> D = Dt_far<NL, 1, false, kSinCosTabBk>(u, wd, tab);
-  const double w3 = wd * wd * wd;
-#pragma unroll
-  for (int l = 0; l < NL; ++l) D.v[l] *= w3;
-  return D;
-}
-
 // fmac_block for l = L .. NL-1 (compile-time recursion).
 template <int L, int NL, int NA, int NY>
 __device__ __forceinline__ void fmac_all(double (&acc)[NA], const double (&yr)[NY], const double (&gl)[NL]) {
@@ -210,14 +204,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   constexpr int NY = (NLM + 15) / 16;
   using YT = YStage<FP64>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  YT *ylds = reinterpret_cast<YT *>(lds_raw);  // [NLM][kYStride]: w_q W y_lm of slot 16 row + i
-  __shared__ double s_r[64], s_ir[64], s_f[64], s_gt[NL][64];
-  __shared__ int hl_j[4][kHitCap];
-  __shared__ unsigned char hl_s[4][kHitCap];
+  YT *ylds = reinterpret_cast<YT *>(lds_raw);  // [NLM][kYStride]: w_q W y_lm of slot kRowBatch row + i
+  __shared__ double s_r[kSlots], s_ir[kSlots], s_f[WITH_C ? kSlots : 1], s_gt[NL][kSlots];
+  // hit rings per class (0: far, every edge of the group at u >= U_BIG;
+  // 1: near) and row; an entry is (secondary index << 5) | image shift code
+  __shared__ unsigned hl[2][4][kHitCap];
   __shared__ int64_t nb_beg[27], nb_end[27], run_beg[27], run_end[27];
   __shared__ int nb_sh[27], run_sh[27], n_runs_s;
+  // the quad's four primaries (x, y, z per row) and each run's image offset,
+  // read per scan step from LDS rather than held in scalar registers
+  __shared__ double q_xyz[4][3], run_off[27][3];
   __shared__ double2 sc_tab[FP64 ? 1 : kSinCosTabBk];
   if constexpr (!FP64) stage_sincos_tab<kSinCosTabBk>(sc_tab);
+  for (int i = threadIdx.x; i < NL * kSlots; i += 64) (&s_gt[0][0])[i] = 0.0;
 
   const int lane = threadIdx.x, row = lane >> 4, col = lane & 15;
   const int64_t e0 = int64_t(16) * A.group;
@@ -233,21 +232,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   // a full group of 16 bins takes its top edge 16 g + 16 from the staging
   const bool top = e0 + 16 <= NK;
   const bool top_lane = top && col == 15;
+  const double top_w = top_lane ? 1.0 : 0.0;
   const double ktop = top ? A.edges[e0 + 16] : 0.0;
   const double ktop3 = ktop * ktop * ktop, iktop = ktop > 0.0 ? 1.0 / ktop : 0.0;
   const double r_neutral = 0.5 / A.inv_r0, ir_neutral = 2.0 * A.inv_r0;
   const double L = A.L;
+  // pairs at r^2 >= rfar2 put every edge of the group on the large-argument
+  // side (no Taylor or sine-integral series); rfar2 = inf leaves all near
+  const double k_lo = A.edges[e0];
+  const double rfar = k_lo > 0.0 ? HIPSTER_U_BIG / k_lo : 0.0;
+  const double rfar2 = (FP64 || !(k_lo > 0.0)) ? __builtin_inf() : rfar * rfar * (1.0 + 1e-12);
 
-  d4_t accG[NL], accC[NL];
+  // C sums (FP64 form) stay in registers; each quad's Gram contribution is
+  // added to the wave's own row right away, so no Gram accumulator occupies
+  // registers during the sweep
+  d4_t accC[NL];
 #pragma unroll
-  for (int l = 0; l < NL; ++l) {
-    accG[l] = d4_t{0.0, 0.0, 0.0, 0.0};
-    accC[l] = d4_t{0.0, 0.0, 0.0, 0.0};
-  }
+  for (int l = 0; l < NL; ++l) accC[l] = d4_t{0.0, 0.0, 0.0, 0.0};
+  double *const wrow = A.partial + int64_t(blockIdx.x) * A.rowlen;
   double s0acc = 0.0;
-  // an AGPR operand makes the backend choose the matrix instructions' AGPR
-  // form, so the Gram accumulators live in AGPRs, not in the VGPRs the sweep needs
-  if constexpr (GRAM) asm volatile("" ::"a"(accG[0]));
   unsigned long long pcount = 0;
   int64_t cur_cell = -1;
   wave_sync();
@@ -298,20 +301,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
             }
           }
           n_runs_s = nr;
+          for (int k = 0; k < nr; ++k) {
+            const int sh = run_sh[k];
+            run_off[k][0] = double(sh / 9 - 1) * L;
+            run_off[k][1] = double((sh / 3) % 3 - 1) * L;
+            run_off[k][2] = double(sh % 3 - 1) * L;
+          }
         }
         wave_sync();
         cur_cell = cell;
       }
       const int n_runs = __builtin_amdgcn_readfirstlane(n_runs_s);
       // the four primaries (uniform), and this row's
-      double qx[4], qy[4], qz[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      if (lane < 12) {
+        const int r = lane / 3, d = lane % 3;
         const int pp = qp[r] >= 0 ? qp[r] : qp[0];
-        qx[r] = uniform_f64(A.prim.x[pp]);
-        qy[r] = uniform_f64(A.prim.y[pp]);
-        qz[r] = uniform_f64(A.prim.z[pp]);
+        q_xyz[r][d] = d == 0 ? A.prim.x[pp] : (d == 1 ? A.prim.y[pp] : A.prim.z[pp]);
       }
+      wave_sync();
       const int my_p = row == 0 ? qp[0] : row == 1 ? qp[1] : row == 2 ? qp[2] : qp[3];
       const bool my_valid = my_p >= 0;
       const int my_pp = my_valid ? my_p : qp[0];
@@ -321,26 +328,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       double acc[NLM];
 #pragma unroll
       for (int k = 0; k < NLM; ++k) acc[k] = 0.0;
-      int hn[4] = {0, 0, 0, 0}, hh[4] = {0, 0, 0, 0};  // per-row hit count and ring head (uniform)
+      // per class and row: hit count and ring head (uniform)
+      int hn[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, hh[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 
-      // one batch: up to kRowBatch pairs of each row
-      auto batch = [&]() {
+      // one batch of class CL: up to kRowBatch pairs of each row
+      auto batch = [&](auto cls) {
+        constexpr int CL = decltype(cls)::value;
         int cnt[4];
         int cmax = 0;
+        unsigned cpack = 0, hpack = 0;  // per-row count and head, 8 bits each
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          cnt[r] = hn[r] < kRowBatch ? hn[r] : kRowBatch;
+          cnt[r] = hn[CL][r] < kRowBatch ? hn[CL][r] : kRowBatch;
           cmax = cnt[r] > cmax ? cnt[r] : cmax;
+          cpack |= unsigned(cnt[r]) << (8 * r);
+          hpack |= unsigned(hh[CL][r]) << (8 * r);
         }
-        const int my_cnt = row == 0 ? cnt[0] : row == 1 ? cnt[1] : row == 2 ? cnt[2] : cnt[3];
-        const int my_head = row == 0 ? hh[0] : row == 1 ? hh[1] : row == 2 ? hh[2] : hh[3];
-        // staging, lane = slot (row, i = col)
-        {
+        const int my_cnt = int((cpack >> (8 * row)) & 255u);
+        const int my_head = int((hpack >> (8 * row)) & 255u);
+        // staging, lane (row, i = col < kRowBatch) = slot kRowBatch row + i
+        if (col < kRowBatch) {
+          const int slot = kRowBatch * row + col;
           double r = r_neutral, ir = ir_neutral, f = 0.0, ux = 0.0, uy = 0.0, uz = 1.0;
           if (col < my_cnt) {
             const int idx = (my_head + col) & (kHitCap - 1);
-            const int j = hl_j[row][idx];
-            const int sh = hl_s[row][idx];
+            const unsigned ent = hl[CL][row][idx];
+            const int j = int(ent >> 5), sh = int(ent & 31u);
             const double ox = double(sh / 9 - 1) * L, oy = double((sh / 3) % 3 - 1) * L, oz = double(sh % 3 - 1) * L;
             const double dx = (px - A.sec.x[j]) - ox;
             const double dy = (py - A.sec.y[j]) - oy;
@@ -354,61 +367,96 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
               uy = dy * ir;
               uz = dz * ir;
             }
+          } else if (CL == 0) {
+            r = rfar < r_neutral ? r_neutral : rfar;  // an idle slot of a far batch stays far
+            ir = 1.0 / r;
           }
-          real_ylm<NL - 1>(ux, uy, uz, YStore<YT>{ylds + lane, f});
-          s_r[lane] = r;
-          s_ir[lane] = ir;
-          s_f[lane] = f;
+          // far class: k_e^3 G_l(k_e r) = Dt_l(k_e r) / r^3, the 1/r^3 goes with
+          // the harmonics and the steps difference Dt values
+          constexpr bool DT = !FP64 && CL == 0;
+          const double fy = DT ? f * (ir * ir * ir) : f;
+          real_ylm<NL - 1>(ux, uy, uz, YStore<YT>{ylds + slot, fy});
+          s_r[slot] = r;
+          s_ir[slot] = ir;
+          if constexpr (WITH_C) s_f[slot] = f;
           if (top) {
-            const Gv<double, NL> T = G_any<NL, FP64>(ktop * r, iktop * ir, sc_tab);
+            if constexpr (DT) {
+              const Gv<double, NL> T = Dt_far<NL, 1, false, kSinCosTabBk>(ktop * r, iktop * ir, sc_tab);
 #pragma unroll
-            for (int l = 0; l < NL; ++l) s_gt[l][lane] = ktop3 * T.v[l];
+              for (int l = 0; l < NL; ++l) s_gt[l][slot] = T.v[l];
+            } else {
+              const Gv<double, NL> T = G_any<NL, FP64>(ktop * r, iktop * ir, sc_tab);
+#pragma unroll
+              for (int l = 0; l < NL; ++l) s_gt[l][slot] = ktop3 * T.v[l];
+            }
           }
         }
         wave_sync();
-        // steps: one pair per row
-        for (int s = 0; s < cmax; ++s) {
-          const int slot = 16 * row + s;
-          const double rq = s_r[slot], irq = s_ir[slot];
-          double yr[NY];
+        // steps: one pair per row.  Two operand sets alternate, so the next
+        // step's LDS operands are read while the current step computes
+        // without register copies.
+        auto ld_step = [&](int s, double &rq, double &irq, double (&yr)[NY]) {
+          const int slot = kRowBatch * row + s;
+          rq = s_r[slot];
+          irq = s_ir[slot];
 #pragma unroll
           for (int i = 0; i < NY; ++i) {
-            const int k = col + 16 * i;
-            yr[i] = k < NLM ? double(ylds[k * kYStride + slot]) : 0.0;
+            // lanes past the last harmonic read a valid row; no multiply-add
+            // broadcasts their value
+            const int k = col + 16 * i < NLM ? col + 16 * i : NLM - 1;
+            yr[i] = double(ylds[k * kYStride + slot]);
           }
+        };
+        auto step = [&](int s, double rq, double irq, const double (&yr)[NY]) {
+          const int slot = kRowBatch * row + s;
           const double u = ke * rq, wd = ike * irq;
+          // gl = [k^3 G_l(k r)] between this lane's edge and the next, without
+          // the bin's 3 / (k_{a+1}^3 - k_a^3) (applied to A after the quad):
+          // far class from Dt values (the 1/r^3 is in the harmonics)
+          constexpr bool DT = !FP64 && CL == 0;
           Gv<double, NL> Ge;
-          if constexpr (FP64) {
-            Ge = G_any<NL, true>(u, wd, sc_tab);
-          } else {
-            if (__ballot(u < HIPSTER_U_BIG) == 0ull) Ge = G_far<NL>(u, wd, sc_tab);
-            else Ge = G_any<NL, false>(u, wd, sc_tab);
-          }
+          if constexpr (FP64) Ge = G_any<NL, true>(u, wd, sc_tab);
+          else if constexpr (DT) Ge = Dt_far<NL, 1, false, kSinCosTabBk>(u, wd, sc_tab);
+          else Ge = G_any<NL, false>(u, wd, sc_tab);
           double gl[NL];
 #pragma unroll
           for (int l = 0; l < NL; ++l) {
+            // lane 15 of a row receives 0 from the shift and adds the top
+            // edge (s_gt is zero unless the group is full)
             const double gn = from_next_lane_in_row(Ge.v[l]);
-            const double hi = top_lane ? s_gt[l][slot] : kn3 * gn;
-            gl[l] = cfb * (hi - ke3 * Ge.v[l]);
+            const double hi = fma(s_gt[l][slot], top_w, DT ? gn : kn3 * gn);
+            gl[l] = DT ? hi - Ge.v[l] : fma(-ke3, Ge.v[l], hi);
           }
           // acc[l*l+m] += (w_q W y_lm)(pair) * jbar^a_l(pair)
           fmac_all<0>(acc, yr, gl);
           if constexpr (WITH_C) {
-            const double fq = s_f[slot];
+            const double fq = s_f[slot] * cfb;
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
               const double gq = gl[l] * fq;
               accC[l] = mfma_f64(gq, wp * gq, accC[l]);
             }
           }
+        };
+        double rq0, irq0, yr0[NY], rq1, irq1, yr1[NY];
+        ld_step(0, rq0, irq0, yr0);
+        for (int s = 0; s < cmax; s += 2) {
+          const bool two = s + 1 < cmax;
+          ld_step(two ? s + 1 : s, rq1, irq1, yr1);
+          step(s, rq0, irq0, yr0);
+          if (!two) break;
+          ld_step(s + 2 < cmax ? s + 2 : s + 1, rq0, irq0, yr0);
+          step(s + 1, rq1, irq1, yr1);
         }
         wave_sync();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          hh[r] = (hh[r] + cnt[r]) & (kHitCap - 1);
-          hn[r] -= cnt[r];
+          hh[CL][r] = (hh[CL][r] + cnt[r]) & (kHitCap - 1);
+          hn[CL][r] -= cnt[r];
         }
       };
+      using Far = std::integral_constant<int, 0>;
+      using Near = std::integral_constant<int, 1>;
 
       // scan: runs of candidates, 64 at a time, the next step's loads in flight
       int ri = 0;
@@ -417,10 +465,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       double cx = 0.0, cy = 0.0, cz = 0.0;
       int cj = 0;
       bool cok = false;
-      int csh = 13;
-      auto fetch = [&](double &x, double &y, double &z, int &j, bool &ok, int &sh) {
+      int csh = 13, crun = 0;
+      auto fetch = [&](double &x, double &y, double &z, int &j, bool &ok, int &sh, int &run) {
         const int64_t end = uniform_i64(run_end[ri]);
         sh = __builtin_amdgcn_readfirstlane(run_sh[ri]);
+        run = ri;
         const int64_t jj = pos + lane;
         ok = jj < end;
         j = int(jj);
@@ -435,43 +484,55 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           if (ri < n_runs) pos = uniform_i64(run_beg[ri]);
         }
       };
-      if (have) fetch(cx, cy, cz, cj, cok, csh);
+      if (have) fetch(cx, cy, cz, cj, cok, csh, crun);
       while (have) {
         const bool have_next = ri < n_runs;
         double nx = 0.0, ny = 0.0, nz = 0.0;
         int nj = 0;
         bool nok = false;
-        int nsh = 13;
-        if (have_next) fetch(nx, ny, nz, nj, nok, nsh);
-        const double ox = double(csh / 9 - 1) * L, oy = double((csh / 3) % 3 - 1) * L, oz = double(csh % 3 - 1) * L;
+        int nsh = 13, nrun = 0;
+        if (have_next) fetch(nx, ny, nz, nj, nok, nsh, nrun);
+        const double ox = run_off[crun][0], oy = run_off[crun][1], oz = run_off[crun][2];
         const bool self_run = A.self_set && csh == 13;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          bool hit = false;
+          bool hit = false, far = false;
           if (cok && qp[r] >= 0) {
-            const double dx = (qx[r] - cx) - ox;
-            const double dy = (qy[r] - cy) - oy;
-            const double dz = (qz[r] - cz) - oz;
-            hit = bk_sq_norm(dx, dy, dz) < A.r02 && !(self_run && cj == qp[r]);
+            const double dx = (q_xyz[r][0] - cx) - ox;
+            const double dy = (q_xyz[r][1] - cy) - oy;
+            const double dz = (q_xyz[r][2] - cz) - oz;
+            const double r2 = bk_sq_norm(dx, dy, dz);
+            hit = r2 < A.r02 && !(self_run && cj == qp[r]);
+            far = r2 >= rfar2;
           }
-          const unsigned long long bal = __ballot(hit);
+          const unsigned long long balf = __ballot(hit && far), baln = __ballot(hit && !far);
           if (hit) {
-            const int k = (hh[r] + hn[r] + __popcll(bal & ((1ull << lane) - 1ull))) & (kHitCap - 1);
-            hl_j[r][k] = cj;
-            hl_s[r][k] = (unsigned char)csh;
+            const unsigned long long lt = (1ull << lane) - 1ull;
+            const int cl = far ? 0 : 1;
+            const int k = (far ? hh[0][r] + hn[0][r] + __popcll(balf & lt) : hh[1][r] + hn[1][r] + __popcll(baln & lt)) &
+                          (kHitCap - 1);
+            hl[cl][r][k] = (unsigned(cj) << 5) | unsigned(csh);
           }
-          const int added = __popcll(bal);
-          hn[r] += added;
-          pcount += unsigned(added);
+          hn[0][r] += __popcll(balf);
+          hn[1][r] += __popcll(baln);
+          pcount += unsigned(__popcll(balf) + __popcll(baln));
         }
-        // a batch when every row has a full batch, or before a row could
-        // overflow in the next step (each step adds at most 64 hits per row)
+        // a batch of a class when every row has a full batch of it, or before a
+        // row could overflow in the next step (each step adds at most 64 hits
+        // per row and class)
         for (;;) {
-          const int mn = min(min(hn[0], hn[1]), min(hn[2], hn[3]));
-          const int mx = max(max(hn[0], hn[1]), max(hn[2], hn[3]));
+          const int mn = min(min(hn[0][0], hn[0][1]), min(hn[0][2], hn[0][3]));
+          const int mx = max(max(hn[0][0], hn[0][1]), max(hn[0][2], hn[0][3]));
           if (!(mn >= kRowBatch || mx > kHitCap - 64)) break;
           wave_sync();
-          batch();
+          batch(Far{});
+        }
+        for (;;) {
+          const int mn = min(min(hn[1][0], hn[1][1]), min(hn[1][2], hn[1][3]));
+          const int mx = max(max(hn[1][0], hn[1][1]), max(hn[1][2], hn[1][3]));
+          if (!(mn >= kRowBatch || mx > kHitCap - 64)) break;
+          wave_sync();
+          batch(Near{});
         }
         cx = nx;
         cy = ny;
@@ -479,18 +540,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
         cj = nj;
         cok = nok;
         csh = nsh;
+        crun = nrun;
         have = have_next;
       }
       wave_sync();
-      while (max(max(hn[0], hn[1]), max(hn[2], hn[3])) > 0) batch();
+      while (max(max(hn[0][0], hn[0][1]), max(hn[0][2], hn[0][3])) > 0) batch(Far{});
+      while (max(max(hn[1][0], hn[1][1]), max(hn[1][2], hn[1][3])) > 0) batch(Near{});
 
-      // the quad's contribution
+      // the quad's contribution; the bin's 3 / (k_{a+1}^3 - k_a^3) first
+#pragma unroll
+      for (int k = 0; k < NLM; ++k) acc[k] *= cfb;
       if constexpr (GRAM) {
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
           const double wsc = wp * (4.0 * kPi / double(2 * l + 1));
+          d4_t g = d4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int m = 0; m < 2 * l + 1; ++m) accG[l] = mfma_f64(acc[l * l + m], wsc * acc[l * l + m], accG[l]);
+          for (int m = 0; m < 2 * l + 1; ++m) g = mfma_f64(acc[l * l + m], wsc * acc[l * l + m], g);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) wrow[l * 256 + (row + 4 * v) * 16 + col] += g[v];
         }
       } else {
         const int64_t slot = (qi - A.q_lo) * 4 + row;
@@ -502,16 +570,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       s0acc = fma(wp, acc[0], s0acc);
     }
   }
-  double *out = A.partial + int64_t(blockIdx.x) * A.rowlen;
+  double *out = wrow;
   if constexpr (GRAM) {
+    if constexpr (WITH_C) {
 #pragma unroll
-    for (int l = 0; l < NL; ++l)
+      for (int l = 0; l < NL; ++l)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int t = (row + 4 * v) * 16 + col;
-        out[l * 256 + t] += accG[l][v];
-        if constexpr (WITH_C) out[NL * 256 + l * 256 + t] += accC[l][v];
-      }
+        for (int v = 0; v < 4; ++v) out[NL * 256 + l * 256 + (row + 4 * v) * 16 + col] += accC[l][v];
+    }
     out[2 * NL * 256 + lane] += s0acc;
   } else {
     out[64 * A.group + lane] += s0acc;
@@ -625,6 +691,8 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   if (fp64 && groups > 1)
     throw Error{HIPSTER_EUNSUPPORTED, "bispectrum: the FP64 form takes at most 16 bins (its C sums are per pair)"};
   if (with_c && !fp64) throw Error{HIPSTER_EINVAL, "bispectrum: the mixed form takes C from the pair histogram"};
+  if (sec.n >= (int64_t(1) << 27))
+    throw Error{HIPSTER_EUNSUPPORTED, "bispectrum: at most 2^27 - 1 data points (27-bit hit indices)"};
   out.NL = NL;
   out.NK = NK;
   out.G.assign(size_t(NL) * NK * NK, 0.0);
@@ -664,8 +732,7 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   a.ld = 16 * groups;
 
   if (groups == 1) {
-    const int nwaves = fp64 ? quad_waves<NL, true, true, true>(c)
-                            : (with_c ? quad_waves<NL, false, true, true>(c) : quad_waves<NL, false, false, true>(c));
+    const int nwaves = fp64 ? quad_waves<NL, true, true, true>(c) : quad_waves<NL, false, false, true>(c);
     double *part = static_cast<double *>(ensure(c, c.bk_partial, size_t(nwaves) * a.rowlen * 8));
     HIPSTER_HIP(hipMemsetAsync(part, 0, size_t(nwaves) * a.rowlen * 8, c.stream));
     a.partial = part;
@@ -673,7 +740,6 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
     a.q_hi = nq;
     a.group = 0;
     if (fp64) launch_quad<NL, true, true, true>(c, a, nwaves);
-    else if (with_c) launch_quad<NL, false, true, true>(c, a, nwaves);
     else launch_quad<NL, false, false, true>(c, a, nwaves);
     double *merged = static_cast<double *>(ensure(c, c.merged, size_t(a.rowlen) * 8));
     merge_partials(c, part, nwaves, a.rowlen, merged);

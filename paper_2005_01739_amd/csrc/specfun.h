@@ -33,12 +33,19 @@ constexpr int kLMax = 6;
 // Horner step whose addend is a constant held in a register, the compiler
 // otherwise emits the two-operand v_fmac_f64 (which overwrites its addend)
 // plus a copy of the constant, two instructions per step.  The result is the
-// same correctly rounded fused multiply-add either way.
-__device__ inline double fma3(double a, double b, double c) {
+// same correctly rounded fused multiply-add either way.  A translation unit
+// that defines HIPSTER_PLAIN_FMA gets the plain fma instead: the asm operands
+// must be VGPRs, so every coefficient then occupies a VGPR pair for the
+// whole loop, which a register-bound kernel cannot afford.
+#ifdef HIPSTER_PLAIN_FMA
+static __device__ inline double fma3(double a, double b, double c) { return fma(a, b, c); }
+#else
+static __device__ inline double fma3(double a, double b, double c) {
   double r;
   asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
   return r;
 }
+#endif
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kHalfPi = 1.57079632679489661923;
 // Below this argument the Taylor series needs only 14 terms, and the mixed
@@ -156,6 +163,27 @@ __device__ inline Gv<double, NL> G_taylor64(double u) {
   else return G_taylor64_call<NL, LSTEP>(u);
 }
 
+// The same below kUSmall only (14 terms), for callers that branch there.
+template <int NL, int LSTEP>
+__device__ __forceinline__ Gv<double, NL> G_taylor_small_inl(double u) {
+  Gv<double, NL> G;
+  double v = u * u, ul = 1.0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    if (i > 0) {
+#pragma unroll
+      for (int q = 0; q < LSTEP; ++q) ul *= u;
+    }
+    G.v[i] = taylor_G64<14>(i * LSTEP, v, ul);
+  }
+  return G;
+}
+
+template <int NL, int LSTEP>
+__device__ __noinline__ Gv<double, NL> G_taylor_small_call(double u) {
+  return G_taylor_small_inl<NL, LSTEP>(u);
+}
+
 // ----------------------------------------------------------- FP64 form
 template <int NL, int LSTEP, bool INL = false>
 __device__ __noinline__ Gv<double, NL> G_fp64(double u) {
@@ -245,7 +273,10 @@ __device__ inline float horner32(const float (&p)[N], float t) {
 template <int NL, int LSTEP, int NTAB = kSinCosTab, bool INL = false>
 __device__ inline Gv<double, NL> G_mixed_w(double u, double wd, const double2 *__restrict__ tab) {
   constexpr bool kNeedSi = (NL - 1) * LSTEP >= 2;  // some even l >= 2 is requested
-  if (u < kUSmall) return G_taylor64<NL, LSTEP, INL>(u);
+  if (u < kUSmall) {
+    if constexpr (INL) return G_taylor_small_inl<NL, LSTEP>(u);
+    else return G_taylor_small_call<NL, LSTEP>(u);
+  }
   Gv<double, NL> G;
   double s, c;
   sincos_tab<NTAB>(u, tab, s, c);
