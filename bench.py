@@ -1,36 +1,37 @@
 """Benchmark of the periodic-box pair sweep on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pk|bk|pk5|bk5|batch|survey]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload headline|pk|bk|...]
 
-Default workload: the mixed-precision power spectrum of a 2,000,000-point
-Thomas cluster catalogue (10 children per parent, sigma = 2 Mpc/h, extra
-N(0, 4 Mpc/h) line-of-sight displacement) in a 1000 Mpc/h periodic box,
-R0 = 25 Mpc/h, ell = 0, 2, 4, 40 log-spaced k-bins over 1-10 h/Mpc.  One step
-is one full hipster_pk_ell call on device-resident positions: cell list,
-pair enumeration, pair-weight sweep, merge and normalisation.
+Default (headline) workload: the largest single-GPU configuration, a
+2^24-point weighted Thomas catalogue (2^20 parents, 16 children each,
+sigma = 1 Mpc/h, weights uniform in [0.5, 1.5]) in a 1000 Mpc/h periodic box
+with R0 = 15 Mpc/h.  One step is the whole hot path on device-resident
+positions: the power spectrum (ell = 0, 2, 4, 60 log k-bins over 2-20 h/Mpc)
+and the bispectrum (ell = 0..4, 16 log k-bins over 2-20 h/Mpc, the DDR^II term
+from f_rand = 3 uniform randoms that the library draws on the device from a
+seed), both in the mixed form: cell lists, pair enumeration, pair weights,
+harmonic sums, Gram contraction, C-term sweep, merges and normalisation.
 
-Other workloads: the bispectrum (bk, bk5), the 2^24-point box (pk5), the
-64-box batch (batch) and the survey-geometry power spectrum (survey: 1e6 Thomas
-points and 3e6 randoms in a 1000 Mpc/h cube 1000-2000 Mpc/h from the observer,
-DD - 2DR + RR with the pair-midpoint line of sight; pairs are the ordered DD,
-DR + RD and RR pairs).
+Beside it: the same step in the FP64 form (`fp64_form`), the 2e6-point power
+spectrum (`pk_config2`, the mixed and table forms) and the FP64 brute-force
+oracle on the host cores over a fixed subset of the same workload's
+primaries (`cpu_baseline`).  Other workloads (--workload) time single
+calls: the bispectrum (bk, bk5, their analytic-DDR^II forms), the 2^24-point
+power spectrum (pk5), the 64-box batch (batch) and the survey-geometry power
+spectrum (survey).
 
-Prints one JSON line.  `value` is pair-weights per second (ordered pairs
-inside R0 x n_k x n_ell, per second of the whole step).  `roofline` refers to
-the dominant kernel: for the mixed power spectrum the far-pair sweep kernel
-k_pk_far (pairs with every edge on the large-argument side, about 90% of the
-pairs), otherwise the whole pair-weight sweep; algorithmic FLOPs per launch
-(the per-pair model 40 + 80 (n_k+1) + 5 n_k n_ell per unordered pair, times
-the pairs that launch sweeps) over its average duration measured with HIP
-events on the library's stream, against the chip's 157.3 TFLOP/s FP32 vector
-peak (the kernels compute mostly in FP64, which issues at half that rate;
-`frac_fp64` gives the fraction of the 78.6 TFLOP/s FP64 vector peak).
-`roofline.whole_sweep` gives the same figures for both sweep kernels
-together.  `traffic` is read from the committed rocprofv3 counter summary of
-that kernel when the kernel's sources are unchanged since the counters were
-taken, else null.
-`cpu_baseline` times the FP64 brute-force oracle on the host cores over a
-fixed subset of primaries of the same catalogue.
+Prints one JSON line.  `value` is pair-weights per second: ordered pairs
+inside R0 x n_k x n_ell for P plus (data-data + random-data ordered pairs)
+x n_k x (ell_max+1)^2 for B, per second of the whole step.  `roofline` refers
+to the dominant kernel, the bispectrum sweep k_bk_quad: its algorithmic
+FLOPs per launch (bk_flops_per_pair, without the C sums in the mixed form,
+which the C-term histogram sweep takes) over its average duration measured
+with HIP events on the library's stream, against the chip's 157.3 TFLOP/s
+FP32 vector peak (the kernel computes mostly in FP64, which issues at half
+that rate; `frac_fp64` is the fraction of the 78.6 TFLOP/s FP64 peak).
+`traffic` is read from the committed rocprofv3 counter summary of that
+kernel when its sources are unchanged since the counters were taken, else
+null.
 """
 from __future__ import annotations
 
@@ -54,12 +55,15 @@ PEAK_VALU_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 SWEEP_SOURCES = ["paper_2005_01739_amd/csrc/pk.hip", "paper_2005_01739_amd/csrc/specfun.h",
                  "paper_2005_01739_amd/csrc/coeffs.h"]
+BK_SOURCES = ["paper_2005_01739_amd/csrc/bk.hip", "paper_2005_01739_amd/csrc/specfun.h",
+              "paper_2005_01739_amd/csrc/coeffs.h", "paper_2005_01739_amd/csrc/fmac_dpp.h"]
 PROFILE = os.path.join(ROOT, "profiles", "k_pk_far_mixed_thomas_2e6.md")
+BK_PROFILE = os.path.join(ROOT, "profiles", "k_bk_quad_mixed_thomas_2p24.md")
 
 
-def sweep_source_hash() -> str:
+def sweep_source_hash(sources=SWEEP_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -90,16 +94,16 @@ def bk_flops_per_pair(n_k: int, ell_max: int, with_c: bool = True) -> float:
     return 40.0 + (60.0 + 10.0 * n_l) * (n_k + 1) + 6.0 * n_l * n_l + 2.0 * n_k * n_l * n_l + c_term
 
 
-def traffic_from_profile():
+def traffic_from_profile(profile=PROFILE, sources=SWEEP_SOURCES):
     """HBM bytes per sweep launch from the committed counter summary, or None."""
-    if not os.path.exists(PROFILE):
+    if not os.path.exists(profile):
         return None
-    txt = open(PROFILE).read()
+    txt = open(profile).read()
     m = re.search(r"<!-- traffic-json (\{.*?\}) -->", txt, re.S)
     if not m:
         return None
     d = json.loads(m.group(1))
-    if d.get("source_hash") != sweep_source_hash():
+    if d.get("source_hash") != sweep_source_hash(sources):
         return None
     return d.get("bytes_per_launch")
 
@@ -129,18 +133,31 @@ def table_form(hp, pos, wl, steps: int, warmup: int):
             "max_rel_err_vs_fp64": float(np.max(np.abs(got - ref) / np.abs(ref)))}
 
 
+def host_cores():
+    """Threads this process may run on, and the CPU model."""
+    threads = os.cpu_count() or 1
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return threads, model
+
+
 def cpu_baseline(wl, n_primaries: int = 16384, seed: int = 0):
     """Time the FP64 oracle on a fixed subset of primaries (every secondary)."""
     import oracle
     rng = np.random.default_rng(seed)
     mask = np.zeros(wl.n, np.uint8)
     mask[rng.choice(wl.n, n_primaries, replace=False)] = 1
-    threads = os.cpu_count() or 1
-    try:
-        threads = len(os.sched_getaffinity(0))
-    except Exception:
-        pass
-    threads = min(threads, 16)
+    threads, _ = host_cores()
     t0 = time.perf_counter()
     ref = oracle.pk_ell(wl.pos, wl.weights, wl.box, wl.r0, wl.k_edges_p, wl.ell_max_p,
                         primary_mask=mask, nthreads=threads)
@@ -151,6 +168,159 @@ def cpu_baseline(wl, n_primaries: int = 16384, seed: int = 0):
     return {"value": pw / dt, "unit": "pair-weights/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_primaries} random primaries of the {wl.n}-point catalogue against all "
                       f"{wl.n} secondaries ({ref['n_pairs']} ordered pairs, {dt:.1f} s)"}
+
+
+def cpu_baseline_headline(wl, n_pk: int, n_bk: int, f_rand: float, seed: int, rseed: int = 0):
+    """The FP64 oracle on the host cores over a fixed subset of the headline
+    workload's primaries: P on n_pk data primaries, B on n_bk data and
+    f_rand n_bk random primaries (the library's drawn catalogue, regenerated
+    here by the oracle), every secondary; pair-weights per second of the
+    two calls together, in the headline's units."""
+    import oracle
+    threads, model = host_cores()
+    rng = np.random.default_rng(rseed)
+    mp = np.zeros(wl.n, np.uint8)
+    mp[rng.choice(wl.n, n_pk, replace=False)] = 1
+    mb = np.zeros(wl.n, np.uint8)
+    mb[rng.choice(wl.n, n_bk, replace=False)] = 1
+    n_r = int(round(f_rand * wl.n))
+    rpos = oracle.philox_randoms(n_r, wl.box, seed)
+    mr = np.zeros(n_r, np.uint8)
+    mr[rng.choice(n_r, int(round(f_rand * n_bk)), replace=False)] = 1
+    t0 = time.perf_counter()
+    rp = oracle.pk_ell(wl.pos, wl.weights, wl.box, wl.r0, wl.k_edges_p, wl.ell_max_p, primary_mask=mp,
+                       nthreads=threads)
+    t1 = time.perf_counter()
+    rb = oracle.bk_ell(wl.pos, wl.weights, rpos, None, wl.box, wl.r0, wl.k_edges_b, wl.ell_max_b, mask_d=mb,
+                       mask_r=mr, nthreads=threads)
+    t2 = time.perf_counter()
+    n_kp, n_lp = len(wl.k_edges_p) - 1, wl.ell_max_p // 2 + 1
+    n_kb, n_lb = len(wl.k_edges_b) - 1, wl.ell_max_b + 1
+    pw = rp["n_pairs"] * n_kp * n_lp + (rb["n_pairs_dd"] + rb["n_pairs_rd"]) * n_kb * n_lb * n_lb
+    return {"value": pw / (t2 - t0), "unit": "pair-weights/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "nproc": os.cpu_count(),
+            "sample": (f"P: {n_pk} random primaries of the {wl.n}-point catalogue against every secondary "
+                       f"({rp['n_pairs']} ordered pairs, {t1 - t0:.1f} s); B: {n_bk} data and "
+                       f"{int(round(f_rand * n_bk))} random primaries ({rb['n_pairs_dd']} + {rb['n_pairs_rd']} "
+                       f"ordered pairs, {t2 - t1:.1f} s)")}
+
+
+def headline(args, hp, torch, synthetic):
+    """The whole hot path on the largest single-GPU configuration: P and B of
+    the 2^24-point weighted box per step (see the module docstring)."""
+    wl = synthetic.workload(5)
+    f_rand, seed = wl.f_rand, wl.seed
+    pos = torch.from_numpy(wl.pos).cuda()
+    w = torch.from_numpy(wl.weights).cuda()
+    n_kp, n_lp = len(wl.k_edges_p) - 1, wl.ell_max_p // 2 + 1
+    n_kb, n_lb = len(wl.k_edges_b) - 1, wl.ell_max_b + 1
+    ctx = hp.Context(0, torch.cuda.current_stream().cuda_stream)
+
+    def step(prec):
+        _, ip = hp.pk_ell(pos, w, box=wl.box, r0=wl.r0, k_edges=wl.k_edges_p, ell_max=wl.ell_max_p,
+                          precision=prec, return_diag=True, ctx=ctx)
+        _, ib = hp.bk_ell(pos, w, box=wl.box, r0=wl.r0, k_edges=wl.k_edges_b, ell_max=wl.ell_max_b,
+                          precision=prec, f_rand=f_rand, seed=seed, return_diag=True, ctx=ctx)
+        return ip, ib
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        acc = {"bk_sweep_ms": 0.0, "bk_launches": 0, "pk_sweep_ms": 0.0, "pk_far_ms": 0.0, "pk_launches": 0,
+               "pk_ms": 0.0, "bk_ms": 0.0, "bk_cterm_ms": 0.0}
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ip, ib = step(prec)
+            acc["bk_sweep_ms"] += ib["ms_sweep"]
+            acc["bk_launches"] += ib["sweep_launches"]
+            acc["bk_ms"] += ib["ms_total"]
+            acc["bk_cterm_ms"] += ib["ms_cterm"]
+            acc["pk_sweep_ms"] += ip["ms_sweep"]
+            acc["pk_far_ms"] += ip["ms_sweep_far"]
+            acc["pk_launches"] += ip["sweep_launches"]
+            acc["pk_ms"] += ip["ms_total"]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        pw_p = ip["n_pairs"] * n_kp * n_lp
+        pw_b = (ib["n_pairs"] + ib["n_pairs_rand"]) * n_kb * n_lb * n_lb
+        return dt, ip, ib, acc, pw_p, pw_b
+
+    dt, ip, ib, acc, pw_p, pw_b = timed("mixed", args.steps, args.warmup)
+    steps = args.steps
+    # dominant kernel: the bispectrum sweep, two launches per step (data and
+    # random primaries); the mixed form's C sums are the histogram sweep's
+    launches_per_step = acc["bk_launches"] / steps
+    bk_flops = (ib["n_pairs"] + ib["n_pairs_rand"]) * bk_flops_per_pair(n_kb, wl.ell_max_b, with_c=False)
+    flops_per_launch = bk_flops / launches_per_step
+    avg_launch_ms = acc["bk_sweep_ms"] / max(acc["bk_launches"], 1)
+    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    # every bispectrum kernel of the step (sweep + C-term histogram), against
+    # the full per-pair model with the C sums
+    bk_full = (ib["n_pairs"] + ib["n_pairs_rand"]) * bk_flops_per_pair(n_kb, wl.ell_max_b, with_c=True)
+    bk_kernels_ms = (acc["bk_sweep_ms"] + acc["bk_cterm_ms"]) / steps
+    whole_b = bk_full / (bk_kernels_ms * 1e-3) / 1e12
+    pk_per_pair = pk_flops_per_pair(n_kp, n_lp)
+    pk_far_ms = acc["pk_far_ms"] / steps
+    out = {"metric": METRIC, "value": (pw_p + pw_b) / dt, "unit": "pair-weights/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+           "config": {"workload": wl.name, "n_points": wl.n, "box": wl.box, "r0": wl.r0, "weights": "U[0.5, 1.5]",
+                      "pk": {"n_k": n_kp, "ells": [0, 2, 4], "k_range": [2.0, 20.0], "bins": "log"},
+                      "bk": {"n_k": n_kb, "ell_max": wl.ell_max_b, "k_range": [2.0, 20.0], "bins": "log",
+                             "f_rand": f_rand, "n_randoms": int(ib["n_rand"]), "randoms": "drawn on the device"},
+                      "precision": "mixed"},
+           "roofline": {"bound": "alu", "kernel": "k_bk_quad", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                        "frac_fp64": achieved / PEAK_FP64_TFLOPS,
+                        "traffic": traffic_from_profile(BK_PROFILE, BK_SOURCES),
+                        "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_launch_ms,
+                        "pairs_per_launch": (ib["n_pairs"] + ib["n_pairs_rand"]) / launches_per_step,
+                        "whole_bispectrum": {"kernels": "k_bk_quad + C-term histogram sweep",
+                                             "flops_per_step": bk_full, "kernel_ms_per_step": bk_kernels_ms,
+                                             "achieved": whole_b, "frac": whole_b / PEAK_VALU_TFLOPS}},
+           "parts": {"pk": {"pair_weights": pw_p, "ordered_pairs": ip["n_pairs"], "ms": acc["pk_ms"] / steps,
+                            "sweep_ms": acc["pk_sweep_ms"] / steps,
+                            "far_kernel": {"ms": pk_far_ms, "pairs": ip["n_pairs_far"],
+                                           "frac": (ip["n_pairs_far"] * pk_per_pair / (pk_far_ms * 1e-3) / 1e12
+                                                    / PEAK_VALU_TFLOPS) if pk_far_ms > 0 else None}},
+                     "bk": {"pair_weights": pw_b, "ordered_pairs_dd": ib["n_pairs"],
+                            "ordered_pairs_rd": ib["n_pairs_rand"], "ms": acc["bk_ms"] / steps,
+                            "sweep_ms": acc["bk_sweep_ms"] / steps, "cterm_ms": acc["bk_cterm_ms"] / steps}}}
+    if not args.no_fp64_form:
+        dt64, ip64, ib64, acc64, pwp64, pwb64 = timed("fp64", 1, 1)
+        out["fp64_form"] = {"value": (pwp64 + pwb64) / dt64, "unit": "pair-weights/s", "ms_per_step": dt64 * 1e3,
+                            "pk_ms": acc64["pk_ms"], "bk_ms": acc64["bk_ms"],
+                            "pair_counts_equal": bool(ip64["n_pairs"] == ip["n_pairs"]
+                                                      and ib64["n_pairs"] == ib["n_pairs"]
+                                                      and ib64["n_pairs_rand"] == ib["n_pairs_rand"]),
+                            "mixed_speedup": dt64 / dt}
+    if not args.no_config2:
+        wl2 = synthetic.workload(2)
+        pos2 = torch.from_numpy(wl2.pos).cuda()
+        nk2, nl2 = len(wl2.k_edges_p) - 1, wl2.ell_max_p // 2 + 1
+        kw2 = dict(box=wl2.box, r0=wl2.r0, k_edges=wl2.k_edges_p, ell_max=wl2.ell_max_p, return_diag=True, ctx=ctx)
+        for _ in range(2):
+            hp.pk_ell(pos2, **kw2)
+        torch.cuda.synchronize()
+        n2, far2, fms2 = 10, 0, 0.0
+        t0 = time.perf_counter()
+        for _ in range(n2):
+            _, i2 = hp.pk_ell(pos2, **kw2)
+            fms2 += i2["ms_sweep_far"]
+            far2 = i2["n_pairs_far"]
+        torch.cuda.synchronize()
+        dt2 = (time.perf_counter() - t0) / n2
+        far_ach = far2 * pk_flops_per_pair(nk2, nl2) / (fms2 / n2 * 1e-3) / 1e12
+        out["pk_config2"] = {"workload": wl2.name, "value": i2["n_pairs"] * nk2 * nl2 / dt2, "unit": "pair-weights/s",
+                             "ms_per_step": dt2 * 1e3,
+                             "roofline": {"kernel": "k_pk_far", "achieved": far_ach,
+                                          "frac": far_ach / PEAK_VALU_TFLOPS, "avg_launch_ms": fms2 / n2,
+                                          "traffic": traffic_from_profile()},
+                             "table_form": table_form(hp, pos2, wl2, 10, 2)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_headline(wl, args.cpu_pk_primaries, args.cpu_bk_primaries, f_rand, seed)
+    print(json.dumps(out), flush=True)
 
 
 def calibrate_copy(nbytes: int = 1 << 30):
@@ -167,15 +337,19 @@ def calibrate_copy(nbytes: int = 1 << 30):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pk",
-                    choices=["pk", "pk-fp64", "pk-table", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64", "survey-table",
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "pk", "pk-fp64", "pk-table", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64", "survey-table",
                              "bk-analytic", "bk-analytic-fp64", "bk5-analytic", "cov", "batch-analytic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-table-form", action="store_true",
                     help="pk workload: leave out the table-form measurement (for profiling the mixed path alone)")
     ap.add_argument("--cpu-primaries", type=int, default=16384)
+    ap.add_argument("--cpu-pk-primaries", type=int, default=2048, help="headline: oracle P sample")
+    ap.add_argument("--cpu-bk-primaries", type=int, default=512, help="headline: oracle B sample (data primaries)")
+    ap.add_argument("--no-fp64-form", action="store_true", help="headline: leave out the FP64-form step")
+    ap.add_argument("--no-config2", action="store_true", help="headline: leave out the 2e6-point power spectrum")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--scale", type=float, default=0.1,
                     help="batch workload: fraction of each box's N (pairs scale as its square)")
@@ -197,6 +371,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.synchronize()
+    if args.workload == "headline":
+        headline(args, hp, torch, synthetic)
+        return
 
     if args.workload in ("pk", "pk-fp64", "pk5", "pk-table"):
         wl = synthetic.workload(5 if args.workload == "pk5" else 2)
@@ -235,15 +412,15 @@ def main():
         prec = "fp64" if args.workload == "bk-fp64" else "mixed"
         pos = torch.from_numpy(wl.pos).cuda()
         w = None if wl.weights is None else torch.from_numpy(wl.weights).cuda()
-        rnd = torch.from_numpy(wl.randoms()).cuda()
         n_k = len(wl.k_edges_b) - 1
 
         def step():
-            return hp.bk_ell(pos, w, rnd, box=wl.box, r0=wl.r0, k_edges=wl.k_edges_b, ell_max=wl.ell_max_b,
-                             precision=prec, return_diag=True)
+            # f_rand = 3 randoms drawn by the library on the device from the seed
+            return hp.bk_ell(pos, w, box=wl.box, r0=wl.r0, k_edges=wl.k_edges_b, ell_max=wl.ell_max_b,
+                             precision=prec, f_rand=wl.f_rand, seed=wl.seed, return_diag=True)
         units_per_pair = n_k * (wl.ell_max_b + 1) ** 2
-        cfg = {"workload": wl.name, "n_points": wl.n, "n_randoms": int(rnd.shape[0]), "box": wl.box, "r0": wl.r0,
-               "n_k": n_k, "ell_max": wl.ell_max_b, "precision": prec}
+        cfg = {"workload": wl.name, "n_points": wl.n, "n_randoms": int(round(wl.f_rand * wl.n)), "box": wl.box,
+               "r0": wl.r0, "n_k": n_k, "ell_max": wl.ell_max_b, "precision": prec, "randoms": "drawn on the device"}
     elif args.workload == "cov":
         # theory side: Gaussian covariance of the headline power spectrum's
         # binning (40 log bins over 1-10 h/Mpc, R0 = 25, l = 0, 2, 4) on a
@@ -363,7 +540,7 @@ def main():
                "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None, "dtype": "f64+f32" if prec == "mixed" else "f64", "data": "synthetic",
                "config": cfg,
-               "roofline": {"bound": "alu", "kernel": "k_bk_fused", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+               "roofline": {"bound": "alu", "kernel": "k_bk_quad", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                             "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
                             "frac_fp64": achieved / PEAK_FP64_TFLOPS, "traffic": None, "flops_per_launch": flops,
                             "avg_launch_ms": avg_launch_ms},
@@ -427,10 +604,10 @@ def main():
                                "traffic": None, "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
     else:
         # both primary catalogues, per launch (data primaries, then random primaries)
-        flops = (pairs * bk_flops_per_pair(n_k, wl.ell_max_b, with_c=prec == "fp64")
-                 + pairs_r * bk_flops_per_pair(n_k, wl.ell_max_b)) / (launches / args.steps)
+        flops = ((pairs + pairs_r) * bk_flops_per_pair(n_k, wl.ell_max_b, with_c=prec == "fp64")
+                 / (launches / args.steps))
         achieved = flops / (avg_launch_ms * 1e-3) / 1e12
-        out["roofline"] = {"bound": "alu", "kernel": "k_bk_fused", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+        out["roofline"] = {"bound": "alu", "kernel": "k_bk_quad", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                            "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
                            "frac_fp64": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                            "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
