@@ -162,6 +162,22 @@ void hipster_destroy(hipster_ctx *ctx);
 hipster_status hipster_pk_ell(hipster_ctx *ctx, const hipster_points *pts,
                               const hipster_params *prm, double *pk, hipster_diag *diag);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and outputs as hipster_pk_ell, with every device buffer taken
+ * from a static 256 MiB workspace that each device holds from the library's
+ * load until the process ends; the call makes no hipMalloc or hipFree and
+ * creates no HIP events (the diag timings read 0).  Inputs and outputs are
+ * the caller's, as for hipster_pk_ell.  The pair stream is cut into as many
+ * chunks as the workspace needs, so sums agree with hipster_pk_ell to
+ * rounding.  A call whose cell lists, or one cell tile's pairs, do not fit
+ * (about 75 B per point and 70 B per cell; some 2e6 points at most) returns
+ * HIPSTER_ENOMEM with a message; diag->l1_mass must be NULL
+ * (HIPSTER_EUNSUPPORTED otherwise).  All calls on one device share its
+ * workspace: calls that overlap on one device race. */
+hipster_status hipster_pk_ell_noalloc(hipster_ctx *ctx, const hipster_points *pts,
+                                      const hipster_params *prm, double *pk, hipster_diag *diag);
+
 /* Bispectrum multipoles (Sec. 4, summary estimator).  The DDR^II term is
  * sampled with uniform random primaries (Sec. 4, a random catalogue f_rand
  * times the size of the data): randoms, if non-NULL with n > 0, is that

@@ -17,7 +17,7 @@ from typing import Any
 
 import numpy as np
 
-__all__ = ["Context", "wtilde", "pk_ell", "bk_ell", "batch", "HipsterError", "library_path", "load_library",
+__all__ = ["Context", "wtilde", "pk_ell", "pk_ell_noalloc", "bk_ell", "batch", "HipsterError", "library_path", "load_library",
            "EXPORTED_SYMBOLS", "MIXED", "FP64", "TABLE", "pk_survey", "bk_ell_analytic", "eii_table",
            "omega", "pk_window_theory", "cov_gauss", "cov_poisson2", "cov_poisson3", "cov_nongauss"]
 
@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = ("hipster_create", "hipster_destroy", "hipster_pk_ell", "hips
                     "hipster_set_memory_cap", "hipster_wtilde", "hipster_pk_survey",
                     "hipster_bk_ell_analytic", "hipster_eii_table", "hipster_omega",
                     "hipster_pk_window_theory", "hipster_cov_gauss", "hipster_cov_poisson2",
-                    "hipster_cov_poisson3", "hipster_cov_nongauss")
+                    "hipster_cov_poisson3", "hipster_cov_nongauss", "hipster_pk_ell_noalloc")
 
 
 class HipsterError(RuntimeError):
@@ -100,6 +100,9 @@ def load_library():
     L.hipster_destroy.argtypes = [ct.c_void_p]
     L.hipster_pk_ell.restype = ct.c_int
     L.hipster_pk_ell.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Params), _dp, ct.POINTER(_Diag)]
+    L.hipster_pk_ell_noalloc.restype = ct.c_int
+    L.hipster_pk_ell_noalloc.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Params), _dp,
+                                         ct.POINTER(_Diag)]
     L.hipster_pk_survey.restype = ct.c_int
     L.hipster_pk_survey.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Points), ct.POINTER(_SurveyParams),
                                     _dp, ct.POINTER(_Diag)]
@@ -278,6 +281,22 @@ def pk_ell(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, los
     count and device timings (and "table_nodes", the table's interval count,
     in the table form); with l1_mass as well, "l1_mass", the L1 mass of the
     raw sums per bin (an extra double-precision pass of the library)."""
+    return _pk_ell_call("hipster_pk_ell", pos, w, box, r0, k_edges, ell_max, los_axis, precision, primary_mask,
+                        ctx, return_diag, l1_mass)
+
+
+def pk_ell_noalloc(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, los_axis: int = 2,
+                   precision: str = "mixed", primary_mask=None, ctx: Context | None = None,
+                   return_diag: bool = False) -> Any:
+    """pk_ell through hipster_pk_ell_noalloc: the same result, with the
+    library's device scratch taken from its static per-device workspace
+    instead of allocations (timings in the diag read 0; no l1_mass)."""
+    return _pk_ell_call("hipster_pk_ell_noalloc", pos, w, box, r0, k_edges, ell_max, los_axis, precision,
+                        primary_mask, ctx, return_diag, False)
+
+
+def _pk_ell_call(entry, pos, w, box, r0, k_edges, ell_max, los_axis, precision, primary_mask, ctx, return_diag,
+                 l1_mass):
     L = load_library()
     keep: list = []
     pts = _points(pos, w, keep)
@@ -290,7 +309,7 @@ def pk_ell(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, los
     d = _Diag()
     d.raw, d.wtilde, d.l1_mass = _ptr(raw), _ptr(wt), _ptr(l1)
     c = ctx or _context_for(pos)
-    c.check(L.hipster_pk_ell(c.handle, ct.byref(pts), ct.byref(prm), _ptr(out), ct.byref(d)))
+    c.check(getattr(L, entry)(c.handle, ct.byref(pts), ct.byref(prm), _ptr(out), ct.byref(d)))
     if not return_diag:
         return out
     info = {"raw": raw, "wtilde": wt, "n_pairs": int(d.n_pairs), "ms_build": d.ms_build,

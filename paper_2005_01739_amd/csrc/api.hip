@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -20,6 +21,17 @@ namespace hipster {
 void *ensure(Ctx &c, DevBuf &b, size_t bytes) {
   if (bytes == 0) bytes = 8;
   if (b.cap >= bytes) return b.p;
+  if (c.arena) {
+    const size_t off = (c.arena_used + 255) & ~size_t(255);
+    if (off > c.arena_cap || bytes > c.arena_cap - off)
+      throw Error{HIPSTER_ENOMEM, "the call needs more device scratch than the " +
+                                      std::to_string(c.arena_cap >> 20) +
+                                      " MiB static workspace of the no-allocation entry point holds"};
+    b.p = c.arena + off;
+    b.cap = bytes;
+    c.arena_used = off + bytes;
+    return b.p;
+  }
   if (b.p) {
     HIPSTER_HIP(hipStreamSynchronize(c.stream));
     HIPSTER_HIP(hipFree(b.p));
@@ -41,6 +53,11 @@ void *ensure(Ctx &c, DevBuf &b, size_t bytes) {
   b.cap = want;
   c.mem_used += want;
   return b.p;
+}
+
+size_t arena_left(const Ctx &c) {
+  const size_t off = (c.arena_used + 255) & ~size_t(255);
+  return off < c.arena_cap ? c.arena_cap - off : 0;
 }
 
 void wtilde_bins(Ctx &c, double r0, int n_k, const double *k_edges, double *out) {
@@ -132,6 +149,7 @@ struct Timer {
   std::vector<hipEvent_t> evs;
   explicit Timer(Ctx &cc) : c(cc) {}
   hipEvent_t mark() {
+    if (c.arena) return nullptr;  // workspace mode: no events, times read 0
     hipEvent_t e;
     HIPSTER_HIP(hipEventCreate(&e));
     HIPSTER_HIP(hipEventRecord(e, c.stream));
@@ -139,6 +157,7 @@ struct Timer {
     return e;
   }
   static double ms(hipEvent_t a, hipEvent_t b) {
+    if (!a || !b) return 0.0;
     float t = 0.f;
     if (hipEventElapsedTime(&t, a, b) != hipSuccess) return 0.0;
     return double(t);
@@ -210,7 +229,20 @@ static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t nunits, CountF &&cou
   const int64_t total = pairs_in(0, nunits);
   if (total == 0) return st;
   int64_t cap = std::min<int64_t>(pair_chunk_capacity(), total);
-  for (int64_t a = 0; a < nunits; ++a) cap = std::max(cap, pairs_in(a, a + 1));
+  int64_t unit_max = 0;
+  for (int64_t a = 0; a < nunits; ++a) unit_max = std::max(unit_max, pairs_in(a, a + 1));
+  cap = std::max(cap, unit_max);
+  if (c.arena && c.pr.cap == 0) {
+    // workspace mode: the three 8-byte pair arrays take what is left after
+    // a reserve for the merged sums, so a larger catalogue runs in more chunks
+    constexpr size_t kReserve = size_t(1) << 16;
+    const size_t left = arena_left(c);
+    const int64_t fit = left > kReserve + 1024 ? int64_t((left - kReserve - 1024) / 24) : 0;
+    if (fit < unit_max)
+      throw Error{HIPSTER_ENOMEM, "the pair stream of one cell tile does not fit the static workspace of the "
+                                  "no-allocation entry point"};
+    cap = std::min(cap, fit);
+  }
   PkPairs pp;
   pp.r = static_cast<double *>(ensure(c, c.pr, size_t(cap) * 8));
   pp.mu = ensure(c, c.pmu, size_t(cap) * 8);
@@ -239,7 +271,8 @@ static SweepStats sweep_pair_set(Ctx &c, Timer &tm, int64_t nunits, CountF &&cou
       hipEvent_t d = tm.mark();
       // the L1 mass, an extra double-precision pass over the same pairs
       if (l1_rows) pk_l1_sweep(c, pp, np, n_ell, r0, edges, n_edges, l1_rows, nwaves);
-      HIPSTER_HIP(hipEventSynchronize(d));
+      if (d) HIPSTER_HIP(hipEventSynchronize(d));
+      else HIPSTER_HIP(hipStreamSynchronize(c.stream));
       st.ms_pairs += Timer::ms(a, b);
       st.ms_sweep += Timer::ms(b, d);
       st.ms_far += Timer::ms(m, d);
@@ -1190,6 +1223,59 @@ static hipster_status guarded(hipster_ctx *ctx, F &&f) {
   }
 }
 
+// ------------------------------------------------ no-allocation workspace
+// Device scratch of hipster_pk_ell_noalloc: a static array that each device
+// holds from the code object's load until the process ends.  In host code the
+// array's name is not a device address: hipster_create looks up the calling
+// device's copy once with hipGetSymbolAddress and the entry point passes that
+// pointer on.  Every call on one device shares its copy, so calls that overlap
+// on a device race; each call clears what its kernels need zeroed.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kScratchDevices];
+
+// With `device` current, record its copy of the workspace (once per device).
+static hipster_status scratch_setup(int device) {
+  if (device < 0 || device >= kScratchDevices) return HIPSTER_OK;  // the entry point reports it
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return HIPSTER_OK;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return HIPSTER_EHIP;
+  }
+  g_scratch_ptr[device] = static_cast<unsigned char *>(p);
+  return HIPSTER_OK;
+}
+
+static unsigned char *scratch_of(int device) {
+  if (device < 0 || device >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+// hipster_pk_ell with every device buffer carved from the workspace: a
+// context of its own (device, stream and the measured kernel parameters of
+// the caller's context) in workspace mode, discarded afterwards without
+// freeing anything.
+static void run_pk_noalloc(Ctx &parent, const hipster_points *pts, const hipster_params *q, double *pk,
+                           hipster_diag *diag) {
+  if (diag && diag->l1_mass)
+    throw Error{HIPSTER_EUNSUPPORTED, "diag->l1_mass is not available from hipster_pk_ell_noalloc"};
+  unsigned char *ws = scratch_of(parent.device);
+  if (!ws) throw Error{HIPSTER_EUNSUPPORTED, "no static workspace on this device"};
+  Ctx w;
+  w.device = parent.device;
+  w.stream = parent.stream;
+  w.tune = parent.tune;
+  w.tune_file_read = parent.tune_file_read;
+  w.arena = ws;
+  w.arena_cap = kScratchBytes;
+  run_pk(w, pts, q, pk, diag);
+}
+
 }  // namespace hipster
 
 using namespace hipster;
@@ -1205,6 +1291,7 @@ hipster_status hipster_create(hipster_ctx **out, int device, void *hip_stream) {
     return HIPSTER_EHIP;
   }
   if (hipSetDevice(device) != hipSuccess) return HIPSTER_EHIP;
+  if (scratch_setup(device) != HIPSTER_OK) return HIPSTER_EHIP;
   hipster_ctx *h = new (std::nothrow) hipster_ctx();
   if (!h) return HIPSTER_ENOMEM;
   h->c.device = device;
@@ -1237,6 +1324,11 @@ void hipster_destroy(hipster_ctx *ctx) {
 hipster_status hipster_pk_ell(hipster_ctx *ctx, const hipster_points *pts, const hipster_params *prm, double *pk,
                               hipster_diag *diag) {
   return guarded(ctx, [&] { run_pk(ctx->c, pts, prm, pk, diag); });
+}
+
+hipster_status hipster_pk_ell_noalloc(hipster_ctx *ctx, const hipster_points *pts, const hipster_params *prm,
+                                      double *pk, hipster_diag *diag) {
+  return guarded(ctx, [&] { run_pk_noalloc(ctx->c, pts, prm, pk, diag); });
 }
 
 hipster_status hipster_pk_survey(hipster_ctx *ctx, const hipster_points *data, const hipster_points *randoms,

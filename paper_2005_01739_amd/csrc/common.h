@@ -42,6 +42,8 @@ struct DevBuf {
 
 struct Ctx;
 void *ensure(Ctx &c, DevBuf &b, size_t bytes);
+// Bytes of the workspace still free after alignment (workspace mode only).
+size_t arena_left(const Ctx &c);
 
 // Cell grid: n_c cells per axis of side L / n_c > R0 covering the cube
 // [o, o + L)^3.  A periodic box has o = 0; a survey grid is the bounding cube
@@ -113,6 +115,11 @@ struct Ctx {
   hipStream_t stream = nullptr;
   uint64_t mem_cap = 0;
   uint64_t mem_used = 0;
+  // Workspace mode (the no-allocation entry point): when arena is set,
+  // ensure() hands out 256-byte-aligned pieces of [arena, arena + arena_cap)
+  // in order and never calls the allocator, and no HIP events are created.
+  unsigned char *arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
   std::string last_error;
   CellScratch cells_d, cells_r;
   DevBuf pos_in, w_in, mask_in, rpos_in, rw_in, rmask_in;

@@ -240,7 +240,8 @@ static void launch_far_any(Ctx &c, int ch, const PkPairs &p, int64_t npairs, boo
 // compiled size on the first kTunePairs pairs into a scratch row set (two
 // runs each, the faster counted) and keeps the fastest in the context, and
 // in the file named by HIPSTER_TUNE_CACHE if set (one line per shape, keyed
-// by the device).  Smaller sweeps use the cost model of pick_chunk.  The
+// by the device).  Smaller sweeps, and sweeps in workspace mode (which
+// creates no events), use the cost model of pick_chunk.  The
 // chunk size does not change any sum (each edge adds the same pairs in the
 // same order), so the choice affects time only.
 constexpr int64_t kTunePairs = int64_t(1) << 22;
@@ -253,7 +254,7 @@ static int tuned_chunk(Ctx &c, const PkPairs &p, int64_t npairs, bool fp64, doub
   const std::string key = tune_key(c, "pk_far", {NE, n_edges, fp64 ? 1 : 0});
   const int known = tune_lookup(c, key);
   if (known > 0) return known;
-  if (npairs < kTunePairs) return pick_chunk(sizes, n_edges);
+  if (npairs < kTunePairs || c.arena) return pick_chunk(sizes, n_edges);
   const size_t rows = size_t(nwaves) * NE * n_edges;
   double *scratch = static_cast<double *>(ensure(c, c.tune_scratch, rows * 8));
   hipEvent_t e0, e1;
