@@ -13,17 +13,22 @@
 // ring buffer per row; batches of up to 8 pairs per row are staged (lane =
 // (row, pair): geometry, y_lm times w_q W, the top bin edge) and then swept in
 // steps of one pair per row.  (Eight, not sixteen: the staging's LDS is what
-// limits the waves per CU.)  In a step lane (col, row) evaluates G_l at bin
-// edge 16 g + col for its row's pair, takes the next edge's value from lane
-// col + 1 by DPP, forms the bin average, and adds it times every y_lm into
-// FP64 accumulators A^{16g+col}_lm of its row's primary.  The y_lm of the
-// step's pair reach all lanes of a row as 64-bit DPP broadcasts
-// (row_newbcast) fused into the multiply-adds (fmac_dpp.h).
+// limits the waves per CU.)  In a step lane (col, row) evaluates
+// k_e^3 G_l(k_e r) at bin edge e = 16 g + col for its row's pair and adds it
+// times every y_lm into FP64 accumulators of its row's primary.  The y_lm of
+// the step's pair reach all lanes of a row as 64-bit DPP broadcasts
+// (row_newbcast) fused into the multiply-adds (fmac_dpp.h).  The mixed form
+// sums per edge and takes each bin's sum A^{16g+col}_lm once per quad as the
+// difference of adjacent lanes' edge sums (the top edge of the group summed
+// from the staged values); the FP64 form, which also forms the C sums from
+// each pair's bin values, takes the next edge's value from lane col + 1 by
+// DPP in every step.
 //
-// Up to 16 bins: after the quad, G_l += A_l A_l^T on the FP64 matrix cores,
-// the four primaries of the quad forming the instruction's K = 4 dimension.
-// More bins: one pass over the quads per group of 16 bins, A written to a
-// buffer, then the Gram as a separate matrix-core contraction (k_bk_gram).
+// Up to 16 bins: after each quad, G_l += A_l A_l^T on the FP64 matrix cores,
+// the four primaries of the quad forming the instruction's K = 4 dimension,
+// into accumulators that stay in registers until the wave ends.  More bins:
+// one pass over the quads per group of 16 bins, A written to a buffer, then
+// the Gram as a separate matrix-core contraction (k_bk_gram).
 //
 // Quads go to waves by a fixed rule and every sum is taken in a fixed order,
 // so results are bitwise reproducible.
@@ -237,18 +242,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   const double ktop3 = ktop * ktop * ktop, iktop = ktop > 0.0 ? 1.0 / ktop : 0.0;
   const double r_neutral = 0.5 / A.inv_r0, ir_neutral = 2.0 * A.inv_r0;
   const double L = A.L;
+  // Without the C sums (mixed form) each lane sums its own edge's values,
+  // E^e_lm = sum_pairs k_e^3 G_l(k_e r) w_q W y_lm, and the bin sums are taken
+  // once per quad as differences of adjacent lanes' sums; the top edge of a
+  // full group is summed from the staged values (tacc, harmonic k = col + 16 i
+  // of this row, multipole lk[i]).  The C sums need each pair's bin values,
+  // so the FP64 form differences per pair.
+  constexpr bool PER_EDGE = !WITH_C;
+  int lk[NY];
+#pragma unroll
+  for (int i = 0; i < NY; ++i) {
+    const int k = col + 16 * i;
+    int l = 0;
+#pragma unroll
+    for (int t = 1; t < NL; ++t) l += k >= t * t ? 1 : 0;
+    lk[i] = l;
+  }
   // pairs at r^2 >= rfar2 put every edge of the group on the large-argument
   // side (no Taylor or sine-integral series); rfar2 = inf leaves all near
   const double k_lo = A.edges[e0];
   const double rfar = k_lo > 0.0 ? HIPSTER_U_BIG / k_lo : 0.0;
   const double rfar2 = (FP64 || !(k_lo > 0.0)) ? __builtin_inf() : rfar * rfar * (1.0 + 1e-12);
 
-  // C sums (FP64 form) stay in registers; each quad's Gram contribution is
-  // added to the wave's own row right away, so no Gram accumulator occupies
-  // registers during the sweep
-  d4_t accC[NL];
+  // C sums (FP64 form) and the Gram tiles stay in matrix-core accumulators
+  // for the wave's whole life and reach its row once, at the end (a
+  // per-quad update of the 16 x 16 tiles in memory cost 10 KiB of writes per
+  // quad at l_max = 4, every one of them leaving L2)
+  d4_t accC[NL], accG[NL];
 #pragma unroll
-  for (int l = 0; l < NL; ++l) accC[l] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int l = 0; l < NL; ++l) accC[l] = accG[l] = d4_t{0.0, 0.0, 0.0, 0.0};
   double *const wrow = A.partial + int64_t(blockIdx.x) * A.rowlen;
   double s0acc = 0.0;
   unsigned long long pcount = 0;
@@ -325,9 +347,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       const double px = A.prim.x[my_pp], py = A.prim.y[my_pp], pz = A.prim.z[my_pp];
       const double wp = my_valid ? A.prim.w[my_pp] : 0.0;
 
-      double acc[NLM];
+      double acc[NLM], tacc[NY];
 #pragma unroll
       for (int k = 0; k < NLM; ++k) acc[k] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NY; ++i) tacc[i] = 0.0;
       // per class and row: hit count and ring head (uniform)
       int hn[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, hh[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 
@@ -392,6 +416,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           }
         }
         wave_sync();
+        if constexpr (PER_EDGE) {
+          if (top) {
+            for (int s = 0; s < cmax; ++s) {
+              const int slot = kRowBatch * row + s;
+#pragma unroll
+              for (int i = 0; i < NY; ++i) {
+                const int k = col + 16 * i;
+                if (k < NLM)
+                  tacc[i] = fma((&s_gt[0][0])[lk[i] * kSlots + slot], double(ylds[k * kYStride + slot]), tacc[i]);
+              }
+            }
+          }
+        }
         // steps: one pair per row.  Two operand sets alternate, so the next
         // step's LDS operands are read while the current step computes
         // without register copies.
@@ -421,11 +458,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           double gl[NL];
 #pragma unroll
           for (int l = 0; l < NL; ++l) {
-            // lane 15 of a row receives 0 from the shift and adds the top
-            // edge (s_gt is zero unless the group is full)
-            const double gn = from_next_lane_in_row(Ge.v[l]);
-            const double hi = fma(s_gt[l][slot], top_w, DT ? gn : kn3 * gn);
-            gl[l] = DT ? hi - Ge.v[l] : fma(-ke3, Ge.v[l], hi);
+            if constexpr (PER_EDGE) {
+              gl[l] = DT ? Ge.v[l] : ke3 * Ge.v[l];
+            } else {
+              // lane 15 of a row receives 0 from the shift and adds the top
+              // edge (s_gt is zero unless the group is full)
+              const double gn = from_next_lane_in_row(Ge.v[l]);
+              const double hi = fma(s_gt[l][slot], top_w, DT ? gn : kn3 * gn);
+              gl[l] = DT ? hi - Ge.v[l] : fma(-ke3, Ge.v[l], hi);
+            }
           }
           // acc[l*l+m] += (w_q W y_lm)(pair) * jbar^a_l(pair)
           fmac_all<0>(acc, yr, gl);
@@ -547,6 +588,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       while (max(max(hn[0][0], hn[0][1]), max(hn[0][2], hn[0][3])) > 0) batch(Far{});
       while (max(max(hn[1][0], hn[1][1]), max(hn[1][2], hn[1][3])) > 0) batch(Near{});
 
+      if constexpr (PER_EDGE) {
+        // bin e = E^{e+1} - E^e; lane 15 of a row takes E^{e+1} from tacc,
+        // each harmonic broadcast from the lane that holds it
+        double tk[NLM], ones[NL];
+#pragma unroll
+        for (int k = 0; k < NLM; ++k) tk[k] = 0.0;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) ones[l] = 1.0;
+        fmac_all<0>(tk, tacc, ones);
+#pragma unroll
+        for (int k = 0; k < NLM; ++k) {
+          const double nx = from_next_lane_in_row(acc[k]);
+          acc[k] = (col == 15 ? tk[k] : nx) - acc[k];
+        }
+      }
       // the quad's contribution; the bin's 3 / (k_{a+1}^3 - k_a^3) first
 #pragma unroll
       for (int k = 0; k < NLM; ++k) acc[k] *= cfb;
@@ -554,11 +610,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
           const double wsc = wp * (4.0 * kPi / double(2 * l + 1));
-          d4_t g = d4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int m = 0; m < 2 * l + 1; ++m) g = mfma_f64(acc[l * l + m], wsc * acc[l * l + m], g);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) wrow[l * 256 + (row + 4 * v) * 16 + col] += g[v];
+          for (int m = 0; m < 2 * l + 1; ++m) accG[l] = mfma_f64(acc[l * l + m], wsc * acc[l * l + m], accG[l]);
         }
       } else {
         const int64_t slot = (qi - A.q_lo) * 4 + row;
@@ -572,6 +625,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   }
   double *out = wrow;
   if constexpr (GRAM) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[l * 256 + (row + 4 * v) * 16 + col] += accG[l][v];
     if constexpr (WITH_C) {
 #pragma unroll
       for (int l = 0; l < NL; ++l)
