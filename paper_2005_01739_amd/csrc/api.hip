@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -669,141 +670,211 @@ static int check_eii_nodes(Ctx &c, const hipster_params *q, int n_x) {
 // analytic_nx < 0: the DDR^II term from the random primaries `rp`;
 // otherwise from the E^II kernel with that many table intervals (0: default)
 // and no randoms.
-static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, double f_rand, uint64_t seed,
-                   const hipster_params *q, double *bk, hipster_diag *diag, int analytic_nx = -1) {
-  check_points(dp, "data", q ? q->box : 0.0);
+// One box's bispectrum call in stages: checks, device inputs, the sweeps, the
+// C-term and analytic stages, and the host assembly.  A single call runs them
+// in turn on the context's scratch; a batch prepares every box on scratch of
+// its own, sweeps all of them in one queued launch, then finishes each.
+struct BkBufs {
+  CellScratch *cd, *cr;
+  DevBuf *pos, *w, *mask, *rpos, *rw, *rmask, *rgen, *edges, *coef, *cnt;
+};
+
+struct BkBox {
+  const hipster_points *dp = nullptr, *rp = nullptr;
+  hipster_points genp{};
+  const hipster_params *q = nullptr;
+  double *bk = nullptr;
+  hipster_diag *diag = nullptr;
+  double f_rand = 0.0;
+  uint64_t seed = 0;
+  int analytic_nx = -1;
+  bool analytic = false, have_r = false, gen_r = false, c_hist = false, fp64 = false;
+  int64_t n_gen = 0;
+  Grid g{};
+  Sorted sd, sr;
+  const void *pos = nullptr, *w = nullptr;
+  const uint8_t *mask = nullptr;
+  double *edges = nullptr, *coef = nullptr;
+  unsigned long long *cnt = nullptr;  // [data pairs, random (or 2 R0) pairs, C-term pairs]
+  BkSums sums[2];
+  std::vector<double> Ch[2], T;
+  unsigned long long hcnt[2] = {0, 0};
+  double ms_build = 0.0, ms_sweep = 0.0, ms_cterm = 0.0, ms_table = 0.0, ms_ddr2 = 0.0;
+  hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;  // around the preparation (read after the last sync)
+  uint64_t launches = 0;
+};
+
+static void bk_check(Ctx &c, BkBox &x) {
+  const hipster_params *q = x.q;
+  check_points(x.dp, "data", q ? q->box : 0.0);
   check_params(q, true);
-  if (!bk) throw Error{HIPSTER_EINVAL, "NULL output"};
-  if (dp->n < 2) throw Error{HIPSTER_EINVAL, "need at least two points"};
-  const bool analytic = analytic_nx >= 0;
-  if (analytic) {
+  if (!x.bk) throw Error{HIPSTER_EINVAL, "NULL output"};
+  if (x.dp->n < 2) throw Error{HIPSTER_EINVAL, "need at least two points"};
+  x.analytic = x.analytic_nx >= 0;
+  if (x.analytic) {
     if (q->n_k > kEiiMaxNkApi)
       throw Error{HIPSTER_EUNSUPPORTED, "analytic DDR^II: n_k must lie in [1, " + std::to_string(kEiiMaxNkApi) + "]"};
-    analytic_nx = check_eii_nodes(c, q, analytic_nx);
+    x.analytic_nx = check_eii_nodes(c, q, x.analytic_nx);
   }
-  const bool given_r = !analytic && rp && rp->n > 0;
-  if (given_r) check_points(rp, "randoms", q->box);
-  const bool gen_r = !analytic && !given_r;
-  int64_t n_gen = 0;
-  if (gen_r) {
-    if (!(f_rand > 0.0) || !isfinite(f_rand))
+  const bool given_r = !x.analytic && x.rp && x.rp->n > 0;
+  if (given_r) check_points(x.rp, "randoms", q->box);
+  if (!given_r) x.rp = nullptr;
+  x.gen_r = !x.analytic && !given_r;
+  if (x.gen_r) {
+    if (!(x.f_rand > 0.0) || !isfinite(x.f_rand))
       throw Error{HIPSTER_EINVAL,
                   "bispectrum: no random catalogue and f_rand <= 0; the DDR^II term needs random primaries "
                   "(or use hipster_bk_ell_analytic)"};
-    const double want = std::llround(f_rand * double(dp->n));
+    const double want = std::llround(x.f_rand * double(x.dp->n));
     if (want < 1.0 || want > 2147483647.0) throw Error{HIPSTER_EINVAL, "bispectrum: f_rand * N must round into [1, 2^31)"};
-    n_gen = int64_t(want);
+    x.n_gen = int64_t(want);
   }
-  const bool have_r = given_r || gen_r;
-  HIPSTER_HIP(hipSetDevice(c.device));
-  Timer tm(c);
-  hipEvent_t t0 = tm.mark();
-  hipster_points genp{};
-  if (gen_r) {
-    double *gp = static_cast<double *>(ensure(c, c.rgen, size_t(n_gen) * 24));
-    random_points(c, seed, n_gen, q->box, gp);
-    genp.n = n_gen;
-    genp.dtype = HIPSTER_F64;
-    genp.on_device = 1;
-    genp.pos = gp;
-    genp.w = nullptr;
-    rp = &genp;
-  }
+  x.have_r = given_r || x.gen_r;
+  x.fp64 = q->precision == HIPSTER_FP64;
+  // the mixed form takes C from the C-term pair histogram (exact window,
+  // tabulated jbar^a jbar^b); the FP64 form sums C in the pair sweep
+  x.c_hist = !x.fp64;
+}
 
-  const int64_t n = dp->n, nr = have_r ? rp->n : 0;
-  const size_t esz = dp->dtype == HIPSTER_F32 ? 4 : 8;
-  const void *pos = device_view(c, c.pos_in, dp->pos, n * 3 * int64_t(esz), dp->on_device);
-  const void *w = device_view(c, c.w_in, dp->w, n * int64_t(esz), dp->on_device);
-  const uint8_t *mask = device_mask(c, c.mask_in, q->primary_mask, n);
-  const Grid g = make_grid(q->box, q->r0);
-  const Sorted sd = build_cells(c, c.cells_d, g, pos, w, mask, n, dp->dtype);
-  Sorted sr;
-  if (have_r) {
-    const size_t rsz = rp->dtype == HIPSTER_F32 ? 4 : 8;
-    const void *rpos = device_view(c, c.rpos_in, rp->pos, nr * 3 * int64_t(rsz), rp->on_device);
-    const void *rw = device_view(c, c.rw_in, rp->w, nr * int64_t(rsz), rp->on_device);
-    const uint8_t *rmask = device_mask(c, c.rmask_in, q->random_mask, nr);
-    sr = build_cells(c, c.cells_r, g, rpos, rw, rmask, nr, rp->dtype);
+// Randoms (drawn on the device when not given), cell lists, edges and 1/bin
+// volumes, zeroed pair counters.
+static void bk_prepare(Ctx &c, Timer &tm, BkBox &x, const BkBufs &b) {
+  const hipster_params *q = x.q;
+  x.ev_b0 = tm.mark();
+  if (x.gen_r) {
+    double *gp = static_cast<double *>(ensure(c, *b.rgen, size_t(x.n_gen) * 24));
+    random_points(c, x.seed, x.n_gen, q->box, gp);
+    x.genp = hipster_points{};
+    x.genp.n = x.n_gen;
+    x.genp.dtype = HIPSTER_F64;
+    x.genp.on_device = 1;
+    x.genp.pos = gp;
+    x.genp.w = nullptr;
+    x.rp = &x.genp;
   }
-  hipEvent_t t1 = tm.mark();
-
-  const int NK = q->n_k, NL = q->ell_max + 1;
-  const bool fp64 = q->precision == HIPSTER_FP64;
+  const int64_t n = x.dp->n;
+  const size_t esz = x.dp->dtype == HIPSTER_F32 ? 4 : 8;
+  x.pos = device_view(c, *b.pos, x.dp->pos, n * 3 * int64_t(esz), x.dp->on_device);
+  x.w = device_view(c, *b.w, x.dp->w, n * int64_t(esz), x.dp->on_device);
+  x.mask = device_mask(c, *b.mask, q->primary_mask, n);
+  x.g = make_grid(q->box, q->r0);
+  x.sd = build_cells(c, *b.cd, x.g, x.pos, x.w, x.mask, n, x.dp->dtype);
+  if (x.have_r) {
+    const int64_t nr = x.rp->n;
+    const size_t rsz = x.rp->dtype == HIPSTER_F32 ? 4 : 8;
+    const void *rpos = device_view(c, *b.rpos, x.rp->pos, nr * 3 * int64_t(rsz), x.rp->on_device);
+    const void *rw = device_view(c, *b.rw, x.rp->w, nr * int64_t(rsz), x.rp->on_device);
+    const uint8_t *rmask = device_mask(c, *b.rmask, q->random_mask, nr);
+    x.sr = build_cells(c, *b.cr, x.g, rpos, rw, rmask, nr, x.rp->dtype);
+  }
+  const int NK = q->n_k;
   std::vector<double> coef(static_cast<size_t>(NK));
   for (int a = 0; a < NK; ++a) {
     const double ka = q->k_edges[a], kb = q->k_edges[a + 1];
     coef[size_t(a)] = 3.0 / (kb * kb * kb - ka * ka * ka);
   }
-  double *edges = static_cast<double *>(ensure(c, c.edges, size_t(NK + 1) * 8));
-  double *coef_d = static_cast<double *>(ensure(c, c.bk_coef, size_t(NK) * 8));
-  HIPSTER_HIP(hipMemcpyAsync(edges, q->k_edges, size_t(NK + 1) * 8, hipMemcpyHostToDevice, c.stream));
-  HIPSTER_HIP(hipMemcpyAsync(coef_d, coef.data(), size_t(NK) * 8, hipMemcpyHostToDevice, c.stream));
-  unsigned long long *cnt = static_cast<unsigned long long *>(ensure(c, c.ordered_count, 24));
-  HIPSTER_HIP(hipMemsetAsync(cnt, 0, 24, c.stream));
-  // the mixed form takes C from the C-term pair histogram (exact window,
-  // tabulated jbar^a jbar^b); the FP64 form sums C in the pair sweep
-  const bool c_hist = !fp64;
+  x.edges = static_cast<double *>(ensure(c, *b.edges, size_t(NK + 1) * 8));
+  x.coef = static_cast<double *>(ensure(c, *b.coef, size_t(NK) * 8));
+  HIPSTER_HIP(hipMemcpyAsync(x.edges, q->k_edges, size_t(NK + 1) * 8, hipMemcpyHostToDevice, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(x.coef, coef.data(), size_t(NK) * 8, hipMemcpyHostToDevice, c.stream));
+  x.cnt = static_cast<unsigned long long *>(ensure(c, *b.cnt, 24));
+  HIPSTER_HIP(hipMemsetAsync(x.cnt, 0, 24, c.stream));
+  x.ev_b1 = tm.mark();
+}
 
-  double ms_sweep = 0.0;
-  const double ms_pairs = 0.0;  // enumeration is fused into the sweep
-  uint64_t launches = 0;
-  BkSums sums[2];
-  for (int set = 0; set < (have_r ? 2 : 1); ++set) {
-    const Sorted &prim = set == 0 ? sd : sr;
-    hipEvent_t b1 = tm.mark();
-    bk_sweep(c, prim, sd, g, q->r0, set == 0, edges, coef_d, NK, q->ell_max, fp64, !c_hist, cnt + set, sums[set]);
-    hipEvent_t b2 = tm.mark();
-    HIPSTER_HIP(hipEventSynchronize(b2));
-    ms_sweep += Timer::ms(b1, b2);
-    launches += sums[set].launches;
+// The sweep jobs of a box: data primaries, then random primaries if any.
+static int bk_jobs(const BkBox &x, std::vector<BkQueueJob> &out) {
+  const int sets = x.have_r ? 2 : 1;
+  for (int set = 0; set < sets; ++set) {
+    BkQueueJob j;
+    j.prim = set == 0 ? x.sd : x.sr;
+    j.sec = x.sd;
+    j.g = x.g;
+    j.r0 = x.q->r0;
+    j.self_set = set == 0;
+    j.edges = x.edges;
+    j.coef = x.coef;
+    j.NK = x.q->n_k;
+    j.npairs = x.cnt + set;
+    // expected pairs per primary, n (4 pi / 3) R0^3: the same for both sets of a box
+    const double V = x.q->box * x.q->box * x.q->box;
+    j.cost = double(x.dp->n) / V * (4.0 * kPi / 3.0) * x.q->r0 * x.q->r0 * x.q->r0;
+    out.push_back(j);
   }
-  // C of the data primaries (Ch[0]) and of the random primaries (Ch[1])
-  std::vector<double> Ch[2];
-  double ms_cterm = 0.0;
-  if (c_hist) {
+  return sets;
+}
+
+// The sweeps of a single box.
+static void bk_sweeps(Ctx &c, Timer &tm, BkBox &x) {
+  for (int set = 0; set < (x.have_r ? 2 : 1); ++set) {
+    const Sorted &prim = set == 0 ? x.sd : x.sr;
+    hipEvent_t b1 = tm.mark();
+    bk_sweep(c, prim, x.sd, x.g, x.q->r0, set == 0, x.edges, x.coef, x.q->n_k, x.q->ell_max, x.fp64, !x.c_hist,
+             x.cnt + set, x.sums[set]);
+    hipEvent_t b2 = tm.mark();
+    if (b2) HIPSTER_HIP(hipEventSynchronize(b2));
+    x.ms_sweep += Timer::ms(b1, b2);
+    x.launches += x.sums[set].launches;
+  }
+}
+
+// After the sweeps: C of the data primaries (Ch[0]) and of the random
+// primaries (Ch[1]) from the pair histogram (mixed form), the analytic DDR^II
+// stage (the kernel table, then every data pair inside 2 R0 on a grid of cells
+// >= 2 R0, the data re-sorted into the randoms' scratch), the pair counts.
+static void bk_finish_device(Ctx &c, Timer &tm, BkBox &x, const BkBufs &b) {
+  const hipster_params *q = x.q;
+  const int NK = q->n_k, NL = q->ell_max + 1;
+  if (x.c_hist) {
     hipEvent_t c0 = tm.mark();
     const int rows = NL * NK * NK;
     double *Cd = static_cast<double *>(ensure(c, c.ct_C, size_t(2 * rows) * 8));
     unsigned long long n_ord[2] = {0, 0};
-    HIPSTER_HIP(hipMemcpyAsync(n_ord, cnt, 16, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipMemcpyAsync(n_ord, x.cnt, 16, hipMemcpyDeviceToHost, c.stream));
     HIPSTER_HIP(hipStreamSynchronize(c.stream));
     const int n_c = cterm_default_nodes(q->r0, q->k_edges[NK]);
-    for (int set = 0; set < (have_r ? 2 : 1); ++set) {
-      cterm_sweep(c, set == 0 ? sd : sr, sd, set == 1, g, q->r0, NK, q->k_edges, q->ell_max, n_c, n_ord[set],
-                  Cd + size_t(set) * rows, cnt + 2);
-      Ch[set].resize(size_t(rows));
-      HIPSTER_HIP(hipMemcpyAsync(Ch[set].data(), Cd + size_t(set) * rows, size_t(rows) * 8, hipMemcpyDeviceToHost,
-                                 c.stream));
+    for (int set = 0; set < (x.have_r ? 2 : 1); ++set) {
+      cterm_sweep(c, set == 0 ? x.sd : x.sr, x.sd, set == 1, x.g, q->r0, NK, q->k_edges, q->ell_max, n_c,
+                  n_ord[set], Cd + size_t(set) * rows, x.cnt + 2);
+      x.Ch[set].resize(size_t(rows));
+      HIPSTER_HIP(hipMemcpyAsync(x.Ch[set].data(), Cd + size_t(set) * rows, size_t(rows) * 8,
+                                 hipMemcpyDeviceToHost, c.stream));
     }
     hipEvent_t c1 = tm.mark();
-    HIPSTER_HIP(hipEventSynchronize(c1));
-    ms_cterm = Timer::ms(c0, c1);
+    if (c1) HIPSTER_HIP(hipEventSynchronize(c1));
+    else HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    x.ms_cterm += Timer::ms(c0, c1);
   }
-  // analytic DDR^II: the kernel table, then every data pair inside 2 R0 on
-  // a grid of cells >= 2 R0 (the data re-sorted into the randoms' scratch)
-  std::vector<double> T;
-  double ms_table = 0.0, ms_ddr2 = 0.0;
-  if (analytic) {
-    const double *tab = eii_device_table(c, tm, q->r0, NK, q->k_edges, q->ell_max, analytic_nx, &ms_table);
+  if (x.analytic) {
+    const double *tab = eii_device_table(c, tm, q->r0, NK, q->k_edges, q->ell_max, x.analytic_nx, &x.ms_table);
     hipEvent_t d0 = tm.mark();
     const Grid g2 = make_grid(q->box, 2.0 * q->r0);
-    const Sorted s2 = build_cells(c, c.cells_r, g2, pos, w, mask, n, dp->dtype);
+    const Sorted s2 = build_cells(c, *b.cr, g2, x.pos, x.w, x.mask, x.dp->n, x.dp->dtype);
     const int rows = NL * NK * NK;
     double *Td = static_cast<double *>(ensure(c, c.ddr2_T, size_t(rows) * 8));
-    ddr2_sweep(c, s2, g2, q->r0, analytic_nx, tab, rows, Td, cnt + 1);
-    T.resize(size_t(rows));
-    HIPSTER_HIP(hipMemcpyAsync(T.data(), Td, size_t(rows) * 8, hipMemcpyDeviceToHost, c.stream));
+    ddr2_sweep(c, s2, g2, q->r0, x.analytic_nx, tab, rows, Td, x.cnt + 1);
+    x.T.resize(size_t(rows));
+    HIPSTER_HIP(hipMemcpyAsync(x.T.data(), Td, size_t(rows) * 8, hipMemcpyDeviceToHost, c.stream));
     hipEvent_t d1 = tm.mark();
-    HIPSTER_HIP(hipEventSynchronize(d1));
-    ms_ddr2 = Timer::ms(d0, d1);
+    if (d1) HIPSTER_HIP(hipEventSynchronize(d1));
+    x.ms_ddr2 += Timer::ms(d0, d1);
   }
-  unsigned long long hcnt[2] = {0, 0};
-  HIPSTER_HIP(hipMemcpyAsync(hcnt, cnt, 16, hipMemcpyDeviceToHost, c.stream));
-  hipEvent_t t3 = tm.mark();
+  HIPSTER_HIP(hipMemcpyAsync(x.hcnt, x.cnt, 16, hipMemcpyDeviceToHost, c.stream));
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
+}
 
-  // assembly (Sec. 4 summary estimator), host FP64
-  const double p1 = weight_sum(dp), pr = have_r ? (gen_r ? double(n_gen) : weight_sum(rp)) : 0.0;
+// Assembly (Sec. 4 summary estimator), host FP64.
+static void bk_assemble(Ctx &c, BkBox &x) {
+  x.ms_build = Timer::ms(x.ev_b0, x.ev_b1);
+  const hipster_params *q = x.q;
+  hipster_diag *diag = x.diag;
+  double *bk = x.bk;
+  const int NK = q->n_k, NL = q->ell_max + 1;
+  const bool analytic = x.analytic, have_r = x.have_r, c_hist = x.c_hist;
+  const BkSums *sums = x.sums;
+  const std::vector<double> *Ch = x.Ch;
+  const std::vector<double> &T = x.T;
+  const double p1 = weight_sum(x.dp), pr = have_r ? (x.gen_r ? double(x.n_gen) : weight_sum(x.rp)) : 0.0;
   const double V = q->box * q->box * q->box, nw = p1 / V, sR = have_r ? p1 / pr : 0.0;
   std::vector<double> wt(static_cast<size_t>(NK));
   wtilde_bins(c, q->r0, NK, q->k_edges, wt.data());
@@ -862,25 +933,50 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, d
     if (diag->s0)
       for (int b = 0; b < NK; ++b) diag->s0[b] = S0[size_t(b)];
     if (diag->wtilde) memcpy(diag->wtilde, wt.data(), size_t(NK) * 8);
-    diag->n_pairs = hcnt[0];
+    diag->n_pairs = x.hcnt[0];
     diag->n_pairs_rr = 0;
-    diag->n_pairs_rand = analytic ? 0 : hcnt[1];
-    diag->n_rand = have_r ? uint64_t(rp->n) : 0;
-    diag->ms_build = Timer::ms(t0, t1);
-    diag->ms_pairs = ms_pairs;
-    diag->ms_sweep = ms_sweep;
-    diag->ms_total = Timer::ms(t0, t3);
-    diag->sweep_launches = launches;
+    diag->n_pairs_rand = analytic ? 0 : x.hcnt[1];
+    diag->n_rand = have_r ? uint64_t(x.rp->n) : 0;
+    diag->ms_build = x.ms_build;
+    diag->ms_pairs = 0.0;  // enumeration is fused into the sweep
+    diag->ms_sweep = x.ms_sweep;
+    diag->sweep_launches = x.launches;
     diag->ms_sweep_far = 0.0;
     diag->n_pairs_far = 0;
-    diag->ms_eii_table = ms_table;
-    diag->ms_ddr2 = ms_ddr2;
-    diag->n_pairs_2r0 = analytic ? hcnt[1] : 0;
-    diag->eii_nodes = analytic ? analytic_nx : 0;
-    diag->ms_cterm = ms_cterm;
+    diag->ms_eii_table = x.ms_table;
+    diag->ms_ddr2 = x.ms_ddr2;
+    diag->n_pairs_2r0 = analytic ? x.hcnt[1] : 0;
+    diag->eii_nodes = analytic ? x.analytic_nx : 0;
+    diag->ms_cterm = x.ms_cterm;
   }
 }
 
+
+static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, double f_rand, uint64_t seed,
+                   const hipster_params *q, double *bk, hipster_diag *diag, int analytic_nx = -1) {
+  BkBox x;
+  x.dp = dp;
+  x.rp = rp;
+  x.q = q;
+  x.bk = bk;
+  x.diag = diag;
+  x.f_rand = f_rand;
+  x.seed = seed;
+  x.analytic_nx = analytic_nx;
+  bk_check(c, x);
+  HIPSTER_HIP(hipSetDevice(c.device));
+  Timer tm(c);
+  hipEvent_t t0 = tm.mark();
+  const BkBufs b{&c.cells_d, &c.cells_r, &c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in,
+                 &c.rmask_in, &c.rgen, &c.edges, &c.bk_coef, &c.ordered_count};
+  bk_prepare(c, tm, x, b);
+  bk_sweeps(c, tm, x);
+  bk_finish_device(c, tm, x, b);
+  hipEvent_t t3 = tm.mark();
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  bk_assemble(c, x);
+  if (diag) diag->ms_total = Timer::ms(t0, t3);
+}
 // ------------------------------------------------------------ autotuner
 std::string tune_key(Ctx &c, const char *kernel, std::initializer_list<int> shape) {
   hipDeviceProp_t prop{};
@@ -1177,20 +1273,67 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
     }
     j.n_pairs = ordered[size_t(b)];
   }
-  // bispectra, box by box
-  for (int b = 0; b < nb; ++b) {
-    hipster_box_job &j = jobs[b];
-    if (j.bk_params.n_k <= 0) continue;
-    hipster_diag d{};
-    if (j.bk_eii_nodes >= 0)
-      run_bk(c, &j.data, nullptr, 0.0, 0, &j.bk_params, j.bk, &d, j.bk_eii_nodes);
-    else
-      run_bk(c, &j.data, j.randoms.n > 0 ? &j.randoms : nullptr, j.f_rand, j.seed, &j.bk_params, j.bk, &d);
-    ms_build += d.ms_build;
-    ms_pairs += d.ms_pairs;
-    ms_sweep += d.ms_sweep;
-    launches += d.sweep_launches;
-    if (j.pk_params.n_k <= 0) j.n_pairs = d.n_pairs;
+  // bispectra: every box prepared on scratch of its own, the sweeps of all
+  // boxes that share (ell_max, form) in one queued launch (boxes with more
+  // than 16 bins sweep alone), then each box's C-term or analytic stage and
+  // its assembly
+  std::vector<int> bb;
+  for (int b = 0; b < nb; ++b)
+    if (jobs[b].bk_params.n_k > 0) bb.push_back(b);
+  if (!bb.empty()) {
+    const size_t nbk = bb.size();
+    if (c.bt_bk.size() < nbk) c.bt_bk.resize(nbk);
+    std::vector<BkBox> xs(nbk);
+    std::vector<hipster_diag> ds(nbk);
+    std::vector<BkBufs> bufs(nbk);
+    for (size_t i = 0; i < nbk; ++i) {
+      hipster_box_job &j = jobs[bb[i]];
+      BkBox &x = xs[i];
+      ds[i] = hipster_diag{};
+      x.dp = &j.data;
+      x.rp = j.bk_eii_nodes >= 0 ? nullptr : (j.randoms.n > 0 ? &j.randoms : nullptr);
+      x.q = &j.bk_params;
+      x.bk = j.bk;
+      x.diag = &ds[i];
+      x.f_rand = j.f_rand;
+      x.seed = j.seed;
+      x.analytic_nx = j.bk_eii_nodes >= 0 ? j.bk_eii_nodes : -1;
+      bk_check(c, x);
+      BkBoxScratch &sc = c.bt_bk[i];
+      bufs[i] = BkBufs{&sc.cd, &sc.cr, &sc.pos, &sc.w, &sc.mask, &sc.rpos, &sc.rw, &sc.rmask, &sc.rgen, &sc.edges,
+                       &sc.coef, &sc.cnt};
+    }
+    for (size_t i = 0; i < nbk; ++i) bk_prepare(c, tm, xs[i], bufs[i]);
+    std::map<std::pair<int, int>, std::vector<size_t>> classes;
+    for (size_t i = 0; i < nbk; ++i) {
+      if (xs[i].q->n_k <= 16) classes[{xs[i].q->ell_max, xs[i].fp64 ? 1 : 0}].push_back(i);
+      else bk_sweeps(c, tm, xs[i]);
+    }
+    for (const auto &cl : classes) {
+      std::vector<BkQueueJob> qj;
+      std::vector<std::pair<size_t, int>> owner;
+      for (size_t i : cl.second) {
+        const int n = bk_jobs(xs[i], qj);
+        for (int set = 0; set < n; ++set) owner.push_back({i, set});
+      }
+      std::vector<BkSums> res;
+      hipEvent_t a = tm.mark();
+      bk_sweep_queue(c, qj, cl.first.first, cl.first.second != 0, res);
+      hipEvent_t d = tm.mark();
+      if (d) HIPSTER_HIP(hipEventSynchronize(d));
+      ms_sweep += Timer::ms(a, d);
+      ++launches;
+      for (size_t k = 0; k < owner.size(); ++k) xs[owner[k].first].sums[owner[k].second] = std::move(res[k]);
+    }
+    for (size_t i = 0; i < nbk; ++i) {
+      bk_finish_device(c, tm, xs[i], bufs[i]);
+      bk_assemble(c, xs[i]);
+      ms_build += xs[i].ms_build;
+      ms_sweep += xs[i].ms_sweep;
+      launches += xs[i].launches;
+      hipster_box_job &j = jobs[bb[i]];
+      if (j.pk_params.n_k <= 0) j.n_pairs = ds[i].n_pairs;
+    }
   }
   hipEvent_t t9 = tm.mark();
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
@@ -1314,9 +1457,15 @@ void hipster_destroy(hipster_ctx *ctx) {
                    &c.ddr2_partial, &c.ddr2_hist, &c.ddr2_counter, &c.ddr2_T, &c.ct_tab, &c.ct_consts, &c.ct_C,
                    &c.ct_wmax, &c.ct_jbar, &c.ct_sel, &c.rgen, &c.pk_l1, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
                    &c.th_K, &c.th_out, &c.th_wt, &c.th_pb, &c.th_bk, &c.th_T, &c.th_X, &c.pt_tab, &c.pt_consts,
-                   &c.pt_T,
+                   &c.pt_T, &c.bq_jobs, &c.bq_tasks, &c.bq_slots, &c.bq_counter,
                    &c.tune_scratch};
   for (DevBuf *b : all) free_buf(*b);
+  for (BkBoxScratch &s : c.bt_bk) {
+    free_cells(s.cd);
+    free_cells(s.cr);
+    DevBuf *own[] = {&s.pos, &s.w, &s.mask, &s.rpos, &s.rw, &s.rmask, &s.rgen, &s.edges, &s.coef, &s.cnt};
+    for (DevBuf *b : own) free_buf(*b);
+  }
   for (EiiEntry &e : c.eii_cache) free_buf(e.buf);
   delete ctx;
 }

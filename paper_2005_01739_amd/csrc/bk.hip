@@ -144,23 +144,42 @@ struct BkQuad {
   int p[4];
 };
 
-// Arguments of one sweep launch.
-struct BkArgs {
+// One set of primaries against one box's secondaries.
+struct BkJob {
   Sorted prim, sec;
-  const BkQuad *quads;
-  int64_t q_lo, q_hi;  // quads of this launch
   int nc;
   double L, r02, inv_r0;
   int self_set;
   const double *edges;  // n_k + 1
   const double *coef;   // n_k: 3 / (k_{a+1}^3 - k_a^3)
-  int n_k, group;       // bins 16 group .. 16 group + 15 of this pass
+  int n_k;
+  unsigned long long *npairs;  // ordered pairs inside R0 (added to)
+};
+
+// A queued task: quads [q0, q1) of job `job`; its sums go to row `slot`.
+struct BkTask {
+  int64_t q0, q1;
+  int job, slot;
+};
+
+// Arguments of one sweep launch.  A single job: quads [q_lo, q_hi) of
+// `job`, waves assigned by a fixed rule, per-wave rows.  Queued (many boxes):
+// waves take tasks from `counter` until n_tasks are taken.
+struct BkArgs {
+  BkJob job;
+  const BkQuad *quads;
+  int64_t q_lo, q_hi;  // quads of this launch
+  int group;            // bins 16 group .. 16 group + 15 of this pass
   double *partial;      // per-wave rows
   int rowlen;
   double *abuf;         // more than 16 bins: A of slot 4 (q - q_lo) + row, [NL^2][ld]
   double *wbuf;         // and w_p of that slot
   int ld;               // 16 * groups
-  unsigned long long *npairs;
+  const BkJob *jobs;    // queued launch
+  const BkTask *tasks;
+  int n_tasks;
+  int *counter;         // next task (zero before the launch)
+  double *slots;        // one row per task
 };
 
 // Per-wave row layout.  Up to 16 bins: [G tiles NL*256 | C tiles NL*256 | S0 64];
@@ -202,9 +221,10 @@ __device__ __forceinline__ void fmac_all(double (&acc)[NA], const double (&yr)[N
 #define HIPSTER_BK_WAVES 2
 #endif
 
-template <int NL, bool FP64, bool WITH_C, bool GRAM>
+template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HIPSTER_BK_WAVES : 1))) void k_bk_quad(
     BkArgs A) {
+  static_assert(GRAM || !QUEUE, "the queued sweep keeps its Gram tiles in registers");
   constexpr int NLM = NL * NL;
   constexpr int NY = (NLM + 15) / 16;
   using YT = YStage<FP64>;
@@ -225,23 +245,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
 
   const int lane = threadIdx.x, row = lane >> 4, col = lane & 15;
   const int64_t e0 = int64_t(16) * A.group;
-  const int NK = A.n_k;
-  // this lane's edge e = 16 g + col (clamped) and bin e (if it exists)
-  const int e = int(e0) + col;
-  const bool has_bin = e < NK;
-  const double ke = A.edges[e <= NK ? e : NK];
-  const double ke3 = ke * ke * ke, ike = ke > 0.0 ? 1.0 / ke : 0.0;
-  const double kn = A.edges[e + 1 <= NK ? e + 1 : NK];
-  const double kn3 = kn * kn * kn;
-  const double cfb = has_bin ? A.coef[e] : 0.0;
-  // a full group of 16 bins takes its top edge 16 g + 16 from the staging
-  const bool top = e0 + 16 <= NK;
-  const bool top_lane = top && col == 15;
-  const double top_w = top_lane ? 1.0 : 0.0;
-  const double ktop = top ? A.edges[e0 + 16] : 0.0;
-  const double ktop3 = ktop * ktop * ktop, iktop = ktop > 0.0 ? 1.0 / ktop : 0.0;
-  const double r_neutral = 0.5 / A.inv_r0, ir_neutral = 2.0 * A.inv_r0;
-  const double L = A.L;
+  // the job's constants; a queued launch reloads them when its task's job changes
+  BkJob J = A.job;
+  double ke, ke3, ike, kn3, cfb, top_w, ktop, ktop3, iktop, r_neutral, ir_neutral, L, rfar, rfar2;
+  bool top;
+  auto set_job = [&]() {
+    const int NK = J.n_k;
+    // this lane's edge e = 16 g + col (clamped) and bin e (if it exists)
+    const int e = int(e0) + col;
+    ke = J.edges[e <= NK ? e : NK];
+    ke3 = ke * ke * ke;
+    ike = ke > 0.0 ? 1.0 / ke : 0.0;
+    const double kn = J.edges[e + 1 <= NK ? e + 1 : NK];
+    kn3 = kn * kn * kn;
+    cfb = e < NK ? J.coef[e] : 0.0;
+    // a full group of 16 bins takes its top edge 16 g + 16 from the staging
+    top = e0 + 16 <= NK;
+    top_w = top && col == 15 ? 1.0 : 0.0;
+    ktop = top ? J.edges[e0 + 16] : 0.0;
+    ktop3 = ktop * ktop * ktop;
+    iktop = ktop > 0.0 ? 1.0 / ktop : 0.0;
+    r_neutral = 0.5 / J.inv_r0;
+    ir_neutral = 2.0 * J.inv_r0;
+    L = J.L;
+    // pairs at r^2 >= rfar2 put every edge of the group on the large-argument
+    // side (no Taylor or sine-integral series); rfar2 = inf leaves all near
+    const double k_lo = J.edges[e0];
+    rfar = k_lo > 0.0 ? HIPSTER_U_BIG / k_lo : 0.0;
+    rfar2 = (FP64 || !(k_lo > 0.0)) ? __builtin_inf() : rfar * rfar * (1.0 + 1e-12);
+  };
+  set_job();
   // Without the C sums (mixed form) each lane sums its own edge's values,
   // E^e_lm = sum_pairs k_e^3 G_l(k_e r) w_q W y_lm, and the bin sums are taken
   // once per quad as differences of adjacent lanes' sums; the top edge of a
@@ -258,12 +291,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
     for (int t = 1; t < NL; ++t) l += k >= t * t ? 1 : 0;
     lk[i] = l;
   }
-  // pairs at r^2 >= rfar2 put every edge of the group on the large-argument
-  // side (no Taylor or sine-integral series); rfar2 = inf leaves all near
-  const double k_lo = A.edges[e0];
-  const double rfar = k_lo > 0.0 ? HIPSTER_U_BIG / k_lo : 0.0;
-  const double rfar2 = (FP64 || !(k_lo > 0.0)) ? __builtin_inf() : rfar * rfar * (1.0 + 1e-12);
-
   // C sums (FP64 form) and the Gram tiles stay in matrix-core accumulators
   // for the wave's whole life and reach its row once, at the end (a
   // per-quad update of the 16 x 16 tiles in memory cost 10 KiB of writes per
@@ -271,7 +298,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   d4_t accC[NL], accG[NL];
 #pragma unroll
   for (int l = 0; l < NL; ++l) accC[l] = accG[l] = d4_t{0.0, 0.0, 0.0, 0.0};
-  double *const wrow = A.partial + int64_t(blockIdx.x) * A.rowlen;
   double s0acc = 0.0;
   unsigned long long pcount = 0;
   int64_t cur_cell = -1;
@@ -281,21 +307,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   // the waves of XCD x (blockIdx % 8 == x) share one contiguous eighth of the
   // quads (a slab of cells), whose neighbour data then stays in that XCD's
   // L2.  Within the slab, runs of kQuadRun quads go round-robin to its waves.
-  const int xcd = int(blockIdx.x % kXcds), wx = int(blockIdx.x / kXcds), nwx = int(gridDim.x / kXcds);
-  const int64_t nq = A.q_hi - A.q_lo;
-  const int64_t s_lo = A.q_lo + nq * xcd / kXcds, s_hi = A.q_lo + nq * (xcd + 1) / kXcds;
-  for (int64_t c0 = s_lo + int64_t(wx) * kQuadRun; c0 < s_hi; c0 += int64_t(nwx) * kQuadRun) {
-    const int64_t c1 = c0 + kQuadRun < s_hi ? c0 + kQuadRun : s_hi;
-    for (int64_t qi = c0; qi < c1; ++qi) {
+  auto quad = [&](int64_t qi) {
+    {
       const BkQuad qd = A.quads[qi];
       int qp[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) qp[r] = __builtin_amdgcn_readfirstlane(qd.p[r]);
-      const int64_t cell = A.prim.scell[qp[0]];
+      const int64_t cell = J.prim.scell[qp[0]];
       if (cell != cur_cell) {
         // neighbour cells in (dx, dy, dz) order, merged into runs of the
         // sorted secondaries (cells adjacent along z are adjacent in memory)
-        const int nc = A.nc;
+        const int nc = J.nc;
         const int cz = int(cell % nc), cy = int((cell / nc) % nc), cx = int(cell / (int64_t(nc) * nc));
         if (lane < 27) {
           int sx = 0, sy = 0, sz = 0;
@@ -304,8 +326,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           if (ny >= nc) { ny -= nc; sy = 1; } else if (ny < 0) { ny += nc; sy = -1; }
           if (nz >= nc) { nz -= nc; sz = 1; } else if (nz < 0) { nz += nc; sz = -1; }
           const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
-          nb_beg[lane] = A.sec.cell_start[nb];
-          nb_end[lane] = A.sec.cell_start[nb + 1];
+          nb_beg[lane] = J.sec.cell_start[nb];
+          nb_end[lane] = J.sec.cell_start[nb + 1];
           nb_sh[lane] = (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1);
         }
         wave_sync();
@@ -338,14 +360,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       if (lane < 12) {
         const int r = lane / 3, d = lane % 3;
         const int pp = qp[r] >= 0 ? qp[r] : qp[0];
-        q_xyz[r][d] = d == 0 ? A.prim.x[pp] : (d == 1 ? A.prim.y[pp] : A.prim.z[pp]);
+        q_xyz[r][d] = d == 0 ? J.prim.x[pp] : (d == 1 ? J.prim.y[pp] : J.prim.z[pp]);
       }
       wave_sync();
       const int my_p = row == 0 ? qp[0] : row == 1 ? qp[1] : row == 2 ? qp[2] : qp[3];
       const bool my_valid = my_p >= 0;
       const int my_pp = my_valid ? my_p : qp[0];
-      const double px = A.prim.x[my_pp], py = A.prim.y[my_pp], pz = A.prim.z[my_pp];
-      const double wp = my_valid ? A.prim.w[my_pp] : 0.0;
+      const double px = J.prim.x[my_pp], py = J.prim.y[my_pp], pz = J.prim.z[my_pp];
+      const double wp = my_valid ? J.prim.w[my_pp] : 0.0;
 
       double acc[NLM], tacc[NY];
 #pragma unroll
@@ -379,13 +401,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
             const unsigned ent = hl[CL][row][idx];
             const int j = int(ent >> 5), sh = int(ent & 31u);
             const double ox = double(sh / 9 - 1) * L, oy = double((sh / 3) % 3 - 1) * L, oz = double(sh % 3 - 1) * L;
-            const double dx = (px - A.sec.x[j]) - ox;
-            const double dy = (py - A.sec.y[j]) - oy;
-            const double dz = (pz - A.sec.z[j]) - oz;
+            const double dx = (px - J.sec.x[j]) - ox;
+            const double dy = (py - J.sec.y[j]) - oy;
+            const double dz = (pz - J.sec.z[j]) - oz;
             const double r2 = bk_sq_norm(dx, dy, dz);
             r = sqrt(r2);
             ir = r > 0.0 ? 1.0 / r : 0.0;
-            f = A.sec.w[j] * window<double>(r * A.inv_r0);
+            f = J.sec.w[j] * window<double>(r * J.inv_r0);
             if (r > 0.0) {
               ux = dx * ir;
               uy = dy * ir;
@@ -515,9 +537,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
         ok = jj < end;
         j = int(jj);
         if (ok) {
-          x = A.sec.x[jj];
-          y = A.sec.y[jj];
-          z = A.sec.z[jj];
+          x = J.sec.x[jj];
+          y = J.sec.y[jj];
+          z = J.sec.z[jj];
         }
         pos += 64;
         if (pos >= end) {
@@ -534,7 +556,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
         int nsh = 13, nrun = 0;
         if (have_next) fetch(nx, ny, nz, nj, nok, nsh, nrun);
         const double ox = run_off[crun][0], oy = run_off[crun][1], oz = run_off[crun][2];
-        const bool self_run = A.self_set && csh == 13;
+        const bool self_run = J.self_set && csh == 13;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           bool hit = false, far = false;
@@ -543,7 +565,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
             const double dy = (q_xyz[r][1] - cy) - oy;
             const double dz = (q_xyz[r][2] - cz) - oz;
             const double r2 = bk_sq_norm(dx, dy, dz);
-            hit = r2 < A.r02 && !(self_run && cj == qp[r]);
+            hit = r2 < J.r02 && !(self_run && cj == qp[r]);
             far = r2 >= rfar2;
           }
           const unsigned long long balf = __ballot(hit && far), baln = __ballot(hit && !far);
@@ -622,24 +644,73 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       }
       s0acc = fma(wp, acc[0], s0acc);
     }
-  }
-  double *out = wrow;
-  if constexpr (GRAM) {
-#pragma unroll
-    for (int l = 0; l < NL; ++l)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) out[l * 256 + (row + 4 * v) * 16 + col] += accG[l][v];
-    if constexpr (WITH_C) {
+  };
+
+  if constexpr (!QUEUE) {
+    const int xcd = int(blockIdx.x % kXcds), wx = int(blockIdx.x / kXcds), nwx = int(gridDim.x / kXcds);
+    const int64_t nq = A.q_hi - A.q_lo;
+    const int64_t s_lo = A.q_lo + nq * xcd / kXcds, s_hi = A.q_lo + nq * (xcd + 1) / kXcds;
+    for (int64_t c0 = s_lo + int64_t(wx) * kQuadRun; c0 < s_hi; c0 += int64_t(nwx) * kQuadRun) {
+      const int64_t c1 = c0 + kQuadRun < s_hi ? c0 + kQuadRun : s_hi;
+      for (int64_t qi = c0; qi < c1; ++qi) quad(qi);
+    }
+    double *out = A.partial + int64_t(blockIdx.x) * A.rowlen;
+    if constexpr (GRAM) {
 #pragma unroll
       for (int l = 0; l < NL; ++l)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) out[NL * 256 + l * 256 + (row + 4 * v) * 16 + col] += accC[l][v];
+        for (int v = 0; v < 4; ++v) out[l * 256 + (row + 4 * v) * 16 + col] += accG[l][v];
+      if constexpr (WITH_C) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) out[NL * 256 + l * 256 + (row + 4 * v) * 16 + col] += accC[l][v];
+      }
+      out[2 * NL * 256 + lane] += s0acc;
+    } else {
+      out[64 * A.group + lane] += s0acc;
     }
-    out[2 * NL * 256 + lane] += s0acc;
+    if (lane == 0 && pcount && A.group == 0) atomicAdd(J.npairs, pcount);
   } else {
-    out[64 * A.group + lane] += s0acc;
+    // tasks in queue order until none is left; each task's sums go to its
+    // own row, so the per-job merge is in a fixed order whichever wave ran it
+    int cur_job = -1;
+    for (;;) {
+      int t = 0;
+      if (lane == 0) t = atomicAdd(A.counter, 1);
+      t = __builtin_amdgcn_readfirstlane(t);
+      if (t >= A.n_tasks) break;
+      const BkTask T = A.tasks[t];
+      const int job = __builtin_amdgcn_readfirstlane(T.job);
+      if (job != cur_job) {
+        J = A.jobs[job];
+        set_job();
+        cur_job = job;
+        cur_cell = -1;
+      }
+      const int64_t q0 = uniform_i64(T.q0), q1 = uniform_i64(T.q1);
+      for (int64_t qi = q0; qi < q1; ++qi) quad(qi);
+      double *out = A.slots + int64_t(__builtin_amdgcn_readfirstlane(T.slot)) * A.rowlen;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[l * 256 + (row + 4 * v) * 16 + col] = accG[l][v];
+        accG[l] = d4_t{0.0, 0.0, 0.0, 0.0};
+      }
+      if constexpr (WITH_C) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) out[NL * 256 + l * 256 + (row + 4 * v) * 16 + col] = accC[l][v];
+          accC[l] = d4_t{0.0, 0.0, 0.0, 0.0};
+        }
+      }
+      out[2 * NL * 256 + lane] = s0acc;
+      s0acc = 0.0;
+      if (lane == 0 && pcount) atomicAdd(J.npairs, pcount);
+      pcount = 0;
+    }
   }
-  if (lane == 0 && pcount && A.group == 0) atomicAdd(A.npairs, pcount);
 }
 
 // Gram of the A buffer: one wave per (tile, chunk of slots), tile = (l, ga,
@@ -717,18 +788,18 @@ __global__ __launch_bounds__(256) void k_quad_fill(const int64_t *__restrict__ c
 }
 
 // ------------------------------------------------------------------- host
-template <int NL, bool FP64, bool WITH_C, bool GRAM>
+template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE = false>
 static void launch_quad(Ctx &c, const BkArgs &a, int nwaves) {
   const size_t lds = bk_lds_bytes<NL, FP64>();
-  k_bk_quad<NL, FP64, WITH_C, GRAM><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(a);
+  k_bk_quad<NL, FP64, WITH_C, GRAM, QUEUE><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(a);
   HIPSTER_HIP(hipGetLastError());
 }
 
-template <int NL, bool FP64, bool WITH_C, bool GRAM>
+template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE = false>
 static int quad_waves(Ctx &c) {
   int per_cu = 0;
   const size_t lds = bk_lds_bytes<NL, FP64>();
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bk_quad<NL, FP64, WITH_C, GRAM>, 64, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bk_quad<NL, FP64, WITH_C, GRAM, QUEUE>, 64, lds) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -738,6 +809,23 @@ static int quad_waves(Ctx &c) {
     cus = prop.multiProcessorCount;
   int n = cus * per_cu;
   return std::max(kXcds, n / kXcds * kXcds);
+}
+
+static BkJob bk_job(const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
+                    const double *edges, const double *coef, int NK, unsigned long long *npairs) {
+  BkJob j{};
+  j.prim = prim;
+  j.sec = sec;
+  j.nc = g.nc;
+  j.L = g.L;
+  j.r02 = r0 * r0;
+  j.inv_r0 = 1.0 / r0;
+  j.self_set = self_set ? 1 : 0;
+  j.edges = edges;
+  j.coef = coef;
+  j.n_k = NK;
+  j.npairs = npairs;
+  return j;
 }
 
 template <int NL>
@@ -773,18 +861,8 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   HIPSTER_HIP(hipGetLastError());
 
   BkArgs a{};
-  a.prim = prim;
-  a.sec = sec;
+  a.job = bk_job(prim, sec, g, r0, self_set, edges, coef, NK, npairs);
   a.quads = quads;
-  a.nc = g.nc;
-  a.L = g.L;
-  a.r02 = r0 * r0;
-  a.inv_r0 = 1.0 / r0;
-  a.self_set = self_set ? 1 : 0;
-  a.edges = edges;
-  a.coef = coef;
-  a.n_k = NK;
-  a.npairs = npairs;
   a.rowlen = bk_rowlen(NL, groups);
   a.ld = 16 * groups;
 
@@ -880,6 +958,149 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
     out.S0[size_t(b)] = s;
   }
   out.launches = launches;
+}
+
+template <int NL>
+static void bk_sweep_queue_nl(Ctx &c, const std::vector<BkQueueJob> &jobs, bool fp64, std::vector<BkSums> &out) {
+  const int nj = int(jobs.size());
+  out.assign(size_t(nj), BkSums{});
+  for (int j = 0; j < nj; ++j) {
+    const BkQueueJob &J = jobs[size_t(j)];
+    if (J.NK < 1 || J.NK > 16) throw Error{HIPSTER_EUNSUPPORTED, "queued bispectrum: n_k must lie in [1, 16]"};
+    if (J.sec.n >= (int64_t(1) << 27))
+      throw Error{HIPSTER_EUNSUPPORTED, "bispectrum: at most 2^27 - 1 data points (27-bit hit indices)"};
+    out[size_t(j)].NL = NL;
+    out[size_t(j)].NK = J.NK;
+    out[size_t(j)].G.assign(size_t(NL) * J.NK * J.NK, 0.0);
+    out[size_t(j)].C.assign(size_t(NL) * J.NK * J.NK, 0.0);
+    out[size_t(j)].S0.assign(size_t(J.NK), 0.0);
+  }
+  if (nj == 0) return;
+  // quads of every job: per-job counts and offsets side by side, one readback
+  std::vector<int64_t> cbase(size_t(nj) + 1, 0);
+  for (int j = 0; j < nj; ++j) cbase[size_t(j) + 1] = cbase[size_t(j)] + jobs[size_t(j)].g.ncells() + 1;
+  int64_t *qcount = static_cast<int64_t *>(ensure(c, c.bq_count, size_t(cbase[size_t(nj)]) * 8));
+  int64_t *qoff = static_cast<int64_t *>(ensure(c, c.bq_off, size_t(cbase[size_t(nj)]) * 8));
+  std::vector<int64_t> nq(size_t(nj), 0);
+  for (int j = 0; j < nj; ++j) {
+    const BkQueueJob &J = jobs[size_t(j)];
+    const int64_t ncells = J.g.ncells();
+    if (J.prim.n == 0) continue;
+    const unsigned cb = unsigned((ncells + 255) / 256);
+    k_quad_count<<<dim3(cb), dim3(256), 0, c.stream>>>(J.prim.cell_start, J.prim.m, ncells, qcount + cbase[size_t(j)]);
+    HIPSTER_HIP(hipGetLastError());
+    scan_i64(c, qcount + cbase[size_t(j)], qoff + cbase[size_t(j)], ncells, c.bq_scan);
+    HIPSTER_HIP(hipMemcpyAsync(&nq[size_t(j)], qoff + cbase[size_t(j)] + ncells, 8, hipMemcpyDeviceToHost, c.stream));
+  }
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  std::vector<int64_t> qbase(size_t(nj) + 1, 0);
+  for (int j = 0; j < nj; ++j) qbase[size_t(j) + 1] = qbase[size_t(j)] + nq[size_t(j)];
+  const int64_t total = qbase[size_t(nj)];
+  if (total == 0) return;
+  BkQuad *quads = static_cast<BkQuad *>(ensure(c, c.bq_quads, size_t(total) * sizeof(BkQuad)));
+  for (int j = 0; j < nj; ++j) {
+    const BkQueueJob &J = jobs[size_t(j)];
+    if (nq[size_t(j)] == 0) continue;
+    const int64_t ncells = J.g.ncells();
+    const unsigned cb = unsigned((ncells + 255) / 256);
+    k_quad_fill<<<dim3(cb), dim3(256), 0, c.stream>>>(J.prim.cell_start, J.prim.m, ncells, qoff + cbase[size_t(j)],
+                                                      quads + qbase[size_t(j)]);
+    HIPSTER_HIP(hipGetLastError());
+  }
+  // tasks of about equal expected work (pairs), some eight per wave; jobs in
+  // order of expected pairs per quad (dearest first), each job's tasks
+  // consecutive.  A box's pairs per quad can differ from another's by 1e4.
+  const int nwaves = fp64 ? quad_waves<NL, true, true, true, true>(c) : quad_waves<NL, false, false, true, true>(c);
+  double work = 0.0;
+  for (int j = 0; j < nj; ++j) work += double(nq[size_t(j)]) * (4.0 * jobs[size_t(j)].cost + 1.0);
+  const double per_task = std::max(1.0, work / (8.0 * nwaves));
+  std::vector<int> order(static_cast<size_t>(nj));
+  for (int j = 0; j < nj; ++j) order[size_t(j)] = j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return jobs[size_t(a)].cost > jobs[size_t(b)].cost; });
+  std::vector<BkTask> tasks;
+  std::vector<int> tfirst(size_t(nj), 0), tcount(size_t(nj), 0);
+  for (int j : order) {
+    tfirst[size_t(j)] = int(tasks.size());
+    const int64_t tq = std::max<int64_t>(
+        1, std::min<int64_t>(4096, int64_t(per_task / (4.0 * jobs[size_t(j)].cost + 1.0))));
+    for (int64_t q0 = qbase[size_t(j)]; q0 < qbase[size_t(j) + 1]; q0 += tq) {
+      const int slot = int(tasks.size());
+      tasks.push_back(BkTask{q0, std::min(qbase[size_t(j) + 1], q0 + tq), j, slot});
+    }
+    tcount[size_t(j)] = int(tasks.size()) - tfirst[size_t(j)];
+  }
+  std::vector<BkJob> hj(static_cast<size_t>(nj));
+  for (int j = 0; j < nj; ++j) {
+    const BkQueueJob &J = jobs[size_t(j)];
+    hj[size_t(j)] = bk_job(J.prim, J.sec, J.g, J.r0, J.self_set, J.edges, J.coef, J.NK, J.npairs);
+  }
+  const int rowlen = bk_rowlen(NL, 1);
+  BkJob *djobs = static_cast<BkJob *>(ensure(c, c.bq_jobs, hj.size() * sizeof(BkJob)));
+  BkTask *dtasks = static_cast<BkTask *>(ensure(c, c.bq_tasks, tasks.size() * sizeof(BkTask)));
+  double *slots = static_cast<double *>(ensure(c, c.bq_slots, tasks.size() * size_t(rowlen) * 8));
+  int *counter = static_cast<int *>(ensure(c, c.bq_counter, 16));
+  HIPSTER_HIP(hipMemcpyAsync(djobs, hj.data(), hj.size() * sizeof(BkJob), hipMemcpyHostToDevice, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(dtasks, tasks.data(), tasks.size() * sizeof(BkTask), hipMemcpyHostToDevice, c.stream));
+  HIPSTER_HIP(hipMemsetAsync(counter, 0, 4, c.stream));
+  BkArgs a{};
+  a.job = hj[size_t(order[0])];
+  a.quads = quads;
+  a.group = 0;
+  a.rowlen = rowlen;
+  a.ld = 16;
+  a.jobs = djobs;
+  a.tasks = dtasks;
+  a.n_tasks = int(tasks.size());
+  a.counter = counter;
+  a.slots = slots;
+  if (fp64) launch_quad<NL, true, true, true, true>(c, a, nwaves);
+  else launch_quad<NL, false, false, true, true>(c, a, nwaves);
+  // per job: its task rows in task order
+  double *merged = static_cast<double *>(ensure(c, c.bk_gmerged, size_t(nj) * rowlen * 8));
+  for (int j = 0; j < nj; ++j) {
+    if (tcount[size_t(j)] == 0) {
+      HIPSTER_HIP(hipMemsetAsync(merged + size_t(j) * rowlen, 0, size_t(rowlen) * 8, c.stream));
+      continue;
+    }
+    merge_partials(c, slots + size_t(tfirst[size_t(j)]) * rowlen, tcount[size_t(j)], rowlen,
+                   merged + size_t(j) * rowlen);
+  }
+  std::vector<double> M(size_t(nj) * rowlen);
+  HIPSTER_HIP(hipMemcpyAsync(M.data(), merged, M.size() * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  for (int j = 0; j < nj; ++j) {
+    const int NK = jobs[size_t(j)].NK;
+    const double *Mj = M.data() + size_t(j) * rowlen;
+    BkSums &o = out[size_t(j)];
+    for (int l = 0; l < NL; ++l)
+      for (int x = 0; x < NK; ++x)
+        for (int y = 0; y < NK; ++y) {
+          const int t = l * 256 + std::min(x, y) * 16 + std::max(x, y);
+          const size_t oi = (size_t(l) * NK + x) * NK + y;
+          o.G[oi] = Mj[size_t(t)];
+          o.C[oi] = fp64 ? Mj[size_t(NL * 256 + t)] : 0.0;
+        }
+    for (int b = 0; b < NK; ++b) {
+      double s0 = 0.0;
+      for (int r = 0; r < 4; ++r) s0 += Mj[size_t(2 * NL * 256 + 16 * r + b)];
+      o.S0[size_t(b)] = s0;
+    }
+    o.launches = 1;
+  }
+}
+
+void bk_sweep_queue(Ctx &c, const std::vector<BkQueueJob> &jobs, int ell_max, bool fp64, std::vector<BkSums> &out) {
+  switch (ell_max) {
+    case 0: bk_sweep_queue_nl<1>(c, jobs, fp64, out); break;
+    case 1: bk_sweep_queue_nl<2>(c, jobs, fp64, out); break;
+    case 2: bk_sweep_queue_nl<3>(c, jobs, fp64, out); break;
+    case 3: bk_sweep_queue_nl<4>(c, jobs, fp64, out); break;
+    case 4: bk_sweep_queue_nl<5>(c, jobs, fp64, out); break;
+    case 5: bk_sweep_queue_nl<6>(c, jobs, fp64, out); break;
+    case 6: bk_sweep_queue_nl<7>(c, jobs, fp64, out); break;
+    default: throw Error{HIPSTER_EDOMAIN, "ell_max must lie in [0, 6]"};
+  }
 }
 
 void bk_sweep(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,

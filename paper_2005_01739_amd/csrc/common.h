@@ -110,6 +110,13 @@ struct CellScratch {
   DevBuf cell, count, start, cursor, idx, x, y, z, w, m, bad, scan_tmp, scell, sort_tmp;
 };
 
+// Device inputs of one box of a batched bispectrum (kept until the batch's
+// queued sweep has run).
+struct BkBoxScratch {
+  CellScratch cd, cr;
+  DevBuf pos, w, mask, rpos, rw, rmask, rgen, edges, coef, cnt;
+};
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -129,6 +136,8 @@ struct Ctx {
   DevBuf unit_tiles, unit_base, unit_cell, unit_tile;
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bq_count, bq_off, bq_scan, bq_quads, bk_abuf, bk_wbuf, bk_tiles, bk_gpart, bk_gmerged;
+  DevBuf bq_jobs, bq_tasks, bq_slots, bq_counter;  // queued bispectrum sweep
+  std::vector<BkBoxScratch> bt_bk;                  // batched bispectrum, per box
   DevBuf rgen, pk_l1;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
   DevBuf eii_consts, ddr2_partial, ddr2_hist, ddr2_counter, ddr2_T, ct_tab, ct_consts, ct_C, ct_wmax, ct_jbar, ct_sel;
@@ -221,6 +230,25 @@ void bk_sweep(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, doub
               const double *edges, const double *coef, int NK, int ell_max, bool fp64, bool with_c,
               unsigned long long *npairs, BkSums &out);
 void widen_i32(Ctx &c, const int *in, int64_t *out, int64_t n);
+
+// Many boxes' bispectrum sums in one queued sweep: each job is one primary
+// set against its box's data (as for bk_sweep), all with ell_max and the
+// form `fp64`, at most 16 bins each.  Quads of every job are cut into tasks
+// that the waves of one launch take in turn, the jobs with the most pairs
+// per quad first; each task's sums go to a row of their own and each job's
+// rows are merged in task order, so the result does not depend on which wave
+// ran which task.  out[j] receives job j's sums.
+struct BkQueueJob {
+  Sorted prim, sec;
+  Grid g;
+  double r0 = 0.0;
+  bool self_set = false;
+  const double *edges = nullptr, *coef = nullptr;  // device
+  int NK = 0;
+  unsigned long long *npairs = nullptr;  // device
+  double cost = 0.0;                     // expected pairs per primary (task order)
+};
+void bk_sweep_queue(Ctx &c, const std::vector<BkQueueJob> &jobs, int ell_max, bool fp64, std::vector<BkSums> &out);
 
 // n uniform points in [0, L)^3 (device, [n][3] doubles), point i from block
 // i + 1 of the Philox4x64-10 generator keyed by (seed, 0): x_d = L (word_d >> 11)

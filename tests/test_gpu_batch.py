@@ -140,7 +140,9 @@ def test_batch_deterministic():
 
 def test_batch_analytic_ddr2_matches_oracle():
     # the randoms-free bispectrum in a batch: each box's B against the oracle's
-    # analytic estimator (its own table), and bitwise against the single call
+    # analytic estimator (its own table), and against the single call to FP64
+    # rounding (the batch's queued sweep adds each box's quads in task order,
+    # the single call in per-wave rows)
     import paper_2005_01739_amd as hp
     specs = []
     rng = np.random.default_rng(5)
@@ -155,7 +157,7 @@ def test_batch_analytic_ddr2_matches_oracle():
     for spec, res in zip(specs, outs):
         single = hp.bk_ell_analytic(spec["pos"], box=spec["box"], r0=spec["r0"], k_edges=spec["bk_edges"],
                                     ell_max=2, n_x=64, precision="mixed")
-        assert np.array_equal(res["bk"], single)
+        assert np.allclose(res["bk"], single, rtol=1e-10, atol=1e-10 * np.abs(single).max())
         ref = oracle.bk_ell_analytic(spec["pos"], None, spec["box"], spec["r0"], spec["bk_edges"], 2, 64)
         scale = np.abs(ref["bk"]).max()
         assert np.allclose(res["bk"], ref["bk"], rtol=1e-6, atol=1e-7 * scale)
