@@ -353,6 +353,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--scale", type=float, default=0.1,
                     help="batch workload: fraction of each box's N (pairs scale as its square)")
+    ap.add_argument("--split", type=int, default=1,
+                    help="batch workload: run the 64 boxes as this many batch calls of about equal work")
+    ap.add_argument("--device-randoms", action="store_true",
+                    help="batch workload: randoms drawn by the library (f_rand, seed) instead of given")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -481,28 +485,64 @@ def main():
     else:
         boxes = synthetic.batch_boxes(64, args.scale)
         analytic = args.workload == "batch-analytic"
-        specs = []
+        specs, work = [], []
         for b in boxes:
             pos = torch.from_numpy(b.pos).cuda()
-            spec = dict(pos=pos, box=b.box, r0=b.r0, pk_edges=b.k_edges_p, pk_ell_max=b.ell_max_p,
-                        bk_edges=b.k_edges_b, bk_ell_max=b.ell_max_b)
+            pk = dict(pk_edges=b.k_edges_p, pk_ell_max=b.ell_max_p)
+            bk = dict(bk_edges=b.k_edges_b, bk_ell_max=b.ell_max_b)
             if analytic:
-                spec["bk_eii_nodes"] = 0  # DDR^II from the E^II kernel, default table, no randoms
+                bk["bk_eii_nodes"] = 0  # DDR^II from the E^II kernel, default table, no randoms
+            elif args.device_randoms:
+                bk["f_rand"], bk["seed"] = b.f_rand, b.seed  # drawn by the library on the device
             else:
-                spec["randoms"] = torch.from_numpy(b.randoms()).cuda()
-            specs.append(spec)
+                bk["randoms"] = torch.from_numpy(b.randoms()).cuda()
+            # expected ordered pairs inside R0 (Poisson part)
+            pairs = b.n * b.n / b.box ** 3 * 4.18879 * b.r0 ** 3
+            if args.split > 1:
+                # a box's P and B as two units of work (a P pair costs about a
+                # quarter of a B pair visit)
+                specs += [dict(pos=pos, box=b.box, r0=b.r0, **pk), dict(pos=pos, box=b.box, r0=b.r0, **bk)]
+                work += [0.125 * pairs, pairs * (1.0 if analytic else 1.0 + b.f_rand)]
+            else:
+                specs.append(dict(pos=pos, box=b.box, r0=b.r0, **pk, **bk))
+                work.append(pairs * (1.0 if analytic else 1.0 + b.f_rand))
         prec = "mixed"
         nkp, nkb = len(boxes[0].k_edges_p) - 1, len(boxes[0].k_edges_b) - 1
+        print(f"batch inputs on the device: {len(boxes)} boxes ({len(specs)} calls' worth of specs), "
+              f"{sum(b.n for b in boxes)} points",
+              file=sys.stderr, flush=True)
+        # --split K: the 64 boxes' P and B as K batch calls of about equal
+        # expected work (greedy, dearest first), each call's end printed as it
+        # happens
+        parts = [[] for _ in range(max(1, args.split))]
+        load = [0.0] * len(parts)
+        for i in sorted(range(len(specs)), key=lambda i: -work[i]):
+            k = min(range(len(parts)), key=lambda k: load[k])
+            parts[k].append(i)
+            load[k] += work[i]
+        parts = [sorted(p) for p in parts if p]
 
         def step():
-            outs, info = hp.batch(specs, precision=prec, return_diag=True)
-            info["n_pairs"] = sum(o["n_pairs"] for o in outs)
+            outs, info = [], {}
+            for k, part in enumerate(parts):
+                t = time.perf_counter()
+                o, inf = hp.batch([specs[i] for i in part], precision=prec, return_diag=True)
+                outs += o
+                for key, v in inf.items():
+                    info[key] = info.get(key, 0) + v if isinstance(v, (int, float)) else v
+                if len(parts) > 1:
+                    print(f"batch call {k + 1}/{len(parts)}: {len(part)} units, {time.perf_counter() - t:.1f} s",
+                          file=sys.stderr, flush=True)
+            info["n_pairs"] = sum(o["n_pairs"] for o, sp in zip(outs, [specs[i] for p in parts for i in p])
+                                  if "pk_edges" in sp)
             return outs, info
         units_per_pair = None
         cfg = {"workload": "batch_64_boxes" + ("_analytic_ddr2" if analytic else ""), "n_boxes": 64,
                "scale": args.scale, "n_points_total": int(sum(b.n for b in boxes)),
                "pk": {"n_k": nkp, "ells": [0, 2, 4]}, "bk": {"n_k": nkb, "ell_max": boxes[0].ell_max_b},
-               "randoms_per_point": 0 if analytic else 3, "precision": prec}
+               "randoms_per_point": 0 if analytic else 3,
+               "randoms": None if analytic else ("drawn on the device" if args.device_randoms else "given"),
+               "batch_calls": len(parts), "precision": prec}
 
     for _ in range(args.warmup):
         step()

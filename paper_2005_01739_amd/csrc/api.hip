@@ -1095,15 +1095,22 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
   double ms_pairs = 0.0, ms_sweep = 0.0, ms_build = 0.0;
   uint64_t launches = 0;
 
-  // boxes with a power spectrum, largest expected pair count first
-  std::vector<int> order;
-  for (int b = 0; b < nb; ++b)
-    if (jobs[b].pk_params.n_k > 0) order.push_back(b);
-  auto cost = [&](int b) {
+  // boxes with a power spectrum, largest expected pair count first; a box
+  // with more than kBatchOwnPairs expected pairs takes the single-box path
+  // (near and far kernels over its own stream) after the shared queue
+  constexpr double kBatchOwnPairs = double(int64_t(1) << 25);
+  std::vector<int> order, own;
+  auto pairs_expected = [&](int b) {
     const hipster_params &q = jobs[b].pk_params;
     const double n = double(jobs[b].data.n), V = q.box * q.box * q.box;
-    return n * n / V * q.r0 * q.r0 * q.r0 * double(q.n_k + 1);
+    return 0.5 * n * n / V * (4.0 * kPi / 3.0) * q.r0 * q.r0 * q.r0;
   };
+  for (int b = 0; b < nb; ++b) {
+    if (jobs[b].pk_params.n_k <= 0) continue;
+    if (pairs_expected(b) > kBatchOwnPairs) own.push_back(b);
+    else order.push_back(b);
+  }
+  auto cost = [&](int b) { return pairs_expected(b) * double(jobs[b].pk_params.n_k + 1); };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
 
   const int cols = ne_max * std::max(cols_edges, 1);
@@ -1272,6 +1279,16 @@ static void run_batch(Ctx &c, int nb, hipster_box_job *jobs, hipster_diag *diag)
       }
     }
     j.n_pairs = ordered[size_t(b)];
+  }
+  for (int b : own) {
+    hipster_box_job &j = jobs[b];
+    hipster_diag d{};
+    run_pk(c, &j.data, &j.pk_params, j.pk, &d);
+    ms_build += d.ms_build;
+    ms_pairs += d.ms_pairs;
+    ms_sweep += d.ms_sweep;
+    launches += d.sweep_launches;
+    j.n_pairs = d.n_pairs;
   }
   // bispectra: every box prepared on scratch of its own, the sweeps of all
   // boxes that share (ell_max, form) in one queued launch (boxes with more
