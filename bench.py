@@ -508,7 +508,7 @@ def main():
                 work.append(pairs * (1.0 if analytic else 1.0 + b.f_rand))
         prec = "mixed"
         nkp, nkb = len(boxes[0].k_edges_p) - 1, len(boxes[0].k_edges_b) - 1
-        print(f"batch inputs on the device: {len(boxes)} boxes ({len(specs)} calls' worth of specs), "
+        print(f"batch inputs on the device: {len(boxes)} boxes ({len(specs)} P/B specs), "
               f"{sum(b.n for b in boxes)} points",
               file=sys.stderr, flush=True)
         # --split K: the 64 boxes' P and B as K batch calls of about equal
@@ -568,7 +568,10 @@ def main():
         # DD pairs inside R0 carry n_k (l_max+1)^2 weights (the a_lm sums); each
         # (pair, image) inside 2 R0 carries one interpolated kernel value per
         # (l, a <= b) table
-        value = (pairs * units_per_pair + pairs_2r0 * n_tables) / (dt / args.steps)
+        # the rate in its own unit: DD pair-weights of the randoms-free
+        # estimator per second of the whole call (the 2 R0 stage's (pair, image)
+        # terms are reported beside it, per second of that stage)
+        value = pairs * units_per_pair / (dt / args.steps)
         avg_launch_ms = sweep_ms / max(launches, 1)
         flops = pairs * bk_flops_per_pair(n_k, wl.ell_max_b, with_c=prec == "fp64") / (launches / args.steps)
         achieved = flops / (avg_launch_ms * 1e-3) / 1e12
@@ -576,10 +579,11 @@ def main():
         # context in the timed steps; its cold build time is reported beside
         _, cold = hp.bk_ell_analytic(pos, w, box=wl.box, r0=wl.r0, k_edges=wl.k_edges_b, ell_max=wl.ell_max_b,
                                      precision=prec, ctx=hp.Context(0), return_diag=True)
-        out = {"metric": METRIC, "value": value, "unit": "pair-weights/s", "n_gpus": 1, "steps": args.steps,
-               "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-               "vs_baseline": None, "dtype": "f64+f32" if prec == "mixed" else "f64", "data": "synthetic",
-               "config": cfg,
+        out = {"metric": METRIC, "value": value, "unit": "DD pair-weights/s (analytic DDR^II)", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32" if prec == "mixed" else "f64",
+               "data": "synthetic", "config": cfg,
+               "ddr2_terms_per_s": pairs_2r0 * n_tables / (ddr2_ms / args.steps * 1e-3) if ddr2_ms > 0 else None,
                "roofline": {"bound": "alu", "kernel": "k_bk_quad", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                             "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
                             "frac_fp64": achieved / PEAK_FP64_TFLOPS, "traffic": None, "flops_per_launch": flops,
