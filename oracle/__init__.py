@@ -62,6 +62,12 @@ def lib():
         L.oracle_bk_ell.argtypes = [ct.c_int64, _dp, _dp, ct.c_int64, _dp, _dp, ct.c_double,
                                     ct.c_double, ct.c_int, _dp, ct.c_int, _u8p, _u8p, _dp, _dp,
                                     _dp, _dp, _dp, _dp, _dp, _u64p, _u64p, ct.c_int]
+        L.oracle_aniso_count.restype = ct.c_int
+        L.oracle_aniso_count.argtypes = [ct.c_int]
+        L.oracle_bk_aniso.restype = ct.c_int
+        L.oracle_bk_aniso.argtypes = [ct.c_int64, _dp, _dp, ct.c_int64, _dp, _dp, ct.c_double, ct.c_double, ct.c_int,
+                                      _dp, ct.c_int, _u8p, _u8p, _dp, _dp, _dp, _dp, _dp, _dp, _u64p, _u64p,
+                                      ct.c_int]
         L.oracle_eii.restype = ct.c_int
         L.oracle_eii.argtypes = [ct.c_double, ct.c_double, ct.c_int, ct.c_int, _dp, _dp]
         L.oracle_eii_table.restype = ct.c_int
@@ -240,6 +246,37 @@ def bk_ell(pos, w, rpos, rw, box, r0, k_edges, ell_max, mask_d=None, mask_r=None
     if rc != 0:
         raise ValueError("oracle_bk_ell: argument outside the oracle's range")
     out.update(s0=s0, wtilde=wt, n_pairs_dd=int(ndd.value), n_pairs_rd=int(nrd.value))
+    return out
+
+
+def aniso_combos(ell_max):
+    """(l1, l2, m) of the anisotropic bispectrum, l1 <= l2 <= ell_max, m = 0..l1."""
+    return [(l1, l2, m) for l1 in range(ell_max + 1) for l2 in range(l1, ell_max + 1) for m in range(l1 + 1)]
+
+
+def bk_aniso(pos, w, rpos, rw, box, r0, k_edges, ell_max, mask_d=None, mask_r=None, nthreads=0):
+    """Brute-force anisotropic B^{ab}_{l1 l2 m} (the reading of Sec. 10 in
+    oracle.c).  Returns a dict with combos, bk, gd, cd, gr, cr ([n_c, n_k,
+    n_k]), t [ell_max+1, n_k], n_pairs_dd, n_pairs_rd."""
+    pos = _f64(pos).reshape(-1, 3)
+    w = _f64(w)
+    rpos = np.zeros((0, 3)) if rpos is None else _f64(rpos).reshape(-1, 3)
+    rw = _f64(rw)
+    k = _f64(k_edges)
+    n_k = k.size - 1
+    nc = lib().oracle_aniso_count(int(ell_max))
+    out = {name: np.zeros((nc, n_k, n_k)) for name in ("bk", "gd", "cd", "gr", "cr")}
+    t = np.zeros((ell_max + 1, n_k))
+    ndd, nrd = ct.c_uint64(0), ct.c_uint64(0)
+    md = None if mask_d is None else np.ascontiguousarray(mask_d, dtype=np.uint8)
+    mr = None if mask_r is None else np.ascontiguousarray(mask_r, dtype=np.uint8)
+    st = lib().oracle_bk_aniso(pos.shape[0], _ptr(pos), _ptr(w), rpos.shape[0], _ptr(rpos), _ptr(rw), float(box),
+                               float(r0), n_k, _ptr(k), int(ell_max), _ptr(md, _u8p), _ptr(mr, _u8p),
+                               _ptr(out["bk"]), _ptr(out["gd"]), _ptr(out["cd"]), _ptr(out["gr"]), _ptr(out["cr"]),
+                               _ptr(t), ct.byref(ndd), ct.byref(nrd), int(nthreads))
+    if st != 0:
+        raise ValueError("oracle_bk_aniso: bad arguments")
+    out.update(combos=aniso_combos(ell_max), t=t, n_pairs_dd=int(ndd.value), n_pairs_rd=int(nrd.value))
     return out
 
 

@@ -46,7 +46,11 @@
  * result under (l, a) <-> (l', b) pins it (parity unpinned for that term).
  * The non-Gaussian term (oracle_cov_nongauss) is pinned by its reduction to
  * the (pinned) Gaussian term for a trispectrum diagonal on the quadrature
- * grid, and by its symmetry.
+ * grid, and by its symmetry.  The anisotropic bispectrum (oracle_bk_aniso, a
+ * reading of Sec. 10) is pinned by literal triple sums over distinct triples
+ * with scipy's harmonics (data and random primaries), by the literal pair sum
+ * of its DDR^I term, and by the identity that its m-sum at l1 = l2 is the
+ * (pinned) isotropic estimator.
  */
 #include <complex.h>
 #include <math.h>
@@ -723,6 +727,198 @@ int oracle_bk_ell(int64_t n, const double *pos, const double *w, int64_t n_r,
     if (n_pairs_dd) *n_pairs_dd = cdd;
     if (n_pairs_rd) *n_pairs_rd = crd;
     free(GD); free(CD); free(GR); free(CR); free(S0); free(Wt);
+    return 0;
+}
+
+/* ------------------------------------------- anisotropic bispectrum */
+/* The anisotropic bispectrum (Sec. 10 names it: the sum over spherical
+ * harmonics of the Sec. 4 estimators replaced by a product of harmonics of
+ * different order about the fixed line of sight z).  The reading: the kernel
+ * (-1)^l (2l+1) j_l j_l L_l(xhat_ij . xhat_ik) of Sec. 4 becomes
+ *   s_{l1 l2} 4 pi jbar^a_{l1}(r_ij) W jbar^b_{l2}(r_ik) W
+ *     sum_{mu in M(m)} Y_{l1 mu}(xhat_ij) Y*_{l2 mu}(xhat_ik),
+ * M(m) = {0} for m = 0 and {m, -m} for m > 0, s_{l1 l2} = (-1)^{(l1+l2)/2}
+ * for even l1 + l2 and (-1)^{(l1+l2-1)/2} for odd (the real factor of
+ * (-i)^{l1+l2}; an odd l1 + l2 multipole is that factor times -i).  The
+ * random integrals of Sec. 4 follow for a fixed line of sight: RRR survives
+ * at l1 = l2 = m = 0 only; DDR^I at m = 0 with l2 = 0 (or l1 = 0), where it
+ * is W~^b times the pair sum T^a_{l1} = sum_{i != j} w_i w_j jbar^a_{l1} W
+ * Y_{l1 0}(xhat_ij) times sqrt(4 pi); DDR^II from random primaries.  Then
+ *   B^{ab}_{l1 l2 m} = s 4 pi / (V n_w^3) [(G_D - C_D) - s_R (G_R - C_R)]
+ *     - s sqrt(4 pi) / (V n_w^2) delta_m0 [delta_{l2 0} W~^b T^a_{l1}
+ *       + delta_{l1 0} W~^a T^b_{l2}] + 2 delta_{l1 0} delta_{l2 0} delta_m0 W~^a W~^b,
+ * G^{ab} = sum_p w_p sum_{mu in M(m)} A^a_{l1 mu} A^{b*}_{l2 mu} and
+ * C^{ab} = sum_p w_p sum_{j != p} w_j^2 jbar^a_{l1} jbar^b_{l2} W^2
+ *   sum_{mu in M(m)} Y_{l1 mu}(xhat_pj) Y*_{l2 mu}(xhat_pj) (its j = k part).
+ * Summed over m at l1 = l2 = l it is the isotropic B^{ab}_l.
+ * Combinations c: l1 <= l2 <= ell_max, m = 0 .. l1, in that (l1, l2, m)
+ * order; outputs [n_c][n_k][n_k], t [ell_max+1][n_k].  Any of gd..t may be
+ * NULL. */
+int oracle_aniso_count(int ell_max)
+{
+    int c = 0;
+    for (int l1 = 0; l1 <= ell_max; ++l1)
+        for (int l2 = l1; l2 <= ell_max; ++l2) c += l1 + 1;
+    return c;
+}
+
+static uint64_t bk_aniso_sums(int64_t np, const double *ppos, const double *pw, const uint8_t *mask,
+                              int self_exclude, int64_t n, const double *pos, const double *w, double box,
+                              double r0, int n_k, const double *k, int lmax, double *G, double *Cs, double *T,
+                              int nt)
+{
+    const int nlm = (lmax + 1) * (lmax + 1), nc = oracle_aniso_count(lmax);
+    const size_t ng = (size_t)nc * n_k * n_k, nT = (size_t)(lmax + 1) * n_k;
+    int cl1[128], cl2[128], cm[128];
+    {
+        int c = 0;
+        for (int l1 = 0; l1 <= lmax; ++l1)
+            for (int l2 = l1; l2 <= lmax; ++l2)
+                for (int m = 0; m <= l1; ++m) { cl1[c] = l1; cl2[c] = l2; cm[c] = m; ++c; }
+    }
+    double *acc = calloc((size_t)nt * (2 * ng + nT), sizeof(double));
+    uint64_t *cnt = calloc((size_t)nt, sizeof(uint64_t));
+    const double r02 = r0 * r0;
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+        double *tG = acc + (size_t)tid * (2 * ng + nT), *tC = tG + ng, *tT = tC + ng;
+        double complex *Alm = malloc(sizeof(double complex) * (size_t)n_k * nlm);
+        double *Cp = malloc(sizeof(double) * ng);
+        double *g = malloc(sizeof(double) * (size_t)(lmax + 1) * n_k);
+        double yre[(ORACLE_ELL_MAX + 1) * (ORACLE_ELL_MAX + 1)], yim[(ORACLE_ELL_MAX + 1) * (ORACLE_ELL_MAX + 1)];
+        uint64_t cn = 0;
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < np; ++p) {
+            if (mask && !mask[p]) continue;
+            const double wp = pw ? pw[p] : 1.0;
+            memset(Alm, 0, sizeof(double complex) * (size_t)n_k * nlm);
+            memset(Cp, 0, sizeof(double) * ng);
+            for (int64_t j = 0; j < n; ++j) {
+                if (self_exclude && j == p) continue;
+                double d[3];
+                for (int ax = 0; ax < 3; ++ax) d[ax] = min_image(ppos[3 * p + ax] - pos[3 * j + ax], box);
+                double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                if (!(r2 < r02)) continue;
+                ++cn;
+                double r = sqrt(r2);
+                double wj = w ? w[j] : 1.0;
+                double W = oracle_window(r / r0);
+                for (int l = 0; l <= lmax; ++l) {
+                    jbar_all_bins(l, r, n_k, k, g + (size_t)l * n_k);
+                    for (int a = 0; a < n_k; ++a) g[(size_t)l * n_k + a] *= W;
+                }
+                oracle_ylm(lmax, d[0], d[1], d[2], yre, yim);
+                for (int l = 0; l <= lmax; ++l)
+                    for (int m = -l; m <= l; ++m) {
+                        double complex y = yre[l * l + l + m] + I * yim[l * l + l + m];
+                        for (int a = 0; a < n_k; ++a) Alm[(size_t)a * nlm + l * l + l + m] += wj * g[(size_t)l * n_k + a] * y;
+                    }
+                /* j = k part: the product of the pair's own harmonics */
+                for (int c = 0; c < nc; ++c) {
+                    const int l1 = cl1[c], l2 = cl2[c], m = cm[c];
+                    double q = 0.0;
+                    for (int sgn = (m == 0 ? 1 : -1); sgn <= 1; sgn += 2) {
+                        const int mu = sgn * m;
+                        double complex y1 = yre[l1 * l1 + l1 + mu] + I * yim[l1 * l1 + l1 + mu];
+                        double complex y2 = yre[l2 * l2 + l2 + mu] + I * yim[l2 * l2 + l2 + mu];
+                        q += creal(y1 * conj(y2));
+                    }
+                    for (int a = 0; a < n_k; ++a)
+                        for (int b = 0; b < n_k; ++b)
+                            Cp[((size_t)c * n_k + a) * n_k + b] += wj * wj * g[(size_t)l1 * n_k + a] * g[(size_t)l2 * n_k + b] * q;
+                }
+            }
+            for (int c = 0; c < nc; ++c) {
+                const int l1 = cl1[c], l2 = cl2[c], m = cm[c];
+                for (int a = 0; a < n_k; ++a)
+                    for (int b = 0; b < n_k; ++b) {
+                        double s = 0.0;
+                        for (int sgn = (m == 0 ? 1 : -1); sgn <= 1; sgn += 2) {
+                            const int mu = sgn * m;
+                            s += creal(Alm[(size_t)a * nlm + l1 * l1 + l1 + mu] * conj(Alm[(size_t)b * nlm + l2 * l2 + l2 + mu]));
+                        }
+                        size_t q = ((size_t)c * n_k + a) * n_k + b;
+                        tG[q] += wp * s;
+                        tC[q] += wp * Cp[q];
+                    }
+            }
+            for (int l = 0; l <= lmax; ++l)
+                for (int a = 0; a < n_k; ++a) tT[(size_t)l * n_k + a] += wp * creal(Alm[(size_t)a * nlm + l * l + l]);
+        }
+        cnt[tid] = cn;
+        free(Alm);
+        free(Cp);
+        free(g);
+    }
+    uint64_t ctot = 0;
+    for (size_t q = 0; q < ng; ++q) { G[q] = 0.0; Cs[q] = 0.0; }
+    if (T) for (size_t q = 0; q < nT; ++q) T[q] = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        const double *b = acc + (size_t)t * (2 * ng + nT);
+        for (size_t q = 0; q < ng; ++q) { G[q] += b[q]; Cs[q] += b[ng + q]; }
+        if (T) for (size_t q = 0; q < nT; ++q) T[q] += b[2 * ng + q];
+        ctot += cnt[t];
+    }
+    free(acc);
+    free(cnt);
+    return ctot;
+}
+
+int oracle_bk_aniso(int64_t n, const double *pos, const double *w, int64_t n_r, const double *rpos,
+                    const double *rw, double box, double r0, int n_k, const double *k, int ell_max,
+                    const uint8_t *mask_d, const uint8_t *mask_r, double *bk, double *gd, double *cd,
+                    double *gr, double *cr, double *t, uint64_t *n_pairs_dd, uint64_t *n_pairs_rd, int nthreads)
+{
+    if (n < 1 || n_r < 0 || n_k < 1 || n_k > ORACLE_NK_MAX || ell_max < 0 || ell_max > ORACLE_ELL_MAX ||
+        !(r0 > 0.0) || r0 > 0.5 * box)
+        return -1;
+    const int nt = nthreads_or_default(nthreads), nc = oracle_aniso_count(ell_max);
+    const size_t ng = (size_t)nc * n_k * n_k, nT = (size_t)(ell_max + 1) * n_k;
+    double *GD = calloc(ng, sizeof(double)), *CD = calloc(ng, sizeof(double));
+    double *GR = calloc(ng, sizeof(double)), *CR = calloc(ng, sizeof(double));
+    double *TD = calloc(nT, sizeof(double)), *Wt = calloc((size_t)n_k, sizeof(double));
+    uint64_t cdd = bk_aniso_sums(n, pos, w, mask_d, 1, n, pos, w, box, r0, n_k, k, ell_max, GD, CD, TD, nt);
+    uint64_t crd = 0;
+    if (n_r > 0) crd = bk_aniso_sums(n_r, rpos, rw, mask_r, 0, n, pos, w, box, r0, n_k, k, ell_max, GR, CR, NULL, nt);
+    double p1 = 0.0, pr = 0.0;
+    for (int64_t i = 0; i < n; ++i) p1 += w ? w[i] : 1.0;
+    for (int64_t i = 0; i < n_r; ++i) pr += rw ? rw[i] : 1.0;
+    const double V = box * box * box, nw = p1 / V, sR = n_r > 0 ? p1 / pr : 0.0;
+    const double sq4pi = sqrt(4.0 * PI);
+    for (int a = 0; a < n_k; ++a) Wt[a] = oracle_wtilde(r0, k[a], k[a + 1], 4.0);
+    int c = 0;
+    for (int l1 = 0; l1 <= ell_max; ++l1)
+        for (int l2 = l1; l2 <= ell_max; ++l2)
+            for (int m = 0; m <= l1; ++m, ++c) {
+                const int L = l1 + l2;
+                const double sgn = (((L & 1) ? (L - 1) / 2 : L / 2) & 1) ? -1.0 : 1.0;
+                for (int a = 0; a < n_k; ++a)
+                    for (int b = 0; b < n_k; ++b) {
+                        size_t q = ((size_t)c * n_k + a) * n_k + b;
+                        double v = sgn * 4.0 * PI / (V * nw * nw * nw) * ((GD[q] - CD[q]) - sR * (GR[q] - CR[q]));
+                        if (m == 0) {
+                            double d1 = 0.0;
+                            if (l2 == 0) d1 += Wt[b] * TD[(size_t)l1 * n_k + a];
+                            if (l1 == 0) d1 += Wt[a] * TD[(size_t)l2 * n_k + b];
+                            v -= sgn * sq4pi / (V * nw * nw) * d1;
+                            if (l1 == 0 && l2 == 0) v += 2.0 * Wt[a] * Wt[b];
+                        }
+                        bk[q] = v;
+                    }
+            }
+    if (gd) memcpy(gd, GD, ng * sizeof(double));
+    if (cd) memcpy(cd, CD, ng * sizeof(double));
+    if (gr) memcpy(gr, GR, ng * sizeof(double));
+    if (cr) memcpy(cr, CR, ng * sizeof(double));
+    if (t) memcpy(t, TD, nT * sizeof(double));
+    if (n_pairs_dd) *n_pairs_dd = cdd;
+    if (n_pairs_rd) *n_pairs_rd = crd;
+    free(GD); free(CD); free(GR); free(CR); free(TD); free(Wt);
     return 0;
 }
 
