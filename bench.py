@@ -341,7 +341,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "pk", "pk-fp64", "pk-table", "bk", "bk-fp64", "pk5", "bk5", "batch", "survey", "survey-fp64", "survey-table",
-                             "bk-analytic", "bk-analytic-fp64", "bk5-analytic", "cov", "batch-analytic"])
+                             "bk-analytic", "bk-analytic-fp64", "bk5-analytic", "cov", "batch-analytic", "bk-aniso"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-table-form", action="store_true",
                     help="pk workload: leave out the table-form measurement (for profiling the mixed path alone)")
@@ -425,6 +425,26 @@ def main():
         units_per_pair = n_k * (wl.ell_max_b + 1) ** 2
         cfg = {"workload": wl.name, "n_points": wl.n, "n_randoms": int(round(wl.f_rand * wl.n)), "box": wl.box,
                "r0": wl.r0, "n_k": n_k, "ell_max": wl.ell_max_b, "precision": prec, "randoms": "drawn on the device"}
+    elif args.workload == "bk-aniso":
+        # the anisotropic bispectrum (l1 <= l2 <= 4, m <= l1: 35 combinations)
+        # of the 5e5-point clustered box, 3N randoms drawn on the device
+        wl = synthetic.workload(3)
+        prec = "mixed"
+        pos = torch.from_numpy(wl.pos).cuda()
+        w = None
+        n_k = len(wl.k_edges_b) - 1
+        lmax_a = 4
+
+        def step():
+            out, info = hp.bk_aniso(pos, box=wl.box, r0=wl.r0, k_edges=wl.k_edges_b, ell_max=lmax_a,
+                                    f_rand=wl.f_rand, seed=wl.seed, return_diag=True)
+            info = dict(info)
+            info["sweep_launches"] = 2
+            return out, info
+        units_per_pair = n_k * (lmax_a + 1) ** 2
+        cfg = {"workload": wl.name + "_anisotropic", "n_points": wl.n, "n_randoms": int(round(wl.f_rand * wl.n)),
+               "box": wl.box, "r0": wl.r0, "n_k": n_k, "ell_max": lmax_a, "n_combinations": 35,
+               "precision": prec, "randoms": "drawn on the device", "line_of_sight": "z"}
     elif args.workload == "cov":
         # theory side: Gaussian covariance of the headline power spectrum's
         # binning (40 log bins over 1-10 h/Mpc, R0 = 25, l = 0, 2, 4) on a
@@ -648,10 +668,12 @@ def main():
                                "traffic": None, "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
     else:
         # both primary catalogues, per launch (data primaries, then random primaries)
-        flops = ((pairs + pairs_r) * bk_flops_per_pair(n_k, wl.ell_max_b, with_c=prec == "fp64")
+        lm = lmax_a if args.workload == "bk-aniso" else wl.ell_max_b
+        flops = ((pairs + pairs_r) * bk_flops_per_pair(n_k, lm, with_c=prec == "fp64")
                  / (launches / args.steps))
         achieved = flops / (avg_launch_ms * 1e-3) / 1e12
-        out["roofline"] = {"bound": "alu", "kernel": "k_bk_quad", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+        kname = "k_bk_quad (anisotropic contraction)" if args.workload == "bk-aniso" else "k_bk_quad"
+        out["roofline"] = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                            "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
                            "frac_fp64": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                            "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}

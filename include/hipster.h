@@ -195,6 +195,30 @@ hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data,
                               const hipster_points *randoms, double f_rand, uint64_t seed,
                               const hipster_params *prm, double *bk, hipster_diag *diag);
 
+/* Anisotropic bispectrum multipoles about the line of sight z (Sec. 10: the
+ * Sec. 4 estimators with the sum over harmonics of one order replaced by a
+ * product of harmonics of different orders).  The reading:
+ *   B^{ab}_{l1 l2 m} = s 4 pi / (V n_w^3) [(G_D - C_D) - s_R (G_R - C_R)]
+ *     - s sqrt(4 pi) / (V n_w^2) delta_m0 [delta_{l2 0} W~^b T^a_{l1} + delta_{l1 0} W~^a T^b_{l2}]
+ *     + 2 delta_{l1 0} delta_{l2 0} delta_m0 W~^a W~^b,
+ * G = sum_p w_p sum_{mu = +-m} A^a_{l1 mu} A^b_{l2 mu} (A as for hipster_bk_ell,
+ * real orthonormal harmonics), C its j = k part, T^a_l = sum_p w_p A^a_{l0}
+ * over data primaries, s the real factor of (-i)^{l1+l2} ((-1)^{(l1+l2)/2},
+ * or (-1)^{(l1+l2-1)/2} when l1 + l2 is odd: that multipole is s(...) times -i).
+ * Summed over m at l1 = l2 = l it is hipster_bk_ell's B^{ab}_l.  Random
+ * primaries as for hipster_bk_ell (a given catalogue, or f_rand and seed).
+ * Mixed form only (HIPSTER_FP64 gives HIPSTER_EUNSUPPORTED: C comes from
+ * fixed-point r-histograms of w_p w_q^2 W^2 P_L(mu), one per L, contracted with
+ * tables of jbar^a_{l1} jbar^b_{l2}), n_k <= 16, ell_max <= 4.
+ * bk: host output [n_c][n_k][n_k], the combinations c = (l1, l2, m) with
+ * l1 <= l2 <= ell_max and m = 0 .. l1 in that order (n_c = 35 at ell_max 4);
+ * B^{ab}_{l1 l2 m} = B^{ba}_{l2 l1 m} gives the others.  diag: the pair
+ * counts, n_rand, wtilde and the timings (ms_sweep: the two sweeps; ms_cterm:
+ * the C-term histograms); the other arrays are not filled. */
+hipster_status hipster_bk_aniso(hipster_ctx *ctx, const hipster_points *data, const hipster_points *randoms,
+                                double f_rand, uint64_t seed, const hipster_params *prm, double *bk,
+                                hipster_diag *diag);
+
 /* Bispectrum multipoles with the DDR^II term computed without randoms
  * (Sec. 4, eq. EII-intro; Appendix A, eq. DDRII-kernel and its binned form;
  * Appendix B): the random-primary sum of hipster_bk_ell,

@@ -17,7 +17,7 @@ from typing import Any
 
 import numpy as np
 
-__all__ = ["Context", "wtilde", "pk_ell", "pk_ell_noalloc", "bk_ell", "batch", "HipsterError", "library_path", "load_library",
+__all__ = ["Context", "wtilde", "pk_ell", "pk_ell_noalloc", "bk_ell", "bk_aniso", "aniso_combos", "batch", "HipsterError", "library_path", "load_library",
            "EXPORTED_SYMBOLS", "MIXED", "FP64", "TABLE", "pk_survey", "bk_ell_analytic", "eii_table",
            "omega", "pk_window_theory", "cov_gauss", "cov_poisson2", "cov_poisson3", "cov_nongauss"]
 
@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = ("hipster_create", "hipster_destroy", "hipster_pk_ell", "hips
                     "hipster_set_memory_cap", "hipster_wtilde", "hipster_pk_survey",
                     "hipster_bk_ell_analytic", "hipster_eii_table", "hipster_omega",
                     "hipster_pk_window_theory", "hipster_cov_gauss", "hipster_cov_poisson2",
-                    "hipster_cov_poisson3", "hipster_cov_nongauss", "hipster_pk_ell_noalloc")
+                    "hipster_cov_poisson3", "hipster_cov_nongauss", "hipster_pk_ell_noalloc", "hipster_bk_aniso")
 
 
 class HipsterError(RuntimeError):
@@ -100,6 +100,9 @@ def load_library():
     L.hipster_destroy.argtypes = [ct.c_void_p]
     L.hipster_pk_ell.restype = ct.c_int
     L.hipster_pk_ell.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Params), _dp, ct.POINTER(_Diag)]
+    L.hipster_bk_aniso.restype = ct.c_int
+    L.hipster_bk_aniso.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Points), ct.c_double, ct.c_uint64,
+                                   ct.POINTER(_Params), _dp, ct.POINTER(_Diag)]
     L.hipster_pk_ell_noalloc.restype = ct.c_int
     L.hipster_pk_ell_noalloc.argtypes = [ct.c_void_p, ct.POINTER(_Points), ct.POINTER(_Params), _dp,
                                          ct.POINTER(_Diag)]
@@ -394,6 +397,37 @@ def bk_ell(pos, w=None, randoms=None, rw=None, *, box: float, r0: float, k_edges
                 n_rand=int(d.n_rand), ms_build=d.ms_build, ms_pairs=d.ms_pairs, ms_sweep=d.ms_sweep,
                 ms_total=d.ms_total, sweep_launches=int(d.sweep_launches), ms_cterm=d.ms_cterm)
     return out, info
+
+
+def aniso_combos(ell_max: int):
+    """(l1, l2, m) of hipster_bk_aniso's output rows: l1 <= l2 <= ell_max, m = 0..l1."""
+    return [(l1, l2, m) for l1 in range(ell_max + 1) for l2 in range(l1, ell_max + 1) for m in range(l1 + 1)]
+
+
+def bk_aniso(pos, w=None, randoms=None, rw=None, *, box: float, r0: float, k_edges, ell_max: int = 4,
+             precision: str = "mixed", primary_mask=None, random_mask=None, f_rand: float = 0.0, seed: int = 0,
+             ctx: Context | None = None, return_diag: bool = False) -> Any:
+    """Anisotropic bispectrum multipoles B^ab_{l1 l2 m} about the z axis:
+    float64 array (n_c, n_k, n_k), rows in the order of aniso_combos(ell_max).
+    Random primaries as for bk_ell.  With return_diag, also the pair counts,
+    the random count, W~^a and timings."""
+    L = load_library()
+    keep: list = []
+    pts = _points(pos, w, keep)
+    rpts = _points(randoms, rw, keep)
+    prm = _params(box, r0, k_edges, ell_max, 2, precision, primary_mask, random_mask, keep)
+    n_k = prm.n_k
+    out = np.zeros((len(aniso_combos(ell_max)), n_k, n_k))
+    wt = np.zeros(n_k)
+    d = _Diag()
+    d.wtilde = _ptr(wt)
+    c = ctx or _context_for(pos)
+    c.check(L.hipster_bk_aniso(c.handle, ct.byref(pts), ct.byref(rpts), float(f_rand), int(seed) & (2 ** 64 - 1),
+                               ct.byref(prm), _ptr(out), ct.byref(d)))
+    if not return_diag:
+        return out
+    return out, dict(wtilde=wt, n_pairs=int(d.n_pairs), n_pairs_rand=int(d.n_pairs_rand), n_rand=int(d.n_rand),
+                     ms_build=d.ms_build, ms_sweep=d.ms_sweep, ms_cterm=d.ms_cterm, ms_total=d.ms_total)
 
 
 def bk_ell_analytic(pos, w=None, *, box: float, r0: float, k_edges, ell_max: int = 4, n_x: int = 0,

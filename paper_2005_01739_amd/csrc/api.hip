@@ -977,6 +977,164 @@ static void run_bk(Ctx &c, const hipster_points *dp, const hipster_points *rp, d
   bk_assemble(c, x);
   if (diag) diag->ms_total = Timer::ms(t0, t3);
 }
+// ------------------------------------------------- anisotropic bispectrum
+// Legendre coefficients q[c][L], L = 0 .. 2 ell_max, of
+//   Q_c(mu) = sum_{mu' = +-m} y_{l1 mu'} y_{l2 mu'} = (2 - delta_m0) N_{l1 m} N_{l2 m} P^m_{l1}(mu) P^m_{l2}(mu)
+// (real orthonormal harmonics about z; the azimuth drops out), by 32-point
+// Gauss-Legendre quadrature, exact for these polynomials of degree <= 2 ell_max.
+static void aniso_qcoef(int ell_max, const std::vector<int> &cl1, const std::vector<int> &cl2,
+                        const std::vector<int> &cm, std::vector<double> &q) {
+  const int nc = int(cl1.size()), ns = 2 * ell_max + 1;
+  constexpr int NG = 32;
+  double xg[NG], wg[NG];
+  for (int i = 0; i < NG; ++i) {  // Newton on P_NG from the Chebyshev guess
+    double x = cos(kPi * (i + 0.75) / (NG + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int n = 2; n <= NG; ++n) {
+        const double p2 = ((2.0 * n - 1.0) * x * p1 - (n - 1.0) * p0) / n;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = NG * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    xg[i] = x;
+    wg[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  // associated Legendre P^m_l without the Condon-Shortley phase (it cancels in Q)
+  auto plm = [](int l, int m, double x) {
+    double pmm = 1.0;
+    const double sx = sqrt(std::max(0.0, 1.0 - x * x));
+    for (int i = 1; i <= m; ++i) pmm *= (2.0 * i - 1.0) * sx;
+    if (l == m) return pmm;
+    double p1 = x * (2.0 * m + 1.0) * pmm;
+    if (l == m + 1) return p1;
+    double p0 = pmm;
+    for (int n = m + 2; n <= l; ++n) {
+      const double p2 = ((2.0 * n - 1.0) * x * p1 - (n + m - 1.0) * p0) / (n - m);
+      p0 = p1;
+      p1 = p2;
+    }
+    return p1;
+  };
+  auto norm = [](int l, int m) {
+    double r = 1.0;
+    for (int i = l - m + 1; i <= l + m; ++i) r /= double(i);
+    return sqrt((2.0 * l + 1.0) / (4.0 * kPi) * r);
+  };
+  q.assign(size_t(nc) * ns, 0.0);
+  for (int c = 0; c < nc; ++c) {
+    const int l1 = cl1[size_t(c)], l2 = cl2[size_t(c)], m = cm[size_t(c)];
+    const double f = (m == 0 ? 1.0 : 2.0) * norm(l1, m) * norm(l2, m);
+    for (int L = 0; L < ns; ++L) {
+      double acc = 0.0;
+      for (int i = 0; i < NG; ++i) acc += wg[i] * f * plm(l1, m, xg[i]) * plm(l2, m, xg[i]) * plm(L, 0, xg[i]);
+      q[size_t(c) * ns + L] = 0.5 * (2.0 * L + 1.0) * acc;
+    }
+  }
+}
+
+// B^{ab}_{l1 l2 m} about the line of sight z (the reading of Sec. 10 in the
+// header): the sweep's G and T sums, the C term from the Legendre-section
+// histograms, and the assembly of the Sec. 4 summary estimator with the
+// harmonic products of different order.
+static void run_bk_aniso(Ctx &c, const hipster_points *dp, const hipster_points *rp, double f_rand, uint64_t seed,
+                         const hipster_params *q, double *bk, hipster_diag *diag) {
+  BkBox x;
+  x.dp = dp;
+  x.rp = rp;
+  x.q = q;
+  x.bk = bk;
+  x.diag = nullptr;
+  x.f_rand = f_rand;
+  x.seed = seed;
+  bk_check(c, x);
+  if (x.fp64)
+    throw Error{HIPSTER_EUNSUPPORTED, "anisotropic bispectrum: the mixed form only (its C term is tabulated)"};
+  if (q->n_k > 16) throw Error{HIPSTER_EUNSUPPORTED, "anisotropic bispectrum: n_k must lie in [1, 16]"};
+  if (q->ell_max > 4) throw Error{HIPSTER_EUNSUPPORTED, "anisotropic bispectrum: ell_max must lie in [0, 4]"};
+  HIPSTER_HIP(hipSetDevice(c.device));
+  Timer tm(c);
+  hipEvent_t t0 = tm.mark();
+  const BkBufs b{&c.cells_d, &c.cells_r, &c.pos_in, &c.w_in, &c.mask_in, &c.rpos_in, &c.rw_in,
+                 &c.rmask_in, &c.rgen, &c.edges, &c.bk_coef, &c.ordered_count};
+  bk_prepare(c, tm, x, b);
+  const int NK = q->n_k, NL = q->ell_max + 1;
+  std::vector<int> cl1, cl2, cm;
+  for (int l1 = 0; l1 < NL; ++l1)
+    for (int l2 = l1; l2 < NL; ++l2)
+      for (int m = 0; m <= l1; ++m) {
+        cl1.push_back(l1);
+        cl2.push_back(l2);
+        cm.push_back(m);
+      }
+  const int NC = int(cl1.size());
+  std::vector<double> G[2], T[2], C[2];
+  hipEvent_t s0 = tm.mark();
+  for (int set = 0; set < 2; ++set)
+    bk_aniso_sweep(c, set == 0 ? x.sd : x.sr, x.sd, x.g, q->r0, set == 0, x.edges, x.coef, NK, q->ell_max,
+                   x.cnt + set, G[set], T[set]);
+  hipEvent_t s1 = tm.mark();
+  unsigned long long n_ord[2] = {0, 0};
+  HIPSTER_HIP(hipMemcpyAsync(n_ord, x.cnt, 16, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  std::vector<double> qc;
+  aniso_qcoef(q->ell_max, cl1, cl2, cm, qc);
+  const int n_c = cterm_default_nodes(q->r0, q->k_edges[NK]);
+  hipEvent_t c0 = tm.mark();
+  for (int set = 0; set < 2; ++set) {
+    C[set].resize(size_t(NC) * NK * NK);
+    cterm_aniso_sweep(c, set == 0 ? x.sd : x.sr, x.sd, set == 1, x.g, q->r0, NK, q->k_edges, q->ell_max, n_c,
+                      n_ord[set], NC, cl1.data(), cl2.data(), qc.data(), C[set].data(), x.cnt + 2);
+  }
+  hipEvent_t c1 = tm.mark();
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  // assembly, host FP64
+  const double p1 = weight_sum(dp), pr = x.gen_r ? double(x.n_gen) : weight_sum(x.rp);
+  const double V = q->box * q->box * q->box, nw = p1 / V, sR = p1 / pr;
+  std::vector<double> wt(static_cast<size_t>(NK));
+  wtilde_bins(c, q->r0, NK, q->k_edges, wt.data());
+  const double sq4pi = sqrt(4.0 * kPi);
+  for (int ci = 0; ci < NC; ++ci) {
+    const int l1 = cl1[size_t(ci)], l2 = cl2[size_t(ci)], m = cm[size_t(ci)], L = l1 + l2;
+    // the real factor of (-i)^{l1 + l2}
+    const double sgn = ((((L & 1) ? (L - 1) / 2 : L / 2) & 1) != 0) ? -1.0 : 1.0;
+    for (int a = 0; a < NK; ++a)
+      for (int bb = 0; bb < NK; ++bb) {
+        const size_t o = (size_t(ci) * NK + a) * NK + bb;
+        double v = sgn * 4.0 * kPi / (V * nw * nw * nw) * ((G[0][o] - C[0][o]) - sR * (G[1][o] - C[1][o]));
+        if (m == 0) {
+          double d1 = 0.0;
+          if (l2 == 0) d1 += wt[size_t(bb)] * T[0][size_t(l1) * NK + a];
+          if (l1 == 0) d1 += wt[size_t(a)] * T[0][size_t(l2) * NK + bb];
+          v -= sgn * sq4pi / (V * nw * nw) * d1;
+          if (l1 == 0 && l2 == 0) v += 2.0 * wt[size_t(a)] * wt[size_t(bb)];
+        }
+        bk[o] = v;
+      }
+  }
+  if (diag) {
+    unsigned long long hcnt[2] = {0, 0};
+    HIPSTER_HIP(hipMemcpy(hcnt, x.cnt, 16, hipMemcpyDeviceToHost));
+    diag->n_pairs = hcnt[0];
+    diag->n_pairs_rand = hcnt[1];
+    diag->n_pairs_rr = 0;
+    diag->n_rand = uint64_t(x.rp->n);
+    diag->ms_build = Timer::ms(x.ev_b0, x.ev_b1);
+    diag->ms_pairs = 0.0;
+    diag->ms_sweep = Timer::ms(s0, s1);
+    diag->ms_cterm = Timer::ms(c0, c1);
+    diag->ms_total = Timer::ms(t0, c1);
+    diag->sweep_launches = 2;
+    diag->ms_sweep_far = 0.0;
+    diag->n_pairs_far = 0;
+    if (diag->wtilde) memcpy(diag->wtilde, wt.data(), size_t(NK) * 8);
+  }
+}
+
 // ------------------------------------------------------------ autotuner
 std::string tune_key(Ctx &c, const char *kernel, std::initializer_list<int> shape) {
   hipDeviceProp_t prop{};
@@ -1475,6 +1633,7 @@ void hipster_destroy(hipster_ctx *ctx) {
                    &c.ct_wmax, &c.ct_jbar, &c.ct_sel, &c.rgen, &c.pk_l1, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
                    &c.th_K, &c.th_out, &c.th_wt, &c.th_pb, &c.th_bk, &c.th_T, &c.th_X, &c.pt_tab, &c.pt_consts,
                    &c.pt_T, &c.bq_jobs, &c.bq_tasks, &c.bq_slots, &c.bq_counter,
+                   &c.ca_q, &c.ca_l, &c.ca_count, &c.ca_out, &c.ca_tab,
                    &c.tune_scratch};
   for (DevBuf *b : all) free_buf(*b);
   for (BkBoxScratch &s : c.bt_bk) {
@@ -1506,6 +1665,12 @@ hipster_status hipster_bk_ell(hipster_ctx *ctx, const hipster_points *data, cons
                               double f_rand, uint64_t seed, const hipster_params *prm, double *bk,
                               hipster_diag *diag) {
   return guarded(ctx, [&] { run_bk(ctx->c, data, randoms, f_rand, seed, prm, bk, diag); });
+}
+
+hipster_status hipster_bk_aniso(hipster_ctx *ctx, const hipster_points *data, const hipster_points *randoms,
+                                double f_rand, uint64_t seed, const hipster_params *prm, double *bk,
+                                hipster_diag *diag) {
+  return guarded(ctx, [&] { run_bk_aniso(ctx->c, data, randoms, f_rand, seed, prm, bk, diag); });
 }
 
 hipster_status hipster_bk_ell_analytic(hipster_ctx *ctx, const hipster_points *data, const hipster_params *prm,

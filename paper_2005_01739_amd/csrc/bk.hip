@@ -221,10 +221,18 @@ __device__ __forceinline__ void fmac_all(double (&acc)[NA], const double (&yr)[N
 #define HIPSTER_BK_WAVES 2
 #endif
 
-template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE>
+// Anisotropic combinations (l1 <= l2 < NL, m = 0 .. l1) in (l1, l2, m) order.
+__host__ __device__ constexpr int aniso_count(int NL) {
+  int c = 0;
+  for (int l1 = 0; l1 < NL; ++l1) c += (NL - l1) * (l1 + 1);
+  return c;
+}
+
+template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE, bool ANISO = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HIPSTER_BK_WAVES : 1))) void k_bk_quad(
     BkArgs A) {
   static_assert(GRAM || !QUEUE, "the queued sweep keeps its Gram tiles in registers");
+  static_assert(!ANISO || (GRAM && !FP64 && !WITH_C && !QUEUE), "the anisotropic sweep is single-box, mixed form");
   constexpr int NLM = NL * NL;
   constexpr int NY = (NLM + 15) / 16;
   using YT = YStage<FP64>;
@@ -299,6 +307,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
 #pragma unroll
   for (int l = 0; l < NL; ++l) accC[l] = accG[l] = d4_t{0.0, 0.0, 0.0, 0.0};
   double s0acc = 0.0;
+  double tl[ANISO ? NL : 1];  // anisotropic: sum_p w_p A^a_{l0}, per multipole
+#pragma unroll
+  for (int l = 0; l < (ANISO ? NL : 1); ++l) tl[l] = 0.0;
   unsigned long long pcount = 0;
   int64_t cur_cell = -1;
   wave_sync();
@@ -628,7 +639,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       // the quad's contribution; the bin's 3 / (k_{a+1}^3 - k_a^3) first
 #pragma unroll
       for (int k = 0; k < NLM; ++k) acc[k] *= cfb;
-      if constexpr (GRAM) {
+      if constexpr (ANISO) {
+        // G^{ab}_{l1 l2 m} += w_p sum_{mu = +-m} A^a_{l1 mu} A^b_{l2 mu}, added to
+        // the wave's row after every quad (too many tiles for registers)
+        double *const wrow = A.partial + int64_t(blockIdx.x) * A.rowlen;
+        int cidx = 0;
+#pragma unroll
+        for (int l1 = 0; l1 < NL; ++l1)
+#pragma unroll
+          for (int l2 = l1; l2 < NL; ++l2)
+#pragma unroll
+            for (int m = 0; m <= l1; ++m, ++cidx) {
+              d4_t g = mfma_f64(acc[l1 * l1 + l1 + m], wp * acc[l2 * l2 + l2 + m], d4_t{0.0, 0.0, 0.0, 0.0});
+              if (m > 0) g = mfma_f64(acc[l1 * l1 + l1 - m], wp * acc[l2 * l2 + l2 - m], g);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) wrow[cidx * 256 + (row + 4 * v) * 16 + col] += g[v];
+              // one tile's read-modify-write at a time: hoisting every tile's
+              // loads would need all of their registers at once
+              __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+        for (int l = 0; l < NL; ++l) tl[l] = fma(wp, acc[l * l + l], tl[l]);
+      } else if constexpr (GRAM) {
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
           const double wsc = wp * (4.0 * kPi / double(2 * l + 1));
@@ -655,7 +687,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       for (int64_t qi = c0; qi < c1; ++qi) quad(qi);
     }
     double *out = A.partial + int64_t(blockIdx.x) * A.rowlen;
-    if constexpr (GRAM) {
+    if constexpr (ANISO) {
+#pragma unroll
+      for (int l = 0; l < NL; ++l) out[aniso_count(NL) * 256 + l * 64 + lane] += tl[l];
+    } else if constexpr (GRAM) {
 #pragma unroll
       for (int l = 0; l < NL; ++l)
 #pragma unroll
@@ -1100,6 +1135,85 @@ void bk_sweep_queue(Ctx &c, const std::vector<BkQueueJob> &jobs, int ell_max, bo
     case 5: bk_sweep_queue_nl<6>(c, jobs, fp64, out); break;
     case 6: bk_sweep_queue_nl<7>(c, jobs, fp64, out); break;
     default: throw Error{HIPSTER_EDOMAIN, "ell_max must lie in [0, 6]"};
+  }
+}
+
+template <int NL>
+static void bk_aniso_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
+                        const double *edges, const double *coef, int NK, unsigned long long *npairs,
+                        std::vector<double> &G, std::vector<double> &T) {
+  constexpr int NC = aniso_count(NL);
+  if (NK < 1 || NK > 16) throw Error{HIPSTER_EUNSUPPORTED, "anisotropic bispectrum: n_k must lie in [1, 16]"};
+  if (sec.n >= (int64_t(1) << 27))
+    throw Error{HIPSTER_EUNSUPPORTED, "bispectrum: at most 2^27 - 1 data points (27-bit hit indices)"};
+  G.assign(size_t(NC) * NK * NK, 0.0);
+  T.assign(size_t(NL) * NK, 0.0);
+  if (prim.n == 0) return;
+  const int64_t ncells = g.ncells();
+  int64_t *qcount = static_cast<int64_t *>(ensure(c, c.bq_count, size_t(ncells + 1) * 8));
+  int64_t *qoff = static_cast<int64_t *>(ensure(c, c.bq_off, size_t(ncells + 1) * 8));
+  const unsigned cb = unsigned((ncells + 255) / 256);
+  k_quad_count<<<dim3(cb), dim3(256), 0, c.stream>>>(prim.cell_start, prim.m, ncells, qcount);
+  HIPSTER_HIP(hipGetLastError());
+  scan_i64(c, qcount, qoff, ncells, c.bq_scan);
+  int64_t nq = 0;
+  HIPSTER_HIP(hipMemcpyAsync(&nq, qoff + ncells, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  if (nq == 0) return;
+  BkQuad *quads = static_cast<BkQuad *>(ensure(c, c.bq_quads, size_t(nq) * sizeof(BkQuad)));
+  k_quad_fill<<<dim3(cb), dim3(256), 0, c.stream>>>(prim.cell_start, prim.m, ncells, qoff, quads);
+  HIPSTER_HIP(hipGetLastError());
+  BkArgs a{};
+  a.job = bk_job(prim, sec, g, r0, self_set, edges, coef, NK, npairs);
+  a.quads = quads;
+  a.q_lo = 0;
+  a.q_hi = nq;
+  a.group = 0;
+  a.rowlen = NC * 256 + NL * 64;
+  a.ld = 16;
+  int per_cu = 0;
+  const size_t lds = bk_lds_bytes<NL, false>();
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bk_quad<NL, false, false, true, false, true>, 64, lds) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  hipDeviceProp_t prop{};
+  int cus = 256;
+  if (hipGetDeviceProperties(&prop, c.device) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  const int nwaves = std::max(kXcds, cus * per_cu / kXcds * kXcds);
+  double *part = static_cast<double *>(ensure(c, c.bk_partial, size_t(nwaves) * a.rowlen * 8));
+  HIPSTER_HIP(hipMemsetAsync(part, 0, size_t(nwaves) * a.rowlen * 8, c.stream));
+  a.partial = part;
+  k_bk_quad<NL, false, false, true, false, true><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(a);
+  HIPSTER_HIP(hipGetLastError());
+  double *merged = static_cast<double *>(ensure(c, c.merged, size_t(a.rowlen) * 8));
+  merge_partials(c, part, nwaves, a.rowlen, merged);
+  std::vector<double> M(size_t(a.rowlen));
+  HIPSTER_HIP(hipMemcpyAsync(M.data(), merged, size_t(a.rowlen) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  // tile c: D[a][b] = sum_p w_p sum_mu A^a_{l1 mu} A^b_{l2 mu} at c 256 + 16 a + b
+  for (int ci = 0; ci < NC; ++ci)
+    for (int x = 0; x < NK; ++x)
+      for (int y = 0; y < NK; ++y) G[(size_t(ci) * NK + x) * NK + y] = M[size_t(ci * 256 + x * 16 + y)];
+  for (int l = 0; l < NL; ++l)
+    for (int b = 0; b < NK; ++b) {
+      double t = 0.0;
+      for (int r = 0; r < 4; ++r) t += M[size_t(NC * 256 + l * 64 + 16 * r + b)];
+      T[size_t(l) * NK + b] = t;
+    }
+}
+
+void bk_aniso_sweep(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
+                    const double *edges, const double *coef, int NK, int ell_max, unsigned long long *npairs,
+                    std::vector<double> &G, std::vector<double> &T) {
+  switch (ell_max) {
+    case 0: bk_aniso_nl<1>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T); break;
+    case 1: bk_aniso_nl<2>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T); break;
+    case 2: bk_aniso_nl<3>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T); break;
+    case 3: bk_aniso_nl<4>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T); break;
+    case 4: bk_aniso_nl<5>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T); break;
+    default: throw Error{HIPSTER_EUNSUPPORTED, "anisotropic bispectrum: ell_max must lie in [0, 4]"};
   }
 }
 

@@ -137,6 +137,7 @@ struct Ctx {
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bq_count, bq_off, bq_scan, bq_quads, bk_abuf, bk_wbuf, bk_tiles, bk_gpart, bk_gmerged;
   DevBuf bq_jobs, bq_tasks, bq_slots, bq_counter;  // queued bispectrum sweep
+  DevBuf ca_q, ca_l, ca_count, ca_out, ca_tab;      // anisotropic C term
   std::vector<BkBoxScratch> bt_bk;                  // batched bispectrum, per box
   DevBuf rgen, pk_l1;
   DevBuf bt_tasks, bt_boxes, bt_counter, bt_rows, bt_first, bt_out;
@@ -250,6 +251,15 @@ struct BkQueueJob {
 };
 void bk_sweep_queue(Ctx &c, const std::vector<BkQueueJob> &jobs, int ell_max, bool fp64, std::vector<BkSums> &out);
 
+// Anisotropic bispectrum sums of one primary set against the data (mixed
+// form, n_k <= 16, ell_max <= 4): G [n_c][n_k][n_k] = sum_p w_p
+// sum_{mu = +-m} A^a_{l1 mu} A^b_{l2 mu} for the combinations (l1 <= l2, m <= l1)
+// in (l1, l2, m) order, and T [ell_max+1][n_k] = sum_p w_p A^a_{l0}
+// (real orthonormal harmonics about z).
+void bk_aniso_sweep(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
+                    const double *edges, const double *coef, int NK, int ell_max, unsigned long long *npairs,
+                    std::vector<double> &G, std::vector<double> &T);
+
 // n uniform points in [0, L)^3 (device, [n][3] doubles), point i from block
 // i + 1 of the Philox4x64-10 generator keyed by (seed, 0): x_d = L (word_d >> 11)
 // 2^-53, a coordinate that rounds to L set to 0.
@@ -291,6 +301,16 @@ void pktab_survey_sweep(Ctx &c, const Sorted &a, const Sorted &b, bool cross, co
 // jbar^a jbar^b; C [ell_max+1][n_k][n_k] (device).  `s` is the data sorted on
 // the R0 grid `g`.
 int cterm_default_nodes(double r0, double k_max);
+// Anisotropic C term (fixed line of sight z): host C[n_comb][n_k][n_k] =
+// sum over ordered pairs (p, q) of w_p w_q^2 W(r/R0)^2 jbar^a_{l1} jbar^b_{l2}
+// Q_c(mu_pq), Q_c = sum_L q[c][L] P_L (L = 0 .. 2 ell_max), through
+// fixed-point r-histograms of w_p w_q^2 W^2 P_L(mu) (one section per L, in
+// passes the LDS holds) contracted with tables of q_L jbar^a_{l1} jbar^b_{l2}.
+// cross: primaries s against neighbours b (all 27 cells), else s with
+// itself.  The first pass adds the ordered pairs to *ordered.
+void cterm_aniso_sweep(Ctx &c, const Sorted &s, const Sorted &b, bool cross, const Grid &g, double r0, int n_k,
+                       const double *k_edges, int ell_max, int n_c, uint64_t n_ordered, int n_comb, const int *cl1,
+                       const int *cl2, const double *q, double *C, unsigned long long *ordered);
 // cross = false: `s` with itself (b ignored); cross = true: primaries `s`
 // (random primaries) against secondaries `b` (the data), every pair once.
 // n_ordered: the ordered pairs inside R0 (bounds the fixed-point sums).

@@ -309,6 +309,8 @@ enum HistKind {
   kHistDdr2 = 0,   // pairs inside 2 R0, weight w_i w_j per orientation
   kHistCterm = 1,  // pairs inside R0, weight w_p w_q^2 W(r/R0)^2 per orientation (p, q)
   kHistPk = 2,     // pairs inside R0, weight w_i w_j W(r/R0) L_l(mu) per orientation, one section per even l
+  kHistCtermL = 3, // pairs inside R0, weight w_p w_q^2 W(r/R0)^2 P_L(mu_pq) per orientation (p, q),
+                   // mu_pq along x_p - x_q; one section per L = los .. los + NLP - 1
 };
 
 // CROSS: the home points (primaries) come from `s` and the neighbours from
@@ -461,6 +463,28 @@ k_ddr2_hist(Sorted s, Sorted b, int nc, double L, double lim2,
           if constexpr (NLP > 1) wv[1] = base * (1.5 * m2 - 0.5);
           if constexpr (NLP > 2) wv[2] = base * (((35.0 * m2 - 30.0) * m2 + 3.0) * 0.125);
           if constexpr (NLP > 3) wv[3] = base * ((((231.0 * m2 - 315.0) * m2 + 105.0) * m2 - 5.0) * 0.0625);
+        } else if constexpr (KIND == kHistCtermL) {
+          // P_L of the (p, q) orientation; the (q, p) one has -mu, (-1)^L P_L
+          const double r = sqrt(r2);
+          const double mu = r2 > 0.0 ? dz / r : 0.0;
+          const double W = window<double>(r * inv_r0);
+          const double a = p.w * q.w * q.w * double(mi_) * (W * W);
+          const double b = CROSS ? 0.0 : q.w * p.w * p.w * double(mj_) * (W * W);
+          // (c0, c1) = (P_L, P_{L+1}), advanced by the three-term recurrence
+          double c0 = 1.0, c1 = mu;
+          int L = 0;
+          for (; L < los; ++L) {
+            const double nx = (double(2 * L + 3) * mu * c1 - double(L + 1) * c0) / double(L + 2);
+            c0 = c1;
+            c1 = nx;
+          }
+#pragma unroll
+          for (int sec = 0; sec < NLP; ++sec, ++L) {
+            wv[sec] = c0 * (a + ((L & 1) ? -b : b));
+            const double nx = (double(2 * L + 3) * mu * c1 - double(L + 1) * c0) / double(L + 2);
+            c0 = c1;
+            c1 = nx;
+          }
         } else if constexpr (CROSS) {
           // (primary i, neighbour j) only
           const double W = window<double>(sqrt(r2) * inv_r0);
@@ -954,6 +978,128 @@ void cterm_sweep(Ctx &c, const Sorted &s, const Sorted &b, bool cross, const Gri
   else
     hist_sweep<kHistCterm, false>(c, s, s, g, r0 * r0, 1.0 / h, n_c, n_nodes, n_nodes, 1.0 / r0, fix_scale, F, rows,
                                   C, ordered);
+}
+
+// ------------------------------------------------ anisotropic C term
+// Table of one pass of Legendre sections: row (c, a, b), entry (sec, m) =
+// q[c][L0 + sec] jbar^a_{l1(c)}(x_m) jbar^b_{l2(c)}(x_m), from the jbar table
+// J [n_l][n_k][n_nodes] of k_cterm_jbar.
+__global__ __launch_bounds__(256) void k_aniso_ctable(int n_nodes, int n_k, const double *__restrict__ J,
+                                                      const double *__restrict__ q, const int *__restrict__ cl1,
+                                                      const int *__restrict__ cl2, int n_sec_all, int L0, int ns,
+                                                      int64_t rows, double *__restrict__ F) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t cols = int64_t(ns) * n_nodes;
+  if (idx >= rows * cols) return;
+  const int64_t row = idx / cols;
+  const int col = int(idx - row * cols), sec = col / n_nodes, m = col - sec * n_nodes;
+  const int b = int(row % n_k), a = int((row / n_k) % n_k), cb = int(row / (int64_t(n_k) * n_k));
+  const double ja = J[(int64_t(cl1[cb]) * n_k + a) * n_nodes + m];
+  const double jb = J[(int64_t(cl2[cb]) * n_k + b) * n_nodes + m];
+  F[idx] = q[int64_t(cb) * n_sec_all + L0 + sec] * ja * jb;
+}
+
+template <bool MASKED, bool CROSS, int NLP>
+static void launch_ctl(Ctx &c, const Sorted &s, const Sorted &b, const Grid &g, const PairUnits &u, double lim2,
+                       double inv_h, int n_c, int n_nodes, double inv_r0, double fix_scale, int L0,
+                       unsigned long long *counter, unsigned long long *ordered, double *partial, int nwg) {
+  const size_t lds = size_t(NLP) * n_nodes * 8;
+  k_ddr2_hist<MASKED, kHistCtermL, CROSS, NLP><<<dim3(unsigned(nwg)), dim3(kHistThreads), lds, c.stream>>>(
+      s, b, g.nc, g.L, lim2, inv_h, n_c, n_nodes, NLP * n_nodes, inv_r0, fix_scale, L0, 1, g.L, 1.0, u.cell, u.tile,
+      u.n, counter, ordered, partial);
+  HIPSTER_HIP(hipGetLastError());
+}
+
+template <bool MASKED, bool CROSS>
+static void launch_ctl_n(Ctx &c, int ns, const Sorted &s, const Sorted &b, const Grid &g, const PairUnits &u,
+                         double lim2, double inv_h, int n_c, int n_nodes, double inv_r0, double fix_scale, int L0,
+                         unsigned long long *counter, unsigned long long *ordered, double *partial, int nwg) {
+  switch (ns) {
+    case 1: launch_ctl<MASKED, CROSS, 1>(c, s, b, g, u, lim2, inv_h, n_c, n_nodes, inv_r0, fix_scale, L0, counter, ordered, partial, nwg); break;
+    case 2: launch_ctl<MASKED, CROSS, 2>(c, s, b, g, u, lim2, inv_h, n_c, n_nodes, inv_r0, fix_scale, L0, counter, ordered, partial, nwg); break;
+    case 3: launch_ctl<MASKED, CROSS, 3>(c, s, b, g, u, lim2, inv_h, n_c, n_nodes, inv_r0, fix_scale, L0, counter, ordered, partial, nwg); break;
+    default: launch_ctl<MASKED, CROSS, 4>(c, s, b, g, u, lim2, inv_h, n_c, n_nodes, inv_r0, fix_scale, L0, counter, ordered, partial, nwg); break;
+  }
+}
+
+void cterm_aniso_sweep(Ctx &c, const Sorted &s, const Sorted &b, bool cross, const Grid &g, double r0, int n_k,
+                       const double *k_edges, int ell_max, int n_c, uint64_t n_ordered, int n_comb, const int *cl1,
+                       const int *cl2, const double *q, double *C, unsigned long long *ordered) {
+  const int n_nodes = n_c + 3, n_l = ell_max + 1, n_sec = 2 * ell_max + 1;
+  const int64_t rows = int64_t(n_comb) * n_k * n_k;
+  const size_t max_nodes = ddr2_max_nodes(c);
+  const int per_pass = int(std::min<size_t>(4, max_nodes / size_t(n_nodes)));
+  if (per_pass < 1) throw Error{HIPSTER_EUNSUPPORTED, "anisotropic C term: k_max R0 too large for the LDS histogram"};
+  // jbar^a_l on the nodes
+  std::vector<double> ek(static_cast<size_t>(2 * (n_k + 1))), coef(static_cast<size_t>(n_k));
+  for (int e = 0; e <= n_k; ++e) {
+    ek[size_t(2 * e)] = k_edges[e];
+    ek[size_t(2 * e + 1)] = k_edges[e] * k_edges[e] * k_edges[e];
+  }
+  for (int a = 0; a < n_k; ++a) coef[size_t(a)] = 3.0 / (ek[size_t(2 * a + 3)] - ek[size_t(2 * a + 1)]);
+  double *dk = static_cast<double *>(ensure(c, c.ct_consts, size_t(3 * n_k + 2) * 8));
+  HIPSTER_HIP(hipMemcpyAsync(dk, ek.data(), ek.size() * 8, hipMemcpyHostToDevice, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(dk + ek.size(), coef.data(), coef.size() * 8, hipMemcpyHostToDevice, c.stream));
+  double *J = static_cast<double *>(ensure(c, c.ct_jbar, size_t(n_l) * n_k * n_nodes * 8));
+  const double h = r0 / n_c;
+  const int64_t nj = int64_t(n_l) * n_k * n_nodes;
+  k_cterm_jbar<<<dim3(unsigned((nj + 255) / 256)), dim3(256), 0, c.stream>>>(h, n_nodes, n_k, n_l, dk, dk + ek.size(), J);
+  HIPSTER_HIP(hipGetLastError());
+  // combination tables
+  double *dq = static_cast<double *>(ensure(c, c.ca_q, size_t(n_comb) * n_sec * 8));
+  int *dl = static_cast<int *>(ensure(c, c.ca_l, size_t(2 * n_comb) * 4));
+  HIPSTER_HIP(hipMemcpyAsync(dq, q, size_t(n_comb) * n_sec * 8, hipMemcpyHostToDevice, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(dl, cl1, size_t(n_comb) * 4, hipMemcpyHostToDevice, c.stream));
+  HIPSTER_HIP(hipMemcpyAsync(dl + n_comb, cl2, size_t(n_comb) * 4, hipMemcpyHostToDevice, c.stream));
+  // fixed-point scale as for the isotropic C term (|P_L| <= 1)
+  const double wa = weight_max(c, s), wb = cross ? weight_max(c, b) : wa;
+  const double bound = (double(n_ordered) + 1.0) * 2.5 * std::max(wa * wb * wb, 1e-300);
+  const int e = std::min(52, 61 - int(ceil(log2(bound))));
+  const double fix_scale = ldexp(1.0, e);
+  const PairUnits u = make_pair_units(c, s, g);
+  int nwg = 0;
+  {
+    int cus = 0;
+    HIPSTER_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
+    nwg = std::max(1, cus) * 4;
+  }
+  unsigned long long *counter = static_cast<unsigned long long *>(ensure(c, c.ddr2_counter, 8));
+  unsigned long long *spare = static_cast<unsigned long long *>(ensure(c, c.ca_count, 8));
+  double *Cd = static_cast<double *>(ensure(c, c.ca_out, size_t(rows) * 8));
+  std::vector<double> part(static_cast<size_t>(rows));
+  for (int64_t i = 0; i < rows; ++i) C[i] = 0.0;
+  for (int L0 = 0; L0 < n_sec; L0 += per_pass) {
+    const int ns = std::min(per_pass, n_sec - L0);
+    const int n_hist = ns * n_nodes;
+    double *F = static_cast<double *>(ensure(c, c.ca_tab, size_t(rows) * n_hist * 8));
+    const int64_t nf = rows * n_hist;
+    k_aniso_ctable<<<dim3(unsigned((nf + 255) / 256)), dim3(256), 0, c.stream>>>(n_nodes, n_k, J, dq, dl, dl + n_comb,
+                                                                                n_sec, L0, ns, rows, F);
+    HIPSTER_HIP(hipGetLastError());
+    double *partial = static_cast<double *>(ensure(c, c.ddr2_partial, size_t(nwg) * n_hist * 8));
+    double *H = static_cast<double *>(ensure(c, c.ddr2_hist, size_t(n_hist) * 8));
+    HIPSTER_HIP(hipMemsetAsync(counter, 0, 8, c.stream));
+    // the ordered pairs are counted by the first pass only
+    unsigned long long *ord = L0 == 0 ? ordered : spare;
+    if (u.n > 0) {
+      const bool masked = s.m || (!cross && b.m);
+      if (cross) {
+        if (masked) launch_ctl_n<true, true>(c, ns, s, b, g, u, r0 * r0, 1.0 / h, n_c, n_nodes, 1.0 / r0, fix_scale, L0, counter, ord, partial, nwg);
+        else launch_ctl_n<false, true>(c, ns, s, b, g, u, r0 * r0, 1.0 / h, n_c, n_nodes, 1.0 / r0, fix_scale, L0, counter, ord, partial, nwg);
+      } else {
+        if (masked) launch_ctl_n<true, false>(c, ns, s, s, g, u, r0 * r0, 1.0 / h, n_c, n_nodes, 1.0 / r0, fix_scale, L0, counter, ord, partial, nwg);
+        else launch_ctl_n<false, false>(c, ns, s, s, g, u, r0 * r0, 1.0 / h, n_c, n_nodes, 1.0 / r0, fix_scale, L0, counter, ord, partial, nwg);
+      }
+    } else {
+      HIPSTER_HIP(hipMemsetAsync(partial, 0, size_t(nwg) * n_hist * 8, c.stream));
+    }
+    hist_reduce(c, partial, nwg, n_hist, 1.0 / fix_scale, H);
+    k_ddr2_contract<<<dim3(unsigned(rows)), dim3(256), 0, c.stream>>>(F, H, n_hist, int(rows), Cd);
+    HIPSTER_HIP(hipGetLastError());
+    HIPSTER_HIP(hipMemcpyAsync(part.data(), Cd, size_t(rows) * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    for (int64_t i = 0; i < rows; ++i) C[i] += part[size_t(i)];
+  }
 }
 
 // ------------------------------------------------- power spectrum, table form
