@@ -119,7 +119,19 @@ __device__ inline void wave_sync() { __syncthreads(); }
 
 constexpr int kXcds = 8;             // accelerator complex dies of the MI355X (the grid is a multiple)
 constexpr int kQuadRun = 4;          // consecutive quads per wave assignment
-constexpr int kHitCap = 128;         // hit ring buffer per row (power of two)
+// hit rings per row (powers of two): far and near class.  A row's hits come
+// in bursts (a primary near one face of the home cell finds most of its
+// neighbours in the cells on that side), so the far ring holds about a
+// quad's imbalance between rows before a batch must run with idle rows.
+constexpr int kHitCapF = 256;
+constexpr int kHitCapN = 128;
+template <int CL>
+constexpr int hit_cap() { return CL == 0 ? kHitCapF : kHitCapN; }
+// entry i of class CL's ring of row r in the flat ring array
+template <int CL>
+__device__ __forceinline__ int ring_at(int r, int i) {
+  return CL == 0 ? r * kHitCapF + i : 4 * kHitCapF + r * kHitCapN + i;
+}
 constexpr int kRowBatch = 8;         // pairs per row per batch
 constexpr int kSlots = 4 * kRowBatch;  // staged pairs per batch, slot = kRowBatch row + i
 constexpr int kYStride = kSlots + 1;   // y staging row stride (odd)
@@ -241,12 +253,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   __shared__ double s_r[kSlots], s_ir[kSlots], s_f[WITH_C ? kSlots : 1], s_gt[NL][kSlots];
   // hit rings per class (0: far, every edge of the group at u >= U_BIG;
   // 1: near) and row; an entry is (secondary index << 5) | image shift code
-  __shared__ unsigned hl[2][4][kHitCap];
+  __shared__ unsigned hl[4 * (kHitCapF + kHitCapN)];
   __shared__ int64_t nb_beg[27], nb_end[27], run_beg[27], run_end[27];
   __shared__ int nb_sh[27], run_sh[27], n_runs_s;
-  // the quad's four primaries (x, y, z per row) and each run's image offset,
-  // read per scan step from LDS rather than held in scalar registers
-  __shared__ double q_xyz[4][3], run_off[27][3];
+  // the quad's four primaries (x, y, z per row), read per scan step from LDS
+  // rather than held in scalar registers
+  __shared__ double q_xyz[4][3];
   __shared__ double2 sc_tab[FP64 ? 1 : kSinCosTabBk];
   if constexpr (!FP64) stage_sincos_tab<kSinCosTabBk>(sc_tab);
   for (int i = threadIdx.x; i < NL * kSlots; i += 64) (&s_gt[0][0])[i] = 0.0;
@@ -356,12 +368,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
             }
           }
           n_runs_s = nr;
-          for (int k = 0; k < nr; ++k) {
-            const int sh = run_sh[k];
-            run_off[k][0] = double(sh / 9 - 1) * L;
-            run_off[k][1] = double((sh / 3) % 3 - 1) * L;
-            run_off[k][2] = double(sh % 3 - 1) * L;
-          }
         }
         wave_sync();
         cur_cell = cell;
@@ -408,8 +414,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           const int slot = kRowBatch * row + col;
           double r = r_neutral, ir = ir_neutral, f = 0.0, ux = 0.0, uy = 0.0, uz = 1.0;
           if (col < my_cnt) {
-            const int idx = (my_head + col) & (kHitCap - 1);
-            const unsigned ent = hl[CL][row][idx];
+            const int idx = (my_head + col) & (hit_cap<CL>() - 1);
+            const unsigned ent = hl[ring_at<CL>(row, idx)];
             const int j = int(ent >> 5), sh = int(ent & 31u);
             const double ox = double(sh / 9 - 1) * L, oy = double((sh / 3) % 3 - 1) * L, oz = double(sh % 3 - 1) * L;
             const double dx = (px - J.sec.x[j]) - ox;
@@ -525,7 +531,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
         wave_sync();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          hh[CL][r] = (hh[CL][r] + cnt[r]) & (kHitCap - 1);
+          hh[CL][r] = (hh[CL][r] + cnt[r]) & (hit_cap<CL>() - 1);
           hn[CL][r] -= cnt[r];
         }
       };
@@ -539,11 +545,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       double cx = 0.0, cy = 0.0, cz = 0.0;
       int cj = 0;
       bool cok = false;
-      int csh = 13, crun = 0;
-      auto fetch = [&](double &x, double &y, double &z, int &j, bool &ok, int &sh, int &run) {
+      int csh = 13;
+      auto fetch = [&](double &x, double &y, double &z, int &j, bool &ok, int &sh) {
         const int64_t end = uniform_i64(run_end[ri]);
         sh = __builtin_amdgcn_readfirstlane(run_sh[ri]);
-        run = ri;
         const int64_t jj = pos + lane;
         ok = jj < end;
         j = int(jj);
@@ -558,15 +563,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           if (ri < n_runs) pos = uniform_i64(run_beg[ri]);
         }
       };
-      if (have) fetch(cx, cy, cz, cj, cok, csh, crun);
+      if (have) fetch(cx, cy, cz, cj, cok, csh);
       while (have) {
         const bool have_next = ri < n_runs;
         double nx = 0.0, ny = 0.0, nz = 0.0;
         int nj = 0;
         bool nok = false;
-        int nsh = 13, nrun = 0;
-        if (have_next) fetch(nx, ny, nz, nj, nok, nsh, nrun);
-        const double ox = run_off[crun][0], oy = run_off[crun][1], oz = run_off[crun][2];
+        int nsh = 13;
+        if (have_next) fetch(nx, ny, nz, nj, nok, nsh);
+        // the run's periodic image offset, from its shift code (uniform)
+        const double ox = double(csh / 9 - 1) * L, oy = double((csh / 3) % 3 - 1) * L, oz = double(csh % 3 - 1) * L;
         const bool self_run = J.self_set && csh == 13;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -582,10 +588,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           const unsigned long long balf = __ballot(hit && far), baln = __ballot(hit && !far);
           if (hit) {
             const unsigned long long lt = (1ull << lane) - 1ull;
-            const int cl = far ? 0 : 1;
-            const int k = (far ? hh[0][r] + hn[0][r] + __popcll(balf & lt) : hh[1][r] + hn[1][r] + __popcll(baln & lt)) &
-                          (kHitCap - 1);
-            hl[cl][r][k] = (unsigned(cj) << 5) | unsigned(csh);
+            const int k = far ? ring_at<0>(r, (hh[0][r] + hn[0][r] + __popcll(balf & lt)) & (kHitCapF - 1))
+                              : ring_at<1>(r, (hh[1][r] + hn[1][r] + __popcll(baln & lt)) & (kHitCapN - 1));
+            hl[k] = (unsigned(cj) << 5) | unsigned(csh);
           }
           hn[0][r] += __popcll(balf);
           hn[1][r] += __popcll(baln);
@@ -597,14 +602,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
         for (;;) {
           const int mn = min(min(hn[0][0], hn[0][1]), min(hn[0][2], hn[0][3]));
           const int mx = max(max(hn[0][0], hn[0][1]), max(hn[0][2], hn[0][3]));
-          if (!(mn >= kRowBatch || mx > kHitCap - 64)) break;
+          if (!(mn >= kRowBatch || mx > kHitCapF - 64)) break;
           wave_sync();
           batch(Far{});
         }
         for (;;) {
           const int mn = min(min(hn[1][0], hn[1][1]), min(hn[1][2], hn[1][3]));
           const int mx = max(max(hn[1][0], hn[1][1]), max(hn[1][2], hn[1][3]));
-          if (!(mn >= kRowBatch || mx > kHitCap - 64)) break;
+          if (!(mn >= kRowBatch || mx > kHitCapN - 64)) break;
           wave_sync();
           batch(Near{});
         }
@@ -614,7 +619,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
         cj = nj;
         cok = nok;
         csh = nsh;
-        crun = nrun;
         have = have_next;
       }
       wave_sync();
@@ -785,8 +789,9 @@ __global__ __launch_bounds__(64) void k_bk_gram(const double *__restrict__ abuf,
 }
 
 // ------------------------------------------------------------------ quads
-// Quads of a catalogue: per cell, its (selected) primaries in sorted order,
-// four at a time.
+// Quads of a catalogue: per cell, its (selected) primaries four at a time, in
+// the order `perm` gives (by neighbour count inside the cell), so that the
+// four rows of a quad carry about the same number of pairs.
 __global__ __launch_bounds__(256) void k_quad_count(const int64_t *__restrict__ cell_start,
                                                     const uint8_t *__restrict__ mask, int64_t ncells,
                                                     int64_t *__restrict__ qcount) {
@@ -802,17 +807,19 @@ __global__ __launch_bounds__(256) void k_quad_count(const int64_t *__restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_quad_fill(const int64_t *__restrict__ cell_start,
-                                                   const uint8_t *__restrict__ mask, int64_t ncells,
-                                                   const int64_t *__restrict__ qoff, BkQuad *__restrict__ quads) {
+                                                   const uint8_t *__restrict__ mask, const int *__restrict__ perm,
+                                                   int64_t ncells, const int64_t *__restrict__ qoff,
+                                                   BkQuad *__restrict__ quads) {
   const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (c >= ncells) return;
   const int64_t b = cell_start[c], e = cell_start[c + 1];
   int64_t o = qoff[c];
   BkQuad q{{-1, -1, -1, -1}};
   int k = 0;
-  for (int64_t p = b; p < e; ++p) {
+  for (int64_t i = b; i < e; ++i) {
+    const int p = perm[i];
     if (mask && !mask[p]) continue;
-    q.p[k++] = int(p);
+    q.p[k++] = p;
     if (k == 4) {
       quads[o++] = q;
       q = BkQuad{{-1, -1, -1, -1}};
@@ -892,7 +899,8 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
   if (nq == 0) return;
   BkQuad *quads = static_cast<BkQuad *>(ensure(c, c.bq_quads, size_t(nq) * sizeof(BkQuad)));
-  k_quad_fill<<<dim3(cb), dim3(256), 0, c.stream>>>(prim.cell_start, prim.m, ncells, qoff, quads);
+  const int *perm = order_by_neighbours(c, prim, sec, g, r0, self_set);
+  k_quad_fill<<<dim3(cb), dim3(256), 0, c.stream>>>(prim.cell_start, prim.m, perm, ncells, qoff, quads);
   HIPSTER_HIP(hipGetLastError());
 
   BkArgs a{};
@@ -1038,8 +1046,9 @@ static void bk_sweep_queue_nl(Ctx &c, const std::vector<BkQueueJob> &jobs, bool 
     if (nq[size_t(j)] == 0) continue;
     const int64_t ncells = J.g.ncells();
     const unsigned cb = unsigned((ncells + 255) / 256);
-    k_quad_fill<<<dim3(cb), dim3(256), 0, c.stream>>>(J.prim.cell_start, J.prim.m, ncells, qoff + cbase[size_t(j)],
-                                                      quads + qbase[size_t(j)]);
+    const int *perm = order_by_neighbours(c, J.prim, J.sec, J.g, J.r0, J.self_set);
+    k_quad_fill<<<dim3(cb), dim3(256), 0, c.stream>>>(J.prim.cell_start, J.prim.m, perm, ncells,
+                                                      qoff + cbase[size_t(j)], quads + qbase[size_t(j)]);
     HIPSTER_HIP(hipGetLastError());
   }
   // tasks of about equal expected work (pairs), some eight per wave; jobs in
@@ -1161,7 +1170,8 @@ static void bk_aniso_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
   if (nq == 0) return;
   BkQuad *quads = static_cast<BkQuad *>(ensure(c, c.bq_quads, size_t(nq) * sizeof(BkQuad)));
-  k_quad_fill<<<dim3(cb), dim3(256), 0, c.stream>>>(prim.cell_start, prim.m, ncells, qoff, quads);
+  const int *perm = order_by_neighbours(c, prim, sec, g, r0, self_set);
+  k_quad_fill<<<dim3(cb), dim3(256), 0, c.stream>>>(prim.cell_start, prim.m, perm, ncells, qoff, quads);
   HIPSTER_HIP(hipGetLastError());
   BkArgs a{};
   a.job = bk_job(prim, sec, g, r0, self_set, edges, coef, NK, npairs);

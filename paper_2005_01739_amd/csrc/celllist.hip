@@ -323,6 +323,106 @@ static Sorted build_cells_t(Ctx &c, CellScratch &s, const Grid &g, const T *pos,
   return out;
 }
 
+// Neighbour count of each selected sorted primary: the secondaries within R0
+// in the 27 cells around its home cell, tested in single precision (the
+// count only orders the primaries inside a cell, so a pair at the boundary
+// may go either way without harm).  One wave per 64 consecutive primaries:
+// the wave takes the distinct home cells of its lanes one at a time and
+// stages that cell's candidates through LDS, 64 at a time; the lanes of the
+// cell test every staged candidate.
+__global__ __launch_bounds__(64) void k_nb_count(Sorted prim, Sorted sec, int nc, double L, float r02, int self_set,
+                                                 int *__restrict__ cnt) {
+  __shared__ float4 cand[64];
+  const int lane = threadIdx.x;
+  const int64_t p = int64_t(blockIdx.x) * 64 + lane;
+  const bool valid = p < prim.n && (prim.m == nullptr || prim.m[p] != 0);
+  const int my_cell = valid ? prim.scell[p] : -1;
+  float px = 0.0f, py = 0.0f, pz = 0.0f;
+  if (valid) {
+    px = float(prim.x[p]);
+    py = float(prim.y[p]);
+    pz = float(prim.z[p]);
+  }
+  int count = 0;
+  bool done = !valid;
+  for (;;) {
+    const unsigned long long pend = __ballot(!done);
+    if (pend == 0) break;
+    const int first = __ffsll((long long)pend) - 1;
+    const int cell = __builtin_amdgcn_readfirstlane(__shfl(my_cell, first));
+    const bool mine = !done && my_cell == cell;
+    const int cz = cell % nc, cy = (cell / nc) % nc, cx = cell / (nc * nc);
+    for (int k = 0; k < 27; ++k) {
+      int nx = cx + k / 9 - 1, ny = cy + (k / 3) % 3 - 1, nz = cz + k % 3 - 1;
+      double ox = 0.0, oy = 0.0, oz = 0.0;
+      if (nx >= nc) { nx -= nc; ox = L; } else if (nx < 0) { nx += nc; ox = -L; }
+      if (ny >= nc) { ny -= nc; oy = L; } else if (ny < 0) { ny += nc; oy = -L; }
+      if (nz >= nc) { nz -= nc; oz = L; } else if (nz < 0) { nz += nc; oz = -L; }
+      const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
+      const int64_t b = sec.cell_start[nb], e = sec.cell_start[nb + 1];
+      for (int64_t j0 = b; j0 < e; j0 += 64) {
+        const int64_t j = j0 + lane;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (j < e) v = make_float4(float(sec.x[j] + ox), float(sec.y[j] + oy), float(sec.z[j] + oz), 0.0f);
+        __syncthreads();
+        cand[lane] = v;
+        __syncthreads();
+        if (mine) {
+          const int n = int(e - j0 < 64 ? e - j0 : 64);
+          for (int i = 0; i < n; ++i) {
+            const float4 q = cand[i];
+            const float dx = px - q.x, dy = py - q.y, dz = pz - q.z;
+            count += dx * dx + dy * dy + dz * dz < r02 ? 1 : 0;
+          }
+        }
+      }
+    }
+    if (mine) done = true;
+  }
+  if (valid) cnt[p] = self_set && count > 0 ? count - 1 : count;
+}
+
+// Sort key (home cell, neighbour count): selected primaries by count, the
+// others after them in their cell.
+constexpr int kNbCountBits = 20;
+__global__ __launch_bounds__(256) void k_nb_key(const int *__restrict__ scell, const uint8_t *__restrict__ m,
+                                                const int *__restrict__ cnt, int64_t n, uint64_t *__restrict__ key,
+                                                int *__restrict__ iota) {
+  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= n) return;
+  const int top = (1 << kNbCountBits) - 1;
+  int v = top;
+  if (m == nullptr || m[p] != 0) v = cnt[p] < 0 ? 0 : (cnt[p] < top - 1 ? cnt[p] : top - 1);
+  key[p] = (uint64_t(unsigned(scell[p])) << kNbCountBits) | uint64_t(unsigned(v));
+  iota[p] = int(p);
+}
+
+const int *order_by_neighbours(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0,
+                               bool self_set) {
+  const int64_t n = prim.n;
+  if (n == 0) return nullptr;
+  if (n >= (int64_t(1) << 31)) throw Error{HIPSTER_EUNSUPPORTED, "bispectrum: at most 2^31 - 1 primaries"};
+  int *cnt = static_cast<int *>(ensure(c, c.bo_cnt, size_t(n) * sizeof(int)));
+  uint64_t *key = static_cast<uint64_t *>(ensure(c, c.bo_key, size_t(n) * sizeof(uint64_t)));
+  uint64_t *key2 = static_cast<uint64_t *>(ensure(c, c.bo_key2, size_t(n) * sizeof(uint64_t)));
+  int *iota = static_cast<int *>(ensure(c, c.bo_iota, size_t(n) * sizeof(int)));
+  int *perm = static_cast<int *>(ensure(c, c.bo_perm, size_t(n) * sizeof(int)));
+  k_nb_count<<<dim3(unsigned((n + 63) / 64)), dim3(64), 0, c.stream>>>(prim, sec, g.nc, g.L, float(r0 * r0),
+                                                                       self_set ? 1 : 0, cnt);
+  HIPSTER_HIP(hipGetLastError());
+  k_nb_key<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, c.stream>>>(prim.scell, prim.m, cnt, n, key, iota);
+  HIPSTER_HIP(hipGetLastError());
+  int cbits = 1;
+  while (cbits < 40 && (int64_t(1) << cbits) < g.ncells()) ++cbits;
+  const int bits = cbits + kNbCountBits;
+  size_t tmp_bytes = 0;
+  HIPSTER_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, key, key2, iota, perm, int(n), 0, bits,
+                                                 c.stream));
+  void *tmp = ensure(c, c.bo_tmp, std::max<size_t>(tmp_bytes, 16));
+  HIPSTER_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, key2, iota, perm, int(n), 0, bits, c.stream));
+  return perm;
+}
+
 Sorted build_cells(Ctx &c, CellScratch &s, const Grid &g, const void *pos, const void *w,
                    const uint8_t *mask_dev, int64_t n, int dtype) {
   if (dtype == HIPSTER_F32)

@@ -137,6 +137,7 @@ struct Ctx {
   DevBuf bk_partial, bk_partial_r, bk_coef;
   DevBuf bq_count, bq_off, bq_scan, bq_quads, bk_abuf, bk_wbuf, bk_tiles, bk_gpart, bk_gmerged;
   DevBuf bq_jobs, bq_tasks, bq_slots, bq_counter;  // queued bispectrum sweep
+  DevBuf bo_cnt, bo_key, bo_key2, bo_iota, bo_perm, bo_tmp;  // primaries ordered by neighbour count
   DevBuf ca_q, ca_l, ca_count, ca_out, ca_tab;      // anisotropic C term
   std::vector<BkBoxScratch> bt_bk;                  // batched bispectrum, per box
   DevBuf rgen, pk_l1;
@@ -163,6 +164,14 @@ void wtilde_bins(Ctx &c, double r0, int n_k, const double *k_edges, double *out)
 // Cell list: sorts `n` points into the grid and fills `out` (device).
 Sorted build_cells(Ctx &c, CellScratch &s, const Grid &g, const void *pos, const void *w,
                    const uint8_t *mask_dev, int64_t n, int dtype);
+
+// Sorted-primary indices in cell order and, inside a cell, selected
+// primaries by their number of secondaries within R0 (the others after
+// them): the bispectrum sweep takes a cell's primaries four at a time in this
+// order, so the four have about the same number of pairs.  Device array,
+// valid until the next call on c; null when prim.n is 0.
+const int *order_by_neighbours(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0,
+                               bool self_set);
 
 // Exclusive scan of n int64 values (in-place allowed); out has n + 1 entries.
 void scan_i64(Ctx &c, const int64_t *in, int64_t *out, int64_t n, DevBuf &tmp);
