@@ -1633,7 +1633,7 @@ void hipster_destroy(hipster_ctx *ctx) {
                    &c.ct_wmax, &c.ct_jbar, &c.ct_sel, &c.rgen, &c.pk_l1, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
                    &c.th_K, &c.th_out, &c.th_wt, &c.th_pb, &c.th_bk, &c.th_T, &c.th_X, &c.pt_tab, &c.pt_consts,
                    &c.pt_T, &c.bq_jobs, &c.bq_tasks, &c.bq_slots, &c.bq_counter,
-                   &c.bo_cnt, &c.bo_key, &c.bo_key2, &c.bo_iota, &c.bo_perm, &c.bo_tmp,
+                   &c.bo_cnt, &c.bo_key, &c.bo_key2, &c.bo_iota, &c.bo_perm, &c.bo_tmp, &c.bo_f4,
                    &c.ca_q, &c.ca_l, &c.ca_count, &c.ca_out, &c.ca_tab,
                    &c.tune_scratch};
   for (DevBuf *b : all) free_buf(*b);

@@ -256,9 +256,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   __shared__ unsigned hl[4 * (kHitCapF + kHitCapN)];
   __shared__ int64_t nb_beg[27], nb_end[27], run_beg[27], run_end[27];
   __shared__ int nb_sh[27], run_sh[27], n_runs_s;
-  // the quad's four primaries (x, y, z per row), read per scan step from LDS
-  // rather than held in scalar registers
+  // the quad's four primaries (x, y, z per row, in double and single
+  // precision), read per scan step from LDS rather than held in registers
   __shared__ double q_xyz[4][3];
+  __shared__ float qf_xyz[4][4];
   __shared__ double2 sc_tab[FP64 ? 1 : kSinCosTabBk];
   if constexpr (!FP64) stage_sincos_tab<kSinCosTabBk>(sc_tab);
   for (int i = threadIdx.x; i < NL * kSlots; i += 64) (&s_gt[0][0])[i] = 0.0;
@@ -268,6 +269,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   // the job's constants; a queued launch reloads them when its task's job changes
   BkJob J = A.job;
   double ke, ke3, ike, kn3, cfb, top_w, ktop, ktop3, iktop, r_neutral, ir_neutral, L, rfar, rfar2;
+  float r2lo_f, r2hi_f, rfar2_f, L_f;
   bool top;
   auto set_job = [&]() {
     const int NK = J.n_k;
@@ -293,6 +295,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
     const double k_lo = J.edges[e0];
     rfar = k_lo > 0.0 ? HIPSTER_U_BIG / k_lo : 0.0;
     rfar2 = (FP64 || !(k_lo > 0.0)) ? __builtin_inf() : rfar * rfar * (1.0 + 1e-12);
+    // The scan tests candidates in single precision.  With every coordinate
+    // in [0, L) and image offsets of 0 or +-L, each single-precision
+    // difference is within 8 u L of the double one (u = 2^-24: the roundings
+    // of the two coordinates, the offset and the two subtractions), so r^2
+    // is within 16 sqrt(3) u L r + 192 u^2 L^2 (+ its own rounding,
+    // 4 u r^2); twice that is the band around R0^2 (and the far threshold)
+    // inside which the double-precision predicate decides.
+    {
+      const double u = 0x1p-24, r0v = sqrt(J.r02);
+      const double band = 2.0 * (16.0 * 1.7320508075688772 * u * L * r0v + 192.0 * u * u * L * L + 4.0 * u * J.r02);
+      r2lo_f = float(J.r02 - band);
+      r2hi_f = float(J.r02 + band);
+      rfar2_f = rfar2 < __builtin_inf() ? float(rfar2 + band) : __builtin_inff();
+      L_f = float(L);
+    }
   };
   set_job();
   // Without the C sums (mixed form) each lane sums its own edge's values,
@@ -377,7 +394,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       if (lane < 12) {
         const int r = lane / 3, d = lane % 3;
         const int pp = qp[r] >= 0 ? qp[r] : qp[0];
-        q_xyz[r][d] = d == 0 ? J.prim.x[pp] : (d == 1 ? J.prim.y[pp] : J.prim.z[pp]);
+        const double v = d == 0 ? J.prim.x[pp] : (d == 1 ? J.prim.y[pp] : J.prim.z[pp]);
+        q_xyz[r][d] = v;
+        qf_xyz[r][d] = float(v);
       }
       wave_sync();
       const int my_p = row == 0 ? qp[0] : row == 1 ? qp[1] : row == 2 ? qp[2] : qp[3];
@@ -455,19 +474,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           }
         }
         wave_sync();
-        if constexpr (PER_EDGE) {
-          if (top) {
-            for (int s = 0; s < cmax; ++s) {
-              const int slot = kRowBatch * row + s;
-#pragma unroll
-              for (int i = 0; i < NY; ++i) {
-                const int k = col + 16 * i;
-                if (k < NLM)
-                  tacc[i] = fma((&s_gt[0][0])[lk[i] * kSlots + slot], double(ylds[k * kYStride + slot]), tacc[i]);
-              }
-            }
-          }
-        }
         // steps: one pair per row.  Two operand sets alternate, so the next
         // step's LDS operands are read while the current step computes
         // without register copies.
@@ -509,6 +515,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           }
           // acc[l*l+m] += (w_q W y_lm)(pair) * jbar^a_l(pair)
           fmac_all<0>(acc, yr, gl);
+          if constexpr (PER_EDGE) {
+            // the top edge of a full group: harmonic k = col + 16 i of this
+            // row's pair (yr[i]) times its staged value.  Lanes past the last
+            // harmonic sum a value no broadcast reads; without a full group
+            // the sum is unused (its bin factor is zero) and s_gt is finite.
+#pragma unroll
+            for (int i = 0; i < NY; ++i) tacc[i] = fma((&s_gt[0][0])[lk[i] * kSlots + slot], yr[i], tacc[i]);
+          }
           if constexpr (WITH_C) {
             const double fq = s_f[slot] * cfb;
 #pragma unroll
@@ -538,52 +552,57 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       using Far = std::integral_constant<int, 0>;
       using Near = std::integral_constant<int, 1>;
 
-      // scan: runs of candidates, 64 at a time, the next step's loads in flight
+      // scan: runs of candidates, 64 at a time.  The next chunk's load is
+      // issued after the current chunk's tests, so that it is in flight during
+      // the batches (a wait for the current chunk would otherwise also wait
+      // for it: loads complete in order)
       int ri = 0;
       int64_t pos = n_runs > 0 ? uniform_i64(run_beg[0]) : 0;
       bool have = n_runs > 0;
-      double cx = 0.0, cy = 0.0, cz = 0.0;
+      float4 cv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       int cj = 0;
       bool cok = false;
       int csh = 13;
-      auto fetch = [&](double &x, double &y, double &z, int &j, bool &ok, int &sh) {
+      auto fetch = [&](float4 &v, int &j, bool &ok, int &sh) {
         const int64_t end = uniform_i64(run_end[ri]);
         sh = __builtin_amdgcn_readfirstlane(run_sh[ri]);
         const int64_t jj = pos + lane;
         ok = jj < end;
         j = int(jj);
-        if (ok) {
-          x = J.sec.x[jj];
-          y = J.sec.y[jj];
-          z = J.sec.z[jj];
-        }
+        if (ok) v = J.sec.f4[jj];
         pos += 64;
         if (pos >= end) {
           ++ri;
           if (ri < n_runs) pos = uniform_i64(run_beg[ri]);
         }
       };
-      if (have) fetch(cx, cy, cz, cj, cok, csh);
+      if (have) fetch(cv, cj, cok, csh);
       while (have) {
         const bool have_next = ri < n_runs;
-        double nx = 0.0, ny = 0.0, nz = 0.0;
-        int nj = 0;
-        bool nok = false;
-        int nsh = 13;
-        if (have_next) fetch(nx, ny, nz, nj, nok, nsh);
         // the run's periodic image offset, from its shift code (uniform)
-        const double ox = double(csh / 9 - 1) * L, oy = double((csh / 3) % 3 - 1) * L, oz = double(csh % 3 - 1) * L;
+        const int sx = csh / 9 - 1, sy = (csh / 3) % 3 - 1, sz = csh % 3 - 1;
+        const float oxf = float(sx) * L_f, oyf = float(sy) * L_f, ozf = float(sz) * L_f;
         const bool self_run = J.self_set && csh == 13;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           bool hit = false, far = false;
           if (cok && qp[r] >= 0) {
-            const double dx = (q_xyz[r][0] - cx) - ox;
-            const double dy = (q_xyz[r][1] - cy) - oy;
-            const double dz = (q_xyz[r][2] - cz) - oz;
-            const double r2 = bk_sq_norm(dx, dy, dz);
-            hit = r2 < J.r02 && !(self_run && cj == qp[r]);
-            far = r2 >= rfar2;
+            const float dx = (qf_xyz[r][0] - cv.x) - oxf;
+            const float dy = (qf_xyz[r][1] - cv.y) - oyf;
+            const float dz = (qf_xyz[r][2] - cv.z) - ozf;
+            const float r2f = dx * dx + dy * dy + dz * dz;
+            hit = r2f < r2lo_f;
+            far = r2f >= rfar2_f;
+            if (r2f >= r2lo_f && r2f < r2hi_f) {
+              // inside the band: the double-precision predicate (the oracle's)
+              const double ddx = (q_xyz[r][0] - J.sec.x[cj]) - double(sx) * L;
+              const double ddy = (q_xyz[r][1] - J.sec.y[cj]) - double(sy) * L;
+              const double ddz = (q_xyz[r][2] - J.sec.z[cj]) - double(sz) * L;
+              const double r2 = bk_sq_norm(ddx, ddy, ddz);
+              hit = r2 < J.r02;
+              far = r2 >= rfar2;
+            }
+            hit = hit && !(self_run && cj == qp[r]);
           }
           const unsigned long long balf = __ballot(hit && far), baln = __ballot(hit && !far);
           if (hit) {
@@ -596,6 +615,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           hn[1][r] += __popcll(baln);
           pcount += unsigned(__popcll(balf) + __popcll(baln));
         }
+        float4 nv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        int nj = 0;
+        bool nok = false;
+        int nsh = 13;
+        if (have_next) fetch(nv, nj, nok, nsh);
         // a batch of a class when every row has a full batch of it, or before a
         // row could overflow in the next step (each step adds at most 64 hits
         // per row and class)
@@ -613,9 +637,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           wave_sync();
           batch(Near{});
         }
-        cx = nx;
-        cy = ny;
-        cz = nz;
+        cv = nv;
         cj = nj;
         cok = nok;
         csh = nsh;
@@ -905,6 +927,8 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
 
   BkArgs a{};
   a.job = bk_job(prim, sec, g, r0, self_set, edges, coef, NK, npairs);
+  a.job.sec.f4 = static_cast<float4 *>(ensure(c, c.bo_f4, size_t(std::max<int64_t>(1, sec.n)) * sizeof(float4)));
+  single_xyz(c, sec, const_cast<float4 *>(a.job.sec.f4));
   a.quads = quads;
   a.rowlen = bk_rowlen(NL, groups);
   a.ld = 16 * groups;
@@ -1075,9 +1099,16 @@ static void bk_sweep_queue_nl(Ctx &c, const std::vector<BkQueueJob> &jobs, bool 
     tcount[size_t(j)] = int(tasks.size()) - tfirst[size_t(j)];
   }
   std::vector<BkJob> hj(static_cast<size_t>(nj));
+  int64_t nsec = 1;
+  for (int j = 0; j < nj; ++j) nsec += jobs[size_t(j)].sec.n;
+  float4 *f4 = static_cast<float4 *>(ensure(c, c.bo_f4, size_t(nsec) * sizeof(float4)));
+  int64_t off = 0;
   for (int j = 0; j < nj; ++j) {
     const BkQueueJob &J = jobs[size_t(j)];
     hj[size_t(j)] = bk_job(J.prim, J.sec, J.g, J.r0, J.self_set, J.edges, J.coef, J.NK, J.npairs);
+    hj[size_t(j)].sec.f4 = f4 + off;
+    single_xyz(c, J.sec, f4 + off);
+    off += J.sec.n;
   }
   const int rowlen = bk_rowlen(NL, 1);
   BkJob *djobs = static_cast<BkJob *>(ensure(c, c.bq_jobs, hj.size() * sizeof(BkJob)));
@@ -1175,6 +1206,8 @@ static void bk_aniso_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   HIPSTER_HIP(hipGetLastError());
   BkArgs a{};
   a.job = bk_job(prim, sec, g, r0, self_set, edges, coef, NK, npairs);
+  a.job.sec.f4 = static_cast<float4 *>(ensure(c, c.bo_f4, size_t(std::max<int64_t>(1, sec.n)) * sizeof(float4)));
+  single_xyz(c, sec, const_cast<float4 *>(a.job.sec.f4));
   a.quads = quads;
   a.q_lo = 0;
   a.q_hi = nq;
