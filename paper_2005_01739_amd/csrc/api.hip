@@ -808,12 +808,10 @@ static int bk_jobs(const BkBox &x, std::vector<BkQueueJob> &out) {
 static void bk_sweeps(Ctx &c, Timer &tm, BkBox &x) {
   for (int set = 0; set < (x.have_r ? 2 : 1); ++set) {
     const Sorted &prim = set == 0 ? x.sd : x.sr;
-    hipEvent_t b1 = tm.mark();
     bk_sweep(c, prim, x.sd, x.g, x.q->r0, set == 0, x.edges, x.coef, x.q->n_k, x.q->ell_max, x.fp64, !x.c_hist,
              x.cnt + set, x.sums[set]);
-    hipEvent_t b2 = tm.mark();
-    if (b2) HIPSTER_HIP(hipEventSynchronize(b2));
-    x.ms_sweep += Timer::ms(b1, b2);
+    // the sweep kernels alone (the quads and their order are built before)
+    x.ms_sweep += x.sums[set].ms_kernel;
     x.launches += x.sums[set].launches;
   }
 }
@@ -1073,11 +1071,10 @@ static void run_bk_aniso(Ctx &c, const hipster_points *dp, const hipster_points 
       }
   const int NC = int(cl1.size());
   std::vector<double> G[2], T[2], C[2];
-  hipEvent_t s0 = tm.mark();
+  double ms_sw = 0.0;
   for (int set = 0; set < 2; ++set)
     bk_aniso_sweep(c, set == 0 ? x.sd : x.sr, x.sd, x.g, q->r0, set == 0, x.edges, x.coef, NK, q->ell_max,
-                   x.cnt + set, G[set], T[set]);
-  hipEvent_t s1 = tm.mark();
+                   x.cnt + set, G[set], T[set], ms_sw);
   unsigned long long n_ord[2] = {0, 0};
   HIPSTER_HIP(hipMemcpyAsync(n_ord, x.cnt, 16, hipMemcpyDeviceToHost, c.stream));
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
@@ -1125,7 +1122,7 @@ static void run_bk_aniso(Ctx &c, const hipster_points *dp, const hipster_points 
     diag->n_rand = uint64_t(x.rp->n);
     diag->ms_build = Timer::ms(x.ev_b0, x.ev_b1);
     diag->ms_pairs = 0.0;
-    diag->ms_sweep = Timer::ms(s0, s1);
+    diag->ms_sweep = ms_sw;
     diag->ms_cterm = Timer::ms(c0, c1);
     diag->ms_total = Timer::ms(t0, c1);
     diag->sweep_launches = 2;
@@ -1633,7 +1630,7 @@ void hipster_destroy(hipster_ctx *ctx) {
                    &c.ct_wmax, &c.ct_jbar, &c.ct_sel, &c.rgen, &c.pk_l1, &c.th_r, &c.th_w, &c.th_p, &c.th_wp, &c.th_pk, &c.th_ek, &c.th_g, &c.th_J, &c.th_om,
                    &c.th_K, &c.th_out, &c.th_wt, &c.th_pb, &c.th_bk, &c.th_T, &c.th_X, &c.pt_tab, &c.pt_consts,
                    &c.pt_T, &c.bq_jobs, &c.bq_tasks, &c.bq_slots, &c.bq_counter,
-                   &c.bo_cnt, &c.bo_key, &c.bo_key2, &c.bo_iota, &c.bo_perm, &c.bo_tmp, &c.bo_f4,
+                   &c.bo_cnt, &c.bo_key, &c.bo_key2, &c.bo_iota, &c.bo_perm, &c.bo_tmp,
                    &c.ca_q, &c.ca_l, &c.ca_count, &c.ca_out, &c.ca_tab,
                    &c.tune_scratch};
   for (DevBuf *b : all) free_buf(*b);

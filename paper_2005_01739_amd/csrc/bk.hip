@@ -256,10 +256,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   __shared__ unsigned hl[4 * (kHitCapF + kHitCapN)];
   __shared__ int64_t nb_beg[27], nb_end[27], run_beg[27], run_end[27];
   __shared__ int nb_sh[27], run_sh[27], n_runs_s;
-  // the quad's four primaries (x, y, z per row, in double and single
-  // precision), read per scan step from LDS rather than held in registers
+  // the quad's four primaries (x, y, z per row), read per scan step from LDS
+  // rather than held in scalar registers
   __shared__ double q_xyz[4][3];
-  __shared__ float qf_xyz[4][4];
   __shared__ double2 sc_tab[FP64 ? 1 : kSinCosTabBk];
   if constexpr (!FP64) stage_sincos_tab<kSinCosTabBk>(sc_tab);
   for (int i = threadIdx.x; i < NL * kSlots; i += 64) (&s_gt[0][0])[i] = 0.0;
@@ -269,7 +268,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   // the job's constants; a queued launch reloads them when its task's job changes
   BkJob J = A.job;
   double ke, ke3, ike, kn3, cfb, top_w, ktop, ktop3, iktop, r_neutral, ir_neutral, L, rfar, rfar2;
-  float r2lo_f, r2hi_f, rfar2_f, L_f;
   bool top;
   auto set_job = [&]() {
     const int NK = J.n_k;
@@ -295,21 +293,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
     const double k_lo = J.edges[e0];
     rfar = k_lo > 0.0 ? HIPSTER_U_BIG / k_lo : 0.0;
     rfar2 = (FP64 || !(k_lo > 0.0)) ? __builtin_inf() : rfar * rfar * (1.0 + 1e-12);
-    // The scan tests candidates in single precision.  With every coordinate
-    // in [0, L) and image offsets of 0 or +-L, each single-precision
-    // difference is within 8 u L of the double one (u = 2^-24: the roundings
-    // of the two coordinates, the offset and the two subtractions), so r^2
-    // is within 16 sqrt(3) u L r + 192 u^2 L^2 (+ its own rounding,
-    // 4 u r^2); twice that is the band around R0^2 (and the far threshold)
-    // inside which the double-precision predicate decides.
-    {
-      const double u = 0x1p-24, r0v = sqrt(J.r02);
-      const double band = 2.0 * (16.0 * 1.7320508075688772 * u * L * r0v + 192.0 * u * u * L * L + 4.0 * u * J.r02);
-      r2lo_f = float(J.r02 - band);
-      r2hi_f = float(J.r02 + band);
-      rfar2_f = rfar2 < __builtin_inf() ? float(rfar2 + band) : __builtin_inff();
-      L_f = float(L);
-    }
   };
   set_job();
   // Without the C sums (mixed form) each lane sums its own edge's values,
@@ -394,9 +377,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       if (lane < 12) {
         const int r = lane / 3, d = lane % 3;
         const int pp = qp[r] >= 0 ? qp[r] : qp[0];
-        const double v = d == 0 ? J.prim.x[pp] : (d == 1 ? J.prim.y[pp] : J.prim.z[pp]);
-        q_xyz[r][d] = v;
-        qf_xyz[r][d] = float(v);
+        q_xyz[r][d] = d == 0 ? J.prim.x[pp] : (d == 1 ? J.prim.y[pp] : J.prim.z[pp]);
       }
       wave_sync();
       const int my_p = row == 0 ? qp[0] : row == 1 ? qp[1] : row == 2 ? qp[2] : qp[3];
@@ -559,50 +540,43 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       int ri = 0;
       int64_t pos = n_runs > 0 ? uniform_i64(run_beg[0]) : 0;
       bool have = n_runs > 0;
-      float4 cv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      double cx = 0.0, cy = 0.0, cz = 0.0;
       int cj = 0;
       bool cok = false;
       int csh = 13;
-      auto fetch = [&](float4 &v, int &j, bool &ok, int &sh) {
+      auto fetch = [&](double &x, double &y, double &z, int &j, bool &ok, int &sh) {
         const int64_t end = uniform_i64(run_end[ri]);
         sh = __builtin_amdgcn_readfirstlane(run_sh[ri]);
         const int64_t jj = pos + lane;
         ok = jj < end;
         j = int(jj);
-        if (ok) v = J.sec.f4[jj];
+        if (ok) {
+          x = J.sec.x[jj];
+          y = J.sec.y[jj];
+          z = J.sec.z[jj];
+        }
         pos += 64;
         if (pos >= end) {
           ++ri;
           if (ri < n_runs) pos = uniform_i64(run_beg[ri]);
         }
       };
-      if (have) fetch(cv, cj, cok, csh);
+      if (have) fetch(cx, cy, cz, cj, cok, csh);
       while (have) {
         const bool have_next = ri < n_runs;
         // the run's periodic image offset, from its shift code (uniform)
-        const int sx = csh / 9 - 1, sy = (csh / 3) % 3 - 1, sz = csh % 3 - 1;
-        const float oxf = float(sx) * L_f, oyf = float(sy) * L_f, ozf = float(sz) * L_f;
+        const double ox = double(csh / 9 - 1) * L, oy = double((csh / 3) % 3 - 1) * L, oz = double(csh % 3 - 1) * L;
         const bool self_run = J.self_set && csh == 13;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           bool hit = false, far = false;
           if (cok && qp[r] >= 0) {
-            const float dx = (qf_xyz[r][0] - cv.x) - oxf;
-            const float dy = (qf_xyz[r][1] - cv.y) - oyf;
-            const float dz = (qf_xyz[r][2] - cv.z) - ozf;
-            const float r2f = dx * dx + dy * dy + dz * dz;
-            hit = r2f < r2lo_f;
-            far = r2f >= rfar2_f;
-            if (r2f >= r2lo_f && r2f < r2hi_f) {
-              // inside the band: the double-precision predicate (the oracle's)
-              const double ddx = (q_xyz[r][0] - J.sec.x[cj]) - double(sx) * L;
-              const double ddy = (q_xyz[r][1] - J.sec.y[cj]) - double(sy) * L;
-              const double ddz = (q_xyz[r][2] - J.sec.z[cj]) - double(sz) * L;
-              const double r2 = bk_sq_norm(ddx, ddy, ddz);
-              hit = r2 < J.r02;
-              far = r2 >= rfar2;
-            }
-            hit = hit && !(self_run && cj == qp[r]);
+            const double dx = (q_xyz[r][0] - cx) - ox;
+            const double dy = (q_xyz[r][1] - cy) - oy;
+            const double dz = (q_xyz[r][2] - cz) - oz;
+            const double r2 = bk_sq_norm(dx, dy, dz);
+            hit = r2 < J.r02 && !(self_run && cj == qp[r]);
+            far = r2 >= rfar2;
           }
           const unsigned long long balf = __ballot(hit && far), baln = __ballot(hit && !far);
           if (hit) {
@@ -615,11 +589,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           hn[1][r] += __popcll(baln);
           pcount += unsigned(__popcll(balf) + __popcll(baln));
         }
-        float4 nv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        double nx = 0.0, ny = 0.0, nz = 0.0;
         int nj = 0;
         bool nok = false;
         int nsh = 13;
-        if (have_next) fetch(nv, nj, nok, nsh);
+        if (have_next) fetch(nx, ny, nz, nj, nok, nsh);
         // a batch of a class when every row has a full batch of it, or before a
         // row could overflow in the next step (each step adds at most 64 hits
         // per row and class)
@@ -637,7 +611,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           wave_sync();
           batch(Near{});
         }
-        cv = nv;
+        cx = nx;
+        cy = ny;
+        cz = nz;
         cj = nj;
         cok = nok;
         csh = nsh;
@@ -852,6 +828,33 @@ __global__ __launch_bounds__(256) void k_quad_fill(const int64_t *__restrict__ c
 }
 
 // ------------------------------------------------------------------- host
+// Elapsed time of the sweep launches alone, from two HIP events on the stream
+// (read after the stream has been synchronised; 0 if an event is missing).
+struct LaunchClock {
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  explicit LaunchClock(Ctx &c) : s(c.stream) {
+    if (hipEventCreate(&a) != hipSuccess) a = nullptr;
+    if (hipEventCreate(&b) != hipSuccess) b = nullptr;
+  }
+  void start() {
+    if (a) HIPSTER_HIP(hipEventRecord(a, s));
+  }
+  void stop() {
+    if (b) HIPSTER_HIP(hipEventRecord(b, s));
+  }
+  double ms() const {
+    float t = 0.0f;
+    return a && b && hipEventElapsedTime(&t, a, b) == hipSuccess ? double(t) : 0.0;
+  }
+  ~LaunchClock() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  LaunchClock(const LaunchClock &) = delete;
+  LaunchClock &operator=(const LaunchClock &) = delete;
+};
+
 template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE = false>
 static void launch_quad(Ctx &c, const BkArgs &a, int nwaves) {
   const size_t lds = bk_lds_bytes<NL, FP64>();
@@ -927,8 +930,6 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
 
   BkArgs a{};
   a.job = bk_job(prim, sec, g, r0, self_set, edges, coef, NK, npairs);
-  a.job.sec.f4 = static_cast<float4 *>(ensure(c, c.bo_f4, size_t(std::max<int64_t>(1, sec.n)) * sizeof(float4)));
-  single_xyz(c, sec, const_cast<float4 *>(a.job.sec.f4));
   a.quads = quads;
   a.rowlen = bk_rowlen(NL, groups);
   a.ld = 16 * groups;
@@ -941,13 +942,17 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
     a.q_lo = 0;
     a.q_hi = nq;
     a.group = 0;
+    LaunchClock clk(c);
+    clk.start();
     if (fp64) launch_quad<NL, true, true, true>(c, a, nwaves);
     else launch_quad<NL, false, false, true>(c, a, nwaves);
+    clk.stop();
     double *merged = static_cast<double *>(ensure(c, c.merged, size_t(a.rowlen) * 8));
     merge_partials(c, part, nwaves, a.rowlen, merged);
     std::vector<double> M(size_t(a.rowlen));
     HIPSTER_HIP(hipMemcpyAsync(M.data(), merged, size_t(a.rowlen) * 8, hipMemcpyDeviceToHost, c.stream));
     HIPSTER_HIP(hipStreamSynchronize(c.stream));
+    out.ms_kernel = clk.ms();
     // tiles are 16 x 16 per l; the Gram sums are symmetric up to rounding, so
     // the upper triangle is mirrored to make the output exactly symmetric
     for (int l = 0; l < NL; ++l)
@@ -990,6 +995,8 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   double *gpart = static_cast<double *>(ensure(c, c.bk_gpart, size_t(nchunks) * ntiles * 256 * 8));
   HIPSTER_HIP(hipMemsetAsync(gpart, 0, size_t(nchunks) * ntiles * 256 * 8, c.stream));
   uint64_t launches = 0;
+  LaunchClock clk(c);
+  clk.start();
   for (int64_t q0 = 0; q0 < nq; q0 += qchunk) {
     a.q_lo = q0;
     a.q_hi = std::min(nq, q0 + qchunk);
@@ -1002,6 +1009,7 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
                                                                            ld, tiles, ntiles, nchunks, gpart);
     HIPSTER_HIP(hipGetLastError());
   }
+  clk.stop();
   double *merged = static_cast<double *>(ensure(c, c.merged, size_t(std::max(a.rowlen, ntiles * 256)) * 8));
   double *gmerged = static_cast<double *>(ensure(c, c.bk_gmerged, size_t(ntiles) * 256 * 8));
   merge_partials(c, part, nwaves, a.rowlen, merged);
@@ -1010,6 +1018,7 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   HIPSTER_HIP(hipMemcpyAsync(M.data(), merged, size_t(a.rowlen) * 8, hipMemcpyDeviceToHost, c.stream));
   HIPSTER_HIP(hipMemcpyAsync(GM.data(), gmerged, GM.size() * 8, hipMemcpyDeviceToHost, c.stream));
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  out.ms_kernel = clk.ms();
   std::vector<int> tindex(size_t(NL) * groups * groups, -1);
   for (int t = 0; t < ntiles; ++t) tindex[(size_t(tl[t].l) * groups + tl[t].ga) * groups + tl[t].gb] = t;
   for (int l = 0; l < NL; ++l)
@@ -1099,16 +1108,9 @@ static void bk_sweep_queue_nl(Ctx &c, const std::vector<BkQueueJob> &jobs, bool 
     tcount[size_t(j)] = int(tasks.size()) - tfirst[size_t(j)];
   }
   std::vector<BkJob> hj(static_cast<size_t>(nj));
-  int64_t nsec = 1;
-  for (int j = 0; j < nj; ++j) nsec += jobs[size_t(j)].sec.n;
-  float4 *f4 = static_cast<float4 *>(ensure(c, c.bo_f4, size_t(nsec) * sizeof(float4)));
-  int64_t off = 0;
   for (int j = 0; j < nj; ++j) {
     const BkQueueJob &J = jobs[size_t(j)];
     hj[size_t(j)] = bk_job(J.prim, J.sec, J.g, J.r0, J.self_set, J.edges, J.coef, J.NK, J.npairs);
-    hj[size_t(j)].sec.f4 = f4 + off;
-    single_xyz(c, J.sec, f4 + off);
-    off += J.sec.n;
   }
   const int rowlen = bk_rowlen(NL, 1);
   BkJob *djobs = static_cast<BkJob *>(ensure(c, c.bq_jobs, hj.size() * sizeof(BkJob)));
@@ -1181,7 +1183,7 @@ void bk_sweep_queue(Ctx &c, const std::vector<BkQueueJob> &jobs, int ell_max, bo
 template <int NL>
 static void bk_aniso_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
                         const double *edges, const double *coef, int NK, unsigned long long *npairs,
-                        std::vector<double> &G, std::vector<double> &T) {
+                        std::vector<double> &G, std::vector<double> &T, double &ms_kernel) {
   constexpr int NC = aniso_count(NL);
   if (NK < 1 || NK > 16) throw Error{HIPSTER_EUNSUPPORTED, "anisotropic bispectrum: n_k must lie in [1, 16]"};
   if (sec.n >= (int64_t(1) << 27))
@@ -1206,8 +1208,6 @@ static void bk_aniso_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   HIPSTER_HIP(hipGetLastError());
   BkArgs a{};
   a.job = bk_job(prim, sec, g, r0, self_set, edges, coef, NK, npairs);
-  a.job.sec.f4 = static_cast<float4 *>(ensure(c, c.bo_f4, size_t(std::max<int64_t>(1, sec.n)) * sizeof(float4)));
-  single_xyz(c, sec, const_cast<float4 *>(a.job.sec.f4));
   a.quads = quads;
   a.q_lo = 0;
   a.q_hi = nq;
@@ -1228,13 +1228,17 @@ static void bk_aniso_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   double *part = static_cast<double *>(ensure(c, c.bk_partial, size_t(nwaves) * a.rowlen * 8));
   HIPSTER_HIP(hipMemsetAsync(part, 0, size_t(nwaves) * a.rowlen * 8, c.stream));
   a.partial = part;
+  LaunchClock clk(c);
+  clk.start();
   k_bk_quad<NL, false, false, true, false, true><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(a);
   HIPSTER_HIP(hipGetLastError());
+  clk.stop();
   double *merged = static_cast<double *>(ensure(c, c.merged, size_t(a.rowlen) * 8));
   merge_partials(c, part, nwaves, a.rowlen, merged);
   std::vector<double> M(size_t(a.rowlen));
   HIPSTER_HIP(hipMemcpyAsync(M.data(), merged, size_t(a.rowlen) * 8, hipMemcpyDeviceToHost, c.stream));
   HIPSTER_HIP(hipStreamSynchronize(c.stream));
+  ms_kernel += clk.ms();
   // tile c: D[a][b] = sum_p w_p sum_mu A^a_{l1 mu} A^b_{l2 mu} at c 256 + 16 a + b
   for (int ci = 0; ci < NC; ++ci)
     for (int x = 0; x < NK; ++x)
@@ -1249,13 +1253,13 @@ static void bk_aniso_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
 
 void bk_aniso_sweep(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
                     const double *edges, const double *coef, int NK, int ell_max, unsigned long long *npairs,
-                    std::vector<double> &G, std::vector<double> &T) {
+                    std::vector<double> &G, std::vector<double> &T, double &ms_kernel) {
   switch (ell_max) {
-    case 0: bk_aniso_nl<1>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T); break;
-    case 1: bk_aniso_nl<2>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T); break;
-    case 2: bk_aniso_nl<3>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T); break;
-    case 3: bk_aniso_nl<4>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T); break;
-    case 4: bk_aniso_nl<5>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T); break;
+    case 0: bk_aniso_nl<1>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T, ms_kernel); break;
+    case 1: bk_aniso_nl<2>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T, ms_kernel); break;
+    case 2: bk_aniso_nl<3>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T, ms_kernel); break;
+    case 3: bk_aniso_nl<4>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T, ms_kernel); break;
+    case 4: bk_aniso_nl<5>(c, prim, sec, g, r0, self_set, edges, coef, NK, npairs, G, T, ms_kernel); break;
     default: throw Error{HIPSTER_EUNSUPPORTED, "anisotropic bispectrum: ell_max must lie in [0, 4]"};
   }
 }

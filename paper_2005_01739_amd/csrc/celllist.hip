@@ -382,19 +382,6 @@ __global__ __launch_bounds__(64) void k_nb_count(Sorted prim, Sorted sec, int nc
   if (valid) cnt[p] = self_set && count > 0 ? count - 1 : count;
 }
 
-// Single-precision (x, y, z, 0) of a sorted catalogue.
-__global__ __launch_bounds__(256) void k_single_xyz(const double *__restrict__ x, const double *__restrict__ y,
-                                                    const double *__restrict__ z, int64_t n, float4 *__restrict__ out) {
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i < n) out[i] = make_float4(float(x[i]), float(y[i]), float(z[i]), 0.0f);
-}
-
-void single_xyz(Ctx &c, const Sorted &s, float4 *out) {
-  if (s.n == 0) return;
-  k_single_xyz<<<dim3(unsigned((s.n + 255) / 256)), dim3(256), 0, c.stream>>>(s.x, s.y, s.z, s.n, out);
-  HIPSTER_HIP(hipGetLastError());
-}
-
 // Sort key (home cell, neighbour count): selected primaries by count, the
 // others after them in their cell.
 constexpr int kNbCountBits = 20;

@@ -72,7 +72,6 @@ struct Sorted {
   const uint8_t *m = nullptr;      // primary mask per sorted particle (may be null)
   const int64_t *cell_start = nullptr; // [ncells + 1]
   const int *scell = nullptr;          // cell of each sorted point
-  const float4 *f4 = nullptr;          // (x, y, z, 0) in single precision, where a sweep needs it
 };
 
 
@@ -139,7 +138,6 @@ struct Ctx {
   DevBuf bq_count, bq_off, bq_scan, bq_quads, bk_abuf, bk_wbuf, bk_tiles, bk_gpart, bk_gmerged;
   DevBuf bq_jobs, bq_tasks, bq_slots, bq_counter;  // queued bispectrum sweep
   DevBuf bo_cnt, bo_key, bo_key2, bo_iota, bo_perm, bo_tmp;  // primaries ordered by neighbour count
-  DevBuf bo_f4;  // secondaries in single precision for the bispectrum scan
   DevBuf ca_q, ca_l, ca_count, ca_out, ca_tab;      // anisotropic C term
   std::vector<BkBoxScratch> bt_bk;                  // batched bispectrum, per box
   DevBuf rgen, pk_l1;
@@ -174,10 +172,6 @@ Sorted build_cells(Ctx &c, CellScratch &s, const Grid &g, const void *pos, const
 // valid until the next call on c; null when prim.n is 0.
 const int *order_by_neighbours(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0,
                                bool self_set);
-
-// out[i] = (x, y, z, 0) of sorted point i in single precision (device; out
-// holds s.n entries).
-void single_xyz(Ctx &c, const Sorted &s, float4 *out);
 
 // Exclusive scan of n int64 values (in-place allowed); out has n + 1 entries.
 void scan_i64(Ctx &c, const int64_t *in, int64_t *out, int64_t n, DevBuf &tmp);
@@ -241,6 +235,7 @@ struct BkSums {
   int NL = 0, NK = 0;
   std::vector<double> G, C, S0;
   uint64_t launches = 0;
+  double ms_kernel = 0.0;  // the sweep launches alone (HIP events)
 };
 void bk_sweep(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
               const double *edges, const double *coef, int NK, int ell_max, bool fp64, bool with_c,
@@ -273,7 +268,7 @@ void bk_sweep_queue(Ctx &c, const std::vector<BkQueueJob> &jobs, int ell_max, bo
 // (real orthonormal harmonics about z).
 void bk_aniso_sweep(Ctx &c, const Sorted &prim, const Sorted &sec, const Grid &g, double r0, bool self_set,
                     const double *edges, const double *coef, int NK, int ell_max, unsigned long long *npairs,
-                    std::vector<double> &G, std::vector<double> &T);
+                    std::vector<double> &G, std::vector<double> &T, double &ms_kernel);
 
 // n uniform points in [0, L)^3 (device, [n][3] doubles), point i from block
 // i + 1 of the Philox4x64-10 generator keyed by (seed, 0): x_d = L (word_d >> 11)
