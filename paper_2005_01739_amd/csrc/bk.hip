@@ -42,38 +42,47 @@
 
 namespace hipster {
 
-// Real orthonormal spherical harmonics y_lm of a unit vector, index l*l+l+m:
-// y_l0 = N_l0 Q_l^0(z), y_lm = N_lm Q_l^m(z) Re (x+iy)^m, y_l-m = N_lm Q_l^m(z) Im (x+iy)^m,
-// with Q_l^m = d^m P_l / dz^m by its three-term recurrence.
+// f times the real orthonormal spherical harmonics y_lm of a unit vector,
+// index l*l+l+m: y_l0 = N_l0 Q_l^0(z), y_lm = N_lm Q_l^m(z) Re (x+iy)^m,
+// y_l-m = N_lm Q_l^m(z) Im (x+iy)^m, with Q_l^m = d^m P_l / dz^m.  The factor f
+// seeds the powers of (x+iy), and p_l = N_lm Q_l^m runs the three-term
+// recurrence of Q_l^m with the normalisation ratios folded into its
+// (compile-time) coefficients.
 template <int LM, typename Out>
-__device__ inline void real_ylm(double x, double y, double z, Out Y) {
+__device__ inline void real_ylm(double x, double y, double z, double f, Out Y) {
   double C[LM + 1], S[LM + 1];
-  C[0] = 1.0;
+  C[0] = f;
   S[0] = 0.0;
 #pragma unroll
   for (int m = 1; m <= LM; ++m) {
     C[m] = C[m - 1] * x - S[m - 1] * y;
     S[m] = S[m - 1] * x + C[m - 1] * y;
   }
-  double qmm = 1.0;
+  double dfact = 1.0;  // (2m - 1)!!
 #pragma unroll
   for (int m = 0; m <= LM; ++m) {
-    if (m > 0) qmm *= double(2 * m - 1);
-    double q2 = 0.0, q1 = 0.0;
+    if (m > 0) dfact *= double(2 * m - 1);
+    double p2 = 0.0, p1 = 0.0;
 #pragma unroll
     for (int l = m; l <= LM; ++l) {
-      double q;
-      if (l == m) q = qmm;
-      else if (l == m + 1) q = z * double(2 * m + 1) * qmm;
-      else q = (double(2 * l - 1) * z * q1 - double(l + m - 1) * q2) * (1.0 / double(l - m));
-      q2 = q1;
-      q1 = q;
-      const double nq = YLM_NORM[l][m] * q;
-      if (m == 0) {
-        Y[l * l + l] = nq;
+      double p;
+      if (l == m) {
+        p = YLM_NORM[l][m] * dfact;
+      } else if (l == m + 1) {
+        p = (YLM_NORM[l][m] * double(2 * m + 1) * dfact) * z;
       } else {
-        Y[l * l + l + m] = nq * C[m];
-        Y[l * l + l - m] = nq * S[m];
+        // Q_l = [(2l-1) z Q_{l-1} - (l+m-1) Q_{l-2}] / (l-m), in terms of p
+        const double a = double(2 * l - 1) / double(l - m) * (YLM_NORM[l][m] / YLM_NORM[l - 1][m]);
+        const double b = double(l + m - 1) / double(l - m) * (YLM_NORM[l][m] / YLM_NORM[l - 2][m]);
+        p = fma(a * z, p1, -b * p2);
+      }
+      p2 = p1;
+      p1 = p;
+      if (m == 0) {
+        Y[l * l + l] = p * f;
+      } else {
+        Y[l * l + l + m] = p * C[m];
+        Y[l * l + l - m] = p * S[m];
       }
     }
   }
@@ -138,17 +147,15 @@ constexpr int kYStride = kSlots + 1;   // y staging row stride (odd)
 constexpr int kSinCosTabBk = 256;    // sine/cosine table entries (LDS)
 
 // Writes w_q W y_lm of one slot into the y staging as real_ylm produces it:
-// element idx goes to base[idx * kYStride], scaled by f.
+// element idx goes to base[idx * kYStride].
 template <typename YT>
 struct YStore {
   YT *base;
-  double f;
   struct Ref {
     YT *p;
-    double f;
-    __device__ void operator=(double v) const { *p = YT(f * v); }
+    __device__ void operator=(double v) const { *p = YT(v); }
   };
-  __device__ Ref operator[](int idx) const { return Ref{base + idx * kYStride, f}; }
+  __device__ Ref operator[](int idx) const { return Ref{base + idx * kYStride}; }
 };
 
 // Four primaries of one home cell (sorted indices; -1 = none, never first).
@@ -438,7 +445,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           // the harmonics and the steps difference Dt values
           constexpr bool DT = !FP64 && CL == 0;
           const double fy = DT ? f * (ir * ir * ir) : f;
-          real_ylm<NL - 1>(ux, uy, uz, YStore<YT>{ylds + slot, fy});
+          real_ylm<NL - 1>(ux, uy, uz, fy, YStore<YT>{ylds + slot});
           s_r[slot] = r;
           s_ir[slot] = ir;
           if constexpr (WITH_C) s_f[slot] = f;
