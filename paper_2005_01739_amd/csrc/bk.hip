@@ -574,23 +574,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
         // the run's periodic image offset, from its shift code (uniform)
         const double ox = double(csh / 9 - 1) * L, oy = double((csh / 3) % 3 - 1) * L, oz = double(csh % 3 - 1) * L;
         const bool self_run = J.self_set && csh == 13;
+        const unsigned ent = (unsigned(cj) << 5) | unsigned(csh);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          bool hit = false, far = false;
-          if (cok && qp[r] >= 0) {
-            const double dx = (q_xyz[r][0] - cx) - ox;
-            const double dy = (q_xyz[r][1] - cy) - oy;
-            const double dz = (q_xyz[r][2] - cz) - oz;
-            const double r2 = bk_sq_norm(dx, dy, dz);
-            hit = r2 < J.r02 && !(self_run && cj == qp[r]);
-            far = r2 >= rfar2;
-          }
+          // (uniform) a row without a primary: only the last quad of a cell
+          if (qp[r] < 0) continue;
+          const double dx = (q_xyz[r][0] - cx) - ox;
+          const double dy = (q_xyz[r][1] - cy) - oy;
+          const double dz = (q_xyz[r][2] - cz) - oz;
+          const double r2 = bk_sq_norm(dx, dy, dz);
+          bool hit = cok && r2 < J.r02;
+          if (self_run) hit = hit && cj != qp[r];
+          const bool far = r2 >= rfar2;
           const unsigned long long balf = __ballot(hit && far), baln = __ballot(hit && !far);
-          if (hit) {
-            const unsigned long long lt = (1ull << lane) - 1ull;
-            const int k = far ? ring_at<0>(r, (hh[0][r] + hn[0][r] + __popcll(balf & lt)) & (kHitCapF - 1))
-                              : ring_at<1>(r, (hh[1][r] + hn[1][r] + __popcll(baln & lt)) & (kHitCapN - 1));
-            hl[k] = (unsigned(cj) << 5) | unsigned(csh);
+          // each class appends to its ring at the row's (uniform) end plus the
+          // lane's rank among the class's hits
+          if (hit && far) {
+            const int pre = int(__builtin_amdgcn_mbcnt_hi(unsigned(balf >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(balf), 0u)));
+            hl[ring_at<0>(r, (hh[0][r] + hn[0][r] + pre) & (kHitCapF - 1))] = ent;
+          }
+          if (hit && !far) {
+            const int pre = int(__builtin_amdgcn_mbcnt_hi(unsigned(baln >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(baln), 0u)));
+            hl[ring_at<1>(r, (hh[1][r] + hn[1][r] + pre) & (kHitCapN - 1))] = ent;
           }
           hn[0][r] += __popcll(balf);
           hn[1][r] += __popcll(baln);
