@@ -326,29 +326,32 @@ static Sorted build_cells_t(Ctx &c, CellScratch &s, const Grid &g, const T *pos,
 // Neighbour count of each selected sorted primary: the secondaries within R0
 // in the 27 cells around its home cell, tested in single precision (the
 // count only orders the primaries inside a cell, so a pair at the boundary
-// may go either way without harm).  One wave per home cell: it takes the
-// cell's primaries 64 at a time and, for each such chunk, stages the 27
-// neighbour cells' candidates through LDS, 64 at a time, every lane testing
-// every staged candidate against its own primary.
+// may go either way without harm).  One wave per 64 consecutive primaries:
+// the wave takes the distinct home cells of its lanes one at a time and
+// stages that cell's candidates through LDS, 64 at a time; the lanes of the
+// cell test every staged candidate.
 __global__ __launch_bounds__(64) void k_nb_count(Sorted prim, Sorted sec, int nc, double L, float r02, int self_set,
                                                  int *__restrict__ cnt) {
   __shared__ float4 cand[64];
   const int lane = threadIdx.x;
-  const int cell = int(blockIdx.x);
-  const int64_t b = prim.cell_start[cell], e = prim.cell_start[cell + 1];
-  if (b == e) return;
-  const int cz = cell % nc, cy = (cell / nc) % nc, cx = cell / (nc * nc);
-  for (int64_t p0 = b; p0 < e; p0 += 64) {
-    const int64_t p = p0 + lane;
-    const bool valid = p < e && (prim.m == nullptr || prim.m[p] != 0);
-    if (__ballot(valid) == 0ull) continue;
-    float px = 0.0f, py = 0.0f, pz = 0.0f;
-    if (valid) {
-      px = float(prim.x[p]);
-      py = float(prim.y[p]);
-      pz = float(prim.z[p]);
-    }
-    int count = 0;
+  const int64_t p = int64_t(blockIdx.x) * 64 + lane;
+  const bool valid = p < prim.n && (prim.m == nullptr || prim.m[p] != 0);
+  const int my_cell = valid ? prim.scell[p] : -1;
+  float px = 0.0f, py = 0.0f, pz = 0.0f;
+  if (valid) {
+    px = float(prim.x[p]);
+    py = float(prim.y[p]);
+    pz = float(prim.z[p]);
+  }
+  int count = 0;
+  bool done = !valid;
+  for (;;) {
+    const unsigned long long pend = __ballot(!done);
+    if (pend == 0) break;
+    const int first = __ffsll((long long)pend) - 1;
+    const int cell = __builtin_amdgcn_readfirstlane(__shfl(my_cell, first));
+    const bool mine = !done && my_cell == cell;
+    const int cz = cell % nc, cy = (cell / nc) % nc, cx = cell / (nc * nc);
     for (int k = 0; k < 27; ++k) {
       int nx = cx + k / 9 - 1, ny = cy + (k / 3) % 3 - 1, nz = cz + k % 3 - 1;
       double ox = 0.0, oy = 0.0, oz = 0.0;
@@ -356,16 +359,16 @@ __global__ __launch_bounds__(64) void k_nb_count(Sorted prim, Sorted sec, int nc
       if (ny >= nc) { ny -= nc; oy = L; } else if (ny < 0) { ny += nc; oy = -L; }
       if (nz >= nc) { nz -= nc; oz = L; } else if (nz < 0) { nz += nc; oz = -L; }
       const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
-      const int64_t cb = sec.cell_start[nb], ce = sec.cell_start[nb + 1];
-      for (int64_t j0 = cb; j0 < ce; j0 += 64) {
+      const int64_t b = sec.cell_start[nb], e = sec.cell_start[nb + 1];
+      for (int64_t j0 = b; j0 < e; j0 += 64) {
         const int64_t j = j0 + lane;
         float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (j < ce) v = make_float4(float(sec.x[j] + ox), float(sec.y[j] + oy), float(sec.z[j] + oz), 0.0f);
+        if (j < e) v = make_float4(float(sec.x[j] + ox), float(sec.y[j] + oy), float(sec.z[j] + oz), 0.0f);
         __syncthreads();
         cand[lane] = v;
         __syncthreads();
-        if (valid) {
-          const int n = int(ce - j0 < 64 ? ce - j0 : 64);
+        if (mine) {
+          const int n = int(e - j0 < 64 ? e - j0 : 64);
           for (int i = 0; i < n; ++i) {
             const float4 q = cand[i];
             const float dx = px - q.x, dy = py - q.y, dz = pz - q.z;
@@ -374,8 +377,9 @@ __global__ __launch_bounds__(64) void k_nb_count(Sorted prim, Sorted sec, int nc
         }
       }
     }
-    if (valid) cnt[p] = self_set && count > 0 ? count - 1 : count;
+    if (mine) done = true;
   }
+  if (valid) cnt[p] = self_set && count > 0 ? count - 1 : count;
 }
 
 // Sort key (home cell, neighbour count): selected primaries by count, the
@@ -403,7 +407,7 @@ const int *order_by_neighbours(Ctx &c, const Sorted &prim, const Sorted &sec, co
   uint64_t *key2 = static_cast<uint64_t *>(ensure(c, c.bo_key2, size_t(n) * sizeof(uint64_t)));
   int *iota = static_cast<int *>(ensure(c, c.bo_iota, size_t(n) * sizeof(int)));
   int *perm = static_cast<int *>(ensure(c, c.bo_perm, size_t(n) * sizeof(int)));
-  k_nb_count<<<dim3(unsigned(g.ncells())), dim3(64), 0, c.stream>>>(prim, sec, g.nc, g.L, float(r0 * r0),
+  k_nb_count<<<dim3(unsigned((n + 63) / 64)), dim3(64), 0, c.stream>>>(prim, sec, g.nc, g.L, float(r0 * r0),
                                                                        self_set ? 1 : 0, cnt);
   HIPSTER_HIP(hipGetLastError());
   k_nb_key<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, c.stream>>>(prim.scell, prim.m, cnt, n, key, iota);
