@@ -105,6 +105,28 @@ def test_generated_randoms_and_small_grid(precision):
     run_case(pos, None, rpos, None, L, 15.0, np.linspace(0.1, 1.5, 5), 3, precision, gen=(2.5, 123456789))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_clump_and_sparse_primaries(precision):
+    # A dense clump (700 points, sigma 0.3) among sparse background points,
+    # plus a shell of primaries 5 from its centre.  Cells then hold primaries
+    # with ~700 neighbours beside primaries with ~15, so quads mix very
+    # different rows; a clump row's near ring and a shell row's far ring
+    # (bins from k = 2: pairs beyond r = 4 are far) each take hundreds of hits
+    # in a burst, which forces batches with idle rows before a ring overflows.
+    L, r0 = 40.0, 8.0
+    rng = np.random.default_rng(71)
+    centre = np.array([20.0, 20.0, 20.0])
+    clump = centre + rng.normal(scale=0.3, size=(700, 3))
+    d = rng.normal(size=(60, 3))
+    shell = centre + 5.0 * d / np.linalg.norm(d, axis=1)[:, None]
+    background = rng.random((400, 3)) * L
+    pos = np.ascontiguousarray(np.concatenate([clump, shell, background]) % L)
+    rpos = rng.random((600, 3)) * L
+    k = np.geomspace(2.0, 12.0, 9)
+    info = run_case(pos, None, rpos, None, L, r0, k, 4, precision)
+    assert info["n_pairs"] > 700 * 650
+
+
 def test_generated_randoms_equal_given_catalogue():
     # the drawn catalogue is exactly the oracle's: same bits as passing it
     import paper_2005_01739_amd as hp
