@@ -144,7 +144,11 @@ __device__ __forceinline__ int ring_at(int r, int i) {
 constexpr int kRowBatch = 8;         // pairs per row per batch
 constexpr int kSlots = 4 * kRowBatch;  // staged pairs per batch, slot = kRowBatch row + i
 constexpr int kYStride = kSlots + 1;   // y staging row stride (odd)
-constexpr int kSinCosTabBk = 256;    // sine/cosine table entries (LDS)
+// sine/cosine table entries (LDS).  At l_max = 5 the y staging of 36
+// harmonics leaves room within 20 KiB per wave, the LDS share of two waves
+// per SIMD, only for the 64-entry table (two more terms in its polynomials).
+template <int NL>
+constexpr int bk_tab() { return NL == 6 ? 64 : 256; }
 
 // Writes w_q W y_lm of one slot into the y staging as real_ylm produces it:
 // element idx goes to base[idx * kYStride].
@@ -222,7 +226,7 @@ size_t bk_lds_bytes() {
 template <int NL, bool FP64>
 __device__ inline Gv<double, NL> G_any(double u, double wd, const double2 *tab) {
   if constexpr (FP64) return G_fp64<NL, 1>(u);
-  else return G_mixed_w<NL, 1, kSinCosTabBk, false>(u, wd, tab);
+  else return G_mixed_w<NL, 1, bk_tab<NL>(), false>(u, wd, tab);
 }
 
 // fmac_block for l = L .. NL-1 (compile-time recursion).
@@ -231,6 +235,26 @@ __device__ __forceinline__ void fmac_all(double (&acc)[NA], const double (&yr)[N
   if constexpr (L < NL) {
     fmac_block<L>(acc, yr, gl[L]);
     fmac_all<L + 1>(acc, yr, gl);
+  }
+}
+
+// acc[l*l+m] = E^{e+1}_lm - E^e_lm for l = L .. NL-1, E^{e+1} from the next
+// lane of the row, or on lane 15 (last) from the top-edge sums t (harmonic k
+// on lane k % 16 of t[k / 16]).
+template <int L, int NL, int NA, int NY>
+__device__ __forceinline__ void edge_diff(double (&acc)[NA], const double (&t)[NY], bool last) {
+  if constexpr (L < NL) {
+    double tk[NA];
+#pragma unroll
+    for (int m = 0; m < 2 * L + 1; ++m) tk[L * L + m] = 0.0;
+    fmac_block<L>(tk, t, 1.0);
+#pragma unroll
+    for (int m = 0; m < 2 * L + 1; ++m) {
+      const int k = L * L + m;
+      const double nx = from_next_lane_in_row(acc[k]);
+      acc[k] = (last ? tk[k] : nx) - acc[k];
+    }
+    edge_diff<L + 1, NL>(acc, t, last);
   }
 }
 
@@ -248,7 +272,7 @@ __host__ __device__ constexpr int aniso_count(int NL) {
 }
 
 template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE, bool ANISO = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HIPSTER_BK_WAVES : 1))) void k_bk_quad(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HIPSTER_BK_WAVES : 1))) void k_bk_quad(
     BkArgs A) {
   static_assert(GRAM || !QUEUE, "the queued sweep keeps its Gram tiles in registers");
   static_assert(!ANISO || (GRAM && !FP64 && !WITH_C && !QUEUE), "the anisotropic sweep is single-box, mixed form");
@@ -261,13 +285,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
   // hit rings per class (0: far, every edge of the group at u >= U_BIG;
   // 1: near) and row; an entry is (secondary index << 5) | image shift code
   __shared__ unsigned hl[4 * (kHitCapF + kHitCapN)];
-  __shared__ int64_t nb_beg[27], nb_end[27], run_beg[27], run_end[27];
-  __shared__ int nb_sh[27], run_sh[27], n_runs_s;
+  // the home cell's neighbour runs: [begin, end) of the sorted secondaries
+  // (fewer than 2^27) and image shift code
+  __shared__ int run_beg[27], run_end[27], run_sh[27], n_runs_s;
   // the quad's four primaries (x, y, z per row), read per scan step from LDS
   // rather than held in scalar registers
   __shared__ double q_xyz[4][3];
-  __shared__ double2 sc_tab[FP64 ? 1 : kSinCosTabBk];
-  if constexpr (!FP64) stage_sincos_tab<kSinCosTabBk>(sc_tab);
+  __shared__ double2 sc_tab[FP64 ? 1 : bk_tab<NL>()];
+  if constexpr (!FP64) stage_sincos_tab<bk_tab<NL>()>(sc_tab);
   for (int i = threadIdx.x; i < NL * kSlots; i += 64) (&s_gt[0][0])[i] = 0.0;
 
   const int lane = threadIdx.x, row = lane >> 4, col = lane & 15;
@@ -349,6 +374,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
         // sorted secondaries (cells adjacent along z are adjacent in memory)
         const int nc = J.nc;
         const int cz = int(cell % nc), cy = int((cell / nc) % nc), cx = int(cell / (int64_t(nc) * nc));
+        int nbb = 0, nbe = 0, nbs = 0;
         if (lane < 27) {
           int sx = 0, sy = 0, sz = 0;
           int nx = cx + lane / 9 - 1, ny = cy + (lane / 3) % 3 - 1, nz = cz + lane % 3 - 1;
@@ -356,23 +382,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           if (ny >= nc) { ny -= nc; sy = 1; } else if (ny < 0) { ny += nc; sy = -1; }
           if (nz >= nc) { nz -= nc; sz = 1; } else if (nz < 0) { nz += nc; sz = -1; }
           const int64_t nb = (int64_t(nx) * nc + ny) * nc + nz;
-          nb_beg[lane] = J.sec.cell_start[nb];
-          nb_end[lane] = J.sec.cell_start[nb + 1];
-          nb_sh[lane] = (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1);
+          nbb = int(J.sec.cell_start[nb]);
+          nbe = int(J.sec.cell_start[nb + 1]);
+          nbs = (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1);
         }
-        wave_sync();
+        // merged in lane order (uniform), each run written when the next opens
+        int nr = 0, rb = 0, re = 0, rs = 0;
+        for (int k = 0; k < 27; ++k) {
+          const int b = __builtin_amdgcn_readlane(nbb, k), e = __builtin_amdgcn_readlane(nbe, k);
+          const int sc = __builtin_amdgcn_readlane(nbs, k);
+          if (e == b) continue;
+          if (nr > 0 && re == b && rs == sc) {
+            re = e;
+            continue;
+          }
+          if (nr > 0 && lane == 0) {
+            run_beg[nr - 1] = rb;
+            run_end[nr - 1] = re;
+            run_sh[nr - 1] = rs;
+          }
+          rb = b;
+          re = e;
+          rs = sc;
+          ++nr;
+        }
         if (lane == 0) {
-          int nr = 0;
-          for (int k = 0; k < 27; ++k) {
-            if (nb_end[k] == nb_beg[k]) continue;
-            if (nr > 0 && run_end[nr - 1] == nb_beg[k] && run_sh[nr - 1] == nb_sh[k]) {
-              run_end[nr - 1] = nb_end[k];
-            } else {
-              run_beg[nr] = nb_beg[k];
-              run_end[nr] = nb_end[k];
-              run_sh[nr] = nb_sh[k];
-              ++nr;
-            }
+          if (nr > 0) {
+            run_beg[nr - 1] = rb;
+            run_end[nr - 1] = re;
+            run_sh[nr - 1] = rs;
           }
           n_runs_s = nr;
         }
@@ -451,7 +489,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           if constexpr (WITH_C) s_f[slot] = f;
           if (top) {
             if constexpr (DT) {
-              const Gv<double, NL> T = Dt_far<NL, 1, false, kSinCosTabBk>(ktop * r, iktop * ir, sc_tab);
+              const Gv<double, NL> T = Dt_far<NL, 1, false, bk_tab<NL>()>(ktop * r, iktop * ir, sc_tab);
 #pragma unroll
               for (int l = 0; l < NL; ++l) s_gt[l][slot] = T.v[l];
             } else {
@@ -486,7 +524,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
           constexpr bool DT = !FP64 && CL == 0;
           Gv<double, NL> Ge;
           if constexpr (FP64) Ge = G_any<NL, true>(u, wd, sc_tab);
-          else if constexpr (DT) Ge = Dt_far<NL, 1, false, kSinCosTabBk>(u, wd, sc_tab);
+          else if constexpr (DT) Ge = Dt_far<NL, 1, false, bk_tab<NL>()>(u, wd, sc_tab);
           else Ge = G_any<NL, false>(u, wd, sc_tab);
           double gl[NL];
 #pragma unroll
@@ -545,14 +583,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
       // the batches (a wait for the current chunk would otherwise also wait
       // for it: loads complete in order)
       int ri = 0;
-      int64_t pos = n_runs > 0 ? uniform_i64(run_beg[0]) : 0;
+      int64_t pos = n_runs > 0 ? __builtin_amdgcn_readfirstlane(run_beg[0]) : 0;
       bool have = n_runs > 0;
       double cx = 0.0, cy = 0.0, cz = 0.0;
       int cj = 0;
       bool cok = false;
       int csh = 13;
       auto fetch = [&](double &x, double &y, double &z, int &j, bool &ok, int &sh) {
-        const int64_t end = uniform_i64(run_end[ri]);
+        const int64_t end = __builtin_amdgcn_readfirstlane(run_end[ri]);
         sh = __builtin_amdgcn_readfirstlane(run_sh[ri]);
         const int64_t jj = pos + lane;
         ok = jj < end;
@@ -565,7 +603,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
         pos += 64;
         if (pos >= end) {
           ++ri;
-          if (ri < n_runs) pos = uniform_i64(run_beg[ri]);
+          if (ri < n_runs) pos = __builtin_amdgcn_readfirstlane(run_beg[ri]);
         }
       };
       if (have) fetch(cx, cy, cz, cj, cok, csh);
@@ -637,18 +675,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 5 ? HI
 
       if constexpr (PER_EDGE) {
         // bin e = E^{e+1} - E^e; lane 15 of a row takes E^{e+1} from tacc,
-        // each harmonic broadcast from the lane that holds it
-        double tk[NLM], ones[NL];
-#pragma unroll
-        for (int k = 0; k < NLM; ++k) tk[k] = 0.0;
-#pragma unroll
-        for (int l = 0; l < NL; ++l) ones[l] = 1.0;
-        fmac_all<0>(tk, tacc, ones);
-#pragma unroll
-        for (int k = 0; k < NLM; ++k) {
-          const double nx = from_next_lane_in_row(acc[k]);
-          acc[k] = (col == 15 ? tk[k] : nx) - acc[k];
-        }
+        // each harmonic broadcast from the lane that holds it, one multipole
+        // at a time (at most 2 l + 1 broadcasts live beside acc)
+        edge_diff<0, NL>(acc, tacc, col == 15);
       }
       // the quad's contribution; the bin's 3 / (k_{a+1}^3 - k_a^3) first
 #pragma unroll
