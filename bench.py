@@ -59,6 +59,7 @@ BK_SOURCES = ["paper_2005_01739_amd/csrc/bk.hip", "paper_2005_01739_amd/csrc/spe
               "paper_2005_01739_amd/csrc/coeffs.h", "paper_2005_01739_amd/csrc/fmac_dpp.h"]
 PROFILE = os.path.join(ROOT, "profiles", "k_pk_far_mixed_thomas_2e6.md")
 BK_PROFILE = os.path.join(ROOT, "profiles", "k_bk_quad_mixed_thomas_2p24.md")
+BK3_PROFILE = os.path.join(ROOT, "profiles", "k_bk_quad_mixed_thomas_5e5.md")
 
 
 def sweep_source_hash(sources=SWEEP_SOURCES) -> str:
@@ -675,7 +676,9 @@ def main():
         kname = "k_bk_quad (anisotropic contraction)" if args.workload == "bk-aniso" else "k_bk_quad"
         out["roofline"] = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                            "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
-                           "frac_fp64": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                           "frac_fp64": achieved / PEAK_FP64_TFLOPS,
+                           "traffic": (traffic_from_profile(BK3_PROFILE, BK_SOURCES)
+                                       if args.workload == "bk" and prec == "mixed" else None),
                            "flops_per_launch": flops, "avg_launch_ms": avg_launch_ms}
     out["pairs_per_step"] = pairs + pairs_r
     if args.workload == "pk" and not args.no_table_form:
