@@ -271,7 +271,9 @@ __host__ __device__ constexpr int aniso_count(int NL) {
   return c;
 }
 
-template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE, bool ANISO = false>
+// NOTOP: the launch's group of bins is not full (no top edge), so the
+// steps carry no top-edge sums.
+template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE, bool ANISO = false, bool NOTOP = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HIPSTER_BK_WAVES : 1))) void k_bk_quad(
     BkArgs A) {
   static_assert(GRAM || !QUEUE, "the queued sweep keeps its Gram tiles in registers");
@@ -487,7 +489,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
           s_r[slot] = r;
           s_ir[slot] = ir;
           if constexpr (WITH_C) s_f[slot] = f;
-          if (top) {
+          if (!NOTOP && top) {
             if constexpr (DT) {
               const Gv<double, NL> T = Dt_far<NL, 1, false, bk_tab<NL>()>(ktop * r, iktop * ir, sc_tab);
 #pragma unroll
@@ -546,8 +548,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
             // row's pair (yr[i]) times its staged value.  Lanes past the last
             // harmonic sum a value no broadcast reads; without a full group
             // the sum is unused (its bin factor is zero) and s_gt is finite.
+            if constexpr (!NOTOP) {
 #pragma unroll
-            for (int i = 0; i < NY; ++i) tacc[i] = fma((&s_gt[0][0])[lk[i] * kSlots + slot], yr[i], tacc[i]);
+              for (int i = 0; i < NY; ++i) tacc[i] = fma((&s_gt[0][0])[lk[i] * kSlots + slot], yr[i], tacc[i]);
+            }
           }
           if constexpr (WITH_C) {
             const double fq = s_f[slot] * cfb;
@@ -896,18 +900,19 @@ struct LaunchClock {
   LaunchClock &operator=(const LaunchClock &) = delete;
 };
 
-template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE = false>
+template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE = false, bool NOTOP = false>
 static void launch_quad(Ctx &c, const BkArgs &a, int nwaves) {
   const size_t lds = bk_lds_bytes<NL, FP64>();
-  k_bk_quad<NL, FP64, WITH_C, GRAM, QUEUE><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(a);
+  k_bk_quad<NL, FP64, WITH_C, GRAM, QUEUE, false, NOTOP><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(a);
   HIPSTER_HIP(hipGetLastError());
 }
 
-template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE = false>
+template <int NL, bool FP64, bool WITH_C, bool GRAM, bool QUEUE = false, bool NOTOP = false>
 static int quad_waves(Ctx &c) {
   int per_cu = 0;
   const size_t lds = bk_lds_bytes<NL, FP64>();
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bk_quad<NL, FP64, WITH_C, GRAM, QUEUE>, 64, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bk_quad<NL, FP64, WITH_C, GRAM, QUEUE, false, NOTOP>, 64,
+                                                   lds) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -976,7 +981,12 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   a.ld = 16 * groups;
 
   if (groups == 1) {
-    const int nwaves = fp64 ? quad_waves<NL, true, true, true>(c) : quad_waves<NL, false, false, true>(c);
+    // the mixed form's steps leave out the top-edge sums when the bins do
+    // not fill the group
+    const bool full = NK == 16;
+    const int nwaves = fp64   ? quad_waves<NL, true, true, true>(c)
+                       : full ? quad_waves<NL, false, false, true>(c)
+                              : quad_waves<NL, false, false, true, false, true>(c);
     double *part = static_cast<double *>(ensure(c, c.bk_partial, size_t(nwaves) * a.rowlen * 8));
     HIPSTER_HIP(hipMemsetAsync(part, 0, size_t(nwaves) * a.rowlen * 8, c.stream));
     a.partial = part;
@@ -986,7 +996,8 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
     LaunchClock clk(c);
     clk.start();
     if (fp64) launch_quad<NL, true, true, true>(c, a, nwaves);
-    else launch_quad<NL, false, false, true>(c, a, nwaves);
+    else if (full) launch_quad<NL, false, false, true>(c, a, nwaves);
+    else launch_quad<NL, false, false, true, false, true>(c, a, nwaves);
     clk.stop();
     double *merged = static_cast<double *>(ensure(c, c.merged, size_t(a.rowlen) * 8));
     merge_partials(c, part, nwaves, a.rowlen, merged);
