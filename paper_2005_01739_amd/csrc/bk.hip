@@ -1054,7 +1054,9 @@ static void bk_sweep_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
     a.q_hi = std::min(nq, q0 + qchunk);
     for (int gi = 0; gi < groups; ++gi) {
       a.group = gi;
-      launch_quad<NL, false, false, false>(c, a, nwaves);
+      // the last group, when not full, without the top-edge sums
+      if (16 * (gi + 1) <= NK) launch_quad<NL, false, false, false>(c, a, nwaves);
+      else launch_quad<NL, false, false, false, false, true>(c, a, nwaves);
       ++launches;
     }
     k_bk_gram<<<dim3(unsigned(ntiles * nchunks)), dim3(64), 0, c.stream>>>(a.abuf, a.wbuf, (a.q_hi - a.q_lo) * 4, NLM,
@@ -1268,10 +1270,10 @@ static void bk_aniso_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   a.ld = 16;
   int per_cu = 0;
   const size_t lds = bk_lds_bytes<NL, false>();
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bk_quad<NL, false, false, true, false, true>, 64, lds) !=
-          hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
+  // without a full group of bins the steps carry no top-edge sums
+  void (*const kern)(BkArgs) = NK == 16 ? k_bk_quad<NL, false, false, true, false, true>
+                                        : k_bk_quad<NL, false, false, true, false, true, true>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess || per_cu < 1) per_cu = 1;
   hipDeviceProp_t prop{};
   int cus = 256;
   if (hipGetDeviceProperties(&prop, c.device) == hipSuccess && prop.multiProcessorCount > 0)
@@ -1282,7 +1284,7 @@ static void bk_aniso_nl(Ctx &c, const Sorted &prim, const Sorted &sec, const Gri
   a.partial = part;
   LaunchClock clk(c);
   clk.start();
-  k_bk_quad<NL, false, false, true, false, true><<<dim3(unsigned(nwaves)), dim3(64), lds, c.stream>>>(a);
+  hipLaunchKernelGGL(kern, dim3(unsigned(nwaves)), dim3(64), lds, c.stream, a);
   HIPSTER_HIP(hipGetLastError());
   clk.stop();
   double *merged = static_cast<double *>(ensure(c, c.merged, size_t(a.rowlen) * 8));
