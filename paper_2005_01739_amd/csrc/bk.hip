@@ -1141,7 +1141,13 @@ static void bk_sweep_queue_nl(Ctx &c, const std::vector<BkQueueJob> &jobs, bool 
   // tasks of about equal expected work (pairs), some eight per wave; jobs in
   // order of expected pairs per quad (dearest first), each job's tasks
   // consecutive.  A box's pairs per quad can differ from another's by 1e4.
-  const int nwaves = fp64 ? quad_waves<NL, true, true, true, true>(c) : quad_waves<NL, false, false, true, true>(c);
+  // the mixed form's steps leave out the top-edge sums when no job's bins
+  // fill the group
+  bool any_full = false;
+  for (const BkQueueJob &J : jobs) any_full = any_full || J.NK == 16;
+  const int nwaves = fp64       ? quad_waves<NL, true, true, true, true>(c)
+                     : any_full ? quad_waves<NL, false, false, true, true>(c)
+                                : quad_waves<NL, false, false, true, true, true>(c);
   double work = 0.0;
   for (int j = 0; j < nj; ++j) work += double(nq[size_t(j)]) * (4.0 * jobs[size_t(j)].cost + 1.0);
   const double per_task = std::max(1.0, work / (8.0 * nwaves));
@@ -1186,7 +1192,8 @@ static void bk_sweep_queue_nl(Ctx &c, const std::vector<BkQueueJob> &jobs, bool 
   a.counter = counter;
   a.slots = slots;
   if (fp64) launch_quad<NL, true, true, true, true>(c, a, nwaves);
-  else launch_quad<NL, false, false, true, true>(c, a, nwaves);
+  else if (any_full) launch_quad<NL, false, false, true, true>(c, a, nwaves);
+  else launch_quad<NL, false, false, true, true, true>(c, a, nwaves);
   // per job: its task rows in task order
   double *merged = static_cast<double *>(ensure(c, c.bk_gmerged, size_t(nj) * rowlen * 8));
   for (int j = 0; j < nj; ++j) {
