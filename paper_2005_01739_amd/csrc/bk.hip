@@ -290,9 +290,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
   // the home cell's neighbour runs: [begin, end) of the sorted secondaries
   // (fewer than 2^27) and image shift code
   __shared__ int run_beg[27], run_end[27], run_sh[27], n_runs_s;
-  // the quad's four primaries (x, y, z per row), read per scan step from LDS
-  // rather than held in scalar registers
+  // the quad's four primaries (x, y, z and index per row), read per scan step
+  // from LDS rather than held in scalar registers; a row without a primary
+  // has coordinates far outside any box, so that its tests never hit
   __shared__ double q_xyz[4][3];
+  __shared__ int q_idx[4];
   __shared__ double2 sc_tab[FP64 ? 1 : bk_tab<NL>()];
   if constexpr (!FP64) stage_sincos_tab<bk_tab<NL>()>(sc_tab);
   for (int i = threadIdx.x; i < NL * kSlots; i += 64) (&s_gt[0][0])[i] = 0.0;
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
   const int64_t e0 = int64_t(16) * A.group;
   // the job's constants; a queued launch reloads them when its task's job changes
   BkJob J = A.job;
-  double ke, ke3, ike, kn3, cfb, top_w, ktop, ktop3, iktop, r_neutral, ir_neutral, L, rfar, rfar2;
+  double ke, ke3, ike, kn3, cfb, top_w, ktop, ktop3, iktop, r_neutral, ir_neutral, L, rfar, rfar2, r02v;
   bool top;
   auto set_job = [&]() {
     const int NK = J.n_k;
@@ -327,6 +329,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
     const double k_lo = J.edges[e0];
     rfar = k_lo > 0.0 ? HIPSTER_U_BIG / k_lo : 0.0;
     rfar2 = (FP64 || !(k_lo > 0.0)) ? __builtin_inf() : rfar * rfar * (1.0 + 1e-12);
+    // R0^2 for the scan's tests, kept in vector registers: the scalar ones
+    // are short there
+    r02v = J.r02;
+    asm volatile("" : "+v"(r02v));
   };
   set_job();
   // Without the C sums (mixed form) each lane sums its own edge's values,
@@ -421,10 +427,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
       }
       const int n_runs = __builtin_amdgcn_readfirstlane(n_runs_s);
       // the four primaries (uniform), and this row's
-      if (lane < 12) {
-        const int r = lane / 3, d = lane % 3;
+      if (lane < 16) {
+        const int r = lane / 4, d = lane % 4;
         const int pp = qp[r] >= 0 ? qp[r] : qp[0];
-        q_xyz[r][d] = d == 0 ? J.prim.x[pp] : (d == 1 ? J.prim.y[pp] : J.prim.z[pp]);
+        if (d == 3) q_idx[r] = qp[r];
+        else if (qp[r] < 0) q_xyz[r][d] = 1e300;
+        else q_xyz[r][d] = d == 0 ? J.prim.x[pp] : (d == 1 ? J.prim.y[pp] : J.prim.z[pp]);
       }
       wave_sync();
       const int my_p = row == 0 ? qp[0] : row == 1 ? qp[1] : row == 2 ? qp[2] : qp[3];
@@ -619,14 +627,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
         const unsigned ent = (unsigned(cj) << 5) | unsigned(csh);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          // (uniform) a row without a primary: only the last quad of a cell
-          if (qp[r] < 0) continue;
+          // a row without a primary (only in the last quad of a cell) finds
+          // r2 = inf
           const double dx = (q_xyz[r][0] - cx) - ox;
           const double dy = (q_xyz[r][1] - cy) - oy;
           const double dz = (q_xyz[r][2] - cz) - oz;
           const double r2 = bk_sq_norm(dx, dy, dz);
-          bool hit = cok && r2 < J.r02;
-          if (self_run) hit = hit && cj != qp[r];
+          bool hit = cok && r2 < r02v;
+          if (self_run) hit = hit && cj != q_idx[r];
           const bool far = r2 >= rfar2;
           const unsigned long long balf = __ballot(hit && far), baln = __ballot(hit && !far);
           // each class appends to its ring at the row's (uniform) end plus the
