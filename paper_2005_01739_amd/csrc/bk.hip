@@ -625,6 +625,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
         const double ox = double(csh / 9 - 1) * L, oy = double((csh / 3) % 3 - 1) * L, oz = double(csh % 3 - 1) * L;
         const bool self_run = J.self_set && csh == 13;
         const unsigned ent = (unsigned(cj) << 5) | unsigned(csh);
+        // the lane masks are formed as ballots of single compares (each is
+        // the compare's own mask) joined by scalar operations; a ballot of a
+        // compound predicate goes through a vector register
+        const unsigned long long okm = __builtin_amdgcn_ballot_w64(cok);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           // a row without a primary (only in the last quad of a cell) finds
@@ -633,10 +637,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
           const double dy = (q_xyz[r][1] - cy) - oy;
           const double dz = (q_xyz[r][2] - cz) - oz;
           const double r2 = bk_sq_norm(dx, dy, dz);
-          bool hit = cok && r2 < r02v;
-          if (self_run) hit = hit && cj != q_idx[r];
-          const bool far = r2 >= rfar2;
-          const unsigned long long balf = __ballot(hit && far), baln = __ballot(hit && !far);
+          const bool in = r2 < r02v, far = r2 >= rfar2, other = cj != q_idx[r];
+          unsigned long long mh = __builtin_amdgcn_ballot_w64(in) & okm;
+          if (self_run) mh &= __builtin_amdgcn_ballot_w64(other);
+          const unsigned long long mf = __builtin_amdgcn_ballot_w64(far);
+          const unsigned long long balf = mh & mf, baln = mh & ~mf;
+          const bool hit = cok && in && (!self_run || other);
           // each class appends to its ring at the row's (uniform) end plus the
           // lane's rank among the class's hits
           if (hit && far) {
