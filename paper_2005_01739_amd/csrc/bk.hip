@@ -629,13 +629,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
         // the compare's own mask) joined by scalar operations; a ballot of a
         // compound predicate goes through a vector register
         const unsigned long long okm = __builtin_amdgcn_ballot_w64(cok);
+        // the row tests, in one form for a run of the home image (no offset to
+        // subtract: most runs) and one for a shifted image
+        auto rows = [&](auto shifted) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           // a row without a primary (only in the last quad of a cell) finds
           // r2 = inf
-          const double dx = (q_xyz[r][0] - cx) - ox;
-          const double dy = (q_xyz[r][1] - cy) - oy;
-          const double dz = (q_xyz[r][2] - cz) - oz;
+          double dx = q_xyz[r][0] - cx, dy = q_xyz[r][1] - cy, dz = q_xyz[r][2] - cz;
+          if constexpr (decltype(shifted)::value) {
+            dx -= ox;
+            dy -= oy;
+            dz -= oz;
+          }
           const double r2 = bk_sq_norm(dx, dy, dz);
           const bool in = r2 < r02v, far = r2 >= rfar2, other = cj != q_idx[r];
           unsigned long long mh = __builtin_amdgcn_ballot_w64(in) & okm;
@@ -657,6 +663,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NL <= 6 ? HI
           hn[1][r] += __popcll(baln);
           pcount += unsigned(__popcll(balf) + __popcll(baln));
         }
+        };
+        if (csh == 13) rows(std::false_type{});
+        else rows(std::true_type{});
         double nx = 0.0, ny = 0.0, nz = 0.0;
         int nj = 0;
         bool nok = false;
