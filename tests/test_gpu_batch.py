@@ -107,6 +107,23 @@ def test_batch_generated_randoms():
     _check_boxes(specs, outs, "mixed")
 
 
+def test_batch_full_and_partial_bin_groups():
+    # One queued bispectrum sweep holding a box whose 16 bins fill the group
+    # of edges (its steps carry the top-edge sums) beside boxes with fewer
+    # bins (their top-edge sums are zero); every box against the oracle.
+    import paper_2005_01739_amd as hp
+    specs = []
+    for b, nb in enumerate((16, 5, 11)):
+        n = 800 + 200 * b
+        L = 80.0 + 10.0 * b
+        pos = synthetic.thomas(n, L, 10, 2.0, 1.0, [21, b], np.float32)
+        specs.append(dict(pos=pos, box=L, r0=12.0, pk_edges=np.geomspace(1.0, 10.0, 13), pk_ell_max=4,
+                          bk_edges=np.geomspace(0.3, 3.0, nb + 1), bk_ell_max=3,
+                          randoms=synthetic.poisson(2 * n, L, [21, b, 1], np.float32)))
+    outs = hp.batch(specs, precision="mixed")
+    _check_boxes(specs, outs, "mixed")
+
+
 def test_batch_64_box_recipe_subset():
     # The 64-box recipe (N log-uniform in [1e5, 4e6] scaled by 0.1, L in
     # [250, 1500], R0 in [15, 50], half Poisson, half Thomas; P with 30 log
